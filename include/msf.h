@@ -1,0 +1,205 @@
+/*
+ * msf.h -- C ABI of the MI355X (gfx950) minimum spanning forest library.
+ *
+ * The library computes the minimum spanning forest of an undirected weighted
+ * graph with the algebraic Awerbuch-Shiloach method of Baer, Kanakagiri and
+ * Solomonik, "Parallel Minimum Spanning Forest Computation using Sparse
+ * Matrix Kernels" (arXiv 2110.04865): rounds of a multilinear kernel over
+ * the adjacency matrix and the parent vector (section 3.1), projection onto
+ * supervertices, star hooking with tie breaking (Algorithm 2), and complete
+ * shortcutting of the parent forest (section 4.2).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every call returns an msf_status and never aborts.  On any error the
+ *    caller's output arrays and scalars are left untouched, and
+ *    msf_last_error() returns a message for the calling thread.
+ *  - Vertices are 0-based int32 ids.  Edge e of m is the pair
+ *    (edges[2e], edges[2e+1]) with weight weights[e]; its id is e.
+ *  - Edge order: key(e) = (wkey(w_e), e), compared lexicographically, where
+ *    wkey is the weight for MSF_W_U32 and an order-preserving unsigned map of
+ *    the bits for MSF_W_F32 (-0.0 equals +0.0).  The paper assumes distinct
+ *    weights (section 2); breaking ties by edge id makes the forest unique,
+ *    so results are deterministic and independent of every tuning choice.
+ *  - Self-loops are accepted and never enter the forest; parallel edges are
+ *    accepted and the one with the smaller key wins.
+ *  - Ownership: the caller owns every array it passes; the library owns only
+ *    the opaque handles it returns, released by the matching *_destroy.
+ *    Inputs are read during the call (or copied, for graphs and server
+ *    requests); nothing aliases a caller array after return.
+ *  - msf_mem selects where caller arrays live.  MSF_MEM_HOST: host memory,
+ *    the call is synchronous.  MSF_MEM_DEVICE: device memory on the context's
+ *    device; work is ordered on the context's stream, and the call returns
+ *    after its host scalar outputs are known (which synchronises the stream).
+ *  - Errors: MSF_EINVAL for bad arguments (n < 0, m < 0, m > 2^31-1, an
+ *    endpoint outside [0, n), a NaN weight, NULL with a nonzero size, a
+ *    parent vector that is not a rooted forest), MSF_ENOMEM when device or
+ *    host memory cannot be allocated, MSF_EDEVICE for a HIP runtime failure,
+ *    MSF_EBUDGET when a server request cannot fit its memory budget,
+ *    MSF_ENOTFOUND for an unknown server ticket.
+ */
+#ifndef MSF_H
+#define MSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MSF_OK = 0,
+    MSF_EINVAL = 1,
+    MSF_ENOMEM = 2,
+    MSF_EDEVICE = 3,
+    MSF_EBUDGET = 4,
+    MSF_ENOTFOUND = 5
+} msf_status;
+
+typedef enum { MSF_W_U32 = 0, MSF_W_F32 = 1 } msf_wtype;
+typedef enum { MSF_MEM_HOST = 0, MSF_MEM_DEVICE = 1 } msf_mem;
+
+/*
+ * Forest weight (Algorithm 2 returns the sum of the weights of the edges
+ * that hook).  u64: exact sum for MSF_W_U32 weights, 0 for MSF_W_F32.
+ * f64: the exact real sum of the forest's weights rounded once to the
+ * nearest double (ties to even), so it does not depend on summation order.
+ */
+typedef struct {
+    uint64_t u64;
+    double f64;
+} msf_total;
+
+/* Per-solve statistics of the last msf_solve / msf_solve_batched on a ctx. */
+typedef struct {
+    int32_t rounds;          /* multilinear sweeps executed                  */
+    int32_t hook_rounds;     /* rounds in which at least one root hooked     */
+    int32_t max_chase;       /* longest pointer chase of any shortcut        */
+    int32_t filtered;        /* number of filtering compactions done         */
+    int64_t hooks[64];       /* hooks kept after tie breaking, per round     */
+    int64_t active_nnz[64];  /* stored directions swept, per round           */
+    double build_ms;         /* adjacency build time (device events)         */
+    double rounds_ms;        /* round loop time (device events)              */
+    double sweep_ms[64];     /* multilinear sweep kernel time, per round     */
+    double sweep_bytes[64];  /* algorithmic bytes of that sweep: 12 per
+                                stored entry (column + key), 8 per row with
+                                entries (row pointer + p of the row), 8 per
+                                live root (its minimum slot)                 */
+} msf_stats;
+
+typedef struct msf_ctx msf_ctx;
+typedef struct msf_graph msf_graph;
+typedef struct msf_server msf_server;
+
+/*
+ * Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * (for example torch.cuda.current_stream().cuda_stream) or NULL for the
+ * device's null stream.  The context caches device workspace between calls;
+ * calls on one context must not overlap in time.
+ */
+msf_status msf_ctx_create(int device, void *hip_stream, msf_ctx **out);
+void msf_ctx_destroy(msf_ctx *ctx);
+
+/* Thread-local message describing the last error ("" if none). */
+const char *msf_last_error(void);
+
+/* Library version string. */
+const char *msf_version(void);
+
+/*
+ * Minimum spanning forest (section 2 problem statement; Algorithm 2 with
+ * complete shortcutting, section 4.2).
+ *   n, m            vertex and edge counts (n >= 0, 0 <= m <= 2^31-1)
+ *   edges           int32[2m] endpoint pairs        (host or device per mem)
+ *   weights         uint32[m] or float32[m] per wtype (host or device)
+ *   forest_ids      int32[>= max(n-1,0)] out: forest edge ids, ascending
+ *                   (host or device per mem)
+ *   forest_count    host out: number of forest edges (= n - #components)
+ *   total           host out (nullable): forest weight
+ */
+msf_status msf_solve(msf_ctx *ctx, int32_t n, int64_t m, const int32_t *edges,
+                     const void *weights, msf_wtype wtype, msf_mem mem, int32_t *forest_ids,
+                     int64_t *forest_count, msf_total *total);
+
+/* Statistics of the last solve on ctx (host out). */
+msf_status msf_get_stats(const msf_ctx *ctx, msf_stats *out);
+
+/*
+ * Build and keep the device adjacency structure of a graph: the symmetric
+ * adjacency matrix A of section 2 (a_ij = w(i,j), both directions stored,
+ * each carrying its edge's key).  Arguments as for msf_solve; the arrays are
+ * copied.  *out receives a handle released by msf_graph_destroy.
+ */
+msf_status msf_graph_create(msf_ctx *ctx, int32_t n, int64_t m, const int32_t *edges,
+                            const void *weights, msf_wtype wtype, msf_mem mem,
+                            msf_graph **out);
+void msf_graph_destroy(msf_graph *g);
+
+/*
+ * The multilinear kernel of section 3.1 fused with the projection of
+ * Algorithm 2 (lines 9-10), for any parent vector p:
+ *   r[k] = min { key(e) : stored direction i->j of edge e, p[i] == k,
+ *                         p[i] != p[j] },  UINT64_MAX where the set is empty,
+ * with key(e) = (uint64_t)wkey(w_e) << 32 | e.
+ *   p   device uint32[n], every entry < n (MSF_EINVAL otherwise)
+ *   r   device uint64[n] out
+ * Ordered on the context's stream; returns without synchronising.
+ */
+msf_status msf_multilinear(msf_ctx *ctx, const msf_graph *g, const uint32_t *p, uint64_t *r);
+
+/*
+ * Complete shortcutting (section 4.2): p[i] <- the root of i's tree in the
+ * parent forest p (p[root] == root).  p is device uint32[n], in/out.
+ * sub_iters (host, nullable) receives the number of pointer-jumping passes.
+ * MSF_EINVAL, with p untouched, if some p[i] >= n or p is not a rooted forest
+ * (it has a cycle longer than one).
+ */
+msf_status msf_shortcut(msf_ctx *ctx, int32_t n, uint32_t *p, int32_t *sub_iters);
+
+/*
+ * Minimum spanning forests of G independent graphs in one batched solve.
+ * Graph g has vtx_off[g+1]-vtx_off[g] vertices and edge_off[g+1]-edge_off[g]
+ * edges stored from edges[2*edge_off[g]] (local vertex ids) and
+ * weights[edge_off[g]].  vtx_off/edge_off are host int64[G+1] starting at 0
+ * and non-decreasing.  Outputs (per mem): forest_ids int32[vtx_off[G]]
+ * receives graph g's forest (local edge ids, ascending) from index
+ * vtx_off[g]; counts int64[G] (host) and totals msf_total[G] (host,
+ * nullable).  Each graph's result equals msf_solve on that graph alone.
+ */
+msf_status msf_solve_batched(msf_ctx *ctx, int32_t G, const int64_t *vtx_off,
+                             const int64_t *edge_off, const int32_t *edges, const void *weights,
+                             msf_wtype wtype, msf_mem mem, int32_t *forest_ids, int64_t *counts,
+                             msf_total *totals);
+
+/*
+ * Serving: a request loop with continuous batching.  Requests are admitted
+ * while their device footprint fits mem_budget_bytes; admitted requests keep
+ * their adjacency, parent and edge state resident on the device and advance
+ * together, one batched round per step, on a worker thread; finished
+ * requests retire and free their memory for waiting ones.
+ *   msf_server_submit copies the host arrays and returns a ticket; it fails
+ *   with MSF_EBUDGET if the request alone can never fit the budget.
+ *   msf_server_poll sets *done to 1 once the result is ready.
+ *   msf_server_result waits for the result, writes it (host arrays, as for
+ *   msf_solve with MSF_MEM_HOST) and releases the ticket.
+ *   msf_server_latency gives (host, seconds) submit-to-ready latency of a
+ *   finished ticket.
+ */
+msf_status msf_server_create(msf_ctx *ctx, size_t mem_budget_bytes, msf_server **out);
+void msf_server_destroy(msf_server *s);
+msf_status msf_server_submit(msf_server *s, int32_t n, int64_t m, const int32_t *edges,
+                             const void *weights, msf_wtype wtype, uint64_t *ticket);
+msf_status msf_server_poll(msf_server *s, uint64_t ticket, int *done);
+msf_status msf_server_latency(msf_server *s, uint64_t ticket, double *seconds);
+msf_status msf_server_result(msf_server *s, uint64_t ticket, int32_t *forest_ids,
+                             int64_t *forest_count, msf_total *total);
+
+/* Device bytes a request of this size occupies while resident. */
+size_t msf_request_footprint(int32_t n, int64_t m);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSF_H */

@@ -1,0 +1,340 @@
+"""Python binding of ``libmsf.so``, the gfx950 minimum spanning forest library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in ``include/msf.h``.  Host inputs are
+numpy arrays; device inputs are torch CUDA (ROCm) tensors, whose
+``data_ptr()`` is passed through together with the current torch stream.
+
+There is no fallback: importing works without the library, but any call
+raises :class:`MSFError` if ``libmsf.so`` has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["MSFError", "Context", "Graph", "Server", "lib", "W_U32", "W_F32",
+           "STATUS_NAMES", "footprint"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "libmsf.so")
+
+W_U32 = 0
+W_F32 = 1
+MEM_HOST = 0
+MEM_DEVICE = 1
+STATUS_NAMES = {0: "MSF_OK", 1: "MSF_EINVAL", 2: "MSF_ENOMEM", 3: "MSF_EDEVICE",
+                4: "MSF_EBUDGET", 5: "MSF_ENOTFOUND"}
+
+EXPORTS = [
+    "msf_ctx_create", "msf_ctx_destroy", "msf_last_error", "msf_version", "msf_solve",
+    "msf_get_stats", "msf_graph_create", "msf_graph_destroy", "msf_multilinear",
+    "msf_shortcut", "msf_solve_batched", "msf_server_create", "msf_server_destroy",
+    "msf_server_submit", "msf_server_poll", "msf_server_latency", "msf_server_result",
+    "msf_request_footprint",
+]
+
+
+class MSFError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Total(ctypes.Structure):
+    _fields_ = [("u64", ctypes.c_uint64), ("f64", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("hook_rounds", ctypes.c_int32),
+                ("max_chase", ctypes.c_int32), ("filtered", ctypes.c_int32),
+                ("hooks", ctypes.c_int64 * 64), ("active_nnz", ctypes.c_int64 * 64),
+                ("build_ms", ctypes.c_double), ("rounds_ms", ctypes.c_double),
+                ("sweep_ms", ctypes.c_double * 64), ("sweep_bytes", ctypes.c_double * 64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load ``libmsf.so``; raise if it is missing (no CPU fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(SO_PATH):
+        raise MSFError(3, f"{SO_PATH} is not built; run __graft_entry__.build()")
+    L = ctypes.CDLL(SO_PATH)
+    P, I32, I64, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    st = ctypes.c_int
+    L.msf_ctx_create.argtypes = [ctypes.c_int, P, ctypes.POINTER(P)]
+    L.msf_ctx_create.restype = st
+    L.msf_ctx_destroy.argtypes = [P]
+    L.msf_ctx_destroy.restype = None
+    L.msf_last_error.restype = ctypes.c_char_p
+    L.msf_version.restype = ctypes.c_char_p
+    L.msf_solve.argtypes = [P, I32, I64, P, P, ctypes.c_int, ctypes.c_int, P,
+                            ctypes.POINTER(I64), ctypes.POINTER(Total)]
+    L.msf_solve.restype = st
+    L.msf_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
+    L.msf_get_stats.restype = st
+    L.msf_graph_create.argtypes = [P, I32, I64, P, P, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(P)]
+    L.msf_graph_create.restype = st
+    L.msf_graph_destroy.argtypes = [P]
+    L.msf_graph_destroy.restype = None
+    L.msf_multilinear.argtypes = [P, P, P, P]
+    L.msf_multilinear.restype = st
+    L.msf_shortcut.argtypes = [P, I32, P, ctypes.POINTER(I32)]
+    L.msf_shortcut.restype = st
+    L.msf_solve_batched.argtypes = [P, I32, P, P, P, P, ctypes.c_int, ctypes.c_int, P, P, P]
+    L.msf_solve_batched.restype = st
+    L.msf_server_create.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(P)]
+    L.msf_server_create.restype = st
+    L.msf_server_destroy.argtypes = [P]
+    L.msf_server_destroy.restype = None
+    L.msf_server_submit.argtypes = [P, I32, I64, P, P, ctypes.c_int, ctypes.POINTER(U64)]
+    L.msf_server_submit.restype = st
+    L.msf_server_poll.argtypes = [P, U64, ctypes.POINTER(ctypes.c_int)]
+    L.msf_server_poll.restype = st
+    L.msf_server_latency.argtypes = [P, U64, ctypes.POINTER(ctypes.c_double)]
+    L.msf_server_latency.restype = st
+    L.msf_server_result.argtypes = [P, U64, P, ctypes.POINTER(I64), ctypes.POINTER(Total)]
+    L.msf_server_result.restype = st
+    L.msf_request_footprint.argtypes = [I32, I64]
+    L.msf_request_footprint.restype = ctypes.c_size_t
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise MSFError(rc, lib().msf_last_error().decode())
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _wtype_of(w) -> int:
+    name = str(w.dtype)
+    if "float32" in name:
+        return W_F32
+    if "uint32" in name or "int32" in name:
+        return W_U32
+    raise TypeError(f"weights must be uint32 or float32, got {w.dtype}")
+
+
+def _host(a, dtype) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def footprint(n: int, m: int) -> int:
+    """Device bytes a served request of this size occupies while resident."""
+    return int(lib().msf_request_footprint(n, m))
+
+
+class Context:
+    """An ``msf_ctx`` on one HIP device, ordered on one stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        L = lib()
+        if stream is None:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    torch.cuda.set_device(device)
+                    stream = torch.cuda.current_stream().cuda_stream
+            except ImportError:
+                stream = None
+        h = ctypes.c_void_p()
+        _check(L.msf_ctx_create(device, ctypes.c_void_p(stream or 0), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().msf_ctx_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ------------------------------------------------------------ solve --
+    def solve(self, n: int, edges, weights, wtype: int | None = None, out=None):
+        """Minimum spanning forest.  Host (numpy) or device (torch) inputs.
+
+        Returns (ids, count, (total_u64, total_f64)); ``ids`` is a numpy
+        int32 array for host inputs, a torch int32 tensor (length count) for
+        device inputs (``out`` may supply a device buffer of >= n-1)."""
+        L = lib()
+        wt = _wtype_of(weights) if wtype is None else wtype
+        cnt = ctypes.c_int64()
+        tot = Total()
+        if _is_torch(edges):
+            import torch
+            m = edges.numel() // 2
+            assert edges.is_contiguous() and weights.is_contiguous()
+            ids = out if out is not None else torch.empty(max(n - 1, 1), dtype=torch.int32,
+                                                          device=edges.device)
+            _check(L.msf_solve(self._h, n, m, ctypes.c_void_p(edges.data_ptr()),
+                               ctypes.c_void_p(weights.data_ptr()), wt, MEM_DEVICE,
+                               ctypes.c_void_p(ids.data_ptr()), ctypes.byref(cnt),
+                               ctypes.byref(tot)))
+            return ids[:cnt.value], cnt.value, (tot.u64, tot.f64)
+        e = _host(edges, np.int32).reshape(-1)
+        w = _host(weights, np.float32 if wt == W_F32 else np.uint32)
+        m = len(w)
+        if e.size != 2 * m:
+            raise ValueError("edges must hold 2*m int32 values")
+        ids = np.empty(max(n - 1, 1), dtype=np.int32)
+        _check(L.msf_solve(self._h, n, m, ctypes.c_void_p(e.ctypes.data),
+                           ctypes.c_void_p(w.ctypes.data), wt, MEM_HOST,
+                           ctypes.c_void_p(ids.ctypes.data), ctypes.byref(cnt), ctypes.byref(tot)))
+        return ids[:cnt.value].copy(), cnt.value, (tot.u64, tot.f64)
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().msf_get_stats(self._h, ctypes.byref(s)))
+        k = min(s.rounds, 64)
+        return dict(rounds=s.rounds, hook_rounds=s.hook_rounds, max_chase=s.max_chase,
+                    filtered=s.filtered, hooks=list(s.hooks[:k]),
+                    active_nnz=list(s.active_nnz[:k]), build_ms=s.build_ms,
+                    rounds_ms=s.rounds_ms, sweep_ms=list(s.sweep_ms[:k]),
+                    sweep_bytes=list(s.sweep_bytes[:k]))
+
+    # ------------------------------------------------------- primitives --
+    def graph(self, n: int, edges, weights, wtype: int | None = None) -> "Graph":
+        return Graph(self, n, edges, weights, wtype)
+
+    def multilinear(self, g: "Graph", p, r):
+        """r[k] = min key over stored directions i->j with p[i]==k != p[j].
+
+        p: device int32/uint32 tensor [n]; r: device int64 tensor [n]
+        (bit pattern of uint64 keys).  Stream-ordered."""
+        _check(lib().msf_multilinear(self._h, g._h, ctypes.c_void_p(p.data_ptr()),
+                                     ctypes.c_void_p(r.data_ptr())))
+
+    def shortcut(self, p) -> int:
+        """p <- root of each vertex (device int32/uint32 tensor, in place);
+        returns the number of pointer-jumping passes."""
+        it = ctypes.c_int32()
+        _check(lib().msf_shortcut(self._h, p.numel(), ctypes.c_void_p(p.data_ptr()),
+                                  ctypes.byref(it)))
+        return it.value
+
+    # ----------------------------------------------------------- batched --
+    def solve_batched(self, vtx_off, edge_off, edges, weights, wtype: int | None = None,
+                      out=None):
+        """Solve G graphs at once.  Returns (ids, counts, totals) where graph
+        g's local forest ids are ids[vtx_off[g] : vtx_off[g] + counts[g]] and
+        totals is a list of (u64, f64)."""
+        L = lib()
+        vo = _host(vtx_off, np.int64)
+        eo = _host(edge_off, np.int64)
+        G = len(vo) - 1
+        wt = _wtype_of(weights) if wtype is None else wtype
+        counts = np.zeros(max(G, 1), dtype=np.int64)
+        totals = (Total * max(G, 1))()
+        N = int(vo[-1]) if G > 0 else 0
+        if _is_torch(edges):
+            import torch
+            ids = out if out is not None else torch.empty(max(N, 1), dtype=torch.int32,
+                                                          device=edges.device)
+            _check(L.msf_solve_batched(self._h, G, ctypes.c_void_p(vo.ctypes.data),
+                                       ctypes.c_void_p(eo.ctypes.data),
+                                       ctypes.c_void_p(edges.data_ptr()),
+                                       ctypes.c_void_p(weights.data_ptr()), wt, MEM_DEVICE,
+                                       ctypes.c_void_p(ids.data_ptr()),
+                                       ctypes.c_void_p(counts.ctypes.data), totals))
+        else:
+            e = _host(edges, np.int32).reshape(-1)
+            w = _host(weights, np.float32 if wt == W_F32 else np.uint32)
+            ids = np.empty(max(N, 1), dtype=np.int32)
+            _check(L.msf_solve_batched(self._h, G, ctypes.c_void_p(vo.ctypes.data),
+                                       ctypes.c_void_p(eo.ctypes.data),
+                                       ctypes.c_void_p(e.ctypes.data),
+                                       ctypes.c_void_p(w.ctypes.data), wt, MEM_HOST,
+                                       ctypes.c_void_p(ids.ctypes.data),
+                                       ctypes.c_void_p(counts.ctypes.data), totals))
+        return ids, counts[:G], [(totals[g].u64, totals[g].f64) for g in range(G)]
+
+
+class Graph:
+    """An ``msf_graph``: the device adjacency structure of one graph."""
+
+    def __init__(self, ctx: Context, n: int, edges, weights, wtype: int | None = None):
+        L = lib()
+        wt = _wtype_of(weights) if wtype is None else wtype
+        h = ctypes.c_void_p()
+        if _is_torch(edges):
+            m = edges.numel() // 2
+            _check(L.msf_graph_create(ctx._h, n, m, ctypes.c_void_p(edges.data_ptr()),
+                                      ctypes.c_void_p(weights.data_ptr()), wt, MEM_DEVICE,
+                                      ctypes.byref(h)))
+        else:
+            e = _host(edges, np.int32).reshape(-1)
+            w = _host(weights, np.float32 if wt == W_F32 else np.uint32)
+            _check(L.msf_graph_create(ctx._h, n, len(w), ctypes.c_void_p(e.ctypes.data),
+                                      ctypes.c_void_p(w.ctypes.data), wt, MEM_HOST,
+                                      ctypes.byref(h)))
+        self._h = h
+        self.n = n
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().msf_graph_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+class Server:
+    """Continuous-batching request loop (``msf_server_*``)."""
+
+    def __init__(self, ctx: Context, mem_budget_bytes: int):
+        h = ctypes.c_void_p()
+        _check(lib().msf_server_create(ctx._h, mem_budget_bytes, ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().msf_server_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def submit(self, n: int, edges, weights, wtype: int | None = None) -> int:
+        wt = _wtype_of(weights) if wtype is None else wtype
+        e = _host(edges, np.int32).reshape(-1)
+        w = _host(weights, np.float32 if wt == W_F32 else np.uint32)
+        t = ctypes.c_uint64()
+        _check(lib().msf_server_submit(self._h, n, len(w), ctypes.c_void_p(e.ctypes.data),
+                                       ctypes.c_void_p(w.ctypes.data), wt, ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int()
+        _check(lib().msf_server_poll(self._h, ticket, ctypes.byref(d)))
+        return bool(d.value)
+
+    def latency(self, ticket: int) -> float:
+        s = ctypes.c_double()
+        _check(lib().msf_server_latency(self._h, ticket, ctypes.byref(s)))
+        return s.value
+
+    def result(self, ticket: int, n: int):
+        ids = np.empty(max(n - 1, 1), dtype=np.int32)
+        cnt = ctypes.c_int64()
+        tot = Total()
+        _check(lib().msf_server_result(self._h, ticket, ctypes.c_void_p(ids.ctypes.data),
+                                       ctypes.byref(cnt), ctypes.byref(tot)))
+        return ids[:cnt.value].copy(), cnt.value, (tot.u64, tot.f64)

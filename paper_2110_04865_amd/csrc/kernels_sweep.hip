@@ -1,0 +1,282 @@
+// The multilinear kernel of section 3.1 fused with the projection of
+// Algorithm 2 (lines 9-10), evaluated all-at-once: for every stored
+// direction i->j with key k,
+//     f(p_i, a_ij, p_j) = k if p_i != p_j, else the empty key,
+// reduced with MinWeight (unsigned min of packed keys) over each run of
+// entries whose row shares the same root p_i, and written with one 64-bit
+// atomicMin per run into r[p_i].  The per-vertex minimum q_i of the paper
+// is never materialised: it lives in registers, as in the all-at-once
+// formulation that writes n values instead of nnz (section 4.1).
+//
+// Work split: the nnz stored entries are cut into chunks of SWEEP_CHUNK
+// (one workgroup each), independent of row lengths, so skewed degree
+// distributions (R-MAT) stay balanced.  Each lane owns SWEEP_E consecutive
+// entries (16-byte vector loads of col, two of key); runs that cross lanes
+// are merged with a wave-wide segmented scan; the first and last run of a
+// wave may be partial and are combined through the atomic.
+//
+// COMPACT variant (intra-component edge filtering): entries with
+// p_i == p_j can never become outgoing again (trees only merge), so the
+// sweep also writes the surviving entries, in order, to a second CSR.  The
+// chunk's output offset comes from a decoupled look-back over chunk
+// survivor counts; row_ptr of the output is written by the lane holding each
+// row's first entry.
+#include "msf_internal.hpp"
+#include "wave.hpp"
+
+namespace msf {
+
+namespace {
+
+// largest r in [lo, hi] with row_ptr[r] <= idx (row_ptr[lo] <= idx holds)
+__device__ __forceinline__ uint32_t row_search(const uint32_t *__restrict__ row_ptr, uint32_t lo,
+                                               uint32_t hi, uint32_t idx)
+{
+    while (lo < hi) {
+        uint32_t mid = lo + ((hi - lo + 1) >> 1);
+        if (row_ptr[mid] <= idx) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+struct RunAgg {
+    uint32_t first_root, last_root;
+    uint32_t hib;  // a run boundary lies inside the span
+    uint64_t lrm;  // min over the span's last run
+};
+
+__device__ __forceinline__ RunAgg combine(const RunAgg &a, const RunAgg &b)
+{
+    RunAgg r;
+    const bool boundary = a.last_root != b.first_root;
+    r.first_root = a.first_root;
+    r.last_root = b.last_root;
+    r.hib = a.hib | b.hib | (boundary ? 1u : 0u);
+    r.lrm = (b.hib || boundary) ? b.lrm : (a.lrm < b.lrm ? a.lrm : b.lrm);
+    return r;
+}
+
+}  // namespace
+
+template <bool COMPACT>
+__global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
+    const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
+    const uint64_t *__restrict__ key, const uint32_t *__restrict__ chunk_row, uint32_t nnz,
+    uint32_t nchunks, int32_t n, const uint32_t *__restrict__ p, uint64_t *__restrict__ r,
+    uint32_t *__restrict__ row_ptr_out, uint32_t *__restrict__ col_out,
+    uint64_t *__restrict__ key_out, uint64_t *status, Counters *cnt, uint32_t *block_live)
+{
+    constexpr int E = SWEEP_E;
+    __shared__ uint32_t s_chunk;
+    __shared__ uint32_t s_lds[SWEEP_BLOCK / 64 + 1];
+    __shared__ uint64_t s_prefix;
+
+    uint32_t c;
+    if (COMPACT) {
+        if (threadIdx.x == 0) s_chunk = atomicAdd(&cnt->ticket, 1u);
+        __syncthreads();
+        c = s_chunk;
+    } else {
+        c = blockIdx.x;
+    }
+    const uint32_t lane = __lane_id();
+    const uint32_t base = c * (uint32_t)SWEEP_CHUNK + threadIdx.x * E;
+    const int nvalid = base >= nnz ? 0 : (nnz - base >= (uint32_t)E ? E : (int)(nnz - base));
+
+    uint32_t cl[E];
+    uint64_t ky[E];
+    if (nvalid == E) {
+        const uint4 c4 = *reinterpret_cast<const uint4 *>(col + base);
+        const ulonglong2 k01 = *reinterpret_cast<const ulonglong2 *>(key + base);
+        const ulonglong2 k23 = *reinterpret_cast<const ulonglong2 *>(key + base + 2);
+        cl[0] = c4.x; cl[1] = c4.y; cl[2] = c4.z; cl[3] = c4.w;
+        ky[0] = k01.x; ky[1] = k01.y; ky[2] = k23.x; ky[3] = k23.y;
+    } else {
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            cl[k] = k < nvalid ? col[base + k] : 0u;
+            ky[k] = k < nvalid ? key[base + k] : KEY_INF;
+        }
+    }
+
+    // rows and roots of the lane's entries
+    uint32_t root[E];
+    uint64_t cand[E];
+    uint32_t rowk[E];
+    bool live[E];
+    if (nvalid > 0) {
+        const uint32_t lo = chunk_row[c];
+        const uint32_t hi = chunk_row[c + 1 <= nchunks ? c + 1 : nchunks];
+        uint32_t row = row_search(row_ptr, lo, hi, base);
+        uint32_t nxt = row_ptr[row + 1];
+        uint32_t prow = p[row];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const uint32_t idx = base + k;
+            if (k < nvalid) {
+                if (idx >= nxt) {
+                    row = row_search(row_ptr, row + 1, hi, idx);
+                    nxt = row_ptr[row + 1];
+                    prow = p[row];
+                }
+                const uint32_t pc = p[cl[k]];
+                live[k] = prow != pc;
+                cand[k] = live[k] ? ky[k] : KEY_INF;
+                root[k] = prow;
+                rowk[k] = row;
+            } else {
+                live[k] = false;
+                cand[k] = KEY_INF;
+                root[k] = NONE32;
+                rowk[k] = NONE32;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            live[k] = false;
+            cand[k] = KEY_INF;
+            root[k] = NONE32;
+            rowk[k] = NONE32;
+        }
+    }
+
+    // lane-local runs by root; interior runs are complete and flushed now
+    uint32_t froot = root[0], lroot = root[0];
+    uint64_t fmin = cand[0], lmin = KEY_INF;
+    bool single = true;
+#pragma unroll
+    for (int k = 1; k < E; ++k) {
+        if (k >= nvalid) break;
+        if (root[k] == lroot) {
+            if (single) fmin = fmin < cand[k] ? fmin : cand[k];
+            else lmin = lmin < cand[k] ? lmin : cand[k];
+        } else {
+            if (!single) min_into(r, lroot, lmin);
+            single = false;
+            lroot = root[k];
+            lmin = cand[k];
+        }
+    }
+
+    // wave-wide segmented scan of lane aggregates
+    RunAgg agg;
+    agg.first_root = froot;
+    agg.last_root = lroot;
+    agg.hib = single ? 0u : 1u;
+    agg.lrm = single ? fmin : lmin;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        RunAgg o;
+        o.first_root = __shfl_up(agg.first_root, d, 64);
+        o.last_root = __shfl_up(agg.last_root, d, 64);
+        o.hib = __shfl_up(agg.hib, d, 64);
+        o.lrm = __shfl_up(agg.lrm, d, 64);
+        if (lane >= (uint32_t)d) agg = combine(o, agg);
+    }
+    const uint32_t prev_last = __shfl_up(agg.last_root, 1, 64);
+    const uint64_t prev_lrm = __shfl_up(agg.lrm, 1, 64);
+    uint32_t next_first = __shfl_down(froot, 1, 64);
+    if (lane == 63) next_first = NONE32;
+    if (nvalid > 0) {
+        uint64_t ffull = fmin;
+        if (lane > 0 && prev_last == froot) ffull = ffull < prev_lrm ? ffull : prev_lrm;
+        if (single) {
+            if (next_first != froot) min_into(r, froot, ffull);
+        } else {
+            min_into(r, froot, ffull);
+            if (next_first != lroot) min_into(r, lroot, lmin);
+        }
+    }
+
+    uint32_t lcnt = 0;
+#pragma unroll
+    for (int k = 0; k < E; ++k) lcnt += live[k] ? 1u : 0u;
+
+    if (!COMPACT) {
+        if (block_live) {  // live-entry count of this chunk (filtering policy)
+            uint32_t btot;
+            block_excl_sum<SWEEP_BLOCK>(lcnt, s_lds, &btot);
+            if (threadIdx.x == 0) block_live[c] = btot;
+        }
+        return;
+    }
+
+    // ---- filtering: order-preserving compaction of live entries ----
+    uint32_t btot;
+    const uint32_t lex = block_excl_sum<SWEEP_BLOCK>(lcnt, s_lds, &btot);
+    if (threadIdx.x < 64) {
+        const uint64_t e = lookback(status, c, (uint64_t)btot);
+        if (threadIdx.x == 0) s_prefix = e;
+    }
+    __syncthreads();
+    const uint64_t P = s_prefix;
+    uint32_t pos = (uint32_t)P + lex;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        if (k < nvalid) {
+            const uint32_t idx = base + k;
+            const uint32_t row = rowk[k];
+            if (row_ptr[row] == idx) {
+                // first entry of `row` (and of any empty rows just before it)
+                row_ptr_out[row] = pos;
+                for (int64_t j = (int64_t)row - 1; j >= 0 && row_ptr[j] == idx; --j)
+                    row_ptr_out[j] = pos;
+            }
+            if (live[k]) {
+                col_out[pos] = cl[k];
+                key_out[pos] = ky[k];
+                ++pos;
+            }
+        }
+    }
+    if (c == nchunks - 1) {
+        // rows starting at nnz (trailing empty rows and row_ptr[n])
+        const uint32_t total = (uint32_t)(P + btot);
+        const uint32_t last_row = chunk_row[nchunks];
+        for (int64_t j = (int64_t)last_row + 1 + threadIdx.x; j <= n; j += SWEEP_BLOCK)
+            row_ptr_out[j] = total;
+        if (threadIdx.x == 0) cnt->nnz_out = total;
+    }
+}
+
+__global__ void k_reduce_live(const uint32_t *__restrict__ block_live, uint32_t nchunks,
+                              Counters *cnt)
+{
+    uint64_t s = 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nchunks;
+         i += gridDim.x * blockDim.x)
+        s += block_live[i];
+    s = wave_sum(s);
+    if (__lane_id() == 0 && s) atomicAdd((unsigned long long *)&cnt->live, (unsigned long long)s);
+}
+
+void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
+                  uint32_t *block_live, Counters *dcnt)
+{
+    if (a.nnz == 0) return;
+    k_sweep<false><<<a.nchunks, SWEEP_BLOCK, 0, s>>>(a.row_ptr, a.col, a.key, a.chunk_row, a.nnz,
+                                                     a.nchunks, a.n, p, r, nullptr, nullptr,
+                                                     nullptr, nullptr, nullptr, block_live);
+    if (block_live && dcnt) {
+        launch_fill_u64(s, &dcnt->live, 0ull, 1);
+        unsigned g = (a.nchunks + 255) / 256;
+        if (g > 64) g = 64;
+        k_reduce_live<<<g, 256, 0, s>>>(block_live, a.nchunks, dcnt);
+    }
+}
+
+void launch_sweep_compact(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
+                          uint32_t *row_ptr_out, uint32_t *col_out, uint64_t *key_out,
+                          uint64_t *status, Counters *dcnt)
+{
+    if (a.nnz == 0) return;
+    launch_fill_u64(s, status, 0ull, a.nchunks);
+    launch_fill_u32(s, &dcnt->ticket, 0u, 1);
+    k_sweep<true><<<a.nchunks, SWEEP_BLOCK, 0, s>>>(a.row_ptr, a.col, a.key, a.chunk_row, a.nnz,
+                                                    a.nchunks, a.n, p, r, row_ptr_out, col_out,
+                                                    key_out, status, dcnt, nullptr);
+}
+
+}  // namespace msf

@@ -1,0 +1,222 @@
+// Internal declarations of the gfx950 MSF library (not part of the C ABI).
+//
+// Device data layout (all arrays in HBM, 256-byte aligned):
+//   adjacency  CSR over all n vertices, both directions of every non-loop
+//              edge stored (the symmetric adjacency matrix A of section 2):
+//                row_ptr u32[n+1], col u32[nnz], key u64[nnz]  (SoA)
+//              key = (u64)wkey(w_e) << 32 | e, identical in both directions.
+//   chunk_row  u32[nchunks+1]: row holding the first entry of each sweep chunk
+//   p          u32[n]  parent vector (a star forest at every round start)
+//   r          u64[n]  per-root minimum outgoing key (UINT64_MAX = none)
+//   h          u32[n]  hook targets, then roots after shortcutting
+//   hedge      u32[n]  edge id each root hooked with
+//   R, F       u32[n]  compacted lists: live roots, roots that hooked
+//   in_forest  u8[m]   forest flags
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <string>
+
+#include "../../include/msf.h"
+
+namespace msf {
+
+constexpr uint64_t KEY_INF = ~0ull;
+constexpr uint32_t NONE32 = 0xFFFFFFFFu;
+
+// Sweep geometry: a workgroup of SWEEP_BLOCK lanes handles SWEEP_E
+// consecutive entries per lane (one chunk of SWEEP_BLOCK*SWEEP_E entries).
+constexpr int SWEEP_BLOCK = 256;
+constexpr int SWEEP_E = 4;
+constexpr int SWEEP_CHUNK = SWEEP_BLOCK * SWEEP_E;
+
+// Device error flags raised by validation kernels.
+enum : uint32_t { ERR_ENDPOINT = 1u, ERR_NAN = 2u, ERR_PARENT = 4u, ERR_CYCLE = 8u };
+
+// ---------------------------------------------------------------- device --
+
+// Order-preserving unsigned key of a float32 weight: -0.0 is +0.0;
+// negative values have every bit flipped, non-negative ones gain the sign
+// bit, so unsigned comparison of keys follows float comparison.
+__device__ __forceinline__ uint32_t wkey_f32_bits(uint32_t b)
+{
+    if (b == 0x80000000u) b = 0u;
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ __forceinline__ uint64_t load_relaxed_u64(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_relaxed_u32(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_relaxed_u32(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// r[slot] <- min(r[slot], v), skipping the atomic when a plain read already
+// shows a value <= v (r only decreases within a sweep, so a stale read can
+// only cause an unnecessary atomic, never a missed one).
+__device__ __forceinline__ void min_into(uint64_t *r, uint32_t slot, uint64_t v)
+{
+    if (v == KEY_INF) return;
+    uint64_t cur = load_relaxed_u64(r + slot);
+    if (v < cur) __hip_atomic_fetch_min(r + slot, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------------ host --
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t cap = 0;
+};
+
+// Workspace slots cached per context (grow-only).
+enum Slot {
+    WS_EDGES, WS_W, WS_SLOT, WS_DEG, WS_ROWPTR, WS_COL, WS_KEY, WS_CHUNKROW,
+    WS_ROWPTR2, WS_COL2, WS_KEY2, WS_CHUNKROW2,
+    WS_P, WS_R, WS_H, WS_HEDGE, WS_RL, WS_RL2, WS_FL, WS_FLAGS, WS_IDS,
+    WS_STATUS, WS_SCRATCH, WS_Q, WS_Q2,
+    WS_BATCH0, WS_BATCH1, WS_BATCH2, WS_BATCH3,
+    WS_COUNT
+};
+
+// Small device-side counters, mirrored to pinned host memory per round.
+struct Counters {
+    uint32_t err;         // ERR_* flags
+    uint32_t nR;          // live roots for the next round
+    uint32_t nF;          // roots that hooked this round
+    uint32_t hooks;       // hooks kept after tie breaking
+    uint32_t max_chase;   // longest shortcut chase
+    uint32_t ticket;      // tile ticket for look-back scans
+    uint32_t nnz_out;     // survivors of a compaction
+    uint32_t count;       // generic output count
+    uint32_t inf_pos;     // +inf forest weights
+    uint32_t inf_neg;     // -inf forest weights
+    uint64_t total_u64;   // forest weight (uint32 weights)
+    int64_t acc[10];      // exact float accumulator: signed 32-bit digits
+    double total_f64;     // finalised forest weight
+    uint64_t live;        // live entries counted by the last plain sweep
+    uint32_t rows;        // rows with stored entries (counted by update)
+    uint32_t pad_;
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    DevBuf ws[WS_COUNT];
+    Counters *dcnt = nullptr;   // device
+    Counters *hcnt = nullptr;   // pinned host mirror
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t sev[2 * 64] = {};  // sweep start/end events, per round
+    msf_stats stats{};
+    int filter_mode = 1;        // 0 never, 1 adaptive, 2 every round
+    double filter_threshold = 0.80;
+    bool check_rounds = false;  // read back error flags after every shortcut
+};
+
+// Device view of an adjacency structure.
+struct Adj {
+    int32_t n = 0;
+    int64_t m = 0;
+    uint32_t nnz = 0;
+    uint32_t *row_ptr = nullptr;
+    uint32_t *col = nullptr;
+    uint64_t *key = nullptr;
+    uint32_t *chunk_row = nullptr;
+    uint32_t nchunks = 0;
+    const int32_t *edges = nullptr;   // endpoint pairs, for hook decoding
+    const void *w = nullptr;          // weights, for totals
+    msf_wtype wtype = MSF_W_U32;
+};
+
+// Error reporting (thread-local message).
+void set_error(const char *fmt, ...);
+msf_status hip_fail(hipError_t e, const char *what);
+
+#define MSF_HIP(call)                                              \
+    do {                                                           \
+        hipError_t _e = (call);                                    \
+        if (_e != hipSuccess) return msf::hip_fail(_e, #call);     \
+    } while (0)
+
+#define MSF_TRY(call)                                              \
+    do {                                                           \
+        msf_status _s = (call);                                    \
+        if (_s != MSF_OK) return _s;                               \
+    } while (0)
+
+// Workspace: returns a device buffer of at least `bytes` for slot s.
+msf_status ws_get(Ctx *c, Slot s, size_t bytes, void **out);
+
+// Sync the context stream and copy the counters to the host mirror.
+msf_status read_counters(Ctx *c);
+
+// ---- kernels (launch wrappers), all ordered on c->stream -----------------
+
+// Adjacency build (section 2 adjacency matrix, both directions).
+msf_status build_adjacency(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
+                           msf_wtype wt, Adj *a, uint32_t *row_ptr, uint32_t *col, uint64_t *key,
+                           uint32_t *deg_tmp, uint2 *slot_tmp, uint32_t *chunk_row);
+uint32_t sweep_nchunks(uint32_t nnz);
+// Exclusive scan of u32 in[0..N) -> out[0..N]; out[N] (and *total_out,
+// nullable, device) receive the total.
+msf_status scan_u32(Ctx *c, const uint32_t *in, uint32_t *out, int64_t N, uint32_t *total_out);
+void launch_chunk_rows(hipStream_t s, const uint32_t *row_ptr, int32_t n, uint32_t nnz,
+                       uint32_t *chunk_row, uint32_t nchunks);
+
+// Multilinear sweep (+ optional compaction into out_*).
+void launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t v, size_t n);
+void launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, size_t n);
+void launch_iota_u32(hipStream_t s, uint32_t *p, size_t n);
+void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
+                  uint32_t *block_live = nullptr, Counters *dcnt = nullptr);
+void launch_sweep_compact(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
+                          uint32_t *row_ptr_out, uint32_t *col_out, uint64_t *key_out,
+                          uint64_t *status, Counters *dcnt);
+
+// Round kernels.
+void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, uint32_t *R,
+                       Counters *dcnt);
+void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, const uint32_t *p,
+                 const int32_t *edges, uint32_t *h, uint32_t *hedge);
+void launch_tiebreak(hipStream_t s, const uint32_t *R, uint32_t nR, uint32_t *h,
+                     const uint32_t *hedge, uint8_t *in_forest, uint32_t *Rnext, uint32_t *F,
+                     Counters *dcnt);
+void launch_chase(hipStream_t s, const uint32_t *F, uint32_t nF, uint32_t *h, Counters *dcnt);
+void launch_update_parents(hipStream_t s, const uint32_t *row_ptr, int32_t n, uint32_t *p,
+                           const uint32_t *h, Counters *dcnt);
+void launch_output(hipStream_t s, const uint8_t *in_forest, int64_t m, const void *w,
+                   msf_wtype wt, int32_t *ids, uint64_t *status, Counters *dcnt);
+void launch_finalize_total(hipStream_t s, Counters *dcnt, msf_wtype wt);
+int64_t output_tiles(int64_t m);
+
+// Shortcut of an arbitrary parent vector (msf_shortcut).
+void launch_check_parents(hipStream_t s, const uint32_t *p, int32_t n, Counters *dcnt);
+void launch_jump_init(hipStream_t s, const uint32_t *q, int32_t n, uint32_t *F, Counters *dcnt);
+void launch_jump_pass(hipStream_t s, const uint32_t *Fin, uint32_t nF, uint32_t *q,
+                      uint32_t *Fout, Counters *dcnt);
+void launch_check_roots(hipStream_t s, const uint32_t *p, const uint32_t *q, int32_t n,
+                        Counters *dcnt);
+
+// Whole-graph solve on prepared device inputs; writes ids (device) and
+// fills count/total.  `keep_adj` graphs are left intact (msf_graph path).
+msf_status solve_device(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
+                        msf_wtype wt, int32_t *d_ids, int64_t *count, msf_total *total);
+
+}  // namespace msf
+
+struct msf_ctx {
+    msf::Ctx c;
+};
+
+struct msf_graph {
+    msf_ctx *ctx = nullptr;
+    msf::Adj a;
+    void *bufs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+};

@@ -1,0 +1,120 @@
+// Wave64 and workgroup primitives for gfx950, plus the single-pass
+// decoupled look-back prefix used by every order-preserving compaction
+// (Merrill and Garland, "Single-pass Parallel Prefix Scan with Decoupled
+// Look-back", NVIDIA tech report NVR-2016-002; restated for 64-lane waves).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msf {
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_sum(T v)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T o = __shfl_up(v, d, 64);
+        if (__lane_id() >= d) v += o;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        uint64_t o = __shfl_xor(v, d, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// Exclusive prefix sum over a workgroup of NT threads (NT/64 waves).
+// Returns this thread's exclusive prefix; *total receives the block sum.
+// `lds` must hold NT/64 + 1 elements.  Contains __syncthreads().
+template <int NT, typename T>
+__device__ __forceinline__ T block_excl_sum(T v, T *lds, T *total)
+{
+    constexpr int NW = NT / 64;
+    const int w = threadIdx.x >> 6;
+    T inc = wave_incl_sum(v);
+    if (__lane_id() == 63) lds[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T s = 0;
+        for (int i = 0; i < NW; ++i) {
+            T t = lds[i];
+            lds[i] = s;
+            s += t;
+        }
+        lds[NW] = s;
+    }
+    __syncthreads();
+    T r = lds[w] + inc - v;
+    *total = lds[NW];
+    return r;
+}
+
+// ---- decoupled look-back ---------------------------------------------------
+// status[t] = flag << 62 | value; flag 1 = tile aggregate, 2 = inclusive
+// prefix.  The status array must be zero before the launch, and tiles must
+// be numbered in the order they start (take them from an atomic ticket), so
+// a tile only ever waits on tiles that are already running or done.
+
+constexpr uint64_t LB_AGG = 1ull << 62;
+constexpr uint64_t LB_PRE = 2ull << 62;
+constexpr uint64_t LB_VAL = (1ull << 62) - 1ull;
+
+__device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by all 64 lanes of ONE wave.  Returns the exclusive prefix of
+// `tile` (identical in every lane) and publishes its inclusive prefix.
+__device__ __forceinline__ uint64_t lookback(uint64_t *status, uint32_t tile, uint64_t agg)
+{
+    const int lane = __lane_id();
+    if (tile == 0) {
+        if (lane == 0) lb_store(status, LB_PRE | agg);
+        return 0;
+    }
+    if (lane == 0) lb_store(status + tile, LB_AGG | agg);
+    uint64_t excl = 0;
+    int64_t base = (int64_t)tile - 1;
+    for (;;) {
+        const int64_t t = base - lane;
+        uint64_t s = LB_PRE;  // virtual tile before 0: prefix 0
+        if (t >= 0) s = __hip_atomic_load(status + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t flag = (uint32_t)(s >> 62);
+        const uint64_t pmask = __ballot(flag == 2u);
+        const uint64_t zmask = __ballot(flag == 0u);
+        const int first = pmask ? (int)__builtin_ctzll(pmask) : 64;
+        const uint64_t need = (first >= 63) ? ~0ull : ((2ull << first) - 1ull);
+        if (zmask & need) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;  // a needed predecessor has not published yet
+        }
+        uint64_t v = (lane <= first) ? (s & LB_VAL) : 0ull;
+        excl += wave_sum(v);
+        if (first < 64) break;
+        base -= 64;
+    }
+    if (lane == 0) lb_store(status + tile, LB_PRE | (excl + agg));
+    return excl;
+}
+
+}  // namespace msf

@@ -1,0 +1,70 @@
+"""Host-side checks of the C ABI library (no GPU needed, no compute calls)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2110_04865_amd as pkg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "msf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(msf_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_is_built_for_gfx950():
+    assert os.path.exists(pkg.SO_PATH), "run __graft_entry__.build() first"
+    out = subprocess.run(["/opt/rocm/bin/roc-obj-ls", pkg.SO_PATH], capture_output=True,
+                         text=True)
+    if out.returncode == 0 and out.stdout.strip():
+        assert "gfx950" in out.stdout
+
+
+def test_exports_every_declared_symbol():
+    L = ctypes.CDLL(pkg.SO_PATH)
+    names = declared_functions()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(L, name), f"{name} declared in msf.h but not exported"
+    assert set(names) == set(pkg.EXPORTS)
+
+
+def test_binding_loads_and_reports_version():
+    L = pkg.lib()
+    assert L.msf_version().decode().startswith("msf-gfx950")
+    assert L.msf_last_error() is not None
+
+
+def test_footprint_monotone():
+    a = pkg.footprint(1000, 4000)
+    b = pkg.footprint(2000, 4000)
+    c = pkg.footprint(2000, 8000)
+    assert 0 < a < b < c
+
+
+def test_null_arguments_are_rejected_without_device():
+    L = pkg.lib()
+    # NULL context: rejected before any device call
+    cnt = ctypes.c_int64(-7)
+    rc = L.msf_solve(None, 3, 1, None, None, 0, 0, None, ctypes.byref(cnt), None)
+    assert rc == 1 and cnt.value == -7
+    assert b"ctx" in L.msf_last_error()
+    rc = L.msf_shortcut(None, 3, None, None)
+    assert rc == 1
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd") and os.access("/dev/kfd", os.R_OK),
+                    reason="a GPU is present")
+def test_context_without_gpu_fails_cleanly():
+    L = pkg.lib()
+    h = ctypes.c_void_p()
+    rc = L.msf_ctx_create(0, None, ctypes.byref(h))
+    assert rc in (3, 1)  # MSF_EDEVICE (no device) or MSF_EINVAL
+    assert not h.value

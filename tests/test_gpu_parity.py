@@ -1,0 +1,375 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Bar: the forest is unique under the (weight, edge id) order, so edge ids,
+count and both totals must match the oracle exactly (tolerance 0).  The
+multilinear kernel and the shortcut are compared element by element with
+their oracle definitions.
+"""
+import math
+import os
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+U32, F32 = oracle.W_U32, oracle.W_F32
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_04865_amd as p
+    p.lib()
+    return p
+
+
+@pytest.fixture(scope="module")
+def ctx(pkg):
+    c = pkg.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a.reshape(-1).copy()).to("cuda:0")
+
+
+def check_solve(ctx, pkg, n, e, w, wt, label, device=True):
+    say(label, f"n={n} m={len(e)} wt={wt} device={device}")
+    want_ids, want_cnt, want_tot = oracle.msf(n, e, w, wt)
+    if device:
+        ids, cnt, tot = ctx.solve(n, dev(e), dev(w), wtype=wt)
+        torch.cuda.synchronize()
+        got = ids.cpu().numpy().astype(np.int64)
+    else:
+        got, cnt, tot = ctx.solve(n, e, w, wtype=wt)
+        got = got.astype(np.int64)
+    assert cnt == want_cnt, (label, cnt, want_cnt)
+    assert np.array_equal(got, want_ids), label
+    if wt == U32:
+        assert tot[0] == want_tot[0], (label, tot, want_tot)
+    assert tot[1] == want_tot[1] or (math.isnan(tot[1]) and math.isnan(want_tot[1])), \
+        (label, tot, want_tot)
+    return ctx.stats()
+
+
+# ----------------------------------------------------------- small cases --
+
+def test_er4096_many_seeds(ctx, pkg):
+    for seed in range(1, 11):
+        e, w = gen.er(4096, 32768, seed=seed)
+        check_solve(ctx, pkg, 4096, e, w, U32, f"er4096 seed={seed}", device=seed % 2 == 0)
+
+
+def test_er4096_golden(ctx, pkg):
+    import json
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "er4096_seed1.json")))
+    n, e, w = gen.workload_er_4096()
+    ids, cnt, tot = ctx.solve(n, e, w, wtype=U32)
+    assert cnt == g["count"] and tot[0] == g["total_u64"]
+    assert int(np.asarray(ids, dtype=np.int64).sum()) == g["id_sum"]
+
+
+def test_tiny_random_graphs(ctx, pkg):
+    rng = random.Random(7)
+    for t in range(150):
+        n = rng.randint(0, 40)
+        m = rng.randint(0, 120) if n > 0 else 0
+        e = np.array([[rng.randrange(n), rng.randrange(n)] for _ in range(m)],
+                     dtype=np.int32).reshape(-1, 2)
+        if t % 2:
+            w = np.array([rng.randint(0, 5) for _ in range(m)], dtype=np.uint32)
+            wt = U32
+        else:
+            w = np.array([rng.choice([-2.5, -0.0, 0.0, 1.0, 3.25, 1e-30, -1e30])
+                          for _ in range(m)], dtype=np.float32)
+            wt = F32
+        check_solve(ctx, pkg, n, e, w, wt, f"tiny t={t}", device=(t % 3 == 0 and m > 0))
+
+
+def test_ragged_sizes_span_tiles(ctx, pkg):
+    # nnz around multiples of the 1024-entry sweep chunk and the 4096-edge
+    # output tile, plus a long row (star) spanning many chunks
+    for m in (511, 512, 513, 1023, 2047, 2049, 4095, 4097, 5000):
+        n = max(64, m // 3)
+        e, w = gen.er(n, m, seed=m)
+        check_solve(ctx, pkg, n, e, w, U32, f"ragged m={m}")
+    n = 20000
+    e = np.stack([np.zeros(n - 1, np.int32), np.arange(1, n, dtype=np.int32)], 1)
+    e2, _ = gen.er(n, 30000, seed=5)
+    e = np.concatenate([e, e2])
+    w = gen.weights(len(e), gen.W_U32, seed=9)
+    check_solve(ctx, pkg, n, e, w, U32, "star+er")
+
+
+def test_isolated_and_empty_rows(ctx, pkg):
+    # long runs of isolated vertices between and after the used ones
+    e = np.array([[0, 1], [1, 2], [2000000, 2000001], [0, 2], [2000001, 1999999]], np.int32)
+    w = np.array([5, 3, 9, 1, 2], np.uint32)
+    check_solve(ctx, pkg, 3000000, e, w, U32, "isolated runs")
+    check_solve(ctx, pkg, 5, np.zeros((0, 2), np.int32), np.zeros(0, np.uint32), U32, "m=0",
+                device=False)
+    check_solve(ctx, pkg, 0, np.zeros((0, 2), np.int32), np.zeros(0, np.uint32), U32, "n=0",
+                device=False)
+
+
+def test_float_specials(ctx, pkg):
+    e, _ = gen.er(300, 900, seed=3)
+    rng = np.random.default_rng(3)
+    for case in range(4):
+        w = (rng.standard_normal(900) * 10.0 ** rng.integers(-30, 30, 900)).astype(np.float32)
+        if case == 1:
+            w[::7] = np.inf
+        if case == 2:
+            w[::5] = -np.inf
+        if case == 3:
+            w[::11] = -0.0
+            w[1::11] = 0.0
+        check_solve(ctx, pkg, 300, e, w, F32, f"float specials {case}")
+
+
+def test_ties_and_parallel_edges(ctx, pkg):
+    e, _ = gen.er(2000, 12000, seed=4)
+    e = np.concatenate([e, e[::3], e[::7, ::-1]])  # parallel edges, both orientations
+    w = (np.arange(len(e)) % 4).astype(np.uint32)
+    check_solve(ctx, pkg, 2000, e, w, U32, "ties+parallel")
+    w = np.full(len(e), 7, np.uint32)
+    check_solve(ctx, pkg, 2000, e, w, U32, "all equal")
+
+
+def test_invalid_inputs_leave_outputs_untouched(ctx, pkg):
+    L = pkg.lib()
+    import ctypes
+    for e, w, wt, what in [
+        (np.array([[0, 1], [1, 5]], np.int32), np.array([1, 2], np.uint32), U32, "endpoint"),
+        (np.array([[0, 1], [-1, 0]], np.int32), np.array([1, 2], np.uint32), U32, "negative"),
+        (np.array([[0, 1]], np.int32), np.array([np.nan], np.float32), F32, "nan"),
+    ]:
+        say("invalid", what)
+        ids = np.full(4, -5, np.int32)
+        cnt = ctypes.c_int64(-9)
+        tot = pkg.Total(123, 4.5)
+        rc = L.msf_solve(ctx._h, 3, len(w), ctypes.c_void_p(e.ctypes.data),
+                         ctypes.c_void_p(w.ctypes.data), wt, 0,
+                         ctypes.c_void_p(ids.ctypes.data), ctypes.byref(cnt), ctypes.byref(tot))
+        assert rc == 1, what
+        assert cnt.value == -9 and (ids == -5).all() and tot.u64 == 123
+    with pytest.raises(pkg.MSFError):
+        ctx.solve(-1, np.zeros((0, 2), np.int32), np.zeros(0, np.uint32), wtype=U32)
+
+
+# ---------------------------------------------------- per-round behaviour --
+
+def test_rounds_match_algorithm2_oracle(ctx, pkg):
+    for label, (n, e, w, wt) in {
+        "er": (2000, *gen.er(2000, 8000, seed=2), U32),
+        "rmat12": (*gen.rmat(12, 16, seed=2), F32),
+        "grid16": (*gen.grid(16, 16, 16, 0.05, seed=3), U32),
+        "grid12-40": (*gen.grid(12, 12, 12, 0.4, seed=3), U32),
+    }.items():
+        ref = oracle.as_rounds(n, e, w, wt)
+        st = check_solve(ctx, pkg, n, e, w, wt, f"rounds {label}")
+        hooks = [h for h in ref["hooks"] if h]
+        assert st["hooks"][:len(hooks)] == hooks, (label, st["hooks"], hooks)
+        assert st["hook_rounds"] == len(hooks)
+        assert st["hook_rounds"] <= max(1, int(math.floor(math.log2(max(n, 2)))))
+
+
+def test_filter_policies_are_result_invariant(pkg):
+    n, e, w = gen.grid(24, 24, 24, 0.05, seed=3)
+    n2, e2, w2 = gen.rmat(13, 16, seed=2)
+    old = os.environ.get("MSF_FILTER")
+    try:
+        for mode in ("0", "1", "2"):
+            os.environ["MSF_FILTER"] = mode
+            c = pkg.Context(0)
+            st = check_solve(c, pkg, n, e, w, U32, f"filter mode {mode} grid")
+            if mode == "2":
+                assert st["filtered"] >= 1
+            check_solve(c, pkg, n2, e2, w2, F32, f"filter mode {mode} rmat")
+            c.close()
+    finally:
+        if old is None:
+            os.environ.pop("MSF_FILTER", None)
+        else:
+            os.environ["MSF_FILTER"] = old
+
+
+# ---------------------------------------------------------- multilinear --
+
+def multilinear_case(ctx, pkg, n, e, w, wt, p, label):
+    say("multilinear", label, f"n={n} m={len(e)}")
+    g = pkg.Graph(ctx, n, e, w, wtype=wt)
+    dp = dev(np.asarray(p, np.uint32))
+    dr = torch.empty(max(n, 1), dtype=torch.int64, device="cuda:0")
+    ctx.multilinear(g, dp, dr)
+    torch.cuda.synchronize()
+    got = dr.cpu().numpy()[:n].view(np.uint64)
+    want = oracle.multilinear(n, e, w, wt, p)
+    assert np.array_equal(got, want), label
+    g.close()
+
+
+def test_multilinear_matches_definition(ctx, pkg):
+    rng = np.random.default_rng(1)
+    for label, (n, e, w, wt) in {
+        "er4096": (4096, *gen.er(4096, 32768, seed=1), U32),
+        "rmat14": (*gen.rmat(14, 16, seed=2), F32),
+        "grid20": (*gen.grid(20, 20, 20, 0.05, seed=3), U32),
+        "ragged": (3001, *gen.er(3001, 7777, seed=8), U32),
+    }.items():
+        ident = np.arange(n, dtype=np.uint32)
+        multilinear_case(ctx, pkg, n, e, w, wt, ident, label + " identity")
+        roots = rng.choice(n, size=max(1, n // 50), replace=False).astype(np.uint32)
+        star = roots[rng.integers(0, len(roots), n)]
+        star[roots] = roots
+        multilinear_case(ctx, pkg, n, e, w, wt, star, label + " stars")
+        arb = rng.integers(0, n, n).astype(np.uint32)
+        multilinear_case(ctx, pkg, n, e, w, wt, arb, label + " arbitrary")
+        sorted_blocks = (np.arange(n) // 7 * 7).astype(np.uint32)  # runs of equal roots
+        multilinear_case(ctx, pkg, n, e, w, wt, sorted_blocks, label + " blocks")
+
+
+def test_multilinear_rejects_bad_parent(ctx, pkg):
+    n, e, w = 100, *gen.er(100, 300, seed=1)
+    g = pkg.Graph(ctx, n, e, w, wtype=U32)
+    p = np.arange(n, dtype=np.uint32)
+    p[5] = 1000
+    dr = torch.zeros(n, dtype=torch.int64, device="cuda:0")
+    with pytest.raises(pkg.MSFError):
+        ctx.multilinear(g, dev(p), dr)
+    torch.cuda.synchronize()
+    assert (dr.cpu().numpy() == 0).all()
+    g.close()
+
+
+# ------------------------------------------------------------- shortcut --
+
+def test_shortcut_matches_find_roots(ctx, pkg):
+    rng = np.random.default_rng(2)
+    for n in (1, 2, 1000, 65537, 1 << 20):
+        par = np.minimum(np.arange(n), rng.integers(0, n, n)).astype(np.uint32)
+        perm = rng.permutation(n).astype(np.uint32)
+        inv = np.empty_like(perm)
+        inv[perm] = np.arange(n, dtype=np.uint32)
+        p = perm[par[inv]]
+        say("shortcut", n)
+        dp = dev(p)
+        passes = ctx.shortcut(dp)
+        torch.cuda.synchronize()
+        got = dp.cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, oracle.find_roots(p)), n
+        assert passes <= max(1, math.ceil(math.log2(max(n, 2)))) + 1
+    # a long chain: depth n-1
+    n = 1 << 18
+    p = np.maximum(np.arange(n) - 1, 0).astype(np.uint32)[rng.permutation(n)]
+    p = np.arange(n, dtype=np.uint32)
+    order = rng.permutation(n)
+    p[order[1:]] = order[:-1]
+    say("shortcut chain", n)
+    dp = dev(p)
+    ctx.shortcut(dp)
+    torch.cuda.synchronize()
+    assert np.array_equal(dp.cpu().numpy().view(np.uint32), oracle.find_roots(p))
+
+
+def test_shortcut_rejects_cycles(ctx, pkg):
+    for p in ([1, 0, 2], [1, 2, 0, 3], [0, 2, 3, 1, 4, 4], [0, 7]):
+        say("shortcut cycle", p)
+        p = np.array(p, np.uint32)
+        dp = dev(p)
+        with pytest.raises(pkg.MSFError):
+            ctx.shortcut(dp)
+        torch.cuda.synchronize()
+        assert np.array_equal(dp.cpu().numpy().view(np.uint32), p)  # untouched
+
+
+# --------------------------------------------------------------- batched --
+
+def test_batched_equals_oracle_per_graph(ctx, pkg):
+    vo, eo, e, w = gen.batch(200, seed=4)
+    say("batched 200 graphs", int(vo[-1]), int(eo[-1]))
+    ids, counts, totals = ctx.solve_batched(vo, eo, e, w, wtype=U32)
+    for g in range(200):
+        n = int(vo[g + 1] - vo[g])
+        ee, ww = e[eo[g]:eo[g + 1]], w[eo[g]:eo[g + 1]]
+        wi, wc, wtot = oracle.msf(n, ee, ww, U32)
+        assert counts[g] == wc, g
+        assert np.array_equal(ids[vo[g]:vo[g] + wc].astype(np.int64), wi), g
+        assert totals[g][0] == wtot[0] and totals[g][1] == wtot[1], g
+
+
+def test_batched_device_float_and_solo_agree(ctx, pkg):
+    vo, eo, e, _ = gen.batch(64, seed=6, lo=16, hi=3000)
+    w = gen.weights(len(e), gen.W_F32, seed=6)
+    w[::13] = -w[::13]
+    say("batched device f32", int(vo[-1]), int(eo[-1]))
+    ids, counts, totals = ctx.solve_batched(vo, eo, dev(e), dev(w), wtype=F32)
+    torch.cuda.synchronize()
+    ids = ids.cpu().numpy()
+    for g in range(64):
+        n = int(vo[g + 1] - vo[g])
+        ee, ww = e[eo[g]:eo[g + 1]], w[eo[g]:eo[g + 1]]
+        si, sc, stot = ctx.solve(n, ee, ww, wtype=F32)
+        wi, wc, wtot = oracle.msf(n, ee, ww, F32)
+        assert sc == wc == counts[g], g
+        assert np.array_equal(si.astype(np.int64), wi)
+        assert np.array_equal(ids[vo[g]:vo[g] + wc].astype(np.int64), wi)
+        assert totals[g][1] == stot[1] == wtot[1]
+
+
+def test_batched_rejects_out_of_graph_endpoint(ctx, pkg):
+    vo = np.array([0, 3, 6], np.int64)
+    eo = np.array([0, 1, 2], np.int64)
+    e = np.array([[0, 1], [2, 3]], np.int32)  # 3 is outside graph 1 (n=3)
+    w = np.array([1, 2], np.uint32)
+    with pytest.raises(pkg.MSFError):
+        ctx.solve_batched(vo, eo, e, w, wtype=U32)
+
+
+# ------------------------------------------------------------ full sizes --
+
+def test_full_rmat_s22(ctx, pkg):
+    n, e, w = gen.workload_rmat_s22()
+    st = check_solve(ctx, pkg, n, e, w, F32, "rmat s22 full")
+    say("rmat s22 stats", st)
+
+
+def test_full_grid_256(ctx, pkg):
+    n, e, w = gen.workload_grid_256()
+    st = check_solve(ctx, pkg, n, e, w, U32, "grid 256^3 full")
+    say("grid stats", st)
+
+
+def test_full_batch_sampled(ctx, pkg):
+    vo, eo, e, w = gen.workload_batch_10k()
+    say("batch 10k full", int(vo[-1]), int(eo[-1]))
+    ids, counts, totals = ctx.solve_batched(vo, eo, dev(e), dev(w), wtype=U32)
+    torch.cuda.synchronize()
+    ids = ids.cpu().numpy()
+    for g in list(range(0, 10000, 97)) + [9999]:
+        n = int(vo[g + 1] - vo[g])
+        ee, ww = e[eo[g]:eo[g + 1]], w[eo[g]:eo[g + 1]]
+        wi, wc, wtot = oracle.msf(n, ee, ww, U32)
+        assert counts[g] == wc, g
+        assert np.array_equal(ids[vo[g]:vo[g] + wc].astype(np.int64), wi), g
+        assert totals[g][0] == wtot[0], g
+    # every graph: count = n - components is implied by the forest; check sums
+    assert int(counts.sum()) == int(sum(counts))
