@@ -96,6 +96,7 @@ struct SolveBufs {
     uint32_t *deg, *rp[2], *col[2], *crow[2], *p, *h, *hedge, *R[2], *F, *blive;
     uint64_t *key[2], *r, *status;
     uint8_t *flags;
+    void *part;
 };
 
 static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, SolveBufs *b)
@@ -105,12 +106,11 @@ static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, SolveBufs *b)
     const size_t nch = sweep_nchunks((uint32_t)std::min<size_t>(nnz_cap, 0xFFFFFFFFull)) + 2;
     size_t st = std::max<size_t>(nch, (size_t)output_tiles((int64_t)mm) + 1);
     st = std::max<size_t>(st, nn / 2048 + 2);
+    const size_t part_bytes = std::max<size_t>(output_part_bytes((int64_t)mm), 4 * 4096 + 256);
     void *v[22];
     msf_status rc;
 #define GET(i, slot, bytes)                                  \
     if ((rc = ws_get(c, slot, (bytes), &v[i])) != MSF_OK) return rc;
-    GET(0, WS_SLOT, sizeof(uint2) * mm);
-    GET(1, WS_DEG, 4 * nn);
     GET(2, WS_ROWPTR, 4 * (nn + 1));
     GET(3, WS_COL, 4 * nnz_cap);
     GET(4, WS_KEY, 8 * nnz_cap);
@@ -125,9 +125,8 @@ static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, SolveBufs *b)
     GET(13, WS_FLAGS, (mm + 16) & ~(size_t)3);
     GET(14, WS_STATUS, 8 * st);
     GET(15, WS_SCRATCH, 4 * nch);
+    GET(16, WS_PART, part_bytes);
 #undef GET
-    b->slot = (uint2 *)v[0];
-    b->deg = (uint32_t *)v[1];
     b->rp[0] = (uint32_t *)v[2];
     b->col[0] = (uint32_t *)v[3];
     b->key[0] = (uint64_t *)v[4];
@@ -142,6 +141,7 @@ static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, SolveBufs *b)
     b->flags = (uint8_t *)v[13];
     b->status = (uint64_t *)v[14];
     b->blive = (uint32_t *)v[15];
+    b->part = v[16];
     b->rp[1] = b->col[1] = b->crow[1] = nullptr;
     b->key[1] = nullptr;
     return MSF_OK;
@@ -178,8 +178,7 @@ msf_status solve_device(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, co
     MSF_HIP(hipEventRecord(c->ev[0], s));
     zero_counters(c);
     Adj a;
-    rc = build_adjacency(c, n, m, d_edges, d_w, wt, &a, b.rp[0], b.col[0], b.key[0], b.deg,
-                         b.slot, b.crow[0]);
+    rc = build_adjacency(c, n, m, d_edges, d_w, wt, &a, b.rp[0], b.col[0], b.key[0], b.crow[0]);
     if (rc) return rc;
     MSF_TRY(read_counters(c));
     if ((rc = decode_err(c->hcnt->err))) return rc;
@@ -193,7 +192,7 @@ msf_status solve_device(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, co
     launch_iota_u32(s, b.h, (size_t)n);
     launch_fill_u64(s, b.r, KEY_INF, (size_t)n);
     launch_fill_u32(s, reinterpret_cast<uint32_t *>(b.flags), 0u, ((size_t)m + 3) / 4);
-    launch_init_roots(s, a.row_ptr, n, b.R[0], c->dcnt);
+    launch_init_roots(s, a.row_ptr, n, b.R[0], b.status, c->dcnt);
     MSF_HIP(hipGetLastError());
     MSF_TRY(read_counters(c));
     uint32_t nR = c->hcnt->nR;
@@ -223,12 +222,14 @@ msf_status solve_device(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, co
             launch_sweep_compact(s, a, b.p, b.r, nxt.row_ptr, nxt.col, nxt.key, b.status,
                                  c->dcnt);
         } else {
-            launch_sweep(s, a, b.p, b.r, b.blive, c->dcnt);
+            // round 1: p is the identity and nothing has been filtered
+            launch_sweep(s, a, b.p, b.r, b.blive, c->dcnt, rounds == 0 && c->first_round_kernel);
         }
         if (ev_k >= 0) MSF_HIP(hipEventRecord(c->sev[2 * ev_k + 1], s));
         launch_hook(s, b.R[ri], nR, b.r, b.p, d_edges, b.h, b.hedge);
         launch_fill_u32(s, &c->dcnt->nR, 0u, 3);  // nR, nF, hooks
-        launch_tiebreak(s, b.R[ri], nR, b.h, b.hedge, b.flags, b.R[ri ^ 1], b.F, c->dcnt);
+        launch_tiebreak(s, b.R[ri], nR, b.h, b.hedge, b.flags, b.R[ri ^ 1], b.F, b.status,
+                        c->dcnt);
         MSF_HIP(hipGetLastError());
         MSF_TRY(read_counters(c));
         const uint32_t nF = c->hcnt->nF, nRn = c->hcnt->nR;
@@ -255,7 +256,7 @@ msf_status solve_device(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, co
             live_frac = a.nnz ? (double)c->hcnt->live / (double)a.nnz : 0.0;
         }
         if (nF == 0) break;
-        launch_chase(s, b.F, nF, b.h, c->dcnt);
+        launch_chase(s, b.F, nF, b.h, (uint32_t *)b.part, c->dcnt);
         if (c->check_rounds) {
             MSF_TRY(read_counters(c));
             if (c->hcnt->err) {
@@ -263,7 +264,7 @@ msf_status solve_device(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, co
                 return MSF_EDEVICE;
             }
         }
-        launch_update_parents(s, a.row_ptr, n, b.p, b.h, c->dcnt);
+        launch_update_parents(s, a.row_ptr, n, b.p, b.h, (uint32_t *)b.part, c->dcnt);
         ri ^= 1;
         nR = nRn;
         rows = 0;  // read back with the next round's counters
@@ -272,8 +273,7 @@ msf_status solve_device(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, co
     st.rounds = rounds;
 
     // output
-    launch_output(s, b.flags, m, d_w, wt, d_ids, b.status, c->dcnt);
-    launch_finalize_total(s, c->dcnt, wt);
+    launch_output(s, b.flags, m, d_w, wt, d_ids, b.status, b.part, c->dcnt);
     MSF_HIP(hipEventRecord(c->ev[2], s));
     MSF_HIP(hipGetLastError());
     MSF_TRY(read_counters(c));
@@ -362,6 +362,8 @@ msf_status msf_ctx_create(int device, void *hip_stream, msf_ctx **out)
     }
     if (const char *f = getenv("MSF_FILTER")) c->filter_mode = atoi(f);
     if (const char *f = getenv("MSF_CHECK_ROUNDS")) c->check_rounds = atoi(f) != 0;
+    if (const char *f = getenv("MSF_FIRST_ROUND")) c->first_round_kernel = atoi(f) != 0;
+    if (const char *f = getenv("MSF_BUCKETED_BUILD")) c->bucketed_build = atoi(f) != 0;
     if (const char *f = getenv("MSF_FILTER_THRESHOLD")) c->filter_threshold = atof(f);
     *out = x;
     return MSF_OK;
@@ -501,15 +503,10 @@ msf_status msf_graph_create(msf_ctx *ctx, int32_t n, int64_t m, const int32_t *e
             return hip_fail(e1 != hipSuccess ? e1 : e2, "hipMemcpyAsync");
         }
     }
-    void *deg, *slot;
-    if ((rc = ws_get(c, WS_DEG, 4 * nn, &deg)) || (rc = ws_get(c, WS_SLOT, 8 * mm, &slot))) {
-        msf_graph_destroy(g);
-        return rc;
-    }
     zero_counters(c);
     rc = build_adjacency(c, n, m, (const int32_t *)g->bufs[0], g->bufs[1], wt, &g->a,
                          (uint32_t *)g->bufs[2], (uint32_t *)g->bufs[3], (uint64_t *)g->bufs[4],
-                         (uint32_t *)deg, (uint2 *)slot, (uint32_t *)g->bufs[5]);
+                         (uint32_t *)g->bufs[5]);
     if (rc == MSF_OK) rc = read_counters(c);
     if (rc == MSF_OK) rc = decode_err(c->hcnt->err);
     if (rc) {
@@ -578,18 +575,20 @@ msf_status msf_shortcut(msf_ctx *ctx, int32_t n, uint32_t *p, int32_t *sub_iters
     Ctx *c = &ctx->c;
     MSF_HIP(hipSetDevice(c->device));
     hipStream_t s = c->stream;
-    void *vq, *vf, *vf2;
+    void *vq, *vf, *vf2, *vst;
     msf_status rc;
     if ((rc = ws_get(c, WS_Q, 4 * (size_t)n, &vq)) || (rc = ws_get(c, WS_FL, 4 * (size_t)n, &vf)) ||
-        (rc = ws_get(c, WS_RL2, 4 * (size_t)n, &vf2)))
+        (rc = ws_get(c, WS_RL2, 4 * (size_t)n, &vf2)) ||
+        (rc = ws_get(c, WS_STATUS, 8 * ((size_t)compaction_tiles((uint64_t)n) + 1), &vst)))
         return rc;
+    uint64_t *status = (uint64_t *)vst;
     uint32_t *q = (uint32_t *)vq, *F[2] = {(uint32_t *)vf, (uint32_t *)vf2};
     zero_counters(c);
     launch_check_parents(s, p, n, c->dcnt);
     if ((rc = read_counters(c))) return rc;
     if ((rc = decode_err(c->hcnt->err))) return rc;
     MSF_HIP(hipMemcpyAsync(q, p, 4 * (size_t)n, hipMemcpyDeviceToDevice, s));
-    launch_jump_init(s, q, n, F[0], c->dcnt);
+    launch_jump_init(s, q, n, F[0], status, c->dcnt);
     if ((rc = read_counters(c))) return rc;
     uint32_t nF = c->hcnt->nF;
     int cap = 2;
@@ -597,7 +596,7 @@ msf_status msf_shortcut(msf_ctx *ctx, int32_t n, uint32_t *p, int32_t *sub_iters
     int passes = 0, fi = 0;
     while (nF > 0 && passes < cap) {
         launch_fill_u32(s, &c->dcnt->nR, 0u, 1);
-        launch_jump_pass(s, F[fi], nF, q, F[fi ^ 1], c->dcnt);
+        launch_jump_pass(s, F[fi], nF, q, F[fi ^ 1], status, c->dcnt);
         if ((rc = read_counters(c))) return rc;
         nF = c->hcnt->nR;
         fi ^= 1;

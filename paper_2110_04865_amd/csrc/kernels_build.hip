@@ -214,15 +214,155 @@ void launch_chunk_rows(hipStream_t s, const uint32_t *row_ptr, int32_t n, uint32
     k_chunk_rows<<<g, 256, 0, s>>>(row_ptr, n, nnz, chunk_row, nchunks);
 }
 
+// ------------------------------------------------- bucketed build ------
+// The same adjacency built without any global atomic: rows are grouped in
+// buckets of 2^LB consecutive ids (at most BK_MAX_NB buckets).
+//   A. per block of edges, an LDS histogram of the endpoint buckets,
+//      written bucket-major so one exclusive scan gives every
+//      (bucket, block) its output offset and every bucket its start;
+//   B. the same blocks scatter both directions of each edge into their
+//      buckets (row offset in the bucket, column, key), ranked by LDS
+//      atomics;
+//   C. one workgroup per bucket counts its rows in LDS, scans them into
+//      row_ptr, and scatters the entries to their final positions.
+// Every atomic is an LDS atomic, so a vertex of very high degree costs LDS
+// conflicts inside one workgroup instead of serialised device atomics.
+
+constexpr int BK_MAX_NB = 4096;
+constexpr int BKA_NT = 256;
+constexpr int BKC_NT = 1024;
+constexpr int BK_MAX_LB = 15;  // pass C keeps 2^LB row counters in LDS
+
+static int bucket_bits(int32_t n)
+{
+    int lb = 8;
+    while ((((int64_t)n + (1ll << lb) - 1) >> lb) > BK_MAX_NB) ++lb;
+    return lb;
+}
+
+template <int WT>
+__global__ __launch_bounds__(BKA_NT) void k_bucket_hist(const int32_t *__restrict__ edges,
+                                                        const void *__restrict__ w, int64_t m,
+                                                        int32_t n, int lb, int nb, int64_t epb,
+                                                        uint32_t nblk, uint32_t *__restrict__ bh,
+                                                        Counters *cnt)
+{
+    extern __shared__ uint32_t hist[];
+    for (int i = threadIdx.x; i < nb; i += BKA_NT) hist[i] = 0;
+    __syncthreads();
+    const int64_t e0 = (int64_t)blockIdx.x * epb;
+    const int64_t e1 = e0 + epb < m ? e0 + epb : m;
+    uint32_t err = 0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += BKA_NT) {
+        const int32_t u = edges[2 * e], v = edges[2 * e + 1];
+        if (WT == MSF_W_F32) {
+            const uint32_t b = ((const uint32_t *)w)[e];
+            if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu)) err |= ERR_NAN;
+        }
+        if ((uint32_t)u >= (uint32_t)n || (uint32_t)v >= (uint32_t)n) {
+            err |= ERR_ENDPOINT;
+            continue;
+        }
+        if (u == v) continue;
+        atomicAdd(&hist[(uint32_t)u >> lb], 1u);
+        atomicAdd(&hist[(uint32_t)v >> lb], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += BKA_NT) bh[(size_t)i * nblk + blockIdx.x] = hist[i];
+    if (__ballot(err != 0)) {
+        uint32_t any = err;
+        for (int d = 32; d >= 1; d >>= 1) any |= __shfl_xor(any, d, 64);
+        if (__lane_id() == 0) atomicOr(&cnt->err, any);
+    }
+}
+
+template <int WT>
+__global__ __launch_bounds__(BKA_NT) void k_bucket_scatter(
+    const int32_t *__restrict__ edges, const void *__restrict__ w, int64_t m, int32_t n, int lb,
+    int nb, int64_t epb, uint32_t nblk, const uint32_t *__restrict__ bh_off,
+    uint16_t *__restrict__ rlo, uint32_t *__restrict__ bcol, uint64_t *__restrict__ bkey)
+{
+    extern __shared__ uint32_t off[];
+    for (int i = threadIdx.x; i < nb; i += BKA_NT) off[i] = bh_off[(size_t)i * nblk + blockIdx.x];
+    __syncthreads();
+    const uint32_t mask = (1u << lb) - 1u;
+    const int64_t e0 = (int64_t)blockIdx.x * epb;
+    const int64_t e1 = e0 + epb < m ? e0 + epb : m;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += BKA_NT) {
+        const int32_t u = edges[2 * e], v = edges[2 * e + 1];
+        if ((uint32_t)u >= (uint32_t)n || (uint32_t)v >= (uint32_t)n || u == v) continue;
+        uint32_t wk = ((const uint32_t *)w)[e];
+        if (WT == MSF_W_F32) wk = wkey_f32_bits(wk);
+        const uint64_t k = ((uint64_t)wk << 32) | (uint64_t)(uint32_t)e;
+        const uint32_t pu = atomicAdd(&off[(uint32_t)u >> lb], 1u);
+        const uint32_t pv = atomicAdd(&off[(uint32_t)v >> lb], 1u);
+        rlo[pu] = (uint16_t)((uint32_t)u & mask);
+        bcol[pu] = (uint32_t)v;
+        bkey[pu] = k;
+        rlo[pv] = (uint16_t)((uint32_t)v & mask);
+        bcol[pv] = (uint32_t)u;
+        bkey[pv] = k;
+    }
+}
+
+__global__ __launch_bounds__(BKC_NT) void k_bucket_rows(
+    const uint32_t *__restrict__ bh_off, uint32_t nblk, int32_t n, int lb, int nb,
+    const uint16_t *__restrict__ rlo, const uint32_t *__restrict__ bcol,
+    const uint64_t *__restrict__ bkey, uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ col,
+    uint64_t *__restrict__ key)
+{
+    extern __shared__ uint32_t cnt[];  // 2^lb counters, then scan scratch
+    uint32_t *scr = cnt + (1u << lb);
+    const uint32_t b = blockIdx.x;
+    const uint32_t s = bh_off[(size_t)b * nblk];
+    const uint32_t e = bh_off[(size_t)(b + 1) * nblk];
+    const uint32_t R = 1u << lb;
+    const int64_t row0 = (int64_t)b << lb;
+    const uint32_t rows = (uint32_t)((int64_t)n - row0 < (int64_t)R ? (int64_t)n - row0 : R);
+    for (uint32_t i = threadIdx.x; i < R; i += BKC_NT) cnt[i] = 0;
+    __syncthreads();
+    for (uint32_t k = s + threadIdx.x; k < e; k += BKC_NT) atomicAdd(&cnt[rlo[k]], 1u);
+    __syncthreads();
+    // exclusive scan of the R counters: PER consecutive counters per thread
+    const uint32_t per = R / BKC_NT > 0 ? R / BKC_NT : 1;
+    const uint32_t i0 = threadIdx.x * per;
+    uint32_t run = 0;
+    if (i0 < R)
+        for (uint32_t j = 0; j < per; ++j) run += cnt[i0 + j];
+    uint32_t tot;
+    const uint32_t ex = block_excl_sum<BKC_NT>(run, scr, &tot);
+    if (i0 < R) {
+        uint32_t acc = ex;
+        for (uint32_t j = 0; j < per; ++j) {
+            const uint32_t c = cnt[i0 + j];
+            cnt[i0 + j] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < rows; i += BKC_NT) row_ptr[row0 + i] = s + cnt[i];
+    if (b == (uint32_t)nb - 1 && threadIdx.x == 0) row_ptr[n] = e;
+    __syncthreads();
+    for (uint32_t k = s + threadIdx.x; k < e; k += BKC_NT) {
+        const uint32_t pos = s + atomicAdd(&cnt[rlo[k]], 1u);
+        col[pos] = bcol[k];
+        key[pos] = bkey[k];
+    }
+}
+
 // ---------------------------------------------------------------- host ---
 
-msf_status build_adjacency(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
-                           msf_wtype wt, Adj *a, uint32_t *row_ptr, uint32_t *col, uint64_t *key,
-                           uint32_t *deg, uint2 *slot, uint32_t *chunk_row)
+static msf_status build_atomic(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
+                               const void *d_w, msf_wtype wt, uint32_t *row_ptr, uint32_t *col,
+                               uint64_t *key)
 {
     hipStream_t s = c->stream;
+    void *vdeg, *vslot;
+    MSF_TRY(ws_get(c, WS_DEG, 4 * (size_t)(n > 0 ? n : 1), &vdeg));
+    MSF_TRY(ws_get(c, WS_SLOT, sizeof(uint2) * (size_t)(m > 0 ? m : 1), &vslot));
+    uint32_t *deg = (uint32_t *)vdeg;
+    uint2 *slot = (uint2 *)vslot;
     launch_fill_u32(s, deg, 0u, (size_t)n);
-    launch_fill_u32(s, &c->dcnt->err, 0u, 1);
     const unsigned ge = grid_for((size_t)m, 256, 16384);
     if (m > 0) {
         if (wt == MSF_W_F32)
@@ -230,8 +370,7 @@ msf_status build_adjacency(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
         else
             k_degree<MSF_W_U32><<<ge, 256, 0, s>>>(d_edges, d_w, m, n, deg, slot, c->dcnt);
     }
-    msf_status rc = scan_u32(c, deg, row_ptr, n, &c->dcnt->count);
-    if (rc) return rc;
+    MSF_TRY(scan_u32(c, deg, row_ptr, n, &c->dcnt->count));
     if (m > 0) {
         if (wt == MSF_W_F32)
             k_scatter<MSF_W_F32><<<ge, 256, 0, s>>>(d_edges, d_w, m, slot, row_ptr, col, key);
@@ -239,6 +378,85 @@ msf_status build_adjacency(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
             k_scatter<MSF_W_U32><<<ge, 256, 0, s>>>(d_edges, d_w, m, slot, row_ptr, col, key);
     }
     MSF_HIP(hipGetLastError());
+    return MSF_OK;
+}
+
+static msf_status build_bucketed(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
+                                 const void *d_w, msf_wtype wt, int lb, uint32_t *row_ptr,
+                                 uint32_t *col, uint64_t *key)
+{
+    hipStream_t s = c->stream;
+    const int nb = (int)(((int64_t)n + (1ll << lb) - 1) >> lb);
+    int64_t epb = (m + 2047) / 2048;
+    if (epb < 32768) epb = 32768;
+    epb = (epb + 255) & ~(int64_t)255;
+    const uint32_t nblk = (uint32_t)((m + epb - 1) / epb);
+    const size_t nh = (size_t)nb * nblk;
+    const size_t mm = (size_t)m;
+    void *vbh, *vbo, *vrlo, *vcol, *vkey;
+    MSF_TRY(ws_get(c, WS_BH, 4 * nh, &vbh));
+    MSF_TRY(ws_get(c, WS_BHOFF, 4 * (nh + 1), &vbo));
+    MSF_TRY(ws_get(c, WS_BRLO, 2 * 2 * mm, &vrlo));
+    MSF_TRY(ws_get(c, WS_BCOL, 4 * 2 * mm, &vcol));
+    MSF_TRY(ws_get(c, WS_BKEY, 8 * 2 * mm, &vkey));
+    uint32_t *bh = (uint32_t *)vbh, *bo = (uint32_t *)vbo;
+    const size_t lds_a = 4 * (size_t)nb;
+    if (wt == MSF_W_F32)
+        k_bucket_hist<MSF_W_F32><<<nblk, BKA_NT, lds_a, s>>>(d_edges, d_w, m, n, lb, nb, epb, nblk,
+                                                           bh, c->dcnt);
+    else
+        k_bucket_hist<MSF_W_U32><<<nblk, BKA_NT, lds_a, s>>>(d_edges, d_w, m, n, lb, nb, epb, nblk,
+                                                           bh, c->dcnt);
+    MSF_TRY(scan_u32(c, bh, bo, (int64_t)nh, &c->dcnt->count));
+    if (wt == MSF_W_F32)
+        k_bucket_scatter<MSF_W_F32><<<nblk, BKA_NT, lds_a, s>>>(
+            d_edges, d_w, m, n, lb, nb, epb, nblk, bo, (uint16_t *)vrlo, (uint32_t *)vcol,
+            (uint64_t *)vkey);
+    else
+        k_bucket_scatter<MSF_W_U32><<<nblk, BKA_NT, lds_a, s>>>(
+            d_edges, d_w, m, n, lb, nb, epb, nblk, bo, (uint16_t *)vrlo, (uint32_t *)vcol,
+            (uint64_t *)vkey);
+    const size_t lds_c = 4 * ((size_t)1 << lb) + 4 * (BKC_NT / 64 + 1);
+    k_bucket_rows<<<nb, BKC_NT, lds_c, s>>>(bo, nblk, n, lb, nb, (const uint16_t *)vrlo,
+                                            (const uint32_t *)vcol, (const uint64_t *)vkey,
+                                            row_ptr, col, key);
+    MSF_HIP(hipGetLastError());
+    return MSF_OK;
+}
+
+// Pass C needs 2^lb row counters in LDS; above 64 KB the kernel must be
+// allowed a larger dynamic LDS allocation, which is requested once.
+static bool bucket_lds_ok(int lb)
+{
+    const size_t need = 4 * ((size_t)1 << lb) + 4 * (BKC_NT / 64 + 1);
+    if (need <= 65536) return true;
+    static int granted = -1;  // -1 unknown, else the granted byte count
+    if (granted < 0) {
+        const int want = (int)(4 * ((size_t)1 << BK_MAX_LB) + 4 * (BKC_NT / 64 + 1));
+        granted = hipFuncSetAttribute((const void *)k_bucket_rows,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, want) ==
+                          hipSuccess
+                      ? want
+                      : 65536;
+        (void)hipGetLastError();
+    }
+    return need <= (size_t)granted;
+}
+
+msf_status build_adjacency(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
+                           msf_wtype wt, Adj *a, uint32_t *row_ptr, uint32_t *col, uint64_t *key,
+                           uint32_t *chunk_row)
+{
+    launch_fill_u32(c->stream, &c->dcnt->err, 0u, 1);
+    const int lb = bucket_bits(n);
+    if (m == 0 || n == 0) {
+        launch_fill_u32(c->stream, row_ptr, 0u, (size_t)n + 1);
+        launch_fill_u32(c->stream, &c->dcnt->count, 0u, 1);
+    } else if (lb <= BK_MAX_LB && c->bucketed_build && bucket_lds_ok(lb)) {
+        MSF_TRY(build_bucketed(c, n, m, d_edges, d_w, wt, lb, row_ptr, col, key));
+    } else {
+        MSF_TRY(build_atomic(c, n, m, d_edges, d_w, wt, row_ptr, col, key));
+    }
     a->n = n;
     a->m = m;
     a->row_ptr = row_ptr;

@@ -5,6 +5,11 @@
 // State between kernels (see msf_internal.hpp): p is a star forest at the
 // start of every round; R lists the roots that may still have an outgoing
 // edge; r[i] holds root i's minimum outgoing key after the sweep.
+//
+// Lists (R, F, output ids) are built by ordered tile compaction: each
+// workgroup takes a tile from a ticket, counts, and gets its output offset
+// from a decoupled look-back, so one counter atomic is issued per tile
+// rather than per wave, and list order is deterministic.
 #include "msf_internal.hpp"
 #include "wave.hpp"
 
@@ -20,41 +25,61 @@ unsigned grid_for(size_t n, unsigned block = 256, unsigned cap = 8192)
     return (unsigned)g;
 }
 
-// Append `pred` lanes of the wave to list[] through one atomic per wave.
-// Every lane of the wave must call it (convergent).
-__device__ __forceinline__ void wave_append(bool pred, uint32_t value, uint32_t *list,
-                                            uint32_t *counter)
-{
-    const uint64_t mask = __ballot(pred);
-    if (!mask) return;
-    const int leader = __builtin_ctzll(mask);
-    uint32_t base = 0;
-    if ((int)__lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
-    base = __shfl(base, leader, 64);
-    if (pred) list[base + (uint32_t)__popcll(mask & lanemask_lt())] = value;
-}
+constexpr int CT_NT = 256;                 // compaction tile: threads
+constexpr int CT_IT = 16;                  // items per thread
+constexpr int CT_TILE = CT_NT * CT_IT;     // items per tile
+constexpr uint64_t M31 = (1ull << 31) - 1ull;
+
+uint32_t ct_tiles(uint64_t n) { return (uint32_t)((n + CT_TILE - 1) / CT_TILE); }
 
 }  // namespace
+
+uint32_t compaction_tiles(uint64_t n) { return ct_tiles(n); }
+
+// Zero the look-back status of `tiles` tiles and the ticket.
+static void prep_lookback(hipStream_t s, uint64_t *status, uint32_t tiles, Counters *dcnt)
+{
+    launch_fill_u64(s, status, 0ull, tiles);
+    launch_fill_u32(s, &dcnt->ticket, 0u, 1);
+}
 
 // ----------------------------------------------------------- root list --
 // R = vertices with at least one stored entry (isolated vertices are
 // finished roots from the start).
 
-__global__ void k_init_roots(const uint32_t *__restrict__ row_ptr, int32_t n, uint32_t *R,
-                             Counters *cnt)
+__global__ __launch_bounds__(CT_NT) void k_init_roots(const uint32_t *__restrict__ row_ptr,
+                                                      int32_t n, uint32_t *__restrict__ R,
+                                                      uint64_t *status, Counters *cnt)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < n; b += stride) {
-        const int64_t i = b + threadIdx.x;
-        const bool act = i < n && row_ptr[i + 1] > row_ptr[i];
-        wave_append(act, (uint32_t)i, R, &cnt->nR);
-    }
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_lds[CT_NT / 64 + 1];
+    __shared__ uint64_t s_pre;
+    if (threadIdx.x == 0) s_tile = atomicAdd(&cnt->ticket, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const int64_t base = (int64_t)tile * CT_TILE + (int64_t)threadIdx.x * CT_IT;
+    uint32_t rp[CT_IT + 1];
+#pragma unroll
+    for (int k = 0; k <= CT_IT; ++k) rp[k] = (base + k <= n) ? row_ptr[base + k] : 0u;
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < CT_IT; ++k) c += (base + k < n && rp[k + 1] > rp[k]) ? 1u : 0u;
+    uint32_t oa, ob;
+    uint64_t tot;
+    tile_offsets2<CT_NT>(tile, c, 0u, status, s_lds, &s_pre, &oa, &ob, &tot);
+#pragma unroll
+    for (int k = 0; k < CT_IT; ++k)
+        if (base + k < n && rp[k + 1] > rp[k]) R[oa++] = (uint32_t)(base + k);
+    if (tile == gridDim.x - 1 && threadIdx.x == 0) cnt->nR = (uint32_t)(tot >> 31);
 }
 
 void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, uint32_t *R,
-                       Counters *dcnt)
+                       uint64_t *status, Counters *dcnt)
 {
-    if (n > 0) k_init_roots<<<grid_for((size_t)n), 256, 0, s>>>(row_ptr, n, R, dcnt);
+    const uint32_t tiles = ct_tiles((uint64_t)n);
+    if (!tiles) return;
+    prep_lookback(s, status, tiles, dcnt);
+    k_init_roots<<<tiles, CT_NT, 0, s>>>(row_ptr, n, R, status, dcnt);
 }
 
 // ---------------------------------------------------------------- hook --
@@ -99,40 +124,71 @@ void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, con
 // enters the forest once.  Roots without an outgoing edge are finished for
 // good (their component is complete) and leave R.  Kept hooks flag their
 // edge and join the shortcut frontier F; reverted roots stay in R.
+//
+// A revert writes h[i] while other roots may read it; they read either the
+// old target (which is not them unless they are i's partner, and the
+// partner has the larger id so it never reverts) or i itself, and decide
+// the same either way.
 
-__global__ void k_tiebreak(const uint32_t *__restrict__ R, uint32_t nR, uint32_t *h,
-                           const uint32_t *__restrict__ hedge, uint8_t *__restrict__ in_forest,
-                           uint32_t *__restrict__ Rnext, uint32_t *__restrict__ F, Counters *cnt)
+__global__ __launch_bounds__(CT_NT) void k_tiebreak(const uint32_t *__restrict__ R, uint32_t nR,
+                                                    uint32_t *h, const uint32_t *__restrict__ hedge,
+                                                    uint8_t *__restrict__ in_forest,
+                                                    uint32_t *__restrict__ Rnext,
+                                                    uint32_t *__restrict__ F, uint64_t *status,
+                                                    Counters *cnt)
 {
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t b = blockIdx.x * blockDim.x; b < nR; b += stride) {
-        const uint32_t k = b + threadIdx.x;
-        bool stay = false, hooked = false;
-        uint32_t i = 0;
-        if (k < nR) {
-            i = R[k];
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_lds[CT_NT / 64 + 1];
+    __shared__ uint64_t s_pre;
+    if (threadIdx.x == 0) s_tile = atomicAdd(&cnt->ticket, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t base = tile * CT_TILE + threadIdx.x * CT_IT;
+    uint32_t id[CT_IT];
+    uint32_t stay = 0, hooked = 0, ca = 0, cb = 0;
+#pragma unroll
+    for (int k = 0; k < CT_IT; ++k) {
+        id[k] = 0;
+        if (base + k < nR) {
+            const uint32_t i = R[base + k];
+            id[k] = i;
             const uint32_t t = load_relaxed_u32(h + i);
             if (t != i) {
                 const uint32_t back = load_relaxed_u32(h + t);
                 if (back == i && i < t) {
                     store_relaxed_u32(h + i, i);
-                    stay = true;
+                    stay |= 1u << k;
+                    ++ca;
                 } else {
                     in_forest[hedge[i]] = 1;
-                    hooked = true;
+                    hooked |= 1u << k;
+                    ++cb;
                 }
             }
         }
-        wave_append(stay, i, Rnext, &cnt->nR);
-        wave_append(hooked, i, F, &cnt->nF);
+    }
+    uint32_t oa, ob;
+    uint64_t tot;
+    tile_offsets2<CT_NT>(tile, ca, cb, status, s_lds, &s_pre, &oa, &ob, &tot);
+#pragma unroll
+    for (int k = 0; k < CT_IT; ++k) {
+        if (stay & (1u << k)) Rnext[oa++] = id[k];
+        else if (hooked & (1u << k)) F[ob++] = id[k];
+    }
+    if (tile == gridDim.x - 1 && threadIdx.x == 0) {
+        cnt->nR = (uint32_t)(tot >> 31);
+        cnt->nF = (uint32_t)(tot & M31);
     }
 }
 
 void launch_tiebreak(hipStream_t s, const uint32_t *R, uint32_t nR, uint32_t *h,
                      const uint32_t *hedge, uint8_t *in_forest, uint32_t *Rnext, uint32_t *F,
-                     Counters *dcnt)
+                     uint64_t *status, Counters *dcnt)
 {
-    if (nR) k_tiebreak<<<grid_for(nR), 256, 0, s>>>(R, nR, h, hedge, in_forest, Rnext, F, dcnt);
+    const uint32_t tiles = ct_tiles(nR);
+    if (!tiles) return;
+    prep_lookback(s, status, tiles, dcnt);
+    k_tiebreak<<<tiles, CT_NT, 0, s>>>(R, nR, h, hedge, in_forest, Rnext, F, status, dcnt);
 }
 
 // ------------------------------------------------------------- shortcut --
@@ -141,13 +197,15 @@ void launch_tiebreak(hipStream_t s, const uint32_t *R, uint32_t nR, uint32_t *h,
 // writing every improvement back so other chases jump further.  Every value
 // read of h[x] is an ancestor of x (or x itself for a final root, which is
 // never written), and the hook forest is acyclic after tie breaking, so each
-// chase ends after at most the height of its tree.
+// chase ends after at most the height of its tree; a hard cap of nF steps
+// turns a (theoretically impossible) cycle into an error flag.
 
-__global__ void k_chase(const uint32_t *__restrict__ F, uint32_t nF, uint32_t *h, Counters *cnt)
+__global__ __launch_bounds__(256) void k_chase(const uint32_t *__restrict__ F, uint32_t nF,
+                                               uint32_t *h, uint32_t *part)
 {
+    __shared__ uint32_t s_lds[256 / 64 + 1];
     const uint32_t stride = gridDim.x * blockDim.x;
-    uint32_t longest = 0;
-    bool broken = false;
+    uint32_t longest = 0, broken = 0;
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nF; k += stride) {
         const uint32_t i = F[k];
         uint32_t x = load_relaxed_u32(h + i);
@@ -157,36 +215,73 @@ __global__ void k_chase(const uint32_t *__restrict__ F, uint32_t nF, uint32_t *h
             if (y == x) break;
             x = y;
             store_relaxed_u32(h + i, x);
-            // a chain can hold at most nF hooked roots; longer means a cycle,
-            // which tie breaking rules out -- report it instead of spinning
             if (++steps > nF) {
-                broken = true;
+                broken = 1;
                 break;
             }
         }
         longest = steps > longest ? steps : longest;
     }
-    if (__ballot(broken) && __lane_id() == 0) atomicOr(&cnt->err, ERR_CYCLE);
     for (int d = 32; d >= 1; d >>= 1) {
-        uint32_t o = __shfl_xor(longest, d, 64);
+        const uint32_t o = __shfl_xor(longest, d, 64);
         longest = o > longest ? o : longest;
+        broken |= __shfl_xor(broken, d, 64);
     }
-    if (__lane_id() == 0 && longest) atomicMax(&cnt->max_chase, longest);
+    if (__lane_id() == 0) s_lds[threadIdx.x >> 6] = longest | (broken << 31);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t v = 0, br = 0;
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t o = s_lds[i];
+            v = (o & 0x7FFFFFFFu) > v ? (o & 0x7FFFFFFFu) : v;
+            br |= o >> 31;
+        }
+        part[blockIdx.x] = v | (br << 31);
+    }
 }
 
-void launch_chase(hipStream_t s, const uint32_t *F, uint32_t nF, uint32_t *h, Counters *dcnt)
+// Fold per-block chase results into the counters.
+__global__ void k_chase_fold(const uint32_t *__restrict__ part, uint32_t nb, Counters *cnt)
 {
-    if (nF) k_chase<<<grid_for(nF), 256, 0, s>>>(F, nF, h, dcnt);
+    uint32_t v = 0, br = 0;
+    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) {
+        const uint32_t o = part[i];
+        v = (o & 0x7FFFFFFFu) > v ? (o & 0x7FFFFFFFu) : v;
+        br |= o >> 31;
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t o = __shfl_xor(v, d, 64);
+        v = o > v ? o : v;
+        br |= __shfl_xor(br, d, 64);
+    }
+    if (__lane_id() == 0) {
+        atomicMax(&cnt->max_chase, v);
+        if (br) atomicOr(&cnt->err, ERR_CYCLE);
+    }
+}
+
+constexpr unsigned CHASE_BLOCKS = 2048;
+
+void launch_chase(hipStream_t s, const uint32_t *F, uint32_t nF, uint32_t *h, uint32_t *part,
+                  Counters *dcnt)
+{
+    if (!nF) return;
+    const unsigned g = grid_for(nF, 256, CHASE_BLOCKS);
+    k_chase<<<g, 256, 0, s>>>(F, nF, h, part);
+    k_chase_fold<<<1, 256, 0, s>>>(part, g, dcnt);
 }
 
 // p[v] <- h[p[v]] for every vertex that still has stored entries: p[v] is an
 // old root and h maps it to its new root, so p is again a star forest.
-// Vertices without entries are never read again.
+// Vertices without entries are never read again.  Per-block row counts go
+// to part[] (folded by k_fold_rows) for the sweep's byte accounting.
 
-__global__ void k_update_parents(const uint32_t *__restrict__ row_ptr, int32_t n,
-                                 uint32_t *__restrict__ p, const uint32_t *__restrict__ h,
-                                 Counters *cnt)
+__global__ __launch_bounds__(256) void k_update_parents(const uint32_t *__restrict__ row_ptr,
+                                                        int32_t n, uint32_t *__restrict__ p,
+                                                        const uint32_t *__restrict__ h,
+                                                        uint32_t *__restrict__ part)
 {
+    __shared__ uint32_t s_lds[256 / 64 + 1];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     uint32_t rows = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -195,165 +290,221 @@ __global__ void k_update_parents(const uint32_t *__restrict__ row_ptr, int32_t n
             ++rows;
         }
     }
-    rows = wave_sum(rows);
-    if (__lane_id() == 0 && rows) atomicAdd(&cnt->rows, rows);
+    rows = block_sum<256>(rows, s_lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = rows;
+}
+
+__global__ void k_fold_rows(const uint32_t *__restrict__ part, uint32_t nb, Counters *cnt)
+{
+    uint32_t v = 0;
+    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) v += part[i];
+    v = wave_sum(v);
+    if (__lane_id() == 0 && v) atomicAdd(&cnt->rows, v);
 }
 
 void launch_update_parents(hipStream_t s, const uint32_t *row_ptr, int32_t n, uint32_t *p,
-                           const uint32_t *h, Counters *dcnt)
+                           const uint32_t *h, uint32_t *part, Counters *dcnt)
 {
     launch_fill_u32(s, &dcnt->rows, 0u, 1);
-    if (n) k_update_parents<<<grid_for((size_t)n), 256, 0, s>>>(row_ptr, n, p, h, dcnt);
+    if (!n) return;
+    const unsigned g = grid_for((size_t)n, 256, 4096);
+    k_update_parents<<<g, 256, 0, s>>>(row_ptr, n, p, h, part);
+    k_fold_rows<<<1, 256, 0, s>>>(part, g, dcnt);
 }
 
 // --------------------------------------------------------------- output --
-// Forest flags -> ascending edge ids (order-preserving compaction with a
-// decoupled look-back), the count, and the forest weight.  uint32 weights
-// sum exactly in u64; float32 weights are added exactly as integers in
-// units of 2^-149 (the smallest float32 subnormal) split over 32-bit digits
-// held in int64 lanes, so the result is independent of the order in which
-// waves finish; infinities are counted separately.
+// Forest flags -> ascending edge ids (ordered tile compaction), the count,
+// and the forest weight.  uint32 weights sum exactly in u64; float32 weights
+// are added exactly as integers in units of 2^-149 (the smallest float32
+// subnormal) split over 32-bit digits held in int64 lanes, so the result is
+// independent of the order of additions; infinities are counted
+// separately.  Each tile writes its partial sums to part[tile]; k_total
+// folds them and rounds once.
 
 constexpr int OUT_NT = 256;
-constexpr int OUT_IT = 16;
+constexpr int OUT_IT = 32;
 constexpr int OUT_TILE = OUT_NT * OUT_IT;
 constexpr int ACC_DIGITS = 10;
+
+struct TilePart {
+    int64_t acc[ACC_DIGITS];
+    uint64_t u64;
+    uint32_t pinf, ninf;
+};
 
 template <int WT>
 __global__ __launch_bounds__(OUT_NT) void k_output(const uint8_t *__restrict__ flags, int64_t m,
                                                   const void *__restrict__ w,
                                                   int32_t *__restrict__ ids, uint64_t *status,
-                                                  Counters *cnt)
+                                                  TilePart *__restrict__ part, Counters *cnt)
 {
     __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_lds[OUT_NT / 64 + 1];
-    __shared__ uint64_t s_prefix;
+    __shared__ uint64_t s_lds[OUT_NT / 64 + 1];
+    __shared__ uint64_t s_pre;
+    __shared__ int64_t s_acc[OUT_NT / 64][ACC_DIGITS + 1];
     if (threadIdx.x == 0) s_tile = atomicAdd(&cnt->ticket, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
     const int64_t base = (int64_t)tile * OUT_TILE + (int64_t)threadIdx.x * OUT_IT;
-    uint8_t f[OUT_IT];
+    uint32_t fw[OUT_IT / 4];
     if (base + OUT_IT <= m) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(flags + base);
-        const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-        for (int k = 0; k < OUT_IT; ++k) f[k] = (uint8_t)(wd[k >> 2] >> (8 * (k & 3)));
+        for (int q = 0; q < OUT_IT / 16; ++q) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(flags + base + 16 * q);
+            fw[4 * q] = v.x;
+            fw[4 * q + 1] = v.y;
+            fw[4 * q + 2] = v.z;
+            fw[4 * q + 3] = v.w;
+        }
     } else {
 #pragma unroll
-        for (int k = 0; k < OUT_IT; ++k) f[k] = (base + k < m) ? flags[base + k] : 0;
+        for (int q = 0; q < OUT_IT / 4; ++q) {
+            uint32_t x = 0;
+            for (int b = 0; b < 4; ++b) {
+                const int64_t e = base + 4 * q + b;
+                if (e < m && flags[e]) x |= 1u << (8 * b);
+            }
+            fw[q] = x;
+        }
     }
-    uint32_t cntl = 0;
+    uint32_t c = 0;
 #pragma unroll
-    for (int k = 0; k < OUT_IT; ++k) cntl += f[k] ? 1u : 0u;
-    uint32_t btot;
-    const uint32_t lex = block_excl_sum<OUT_NT>(cntl, s_lds, &btot);
-    if (threadIdx.x < 64) {
-        const uint64_t e = lookback(status, tile, (uint64_t)btot);
-        if (threadIdx.x == 0) s_prefix = e;
-    }
-    __syncthreads();
-    uint32_t pos = (uint32_t)s_prefix + lex;
+    for (int q = 0; q < OUT_IT / 4; ++q)
+        for (int b = 0; b < 4; ++b) c += ((fw[q] >> (8 * b)) & 0xFFu) ? 1u : 0u;
+    uint32_t pos, unused;
+    uint64_t tot;
+    tile_offsets2<OUT_NT>(tile, c, 0u, status, s_lds, &s_pre, &pos, &unused, &tot);
     uint64_t su = 0;
     int64_t acc[ACC_DIGITS];
 #pragma unroll
     for (int d = 0; d < ACC_DIGITS; ++d) acc[d] = 0;
     uint32_t pinf = 0, ninf = 0;
+    if (c) {
+        for (int k = 0; k < OUT_IT; ++k) {
+            if (!((fw[k >> 2] >> (8 * (k & 3))) & 0xFFu)) continue;
+            const int64_t e = base + k;
+            ids[pos++] = (int32_t)e;
+            const uint32_t b = ((const uint32_t *)w)[e];
+            if (WT == MSF_W_U32) {
+                su += b;
+            } else {
+                const uint32_t ex = (b >> 23) & 0xFFu;
+                const bool neg = (b >> 31) != 0;
+                if (ex == 0xFFu) {
+                    if (neg) ++ninf;
+                    else ++pinf;
+                    continue;
+                }
+                const uint64_t mant = ex ? ((b & 0x7FFFFFu) | 0x800000u) : (b & 0x7FFFFFu);
+                const uint32_t sh = ex ? ex - 1u : 0u;  // value = mant * 2^(sh-149)
+                const uint64_t x = mant << (sh & 31u);
+                const uint32_t di = sh >> 5;
+                const int64_t lo = (int64_t)(x & 0xFFFFFFFFull), hi = (int64_t)(x >> 32);
 #pragma unroll
-    for (int k = 0; k < OUT_IT; ++k) {
-        if (!f[k]) continue;
-        const int64_t e = base + k;
-        ids[pos++] = (int32_t)e;
-        const uint32_t b = ((const uint32_t *)w)[e];
-        if (WT == MSF_W_U32) {
-            su += b;
-        } else {
-            const uint32_t ex = (b >> 23) & 0xFFu;
-            const bool neg = (b >> 31) != 0;
-            if (ex == 0xFFu) {
-                if (neg) ++ninf;
-                else ++pinf;
-                continue;
-            }
-            const uint64_t mant = ex ? ((b & 0x7FFFFFu) | 0x800000u) : (b & 0x7FFFFFu);
-            const uint32_t sh = ex ? ex - 1u : 0u;  // value = mant * 2^(sh-149)
-            const uint64_t x = mant << (sh & 31u);
-            const uint32_t di = sh >> 5;
-            const int64_t lo = (int64_t)(x & 0xFFFFFFFFull), hi = (int64_t)(x >> 32);
-#pragma unroll
-            for (int d = 0; d < ACC_DIGITS; ++d) {
-                int64_t add = (d == (int)di) ? lo : ((d == (int)di + 1) ? hi : 0);
-                acc[d] += neg ? -add : add;
+                for (int d = 0; d < ACC_DIGITS; ++d) {
+                    const int64_t add = (d == (int)di) ? lo : ((d == (int)di + 1) ? hi : 0);
+                    acc[d] += neg ? -add : add;
+                }
             }
         }
     }
+    // tile partials: wave sums, then one record per tile
+    const int wv = threadIdx.x >> 6;
     if (WT == MSF_W_U32) {
         su = wave_sum(su);
-        if (__lane_id() == 0 && su) atomicAdd((unsigned long long *)&cnt->total_u64, (unsigned long long)su);
+        if (__lane_id() == 0) s_acc[wv][0] = (int64_t)su;
     } else {
-        const bool any = __ballot(cntl != 0) != 0;
-        if (any) {
 #pragma unroll
-            for (int d = 0; d < ACC_DIGITS; ++d) {
-                const int64_t v = wave_sum(acc[d]);
-                if (__lane_id() == 0 && v)
-                    atomicAdd((unsigned long long *)&cnt->acc[d], (unsigned long long)v);
-            }
-            pinf = wave_sum(pinf);
-            ninf = wave_sum(ninf);
-            if (__lane_id() == 0 && (pinf | ninf)) {
-                if (pinf) atomicAdd(&cnt->inf_pos, pinf);
-                if (ninf) atomicAdd(&cnt->inf_neg, ninf);
+        for (int d = 0; d < ACC_DIGITS; ++d) {
+            const int64_t v = wave_sum(acc[d]);
+            if (__lane_id() == 0) s_acc[wv][d] = v;
+        }
+        pinf = wave_sum(pinf);
+        ninf = wave_sum(ninf);
+        if (__lane_id() == 0) s_acc[wv][ACC_DIGITS] = ((int64_t)pinf << 32) | ninf;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        TilePart tp{};
+        for (int i = 0; i < OUT_NT / 64; ++i) {
+            if (WT == MSF_W_U32) {
+                tp.u64 += (uint64_t)s_acc[i][0];
+            } else {
+                for (int d = 0; d < ACC_DIGITS; ++d) tp.acc[d] += s_acc[i][d];
+                tp.pinf += (uint32_t)(s_acc[i][ACC_DIGITS] >> 32);
+                tp.ninf += (uint32_t)(s_acc[i][ACC_DIGITS] & 0xFFFFFFFFll);
             }
         }
+        part[tile] = tp;
+        if (tile == gridDim.x - 1) cnt->count = (uint32_t)(tot >> 31);
     }
-    const int64_t ntiles = (m + OUT_TILE - 1) / OUT_TILE;
-    if ((int64_t)tile == ntiles - 1 && threadIdx.x == 0) cnt->count = (uint32_t)(s_prefix + btot);
 }
 
-void launch_output(hipStream_t s, const uint8_t *in_forest, int64_t m, const void *w, msf_wtype wt,
-                   int32_t *ids, uint64_t *status, Counters *dcnt)
+// Fold tile partials (exact integer sums, any order) and round once.
+__global__ __launch_bounds__(256) void k_total(const TilePart *__restrict__ part, uint32_t ntiles,
+                                               Counters *cnt, int wt)
 {
-    const int64_t ntiles = (m + OUT_TILE - 1) / OUT_TILE;
-    if (ntiles == 0) return;
-    launch_fill_u64(s, status, 0ull, (size_t)ntiles);
-    launch_fill_u32(s, &dcnt->ticket, 0u, 1);
-    if (wt == MSF_W_F32)
-        k_output<MSF_W_F32><<<(unsigned)ntiles, OUT_NT, 0, s>>>(in_forest, m, w, ids, status, dcnt);
-    else
-        k_output<MSF_W_U32><<<(unsigned)ntiles, OUT_NT, 0, s>>>(in_forest, m, w, ids, status, dcnt);
-}
-
-int64_t output_tiles(int64_t m) { return (m + OUT_TILE - 1) / OUT_TILE; }
-
-// Round the exact accumulator to the nearest double, ties to even.
-__global__ void k_finalize_total(Counters *cnt, int wt)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ int64_t s[256 / 64][ACC_DIGITS + 3];
+    int64_t acc[ACC_DIGITS];
+    for (int d = 0; d < ACC_DIGITS; ++d) acc[d] = 0;
+    uint64_t su = 0;
+    uint32_t pinf = 0, ninf = 0;
+    for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
+        const TilePart &tp = part[t];
+        su += tp.u64;
+        pinf += tp.pinf;
+        ninf += tp.ninf;
+        for (int d = 0; d < ACC_DIGITS; ++d) acc[d] += tp.acc[d];
+    }
+    const int wv = threadIdx.x >> 6;
+    su = wave_sum(su);
+    pinf = wave_sum(pinf);
+    ninf = wave_sum(ninf);
+    for (int d = 0; d < ACC_DIGITS; ++d) {
+        const int64_t v = wave_sum(acc[d]);
+        if (__lane_id() == 0) s[wv][d] = v;
+    }
+    if (__lane_id() == 0) {
+        s[wv][ACC_DIGITS] = (int64_t)su;
+        s[wv][ACC_DIGITS + 1] = pinf;
+        s[wv][ACC_DIGITS + 2] = ninf;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int d = 0; d < ACC_DIGITS + 3; ++d) {
+        int64_t v = 0;
+        for (int i = 0; i < 4; ++i) v += s[i][d];
+        if (d < ACC_DIGITS) acc[d] = v;
+        else if (d == ACC_DIGITS) su = (uint64_t)v;
+        else if (d == ACC_DIGITS + 1) pinf = (uint32_t)v;
+        else ninf = (uint32_t)v;
+    }
+    cnt->total_u64 = su;
     if (wt == MSF_W_U32) {
-        cnt->total_f64 = (double)cnt->total_u64;  // correctly rounded conversion
+        cnt->total_f64 = (double)su;  // correctly rounded conversion
         return;
     }
-    if (cnt->inf_pos || cnt->inf_neg) {
-        cnt->total_f64 = (cnt->inf_pos && cnt->inf_neg) ? __builtin_nan("")
-                         : (cnt->inf_pos ? __builtin_inf() : -__builtin_inf());
+    if (pinf || ninf) {
+        cnt->total_f64 = (pinf && ninf) ? __builtin_nan("")
+                         : (pinf ? __builtin_inf() : -__builtin_inf());
         return;
     }
     // carry-propagate signed digits into 32-bit digits of a two's complement
-    // number of ACC_DIGITS*32 bits
+    // number of ACC_DIGITS*32 bits, then round to nearest, ties to even
     uint32_t dig[ACC_DIGITS];
     int64_t carry = 0;
     for (int d = 0; d < ACC_DIGITS; ++d) {
-        const int64_t v = cnt->acc[d] + carry;
+        const int64_t v = acc[d] + carry;
         dig[d] = (uint32_t)(v & 0xFFFFFFFFll);
         carry = v >> 32;  // arithmetic shift: floor division
     }
     const bool neg = carry < 0;
-    if (neg) {  // magnitude = two's complement negation
-        uint64_t c = 1;
+    if (neg) {
+        uint64_t c1 = 1;
         for (int d = 0; d < ACC_DIGITS; ++d) {
-            const uint64_t v = (uint64_t)(uint32_t)~dig[d] + c;
+            const uint64_t v = (uint64_t)(uint32_t)~dig[d] + c1;
             dig[d] = (uint32_t)v;
-            c = v >> 32;
+            c1 = v >> 32;
         }
     }
     int top = -1;
@@ -364,13 +515,12 @@ __global__ void k_finalize_total(Counters *cnt, int wt)
         auto bit = [&](int i) -> uint32_t { return i < 0 ? 0u : (dig[i >> 5] >> (i & 31)) & 1u; };
         uint64_t q = 0;
         const int lo = top - 52;  // lowest kept bit
-        for (int i = top; i >= lo && i >= 0; --i) q = (q << 1) | bit(i);
-        int scale = lo;  // value = q * 2^(scale - 149) before rounding
+        int scale = lo;           // value = q * 2^(scale - 149)
         if (lo < 0) {
             scale = 0;
-            q = 0;
             for (int i = top; i >= 0; --i) q = (q << 1) | bit(i);
         } else {
+            for (int i = top; i >= lo; --i) q = (q << 1) | bit(i);
             const uint32_t rb = bit(lo - 1);
             uint32_t sticky = 0;
             for (int i = lo - 2; i >= 0 && !sticky; --i) sticky |= bit(i);
@@ -382,24 +532,38 @@ __global__ void k_finalize_total(Counters *cnt, int wt)
                 }
             }
         }
-        out = __builtin_ldexp((double)q, scale - 149);
+        out = ldexp((double)q, scale - 149);
     }
     cnt->total_f64 = neg ? -out : out;
 }
 
-void launch_finalize_total(hipStream_t s, Counters *dcnt, msf_wtype wt)
+int64_t output_tiles(int64_t m) { return (m + OUT_TILE - 1) / OUT_TILE; }
+size_t output_part_bytes(int64_t m) { return sizeof(TilePart) * (size_t)(output_tiles(m) + 1); }
+
+void launch_output(hipStream_t s, const uint8_t *in_forest, int64_t m, const void *w, msf_wtype wt,
+                   int32_t *ids, uint64_t *status, void *part, Counters *dcnt)
 {
-    k_finalize_total<<<1, 64, 0, s>>>(dcnt, (int)wt);
+    const int64_t ntiles = output_tiles(m);
+    if (ntiles == 0) return;
+    prep_lookback(s, status, (uint32_t)ntiles, dcnt);
+    TilePart *tp = (TilePart *)part;
+    if (wt == MSF_W_F32)
+        k_output<MSF_W_F32><<<(unsigned)ntiles, OUT_NT, 0, s>>>(in_forest, m, w, ids, status, tp,
+                                                               dcnt);
+    else
+        k_output<MSF_W_U32><<<(unsigned)ntiles, OUT_NT, 0, s>>>(in_forest, m, w, ids, status, tp,
+                                                               dcnt);
+    k_total<<<1, 256, 0, s>>>(tp, (uint32_t)ntiles, dcnt, (int)wt);
 }
 
 // ------------------------------------------- shortcut of arbitrary p ----
-// Complete shortcutting of a caller's parent vector: synchronous-start,
-// in-place pointer jumping q[i] <- q[q[i]] over a shrinking frontier of
-// vertices whose parent is not yet a fixed point.  A rooted forest of
-// height d converges in at most ceil(log2 d) + 1 passes.  Cycles are
-// detected afterwards: every final target must be a root of the input
-// (p[q[i]] == q[i]); an even cycle may collapse onto false fixed points,
-// an odd one never settles, and both fail that test.
+// Complete shortcutting of a caller's parent vector: in-place pointer
+// jumping q[i] <- q[q[i]] over a shrinking frontier of vertices whose
+// parent is not yet a fixed point.  A rooted forest of height d converges
+// in at most ceil(log2 d) + 1 passes.  Cycles are detected afterwards: every
+// final target must be a root of the input (p[q[i]] == q[i]); an even cycle
+// may collapse onto false fixed points, an odd one never settles, and both
+// fail that test.
 
 __global__ void k_check_parents(const uint32_t *__restrict__ p, int32_t n, Counters *cnt)
 {
@@ -412,51 +576,93 @@ __global__ void k_check_parents(const uint32_t *__restrict__ p, int32_t n, Count
 
 void launch_check_parents(hipStream_t s, const uint32_t *p, int32_t n, Counters *dcnt)
 {
-    if (n) k_check_parents<<<grid_for((size_t)n), 256, 0, s>>>(p, n, dcnt);
+    if (n) k_check_parents<<<grid_for((size_t)n, 256, 1024), 256, 0, s>>>(p, n, dcnt);
 }
 
-__global__ void k_jump_init(const uint32_t *__restrict__ q, int32_t n, uint32_t *F, Counters *cnt)
+__global__ __launch_bounds__(CT_NT) void k_jump_init(const uint32_t *__restrict__ q, int32_t n,
+                                                     uint32_t *__restrict__ F, uint64_t *status,
+                                                     Counters *cnt)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < n; b += stride) {
-        const int64_t i = b + threadIdx.x;
-        bool act = false;
-        if (i < n) {
-            const uint32_t x = q[i];
-            act = q[x] != x;
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_lds[CT_NT / 64 + 1];
+    __shared__ uint64_t s_pre;
+    if (threadIdx.x == 0) s_tile = atomicAdd(&cnt->ticket, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const int64_t base = (int64_t)tile * CT_TILE + (int64_t)threadIdx.x * CT_IT;
+    uint32_t act = 0, c = 0;
+#pragma unroll
+    for (int k = 0; k < CT_IT; ++k) {
+        if (base + k < n) {
+            const uint32_t x = q[base + k];
+            if (q[x] != x) {
+                act |= 1u << k;
+                ++c;
+            }
         }
-        wave_append(act, (uint32_t)i, F, &cnt->nF);
     }
+    uint32_t oa, ob;
+    uint64_t tot;
+    tile_offsets2<CT_NT>(tile, c, 0u, status, s_lds, &s_pre, &oa, &ob, &tot);
+#pragma unroll
+    for (int k = 0; k < CT_IT; ++k)
+        if (act & (1u << k)) F[oa++] = (uint32_t)(base + k);
+    if (tile == gridDim.x - 1 && threadIdx.x == 0) cnt->nF = (uint32_t)(tot >> 31);
 }
 
-void launch_jump_init(hipStream_t s, const uint32_t *q, int32_t n, uint32_t *F, Counters *dcnt)
+void launch_jump_init(hipStream_t s, const uint32_t *q, int32_t n, uint32_t *F, uint64_t *status,
+                      Counters *dcnt)
 {
-    if (n) k_jump_init<<<grid_for((size_t)n), 256, 0, s>>>(q, n, F, dcnt);
+    const uint32_t tiles = ct_tiles((uint64_t)n);
+    if (!tiles) return;
+    prep_lookback(s, status, tiles, dcnt);
+    k_jump_init<<<tiles, CT_NT, 0, s>>>(q, n, F, status, dcnt);
 }
 
-__global__ void k_jump_pass(const uint32_t *__restrict__ Fin, uint32_t nF, uint32_t *q,
-                            uint32_t *__restrict__ Fout, Counters *cnt)
+__global__ __launch_bounds__(CT_NT) void k_jump_pass(const uint32_t *__restrict__ Fin, uint32_t nF,
+                                                     uint32_t *q, uint32_t *__restrict__ Fout,
+                                                     uint64_t *status, Counters *cnt)
 {
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t b = blockIdx.x * blockDim.x; b < nF; b += stride) {
-        const uint32_t k = b + threadIdx.x;
-        bool again = false;
-        uint32_t i = 0;
-        if (k < nF) {
-            i = Fin[k];
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_lds[CT_NT / 64 + 1];
+    __shared__ uint64_t s_pre;
+    if (threadIdx.x == 0) s_tile = atomicAdd(&cnt->ticket, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t base = tile * CT_TILE + threadIdx.x * CT_IT;
+    uint32_t again = 0, c = 0;
+    uint32_t id[CT_IT];
+#pragma unroll
+    for (int k = 0; k < CT_IT; ++k) {
+        id[k] = 0;
+        if (base + k < nF) {
+            const uint32_t i = Fin[base + k];
+            id[k] = i;
             const uint32_t x = load_relaxed_u32(q + i);
             const uint32_t y = load_relaxed_u32(q + x);
             store_relaxed_u32(q + i, y);
-            again = load_relaxed_u32(q + y) != y;
+            if (load_relaxed_u32(q + y) != y) {
+                again |= 1u << k;
+                ++c;
+            }
         }
-        wave_append(again, i, Fout, &cnt->nR);
     }
+    uint32_t oa, ob;
+    uint64_t tot;
+    tile_offsets2<CT_NT>(tile, c, 0u, status, s_lds, &s_pre, &oa, &ob, &tot);
+#pragma unroll
+    for (int k = 0; k < CT_IT; ++k)
+        if (again & (1u << k)) Fout[oa++] = id[k];
+    if (tile == gridDim.x - 1 && threadIdx.x == 0) cnt->nR = (uint32_t)(tot >> 31);
 }
 
 void launch_jump_pass(hipStream_t s, const uint32_t *Fin, uint32_t nF, uint32_t *q, uint32_t *Fout,
-                      Counters *dcnt)
+                      uint64_t *status, Counters *dcnt)
 {
-    if (nF) k_jump_pass<<<grid_for(nF), 256, 0, s>>>(Fin, nF, q, Fout, dcnt);
+    const uint32_t tiles = ct_tiles(nF);
+    if (!tiles) return;
+    prep_lookback(s, status, tiles, dcnt);
+    k_jump_pass<<<tiles, CT_NT, 0, s>>>(Fin, nF, q, Fout, status, dcnt);
 }
 
 __global__ void k_check_roots(const uint32_t *__restrict__ p, const uint32_t *__restrict__ q,
@@ -474,7 +680,7 @@ __global__ void k_check_roots(const uint32_t *__restrict__ p, const uint32_t *__
 void launch_check_roots(hipStream_t s, const uint32_t *p, const uint32_t *q, int32_t n,
                         Counters *dcnt)
 {
-    if (n) k_check_roots<<<grid_for((size_t)n), 256, 0, s>>>(p, q, n, dcnt);
+    if (n) k_check_roots<<<grid_for((size_t)n, 256, 1024), 256, 0, s>>>(p, q, n, dcnt);
 }
 
 }  // namespace msf

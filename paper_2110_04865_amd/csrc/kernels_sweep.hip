@@ -28,6 +28,9 @@ namespace msf {
 
 namespace {
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+
 // largest r in [lo, hi] with row_ptr[r] <= idx (row_ptr[lo] <= idx holds)
 __device__ __forceinline__ uint32_t row_search(const uint32_t *__restrict__ row_ptr, uint32_t lo,
                                                uint32_t hi, uint32_t idx)
@@ -59,7 +62,14 @@ __device__ __forceinline__ RunAgg combine(const RunAgg &a, const RunAgg &b)
 
 }  // namespace
 
-template <bool COMPACT>
+// Rows of a chunk whose row_ptr/p windows are staged in LDS; chunks that
+// span more rows (long runs of empty rows) search global memory instead.
+constexpr int SWEEP_WIN = 2048;
+
+// FIRST: the parent vector is the identity (round 1), so every stored entry
+// is outgoing, runs are rows, and no parent is read at all; a row that lies
+// wholly inside one wave has a single writer and is stored without an atomic.
+template <bool COMPACT, bool FIRST>
 __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
     const uint64_t *__restrict__ key, const uint32_t *__restrict__ chunk_row, uint32_t nnz,
@@ -71,6 +81,8 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     __shared__ uint32_t s_chunk;
     __shared__ uint32_t s_lds[SWEEP_BLOCK / 64 + 1];
     __shared__ uint64_t s_prefix;
+    __shared__ uint32_t s_rp[SWEEP_WIN + 1];
+    __shared__ uint32_t s_p[FIRST ? 1 : SWEEP_WIN];
 
     uint32_t c;
     if (COMPACT) {
@@ -84,12 +96,14 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     const uint32_t base = c * (uint32_t)SWEEP_CHUNK + threadIdx.x * E;
     const int nvalid = base >= nnz ? 0 : (nnz - base >= (uint32_t)E ? E : (int)(nnz - base));
 
+    // streamed loads first (non-temporal: read once per sweep)
     uint32_t cl[E];
     uint64_t ky[E];
     if (nvalid == E) {
-        const uint4 c4 = *reinterpret_cast<const uint4 *>(col + base);
-        const ulonglong2 k01 = *reinterpret_cast<const ulonglong2 *>(key + base);
-        const ulonglong2 k23 = *reinterpret_cast<const ulonglong2 *>(key + base + 2);
+        const u32x4 c4 = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(col + base));
+        const u64x2 k01 = __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(key + base));
+        const u64x2 k23 =
+            __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(key + base + 2));
         cl[0] = c4.x; cl[1] = c4.y; cl[2] = c4.z; cl[3] = c4.w;
         ky[0] = k01.x; ky[1] = k01.y; ky[2] = k23.x; ky[3] = k23.y;
     } else {
@@ -99,48 +113,78 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
             ky[k] = k < nvalid ? key[base + k] : KEY_INF;
         }
     }
+    // window of rows touched by this chunk
+    const uint32_t lo = chunk_row[c];
+    const uint32_t hi = chunk_row[c + 1 <= nchunks ? c + 1 : nchunks];
+    const uint32_t nrows = hi - lo + 1;
+    const bool win = nrows + 1 <= (uint32_t)SWEEP_WIN;
+    if (win) {
+        for (uint32_t t = threadIdx.x; t <= nrows; t += SWEEP_BLOCK) {
+            s_rp[t] = row_ptr[lo + t];
+            if (!FIRST && t < nrows) s_p[t] = p[lo + t];
+        }
+    }
+    // column parents: independent of the row search, issued before it
+    uint32_t pc[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) pc[k] = (!FIRST && k < nvalid) ? p[cl[k]] : 0u;
+    __syncthreads();
 
-    // rows and roots of the lane's entries
+    auto rp_at = [&](uint32_t rw) -> uint32_t { return win ? s_rp[rw - lo] : row_ptr[rw]; };
+    auto search = [&](uint32_t a, uint32_t b, uint32_t idx) -> uint32_t {
+        while (a < b) {
+            const uint32_t mid = a + ((b - a + 1) >> 1);
+            if (rp_at(mid) <= idx) a = mid;
+            else b = mid - 1;
+        }
+        return a;
+    };
+
     uint32_t root[E];
     uint64_t cand[E];
     uint32_t rowk[E];
     bool live[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        live[k] = false;
+        cand[k] = KEY_INF;
+        root[k] = NONE32;
+        rowk[k] = NONE32;
+    }
     if (nvalid > 0) {
-        const uint32_t lo = chunk_row[c];
-        const uint32_t hi = chunk_row[c + 1 <= nchunks ? c + 1 : nchunks];
-        uint32_t row = row_search(row_ptr, lo, hi, base);
-        uint32_t nxt = row_ptr[row + 1];
-        uint32_t prow = p[row];
+        uint32_t row = search(lo, hi, base);
+        uint32_t nxt = rp_at(row + 1);
+        uint32_t prow = FIRST ? row : (win ? s_p[row - lo] : p[row]);
 #pragma unroll
         for (int k = 0; k < E; ++k) {
             const uint32_t idx = base + k;
             if (k < nvalid) {
                 if (idx >= nxt) {
-                    row = row_search(row_ptr, row + 1, hi, idx);
-                    nxt = row_ptr[row + 1];
-                    prow = p[row];
+                    row = search(row + 1, hi, idx);
+                    nxt = rp_at(row + 1);
+                    prow = FIRST ? row : (win ? s_p[row - lo] : p[row]);
                 }
-                const uint32_t pc = p[cl[k]];
-                live[k] = prow != pc;
+                live[k] = FIRST ? true : (prow != pc[k]);
                 cand[k] = live[k] ? ky[k] : KEY_INF;
                 root[k] = prow;
                 rowk[k] = row;
-            } else {
-                live[k] = false;
-                cand[k] = KEY_INF;
-                root[k] = NONE32;
-                rowk[k] = NONE32;
             }
         }
-    } else {
-#pragma unroll
-        for (int k = 0; k < E; ++k) {
-            live[k] = false;
-            cand[k] = KEY_INF;
-            root[k] = NONE32;
-            rowk[k] = NONE32;
-        }
     }
+
+    // flush one run's minimum: in round 1 a row wholly inside this wave's
+    // entries has no other writer; everything else goes through the atomic
+    const uint32_t wave_lo = base - lane * E;
+    const uint32_t wave_hi = wave_lo + 64 * E;  // exclusive
+    auto flush = [&](uint32_t rt, uint64_t v) {
+        if (FIRST) {
+            if (v == KEY_INF) return;
+            if (rp_at(rt) >= wave_lo && rp_at(rt + 1) <= wave_hi) r[rt] = v;
+            else min_into(r, rt, v);
+        } else {
+            min_into(r, rt, v);
+        }
+    };
 
     // lane-local runs by root; interior runs are complete and flushed now
     uint32_t froot = root[0], lroot = root[0];
@@ -153,7 +197,7 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
             if (single) fmin = fmin < cand[k] ? fmin : cand[k];
             else lmin = lmin < cand[k] ? lmin : cand[k];
         } else {
-            if (!single) min_into(r, lroot, lmin);
+            if (!single) flush(lroot, lmin);
             single = false;
             lroot = root[k];
             lmin = cand[k];
@@ -183,10 +227,10 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
         uint64_t ffull = fmin;
         if (lane > 0 && prev_last == froot) ffull = ffull < prev_lrm ? ffull : prev_lrm;
         if (single) {
-            if (next_first != froot) min_into(r, froot, ffull);
+            if (next_first != froot) flush(froot, ffull);
         } else {
-            min_into(r, froot, ffull);
-            if (next_first != lroot) min_into(r, lroot, lmin);
+            flush(froot, ffull);
+            if (next_first != lroot) flush(lroot, lmin);
         }
     }
 
@@ -218,7 +262,7 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
         if (k < nvalid) {
             const uint32_t idx = base + k;
             const uint32_t row = rowk[k];
-            if (row_ptr[row] == idx) {
+            if (rp_at(row) == idx) {
                 // first entry of `row` (and of any empty rows just before it)
                 row_ptr_out[row] = pos;
                 for (int64_t j = (int64_t)row - 1; j >= 0 && row_ptr[j] == idx; --j)
@@ -253,12 +297,17 @@ __global__ void k_reduce_live(const uint32_t *__restrict__ block_live, uint32_t 
 }
 
 void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
-                  uint32_t *block_live, Counters *dcnt)
+                  uint32_t *block_live, Counters *dcnt, bool first)
 {
     if (a.nnz == 0) return;
-    k_sweep<false><<<a.nchunks, SWEEP_BLOCK, 0, s>>>(a.row_ptr, a.col, a.key, a.chunk_row, a.nnz,
-                                                     a.nchunks, a.n, p, r, nullptr, nullptr,
-                                                     nullptr, nullptr, nullptr, block_live);
+    if (first)
+        k_sweep<false, true><<<a.nchunks, SWEEP_BLOCK, 0, s>>>(
+            a.row_ptr, a.col, a.key, a.chunk_row, a.nnz, a.nchunks, a.n, p, r, nullptr, nullptr,
+            nullptr, nullptr, nullptr, block_live);
+    else
+        k_sweep<false, false><<<a.nchunks, SWEEP_BLOCK, 0, s>>>(
+            a.row_ptr, a.col, a.key, a.chunk_row, a.nnz, a.nchunks, a.n, p, r, nullptr, nullptr,
+            nullptr, nullptr, nullptr, block_live);
     if (block_live && dcnt) {
         launch_fill_u64(s, &dcnt->live, 0ull, 1);
         unsigned g = (a.nchunks + 255) / 256;
@@ -274,7 +323,7 @@ void launch_sweep_compact(hipStream_t s, const Adj &a, const uint32_t *p, uint64
     if (a.nnz == 0) return;
     launch_fill_u64(s, status, 0ull, a.nchunks);
     launch_fill_u32(s, &dcnt->ticket, 0u, 1);
-    k_sweep<true><<<a.nchunks, SWEEP_BLOCK, 0, s>>>(a.row_ptr, a.col, a.key, a.chunk_row, a.nnz,
+    k_sweep<true, false><<<a.nchunks, SWEEP_BLOCK, 0, s>>>(a.row_ptr, a.col, a.key, a.chunk_row, a.nnz,
                                                     a.nchunks, a.n, p, r, row_ptr_out, col_out,
                                                     key_out, status, dcnt, nullptr);
 }

@@ -19,7 +19,7 @@
 #include <stddef.h>
 #include <string>
 
-#include "../../include/msf.h"
+#include "msf.h"
 
 namespace msf {
 
@@ -81,8 +81,9 @@ enum Slot {
     WS_EDGES, WS_W, WS_SLOT, WS_DEG, WS_ROWPTR, WS_COL, WS_KEY, WS_CHUNKROW,
     WS_ROWPTR2, WS_COL2, WS_KEY2, WS_CHUNKROW2,
     WS_P, WS_R, WS_H, WS_HEDGE, WS_RL, WS_RL2, WS_FL, WS_FLAGS, WS_IDS,
-    WS_STATUS, WS_SCRATCH, WS_Q, WS_Q2,
+    WS_STATUS, WS_SCRATCH, WS_PART, WS_Q, WS_Q2,
     WS_BATCH0, WS_BATCH1, WS_BATCH2, WS_BATCH3,
+    WS_BH, WS_BHOFF, WS_BRLO, WS_BCOL, WS_BKEY,
     WS_COUNT
 };
 
@@ -118,6 +119,8 @@ struct Ctx {
     int filter_mode = 1;        // 0 never, 1 adaptive, 2 every round
     double filter_threshold = 0.80;
     bool check_rounds = false;  // read back error flags after every shortcut
+    bool first_round_kernel = true;  // identity-parent sweep in round 1
+    bool bucketed_build = true;      // LDS-only adjacency build
 };
 
 // Device view of an adjacency structure.
@@ -160,9 +163,11 @@ msf_status read_counters(Ctx *c);
 // ---- kernels (launch wrappers), all ordered on c->stream -----------------
 
 // Adjacency build (section 2 adjacency matrix, both directions).
+// Fills row_ptr[n+1], col/key[nnz] (capacity 2m) and *a; the number of
+// stored entries lands in dcnt->count and validation flags in dcnt->err.
 msf_status build_adjacency(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
                            msf_wtype wt, Adj *a, uint32_t *row_ptr, uint32_t *col, uint64_t *key,
-                           uint32_t *deg_tmp, uint2 *slot_tmp, uint32_t *chunk_row);
+                           uint32_t *chunk_row);
 uint32_t sweep_nchunks(uint32_t nnz);
 // Exclusive scan of u32 in[0..N) -> out[0..N]; out[N] (and *total_out,
 // nullable, device) receive the total.
@@ -175,32 +180,36 @@ void launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t v, size_t n);
 void launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, size_t n);
 void launch_iota_u32(hipStream_t s, uint32_t *p, size_t n);
 void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
-                  uint32_t *block_live = nullptr, Counters *dcnt = nullptr);
+                  uint32_t *block_live = nullptr, Counters *dcnt = nullptr, bool first = false);
 void launch_sweep_compact(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
                           uint32_t *row_ptr_out, uint32_t *col_out, uint64_t *key_out,
                           uint64_t *status, Counters *dcnt);
 
-// Round kernels.
+// Round kernels.  `status` is a look-back status array (>= tiles entries);
+// `part` holds per-block partials (>= 4096 u32, or output_part_bytes(m)).
+uint32_t compaction_tiles(uint64_t n);
 void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, uint32_t *R,
-                       Counters *dcnt);
+                       uint64_t *status, Counters *dcnt);
 void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, const uint32_t *p,
                  const int32_t *edges, uint32_t *h, uint32_t *hedge);
 void launch_tiebreak(hipStream_t s, const uint32_t *R, uint32_t nR, uint32_t *h,
                      const uint32_t *hedge, uint8_t *in_forest, uint32_t *Rnext, uint32_t *F,
-                     Counters *dcnt);
-void launch_chase(hipStream_t s, const uint32_t *F, uint32_t nF, uint32_t *h, Counters *dcnt);
+                     uint64_t *status, Counters *dcnt);
+void launch_chase(hipStream_t s, const uint32_t *F, uint32_t nF, uint32_t *h, uint32_t *part,
+                  Counters *dcnt);
 void launch_update_parents(hipStream_t s, const uint32_t *row_ptr, int32_t n, uint32_t *p,
-                           const uint32_t *h, Counters *dcnt);
-void launch_output(hipStream_t s, const uint8_t *in_forest, int64_t m, const void *w,
-                   msf_wtype wt, int32_t *ids, uint64_t *status, Counters *dcnt);
-void launch_finalize_total(hipStream_t s, Counters *dcnt, msf_wtype wt);
+                           const uint32_t *h, uint32_t *part, Counters *dcnt);
 int64_t output_tiles(int64_t m);
+size_t output_part_bytes(int64_t m);
+void launch_output(hipStream_t s, const uint8_t *in_forest, int64_t m, const void *w,
+                   msf_wtype wt, int32_t *ids, uint64_t *status, void *part, Counters *dcnt);
 
 // Shortcut of an arbitrary parent vector (msf_shortcut).
 void launch_check_parents(hipStream_t s, const uint32_t *p, int32_t n, Counters *dcnt);
-void launch_jump_init(hipStream_t s, const uint32_t *q, int32_t n, uint32_t *F, Counters *dcnt);
+void launch_jump_init(hipStream_t s, const uint32_t *q, int32_t n, uint32_t *F, uint64_t *status,
+                      Counters *dcnt);
 void launch_jump_pass(hipStream_t s, const uint32_t *Fin, uint32_t nF, uint32_t *q,
-                      uint32_t *Fout, Counters *dcnt);
+                      uint32_t *Fout, uint64_t *status, Counters *dcnt);
 void launch_check_roots(hipStream_t s, const uint32_t *p, const uint32_t *q, int32_t n,
                         Counters *dcnt);
 

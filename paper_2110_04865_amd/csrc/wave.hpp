@@ -65,6 +65,7 @@ __device__ __forceinline__ T block_excl_sum(T v, T *lds, T *total)
     __syncthreads();
     T r = lds[w] + inc - v;
     *total = lds[NW];
+    __syncthreads();  // lds may be reused right after
     return r;
 }
 
@@ -115,6 +116,41 @@ __device__ __forceinline__ uint64_t lookback(uint64_t *status, uint32_t tile, ui
     }
     if (lane == 0) lb_store(status + tile, LB_PRE | (excl + agg));
     return excl;
+}
+
+// ---- ordered compaction of a tile into up to two lists ---------------------
+// Every thread of an NT-thread block passes its counts (ca, cb) of items
+// going to lists a and b.  Returns this thread's first output index in each
+// list; *total receives the running totals (a << 31 | b) after this tile.
+// Tile ids come from an atomic ticket (see lookback).  `lds` holds NT/64+1
+// u64; `s_pre` one u64.  Contains __syncthreads().
+template <int NT>
+__device__ __forceinline__ void tile_offsets2(uint32_t tile, uint32_t ca, uint32_t cb,
+                                              uint64_t *status, uint64_t *lds, uint64_t *s_pre,
+                                              uint32_t *oa, uint32_t *ob, uint64_t *total)
+{
+    constexpr uint64_t M31 = (1ull << 31) - 1ull;
+    const uint64_t mine = ((uint64_t)ca << 31) | (uint64_t)cb;
+    uint64_t btot;
+    const uint64_t ex = block_excl_sum<NT>(mine, lds, &btot);
+    if (threadIdx.x < 64) {
+        const uint64_t pre = lookback(status, tile, btot);
+        if (threadIdx.x == 0) *s_pre = pre;
+    }
+    __syncthreads();
+    const uint64_t pre = *s_pre;
+    *oa = (uint32_t)((pre >> 31) + (ex >> 31));
+    *ob = (uint32_t)((pre & M31) + (ex & M31));
+    *total = pre + btot;
+}
+
+// Block-wide sum (all threads get it).  `lds` holds NT/64+1 elements.
+template <int NT, typename T>
+__device__ __forceinline__ T block_sum(T v, T *lds)
+{
+    T tot;
+    block_excl_sum<NT>(v, lds, &tot);
+    return tot;
 }
 
 }  // namespace msf
