@@ -36,13 +36,19 @@ msf_status ws_get(Ctx *c, Slot s, size_t bytes, void **out)
     if (bytes == 0) bytes = 256;
     if (b.cap < bytes) {
         if (b.ptr) {
-            MSF_HIP(hipStreamSynchronize(c->stream));
-            MSF_HIP(hipFree(b.ptr));
+            if (c->async_alloc) {
+                MSF_HIP(hipFreeAsync(b.ptr, c->stream));
+            } else {
+                MSF_HIP(hipStreamSynchronize(c->stream));
+                MSF_HIP(hipFree(b.ptr));
+            }
             b.ptr = nullptr;
             b.cap = 0;
         }
-        size_t cap = (bytes + (1u << 20) - 1) & ~(size_t)((1u << 20) - 1);
-        hipError_t e = hipMalloc(&b.ptr, cap);
+        const size_t gran = c->async_alloc ? ((size_t)1 << 16) : ((size_t)1 << 20);
+        size_t cap = (bytes + gran - 1) & ~(gran - 1);
+        hipError_t e = c->async_alloc ? hipMallocAsync(&b.ptr, cap, c->stream)
+                                      : hipMalloc(&b.ptr, cap);
         if (e != hipSuccess) {
             b.ptr = nullptr;
             (void)hipGetLastError();
@@ -62,13 +68,13 @@ msf_status read_counters(Ctx *c)
     return MSF_OK;
 }
 
-static void zero_counters(Ctx *c)
+void zero_counters(Ctx *c)
 {
     launch_fill_u32(c->stream, reinterpret_cast<uint32_t *>(c->dcnt), 0u,
                     sizeof(Counters) / sizeof(uint32_t));
 }
 
-static msf_status decode_err(uint32_t err)
+msf_status decode_err(uint32_t err)
 {
     if (err & ERR_ENDPOINT) {
         set_error("edge endpoint outside [0, n)");
@@ -89,218 +95,6 @@ static msf_status decode_err(uint32_t err)
     return MSF_OK;
 }
 
-// ---------------------------------------------------------------- solve --
-
-struct SolveBufs {
-    uint2 *slot;
-    uint32_t *deg, *rp[2], *col[2], *crow[2], *p, *h, *hedge, *R[2], *F, *blive;
-    uint64_t *key[2], *r, *status;
-    uint8_t *flags;
-    void *part;
-};
-
-static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, SolveBufs *b)
-{
-    const size_t nn = (size_t)std::max(n, 1), mm = (size_t)std::max<int64_t>(m, 1);
-    const size_t nnz_cap = 2 * mm;
-    const size_t nch = sweep_nchunks((uint32_t)std::min<size_t>(nnz_cap, 0xFFFFFFFFull)) + 2;
-    size_t st = std::max<size_t>(nch, (size_t)output_tiles((int64_t)mm) + 1);
-    st = std::max<size_t>(st, nn / 2048 + 2);
-    const size_t part_bytes = std::max<size_t>(output_part_bytes((int64_t)mm), 4 * 4096 + 256);
-    void *v[22];
-    msf_status rc;
-#define GET(i, slot, bytes)                                  \
-    if ((rc = ws_get(c, slot, (bytes), &v[i])) != MSF_OK) return rc;
-    GET(2, WS_ROWPTR, 4 * (nn + 1));
-    GET(3, WS_COL, 4 * nnz_cap);
-    GET(4, WS_KEY, 8 * nnz_cap);
-    GET(5, WS_CHUNKROW, 4 * nch);
-    GET(6, WS_P, 4 * nn);
-    GET(7, WS_R, 8 * nn);
-    GET(8, WS_H, 4 * nn);
-    GET(9, WS_HEDGE, 4 * nn);
-    GET(10, WS_RL, 4 * nn);
-    GET(11, WS_RL2, 4 * nn);
-    GET(12, WS_FL, 4 * nn);
-    GET(13, WS_FLAGS, (mm + 16) & ~(size_t)3);
-    GET(14, WS_STATUS, 8 * st);
-    GET(15, WS_SCRATCH, 4 * nch);
-    GET(16, WS_PART, part_bytes);
-#undef GET
-    b->rp[0] = (uint32_t *)v[2];
-    b->col[0] = (uint32_t *)v[3];
-    b->key[0] = (uint64_t *)v[4];
-    b->crow[0] = (uint32_t *)v[5];
-    b->p = (uint32_t *)v[6];
-    b->r = (uint64_t *)v[7];
-    b->h = (uint32_t *)v[8];
-    b->hedge = (uint32_t *)v[9];
-    b->R[0] = (uint32_t *)v[10];
-    b->R[1] = (uint32_t *)v[11];
-    b->F = (uint32_t *)v[12];
-    b->flags = (uint8_t *)v[13];
-    b->status = (uint64_t *)v[14];
-    b->blive = (uint32_t *)v[15];
-    b->part = v[16];
-    b->rp[1] = b->col[1] = b->crow[1] = nullptr;
-    b->key[1] = nullptr;
-    return MSF_OK;
-}
-
-static msf_status get_filter_bufs(Ctx *c, int32_t n, int64_t m, SolveBufs *b)
-{
-    if (b->rp[1]) return MSF_OK;
-    const size_t nn = (size_t)std::max(n, 1), mm = (size_t)std::max<int64_t>(m, 1);
-    const size_t nnz_cap = 2 * mm;
-    const size_t nch = sweep_nchunks((uint32_t)std::min<size_t>(nnz_cap, 0xFFFFFFFFull)) + 2;
-    void *v[4];
-    msf_status rc;
-    if ((rc = ws_get(c, WS_ROWPTR2, 4 * (nn + 1), &v[0]))) return rc;
-    if ((rc = ws_get(c, WS_COL2, 4 * nnz_cap, &v[1]))) return rc;
-    if ((rc = ws_get(c, WS_KEY2, 8 * nnz_cap, &v[2]))) return rc;
-    if ((rc = ws_get(c, WS_CHUNKROW2, 4 * nch, &v[3]))) return rc;
-    b->rp[1] = (uint32_t *)v[0];
-    b->col[1] = (uint32_t *)v[1];
-    b->key[1] = (uint64_t *)v[2];
-    b->crow[1] = (uint32_t *)v[3];
-    return MSF_OK;
-}
-
-msf_status solve_device(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
-                        msf_wtype wt, int32_t *d_ids, int64_t *count, msf_total *total)
-{
-    hipStream_t s = c->stream;
-    msf_stats st{};
-    SolveBufs b{};
-    msf_status rc = get_solve_bufs(c, n, m, &b);
-    if (rc) return rc;
-
-    MSF_HIP(hipEventRecord(c->ev[0], s));
-    zero_counters(c);
-    Adj a;
-    rc = build_adjacency(c, n, m, d_edges, d_w, wt, &a, b.rp[0], b.col[0], b.key[0], b.crow[0]);
-    if (rc) return rc;
-    MSF_TRY(read_counters(c));
-    if ((rc = decode_err(c->hcnt->err))) return rc;
-    a.nnz = c->hcnt->count;
-    a.nchunks = sweep_nchunks(a.nnz);
-    launch_chunk_rows(s, a.row_ptr, n, a.nnz, a.chunk_row, a.nchunks);
-    MSF_HIP(hipEventRecord(c->ev[1], s));
-
-    // round state
-    launch_iota_u32(s, b.p, (size_t)n);
-    launch_iota_u32(s, b.h, (size_t)n);
-    launch_fill_u64(s, b.r, KEY_INF, (size_t)n);
-    launch_fill_u32(s, reinterpret_cast<uint32_t *>(b.flags), 0u, ((size_t)m + 3) / 4);
-    launch_init_roots(s, a.row_ptr, n, b.R[0], b.status, c->dcnt);
-    MSF_HIP(hipGetLastError());
-    MSF_TRY(read_counters(c));
-    uint32_t nR = c->hcnt->nR;
-    uint32_t rows = nR;  // rows with entries (every non-isolated vertex)
-    bool rows_pending = false;
-    int ri = 0;    // which R buffer is current
-    int ai = 0;    // which adjacency buffer set is current
-    double live_frac = 1.0;
-    int rounds = 0;
-    // fewer than two live roots: no outgoing edge can remain
-    while (nR >= 2 && a.nnz > 0 && rounds < 1000) {
-        bool compact = false;
-        if (c->filter_mode == 2) compact = true;
-        else if (c->filter_mode == 1) compact = live_frac < c->filter_threshold;
-        Adj nxt = a;
-        const int ev_k = rounds < 64 ? rounds : -1;
-        if (ev_k >= 0) {
-            MSF_HIP(hipEventRecord(c->sev[2 * ev_k], s));
-            st.sweep_bytes[ev_k] = 12.0 * a.nnz + 8.0 * rows + 8.0 * nR;
-        }
-        if (compact) {
-            if ((rc = get_filter_bufs(c, n, m, &b))) return rc;
-            nxt.row_ptr = b.rp[ai ^ 1];
-            nxt.col = b.col[ai ^ 1];
-            nxt.key = b.key[ai ^ 1];
-            nxt.chunk_row = b.crow[ai ^ 1];
-            launch_sweep_compact(s, a, b.p, b.r, nxt.row_ptr, nxt.col, nxt.key, b.status,
-                                 c->dcnt);
-        } else {
-            // round 1: p is the identity and nothing has been filtered
-            launch_sweep(s, a, b.p, b.r, b.blive, c->dcnt, rounds == 0 && c->first_round_kernel);
-        }
-        if (ev_k >= 0) MSF_HIP(hipEventRecord(c->sev[2 * ev_k + 1], s));
-        launch_hook(s, b.R[ri], nR, b.r, b.p, d_edges, b.h, b.hedge);
-        launch_fill_u32(s, &c->dcnt->nR, 0u, 3);  // nR, nF, hooks
-        launch_tiebreak(s, b.R[ri], nR, b.h, b.hedge, b.flags, b.R[ri ^ 1], b.F, b.status,
-                        c->dcnt);
-        MSF_HIP(hipGetLastError());
-        MSF_TRY(read_counters(c));
-        const uint32_t nF = c->hcnt->nF, nRn = c->hcnt->nR;
-        if (rows_pending && ev_k >= 0) {
-            st.sweep_bytes[ev_k] += 8.0 * c->hcnt->rows;  // rows of the swept CSR
-            rows_pending = false;
-        }
-        if (rounds < 64) {
-            st.hooks[rounds] = nF;
-            st.active_nnz[rounds] = a.nnz;
-        }
-        ++rounds;
-        if (nF) ++st.hook_rounds;
-        if (compact) {
-            const uint32_t nnz2 = c->hcnt->nnz_out;
-            live_frac = a.nnz ? (double)nnz2 / (double)a.nnz : 0.0;
-            nxt.nnz = nnz2;
-            nxt.nchunks = sweep_nchunks(nnz2);
-            if (nnz2) launch_chunk_rows(s, nxt.row_ptr, n, nnz2, nxt.chunk_row, nxt.nchunks);
-            a = nxt;
-            ai ^= 1;
-            ++st.filtered;
-        } else {
-            live_frac = a.nnz ? (double)c->hcnt->live / (double)a.nnz : 0.0;
-        }
-        if (nF == 0) break;
-        launch_chase(s, b.F, nF, b.h, (uint32_t *)b.part, c->dcnt);
-        if (c->check_rounds) {
-            MSF_TRY(read_counters(c));
-            if (c->hcnt->err) {
-                set_error("internal error: hook cycle in round %d", rounds);
-                return MSF_EDEVICE;
-            }
-        }
-        launch_update_parents(s, a.row_ptr, n, b.p, b.h, (uint32_t *)b.part, c->dcnt);
-        ri ^= 1;
-        nR = nRn;
-        rows = 0;  // read back with the next round's counters
-        rows_pending = true;
-    }
-    st.rounds = rounds;
-
-    // output
-    launch_output(s, b.flags, m, d_w, wt, d_ids, b.status, b.part, c->dcnt);
-    MSF_HIP(hipEventRecord(c->ev[2], s));
-    MSF_HIP(hipGetLastError());
-    MSF_TRY(read_counters(c));
-    if (c->hcnt->err) {
-        set_error("internal error: hook cycle detected");
-        return MSF_EDEVICE;
-    }
-    float ms_build = 0.f, ms_rounds = 0.f;
-    (void)hipEventElapsedTime(&ms_build, c->ev[0], c->ev[1]);
-    (void)hipEventElapsedTime(&ms_rounds, c->ev[1], c->ev[2]);
-    st.build_ms = ms_build;
-    st.rounds_ms = ms_rounds;
-    for (int k = 0; k < rounds && k < 64; ++k) {
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, c->sev[2 * k], c->sev[2 * k + 1]);
-        st.sweep_ms[k] = ms;
-    }
-    st.max_chase = (int32_t)c->hcnt->max_chase;
-    c->stats = st;
-    *count = (m > 0) ? (int64_t)c->hcnt->count : 0;
-    if (total) {
-        total->u64 = (wt == MSF_W_U32) ? c->hcnt->total_u64 : 0;
-        total->f64 = (m > 0) ? c->hcnt->total_f64 : 0.0;
-    }
-    return MSF_OK;
-}
-
 }  // namespace msf
 
 using namespace msf;
@@ -312,6 +106,68 @@ extern "C" {
 const char *msf_last_error(void) { return g_err.c_str(); }
 
 const char *msf_version(void) { return "msf-gfx950 0.1"; }
+
+}  // extern "C"
+
+namespace msf {
+
+msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc)
+{
+    c->device = device;
+    c->stream = stream;
+    c->async_alloc = async_alloc;
+    if (hipMalloc(&c->dcnt, sizeof(Counters)) != hipSuccess ||
+        hipHostMalloc(&c->hcnt, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("counter allocation failed");
+        return MSF_ENOMEM;
+    }
+    for (auto &ev : c->sev)
+        if (hipEventCreate(&ev) != hipSuccess) {
+            set_error("event creation failed");
+            return MSF_EDEVICE;
+        }
+    for (auto &ev : c->ev)
+        if (hipEventCreate(&ev) != hipSuccess) {
+            set_error("event creation failed");
+            return MSF_EDEVICE;
+        }
+    if (const char *f = getenv("MSF_FILTER")) c->filter_mode = atoi(f);
+    if (const char *f = getenv("MSF_FILTER_THRESHOLD")) c->filter_threshold = atof(f);
+    if (const char *f = getenv("MSF_CHECK_ROUNDS")) c->check_rounds = atoi(f) != 0;
+    if (const char *f = getenv("MSF_FIRST_ROUND")) c->first_round_kernel = atoi(f) != 0;
+    if (const char *f = getenv("MSF_BUCKETED_BUILD")) c->bucketed_build = atoi(f) != 0;
+    return MSF_OK;
+}
+
+void ctx_release_workspace(Ctx *c)
+{
+    for (auto &b : c->ws) {
+        if (!b.ptr) continue;
+        if (c->async_alloc) (void)hipFreeAsync(b.ptr, c->stream);
+        else (void)hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.cap = 0;
+    }
+}
+
+void ctx_release(Ctx *c)
+{
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    ctx_release_workspace(c);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &ev : c->ev)
+        if (ev) (void)hipEventDestroy(ev), ev = nullptr;
+    for (auto &ev : c->sev)
+        if (ev) (void)hipEventDestroy(ev), ev = nullptr;
+    if (c->dcnt) (void)hipFree(c->dcnt), c->dcnt = nullptr;
+    if (c->hcnt) (void)hipHostFree(c->hcnt), c->hcnt = nullptr;
+}
+
+}  // namespace msf
+
+extern "C" {
 
 msf_status msf_ctx_create(int device, void *hip_stream, msf_ctx **out)
 {
@@ -335,36 +191,11 @@ msf_status msf_ctx_create(int device, void *hip_stream, msf_ctx **out)
         set_error("host allocation failed");
         return MSF_ENOMEM;
     }
-    Ctx *c = &x->c;
-    c->device = device;
-    c->stream = (hipStream_t)hip_stream;
-    if (hipMalloc(&c->dcnt, sizeof(Counters)) != hipSuccess ||
-        hipHostMalloc(&c->hcnt, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        if (c->dcnt) (void)hipFree(c->dcnt);
-        delete x;
-        set_error("counter allocation failed");
-        return MSF_ENOMEM;
+    msf_status rc = ctx_init(&x->c, device, (hipStream_t)hip_stream, false);
+    if (rc) {
+        msf_ctx_destroy(x);
+        return rc;
     }
-    for (auto &ev : c->sev) {
-        if (hipEventCreate(&ev) != hipSuccess) {
-            set_error("event creation failed");
-            msf_ctx_destroy(x);
-            return MSF_EDEVICE;
-        }
-    }
-    for (auto &ev : c->ev) {
-        if (hipEventCreate(&ev) != hipSuccess) {
-            set_error("event creation failed");
-            msf_ctx_destroy(x);
-            return MSF_EDEVICE;
-        }
-    }
-    if (const char *f = getenv("MSF_FILTER")) c->filter_mode = atoi(f);
-    if (const char *f = getenv("MSF_CHECK_ROUNDS")) c->check_rounds = atoi(f) != 0;
-    if (const char *f = getenv("MSF_FIRST_ROUND")) c->first_round_kernel = atoi(f) != 0;
-    if (const char *f = getenv("MSF_BUCKETED_BUILD")) c->bucketed_build = atoi(f) != 0;
-    if (const char *f = getenv("MSF_FILTER_THRESHOLD")) c->filter_threshold = atof(f);
     *out = x;
     return MSF_OK;
 }
@@ -372,17 +203,7 @@ msf_status msf_ctx_create(int device, void *hip_stream, msf_ctx **out)
 void msf_ctx_destroy(msf_ctx *x)
 {
     if (!x) return;
-    Ctx *c = &x->c;
-    (void)hipSetDevice(c->device);
-    (void)hipStreamSynchronize(c->stream);
-    for (auto &b : c->ws)
-        if (b.ptr) (void)hipFree(b.ptr);
-    for (auto &ev : c->ev)
-        if (ev) (void)hipEventDestroy(ev);
-    for (auto &ev : c->sev)
-        if (ev) (void)hipEventDestroy(ev);
-    if (c->dcnt) (void)hipFree(c->dcnt);
-    if (c->hcnt) (void)hipHostFree(c->hcnt);
+    ctx_release(&x->c);
     delete x;
 }
 
@@ -613,11 +434,12 @@ msf_status msf_shortcut(msf_ctx *ctx, int32_t n, uint32_t *p, int32_t *sub_iters
 
 size_t msf_request_footprint(int32_t n, int64_t m)
 {
-    // edges + weights (12m), slots (8m), CSR (12 * 2m + 4(n+1)), chunk rows,
-    // per-vertex state p, h, hedge, r, lists (32n), forest flags (m)
+    // per edge: input copy (12), bucketed build staging (28), adjacency and
+    // its filtered twin (2 x 24), forest flags (1) -> 89 bytes, rounded up;
+    // per vertex: row pointers x2 (8), p, h, hedge, three lists, ids (28),
+    // r (8) -> 44 bytes; plus chunk tables, partials and allocation slack
     const size_t nn = (size_t)std::max(n, 1), mm = (size_t)std::max<int64_t>(m, 1);
-    return 12 * mm + 8 * mm + 24 * mm + 4 * (nn + 1) + (2 * mm / SWEEP_CHUNK + 2) * 4 + 32 * nn +
-           mm + (1u << 16);
+    return 90 * mm + 44 * nn + ((size_t)32 << 20);
 }
 
 }  // extern "C"

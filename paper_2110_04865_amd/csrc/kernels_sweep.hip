@@ -31,18 +31,6 @@ namespace {
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
-// largest r in [lo, hi] with row_ptr[r] <= idx (row_ptr[lo] <= idx holds)
-__device__ __forceinline__ uint32_t row_search(const uint32_t *__restrict__ row_ptr, uint32_t lo,
-                                               uint32_t hi, uint32_t idx)
-{
-    while (lo < hi) {
-        uint32_t mid = lo + ((hi - lo + 1) >> 1);
-        if (row_ptr[mid] <= idx) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 struct RunAgg {
     uint32_t first_root, last_root;
     uint32_t hib;  // a run boundary lies inside the span

@@ -107,20 +107,11 @@ struct Counters {
     uint32_t pad_;
 };
 
-struct Ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    DevBuf ws[WS_COUNT];
-    Counters *dcnt = nullptr;   // device
-    Counters *hcnt = nullptr;   // pinned host mirror
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    hipEvent_t sev[2 * 64] = {};  // sweep start/end events, per round
-    msf_stats stats{};
-    int filter_mode = 1;        // 0 never, 1 adaptive, 2 every round
-    double filter_threshold = 0.80;
-    bool check_rounds = false;  // read back error flags after every shortcut
-    bool first_round_kernel = true;  // identity-parent sweep in round 1
-    bool bucketed_build = true;      // LDS-only adjacency build
+struct SolveBufs {
+    uint32_t *rp[2], *col[2], *crow[2], *p, *h, *hedge, *R[2], *F, *blive;
+    uint64_t *key[2], *r, *status;
+    uint8_t *flags;
+    void *part;
 };
 
 // Device view of an adjacency structure.
@@ -137,6 +128,42 @@ struct Adj {
     const void *w = nullptr;          // weights, for totals
     msf_wtype wtype = MSF_W_U32;
 };
+
+struct SolveState {
+    int phase = 0;  // 0 idle, 1 build, 2 roots, 3 round, 4 output, 5 done
+    int32_t n = 0;
+    int64_t m = 0;
+    const int32_t *edges = nullptr;
+    const void *w = nullptr;
+    msf_wtype wt = MSF_W_U32;
+    int32_t *ids = nullptr;
+    SolveBufs b{};
+    Adj a;
+    uint32_t nR = 0, rows = 0;
+    bool rows_pending = false, compact = false;
+    int ri = 0, ai = 0, rounds = 0;
+    double live_frac = 1.0;
+    msf_stats st{};
+};
+
+struct Ctx {
+    int device = 0;
+    bool async_alloc = false;   // stream-ordered workspace (server slots)
+    hipStream_t stream = nullptr;
+    DevBuf ws[WS_COUNT];
+    Counters *dcnt = nullptr;   // device
+    Counters *hcnt = nullptr;   // pinned host mirror
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t sev[2 * 64] = {};  // sweep start/end events, per round
+    msf_stats stats{};
+    int filter_mode = 1;        // 0 never, 1 adaptive, 2 every round
+    double filter_threshold = 0.80;
+    bool check_rounds = false;  // read back error flags after every shortcut
+    bool first_round_kernel = true;  // identity-parent sweep in round 1
+    bool bucketed_build = true;      // LDS-only adjacency build
+    SolveState ss;
+};
+
 
 // Error reporting (thread-local message).
 void set_error(const char *fmt, ...);
@@ -213,8 +240,27 @@ void launch_jump_pass(hipStream_t s, const uint32_t *Fin, uint32_t nF, uint32_t 
 void launch_check_roots(hipStream_t s, const uint32_t *p, const uint32_t *q, int32_t n,
                         Counters *dcnt);
 
-// Whole-graph solve on prepared device inputs; writes ids (device) and
-// fills count/total.  `keep_adj` graphs are left intact (msf_graph path).
+void zero_counters(Ctx *c);
+msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc);
+void ctx_release_workspace(Ctx *c);
+void ctx_release(Ctx *c);
+msf_status decode_err(uint32_t err);
+
+// ---- resumable solve (one per context) -----------------------------------
+// solve_start enqueues the adjacency build; every later step is enqueued by
+// solve_advance once the previous step's counters have reached the host
+// (solve_ready polls an event without blocking).  Each step ends with an
+// asynchronous copy of the counters to pinned memory, so a driver can keep
+// many contexts (each with its own stream) in flight at once.
+msf_status solve_start(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
+                       msf_wtype wt, int32_t *d_ids);
+bool solve_ready(Ctx *c);
+msf_status solve_advance(Ctx *c);
+bool solve_done(const Ctx *c);
+void solve_result(const Ctx *c, int64_t *count, msf_total *total);
+
+// Whole-graph solve on device inputs (blocking driver of the above); writes
+// ids (device) and fills count/total.
 msf_status solve_device(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
                         msf_wtype wt, int32_t *d_ids, int64_t *count, msf_total *total);
 

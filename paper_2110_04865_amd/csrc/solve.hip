@@ -1,0 +1,284 @@
+// The round loop of Algorithm 2 with complete shortcutting (section 4.2), as
+// a resumable state machine per context.
+//
+// Step sequence (each step ends with an asynchronous copy of the counters
+// to pinned host memory and an event):
+//   build   adjacency build (validation flags, stored-entry count)
+//   roots   round state: p = identity, r = empty, forest flags cleared, R
+//   round   multilinear sweep (+ filtering when the live fraction is low),
+//           hook, tie break; the counters say how many roots hooked (nF)
+//           and how many stay roots (nR)
+//   -> if some root hooked: shortcut chase + parent update are enqueued in
+//      front of the next round's sweep
+//   output  ascending forest ids, count, exact total
+//
+// The loop stops after a round in which nothing hooks (the parent vector is
+// then unchanged, the paper's termination test), or earlier when fewer than
+// two roots can still have an outgoing edge.
+#include <algorithm>
+
+#include "msf_internal.hpp"
+
+namespace msf {
+
+static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, SolveBufs *b)
+{
+    const size_t nn = (size_t)std::max(n, 1), mm = (size_t)std::max<int64_t>(m, 1);
+    const size_t nnz_cap = 2 * mm;
+    const size_t nch = sweep_nchunks((uint32_t)std::min<size_t>(nnz_cap, 0xFFFFFFFFull)) + 2;
+    size_t st = std::max<size_t>(nch, (size_t)output_tiles((int64_t)mm) + 1);
+    st = std::max<size_t>(st, nn / 2048 + 2);
+    const size_t part_bytes = std::max<size_t>(output_part_bytes((int64_t)mm), 4 * 4096 + 256);
+    struct Req {
+        Slot s;
+        size_t bytes;
+    } req[] = {
+        {WS_ROWPTR, 4 * (nn + 1)}, {WS_COL, 4 * nnz_cap}, {WS_KEY, 8 * nnz_cap},
+        {WS_CHUNKROW, 4 * nch},    {WS_P, 4 * nn},        {WS_R, 8 * nn},
+        {WS_H, 4 * nn},            {WS_HEDGE, 4 * nn},    {WS_RL, 4 * nn},
+        {WS_RL2, 4 * nn},          {WS_FL, 4 * nn},       {WS_FLAGS, (mm + 16) & ~(size_t)3},
+        {WS_STATUS, 8 * st},       {WS_SCRATCH, 4 * nch}, {WS_PART, part_bytes},
+    };
+    void *v[sizeof(req) / sizeof(req[0])];
+    for (size_t i = 0; i < sizeof(req) / sizeof(req[0]); ++i)
+        MSF_TRY(ws_get(c, req[i].s, req[i].bytes, &v[i]));
+    b->rp[0] = (uint32_t *)v[0];
+    b->col[0] = (uint32_t *)v[1];
+    b->key[0] = (uint64_t *)v[2];
+    b->crow[0] = (uint32_t *)v[3];
+    b->p = (uint32_t *)v[4];
+    b->r = (uint64_t *)v[5];
+    b->h = (uint32_t *)v[6];
+    b->hedge = (uint32_t *)v[7];
+    b->R[0] = (uint32_t *)v[8];
+    b->R[1] = (uint32_t *)v[9];
+    b->F = (uint32_t *)v[10];
+    b->flags = (uint8_t *)v[11];
+    b->status = (uint64_t *)v[12];
+    b->blive = (uint32_t *)v[13];
+    b->part = v[14];
+    b->rp[1] = b->col[1] = b->crow[1] = nullptr;
+    b->key[1] = nullptr;
+    return MSF_OK;
+}
+
+static msf_status get_filter_bufs(Ctx *c, int32_t n, int64_t m, SolveBufs *b)
+{
+    if (b->rp[1]) return MSF_OK;
+    const size_t nn = (size_t)std::max(n, 1), mm = (size_t)std::max<int64_t>(m, 1);
+    const size_t nnz_cap = 2 * mm;
+    const size_t nch = sweep_nchunks((uint32_t)std::min<size_t>(nnz_cap, 0xFFFFFFFFull)) + 2;
+    void *v[4];
+    MSF_TRY(ws_get(c, WS_ROWPTR2, 4 * (nn + 1), &v[0]));
+    MSF_TRY(ws_get(c, WS_COL2, 4 * nnz_cap, &v[1]));
+    MSF_TRY(ws_get(c, WS_KEY2, 8 * nnz_cap, &v[2]));
+    MSF_TRY(ws_get(c, WS_CHUNKROW2, 4 * nch, &v[3]));
+    b->rp[1] = (uint32_t *)v[0];
+    b->col[1] = (uint32_t *)v[1];
+    b->key[1] = (uint64_t *)v[2];
+    b->crow[1] = (uint32_t *)v[3];
+    return MSF_OK;
+}
+
+// End a step: counters to pinned host memory, then the step event.
+static msf_status end_step(Ctx *c, int next_phase)
+{
+    MSF_HIP(hipGetLastError());
+    MSF_HIP(hipMemcpyAsync(c->hcnt, c->dcnt, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
+    MSF_HIP(hipEventRecord(c->ev[3], c->stream));
+    c->ss.phase = next_phase;
+    return MSF_OK;
+}
+
+msf_status solve_start(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
+                       msf_wtype wt, int32_t *d_ids)
+{
+    SolveState &S = c->ss;
+    S = SolveState{};
+    S.n = n;
+    S.m = m;
+    S.edges = d_edges;
+    S.w = d_w;
+    S.wt = wt;
+    S.ids = d_ids;
+    MSF_TRY(get_solve_bufs(c, n, m, &S.b));
+    MSF_HIP(hipEventRecord(c->ev[0], c->stream));
+    zero_counters(c);
+    MSF_TRY(build_adjacency(c, n, m, d_edges, d_w, wt, &S.a, S.b.rp[0], S.b.col[0], S.b.key[0],
+                            S.b.crow[0]));
+    return end_step(c, 1);
+}
+
+bool solve_ready(Ctx *c) { return hipEventQuery(c->ev[3]) == hipSuccess; }
+
+bool solve_done(const Ctx *c) { return c->ss.phase == 5; }
+
+// Enqueue one round: sweep (+ filtering), hook, tie break.
+static msf_status enqueue_round(Ctx *c)
+{
+    SolveState &S = c->ss;
+    hipStream_t s = c->stream;
+    S.compact = false;
+    if (c->filter_mode == 2) S.compact = true;
+    else if (c->filter_mode == 1) S.compact = S.live_frac < c->filter_threshold;
+    const int ev_k = S.rounds < 64 ? S.rounds : -1;
+    if (ev_k >= 0) {
+        MSF_HIP(hipEventRecord(c->sev[2 * ev_k], s));
+        S.st.sweep_bytes[ev_k] = 12.0 * S.a.nnz + 8.0 * S.rows + 8.0 * S.nR;
+    }
+    if (S.compact) {
+        MSF_TRY(get_filter_bufs(c, S.n, S.m, &S.b));
+        Adj nxt = S.a;
+        nxt.row_ptr = S.b.rp[S.ai ^ 1];
+        nxt.col = S.b.col[S.ai ^ 1];
+        nxt.key = S.b.key[S.ai ^ 1];
+        launch_sweep_compact(s, S.a, S.b.p, S.b.r, nxt.row_ptr, nxt.col, nxt.key, S.b.status,
+                             c->dcnt);
+    } else {
+        // round 1: p is the identity and nothing has been filtered
+        launch_sweep(s, S.a, S.b.p, S.b.r, S.b.blive, c->dcnt,
+                     S.rounds == 0 && c->first_round_kernel);
+    }
+    if (ev_k >= 0) MSF_HIP(hipEventRecord(c->sev[2 * ev_k + 1], s));
+    launch_hook(s, S.b.R[S.ri], S.nR, S.b.r, S.b.p, S.edges, S.b.h, S.b.hedge);
+    launch_fill_u32(s, &c->dcnt->nR, 0u, 3);  // nR, nF, hooks
+    launch_tiebreak(s, S.b.R[S.ri], S.nR, S.b.h, S.b.hedge, S.b.flags, S.b.R[S.ri ^ 1], S.b.F,
+                    S.b.status, c->dcnt);
+    return end_step(c, 3);
+}
+
+static msf_status enqueue_output(Ctx *c)
+{
+    SolveState &S = c->ss;
+    S.st.rounds = S.rounds;
+    launch_output(c->stream, S.b.flags, S.m, S.w, S.wt, S.ids, S.b.status, S.b.part, c->dcnt);
+    MSF_HIP(hipEventRecord(c->ev[2], c->stream));
+    return end_step(c, 4);
+}
+
+static bool more_rounds(const SolveState &S)
+{
+    // fewer than two live roots: no outgoing edge can remain
+    return S.nR >= 2 && S.a.nnz > 0 && S.rounds < 1000;
+}
+
+msf_status solve_advance(Ctx *c)
+{
+    SolveState &S = c->ss;
+    hipStream_t s = c->stream;
+    const Counters *h = c->hcnt;
+    switch (S.phase) {
+    case 1: {  // adjacency built
+        MSF_TRY(decode_err(h->err));
+        S.a.nnz = h->count;
+        S.a.nchunks = sweep_nchunks(S.a.nnz);
+        launch_chunk_rows(s, S.a.row_ptr, S.n, S.a.nnz, S.a.chunk_row, S.a.nchunks);
+        MSF_HIP(hipEventRecord(c->ev[1], s));
+        launch_iota_u32(s, S.b.p, (size_t)S.n);
+        launch_iota_u32(s, S.b.h, (size_t)S.n);
+        launch_fill_u64(s, S.b.r, KEY_INF, (size_t)S.n);
+        launch_fill_u32(s, reinterpret_cast<uint32_t *>(S.b.flags), 0u, ((size_t)S.m + 3) / 4);
+        launch_init_roots(s, S.a.row_ptr, S.n, S.b.R[0], S.b.status, c->dcnt);
+        return end_step(c, 2);
+    }
+    case 2: {  // root list ready
+        S.nR = h->nR;
+        S.rows = S.nR;  // rows with entries: every non-isolated vertex
+        return more_rounds(S) ? enqueue_round(c) : enqueue_output(c);
+    }
+    case 3: {  // round counters ready
+        const uint32_t nF = h->nF, nRn = h->nR;
+        const int k = S.rounds;
+        if (S.rows_pending && k < 64) {
+            S.st.sweep_bytes[k] += 8.0 * h->rows;  // rows of the swept adjacency
+            S.rows_pending = false;
+        }
+        if (k < 64) {
+            S.st.hooks[k] = nF;
+            S.st.active_nnz[k] = S.a.nnz;
+        }
+        ++S.rounds;
+        if (nF) ++S.st.hook_rounds;
+        if (S.compact) {
+            const uint32_t nnz2 = h->nnz_out;
+            S.live_frac = S.a.nnz ? (double)nnz2 / (double)S.a.nnz : 0.0;
+            Adj nxt = S.a;
+            nxt.row_ptr = S.b.rp[S.ai ^ 1];
+            nxt.col = S.b.col[S.ai ^ 1];
+            nxt.key = S.b.key[S.ai ^ 1];
+            nxt.chunk_row = S.b.crow[S.ai ^ 1];
+            nxt.nnz = nnz2;
+            nxt.nchunks = sweep_nchunks(nnz2);
+            if (nnz2) launch_chunk_rows(s, nxt.row_ptr, S.n, nnz2, nxt.chunk_row, nxt.nchunks);
+            S.a = nxt;
+            S.ai ^= 1;
+            ++S.st.filtered;
+        } else {
+            S.live_frac = S.a.nnz ? (double)h->live / (double)S.a.nnz : 0.0;
+        }
+        if (nF == 0) return enqueue_output(c);
+        launch_chase(s, S.b.F, nF, S.b.h, (uint32_t *)S.b.part, c->dcnt);
+        if (c->check_rounds) {
+            MSF_TRY(read_counters(c));
+            if (c->hcnt->err) {
+                set_error("internal error: hook cycle in round %d", S.rounds);
+                return MSF_EDEVICE;
+            }
+        }
+        launch_update_parents(s, S.a.row_ptr, S.n, S.b.p, S.b.h, (uint32_t *)S.b.part, c->dcnt);
+        S.ri ^= 1;
+        S.nR = nRn;
+        S.rows = 0;  // counted by the update, read back with the next round
+        S.rows_pending = true;
+        return more_rounds(S) ? enqueue_round(c) : enqueue_output(c);
+    }
+    case 4: {  // output ready
+        if (h->err) {
+            set_error("internal error: hook cycle detected");
+            return MSF_EDEVICE;
+        }
+        float ms_build = 0.f, ms_rounds = 0.f;
+        (void)hipEventElapsedTime(&ms_build, c->ev[0], c->ev[1]);
+        (void)hipEventElapsedTime(&ms_rounds, c->ev[1], c->ev[2]);
+        S.st.build_ms = ms_build;
+        S.st.rounds_ms = ms_rounds;
+        for (int k = 0; k < S.rounds && k < 64; ++k) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, c->sev[2 * k], c->sev[2 * k + 1]);
+            S.st.sweep_ms[k] = ms;
+        }
+        S.st.max_chase = (int32_t)h->max_chase;
+        c->stats = S.st;
+        S.phase = 5;
+        return MSF_OK;
+    }
+    default:
+        set_error("solve_advance in phase %d", S.phase);
+        return MSF_EINVAL;
+    }
+}
+
+void solve_result(const Ctx *c, int64_t *count, msf_total *total)
+{
+    const SolveState &S = c->ss;
+    const Counters *h = c->hcnt;
+    *count = (S.m > 0) ? (int64_t)h->count : 0;
+    if (total) {
+        total->u64 = (S.wt == MSF_W_U32) ? h->total_u64 : 0;
+        total->f64 = (S.m > 0) ? h->total_f64 : 0.0;
+    }
+}
+
+msf_status solve_device(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
+                        msf_wtype wt, int32_t *d_ids, int64_t *count, msf_total *total)
+{
+    MSF_TRY(solve_start(c, n, m, d_edges, d_w, wt, d_ids));
+    while (!solve_done(c)) {
+        MSF_HIP(hipEventSynchronize(c->ev[3]));
+        MSF_TRY(solve_advance(c));
+    }
+    solve_result(c, count, total);
+    return MSF_OK;
+}
+
+}  // namespace msf
