@@ -14,11 +14,14 @@ Also reported on the same JSON line:
                 library records on the stream the sweeps run on;
   cpu_baseline  the CPU oracle (sort + union-find, one thread) on the same
                 graph, timed on this host;
-  batched       (--extras) 10^4 uneven Erdos-Renyi graphs in one batched
-                solve vs one msf_solve per graph;
-  served        (--extras) continuous-batching server latency percentiles.
+  batched       10^4 uneven Erdos-Renyi graphs (n log-uniform in [64, 65536),
+                average degree 8) in one batched solve vs one msf_solve per
+                graph;
+  served        continuous-batching server: p50/p99 latency and graphs/s of
+                a Poisson stream of mixed graphs at several rates, vs a plain
+                one-at-a-time FIFO.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extras]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
 """
 from __future__ import annotations
 
@@ -120,13 +123,92 @@ def bench_batched(ctx, pkg, torch, G=10000):
             "speedup": (G / tb) * tp}
 
 
+def bench_served(ctx, pkg, torch, requests_per_rate=200, rates=(0.25, 0.5, 1.0, 2.0, 4.0),
+                 budget=32 << 30, seed=5):
+    """Poisson request stream over a pool of mixed graphs (half R-MAT with
+    edge factor 16, half cubic grids with 5% of edges dropped, n log-uniform
+    in [2^10, 2^22], float32 weights).  The rate is a multiple of the plain
+    sequential throughput mu (one msf_solve per request, host arrays in and
+    out, timed here); the plain FIFO's latencies under the same arrivals are
+    computed from those measured per-graph service times."""
+    import numpy as np
+    import gen
+
+    t = time.perf_counter()
+    pool = gen.serve_pool(64, seed=seed)
+    log(f"served pool generated in {time.perf_counter() - t:.1f}s "
+        f"({sum(len(p[1]) for p in pool)} edges)")
+    # plain sequential service time per pool graph
+    svc = []
+    for n, e, w, kind in pool:
+        ctx.solve(n, e, w, wtype=pkg.W_F32)  # warm the workspace
+    for n, e, w, kind in pool:
+        t = time.perf_counter()
+        ctx.solve(n, e, w, wtype=pkg.W_F32)
+        svc.append(time.perf_counter() - t)
+    svc = np.array(svc)
+    mu = 1.0 / svc.mean()
+    rng = np.random.default_rng(seed)
+    out = {"pool_graphs": len(pool), "requests_per_rate": requests_per_rate,
+           "budget_bytes": budget, "plain_graphs_per_s": mu, "rates": []}
+    srv = pkg.Server(ctx, budget)
+    # warm the server's slots
+    warm = [srv.submit(*pool[i][:3], wtype=pkg.W_F32) for i in range(8)]
+    for i, tk in enumerate(warm):
+        srv.result(tk, pool[i][0])
+    for mult in rates:
+        lam = mult * mu
+        gaps = rng.exponential(1.0 / lam, requests_per_rate)
+        arrivals = np.cumsum(gaps)
+        picks = rng.integers(0, len(pool), requests_per_rate)
+        tickets = []
+        t0 = time.perf_counter()
+        for a, g in zip(arrivals, picks):
+            now = time.perf_counter() - t0
+            if a > now:
+                time.sleep(a - now)
+            n, e, w, kind = pool[g]
+            tickets.append((srv.submit(n, e, w, wtype=pkg.W_F32), n))
+        # results and latencies
+        lat = []
+        for tk, n in tickets:
+            while not srv.poll(tk):
+                time.sleep(0.0005)
+            lat.append(srv.latency(tk))
+            srv.result(tk, n)
+        t_end = time.perf_counter() - t0
+        lat = np.array(lat)
+        # plain FIFO under the same arrivals with the measured service times
+        fin = 0.0
+        fifo = []
+        for a, g in zip(arrivals, picks):
+            fin = max(fin, a) + svc[g]
+            fifo.append(fin - a)
+        fifo = np.array(fifo)
+        out["rates"].append({
+            "rate_x_plain": mult, "arrival_per_s": lam,
+            "served_p50_ms": 1e3 * float(np.percentile(lat, 50)),
+            "served_p99_ms": 1e3 * float(np.percentile(lat, 99)),
+            "served_graphs_per_s": requests_per_rate / t_end,
+            "fifo_p50_ms": 1e3 * float(np.percentile(fifo, 50)),
+            "fifo_p99_ms": 1e3 * float(np.percentile(fifo, 99)),
+            "fifo_graphs_per_s": requests_per_rate / max(fin, arrivals[-1]),
+        })
+        log(f"served x{mult}: {out['rates'][-1]}")
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--extras", action="store_true", help="also run batched and served")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched (10^4 graphs) and served (Poisson stream) legs")
+    ap.add_argument("--served-requests", type=int, default=200,
+                    help="requests per arrival rate in the served leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -182,9 +264,15 @@ def main():
                                 "seconds": cb["seconds"]}
         line["parity"] = (cb["count"] == r["count"] and cb["total"][1] == r["total"][1]
                           and cb["ids_sum"] == r["ids_sum"])
-    if args.extras:
+    if not args.no_extras:
         log("batched: 10^4 Erdos-Renyi graphs")
         line["batched"] = bench_batched(ctx, pkg, torch)
+        log("served: Poisson stream of mixed graphs")
+        sv = bench_served(ctx, pkg, torch, args.served_requests)
+        line["served"] = sv
+        at1 = [r for r in sv["rates"] if r["rate_x_plain"] == 1.0]
+        if at1:
+            line["served_p99_ms_at_plain_rate"] = at1[0]["served_p99_ms"]
     print(json.dumps(line), flush=True)
 
 

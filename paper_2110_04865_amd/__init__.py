@@ -154,9 +154,9 @@ class Context:
         self.device = device
 
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
-            lib().msf_ctx_destroy(self._h)
-            self._h = None
+        if getattr(self, "_h", None) is not None and self._h.value and _lib is not None:
+            _lib.msf_ctx_destroy(self._h)
+        self._h = None
 
     __del__ = close
 
@@ -289,9 +289,9 @@ class Graph:
         self.ctx = ctx
 
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
-            lib().msf_graph_destroy(self._h)
-            self._h = None
+        if getattr(self, "_h", None) is not None and self._h.value and _lib is not None:
+            _lib.msf_graph_destroy(self._h)
+        self._h = None
 
     __del__ = close
 
@@ -306,9 +306,9 @@ class Server:
         self.ctx = ctx
 
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
-            lib().msf_server_destroy(self._h)
-            self._h = None
+        if getattr(self, "_h", None) is not None and self._h.value and _lib is not None:
+            _lib.msf_server_destroy(self._h)
+        self._h = None
 
     __del__ = close
 

@@ -228,14 +228,15 @@ void launch_chunk_rows(hipStream_t s, const uint32_t *row_ptr, int32_t n, uint32
 // Every atomic is an LDS atomic, so a vertex of very high degree costs LDS
 // conflicts inside one workgroup instead of serialised device atomics.
 
-constexpr int BK_MAX_NB = 4096;
+constexpr int BK_MAX_NB = 16384;  // pass A/B keep one LDS counter per bucket
 constexpr int BKA_NT = 256;
 constexpr int BKC_NT = 1024;
+constexpr int BK_MIN_LB = 12;  // fewer, larger buckets keep pass B's writes in long runs
 constexpr int BK_MAX_LB = 15;  // pass C keeps 2^LB row counters in LDS
 
 static int bucket_bits(int32_t n)
 {
-    int lb = 8;
+    int lb = BK_MIN_LB;
     while ((((int64_t)n + (1ll << lb) - 1) >> lb) > BK_MAX_NB) ++lb;
     return lb;
 }

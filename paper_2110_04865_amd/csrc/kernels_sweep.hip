@@ -62,8 +62,9 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
     const uint64_t *__restrict__ key, const uint32_t *__restrict__ chunk_row, uint32_t nnz,
     uint32_t nchunks, int32_t n, const uint32_t *__restrict__ p, uint64_t *__restrict__ r,
-    uint32_t *__restrict__ row_ptr_out, uint32_t *__restrict__ col_out,
-    uint64_t *__restrict__ key_out, uint64_t *status, Counters *cnt, uint32_t *block_live)
+    uint32_t *__restrict__ chunk_wpre, uint32_t *__restrict__ chunk_mask,
+    uint32_t *__restrict__ col_out, uint64_t *__restrict__ key_out, uint64_t *status,
+    Counters *cnt, uint32_t *block_live)
 {
     constexpr int E = SWEEP_E;
     __shared__ uint32_t s_chunk;
@@ -245,31 +246,48 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     __syncthreads();
     const uint64_t P = s_prefix;
     uint32_t pos = (uint32_t)P + lex;
+    // survivor bitmask and per-32-entry prefix of this chunk: the output
+    // row pointers are derived from them by k_rowptr_compact
+    uint32_t nib = 0;
+#pragma unroll
+    for (int k = 0; k < E; ++k) nib |= (live[k] ? 1u : 0u) << k;
+    uint32_t word = nib << ((lane & 7u) * 4u);
+    word |= __shfl_xor(word, 1, 64);
+    word |= __shfl_xor(word, 2, 64);
+    word |= __shfl_xor(word, 4, 64);
+    if ((lane & 7u) == 0) {
+        const size_t wi = (size_t)c * (SWEEP_CHUNK / 32) + (threadIdx.x >> 3);
+        chunk_mask[wi] = word;
+        chunk_wpre[wi] = pos;
+    }
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-        if (k < nvalid) {
-            const uint32_t idx = base + k;
-            const uint32_t row = rowk[k];
-            if (rp_at(row) == idx) {
-                // first entry of `row` (and of any empty rows just before it)
-                row_ptr_out[row] = pos;
-                for (int64_t j = (int64_t)row - 1; j >= 0 && row_ptr[j] == idx; --j)
-                    row_ptr_out[j] = pos;
-            }
-            if (live[k]) {
-                col_out[pos] = cl[k];
-                key_out[pos] = ky[k];
-                ++pos;
-            }
+        if (k < nvalid && live[k]) {
+            col_out[pos] = cl[k];
+            key_out[pos] = ky[k];
+            ++pos;
         }
     }
-    if (c == nchunks - 1) {
-        // rows starting at nnz (trailing empty rows and row_ptr[n])
-        const uint32_t total = (uint32_t)(P + btot);
-        const uint32_t last_row = chunk_row[nchunks];
-        for (int64_t j = (int64_t)last_row + 1 + threadIdx.x; j <= n; j += SWEEP_BLOCK)
-            row_ptr_out[j] = total;
-        if (threadIdx.x == 0) cnt->nnz_out = total;
+    if (c == nchunks - 1 && threadIdx.x == 0) cnt->nnz_out = (uint32_t)(P + btot);
+}
+
+// Output row pointers of a compaction: row_ptr_out[i] = survivors stored
+// before old position row_ptr[i] (all survivors when that position is nnz).
+__global__ void k_rowptr_compact(const uint32_t *__restrict__ row_ptr, int32_t n, uint32_t nnz,
+                                 const uint32_t *__restrict__ chunk_wpre,
+                                 const uint32_t *__restrict__ chunk_mask, const Counters *cnt,
+                                 uint32_t *__restrict__ row_ptr_out)
+{
+    const uint32_t total = cnt->nnz_out;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += stride) {
+        const uint32_t x = row_ptr[i];
+        uint32_t v = total;
+        if (x < nnz) {
+            const uint32_t w = x >> 5;
+            v = chunk_wpre[w] + __popc(chunk_mask[w] & ((1u << (x & 31u)) - 1u));
+        }
+        row_ptr_out[i] = v;
     }
 }
 
@@ -291,11 +309,11 @@ void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
     if (first)
         k_sweep<false, true><<<a.nchunks, SWEEP_BLOCK, 0, s>>>(
             a.row_ptr, a.col, a.key, a.chunk_row, a.nnz, a.nchunks, a.n, p, r, nullptr, nullptr,
-            nullptr, nullptr, nullptr, block_live);
+            nullptr, nullptr, nullptr, nullptr, block_live);
     else
         k_sweep<false, false><<<a.nchunks, SWEEP_BLOCK, 0, s>>>(
             a.row_ptr, a.col, a.key, a.chunk_row, a.nnz, a.nchunks, a.n, p, r, nullptr, nullptr,
-            nullptr, nullptr, nullptr, block_live);
+            nullptr, nullptr, nullptr, nullptr, block_live);
     if (block_live && dcnt) {
         launch_fill_u64(s, &dcnt->live, 0ull, 1);
         unsigned g = (a.nchunks + 255) / 256;
@@ -306,14 +324,22 @@ void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
 
 void launch_sweep_compact(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
                           uint32_t *row_ptr_out, uint32_t *col_out, uint64_t *key_out,
-                          uint64_t *status, Counters *dcnt)
+                          uint32_t *chunk_info, uint64_t *status, Counters *dcnt)
 {
     if (a.nnz == 0) return;
+    uint32_t *wpre = chunk_info;
+    uint32_t *mask = chunk_info + (size_t)a.nchunks * (SWEEP_CHUNK / 32);
     launch_fill_u64(s, status, 0ull, a.nchunks);
     launch_fill_u32(s, &dcnt->ticket, 0u, 1);
-    k_sweep<true, false><<<a.nchunks, SWEEP_BLOCK, 0, s>>>(a.row_ptr, a.col, a.key, a.chunk_row, a.nnz,
-                                                    a.nchunks, a.n, p, r, row_ptr_out, col_out,
-                                                    key_out, status, dcnt, nullptr);
+    k_sweep<true, false><<<a.nchunks, SWEEP_BLOCK, 0, s>>>(
+        a.row_ptr, a.col, a.key, a.chunk_row, a.nnz, a.nchunks, a.n, p, r, wpre, mask, col_out,
+        key_out, status, dcnt, nullptr);
+    size_t g = ((size_t)a.n + 1 + 255) / 256;
+    if (g > 8192) g = 8192;
+    k_rowptr_compact<<<(unsigned)g, 256, 0, s>>>(a.row_ptr, a.n, a.nnz, wpre, mask, dcnt,
+                                                 row_ptr_out);
 }
+
+size_t chunk_info_words(uint32_t nchunks) { return 2 * (size_t)nchunks * (SWEEP_CHUNK / 32); }
 
 }  // namespace msf

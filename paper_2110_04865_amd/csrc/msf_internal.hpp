@@ -83,7 +83,7 @@ enum Slot {
     WS_P, WS_R, WS_H, WS_HEDGE, WS_RL, WS_RL2, WS_FL, WS_FLAGS, WS_IDS,
     WS_STATUS, WS_SCRATCH, WS_PART, WS_Q, WS_Q2,
     WS_BATCH0, WS_BATCH1, WS_BATCH2, WS_BATCH3,
-    WS_BH, WS_BHOFF, WS_BRLO, WS_BCOL, WS_BKEY,
+    WS_BH, WS_BHOFF, WS_BRLO, WS_BCOL, WS_BKEY, WS_CHUNKINFO,
     WS_COUNT
 };
 
@@ -108,7 +108,7 @@ struct Counters {
 };
 
 struct SolveBufs {
-    uint32_t *rp[2], *col[2], *crow[2], *p, *h, *hedge, *R[2], *F, *blive;
+    uint32_t *rp[2], *col[2], *crow[2], *p, *h, *hedge, *R[2], *F, *blive, *cinfo;
     uint64_t *key[2], *r, *status;
     uint8_t *flags;
     void *part;
@@ -208,9 +208,13 @@ void launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, size_t n);
 void launch_iota_u32(hipStream_t s, uint32_t *p, size_t n);
 void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
                   uint32_t *block_live = nullptr, Counters *dcnt = nullptr, bool first = false);
+// Sweep that also writes the surviving entries (p_i != p_j) in order to
+// col_out/key_out and their row pointers to row_ptr_out; chunk_info holds
+// chunk_info_words(a.nchunks) u32 of per-chunk survivor masks and prefixes.
 void launch_sweep_compact(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
                           uint32_t *row_ptr_out, uint32_t *col_out, uint64_t *key_out,
-                          uint64_t *status, Counters *dcnt);
+                          uint32_t *chunk_info, uint64_t *status, Counters *dcnt);
+size_t chunk_info_words(uint32_t nchunks);
 
 // Round kernels.  `status` is a look-back status array (>= tiles entries);
 // `part` holds per-block partials (>= 4096 u32, or output_part_bytes(m)).

@@ -1,8 +1,9 @@
 // Serving loop: continuous batching of minimum-spanning-forest requests
 // under a device-memory budget.
 //
-// submit() copies a request into host memory and queues it; a worker thread
-// owns the device work:
+// submit() copies a request into a pinned host staging buffer (reused from a
+// pool, so the copy touches no fresh pages and the upload is a true
+// asynchronous DMA) and queues it; a worker thread owns the device work:
 //   - admission: waiting requests are admitted in arrival order while their
 //     footprint (msf_request_footprint) fits in the budget left by the
 //     requests in flight; an admitted request gets a slot: its own stream,
@@ -13,9 +14,11 @@
 //     with complete shortcutting, or the build/output stage), so rounds of
 //     all requests in flight overlap on the device, and a request that
 //     arrives mid-flight joins at the next pass;
-//   - retirement: a finished slot's forest is copied out, its latency is
-//     stamped (host steady clock, submit to ready), its workspace is freed
-//     on its stream, and its budget is returned to waiting requests.
+//   - retirement: a finished slot's forest is copied back into the
+//     request's staging buffer (asynchronously, polled like any step), its
+//     latency is stamped (host steady clock, submit to ready), its workspace
+//     is freed on its stream, and its budget is returned to waiting
+//     requests.
 // A failing request completes with its error status and never affects the
 // others.  Each request's result is bit-identical to msf_solve on it alone:
 // every slot runs the same deterministic solve on its own state.
@@ -24,6 +27,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -39,19 +43,79 @@ namespace {
 
 using clk = std::chrono::steady_clock;
 
+// Pinned host buffers, reused across requests (pinning is slow, reuse is
+// free).  A request's buffer holds its edges then its weights (12 bytes per
+// edge) and later its forest ids (at most one per edge).
+struct StagePool {
+    std::mutex mu;
+    std::multimap<size_t, void *> idle;  // capacity -> buffer
+    void *get(size_t bytes, size_t *cap)
+    {
+        if (bytes < 4096) bytes = 4096;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto it = idle.lower_bound(bytes);
+            if (it != idle.end() && it->first <= 4 * bytes) {
+                void *p = it->second;
+                *cap = it->first;
+                idle.erase(it);
+                return p;
+            }
+        }
+        size_t c = (bytes + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
+        void *p = nullptr;
+        if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        *cap = c;
+        return p;
+    }
+    void put(void *p, size_t cap)
+    {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(mu);
+        idle.emplace(cap, p);
+    }
+    ~StagePool()
+    {
+        for (auto &kv : idle) (void)hipHostFree(kv.second);
+    }
+};
+
+// memcpy split over a few threads for large requests.
+void copy_in(void *dst, const void *src, size_t bytes)
+{
+    const size_t piece = (size_t)16 << 20;
+    if (bytes <= 2 * piece) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    size_t nt = bytes / piece;
+    if (nt > 8) nt = 8;
+    const size_t chunk = (bytes + nt - 1) / nt;
+    std::vector<std::thread> th;
+    for (size_t t = 1; t < nt; ++t) {
+        const size_t lo = t * chunk, hi = lo + chunk < bytes ? lo + chunk : bytes;
+        if (lo >= hi) break;
+        th.emplace_back([=] { std::memcpy((char *)dst + lo, (const char *)src + lo, hi - lo); });
+    }
+    std::memcpy(dst, src, chunk < bytes ? chunk : bytes);
+    for (auto &x : th) x.join();
+}
+
 struct Request {
     uint64_t ticket = 0;
     int32_t n = 0;
     int64_t m = 0;
     msf_wtype wt = MSF_W_U32;
-    std::vector<int32_t> edges;
-    std::vector<uint32_t> w;  // raw 32-bit weights
+    void *stage = nullptr;  // pinned: edges, weights; then forest ids
+    size_t stage_cap = 0;
     size_t footprint = 0;
     clk::time_point t_submit, t_done;
     bool done = false;
     msf_status status = MSF_OK;
     std::string err;
-    std::vector<int32_t> ids;
     int64_t count = 0;
     msf_total total{0, 0.0};
 };
@@ -60,6 +124,7 @@ struct ReqSlot {
     Ctx ctx;
     Request *req = nullptr;
     int32_t *d_ids = nullptr;
+    bool downloading = false;
 };
 
 }  // namespace
@@ -79,6 +144,7 @@ struct msf_server {
     std::thread worker;
     std::atomic<bool> stop{false};
     uint64_t next_ticket = 1;
+    StagePool stage;
 };
 
 namespace {
@@ -90,10 +156,6 @@ void finish(msf_server *s, Request *r, msf_status st, const char *msg)
     if (msg) r->err = msg;
     r->t_done = clk::now();
     r->done = true;
-    r->edges.clear();
-    r->edges.shrink_to_fit();
-    r->w.clear();
-    r->w.shrink_to_fit();
     s->used -= r->footprint;
     s->cv_done.notify_all();
 }
@@ -127,6 +189,7 @@ void retire_slot(msf_server *s, ReqSlot *sl)
     ctx_release_workspace(&sl->ctx);  // stream-ordered frees
     sl->req = nullptr;
     sl->d_ids = nullptr;
+    sl->downloading = false;
     s->pool.push_back(sl);
 }
 
@@ -146,9 +209,10 @@ bool admit(msf_server *s, Request *r)
     if (!rc) rc = ws_get(c, msf::WS_W, 4 * mm, &vw);
     if (!rc) rc = ws_get(c, msf::WS_IDS, 4 * nn, &vi);
     if (!rc && r->m > 0) {
-        if (hipMemcpyAsync(ve, r->edges.data(), 8 * (size_t)r->m, hipMemcpyHostToDevice,
-                           c->stream) != hipSuccess ||
-            hipMemcpyAsync(vw, r->w.data(), 4 * (size_t)r->m, hipMemcpyHostToDevice,
+        const char *st = (const char *)r->stage;
+        if (hipMemcpyAsync(ve, st, 8 * (size_t)r->m, hipMemcpyHostToDevice, c->stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(vw, st + 8 * (size_t)r->m, 4 * (size_t)r->m, hipMemcpyHostToDevice,
                            c->stream) != hipSuccess) {
             (void)hipGetLastError();
             rc = MSF_EDEVICE;
@@ -172,6 +236,11 @@ bool step_slot(msf_server *s, ReqSlot *sl)
 {
     Ctx *c = &sl->ctx;
     Request *r = sl->req;
+    if (sl->downloading) {  // forest ids are in the staging buffer
+        finish(s, r, MSF_OK, nullptr);
+        retire_slot(s, sl);
+        return true;
+    }
     msf_status rc = solve_advance(c);
     if (rc) {
         finish(s, r, rc, msf_last_error());
@@ -183,21 +252,25 @@ bool step_slot(msf_server *s, ReqSlot *sl)
     int64_t cnt = 0;
     msf_total tot{0, 0.0};
     solve_result(c, &cnt, &tot);
-    r->ids.resize((size_t)(cnt > 0 ? cnt : 0));
+    r->count = cnt;
+    r->total = tot;
     if (cnt > 0 &&
-        (hipMemcpyAsync(r->ids.data(), sl->d_ids, 4 * (size_t)cnt, hipMemcpyDeviceToHost,
+        (hipMemcpyAsync(r->stage, sl->d_ids, 4 * (size_t)cnt, hipMemcpyDeviceToHost,
                         c->stream) != hipSuccess ||
-         hipStreamSynchronize(c->stream) != hipSuccess)) {
+         hipEventRecord(c->ev[3], c->stream) != hipSuccess)) {
         (void)hipGetLastError();
         finish(s, r, MSF_EDEVICE, "result download failed");
+        (void)hipStreamSynchronize(c->stream);
         retire_slot(s, sl);
         return true;
     }
-    r->count = cnt;
-    r->total = tot;
-    finish(s, r, MSF_OK, nullptr);
-    retire_slot(s, sl);
-    return true;
+    if (cnt == 0) {
+        finish(s, r, MSF_OK, nullptr);
+        retire_slot(s, sl);
+        return true;
+    }
+    sl->downloading = true;
+    return false;
 }
 
 void worker_main(msf_server *s)
@@ -306,7 +379,10 @@ void msf_server_destroy(msf_server *s)
         s->cv_work.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
-    for (auto &kv : s->tickets) delete kv.second;
+    for (auto &kv : s->tickets) {
+        s->stage.put(kv.second->stage, kv.second->stage_cap);
+        delete kv.second;
+    }
     delete s;
 }
 
@@ -332,19 +408,21 @@ msf_status msf_server_submit(msf_server *s, int32_t n, int64_t m, const int32_t 
     r->m = m;
     r->wt = wt;
     r->footprint = fp;
-    try {
-        r->edges.assign(edges, edges + 2 * (size_t)m);
-        r->w.resize((size_t)m);
-    } catch (...) {
+    r->t_submit = clk::now();
+    r->stage = s->stage.get(12 * (size_t)m, &r->stage_cap);
+    if (!r->stage) {
         delete r;
-        set_error("host allocation failed");
+        set_error("pinned host allocation failed");
         return MSF_ENOMEM;
     }
-    if (m > 0) std::memcpy(r->w.data(), weights, 4 * (size_t)m);
-    r->t_submit = clk::now();
+    if (m > 0) {
+        copy_in(r->stage, edges, 8 * (size_t)m);
+        copy_in((char *)r->stage + 8 * (size_t)m, weights, 4 * (size_t)m);
+    }
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) {
+            s->stage.put(r->stage, r->stage_cap);
             delete r;
             set_error("server is stopping");
             return MSF_EINVAL;
@@ -419,13 +497,14 @@ msf_status msf_server_result(msf_server *s, uint64_t ticket, int32_t *forest_ids
             st = MSF_EINVAL;
             set_error("NULL forest_ids");
         } else {
-            if (r->count > 0) std::memcpy(forest_ids, r->ids.data(), 4 * (size_t)r->count);
+            if (r->count > 0) copy_in(forest_ids, r->stage, 4 * (size_t)r->count);
             *forest_count = r->count;
             if (total) *total = r->total;
         }
     } else {
         set_error("%s", r->err.c_str());
     }
+    s->stage.put(r->stage, r->stage_cap);
     delete r;
     return st;
 }

@@ -68,11 +68,13 @@ static msf_status get_filter_bufs(Ctx *c, int32_t n, int64_t m, SolveBufs *b)
     const size_t nn = (size_t)std::max(n, 1), mm = (size_t)std::max<int64_t>(m, 1);
     const size_t nnz_cap = 2 * mm;
     const size_t nch = sweep_nchunks((uint32_t)std::min<size_t>(nnz_cap, 0xFFFFFFFFull)) + 2;
-    void *v[4];
+    void *v[5];
     MSF_TRY(ws_get(c, WS_ROWPTR2, 4 * (nn + 1), &v[0]));
     MSF_TRY(ws_get(c, WS_COL2, 4 * nnz_cap, &v[1]));
     MSF_TRY(ws_get(c, WS_KEY2, 8 * nnz_cap, &v[2]));
     MSF_TRY(ws_get(c, WS_CHUNKROW2, 4 * nch, &v[3]));
+    MSF_TRY(ws_get(c, WS_CHUNKINFO, 4 * chunk_info_words((uint32_t)nch), &v[4]));
+    b->cinfo = (uint32_t *)v[4];
     b->rp[1] = (uint32_t *)v[0];
     b->col[1] = (uint32_t *)v[1];
     b->key[1] = (uint64_t *)v[2];
@@ -132,8 +134,8 @@ static msf_status enqueue_round(Ctx *c)
         nxt.row_ptr = S.b.rp[S.ai ^ 1];
         nxt.col = S.b.col[S.ai ^ 1];
         nxt.key = S.b.key[S.ai ^ 1];
-        launch_sweep_compact(s, S.a, S.b.p, S.b.r, nxt.row_ptr, nxt.col, nxt.key, S.b.status,
-                             c->dcnt);
+        launch_sweep_compact(s, S.a, S.b.p, S.b.r, nxt.row_ptr, nxt.col, nxt.key, S.b.cinfo,
+                             S.b.status, c->dcnt);
     } else {
         // round 1: p is the identity and nothing has been filtered
         launch_sweep(s, S.a, S.b.p, S.b.r, S.b.blive, c->dcnt,
