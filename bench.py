@@ -209,6 +209,9 @@ def main():
                     help="skip the batched (10^4 graphs) and served (Poisson stream) legs")
     ap.add_argument("--served-requests", type=int, default=200,
                     help="requests per arrival rate in the served leg")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB (a reference kernel "
+                         "of known traffic for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -224,6 +227,14 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+        del src, dst
     ctx = pkg.Context(0)
     r = bench_rmat(ctx, pkg, torch, args.steps, args.warmup)
     m = r["m"]
