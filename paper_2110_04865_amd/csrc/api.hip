@@ -137,6 +137,7 @@ msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc)
     if (const char *f = getenv("MSF_CHECK_ROUNDS")) c->check_rounds = atoi(f) != 0;
     if (const char *f = getenv("MSF_FIRST_ROUND")) c->first_round_kernel = atoi(f) != 0;
     if (const char *f = getenv("MSF_BUCKETED_BUILD")) c->bucketed_build = atoi(f) != 0;
+    if (const char *f = getenv("MSF_SLICES")) c->slices = atoi(f);
     return MSF_OK;
 }
 
@@ -305,8 +306,11 @@ msf_status msf_graph_create(msf_ctx *ctx, int32_t n, int64_t m, const int32_t *e
     }
     g->ctx = ctx;
     const size_t nn = (size_t)std::max(n, 1), mm = (size_t)std::max<int64_t>(m, 1);
-    const size_t nch = sweep_nchunks((uint32_t)std::min<size_t>(2 * mm, 0xFFFFFFFFull)) + 2;
-    const size_t sizes[6] = {8 * mm, 4 * mm, 4 * (nn + 1), 4 * 2 * mm, 8 * 2 * mm, 4 * nch};
+    const size_t nch =
+        sweep_nchunks((uint32_t)std::min<size_t>(2 * mm, 0xFFFFFFFFull)) + 2 * MAX_SLICES + 2;
+    const int slices = choose_slices(n, c->slices);
+    const size_t sizes[6] = {8 * mm, 4 * mm, 4 * (size_t)slices * (nn + 1), 4 * 2 * mm,
+                             8 * 2 * mm, 4 * nch};
     for (int i = 0; i < 6; ++i) {
         if (hipMalloc(&g->bufs[i], sizes[i]) != hipSuccess) {
             (void)hipGetLastError();
@@ -325,7 +329,7 @@ msf_status msf_graph_create(msf_ctx *ctx, int32_t n, int64_t m, const int32_t *e
         }
     }
     zero_counters(c);
-    rc = build_adjacency(c, n, m, (const int32_t *)g->bufs[0], g->bufs[1], wt, &g->a,
+    rc = build_adjacency(c, n, m, (const int32_t *)g->bufs[0], g->bufs[1], wt, slices, &g->a,
                          (uint32_t *)g->bufs[2], (uint32_t *)g->bufs[3], (uint64_t *)g->bufs[4],
                          (uint32_t *)g->bufs[5]);
     if (rc == MSF_OK) rc = read_counters(c);
@@ -334,9 +338,10 @@ msf_status msf_graph_create(msf_ctx *ctx, int32_t n, int64_t m, const int32_t *e
         msf_graph_destroy(g);
         return rc;
     }
-    g->a.nnz = c->hcnt->count;
-    g->a.nchunks = sweep_nchunks(g->a.nnz);
-    launch_chunk_rows(c->stream, g->a.row_ptr, n, g->a.nnz, g->a.chunk_row, g->a.nchunks);
+    for (int q = 0; q <= g->a.sl.S; ++q) g->a.sl.sstart[q] = c->hcnt->sstart[q];
+    set_chunks(&g->a);
+    g->a.segs = c->hcnt->segs;
+    if (g->a.nnz) launch_chunk_rows_sliced(c->stream, g->a);
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         msf_graph_destroy(g);

@@ -181,37 +181,97 @@ __global__ void k_scatter(const int32_t *__restrict__ edges, const void *__restr
 }
 
 // --------------------------------------------------------- chunk rows ---
-// chunk_row[c] = the row holding entry min(c*CHUNK, nnz-1): the largest r
-// with row_ptr[r] <= that entry.
+// For chunk k of slice s: the row holding entry sstart[s] + min(k*CHUNK,
+// len_s - 1), i.e. the largest r with rp_s[r] <= that position.
 
 uint32_t sweep_nchunks(uint32_t nnz) { return (nnz + SWEEP_CHUNK - 1) / SWEEP_CHUNK; }
 
-__global__ void k_chunk_rows(const uint32_t *__restrict__ row_ptr, int32_t n, uint32_t nnz,
-                             uint32_t *__restrict__ chunk_row, uint32_t nchunks)
+int choose_slices(int32_t n, int forced)
 {
-    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c > nchunks) return;
-    if (nnz == 0) {
-        chunk_row[c] = 0;
-        return;
-    }
-    uint64_t pos = (uint64_t)c * SWEEP_CHUNK;
-    if (pos > nnz - 1) pos = nnz - 1;
-    // largest r in [0, n-1] with row_ptr[r] <= pos
-    int32_t lo = 0, hi = n - 1;
-    while (lo < hi) {
-        int32_t mid = lo + (hi - lo + 1) / 2;
-        if (row_ptr[mid] <= pos) lo = mid;
-        else hi = mid - 1;
-    }
-    chunk_row[c] = (uint32_t)lo;
+    if (forced >= 1) return forced > MAX_SLICES ? MAX_SLICES : forced;
+    // one L2 (4 MB) holds 2^20 parents; beyond that give each XCD a slice
+    return n >= (1 << 20) ? MAX_SLICES : 1;
 }
 
-void launch_chunk_rows(hipStream_t s, const uint32_t *row_ptr, int32_t n, uint32_t nnz,
-                       uint32_t *chunk_row, uint32_t nchunks)
+void set_chunks(Adj *a)
 {
-    unsigned g = (nchunks + 1 + 255) / 256;
-    k_chunk_rows<<<g, 256, 0, s>>>(row_ptr, n, nnz, chunk_row, nchunks);
+    SliceInfo &sl = a->sl;
+    uint32_t tot = 0, mx = 0;
+    for (int q = 0; q < sl.S; ++q) {
+        sl.cbase[q] = tot;
+        // chunks of a slice start at its first entry rounded down to 4
+        const uint32_t len = sl.sstart[q + 1] - sl.sstart[q];
+        const uint32_t ch = len ? sweep_nchunks(sl.sstart[q + 1] - (sl.sstart[q] & ~3u)) : 0u;
+        tot += ch;
+        mx = ch > mx ? ch : mx;
+    }
+    sl.cbase[sl.S] = tot;
+    sl.maxch = mx;
+    a->nchunks = tot;
+    a->nnz = sl.sstart[sl.S] - sl.sstart[0];
+}
+
+__global__ void k_chunk_rows(const uint32_t *__restrict__ row_ptr, int32_t n, SliceInfo sl,
+                             uint32_t *__restrict__ chunk_row)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= sl.cbase[sl.S] + (uint32_t)sl.S) return;
+    int q = 0;
+    while (q + 1 < sl.S && j >= sl.cbase[q + 1] + (uint32_t)(q + 1)) ++q;
+    const uint32_t k = j - (sl.cbase[q] + (uint32_t)q);
+    const uint32_t len = sl.sstart[q + 1] - sl.sstart[q];
+    if (len == 0) {
+        chunk_row[j] = 0;
+        return;
+    }
+    uint64_t pos = (uint64_t)(sl.sstart[q] & ~3u) + (uint64_t)k * SWEEP_CHUNK;
+    if (pos < sl.sstart[q]) pos = sl.sstart[q];
+    if (pos > sl.sstart[q + 1] - 1) pos = sl.sstart[q + 1] - 1;
+    const uint32_t *rp = row_ptr + (size_t)q * ((size_t)n + 1);
+    int32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo + 1) / 2;
+        if (rp[mid] <= pos) lo = mid;
+        else hi = mid - 1;
+    }
+    chunk_row[j] = (uint32_t)lo;
+}
+
+void launch_chunk_rows_sliced(hipStream_t s, const Adj &a)
+{
+    const uint32_t items = a.sl.cbase[a.sl.S] + (uint32_t)a.sl.S;
+    k_chunk_rows<<<(items + 255) / 256, 256, 0, s>>>(a.row_ptr, a.n, a.sl, a.chunk_row);
+}
+
+// Slice boundaries and the number of non-empty (row, slice) segments.
+__global__ __launch_bounds__(256) void k_slice_info(const uint32_t *__restrict__ row_ptr,
+                                                    int32_t n, int S, Counters *cnt)
+{
+    __shared__ uint32_t s_lds[256 / 64 + 1];
+    const size_t stride = (size_t)n + 1;
+    if (blockIdx.x == 0 && threadIdx.x <= (unsigned)S)
+        cnt->sstart[threadIdx.x] = threadIdx.x < (unsigned)S
+                                       ? row_ptr[(size_t)threadIdx.x * stride]
+                                       : row_ptr[(size_t)(S - 1) * stride + n];
+    uint32_t segs = 0;
+    const size_t total = (size_t)S * n;
+    for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < total;
+         j += (size_t)gridDim.x * blockDim.x) {
+        const size_t q = j / (size_t)n, i = j - q * (size_t)n;
+        const uint32_t *rp = row_ptr + q * stride;
+        segs += rp[i + 1] > rp[i] ? 1u : 0u;
+    }
+    segs = block_sum<256>(segs, s_lds);
+    if (threadIdx.x == 0 && segs) atomicAdd(&cnt->segs, segs);
+}
+
+void launch_slice_info(hipStream_t s, const Adj &a, Counters *dcnt)
+{
+    launch_fill_u32(s, &dcnt->segs, 0u, 1);
+    size_t g = ((size_t)a.sl.S * (size_t)a.n + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 2048) g = 2048;
+    k_slice_info<<<(unsigned)g, 256, 0, s>>>(a.row_ptr, a.n, a.sl.S, dcnt);
 }
 
 // ------------------------------------------------- bucketed build ------
@@ -234,19 +294,26 @@ constexpr int BKC_NT = 1024;
 constexpr int BK_MIN_LB = 12;  // fewer, larger buckets keep pass B's writes in long runs
 constexpr int BK_MAX_LB = 15;  // pass C keeps 2^LB row counters in LDS
 
-static int bucket_bits(int32_t n)
+static int bucket_bits(int32_t n, int S)
 {
     int lb = BK_MIN_LB;
-    while ((((int64_t)n + (1ll << lb) - 1) >> lb) > BK_MAX_NB) ++lb;
+    while ((int64_t)S * ((((int64_t)n + (1ll << lb) - 1) >> lb)) > BK_MAX_NB) ++lb;
     return lb;
+}
+
+// bucket of stored direction row -> col: (slice of col, row >> lb)
+__device__ __forceinline__ uint32_t bucket_of(uint32_t row, uint32_t col, int lb, uint32_t slice_w,
+                                              uint32_t nbr)
+{
+    return (col / slice_w) * nbr + (row >> lb);
 }
 
 template <int WT>
 __global__ __launch_bounds__(BKA_NT) void k_bucket_hist(const int32_t *__restrict__ edges,
                                                         const void *__restrict__ w, int64_t m,
-                                                        int32_t n, int lb, int nb, int64_t epb,
-                                                        uint32_t nblk, uint32_t *__restrict__ bh,
-                                                        Counters *cnt)
+                                                        int32_t n, int lb, int nb, uint32_t slice_w,
+                                                        uint32_t nbr, int64_t epb, uint32_t nblk,
+                                                        uint32_t *__restrict__ bh, Counters *cnt)
 {
     extern __shared__ uint32_t hist[];
     for (int i = threadIdx.x; i < nb; i += BKA_NT) hist[i] = 0;
@@ -265,8 +332,8 @@ __global__ __launch_bounds__(BKA_NT) void k_bucket_hist(const int32_t *__restric
             continue;
         }
         if (u == v) continue;
-        atomicAdd(&hist[(uint32_t)u >> lb], 1u);
-        atomicAdd(&hist[(uint32_t)v >> lb], 1u);
+        atomicAdd(&hist[bucket_of((uint32_t)u, (uint32_t)v, lb, slice_w, nbr)], 1u);
+        atomicAdd(&hist[bucket_of((uint32_t)v, (uint32_t)u, lb, slice_w, nbr)], 1u);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nb; i += BKA_NT) bh[(size_t)i * nblk + blockIdx.x] = hist[i];
@@ -280,7 +347,8 @@ __global__ __launch_bounds__(BKA_NT) void k_bucket_hist(const int32_t *__restric
 template <int WT>
 __global__ __launch_bounds__(BKA_NT) void k_bucket_scatter(
     const int32_t *__restrict__ edges, const void *__restrict__ w, int64_t m, int32_t n, int lb,
-    int nb, int64_t epb, uint32_t nblk, const uint32_t *__restrict__ bh_off,
+    int nb, uint32_t slice_w, uint32_t nbr, int64_t epb, uint32_t nblk,
+    const uint32_t *__restrict__ bh_off,
     uint16_t *__restrict__ rlo, uint32_t *__restrict__ bcol, uint64_t *__restrict__ bkey)
 {
     extern __shared__ uint32_t off[];
@@ -295,8 +363,8 @@ __global__ __launch_bounds__(BKA_NT) void k_bucket_scatter(
         uint32_t wk = ((const uint32_t *)w)[e];
         if (WT == MSF_W_F32) wk = wkey_f32_bits(wk);
         const uint64_t k = ((uint64_t)wk << 32) | (uint64_t)(uint32_t)e;
-        const uint32_t pu = atomicAdd(&off[(uint32_t)u >> lb], 1u);
-        const uint32_t pv = atomicAdd(&off[(uint32_t)v >> lb], 1u);
+        const uint32_t pu = atomicAdd(&off[bucket_of((uint32_t)u, (uint32_t)v, lb, slice_w, nbr)], 1u);
+        const uint32_t pv = atomicAdd(&off[bucket_of((uint32_t)v, (uint32_t)u, lb, slice_w, nbr)], 1u);
         rlo[pu] = (uint16_t)((uint32_t)u & mask);
         bcol[pu] = (uint32_t)v;
         bkey[pu] = k;
@@ -307,7 +375,7 @@ __global__ __launch_bounds__(BKA_NT) void k_bucket_scatter(
 }
 
 __global__ __launch_bounds__(BKC_NT) void k_bucket_rows(
-    const uint32_t *__restrict__ bh_off, uint32_t nblk, int32_t n, int lb, int nb,
+    const uint32_t *__restrict__ bh_off, uint32_t nblk, int32_t n, int lb, int nb, uint32_t nbr,
     const uint16_t *__restrict__ rlo, const uint32_t *__restrict__ bcol,
     const uint64_t *__restrict__ bkey, uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ col,
     uint64_t *__restrict__ key)
@@ -318,7 +386,9 @@ __global__ __launch_bounds__(BKC_NT) void k_bucket_rows(
     const uint32_t s = bh_off[(size_t)b * nblk];
     const uint32_t e = bh_off[(size_t)(b + 1) * nblk];
     const uint32_t R = 1u << lb;
-    const int64_t row0 = (int64_t)b << lb;
+    const uint32_t slice = b / nbr, rb = b - slice * nbr;
+    const int64_t row0 = (int64_t)rb << lb;
+    row_ptr += (size_t)slice * ((size_t)n + 1);
     const uint32_t rows = (uint32_t)((int64_t)n - row0 < (int64_t)R ? (int64_t)n - row0 : R);
     for (uint32_t i = threadIdx.x; i < R; i += BKC_NT) cnt[i] = 0;
     __syncthreads();
@@ -342,7 +412,7 @@ __global__ __launch_bounds__(BKC_NT) void k_bucket_rows(
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < rows; i += BKC_NT) row_ptr[row0 + i] = s + cnt[i];
-    if (b == (uint32_t)nb - 1 && threadIdx.x == 0) row_ptr[n] = e;
+    if (rb == nbr - 1 && threadIdx.x == 0) row_ptr[n] = e;
     __syncthreads();
     for (uint32_t k = s + threadIdx.x; k < e; k += BKC_NT) {
         const uint32_t pos = s + atomicAdd(&cnt[rlo[k]], 1u);
@@ -383,11 +453,12 @@ static msf_status build_atomic(Ctx *c, int32_t n, int64_t m, const int32_t *d_ed
 }
 
 static msf_status build_bucketed(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
-                                 const void *d_w, msf_wtype wt, int lb, uint32_t *row_ptr,
-                                 uint32_t *col, uint64_t *key)
+                                 const void *d_w, msf_wtype wt, int lb, int S, uint32_t slice_w,
+                                 uint32_t *row_ptr, uint32_t *col, uint64_t *key)
 {
     hipStream_t s = c->stream;
-    const int nb = (int)(((int64_t)n + (1ll << lb) - 1) >> lb);
+    const uint32_t nbr = (uint32_t)(((int64_t)n + (1ll << lb) - 1) >> lb);
+    const int nb = (int)nbr * S;
     int64_t epb = (m + 2047) / 2048;
     if (epb < 32768) epb = 32768;
     epb = (epb + 255) & ~(int64_t)255;
@@ -403,22 +474,22 @@ static msf_status build_bucketed(Ctx *c, int32_t n, int64_t m, const int32_t *d_
     uint32_t *bh = (uint32_t *)vbh, *bo = (uint32_t *)vbo;
     const size_t lds_a = 4 * (size_t)nb;
     if (wt == MSF_W_F32)
-        k_bucket_hist<MSF_W_F32><<<nblk, BKA_NT, lds_a, s>>>(d_edges, d_w, m, n, lb, nb, epb, nblk,
-                                                           bh, c->dcnt);
+        k_bucket_hist<MSF_W_F32><<<nblk, BKA_NT, lds_a, s>>>(d_edges, d_w, m, n, lb, nb, slice_w,
+                                                           nbr, epb, nblk, bh, c->dcnt);
     else
-        k_bucket_hist<MSF_W_U32><<<nblk, BKA_NT, lds_a, s>>>(d_edges, d_w, m, n, lb, nb, epb, nblk,
-                                                           bh, c->dcnt);
+        k_bucket_hist<MSF_W_U32><<<nblk, BKA_NT, lds_a, s>>>(d_edges, d_w, m, n, lb, nb, slice_w,
+                                                           nbr, epb, nblk, bh, c->dcnt);
     MSF_TRY(scan_u32(c, bh, bo, (int64_t)nh, &c->dcnt->count));
     if (wt == MSF_W_F32)
         k_bucket_scatter<MSF_W_F32><<<nblk, BKA_NT, lds_a, s>>>(
-            d_edges, d_w, m, n, lb, nb, epb, nblk, bo, (uint16_t *)vrlo, (uint32_t *)vcol,
-            (uint64_t *)vkey);
+            d_edges, d_w, m, n, lb, nb, slice_w, nbr, epb, nblk, bo, (uint16_t *)vrlo,
+            (uint32_t *)vcol, (uint64_t *)vkey);
     else
         k_bucket_scatter<MSF_W_U32><<<nblk, BKA_NT, lds_a, s>>>(
-            d_edges, d_w, m, n, lb, nb, epb, nblk, bo, (uint16_t *)vrlo, (uint32_t *)vcol,
-            (uint64_t *)vkey);
+            d_edges, d_w, m, n, lb, nb, slice_w, nbr, epb, nblk, bo, (uint16_t *)vrlo,
+            (uint32_t *)vcol, (uint64_t *)vkey);
     const size_t lds_c = 4 * ((size_t)1 << lb) + 4 * (BKC_NT / 64 + 1);
-    k_bucket_rows<<<nb, BKC_NT, lds_c, s>>>(bo, nblk, n, lb, nb, (const uint16_t *)vrlo,
+    k_bucket_rows<<<nb, BKC_NT, lds_c, s>>>(bo, nblk, n, lb, nb, nbr, (const uint16_t *)vrlo,
                                             (const uint32_t *)vcol, (const uint64_t *)vkey,
                                             row_ptr, col, key);
     MSF_HIP(hipGetLastError());
@@ -445,21 +516,30 @@ static bool bucket_lds_ok(int lb)
 }
 
 msf_status build_adjacency(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
-                           msf_wtype wt, Adj *a, uint32_t *row_ptr, uint32_t *col, uint64_t *key,
-                           uint32_t *chunk_row)
+                           msf_wtype wt, int S, Adj *a, uint32_t *row_ptr, uint32_t *col,
+                           uint64_t *key, uint32_t *chunk_row)
 {
     launch_fill_u32(c->stream, &c->dcnt->err, 0u, 1);
-    const int lb = bucket_bits(n);
+    if (S < 1 || n < 32 * S) S = 1;
+    int lb = bucket_bits(n, S);
+    const bool bucketed = c->bucketed_build && m > 0 && n > 0 && lb <= BK_MAX_LB &&
+                          bucket_lds_ok(lb);
+    if (!bucketed) S = 1;  // the atomic fallback stores one slice
+    uint32_t slice_w = (uint32_t)n;
+    if (S > 1) slice_w = (uint32_t)((((int64_t)n + S - 1) / S + 31) & ~(int64_t)31);
     if (m == 0 || n == 0) {
         launch_fill_u32(c->stream, row_ptr, 0u, (size_t)n + 1);
         launch_fill_u32(c->stream, &c->dcnt->count, 0u, 1);
-    } else if (lb <= BK_MAX_LB && c->bucketed_build && bucket_lds_ok(lb)) {
-        MSF_TRY(build_bucketed(c, n, m, d_edges, d_w, wt, lb, row_ptr, col, key));
+    } else if (bucketed) {
+        MSF_TRY(build_bucketed(c, n, m, d_edges, d_w, wt, lb, S, slice_w, row_ptr, col, key));
     } else {
         MSF_TRY(build_atomic(c, n, m, d_edges, d_w, wt, row_ptr, col, key));
     }
     a->n = n;
     a->m = m;
+    a->sl = SliceInfo{};
+    a->sl.S = S;
+    a->sl.slice_w = slice_w;
     a->row_ptr = row_ptr;
     a->col = col;
     a->key = key;
@@ -467,6 +547,8 @@ msf_status build_adjacency(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
     a->edges = d_edges;
     a->w = d_w;
     a->wtype = wt;
+    launch_slice_info(c->stream, *a, c->dcnt);
+    MSF_HIP(hipGetLastError());
     return MSF_OK;
 }
 

@@ -48,7 +48,7 @@ static void prep_lookback(hipStream_t s, uint64_t *status, uint32_t tiles, Count
 // finished roots from the start).
 
 __global__ __launch_bounds__(CT_NT) void k_init_roots(const uint32_t *__restrict__ row_ptr,
-                                                      int32_t n, uint32_t *__restrict__ R,
+                                                      int32_t n, int S, uint32_t *__restrict__ R,
                                                       uint64_t *status, Counters *cnt)
 {
     __shared__ uint32_t s_tile;
@@ -58,28 +58,34 @@ __global__ __launch_bounds__(CT_NT) void k_init_roots(const uint32_t *__restrict
     __syncthreads();
     const uint32_t tile = s_tile;
     const int64_t base = (int64_t)tile * CT_TILE + (int64_t)threadIdx.x * CT_IT;
-    uint32_t rp[CT_IT + 1];
+    uint32_t act = 0, c = 0;
+    for (int q = 0; q < S; ++q) {
+        const uint32_t *rp = row_ptr + (size_t)q * ((size_t)n + 1);
+        uint32_t prev = (base <= n) ? rp[base] : 0u;
 #pragma unroll
-    for (int k = 0; k <= CT_IT; ++k) rp[k] = (base + k <= n) ? row_ptr[base + k] : 0u;
-    uint32_t c = 0;
-#pragma unroll
-    for (int k = 0; k < CT_IT; ++k) c += (base + k < n && rp[k + 1] > rp[k]) ? 1u : 0u;
+        for (int k = 0; k < CT_IT; ++k) {
+            const uint32_t nx = (base + k + 1 <= n) ? rp[base + k + 1] : 0u;
+            if (base + k < n && nx > prev) act |= 1u << k;
+            prev = nx;
+        }
+    }
+    c = __popc(act);
     uint32_t oa, ob;
     uint64_t tot;
     tile_offsets2<CT_NT>(tile, c, 0u, status, s_lds, &s_pre, &oa, &ob, &tot);
 #pragma unroll
     for (int k = 0; k < CT_IT; ++k)
-        if (base + k < n && rp[k + 1] > rp[k]) R[oa++] = (uint32_t)(base + k);
+        if (act & (1u << k)) R[oa++] = (uint32_t)(base + k);
     if (tile == gridDim.x - 1 && threadIdx.x == 0) cnt->nR = (uint32_t)(tot >> 31);
 }
 
-void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, uint32_t *R,
+void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S, uint32_t *R,
                        uint64_t *status, Counters *dcnt)
 {
     const uint32_t tiles = ct_tiles((uint64_t)n);
     if (!tiles) return;
     prep_lookback(s, status, tiles, dcnt);
-    k_init_roots<<<tiles, CT_NT, 0, s>>>(row_ptr, n, R, status, dcnt);
+    k_init_roots<<<tiles, CT_NT, 0, s>>>(row_ptr, n, S, R, status, dcnt);
 }
 
 // ---------------------------------------------------------------- hook --
@@ -277,39 +283,23 @@ void launch_chase(hipStream_t s, const uint32_t *F, uint32_t nF, uint32_t *h, ui
 // to part[] (folded by k_fold_rows) for the sweep's byte accounting.
 
 __global__ __launch_bounds__(256) void k_update_parents(const uint32_t *__restrict__ row_ptr,
-                                                        int32_t n, uint32_t *__restrict__ p,
-                                                        const uint32_t *__restrict__ h,
-                                                        uint32_t *__restrict__ part)
+                                                        int32_t n, int S, uint32_t *__restrict__ p,
+                                                        const uint32_t *__restrict__ h)
 {
-    __shared__ uint32_t s_lds[256 / 64 + 1];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    uint32_t rows = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        if (row_ptr[i + 1] > row_ptr[i]) {
-            p[i] = h[p[i]];
-            ++rows;
-        }
+        if (S > 1 || row_ptr[i + 1] > row_ptr[i]) p[i] = h[p[i]];
     }
-    rows = block_sum<256>(rows, s_lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = rows;
 }
 
-__global__ void k_fold_rows(const uint32_t *__restrict__ part, uint32_t nb, Counters *cnt)
-{
-    uint32_t v = 0;
-    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) v += part[i];
-    v = wave_sum(v);
-    if (__lane_id() == 0 && v) atomicAdd(&cnt->rows, v);
-}
-
-void launch_update_parents(hipStream_t s, const uint32_t *row_ptr, int32_t n, uint32_t *p,
+void launch_update_parents(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S, uint32_t *p,
                            const uint32_t *h, uint32_t *part, Counters *dcnt)
 {
-    launch_fill_u32(s, &dcnt->rows, 0u, 1);
+    (void)part;
+    (void)dcnt;
     if (!n) return;
     const unsigned g = grid_for((size_t)n, 256, 4096);
-    k_update_parents<<<g, 256, 0, s>>>(row_ptr, n, p, h, part);
-    k_fold_rows<<<1, 256, 0, s>>>(part, g, dcnt);
+    k_update_parents<<<g, 256, 0, s>>>(row_ptr, n, S, p, h);
 }
 
 // --------------------------------------------------------------- output --

@@ -54,14 +54,20 @@ __device__ __forceinline__ RunAgg combine(const RunAgg &a, const RunAgg &b)
 // span more rows (long runs of empty rows) search global memory instead.
 constexpr int SWEEP_WIN = 2048;
 
+// Chunk k of slice q covers entries [cb + k*CHUNK, cb + (k+1)*CHUNK) with
+// cb = sstart[q] rounded down to 4 entries (16-byte aligned loads); entries
+// outside [sstart[q], sstart[q+1]) belong to neighbouring slices and are
+// ignored.
+
 // FIRST: the parent vector is the identity (round 1), so every stored entry
-// is outgoing, runs are rows, and no parent is read at all; a row that lies
-// wholly inside one wave has a single writer and is stored without an atomic.
+// is outgoing, runs are rows, and no parent is read at all; with a single
+// slice a row that lies wholly inside one wave has a single writer and is
+// stored without an atomic.
 template <bool COMPACT, bool FIRST>
 __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
-    const uint64_t *__restrict__ key, const uint32_t *__restrict__ chunk_row, uint32_t nnz,
-    uint32_t nchunks, int32_t n, const uint32_t *__restrict__ p, uint64_t *__restrict__ r,
+    const uint64_t *__restrict__ key, const uint32_t *__restrict__ chunk_row, SliceInfo sl,
+    int32_t n, const uint32_t *__restrict__ p, uint64_t *__restrict__ r,
     uint32_t *__restrict__ chunk_wpre, uint32_t *__restrict__ chunk_mask,
     uint32_t *__restrict__ col_out, uint64_t *__restrict__ key_out, uint64_t *status,
     Counters *cnt, uint32_t *block_live)
@@ -73,22 +79,36 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     __shared__ uint32_t s_rp[SWEEP_WIN + 1];
     __shared__ uint32_t s_p[FIRST ? 1 : SWEEP_WIN];
 
-    uint32_t c;
+    // chunk c (all slices), slice q, chunk k inside the slice
+    uint32_t c, q = 0, k;
     if (COMPACT) {
         if (threadIdx.x == 0) s_chunk = atomicAdd(&cnt->ticket, 1u);
         __syncthreads();
         c = s_chunk;
+        while (q + 1 < (uint32_t)sl.S && c >= sl.cbase[q + 1]) ++q;
+        k = c - sl.cbase[q];
     } else {
-        c = blockIdx.x;
+        q = blockIdx.x % (uint32_t)sl.S;
+        k = blockIdx.x / (uint32_t)sl.S;
+        if (k >= sl.cbase[q + 1] - sl.cbase[q]) return;  // slice q has fewer chunks
+        c = sl.cbase[q] + k;
     }
     const uint32_t lane = __lane_id();
-    const uint32_t base = c * (uint32_t)SWEEP_CHUNK + threadIdx.x * E;
-    const int nvalid = base >= nnz ? 0 : (nnz - base >= (uint32_t)E ? E : (int)(nnz - base));
+    const uint32_t s_lo = sl.sstart[q], s_hi = sl.sstart[q + 1];
+    const uint32_t cb = (s_lo & ~3u) + k * (uint32_t)SWEEP_CHUNK;
+    const uint32_t base = cb + threadIdx.x * E;
+    const uint32_t *__restrict__ rp = row_ptr + (size_t)q * ((size_t)n + 1);
+    const uint32_t *__restrict__ crow = chunk_row + sl.cbase[q] + q;
+
+    // valid entries of this lane: [base + kb, base + ke)
+    const int kb = base >= s_lo ? 0 : (int)(s_lo - base < (uint32_t)E ? s_lo - base : E);
+    const int ke = base >= s_hi ? 0 : (s_hi - base >= (uint32_t)E ? E : (int)(s_hi - base));
+    const bool full = kb == 0 && ke == E;
 
     // streamed loads first (non-temporal: read once per sweep)
     uint32_t cl[E];
     uint64_t ky[E];
-    if (nvalid == E) {
+    if (full) {
         const u32x4 c4 = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(col + base));
         const u64x2 k01 = __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(key + base));
         const u64x2 k23 =
@@ -97,29 +117,30 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
         ky[0] = k01.x; ky[1] = k01.y; ky[2] = k23.x; ky[3] = k23.y;
     } else {
 #pragma unroll
-        for (int k = 0; k < E; ++k) {
-            cl[k] = k < nvalid ? col[base + k] : 0u;
-            ky[k] = k < nvalid ? key[base + k] : KEY_INF;
+        for (int e = 0; e < E; ++e) {
+            const bool v = e >= kb && e < ke;
+            cl[e] = v ? col[base + e] : 0u;
+            ky[e] = v ? key[base + e] : KEY_INF;
         }
     }
     // window of rows touched by this chunk
-    const uint32_t lo = chunk_row[c];
-    const uint32_t hi = chunk_row[c + 1 <= nchunks ? c + 1 : nchunks];
+    const uint32_t lo = crow[k];
+    const uint32_t hi = crow[k + 1];
     const uint32_t nrows = hi - lo + 1;
     const bool win = nrows + 1 <= (uint32_t)SWEEP_WIN;
     if (win) {
         for (uint32_t t = threadIdx.x; t <= nrows; t += SWEEP_BLOCK) {
-            s_rp[t] = row_ptr[lo + t];
+            s_rp[t] = rp[lo + t];
             if (!FIRST && t < nrows) s_p[t] = p[lo + t];
         }
     }
     // column parents: independent of the row search, issued before it
     uint32_t pc[E];
 #pragma unroll
-    for (int k = 0; k < E; ++k) pc[k] = (!FIRST && k < nvalid) ? p[cl[k]] : 0u;
+    for (int e = 0; e < E; ++e) pc[e] = (!FIRST && e >= kb && e < ke) ? p[cl[e]] : 0u;
     __syncthreads();
 
-    auto rp_at = [&](uint32_t rw) -> uint32_t { return win ? s_rp[rw - lo] : row_ptr[rw]; };
+    auto rp_at = [&](uint32_t rw) -> uint32_t { return win ? s_rp[rw - lo] : rp[rw]; };
     auto search = [&](uint32_t a, uint32_t b, uint32_t idx) -> uint32_t {
         while (a < b) {
             const uint32_t mid = a + ((b - a + 1) >> 1);
@@ -131,42 +152,40 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
 
     uint32_t root[E];
     uint64_t cand[E];
-    uint32_t rowk[E];
     bool live[E];
 #pragma unroll
-    for (int k = 0; k < E; ++k) {
-        live[k] = false;
-        cand[k] = KEY_INF;
-        root[k] = NONE32;
-        rowk[k] = NONE32;
+    for (int e = 0; e < E; ++e) {
+        live[e] = false;
+        cand[e] = KEY_INF;
+        root[e] = NONE32;
     }
-    if (nvalid > 0) {
-        uint32_t row = search(lo, hi, base);
+    if (ke > kb) {
+        uint32_t row = search(lo, hi, base + kb);
         uint32_t nxt = rp_at(row + 1);
         uint32_t prow = FIRST ? row : (win ? s_p[row - lo] : p[row]);
 #pragma unroll
-        for (int k = 0; k < E; ++k) {
-            const uint32_t idx = base + k;
-            if (k < nvalid) {
+        for (int e = 0; e < E; ++e) {
+            const uint32_t idx = base + e;
+            if (e >= kb && e < ke) {
                 if (idx >= nxt) {
                     row = search(row + 1, hi, idx);
                     nxt = rp_at(row + 1);
                     prow = FIRST ? row : (win ? s_p[row - lo] : p[row]);
                 }
-                live[k] = FIRST ? true : (prow != pc[k]);
-                cand[k] = live[k] ? ky[k] : KEY_INF;
-                root[k] = prow;
-                rowk[k] = row;
+                live[e] = FIRST ? true : (prow != pc[e]);
+                cand[e] = live[e] ? ky[e] : KEY_INF;
+                root[e] = prow;
             }
         }
     }
 
-    // flush one run's minimum: in round 1 a row wholly inside this wave's
-    // entries has no other writer; everything else goes through the atomic
+    // flush one run's minimum: in round 1 with one slice, a row wholly
+    // inside this wave's entries has no other writer; everything else goes
+    // through the atomic
     const uint32_t wave_lo = base - lane * E;
     const uint32_t wave_hi = wave_lo + 64 * E;  // exclusive
     auto flush = [&](uint32_t rt, uint64_t v) {
-        if (FIRST) {
+        if (FIRST && sl.S == 1) {
             if (v == KEY_INF) return;
             if (rp_at(rt) >= wave_lo && rp_at(rt + 1) <= wave_hi) r[rt] = v;
             else min_into(r, rt, v);
@@ -176,20 +195,24 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     };
 
     // lane-local runs by root; interior runs are complete and flushed now
-    uint32_t froot = root[0], lroot = root[0];
-    uint64_t fmin = cand[0], lmin = KEY_INF;
-    bool single = true;
+    uint32_t froot = NONE32, lroot = NONE32;
+    uint64_t fmin = KEY_INF, lmin = KEY_INF;
+    bool single = true, started = false;
 #pragma unroll
-    for (int k = 1; k < E; ++k) {
-        if (k >= nvalid) break;
-        if (root[k] == lroot) {
-            if (single) fmin = fmin < cand[k] ? fmin : cand[k];
-            else lmin = lmin < cand[k] ? lmin : cand[k];
+    for (int e = 0; e < E; ++e) {
+        if (e < kb || e >= ke) continue;
+        if (!started) {
+            froot = lroot = root[e];
+            fmin = cand[e];
+            started = true;
+        } else if (root[e] == lroot) {
+            if (single) fmin = fmin < cand[e] ? fmin : cand[e];
+            else lmin = lmin < cand[e] ? lmin : cand[e];
         } else {
             if (!single) flush(lroot, lmin);
             single = false;
-            lroot = root[k];
-            lmin = cand[k];
+            lroot = root[e];
+            lmin = cand[e];
         }
     }
 
@@ -212,7 +235,7 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     const uint64_t prev_lrm = __shfl_up(agg.lrm, 1, 64);
     uint32_t next_first = __shfl_down(froot, 1, 64);
     if (lane == 63) next_first = NONE32;
-    if (nvalid > 0) {
+    if (started) {
         uint64_t ffull = fmin;
         if (lane > 0 && prev_last == froot) ffull = ffull < prev_lrm ? ffull : prev_lrm;
         if (single) {
@@ -225,7 +248,7 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
 
     uint32_t lcnt = 0;
 #pragma unroll
-    for (int k = 0; k < E; ++k) lcnt += live[k] ? 1u : 0u;
+    for (int e = 0; e < E; ++e) lcnt += live[e] ? 1u : 0u;
 
     if (!COMPACT) {
         if (block_live) {  // live-entry count of this chunk (filtering policy)
@@ -250,7 +273,7 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     // row pointers are derived from them by k_rowptr_compact
     uint32_t nib = 0;
 #pragma unroll
-    for (int k = 0; k < E; ++k) nib |= (live[k] ? 1u : 0u) << k;
+    for (int e = 0; e < E; ++e) nib |= (live[e] ? 1u : 0u) << e;
     uint32_t word = nib << ((lane & 7u) * 4u);
     word |= __shfl_xor(word, 1, 64);
     word |= __shfl_xor(word, 2, 64);
@@ -261,33 +284,39 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
         chunk_wpre[wi] = pos;
     }
 #pragma unroll
-    for (int k = 0; k < E; ++k) {
-        if (k < nvalid && live[k]) {
-            col_out[pos] = cl[k];
-            key_out[pos] = ky[k];
+    for (int e = 0; e < E; ++e) {
+        if (live[e]) {
+            col_out[pos] = cl[e];
+            key_out[pos] = ky[e];
             ++pos;
         }
     }
-    if (c == nchunks - 1 && threadIdx.x == 0) cnt->nnz_out = (uint32_t)(P + btot);
+    if (c == sl.cbase[sl.S] - 1 && threadIdx.x == 0) cnt->nnz_out = (uint32_t)(P + btot);
 }
 
-// Output row pointers of a compaction: row_ptr_out[i] = survivors stored
-// before old position row_ptr[i] (all survivors when that position is nnz).
-__global__ void k_rowptr_compact(const uint32_t *__restrict__ row_ptr, int32_t n, uint32_t nnz,
+// Output row pointers of a compaction: rp'_q[i] = survivors stored before
+// old position rp_q[i] (all survivors when that position is the end).
+__global__ void k_rowptr_compact(const uint32_t *__restrict__ row_ptr, int32_t n, SliceInfo sl,
                                  const uint32_t *__restrict__ chunk_wpre,
                                  const uint32_t *__restrict__ chunk_mask, const Counters *cnt,
                                  uint32_t *__restrict__ row_ptr_out)
 {
     const uint32_t total = cnt->nnz_out;
+    const uint32_t nnz = sl.sstart[sl.S];
+    const int64_t count = (int64_t)sl.S * ((int64_t)n + 1);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += stride) {
-        const uint32_t x = row_ptr[i];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < count; j += stride) {
+        const uint32_t x = row_ptr[j];
         uint32_t v = total;
         if (x < nnz) {
-            const uint32_t w = x >> 5;
-            v = chunk_wpre[w] + __popc(chunk_mask[w] & ((1u << (x & 31u)) - 1u));
+            int q = 0;
+            while (q + 1 < sl.S && x >= sl.sstart[q + 1]) ++q;
+            const uint32_t rel = x - (sl.sstart[q] & ~3u);
+            const size_t w = (size_t)(sl.cbase[q] + rel / SWEEP_CHUNK) * (SWEEP_CHUNK / 32) +
+                             (rel % SWEEP_CHUNK) / 32;
+            v = chunk_wpre[w] + __popc(chunk_mask[w] & ((1u << (rel & 31u)) - 1u));
         }
-        row_ptr_out[i] = v;
+        row_ptr_out[j] = v;
     }
 }
 
@@ -306,14 +335,15 @@ void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
                   uint32_t *block_live, Counters *dcnt, bool first)
 {
     if (a.nnz == 0) return;
+    const unsigned grid = a.sl.maxch * (unsigned)a.sl.S;  // slice = block % S
     if (first)
-        k_sweep<false, true><<<a.nchunks, SWEEP_BLOCK, 0, s>>>(
-            a.row_ptr, a.col, a.key, a.chunk_row, a.nnz, a.nchunks, a.n, p, r, nullptr, nullptr,
-            nullptr, nullptr, nullptr, nullptr, block_live);
+        k_sweep<false, true><<<grid, SWEEP_BLOCK, 0, s>>>(
+            a.row_ptr, a.col, a.key, a.chunk_row, a.sl, a.n, p, r, nullptr, nullptr, nullptr,
+            nullptr, nullptr, nullptr, block_live);
     else
-        k_sweep<false, false><<<a.nchunks, SWEEP_BLOCK, 0, s>>>(
-            a.row_ptr, a.col, a.key, a.chunk_row, a.nnz, a.nchunks, a.n, p, r, nullptr, nullptr,
-            nullptr, nullptr, nullptr, nullptr, block_live);
+        k_sweep<false, false><<<grid, SWEEP_BLOCK, 0, s>>>(
+            a.row_ptr, a.col, a.key, a.chunk_row, a.sl, a.n, p, r, nullptr, nullptr, nullptr,
+            nullptr, nullptr, nullptr, block_live);
     if (block_live && dcnt) {
         launch_fill_u64(s, &dcnt->live, 0ull, 1);
         unsigned g = (a.nchunks + 255) / 256;
@@ -332,11 +362,11 @@ void launch_sweep_compact(hipStream_t s, const Adj &a, const uint32_t *p, uint64
     launch_fill_u64(s, status, 0ull, a.nchunks);
     launch_fill_u32(s, &dcnt->ticket, 0u, 1);
     k_sweep<true, false><<<a.nchunks, SWEEP_BLOCK, 0, s>>>(
-        a.row_ptr, a.col, a.key, a.chunk_row, a.nnz, a.nchunks, a.n, p, r, wpre, mask, col_out,
-        key_out, status, dcnt, nullptr);
-    size_t g = ((size_t)a.n + 1 + 255) / 256;
+        a.row_ptr, a.col, a.key, a.chunk_row, a.sl, a.n, p, r, wpre, mask, col_out, key_out,
+        status, dcnt, nullptr);
+    size_t g = ((size_t)a.sl.S * ((size_t)a.n + 1) + 255) / 256;
     if (g > 8192) g = 8192;
-    k_rowptr_compact<<<(unsigned)g, 256, 0, s>>>(a.row_ptr, a.n, a.nnz, wpre, mask, dcnt,
+    k_rowptr_compact<<<(unsigned)g, 256, 0, s>>>(a.row_ptr, a.n, a.sl, wpre, mask, dcnt,
                                                  row_ptr_out);
 }
 

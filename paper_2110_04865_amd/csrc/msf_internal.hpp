@@ -24,6 +24,7 @@
 namespace msf {
 
 constexpr uint64_t KEY_INF = ~0ull;
+constexpr int MAX_SLICES = 8;
 constexpr uint32_t NONE32 = 0xFFFFFFFFu;
 
 // Sweep geometry: a workgroup of SWEEP_BLOCK lanes handles SWEEP_E
@@ -104,6 +105,8 @@ struct Counters {
     double total_f64;     // finalised forest weight
     uint64_t live;        // live entries counted by the last plain sweep
     uint32_t rows;        // rows with stored entries (counted by update)
+    uint32_t segs;        // non-empty (row, slice) segments of an adjacency
+    uint32_t sstart[MAX_SLICES + 1];  // slice boundaries of an adjacency
     uint32_t pad_;
 };
 
@@ -114,20 +117,41 @@ struct SolveBufs {
     void *part;
 };
 
+// Column slices: the stored entries are grouped by the slice of their
+// column (S contiguous vertex ranges of slice_w vertices), and inside a
+// slice by row.  Sweep workgroup b serves slice b % S, and workgroups are
+// dealt to the 8 XCDs round-robin by index, so each XCD gathers parents
+// from one slice only and keeps that slice of p in its own L2.
+
+struct SliceInfo {
+    int S = 1;
+    uint32_t slice_w = 0;                // vertices per slice (multiple of 32)
+    uint32_t sstart[MAX_SLICES + 1] = {};  // slice s holds entries [sstart[s], sstart[s+1])
+    uint32_t cbase[MAX_SLICES + 1] = {};   // first sweep chunk of slice s
+    uint32_t maxch = 0;                  // most chunks in one slice
+};
+
 // Device view of an adjacency structure.
 struct Adj {
     int32_t n = 0;
     int64_t m = 0;
     uint32_t nnz = 0;
-    uint32_t *row_ptr = nullptr;
+    SliceInfo sl;
+    uint32_t *row_ptr = nullptr;    // S*(n+1): slice s at row_ptr + s*(n+1), global positions
     uint32_t *col = nullptr;
     uint64_t *key = nullptr;
-    uint32_t *chunk_row = nullptr;
-    uint32_t nchunks = 0;
-    const int32_t *edges = nullptr;   // endpoint pairs, for hook decoding
-    const void *w = nullptr;          // weights, for totals
+    uint32_t *chunk_row = nullptr;  // slice s: chunks of s + 1 entries from cbase[s] + s
+    uint32_t nchunks = 0;           // all slices
+    uint32_t segs = 0;              // non-empty (row, slice) segments
+    const int32_t *edges = nullptr; // endpoint pairs, for hook decoding
+    const void *w = nullptr;        // weights, for totals
     msf_wtype wtype = MSF_W_U32;
 };
+
+// Slice count for n vertices (columns sliced once p outgrows one L2).
+int choose_slices(int32_t n, int forced);
+// Fill the chunk layout of a from sl.sstart (host values).
+void set_chunks(Adj *a);
 
 struct SolveState {
     int phase = 0;  // 0 idle, 1 build, 2 roots, 3 round, 4 output, 5 done
@@ -161,6 +185,7 @@ struct Ctx {
     bool check_rounds = false;  // read back error flags after every shortcut
     bool first_round_kernel = true;  // identity-parent sweep in round 1
     bool bucketed_build = true;      // LDS-only adjacency build
+    int slices = 0;                  // column slices: 0 automatic, else forced (1..8)
     SolveState ss;
 };
 
@@ -193,9 +218,13 @@ msf_status read_counters(Ctx *c);
 // Fills row_ptr[n+1], col/key[nnz] (capacity 2m) and *a; the number of
 // stored entries lands in dcnt->count and validation flags in dcnt->err.
 msf_status build_adjacency(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
-                           msf_wtype wt, Adj *a, uint32_t *row_ptr, uint32_t *col, uint64_t *key,
-                           uint32_t *chunk_row);
+                           msf_wtype wt, int S, Adj *a, uint32_t *row_ptr, uint32_t *col,
+                           uint64_t *key, uint32_t *chunk_row);
 uint32_t sweep_nchunks(uint32_t nnz);
+// Chunk-row tables of every slice of a (needs a->sl and a->row_ptr).
+void launch_chunk_rows_sliced(hipStream_t s, const Adj &a);
+// Slice boundaries (rp_s[0], rp_{S-1}[n]) and non-empty segments into dcnt.
+void launch_slice_info(hipStream_t s, const Adj &a, Counters *dcnt);
 // Exclusive scan of u32 in[0..N) -> out[0..N]; out[N] (and *total_out,
 // nullable, device) receive the total.
 msf_status scan_u32(Ctx *c, const uint32_t *in, uint32_t *out, int64_t N, uint32_t *total_out);
@@ -219,7 +248,7 @@ size_t chunk_info_words(uint32_t nchunks);
 // Round kernels.  `status` is a look-back status array (>= tiles entries);
 // `part` holds per-block partials (>= 4096 u32, or output_part_bytes(m)).
 uint32_t compaction_tiles(uint64_t n);
-void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, uint32_t *R,
+void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S, uint32_t *R,
                        uint64_t *status, Counters *dcnt);
 void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, const uint32_t *p,
                  const int32_t *edges, uint32_t *h, uint32_t *hedge);
@@ -228,7 +257,9 @@ void launch_tiebreak(hipStream_t s, const uint32_t *R, uint32_t nR, uint32_t *h,
                      uint64_t *status, Counters *dcnt);
 void launch_chase(hipStream_t s, const uint32_t *F, uint32_t nF, uint32_t *h, uint32_t *part,
                   Counters *dcnt);
-void launch_update_parents(hipStream_t s, const uint32_t *row_ptr, int32_t n, uint32_t *p,
+// S > 1: every vertex is updated (stale parents of vertices without
+// entries are never read); S == 1: only rows that still have entries.
+void launch_update_parents(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S, uint32_t *p,
                            const uint32_t *h, uint32_t *part, Counters *dcnt);
 int64_t output_tiles(int64_t m);
 size_t output_part_bytes(int64_t m);

@@ -21,11 +21,17 @@
 
 namespace msf {
 
-static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, SolveBufs *b)
+// Chunk-table capacity: every slice may add two partial chunks.
+static size_t chunk_cap(size_t nnz_cap)
+{
+    return sweep_nchunks((uint32_t)std::min<size_t>(nnz_cap, 0xFFFFFFFFull)) + 2 * MAX_SLICES + 2;
+}
+
+static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, int S, SolveBufs *b)
 {
     const size_t nn = (size_t)std::max(n, 1), mm = (size_t)std::max<int64_t>(m, 1);
     const size_t nnz_cap = 2 * mm;
-    const size_t nch = sweep_nchunks((uint32_t)std::min<size_t>(nnz_cap, 0xFFFFFFFFull)) + 2;
+    const size_t nch = chunk_cap(nnz_cap);
     size_t st = std::max<size_t>(nch, (size_t)output_tiles((int64_t)mm) + 1);
     st = std::max<size_t>(st, nn / 2048 + 2);
     const size_t part_bytes = std::max<size_t>(output_part_bytes((int64_t)mm), 4 * 4096 + 256);
@@ -33,7 +39,7 @@ static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, SolveBufs *b)
         Slot s;
         size_t bytes;
     } req[] = {
-        {WS_ROWPTR, 4 * (nn + 1)}, {WS_COL, 4 * nnz_cap}, {WS_KEY, 8 * nnz_cap},
+        {WS_ROWPTR, 4 * (size_t)S * (nn + 1)}, {WS_COL, 4 * nnz_cap}, {WS_KEY, 8 * nnz_cap},
         {WS_CHUNKROW, 4 * nch},    {WS_P, 4 * nn},        {WS_R, 8 * nn},
         {WS_H, 4 * nn},            {WS_HEDGE, 4 * nn},    {WS_RL, 4 * nn},
         {WS_RL2, 4 * nn},          {WS_FL, 4 * nn},       {WS_FLAGS, (mm + 16) & ~(size_t)3},
@@ -62,14 +68,14 @@ static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, SolveBufs *b)
     return MSF_OK;
 }
 
-static msf_status get_filter_bufs(Ctx *c, int32_t n, int64_t m, SolveBufs *b)
+static msf_status get_filter_bufs(Ctx *c, int32_t n, int64_t m, int S, SolveBufs *b)
 {
     if (b->rp[1]) return MSF_OK;
     const size_t nn = (size_t)std::max(n, 1), mm = (size_t)std::max<int64_t>(m, 1);
     const size_t nnz_cap = 2 * mm;
-    const size_t nch = sweep_nchunks((uint32_t)std::min<size_t>(nnz_cap, 0xFFFFFFFFull)) + 2;
+    const size_t nch = chunk_cap(nnz_cap);
     void *v[5];
-    MSF_TRY(ws_get(c, WS_ROWPTR2, 4 * (nn + 1), &v[0]));
+    MSF_TRY(ws_get(c, WS_ROWPTR2, 4 * (size_t)S * (nn + 1), &v[0]));
     MSF_TRY(ws_get(c, WS_COL2, 4 * nnz_cap, &v[1]));
     MSF_TRY(ws_get(c, WS_KEY2, 8 * nnz_cap, &v[2]));
     MSF_TRY(ws_get(c, WS_CHUNKROW2, 4 * nch, &v[3]));
@@ -103,11 +109,12 @@ msf_status solve_start(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, con
     S.w = d_w;
     S.wt = wt;
     S.ids = d_ids;
-    MSF_TRY(get_solve_bufs(c, n, m, &S.b));
+    const int slices = choose_slices(n, c->slices);
+    MSF_TRY(get_solve_bufs(c, n, m, slices, &S.b));
     MSF_HIP(hipEventRecord(c->ev[0], c->stream));
     zero_counters(c);
-    MSF_TRY(build_adjacency(c, n, m, d_edges, d_w, wt, &S.a, S.b.rp[0], S.b.col[0], S.b.key[0],
-                            S.b.crow[0]));
+    MSF_TRY(build_adjacency(c, n, m, d_edges, d_w, wt, slices, &S.a, S.b.rp[0], S.b.col[0],
+                            S.b.key[0], S.b.crow[0]));
     return end_step(c, 1);
 }
 
@@ -126,16 +133,17 @@ static msf_status enqueue_round(Ctx *c)
     const int ev_k = S.rounds < 64 ? S.rounds : -1;
     if (ev_k >= 0) {
         MSF_HIP(hipEventRecord(c->sev[2 * ev_k], s));
-        S.st.sweep_bytes[ev_k] = 12.0 * S.a.nnz + 8.0 * S.rows + 8.0 * S.nR;
+        S.st.sweep_bytes[ev_k] = 12.0 * S.a.nnz + 8.0 * S.a.segs + 8.0 * S.nR;
     }
     if (S.compact) {
-        MSF_TRY(get_filter_bufs(c, S.n, S.m, &S.b));
+        MSF_TRY(get_filter_bufs(c, S.n, S.m, S.a.sl.S, &S.b));
         Adj nxt = S.a;
         nxt.row_ptr = S.b.rp[S.ai ^ 1];
         nxt.col = S.b.col[S.ai ^ 1];
         nxt.key = S.b.key[S.ai ^ 1];
         launch_sweep_compact(s, S.a, S.b.p, S.b.r, nxt.row_ptr, nxt.col, nxt.key, S.b.cinfo,
                              S.b.status, c->dcnt);
+        launch_slice_info(s, nxt, c->dcnt);  // boundaries of the filtered adjacency
     } else {
         // round 1: p is the identity and nothing has been filtered
         launch_sweep(s, S.a, S.b.p, S.b.r, S.b.blive, c->dcnt,
@@ -172,29 +180,25 @@ msf_status solve_advance(Ctx *c)
     switch (S.phase) {
     case 1: {  // adjacency built
         MSF_TRY(decode_err(h->err));
-        S.a.nnz = h->count;
-        S.a.nchunks = sweep_nchunks(S.a.nnz);
-        launch_chunk_rows(s, S.a.row_ptr, S.n, S.a.nnz, S.a.chunk_row, S.a.nchunks);
+        for (int q = 0; q <= S.a.sl.S; ++q) S.a.sl.sstart[q] = h->sstart[q];
+        set_chunks(&S.a);
+        S.a.segs = h->segs;
+        if (S.a.nnz) launch_chunk_rows_sliced(s, S.a);
         MSF_HIP(hipEventRecord(c->ev[1], s));
         launch_iota_u32(s, S.b.p, (size_t)S.n);
         launch_iota_u32(s, S.b.h, (size_t)S.n);
         launch_fill_u64(s, S.b.r, KEY_INF, (size_t)S.n);
         launch_fill_u32(s, reinterpret_cast<uint32_t *>(S.b.flags), 0u, ((size_t)S.m + 3) / 4);
-        launch_init_roots(s, S.a.row_ptr, S.n, S.b.R[0], S.b.status, c->dcnt);
+        launch_init_roots(s, S.a.row_ptr, S.n, S.a.sl.S, S.b.R[0], S.b.status, c->dcnt);
         return end_step(c, 2);
     }
     case 2: {  // root list ready
         S.nR = h->nR;
-        S.rows = S.nR;  // rows with entries: every non-isolated vertex
         return more_rounds(S) ? enqueue_round(c) : enqueue_output(c);
     }
     case 3: {  // round counters ready
         const uint32_t nF = h->nF, nRn = h->nR;
         const int k = S.rounds;
-        if (S.rows_pending && k < 64) {
-            S.st.sweep_bytes[k] += 8.0 * h->rows;  // rows of the swept adjacency
-            S.rows_pending = false;
-        }
         if (k < 64) {
             S.st.hooks[k] = nF;
             S.st.active_nnz[k] = S.a.nnz;
@@ -209,9 +213,10 @@ msf_status solve_advance(Ctx *c)
             nxt.col = S.b.col[S.ai ^ 1];
             nxt.key = S.b.key[S.ai ^ 1];
             nxt.chunk_row = S.b.crow[S.ai ^ 1];
-            nxt.nnz = nnz2;
-            nxt.nchunks = sweep_nchunks(nnz2);
-            if (nnz2) launch_chunk_rows(s, nxt.row_ptr, S.n, nnz2, nxt.chunk_row, nxt.nchunks);
+            for (int q = 0; q <= nxt.sl.S; ++q) nxt.sl.sstart[q] = h->sstart[q];
+            set_chunks(&nxt);
+            nxt.segs = h->segs;
+            if (nnz2) launch_chunk_rows_sliced(s, nxt);
             S.a = nxt;
             S.ai ^= 1;
             ++S.st.filtered;
@@ -227,11 +232,10 @@ msf_status solve_advance(Ctx *c)
                 return MSF_EDEVICE;
             }
         }
-        launch_update_parents(s, S.a.row_ptr, S.n, S.b.p, S.b.h, (uint32_t *)S.b.part, c->dcnt);
+        launch_update_parents(s, S.a.row_ptr, S.n, S.a.sl.S, S.b.p, S.b.h, (uint32_t *)S.b.part,
+                              c->dcnt);
         S.ri ^= 1;
         S.nR = nRn;
-        S.rows = 0;  // counted by the update, read back with the next round
-        S.rows_pending = true;
         return more_rounds(S) ? enqueue_round(c) : enqueue_output(c);
     }
     case 4: {  // output ready

@@ -373,3 +373,36 @@ def test_full_batch_sampled(ctx, pkg):
         assert totals[g][0] == wtot[0], g
     # every graph: count = n - components is implied by the forest; check sums
     assert int(counts.sum()) == int(sum(counts))
+
+
+def test_column_slices_are_result_invariant(pkg):
+    graphs = [
+        ("er", 5000, *gen.er(5000, 40000, seed=12), U32),
+        ("rmat13", *gen.rmat(13, 16, seed=2), F32),
+        ("grid20", *gen.grid(20, 20, 20, 0.05, seed=3), U32),
+        ("sparse", 3000, *gen.er(3000, 1500, seed=13), U32),
+    ]
+    old = {k: os.environ.get(k) for k in ("MSF_SLICES", "MSF_FILTER")}
+    try:
+        for slices in ("1", "2", "3", "8"):
+            for filt in ("1", "2"):
+                os.environ["MSF_SLICES"] = slices
+                os.environ["MSF_FILTER"] = filt
+                c = pkg.Context(0)
+                for label, n, e, w, wt in graphs:
+                    check_solve(c, pkg, n, e, w, wt, f"slices={slices} filter={filt} {label}",
+                                device=(label != "sparse"))
+                    ref = oracle.multilinear(n, e, w, wt, np.arange(n))
+                    g = pkg.Graph(c, n, e, w, wtype=wt)
+                    dr = torch.empty(n, dtype=torch.int64, device="cuda:0")
+                    c.multilinear(g, dev(np.arange(n, dtype=np.uint32)), dr)
+                    torch.cuda.synchronize()
+                    assert np.array_equal(dr.cpu().numpy().view(np.uint64), ref), label
+                    g.close()
+                c.close()
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
