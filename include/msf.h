@@ -138,7 +138,7 @@ void msf_graph_destroy(msf_graph *g);
 
 /*
  * The multilinear kernel of section 3.1 fused with the projection of
- * Algorithm 2 (lines 9-10), for any parent vector p:
+ * Algorithm 2 (its multilinear kernel and projection), for any parent vector p:
  *   r[k] = min { key(e) : stored direction i->j of edge e, p[i] == k,
  *                         p[i] != p[j] },  UINT64_MAX where the set is empty,
  * with key(e) = (uint64_t)wkey(w_e) << 32 | e.

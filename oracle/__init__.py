@@ -17,7 +17,7 @@ Functions and what each follows
                      problem statement).  Plain Kruskal: a library sort of the
                      keys, then union-find in C (``oracle.c``).
 ``multilinear``      the all-at-once multilinear kernel of section 3.1 with
-                     the projection of Algorithm 2 (lines 9-10):
+                     the projection step of Algorithm 2:
                      r[k] = min{key(e) : stored direction i->j of e,
                      p[i] == k, p[i] != p[j]}, UINT64_MAX where none.
 ``find_roots``       complete shortcutting (section 4.2): every vertex ends at
@@ -185,7 +185,7 @@ def find_roots(p) -> np.ndarray:
 # ------------------------------------------------- Algorithm 2, by rounds --
 
 def as_rounds(n: int, edges, w, wtype: int, max_rounds: int = 1000):
-    """Algorithm 2 with complete shortcutting, one vectorised step per line.
+    """Algorithm 2 with complete shortcutting, one vectorised operation per step.
 
     Readings: vertices are 0-indexed and the empty EDGE is UINT64_MAX; the
     EDGE pair carries the edge id in place of the parent and the hook target

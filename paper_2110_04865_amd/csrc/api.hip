@@ -135,7 +135,7 @@ msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc)
     if (const char *f = getenv("MSF_FILTER")) c->filter_mode = atoi(f);
     if (const char *f = getenv("MSF_FILTER_THRESHOLD")) c->filter_threshold = atof(f);
     if (const char *f = getenv("MSF_CHECK_ROUNDS")) c->check_rounds = atoi(f) != 0;
-    if (const char *f = getenv("MSF_FIRST_ROUND")) c->first_round_kernel = atoi(f) != 0;
+    if (const char *f = getenv("MSF_FIRST_ROUND")) c->first_round = atoi(f);
     if (const char *f = getenv("MSF_BUCKETED_BUILD")) c->bucketed_build = atoi(f) != 0;
     if (const char *f = getenv("MSF_SLICES")) c->slices = atoi(f);
     return MSF_OK;
@@ -308,9 +308,9 @@ msf_status msf_graph_create(msf_ctx *ctx, int32_t n, int64_t m, const int32_t *e
     const size_t nn = (size_t)std::max(n, 1), mm = (size_t)std::max<int64_t>(m, 1);
     const size_t nch =
         sweep_nchunks((uint32_t)std::min<size_t>(2 * mm, 0xFFFFFFFFull)) + 2 * MAX_SLICES + 2;
-    const int slices = choose_slices(n, c->slices);
-    const size_t sizes[6] = {8 * mm, 4 * mm, 4 * (size_t)slices * (nn + 1), 4 * 2 * mm,
-                             8 * 2 * mm, 4 * nch};
+    const int slices = choose_slices(n, m, c->slices);
+    const size_t sizes[6] = {8 * mm, 4 * mm, 4 * (size_t)slices * (nn + 1),
+                             4 * (2 * mm + SWEEP_PAD), 8 * (2 * mm + SWEEP_PAD), 4 * nch};
     for (int i = 0; i < 6; ++i) {
         if (hipMalloc(&g->bufs[i], sizes[i]) != hipSuccess) {
             (void)hipGetLastError();
@@ -383,7 +383,7 @@ msf_status msf_multilinear(msf_ctx *ctx, const msf_graph *g, const uint32_t *p, 
     if (rc) return rc;
     if ((rc = decode_err(c->hcnt->err))) return rc;
     launch_fill_u64(c->stream, r, KEY_INF, (size_t)n);
-    launch_sweep(c->stream, g->a, p, r);
+    launch_sweep(c->stream, g->a, p, r, c->dcnt);
     MSF_HIP(hipGetLastError());
     return MSF_OK;
 }

@@ -186,11 +186,14 @@ __global__ void k_scatter(const int32_t *__restrict__ edges, const void *__restr
 
 uint32_t sweep_nchunks(uint32_t nnz) { return (nnz + SWEEP_CHUNK - 1) / SWEEP_CHUNK; }
 
-int choose_slices(int32_t n, int forced)
+int choose_slices(int32_t n, int64_t m, int forced)
 {
     if (forced >= 1) return forced > MAX_SLICES ? MAX_SLICES : forced;
-    // one L2 (4 MB) holds 2^20 parents; beyond that give each XCD a slice
-    return n >= (1 << 20) ? MAX_SLICES : 1;
+    // One L2 (4 MB) holds 2^20 parents; beyond that each XCD gets a slice of
+    // its own.  Slices cost S row pointers per vertex and cut rows into S
+    // segments, so they are kept for graphs with at least 16 stored entries
+    // per vertex; sparser graphs (grids, unions of small graphs) keep one.
+    return (n >= (1 << 20) && m >= 8 * (int64_t)n) ? MAX_SLICES : 1;
 }
 
 void set_chunks(Adj *a)
@@ -283,8 +286,10 @@ void launch_slice_info(hipStream_t s, const Adj &a, Counters *dcnt)
 //   B. the same blocks scatter both directions of each edge into their
 //      buckets (row offset in the bucket, column, key), ranked by LDS
 //      atomics;
-//   C. one workgroup per bucket counts its rows in LDS, scans them into
-//      row_ptr, and scatters the entries to their final positions.
+//   C. per bucket, a workgroup counts its rows in LDS, scans them into
+//      row_ptr, and scatters the entries to their final positions; in the
+//      solve, one workgroup takes all slices of a row block and also keeps
+//      the row minima that round 1 needs.
 // Every atomic is an LDS atomic, so a vertex of very high degree costs LDS
 // conflicts inside one workgroup instead of serialised device atomics.
 
@@ -374,51 +379,72 @@ __global__ __launch_bounds__(BKA_NT) void k_bucket_scatter(
     }
 }
 
+// Pass C.  Workgroup b serves row block rb = b % nbr and the slices
+// q = b / nbr, b / nbr + G, ... (G = grid / nbr): per slice, count the
+// rows in LDS, scan them into that slice's row_ptr, and place the entries.
+// MIN (grid = nbr, so one workgroup sees every slice of its rows) also
+// keeps each row's smallest key in LDS and stores it to r[row]: round 1 of
+// the multilinear sweep, where the parent vector is the identity and every
+// stored entry is outgoing, so its minima are a by-product of the build.
+template <bool MIN>
 __global__ __launch_bounds__(BKC_NT) void k_bucket_rows(
-    const uint32_t *__restrict__ bh_off, uint32_t nblk, int32_t n, int lb, int nb, uint32_t nbr,
+    const uint32_t *__restrict__ bh_off, uint32_t nblk, int32_t n, int lb, int S, uint32_t nbr,
     const uint16_t *__restrict__ rlo, const uint32_t *__restrict__ bcol,
     const uint64_t *__restrict__ bkey, uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ col,
-    uint64_t *__restrict__ key)
+    uint64_t *__restrict__ key, uint64_t *__restrict__ r)
 {
-    extern __shared__ uint32_t cnt[];  // 2^lb counters, then scan scratch
-    uint32_t *scr = cnt + (1u << lb);
-    const uint32_t b = blockIdx.x;
-    const uint32_t s = bh_off[(size_t)b * nblk];
-    const uint32_t e = bh_off[(size_t)(b + 1) * nblk];
+    extern __shared__ uint64_t lds64[];
     const uint32_t R = 1u << lb;
-    const uint32_t slice = b / nbr, rb = b - slice * nbr;
+    uint64_t *smin = lds64;                                      // R keys (MIN only)
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(lds64 + (MIN ? R : 0));  // R counters
+    uint32_t *scr = cnt + R;                                     // scan scratch
+    const uint32_t rb = blockIdx.x % nbr;
+    const uint32_t qstep = gridDim.x / nbr;
     const int64_t row0 = (int64_t)rb << lb;
-    row_ptr += (size_t)slice * ((size_t)n + 1);
     const uint32_t rows = (uint32_t)((int64_t)n - row0 < (int64_t)R ? (int64_t)n - row0 : R);
-    for (uint32_t i = threadIdx.x; i < R; i += BKC_NT) cnt[i] = 0;
-    __syncthreads();
-    for (uint32_t k = s + threadIdx.x; k < e; k += BKC_NT) atomicAdd(&cnt[rlo[k]], 1u);
-    __syncthreads();
-    // exclusive scan of the R counters: PER consecutive counters per thread
-    const uint32_t per = R / BKC_NT > 0 ? R / BKC_NT : 1;
-    const uint32_t i0 = threadIdx.x * per;
-    uint32_t run = 0;
-    if (i0 < R)
-        for (uint32_t j = 0; j < per; ++j) run += cnt[i0 + j];
-    uint32_t tot;
-    const uint32_t ex = block_excl_sum<BKC_NT>(run, scr, &tot);
-    if (i0 < R) {
-        uint32_t acc = ex;
-        for (uint32_t j = 0; j < per; ++j) {
-            const uint32_t c = cnt[i0 + j];
-            cnt[i0 + j] = acc;
-            acc += c;
+    if (MIN)
+        for (uint32_t i = threadIdx.x; i < R; i += BKC_NT) smin[i] = KEY_INF;
+    for (uint32_t q = blockIdx.x / nbr; q < (uint32_t)S; q += qstep) {
+        const uint32_t b = q * nbr + rb;
+        const uint32_t s = bh_off[(size_t)b * nblk];
+        const uint32_t e = bh_off[(size_t)(b + 1) * nblk];
+        uint32_t *rp = row_ptr + (size_t)q * ((size_t)n + 1);
+        for (uint32_t i = threadIdx.x; i < R; i += BKC_NT) cnt[i] = 0;
+        __syncthreads();
+        for (uint32_t k = s + threadIdx.x; k < e; k += BKC_NT) atomicAdd(&cnt[rlo[k]], 1u);
+        __syncthreads();
+        // exclusive scan of the R counters: PER consecutive counters per thread
+        const uint32_t per = R / BKC_NT > 0 ? R / BKC_NT : 1;
+        const uint32_t i0 = threadIdx.x * per;
+        uint32_t run = 0;
+        if (i0 < R)
+            for (uint32_t j = 0; j < per; ++j) run += cnt[i0 + j];
+        uint32_t tot;
+        const uint32_t ex = block_excl_sum<BKC_NT>(run, scr, &tot);
+        if (i0 < R) {
+            uint32_t acc = ex;
+            for (uint32_t j = 0; j < per; ++j) {
+                const uint32_t c = cnt[i0 + j];
+                cnt[i0 + j] = acc;
+                acc += c;
+            }
         }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < rows; i += BKC_NT) rp[row0 + i] = s + cnt[i];
+        if (rb == nbr - 1 && threadIdx.x == 0) rp[n] = e;
+        __syncthreads();
+        for (uint32_t k = s + threadIdx.x; k < e; k += BKC_NT) {
+            const uint32_t rl = rlo[k];
+            const uint64_t kk = bkey[k];
+            const uint32_t pos = s + atomicAdd(&cnt[rl], 1u);
+            col[pos] = bcol[k];
+            key[pos] = kk;
+            if (MIN) atomicMin((unsigned long long *)&smin[rl], (unsigned long long)kk);
+        }
+        __syncthreads();  // cnt is cleared for the next slice
     }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < rows; i += BKC_NT) row_ptr[row0 + i] = s + cnt[i];
-    if (rb == nbr - 1 && threadIdx.x == 0) row_ptr[n] = e;
-    __syncthreads();
-    for (uint32_t k = s + threadIdx.x; k < e; k += BKC_NT) {
-        const uint32_t pos = s + atomicAdd(&cnt[rlo[k]], 1u);
-        col[pos] = bcol[k];
-        key[pos] = bkey[k];
-    }
+    if (MIN)
+        for (uint32_t i = threadIdx.x; i < rows; i += BKC_NT) r[row0 + i] = smin[i];
 }
 
 // ---------------------------------------------------------------- host ---
@@ -452,9 +478,18 @@ static msf_status build_atomic(Ctx *c, int32_t n, int64_t m, const int32_t *d_ed
     return MSF_OK;
 }
 
+static size_t rows_lds(int lb, bool with_min)
+{
+    const size_t R = (size_t)1 << lb;
+    return (with_min ? 8 * R : 0) + 4 * R + 4 * (BKC_NT / 64 + 1);
+}
+
+template <bool MIN>
+static bool rows_lds_ok(int lb);
+
 static msf_status build_bucketed(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
                                  const void *d_w, msf_wtype wt, int lb, int S, uint32_t slice_w,
-                                 uint32_t *row_ptr, uint32_t *col, uint64_t *key)
+                                 uint32_t *row_ptr, uint32_t *col, uint64_t *key, uint64_t *r_first)
 {
     hipStream_t s = c->stream;
     const uint32_t nbr = (uint32_t)(((int64_t)n + (1ll << lb) - 1) >> lb);
@@ -488,24 +523,32 @@ static msf_status build_bucketed(Ctx *c, int32_t n, int64_t m, const int32_t *d_
         k_bucket_scatter<MSF_W_U32><<<nblk, BKA_NT, lds_a, s>>>(
             d_edges, d_w, m, n, lb, nb, slice_w, nbr, epb, nblk, bo, (uint16_t *)vrlo,
             (uint32_t *)vcol, (uint64_t *)vkey);
-    const size_t lds_c = 4 * ((size_t)1 << lb) + 4 * (BKC_NT / 64 + 1);
-    k_bucket_rows<<<nb, BKC_NT, lds_c, s>>>(bo, nblk, n, lb, nb, nbr, (const uint16_t *)vrlo,
-                                            (const uint32_t *)vcol, (const uint64_t *)vkey,
-                                            row_ptr, col, key);
+    if (r_first)
+        k_bucket_rows<true><<<nbr, BKC_NT, rows_lds(lb, true), s>>>(
+            bo, nblk, n, lb, S, nbr, (const uint16_t *)vrlo, (const uint32_t *)vcol,
+            (const uint64_t *)vkey, row_ptr, col, key, r_first);
+    else
+        k_bucket_rows<false><<<nb, BKC_NT, rows_lds(lb, false), s>>>(
+            bo, nblk, n, lb, S, nbr, (const uint16_t *)vrlo, (const uint32_t *)vcol,
+            (const uint64_t *)vkey, row_ptr, col, key, nullptr);
     MSF_HIP(hipGetLastError());
     return MSF_OK;
 }
 
-// Pass C needs 2^lb row counters in LDS; above 64 KB the kernel must be
-// allowed a larger dynamic LDS allocation, which is requested once.
-static bool bucket_lds_ok(int lb)
+// Pass C keeps 2^lb row counters (and with MIN 2^lb row minima) in LDS;
+// above 64 KB the kernel must be allowed a larger dynamic LDS allocation,
+// which is requested once per variant (at most the 160 KB of a CU).
+template <bool MIN>
+static bool rows_lds_ok(int lb)
 {
-    const size_t need = 4 * ((size_t)1 << lb) + 4 * (BKC_NT / 64 + 1);
+    const size_t need = rows_lds(lb, MIN);
     if (need <= 65536) return true;
     static int granted = -1;  // -1 unknown, else the granted byte count
     if (granted < 0) {
-        const int want = (int)(4 * ((size_t)1 << BK_MAX_LB) + 4 * (BKC_NT / 64 + 1));
-        granted = hipFuncSetAttribute((const void *)k_bucket_rows,
+        const size_t cap = 160 * 1024;
+        const size_t top = rows_lds(BK_MAX_LB, MIN);
+        const int want = (int)(top < cap ? top : cap);
+        granted = hipFuncSetAttribute((const void *)k_bucket_rows<MIN>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, want) ==
                           hipSuccess
                       ? want
@@ -517,13 +560,15 @@ static bool bucket_lds_ok(int lb)
 
 msf_status build_adjacency(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
                            msf_wtype wt, int S, Adj *a, uint32_t *row_ptr, uint32_t *col,
-                           uint64_t *key, uint32_t *chunk_row)
+                           uint64_t *key, uint32_t *chunk_row, uint64_t *r_first,
+                           bool *first_done)
 {
+    if (first_done) *first_done = false;
     launch_fill_u32(c->stream, &c->dcnt->err, 0u, 1);
     if (S < 1 || n < 32 * S) S = 1;
     int lb = bucket_bits(n, S);
     const bool bucketed = c->bucketed_build && m > 0 && n > 0 && lb <= BK_MAX_LB &&
-                          bucket_lds_ok(lb);
+                          rows_lds_ok<false>(lb);
     if (!bucketed) S = 1;  // the atomic fallback stores one slice
     uint32_t slice_w = (uint32_t)n;
     if (S > 1) slice_w = (uint32_t)((((int64_t)n + S - 1) / S + 31) & ~(int64_t)31);
@@ -531,7 +576,10 @@ msf_status build_adjacency(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
         launch_fill_u32(c->stream, row_ptr, 0u, (size_t)n + 1);
         launch_fill_u32(c->stream, &c->dcnt->count, 0u, 1);
     } else if (bucketed) {
-        MSF_TRY(build_bucketed(c, n, m, d_edges, d_w, wt, lb, S, slice_w, row_ptr, col, key));
+        const bool fuse = r_first && rows_lds_ok<true>(lb);
+        MSF_TRY(build_bucketed(c, n, m, d_edges, d_w, wt, lb, S, slice_w, row_ptr, col, key,
+                               fuse ? r_first : nullptr));
+        if (first_done) *first_done = fuse;
     } else {
         MSF_TRY(build_atomic(c, n, m, d_edges, d_w, wt, row_ptr, col, key));
     }

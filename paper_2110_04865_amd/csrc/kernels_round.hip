@@ -89,7 +89,7 @@ void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S,
 }
 
 // ---------------------------------------------------------------- hook --
-// Algorithm 2 line 11: root i takes the parent of the far endpoint of its
+// Hooking step of Algorithm 2: root i takes the parent of the far endpoint of its
 // minimum outgoing edge.  The EDGE pair carries the edge id; the target is
 // recovered from the edge's endpoints (exactly one of them is in i's star).
 // Writes go to h, never to p, so concurrent readers of p see one version.
@@ -124,7 +124,7 @@ void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, con
 }
 
 // ----------------------------------------------------------- tie break --
-// Algorithm 2 lines 12-14: a 2-cycle (i hooks on k and k on i) is the only
+// Tie-breaking step of Algorithm 2: a 2-cycle (i hooks on k and k on i) is the only
 // cycle hooking can form (section 2.3, with keys distinct); its smaller id
 // reverts to being a root and the larger keeps the hook, so the shared edge
 // enters the forest once.  Roots without an outgoing edge are finished for

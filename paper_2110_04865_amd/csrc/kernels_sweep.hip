@@ -1,5 +1,5 @@
 // The multilinear kernel of section 3.1 fused with the projection of
-// Algorithm 2 (lines 9-10), evaluated all-at-once: for every stored
+// Algorithm 2, evaluated all-at-once: for every stored
 // direction i->j with key k,
 //     f(p_i, a_ij, p_j) = k if p_i != p_j, else the empty key,
 // reduced with MinWeight (unsigned min of packed keys) over each run of
@@ -50,97 +50,72 @@ __device__ __forceinline__ RunAgg combine(const RunAgg &a, const RunAgg &b)
 
 }  // namespace
 
-// Rows of a chunk whose row_ptr/p windows are staged in LDS; chunks that
-// span more rows (long runs of empty rows) search global memory instead.
-constexpr int SWEEP_WIN = 2048;
+// Rows of a chunk staged in LDS (two per lane); a chunk that spans more
+// rows (long runs of rows without entries in its slice) searches row_ptr in
+// global memory instead.
+constexpr int SWEEP_WIN = 2 * SWEEP_BLOCK;
 
 // Chunk k of slice q covers entries [cb + k*CHUNK, cb + (k+1)*CHUNK) with
 // cb = sstart[q] rounded down to 4 entries (16-byte aligned loads); entries
 // outside [sstart[q], sstart[q+1]) belong to neighbouring slices and are
-// ignored.
+// ignored.  Geometry of global chunk c for this lane:
+struct ChunkGeom {
+    uint32_t q;       // slice
+    uint32_t lo, hi;  // first and last row the chunk touches
+    uint32_t base;    // first entry of this lane
+    int kb, ke;       // this lane's valid entries: [base + kb, base + ke)
+};
 
-// FIRST: the parent vector is the identity (round 1), so every stored entry
-// is outgoing, runs are rows, and no parent is read at all; with a single
-// slice a row that lies wholly inside one wave has a single writer and is
-// stored without an atomic.
-template <bool COMPACT, bool FIRST>
-__global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
-    const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
-    const uint64_t *__restrict__ key, const uint32_t *__restrict__ chunk_row, SliceInfo sl,
-    int32_t n, const uint32_t *__restrict__ p, uint64_t *__restrict__ r,
-    uint32_t *__restrict__ chunk_wpre, uint32_t *__restrict__ chunk_mask,
-    uint32_t *__restrict__ col_out, uint64_t *__restrict__ key_out, uint64_t *status,
-    Counters *cnt, uint32_t *block_live)
+__device__ __forceinline__ ChunkGeom chunk_geom(const SliceInfo &sl,
+                                                const uint32_t *__restrict__ chunk_row, uint32_t c)
 {
-    constexpr int E = SWEEP_E;
-    __shared__ uint32_t s_chunk;
-    __shared__ uint32_t s_lds[SWEEP_BLOCK / 64 + 1];
-    __shared__ uint64_t s_prefix;
-    __shared__ uint32_t s_rp[SWEEP_WIN + 1];
-    __shared__ uint32_t s_p[FIRST ? 1 : SWEEP_WIN];
-
-    // chunk c (all slices), slice q, chunk k inside the slice
-    uint32_t c, q = 0, k;
-    if (COMPACT) {
-        if (threadIdx.x == 0) s_chunk = atomicAdd(&cnt->ticket, 1u);
-        __syncthreads();
-        c = s_chunk;
-        while (q + 1 < (uint32_t)sl.S && c >= sl.cbase[q + 1]) ++q;
-        k = c - sl.cbase[q];
-    } else {
-        q = blockIdx.x % (uint32_t)sl.S;
-        k = blockIdx.x / (uint32_t)sl.S;
-        if (k >= sl.cbase[q + 1] - sl.cbase[q]) return;  // slice q has fewer chunks
-        c = sl.cbase[q] + k;
-    }
-    const uint32_t lane = __lane_id();
+    ChunkGeom g;
+    uint32_t q = 0;
+    while (q + 1 < (uint32_t)sl.S && c >= sl.cbase[q + 1]) ++q;
+    const uint32_t k = c - sl.cbase[q];
     const uint32_t s_lo = sl.sstart[q], s_hi = sl.sstart[q + 1];
-    const uint32_t cb = (s_lo & ~3u) + k * (uint32_t)SWEEP_CHUNK;
-    const uint32_t base = cb + threadIdx.x * E;
-    const uint32_t *__restrict__ rp = row_ptr + (size_t)q * ((size_t)n + 1);
-    const uint32_t *__restrict__ crow = chunk_row + sl.cbase[q] + q;
+    const uint32_t base = (s_lo & ~3u) + k * (uint32_t)SWEEP_CHUNK + threadIdx.x * SWEEP_E;
+    g.q = q;
+    g.base = base;
+    g.kb = base >= s_lo ? 0 : (int)(s_lo - base < (uint32_t)SWEEP_E ? s_lo - base : SWEEP_E);
+    g.ke = base >= s_hi ? 0 : (s_hi - base >= (uint32_t)SWEEP_E ? SWEEP_E : (int)(s_hi - base));
+    const uint32_t *crow = chunk_row + sl.cbase[q] + q;
+    g.lo = crow[k];
+    g.hi = crow[k + 1];
+    return g;
+}
 
-    // valid entries of this lane: [base + kb, base + ke)
-    const int kb = base >= s_lo ? 0 : (int)(s_lo - base < (uint32_t)E ? s_lo - base : E);
-    const int ke = base >= s_hi ? 0 : (s_hi - base >= (uint32_t)E ? E : (int)(s_hi - base));
-    const bool full = kb == 0 && ke == E;
-
-    // streamed loads first (non-temporal: read once per sweep)
-    uint32_t cl[E];
-    uint64_t ky[E];
-    if (full) {
-        const u32x4 c4 = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(col + base));
-        const u64x2 k01 = __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(key + base));
-        const u64x2 k23 =
-            __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(key + base + 2));
-        cl[0] = c4.x; cl[1] = c4.y; cl[2] = c4.z; cl[3] = c4.w;
-        ky[0] = k01.x; ky[1] = k01.y; ky[2] = k23.x; ky[3] = k23.y;
-    } else {
+// Streamed entry loads (non-temporal: each entry is read once per sweep).
+// The lane's whole 4-entry group is always loaded (the arrays are padded),
+// so the number of loads does not depend on the chunk; entries outside
+// [kb, ke) are masked to column 0 / the empty key.
+__device__ __forceinline__ void load_entries(const uint32_t *__restrict__ col,
+                                             const uint64_t *__restrict__ key, const ChunkGeom &g,
+                                             uint32_t (&cl)[SWEEP_E], uint64_t (&ky)[SWEEP_E])
+{
+    const u32x4 c4 = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(col + g.base));
+    const u64x2 k01 = __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(key + g.base));
+    const u64x2 k23 =
+        __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(key + g.base + 2));
+    const uint32_t cv[SWEEP_E] = {c4.x, c4.y, c4.z, c4.w};
+    const uint64_t kv[SWEEP_E] = {k01.x, k01.y, k23.x, k23.y};
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const bool v = e >= kb && e < ke;
-            cl[e] = v ? col[base + e] : 0u;
-            ky[e] = v ? key[base + e] : KEY_INF;
-        }
+    for (int e = 0; e < SWEEP_E; ++e) {
+        const bool v = e >= g.kb && e < g.ke;
+        cl[e] = v ? cv[e] : 0u;
+        ky[e] = v ? kv[e] : KEY_INF;
     }
-    // window of rows touched by this chunk
-    const uint32_t lo = crow[k];
-    const uint32_t hi = crow[k + 1];
-    const uint32_t nrows = hi - lo + 1;
-    const bool win = nrows + 1 <= (uint32_t)SWEEP_WIN;
-    if (win) {
-        for (uint32_t t = threadIdx.x; t <= nrows; t += SWEEP_BLOCK) {
-            s_rp[t] = rp[lo + t];
-            if (!FIRST && t < nrows) s_p[t] = p[lo + t];
-        }
-    }
-    // column parents: independent of the row search, issued before it
-    uint32_t pc[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) pc[e] = (!FIRST && e >= kb && e < ke) ? p[cl[e]] : 0u;
-    __syncthreads();
+}
 
-    auto rp_at = [&](uint32_t rw) -> uint32_t { return win ? s_rp[rw - lo] : rp[rw]; };
+// Root of the row of each of this lane's valid entries: rows are found by
+// binary search over row_ptr values rp_at(lo..hi+1) (one search for the
+// first entry, further ones only where a row ends); FIRST: the root is the
+// row itself, otherwise p_row(row).
+template <bool FIRST, typename RpAt, typename PRow>
+__device__ __forceinline__ void entry_roots(RpAt rp_at, PRow p_row, uint32_t lo, uint32_t hi,
+                                            uint32_t base, int kb, int ke,
+                                            uint32_t (&root)[SWEEP_E])
+{
     auto search = [&](uint32_t a, uint32_t b, uint32_t idx) -> uint32_t {
         while (a < b) {
             const uint32_t mid = a + ((b - a + 1) >> 1);
@@ -149,45 +124,149 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
         }
         return a;
     };
+    uint32_t row = search(lo, hi, base + kb);
+    uint32_t nx = rp_at(row + 1);
+    uint32_t prow = FIRST ? row : p_row(row);
+#pragma unroll
+    for (int e = 0; e < SWEEP_E; ++e) {
+        const uint32_t idx = base + e;
+        if (e >= kb && e < ke) {
+            if (idx >= nx) {
+                row = search(row + 1, hi, idx);
+                nx = rp_at(row + 1);
+                prow = FIRST ? row : p_row(row);
+            }
+            root[e] = prow;
+        }
+    }
+}
 
+// The same from global memory, for chunks whose rows exceed the LDS window.
+// Kept out of line: merged with the LDS variant, the compiler would select
+// between an LDS and a global pointer and load through the generic address
+// space.
+template <bool FIRST>
+__device__ __attribute__((noinline)) u32x4 entry_roots_global(const uint32_t *__restrict__ rp,
+                                                              const uint32_t *__restrict__ p,
+                                                              uint32_t lo, uint32_t hi,
+                                                              uint32_t base, int kb, int ke)
+{
+    uint32_t root[SWEEP_E] = {NONE32, NONE32, NONE32, NONE32};
+    entry_roots<FIRST>([&](uint32_t rw) { return rp[rw]; }, [&](uint32_t rw) { return p[rw]; },
+                       lo, hi, base, kb, ke, root);
+    return u32x4{root[0], root[1], root[2], root[3]};
+}
+
+// FIRST: the parent vector is the identity (round 1), so every stored entry
+// is outgoing, runs are rows, and no parent is read at all; with a single
+// slice a row that lies wholly inside one wave has a single writer and is
+// stored without an atomic.
+//
+// One chunk per workgroup.  Plain sweep: workgroup b serves chunk b / S of
+// slice b % S (workgroups are dealt to the XCDs round-robin, so a slice's
+// parents stay in one XCD's L2).  Compacting sweep: chunks are taken by
+// ticket in increasing order, so every chunk an earlier one waits on in the
+// look-back is held by a running workgroup.
+template <bool COMPACT, bool FIRST>
+__global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
+    const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
+    const uint64_t *__restrict__ key, const uint32_t *__restrict__ chunk_row, SliceInfo sl,
+    int32_t n, const uint32_t *__restrict__ p, uint64_t *__restrict__ r,
+    uint32_t *__restrict__ chunk_wpre, uint32_t *__restrict__ chunk_mask,
+    uint32_t *__restrict__ col_out, uint64_t *__restrict__ key_out, uint64_t *status,
+    Counters *cnt, uint32_t *__restrict__ wave_live)
+{
+    constexpr int E = SWEEP_E;
+    __shared__ uint32_t s_ticket;
+    __shared__ uint32_t s_lds[SWEEP_BLOCK / 64 + 1];
+    __shared__ uint64_t s_prefix;
+    __shared__ uint32_t s_rp[SWEEP_WIN + 1];
+    __shared__ uint32_t s_p[FIRST ? 1 : SWEEP_WIN];
+
+    const uint32_t lane = __lane_id();
+    const uint32_t S = (uint32_t)sl.S;
+    const uint32_t total = sl.cbase[S];
+    uint32_t c;
+    if (COMPACT) {
+        if (threadIdx.x == 0) s_ticket = atomicAdd(&cnt->ticket, 1u);
+        __syncthreads();
+        c = s_ticket;
+    } else {
+        const uint32_t q = blockIdx.x % S, k = blockIdx.x / S;
+        if (k >= sl.cbase[q + 1] - sl.cbase[q]) return;  // slice q has fewer chunks
+        c = sl.cbase[q] + k;
+    }
+
+    // 1. entries, row window and column parents.  Every load is issued
+    //    unconditionally (indices clamped in bounds), so the compiler's count
+    //    of outstanding loads stays exact and no wait covers more than the
+    //    loads it needs.
+    const ChunkGeom g = chunk_geom(sl, chunk_row, c);
+    uint32_t cl[E];
+    uint64_t ky[E];
+    load_entries(col, key, g, cl, ky);
+    const uint32_t *__restrict__ rp = row_ptr + (size_t)g.q * ((size_t)n + 1);
+    const uint32_t lo = g.lo, hi = g.hi;
+    const uint32_t nrows = hi - lo + 1;
+    const bool win = nrows <= (uint32_t)SWEEP_WIN;
+    const int kb = g.kb, ke = g.ke;
+    const uint32_t base = g.base;
+    const uint32_t t0 = threadIdx.x, t1 = threadIdx.x + SWEEP_BLOCK;
+    const uint32_t wr0 = rp[lo + min(t0, nrows)];
+    const uint32_t wr1 = rp[lo + min(t1, nrows)];
+    const uint32_t wr2 = rp[lo + min((uint32_t)SWEEP_WIN, nrows)];
+    uint32_t wp0 = 0, wp1 = 0;
+    if (!FIRST) {
+        wp0 = p[lo + min(t0, nrows - 1)];
+        wp1 = p[lo + min(t1, nrows - 1)];
+    }
+    uint32_t pc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) pc[e] = FIRST ? 0u : p[cl[e]];
+
+    // 2. stage the window
+    if (win) {
+        if (t0 <= nrows) s_rp[t0] = wr0;
+        if (t1 <= nrows) s_rp[t1] = wr1;
+        if (t0 == 0 && nrows == (uint32_t)SWEEP_WIN) s_rp[SWEEP_WIN] = wr2;
+        if (!FIRST) {
+            if (t0 < nrows) s_p[t0] = wp0;
+            if (t1 < nrows) s_p[t1] = wp1;
+        }
+    }
+    __syncthreads();
+
+    // 3. the root of every entry's row, then runs
     uint32_t root[E];
     uint64_t cand[E];
     bool live[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        live[e] = false;
-        cand[e] = KEY_INF;
-        root[e] = NONE32;
-    }
+    for (int e = 0; e < E; ++e) root[e] = NONE32;
     if (ke > kb) {
-        uint32_t row = search(lo, hi, base + kb);
-        uint32_t nxt = rp_at(row + 1);
-        uint32_t prow = FIRST ? row : (win ? s_p[row - lo] : p[row]);
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const uint32_t idx = base + e;
-            if (e >= kb && e < ke) {
-                if (idx >= nxt) {
-                    row = search(row + 1, hi, idx);
-                    nxt = rp_at(row + 1);
-                    prow = FIRST ? row : (win ? s_p[row - lo] : p[row]);
-                }
-                live[e] = FIRST ? true : (prow != pc[e]);
-                cand[e] = live[e] ? ky[e] : KEY_INF;
-                root[e] = prow;
-            }
+        if (win) {
+            entry_roots<FIRST>([&](uint32_t rw) { return s_rp[rw - lo]; },
+                               [&](uint32_t rw) { return s_p[rw - lo]; }, lo, hi, base, kb, ke,
+                               root);
+        } else {
+            const u32x4 v = entry_roots_global<FIRST>(rp, p, lo, hi, base, kb, ke);
+            root[0] = v.x; root[1] = v.y; root[2] = v.z; root[3] = v.w;
         }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        live[e] = e >= kb && e < ke && (FIRST || root[e] != pc[e]);
+        cand[e] = live[e] ? ky[e] : KEY_INF;
     }
 
     // flush one run's minimum: in round 1 with one slice, a row wholly
-    // inside this wave's entries has no other writer; everything else goes
-    // through the atomic
+    // inside this wave's entries (known from the staged window) has no
+    // other writer; everything else goes through the atomic
     const uint32_t wave_lo = base - lane * E;
     const uint32_t wave_hi = wave_lo + 64 * E;  // exclusive
     auto flush = [&](uint32_t rt, uint64_t v) {
-        if (FIRST && sl.S == 1) {
+        if (FIRST && S == 1 && win) {
             if (v == KEY_INF) return;
-            if (rp_at(rt) >= wave_lo && rp_at(rt + 1) <= wave_hi) r[rt] = v;
+            if (s_rp[rt - lo] >= wave_lo && s_rp[rt + 1 - lo] <= wave_hi) r[rt] = v;
             else min_into(r, rt, v);
         } else {
             min_into(r, rt, v);
@@ -251,10 +330,11 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     for (int e = 0; e < E; ++e) lcnt += live[e] ? 1u : 0u;
 
     if (!COMPACT) {
-        if (block_live) {  // live-entry count of this chunk (filtering policy)
-            uint32_t btot;
-            block_excl_sum<SWEEP_BLOCK>(lcnt, s_lds, &btot);
-            if (threadIdx.x == 0) block_live[c] = btot;
+        // live entries of this sweep (filtering policy): one count per wave,
+        // summed by k_reduce_live (atomics on one counter would serialise)
+        if (wave_live) {
+            const uint32_t ws = wave_sum(lcnt);
+            if (lane == 0) wave_live[(size_t)c * (SWEEP_BLOCK / 64) + threadIdx.x / 64] = ws;
         }
         return;
     }
@@ -263,14 +343,14 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     uint32_t btot;
     const uint32_t lex = block_excl_sum<SWEEP_BLOCK>(lcnt, s_lds, &btot);
     if (threadIdx.x < 64) {
-        const uint64_t e = lookback(status, c, (uint64_t)btot);
-        if (threadIdx.x == 0) s_prefix = e;
+        const uint64_t ex = lookback(status, c, (uint64_t)btot);
+        if (threadIdx.x == 0) s_prefix = ex;
     }
     __syncthreads();
     const uint64_t P = s_prefix;
     uint32_t pos = (uint32_t)P + lex;
-    // survivor bitmask and per-32-entry prefix of this chunk: the output
-    // row pointers are derived from them by k_rowptr_compact
+    // survivor bitmask and per-32-entry prefix of this chunk: the output row
+    // pointers are derived from them by k_rowptr_compact
     uint32_t nib = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) nib |= (live[e] ? 1u : 0u) << e;
@@ -291,7 +371,7 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
             ++pos;
         }
     }
-    if (c == sl.cbase[sl.S] - 1 && threadIdx.x == 0) cnt->nnz_out = (uint32_t)(P + btot);
+    if (c == total - 1 && threadIdx.x == 0) cnt->nnz_out = (uint32_t)(P + btot);
 }
 
 // Output row pointers of a compaction: rp'_q[i] = survivors stored before
@@ -320,35 +400,35 @@ __global__ void k_rowptr_compact(const uint32_t *__restrict__ row_ptr, int32_t n
     }
 }
 
-__global__ void k_reduce_live(const uint32_t *__restrict__ block_live, uint32_t nchunks,
+__global__ void k_reduce_live(const uint32_t *__restrict__ wave_live, size_t count,
                               Counters *cnt)
 {
-    uint64_t s = 0;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nchunks;
-         i += gridDim.x * blockDim.x)
-        s += block_live[i];
-    s = wave_sum(s);
-    if (__lane_id() == 0 && s) atomicAdd((unsigned long long *)&cnt->live, (unsigned long long)s);
+    __shared__ uint64_t s_lds[256 / 64 + 1];
+    uint64_t v = 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (size_t)gridDim.x * blockDim.x)
+        v += wave_live[i];
+    v = block_sum<256>(v, s_lds);
+    if (threadIdx.x == 0 && v) atomicAdd((unsigned long long *)&cnt->live, (unsigned long long)v);
 }
 
-void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
-                  uint32_t *block_live, Counters *dcnt, bool first)
+void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r, Counters *dcnt,
+                  bool first, uint32_t *wave_live)
 {
     if (a.nnz == 0) return;
-    const unsigned grid = a.sl.maxch * (unsigned)a.sl.S;  // slice = block % S
+    const unsigned grid = a.sl.maxch * (unsigned)a.sl.S;  // slice = workgroup % S
     if (first)
         k_sweep<false, true><<<grid, SWEEP_BLOCK, 0, s>>>(
             a.row_ptr, a.col, a.key, a.chunk_row, a.sl, a.n, p, r, nullptr, nullptr, nullptr,
-            nullptr, nullptr, nullptr, block_live);
+            nullptr, nullptr, dcnt, wave_live);
     else
         k_sweep<false, false><<<grid, SWEEP_BLOCK, 0, s>>>(
             a.row_ptr, a.col, a.key, a.chunk_row, a.sl, a.n, p, r, nullptr, nullptr, nullptr,
-            nullptr, nullptr, nullptr, block_live);
-    if (block_live && dcnt) {
+            nullptr, nullptr, dcnt, wave_live);
+    if (wave_live) {
         launch_fill_u64(s, &dcnt->live, 0ull, 1);
-        unsigned g = (a.nchunks + 255) / 256;
-        if (g > 64) g = 64;
-        k_reduce_live<<<g, 256, 0, s>>>(block_live, a.nchunks, dcnt);
+        const size_t count = (size_t)a.nchunks * (SWEEP_BLOCK / 64);
+        k_reduce_live<<<64, 256, 0, s>>>(wave_live, count, dcnt);
     }
 }
 

@@ -32,6 +32,10 @@ constexpr uint32_t NONE32 = 0xFFFFFFFFu;
 constexpr int SWEEP_BLOCK = 256;
 constexpr int SWEEP_E = 4;
 constexpr int SWEEP_CHUNK = SWEEP_BLOCK * SWEEP_E;
+// Column/key arrays are allocated SWEEP_PAD entries beyond their capacity:
+// the sweep loads whole 4-entry groups past the last stored entry (without
+// a branch, so the compiler can count outstanding loads exactly).
+constexpr size_t SWEEP_PAD = SWEEP_CHUNK;
 
 // Device error flags raised by validation kernels.
 enum : uint32_t { ERR_ENDPOINT = 1u, ERR_NAN = 2u, ERR_PARENT = 4u, ERR_CYCLE = 8u };
@@ -82,7 +86,7 @@ enum Slot {
     WS_EDGES, WS_W, WS_SLOT, WS_DEG, WS_ROWPTR, WS_COL, WS_KEY, WS_CHUNKROW,
     WS_ROWPTR2, WS_COL2, WS_KEY2, WS_CHUNKROW2,
     WS_P, WS_R, WS_H, WS_HEDGE, WS_RL, WS_RL2, WS_FL, WS_FLAGS, WS_IDS,
-    WS_STATUS, WS_SCRATCH, WS_PART, WS_Q, WS_Q2,
+    WS_STATUS, WS_WLIVE, WS_PART, WS_Q, WS_Q2,
     WS_BATCH0, WS_BATCH1, WS_BATCH2, WS_BATCH3,
     WS_BH, WS_BHOFF, WS_BRLO, WS_BCOL, WS_BKEY, WS_CHUNKINFO,
     WS_COUNT
@@ -107,11 +111,10 @@ struct Counters {
     uint32_t rows;        // rows with stored entries (counted by update)
     uint32_t segs;        // non-empty (row, slice) segments of an adjacency
     uint32_t sstart[MAX_SLICES + 1];  // slice boundaries of an adjacency
-    uint32_t pad_;
 };
 
 struct SolveBufs {
-    uint32_t *rp[2], *col[2], *crow[2], *p, *h, *hedge, *R[2], *F, *blive, *cinfo;
+    uint32_t *rp[2], *col[2], *crow[2], *p, *h, *hedge, *R[2], *F, *wlive, *cinfo;
     uint64_t *key[2], *r, *status;
     uint8_t *flags;
     void *part;
@@ -149,7 +152,7 @@ struct Adj {
 };
 
 // Slice count for n vertices (columns sliced once p outgrows one L2).
-int choose_slices(int32_t n, int forced);
+int choose_slices(int32_t n, int64_t m, int forced);
 // Fill the chunk layout of a from sl.sstart (host values).
 void set_chunks(Adj *a);
 
@@ -165,6 +168,7 @@ struct SolveState {
     Adj a;
     uint32_t nR = 0, rows = 0;
     bool rows_pending = false, compact = false;
+    bool first_done = false;  // the build wrote round 1's minima into r
     int ri = 0, ai = 0, rounds = 0;
     double live_frac = 1.0;
     msf_stats st{};
@@ -183,7 +187,9 @@ struct Ctx {
     int filter_mode = 1;        // 0 never, 1 adaptive, 2 every round
     double filter_threshold = 0.80;
     bool check_rounds = false;  // read back error flags after every shortcut
-    bool first_round_kernel = true;  // identity-parent sweep in round 1
+    // round 1: 0 generic sweep, 1 identity-parent sweep, 2 row minima
+    // written by the adjacency build (falls back to 1 where it cannot)
+    int first_round = 2;
     bool bucketed_build = true;      // LDS-only adjacency build
     int slices = 0;                  // column slices: 0 automatic, else forced (1..8)
     SolveState ss;
@@ -217,9 +223,12 @@ msf_status read_counters(Ctx *c);
 // Adjacency build (section 2 adjacency matrix, both directions).
 // Fills row_ptr[n+1], col/key[nnz] (capacity 2m) and *a; the number of
 // stored entries lands in dcnt->count and validation flags in dcnt->err.
+// With r_first, the build may also store every row's smallest key into
+// r_first[n] (round 1 of the sweep); *first_done says whether it did.
 msf_status build_adjacency(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
                            msf_wtype wt, int S, Adj *a, uint32_t *row_ptr, uint32_t *col,
-                           uint64_t *key, uint32_t *chunk_row);
+                           uint64_t *key, uint32_t *chunk_row, uint64_t *r_first = nullptr,
+                           bool *first_done = nullptr);
 uint32_t sweep_nchunks(uint32_t nnz);
 // Chunk-row tables of every slice of a (needs a->sl and a->row_ptr).
 void launch_chunk_rows_sliced(hipStream_t s, const Adj &a);
@@ -235,8 +244,10 @@ void launch_chunk_rows(hipStream_t s, const uint32_t *row_ptr, int32_t n, uint32
 void launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t v, size_t n);
 void launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, size_t n);
 void launch_iota_u32(hipStream_t s, uint32_t *p, size_t n);
-void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
-                  uint32_t *block_live = nullptr, Counters *dcnt = nullptr, bool first = false);
+// With wave_live (SWEEP_BLOCK/64 u32 per chunk), dcnt->live receives the
+// number of live entries (p_i != p_j).
+void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r, Counters *dcnt,
+                  bool first = false, uint32_t *wave_live = nullptr);
 // Sweep that also writes the surviving entries (p_i != p_j) in order to
 // col_out/key_out and their row pointers to row_ptr_out; chunk_info holds
 // chunk_info_words(a.nchunks) u32 of per-chunk survivor masks and prefixes.

@@ -39,11 +39,13 @@ static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, int S, SolveBufs 
         Slot s;
         size_t bytes;
     } req[] = {
-        {WS_ROWPTR, 4 * (size_t)S * (nn + 1)}, {WS_COL, 4 * nnz_cap}, {WS_KEY, 8 * nnz_cap},
+        {WS_ROWPTR, 4 * (size_t)S * (nn + 1)}, {WS_COL, 4 * (nnz_cap + SWEEP_PAD)},
+        {WS_KEY, 8 * (nnz_cap + SWEEP_PAD)},
         {WS_CHUNKROW, 4 * nch},    {WS_P, 4 * nn},        {WS_R, 8 * nn},
         {WS_H, 4 * nn},            {WS_HEDGE, 4 * nn},    {WS_RL, 4 * nn},
         {WS_RL2, 4 * nn},          {WS_FL, 4 * nn},       {WS_FLAGS, (mm + 16) & ~(size_t)3},
-        {WS_STATUS, 8 * st},       {WS_SCRATCH, 4 * nch}, {WS_PART, part_bytes},
+        {WS_STATUS, 8 * st},       {WS_WLIVE, 4 * (SWEEP_BLOCK / 64) * nch},
+        {WS_PART, part_bytes},
     };
     void *v[sizeof(req) / sizeof(req[0])];
     for (size_t i = 0; i < sizeof(req) / sizeof(req[0]); ++i)
@@ -61,7 +63,7 @@ static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, int S, SolveBufs 
     b->F = (uint32_t *)v[10];
     b->flags = (uint8_t *)v[11];
     b->status = (uint64_t *)v[12];
-    b->blive = (uint32_t *)v[13];
+    b->wlive = (uint32_t *)v[13];
     b->part = v[14];
     b->rp[1] = b->col[1] = b->crow[1] = nullptr;
     b->key[1] = nullptr;
@@ -76,8 +78,8 @@ static msf_status get_filter_bufs(Ctx *c, int32_t n, int64_t m, int S, SolveBufs
     const size_t nch = chunk_cap(nnz_cap);
     void *v[5];
     MSF_TRY(ws_get(c, WS_ROWPTR2, 4 * (size_t)S * (nn + 1), &v[0]));
-    MSF_TRY(ws_get(c, WS_COL2, 4 * nnz_cap, &v[1]));
-    MSF_TRY(ws_get(c, WS_KEY2, 8 * nnz_cap, &v[2]));
+    MSF_TRY(ws_get(c, WS_COL2, 4 * (nnz_cap + SWEEP_PAD), &v[1]));
+    MSF_TRY(ws_get(c, WS_KEY2, 8 * (nnz_cap + SWEEP_PAD), &v[2]));
     MSF_TRY(ws_get(c, WS_CHUNKROW2, 4 * nch, &v[3]));
     MSF_TRY(ws_get(c, WS_CHUNKINFO, 4 * chunk_info_words((uint32_t)nch), &v[4]));
     b->cinfo = (uint32_t *)v[4];
@@ -109,12 +111,13 @@ msf_status solve_start(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, con
     S.w = d_w;
     S.wt = wt;
     S.ids = d_ids;
-    const int slices = choose_slices(n, c->slices);
+    const int slices = choose_slices(n, m, c->slices);
     MSF_TRY(get_solve_bufs(c, n, m, slices, &S.b));
     MSF_HIP(hipEventRecord(c->ev[0], c->stream));
     zero_counters(c);
     MSF_TRY(build_adjacency(c, n, m, d_edges, d_w, wt, slices, &S.a, S.b.rp[0], S.b.col[0],
-                            S.b.key[0], S.b.crow[0]));
+                            S.b.key[0], S.b.crow[0], c->first_round == 2 ? S.b.r : nullptr,
+                            &S.first_done));
     return end_step(c, 1);
 }
 
@@ -133,7 +136,9 @@ static msf_status enqueue_round(Ctx *c)
     const int ev_k = S.rounds < 64 ? S.rounds : -1;
     if (ev_k >= 0) {
         MSF_HIP(hipEventRecord(c->sev[2 * ev_k], s));
-        S.st.sweep_bytes[ev_k] = 12.0 * S.a.nnz + 8.0 * S.a.segs + 8.0 * S.nR;
+        S.st.sweep_bytes[ev_k] = (S.rounds == 0 && S.first_done)
+                                     ? 0.0
+                                     : 12.0 * S.a.nnz + 8.0 * S.a.segs + 8.0 * S.nR;
     }
     if (S.compact) {
         MSF_TRY(get_filter_bufs(c, S.n, S.m, S.a.sl.S, &S.b));
@@ -144,10 +149,13 @@ static msf_status enqueue_round(Ctx *c)
         launch_sweep_compact(s, S.a, S.b.p, S.b.r, nxt.row_ptr, nxt.col, nxt.key, S.b.cinfo,
                              S.b.status, c->dcnt);
         launch_slice_info(s, nxt, c->dcnt);  // boundaries of the filtered adjacency
+    } else if (S.rounds == 0 && S.first_done) {
+        // round 1's minima were written by the build; every entry is live
+        launch_fill_u64(s, &c->dcnt->live, (uint64_t)S.a.nnz, 1);
     } else {
         // round 1: p is the identity and nothing has been filtered
-        launch_sweep(s, S.a, S.b.p, S.b.r, S.b.blive, c->dcnt,
-                     S.rounds == 0 && c->first_round_kernel);
+        launch_sweep(s, S.a, S.b.p, S.b.r, c->dcnt, S.rounds == 0 && c->first_round >= 1,
+                     S.b.wlive);
     }
     if (ev_k >= 0) MSF_HIP(hipEventRecord(c->sev[2 * ev_k + 1], s));
     launch_hook(s, S.b.R[S.ri], S.nR, S.b.r, S.b.p, S.edges, S.b.h, S.b.hedge);
@@ -187,7 +195,7 @@ msf_status solve_advance(Ctx *c)
         MSF_HIP(hipEventRecord(c->ev[1], s));
         launch_iota_u32(s, S.b.p, (size_t)S.n);
         launch_iota_u32(s, S.b.h, (size_t)S.n);
-        launch_fill_u64(s, S.b.r, KEY_INF, (size_t)S.n);
+        if (!S.first_done) launch_fill_u64(s, S.b.r, KEY_INF, (size_t)S.n);
         launch_fill_u32(s, reinterpret_cast<uint32_t *>(S.b.flags), 0u, ((size_t)S.m + 3) / 4);
         launch_init_roots(s, S.a.row_ptr, S.n, S.a.sl.S, S.b.R[0], S.b.status, c->dcnt);
         return end_step(c, 2);

@@ -406,3 +406,35 @@ def test_column_slices_are_result_invariant(pkg):
                 os.environ.pop(k, None)
             else:
                 os.environ[k] = v
+
+
+def test_first_round_modes_agree(pkg):
+    """Round 1 from the generic sweep (0), the identity-parent sweep (1) and
+    the minima kept by the adjacency build (2) give the same forest, with one
+    and with eight column slices; the 8.5M-vertex grid under eight slices
+    needs 8192-row blocks, whose build keeps 96 KB of LDS."""
+    graphs = [
+        ("er", 5000, *gen.er(5000, 40000, seed=21), U32),
+        ("rmat14", *gen.rmat(14, 16, seed=22), F32),
+        ("grid12", *gen.grid(12, 12, 12, 0.05, seed=23), U32),
+    ]
+    big = ("grid204", *gen.grid(204, 204, 204, 0.05, seed=24), U32)
+    old = {k: os.environ.get(k) for k in ("MSF_SLICES", "MSF_FIRST_ROUND")}
+    try:
+        for slices in ("1", "8"):
+            for first in ("0", "1", "2"):
+                os.environ["MSF_SLICES"] = slices
+                os.environ["MSF_FIRST_ROUND"] = first
+                c = pkg.Context(0)
+                cases = graphs + ([big] if (slices, first) in (("8", "2"), ("1", "2")) else [])
+                for label, n, e, w, wt in cases:
+                    check_solve(c, pkg, n, e, w, wt, f"slices={slices} first={first} {label}")
+                    if first == "2":  # no sweep in round 1
+                        assert c.stats()["sweep_bytes"][0] == 0, label
+                c.close()
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v

@@ -355,7 +355,7 @@ def test_grid_weights_sum_exactly():
 # ---------------------------------------------------------- multilinear --
 
 def dense_two_step(n, edges, keys, p):
-    """Algorithm 2 lines 9-10 over a dense adjacency matrix of keys:
+    """The multilinear kernel and projection of Algorithm 2 over a dense adjacency matrix of keys:
     q_i = min_j f(p_i, a_ij, p_j) with f = a_ij iff p_i != p_j, then
     r_k = min{q_i : p_i = k}."""
     INF = (1 << 64) - 1
