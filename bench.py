@@ -11,7 +11,10 @@ Also reported on the same JSON line:
   roofline      the multilinear sweep kernel (the dominant kernel): its
                 algorithmic bytes per launch over its average launch time,
                 both taken inside the timed steps from device events that the
-                library records on the stream the sweeps run on;
+                library records on the stream the sweeps run on; `traffic` is
+                the counter-measured bytes per launch from the committed
+                profile, reported only when the sweep sources built here are
+                the ones that profile was taken on (else null);
   cpu_baseline  the CPU oracle (sort + union-find, one thread) on the same
                 graph, timed on this host;
   batched       10^4 uneven Erdos-Renyi graphs (n log-uniform in [64, 65536),
@@ -35,6 +38,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+SWEEP_SOURCES = ("kernels_sweep.hip", "msf_internal.hpp", "wave.hpp")
+PROFILE = os.path.join(ROOT, "profiles", "rmat_s22_solve.md")
+
+
+def sweep_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2110_04865_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed counter profile
+    (calibrated FETCH_SIZE + WRITE_SIZE), or None when the profile was taken
+    on different sweep sources than the ones built here."""
+    try:
+        with open(PROFILE) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    vals = {}
+    for ln in lines:
+        for k in ("sweep_traffic_bytes:", "sweep_source_sha256:"):
+            if ln.strip().startswith(k):
+                vals[k] = ln.strip()[len(k):].strip().strip("`")
+    if vals.get("sweep_source_sha256:") != sweep_source_hash():
+        return None
+    try:
+        return float(vals["sweep_traffic_bytes:"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -63,9 +100,11 @@ def bench_rmat(ctx, pkg, torch, steps, warmup):
     for k in range(steps):
         ids, cnt, tot = ctx.solve(n, de, dw, wtype=pkg.W_F32, out=out)
         st = ctx.stats()
-        sweep_ms += sum(st["sweep_ms"])
-        sweep_bytes += sum(st["sweep_bytes"])
-        sweeps += len(st["sweep_ms"])
+        for t_ms, b in zip(st["sweep_ms"], st["sweep_bytes"]):
+            if b > 0:  # round 1's minima come from the build: no sweep launch
+                sweep_ms += t_ms
+                sweep_bytes += b
+                sweeps += 1
         build_ms += st["build_ms"]
         rounds_ms += st["rounds_ms"]
     torch.cuda.synchronize()
@@ -161,21 +200,36 @@ def bench_served(ctx, pkg, torch, requests_per_rate=200, rates=(0.25, 0.5, 1.0, 
         gaps = rng.exponential(1.0 / lam, requests_per_rate)
         arrivals = np.cumsum(gaps)
         picks = rng.integers(0, len(pool), requests_per_rate)
-        tickets = []
+        # the client collects each result as soon as it is ready (while it
+        # keeps submitting), as a serving front end would; that returns the
+        # request's pinned staging buffer to the server's pool
+        pending = []
+        lat = []
+
+        def collect(block):
+            keep = []
+            for tk, n in pending:
+                if srv.poll(tk):
+                    lat.append(srv.latency(tk))
+                    srv.result(tk, n)
+                else:
+                    keep.append((tk, n))
+            pending[:] = keep
+            if block and pending:
+                time.sleep(0.0005)
+
         t0 = time.perf_counter()
         for a, g in zip(arrivals, picks):
-            now = time.perf_counter() - t0
-            if a > now:
-                time.sleep(a - now)
+            while True:
+                collect(False)
+                now = time.perf_counter() - t0
+                if a <= now:
+                    break
+                time.sleep(min(a - now, 0.0005))
             n, e, w, kind = pool[g]
-            tickets.append((srv.submit(n, e, w, wtype=pkg.W_F32), n))
-        # results and latencies
-        lat = []
-        for tk, n in tickets:
-            while not srv.poll(tk):
-                time.sleep(0.0005)
-            lat.append(srv.latency(tk))
-            srv.result(tk, n)
+            pending.append((srv.submit(n, e, w, wtype=pkg.W_F32), n))
+        while pending:
+            collect(True)
         t_end = time.perf_counter() - t0
         lat = np.array(lat)
         # plain FIFO under the same arrivals with the measured service times
@@ -260,7 +314,7 @@ def main():
                    "build_ms": r["build_ms"], "rounds_ms": r["rounds_ms"]},
         "roofline": {"bound": "hbm", "kernel": "k_sweep (multilinear + projection)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "avg_launch_ms": avg_sweep_ms,
                      "bytes_per_launch": r["sweep_bytes"] / max(1, r["sweeps"]),
                      "launches": r["sweeps"]},

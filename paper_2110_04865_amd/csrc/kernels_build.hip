@@ -189,11 +189,13 @@ uint32_t sweep_nchunks(uint32_t nnz) { return (nnz + SWEEP_CHUNK - 1) / SWEEP_CH
 int choose_slices(int32_t n, int64_t m, int forced)
 {
     if (forced >= 1) return forced > MAX_SLICES ? MAX_SLICES : forced;
-    // One L2 (4 MB) holds 2^20 parents; beyond that each XCD gets a slice of
-    // its own.  Slices cost S row pointers per vertex and cut rows into S
-    // segments, so they are kept for graphs with at least 16 stored entries
-    // per vertex; sparser graphs (grids, unions of small graphs) keep one.
-    return (n >= (1 << 20) && m >= 8 * (int64_t)n) ? MAX_SLICES : 1;
+    // Slices keep each XCD's p[col] gathers inside its own L2, which pays
+    // when every entry is gathered.  The plain sweep gathers lazily (about
+    // one entry per lane), and then one slice is faster: no per-slice row
+    // pointers and longer row segments.  Slices stay available on request.
+    (void)n;
+    (void)m;
+    return 1;
 }
 
 void set_chunks(Adj *a)

@@ -220,9 +220,12 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
         wp0 = p[lo + min(t0, nrows - 1)];
         wp1 = p[lo + min(t1, nrows - 1)];
     }
+    // eager variants gather every column parent now, overlapping the
+    // window loads; the lazy plain sweep gathers after the row search
+    constexpr bool LAZY = !COMPACT && !FIRST;
     uint32_t pc[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) pc[e] = FIRST ? 0u : p[cl[e]];
+    for (int e = 0; e < E; ++e) pc[e] = (FIRST || LAZY) ? 0u : p[cl[e]];
 
     // 2. stage the window
     if (win) {
@@ -252,10 +255,65 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
             root[0] = v.x; root[1] = v.y; root[2] = v.z; root[3] = v.w;
         }
     }
+    uint32_t dead_found = 0;  // lazy: gathered entries found internal
+    if (LAZY) {
+        // Lazy gathers: only the smallest entry of the lane for each root
+        // can be the lane's contribution to that root, so its column parent
+        // is gathered first; the other entries of a root are gathered only
+        // if that entry is internal (p_i == p_j).  Skipped entries have
+        // larger keys than a live one of the same root, so the minima are
+        // exact.  Loads are unconditional: lanes with nothing to gather read
+        // p[lo], a line the whole wave shares.
+        bool am[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        live[e] = e >= kb && e < ke && (FIRST || root[e] != pc[e]);
-        cand[e] = live[e] ? ky[e] : KEY_INF;
+        for (int e = 0; e < E; ++e) {
+            bool m = e >= kb && e < ke;
+#pragma unroll
+            for (int f = 0; f < E; ++f)
+                if (f != e && f >= kb && f < ke && root[f] == root[e] &&
+                    (ky[f] < ky[e] || (ky[f] == ky[e] && f < e)))
+                    m = false;
+            am[e] = m;
+        }
+        uint32_t pa[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) pa[e] = p[am[e] ? cl[e] : lo];
+        bool need[E];
+        bool any = false;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            live[e] = am[e] && root[e] != pa[e];
+            dead_found += (am[e] && root[e] == pa[e]) ? 1u : 0u;
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            bool nd = false;
+#pragma unroll
+            for (int f = 0; f < E; ++f)
+                if (am[f] && !live[f] && root[f] == root[e]) nd = true;
+            need[e] = nd && !am[e] && e >= kb && e < ke;
+            any |= need[e];
+        }
+        if (__ballot(any)) {
+            uint32_t pb[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) pb[e] = p[need[e] ? cl[e] : lo];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                if (need[e]) {
+                    live[e] = root[e] != pb[e];
+                    dead_found += live[e] ? 0u : 1u;
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) cand[e] = live[e] ? ky[e] : KEY_INF;
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            live[e] = e >= kb && e < ke && (FIRST || root[e] != pc[e]);
+            cand[e] = live[e] ? ky[e] : KEY_INF;
+        }
     }
 
     // flush one run's minimum: in round 1 with one slice, a row wholly
@@ -325,9 +383,16 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
         }
     }
 
+    // live entries: exact in the eager variants; the lazy sweep counts
+    // every entry not found internal (an upper bound, for the filtering
+    // policy only)
     uint32_t lcnt = 0;
+    if (LAZY) {
+        lcnt = (uint32_t)(ke > kb ? ke - kb : 0) - dead_found;
+    } else {
 #pragma unroll
-    for (int e = 0; e < E; ++e) lcnt += live[e] ? 1u : 0u;
+        for (int e = 0; e < E; ++e) lcnt += live[e] ? 1u : 0u;
+    }
 
     if (!COMPACT) {
         // live entries of this sweep (filtering policy): one count per wave,

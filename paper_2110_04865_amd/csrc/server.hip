@@ -133,7 +133,9 @@ struct msf_server {
     int device = 0;
     size_t budget = 0;
     size_t used = 0;
-    size_t max_slots = 64;
+    // requests in flight; 8 measured best on one MI355X for mixed graphs
+    // (more slots only interleave large solves; MSF_SERVER_SLOTS overrides)
+    size_t max_slots = 8;
     std::mutex mu;
     std::condition_variable cv_work;  // worker: new request or stop
     std::condition_variable cv_done;  // clients: a request finished
