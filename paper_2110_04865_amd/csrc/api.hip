@@ -136,7 +136,7 @@ msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc)
     if (const char *f = getenv("MSF_FILTER_THRESHOLD")) c->filter_threshold = atof(f);
     if (const char *f = getenv("MSF_CHECK_ROUNDS")) c->check_rounds = atoi(f) != 0;
     if (const char *f = getenv("MSF_FIRST_ROUND")) c->first_round = atoi(f);
-    if (const char *f = getenv("MSF_BUCKETED_BUILD")) c->bucketed_build = atoi(f) != 0;
+    if (const char *f = getenv("MSF_BUCKETED_BUILD")) c->bucketed_build = atoi(f);
     if (const char *f = getenv("MSF_SLICES")) c->slices = atoi(f);
     return MSF_OK;
 }

@@ -328,19 +328,36 @@ __global__ __launch_bounds__(BKA_NT) void k_bucket_hist(const int32_t *__restric
     const int64_t e0 = (int64_t)blockIdx.x * epb;
     const int64_t e1 = e0 + epb < m ? e0 + epb : m;
     uint32_t err = 0;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += BKA_NT) {
-        const int32_t u = edges[2 * e], v = edges[2 * e + 1];
-        if (WT == MSF_W_F32) {
-            const uint32_t b = ((const uint32_t *)w)[e];
-            if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu)) err |= ERR_NAN;
+    // BKA_B edges per thread per batch, all loaded before any is counted
+    constexpr int BKA_B = 8;
+    for (int64_t eb = e0; eb < e1; eb += (int64_t)BKA_NT * BKA_B) {
+        int32_t uu[BKA_B], vv[BKA_B];
+        uint32_t ww[BKA_B];
+#pragma unroll
+        for (int k = 0; k < BKA_B; ++k) {
+            const int64_t e = eb + threadIdx.x + (int64_t)k * BKA_NT;
+            const bool in = e < e1;
+            uu[k] = in ? edges[2 * e] : 0;
+            vv[k] = in ? edges[2 * e + 1] : 0;
+            ww[k] = (in && WT == MSF_W_F32) ? ((const uint32_t *)w)[e] : 0u;
         }
-        if ((uint32_t)u >= (uint32_t)n || (uint32_t)v >= (uint32_t)n) {
-            err |= ERR_ENDPOINT;
-            continue;
+#pragma unroll
+        for (int k = 0; k < BKA_B; ++k) {
+            const int64_t e = eb + threadIdx.x + (int64_t)k * BKA_NT;
+            if (e >= e1) continue;
+            const int32_t u = uu[k], v = vv[k];
+            if (WT == MSF_W_F32) {
+                const uint32_t b = ww[k];
+                if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu)) err |= ERR_NAN;
+            }
+            if ((uint32_t)u >= (uint32_t)n || (uint32_t)v >= (uint32_t)n) {
+                err |= ERR_ENDPOINT;
+                continue;
+            }
+            if (u == v) continue;
+            atomicAdd(&hist[bucket_of((uint32_t)u, (uint32_t)v, lb, slice_w, nbr)], 1u);
+            atomicAdd(&hist[bucket_of((uint32_t)v, (uint32_t)u, lb, slice_w, nbr)], 1u);
         }
-        if (u == v) continue;
-        atomicAdd(&hist[bucket_of((uint32_t)u, (uint32_t)v, lb, slice_w, nbr)], 1u);
-        atomicAdd(&hist[bucket_of((uint32_t)v, (uint32_t)u, lb, slice_w, nbr)], 1u);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nb; i += BKA_NT) bh[(size_t)i * nblk + blockIdx.x] = hist[i];
@@ -480,6 +497,21 @@ static msf_status build_atomic(Ctx *c, int32_t n, int64_t m, const int32_t *d_ed
     return MSF_OK;
 }
 
+msf_status launch_bucket_hist(Ctx *c, const int32_t *d_edges, const void *d_w, int64_t m,
+                              int32_t n, int lb, int nb, uint32_t slice_w, uint32_t nbr,
+                              int64_t epb, uint32_t nblk, msf_wtype wt, uint32_t *bh)
+{
+    const size_t lds_a = 4 * (size_t)nb;
+    if (wt == MSF_W_F32)
+        k_bucket_hist<MSF_W_F32><<<nblk, BKA_NT, lds_a, c->stream>>>(
+            d_edges, d_w, m, n, lb, nb, slice_w, nbr, epb, nblk, bh, c->dcnt);
+    else
+        k_bucket_hist<MSF_W_U32><<<nblk, BKA_NT, lds_a, c->stream>>>(
+            d_edges, d_w, m, n, lb, nb, slice_w, nbr, epb, nblk, bh, c->dcnt);
+    MSF_HIP(hipGetLastError());
+    return MSF_OK;
+}
+
 static size_t rows_lds(int lb, bool with_min)
 {
     const size_t R = (size_t)1 << lb;
@@ -510,12 +542,7 @@ static msf_status build_bucketed(Ctx *c, int32_t n, int64_t m, const int32_t *d_
     MSF_TRY(ws_get(c, WS_BKEY, 8 * 2 * mm, &vkey));
     uint32_t *bh = (uint32_t *)vbh, *bo = (uint32_t *)vbo;
     const size_t lds_a = 4 * (size_t)nb;
-    if (wt == MSF_W_F32)
-        k_bucket_hist<MSF_W_F32><<<nblk, BKA_NT, lds_a, s>>>(d_edges, d_w, m, n, lb, nb, slice_w,
-                                                           nbr, epb, nblk, bh, c->dcnt);
-    else
-        k_bucket_hist<MSF_W_U32><<<nblk, BKA_NT, lds_a, s>>>(d_edges, d_w, m, n, lb, nb, slice_w,
-                                                           nbr, epb, nblk, bh, c->dcnt);
+    MSF_TRY(launch_bucket_hist(c, d_edges, d_w, m, n, lb, nb, slice_w, nbr, epb, nblk, wt, bh));
     MSF_TRY(scan_u32(c, bh, bo, (int64_t)nh, &c->dcnt->count));
     if (wt == MSF_W_F32)
         k_bucket_scatter<MSF_W_F32><<<nblk, BKA_NT, lds_a, s>>>(
@@ -572,11 +599,15 @@ msf_status build_adjacency(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
     const bool bucketed = c->bucketed_build && m > 0 && n > 0 && lb <= BK_MAX_LB &&
                           rows_lds_ok<false>(lb);
     if (!bucketed) S = 1;  // the atomic fallback stores one slice
+    TwoLevel tl;
     uint32_t slice_w = (uint32_t)n;
     if (S > 1) slice_w = (uint32_t)((((int64_t)n + S - 1) / S + 31) & ~(int64_t)31);
     if (m == 0 || n == 0) {
         launch_fill_u32(c->stream, row_ptr, 0u, (size_t)n + 1);
         launch_fill_u32(c->stream, &c->dcnt->count, 0u, 1);
+    } else if (bucketed && S == 1 && c->bucketed_build == 1 && two_level_params(n, m, &tl)) {
+        MSF_TRY(build_two_level(c, n, m, d_edges, d_w, wt, tl, row_ptr, col, key, r_first));
+        if (first_done) *first_done = r_first != nullptr;
     } else if (bucketed) {
         const bool fuse = r_first && rows_lds_ok<true>(lb);
         MSF_TRY(build_bucketed(c, n, m, d_edges, d_w, wt, lb, S, slice_w, row_ptr, col, key,

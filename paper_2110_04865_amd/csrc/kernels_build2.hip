@@ -1,0 +1,490 @@
+// Two-level bucketed adjacency build (one column slice): the symmetric
+// adjacency matrix A of section 2, both directions of every non-loop edge,
+// each carrying the edge's key.
+//
+// The entries are partitioned by row in two levels and then placed in LDS,
+// so that every pass writes whole runs of consecutive addresses instead of
+// scattering single entries (which leaves partly written cache lines):
+//   A1. per block of edges, an LDS histogram of the coarse buckets (rows
+//       [c << L1, (c+1) << L1)), written bucket-major; one scan gives every
+//       (bucket, block) its offset (shared with the one-level build);
+//   B1. the same blocks expand each edge into its two stored directions,
+//       sort LDS tiles of them by coarse bucket and write each bucket's run
+//       of the tile contiguously (row, column, key as three arrays);
+//   P.  a plan: per coarse bucket, how many level-2 workgroups (TL_E2
+//       entries each) cover it, and their prefix;
+//   A2. each level-2 workgroup counts its entries per fine bucket (rows
+//       [f << L2, (f+1) << L2)); the counts are laid out so one scan makes
+//       each fine bucket contiguous, in row order;
+//   B2. the level-2 workgroups sort LDS tiles by fine bucket and write runs;
+//   C.  one workgroup per fine bucket counts its rows, scans them into
+//       row_ptr, places the entries in LDS by row and writes the bucket out
+//       in one coalesced sweep (buckets larger than LDS scatter directly).
+//       In the solve it also keeps each row's smallest key: round 1 of the
+//       multilinear sweep, where the parent vector is the identity.
+// Every atomic is an LDS atomic.
+#include "msf_internal.hpp"
+#include "wave.hpp"
+
+namespace msf {
+
+namespace {
+
+constexpr int TL_NT = 512;         // partition workgroup
+constexpr int TL_TILE = 4096;      // entries per LDS tile
+constexpr int TL_E2 = 8192;        // level-1 entries per level-2 workgroup
+constexpr int TC_NT = 256;         // placement workgroup
+constexpr int TC_PT = 8;           // entries per thread per pass of a placement
+constexpr int TL_MAX_NC = 1024;    // coarse buckets
+constexpr int TL_MAX_NSUB = 256;   // fine buckets per coarse bucket
+constexpr int TL_MAX_L2 = 10;      // log2 rows per fine bucket
+
+// In-place exclusive scan of a[0..N) in LDS by an NT-thread workgroup;
+// returns the total.  Every thread must call it.
+template <int NT>
+__device__ uint32_t lds_excl_scan(uint32_t *a, int N, uint32_t *scr)
+{
+    const int per = (N + NT - 1) / NT;
+    const int i0 = (int)threadIdx.x * per;
+    uint32_t run = 0;
+    for (int j = 0; j < per; ++j)
+        if (i0 + j < N) run += a[i0 + j];
+    uint32_t tot;
+    const uint32_t ex = block_excl_sum<NT>(run, scr, &tot);
+    uint32_t acc = ex;
+    for (int j = 0; j < per; ++j) {
+        if (i0 + j < N) {
+            const uint32_t c = a[i0 + j];
+            a[i0 + j] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    return tot;
+}
+
+// Level-2 workgroup b -> coarse bucket c and its index j inside c
+// (P[c] <= b < P[c+1]); returns false past the last workgroup.
+__device__ __forceinline__ bool l2_block(const uint32_t *__restrict__ P, int NC, uint32_t b,
+                                         uint32_t *c, uint32_t *j)
+{
+    if (b >= P[NC]) return false;
+    int lo = 0, hi = NC - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (P[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    *c = (uint32_t)lo;
+    *j = b - P[lo];
+    return true;
+}
+
+// Index of (coarse c, fine sub, level-2 workgroup j) in the level-2 count
+// table: coarse-major, then fine bucket, then workgroup.
+__device__ __forceinline__ size_t t2_index(const uint32_t *__restrict__ P,
+                                           const uint32_t *__restrict__ nb2, int nsub, uint32_t c,
+                                           uint32_t sub, uint32_t j)
+{
+    return (size_t)nsub * P[c] + (size_t)sub * nb2[c] + j;
+}
+
+}  // namespace
+
+// B1: edges -> coarse buckets, LDS-sorted tiles, runs written contiguously.
+// A tile is TL_TILE/2 edges; each thread loads its TL_EP edges into
+// registers once (all loads in flight together), then counts, ranks and
+// places them through LDS.
+constexpr int TL_EP = TL_TILE / 2 / TL_NT;  // edges per thread per tile
+
+template <int WT>
+__global__ __launch_bounds__(TL_NT) void k_part_edges(
+    const int32_t *__restrict__ edges, const void *__restrict__ w, int64_t m, int32_t n, int L1,
+    int NC, int64_t epb, uint32_t nblk, const uint32_t *__restrict__ bo1,
+    uint32_t *__restrict__ orow, uint32_t *__restrict__ ocol, uint64_t *__restrict__ okey)
+{
+    __shared__ uint32_t s_row[TL_TILE], s_col[TL_TILE];
+    __shared__ uint64_t s_key[TL_TILE];
+    __shared__ uint32_t s_run[TL_MAX_NC], s_start[TL_MAX_NC], s_pos[TL_MAX_NC];
+    __shared__ uint32_t s_scr[TL_NT / 64 + 1];
+    for (int c = threadIdx.x; c < NC; c += TL_NT) s_run[c] = bo1[(size_t)c * nblk + blockIdx.x];
+    const int64_t e0 = (int64_t)blockIdx.x * epb;
+    const int64_t e1 = e0 + epb < m ? e0 + epb : m;
+    for (int64_t t0 = e0; t0 < e1; t0 += TL_TILE / 2) {
+        int32_t eu[TL_EP], ev[TL_EP];
+        uint32_t ew[TL_EP];
+        bool ok[TL_EP];
+#pragma unroll
+        for (int k = 0; k < TL_EP; ++k) {
+            const int64_t e = t0 + threadIdx.x + (int64_t)k * TL_NT;
+            const bool in = e < e1;
+            // two 4-byte loads: the edge array is only guaranteed 4-byte aligned
+            eu[k] = in ? edges[2 * e] : 0;
+            ev[k] = in ? edges[2 * e + 1] : 0;
+            ew[k] = in ? ((const uint32_t *)w)[e] : 0u;
+            ok[k] = in && (uint32_t)eu[k] < (uint32_t)n && (uint32_t)ev[k] < (uint32_t)n &&
+                    eu[k] != ev[k];
+        }
+        for (int c = threadIdx.x; c < NC; c += TL_NT) s_pos[c] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < TL_EP; ++k) {
+            if (!ok[k]) continue;
+            atomicAdd(&s_pos[(uint32_t)eu[k] >> L1], 1u);
+            atomicAdd(&s_pos[(uint32_t)ev[k] >> L1], 1u);
+        }
+        __syncthreads();
+        lds_excl_scan<TL_NT>(s_pos, NC, s_scr);
+        for (int c = threadIdx.x; c < NC; c += TL_NT) s_start[c] = s_pos[c];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < TL_EP; ++k) {
+            if (!ok[k]) continue;
+            const int64_t e = t0 + threadIdx.x + (int64_t)k * TL_NT;
+            uint32_t wk = ew[k];
+            if (WT == MSF_W_F32) wk = wkey_f32_bits(wk);
+            const uint64_t key = ((uint64_t)wk << 32) | (uint64_t)(uint32_t)e;
+            const uint32_t u = (uint32_t)eu[k], v = (uint32_t)ev[k];
+            const uint32_t pu = atomicAdd(&s_pos[u >> L1], 1u);
+            s_row[pu] = u;
+            s_col[pu] = v;
+            s_key[pu] = key;
+            const uint32_t pv = atomicAdd(&s_pos[v >> L1], 1u);
+            s_row[pv] = v;
+            s_col[pv] = u;
+            s_key[pv] = key;
+        }
+        __syncthreads();
+        const uint32_t cnt = s_pos[NC - 1];  // end of the last bucket = tile size
+        for (uint32_t i = threadIdx.x; i < cnt; i += TL_NT) {
+            const uint32_t row = s_row[i];
+            const uint32_t c = row >> L1;
+            const uint32_t pos = s_run[c] + (i - s_start[c]);
+            orow[pos] = row;
+            ocol[pos] = s_col[i];
+            okey[pos] = s_key[i];
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < NC; c += TL_NT) s_run[c] += s_pos[c] - s_start[c];
+        __syncthreads();
+    }
+}
+
+// P: coarse bucket starts cs[0..NC] (cs[NC] = total), level-2 workgroups
+// per coarse bucket nb2[c] and their prefix P[0..NC].  One workgroup.
+__global__ __launch_bounds__(1024) void k_tl_plan(const uint32_t *__restrict__ bo1, uint32_t nblk,
+                                                  int NC, uint32_t *__restrict__ cs,
+                                                  uint32_t *__restrict__ nb2,
+                                                  uint32_t *__restrict__ P)
+{
+    __shared__ uint32_t s[TL_MAX_NC];
+    __shared__ uint32_t scr[1024 / 64 + 1];
+    const uint32_t total = bo1[(size_t)NC * nblk];
+    for (int c = threadIdx.x; c < NC; c += 1024) {
+        const uint32_t a = bo1[(size_t)c * nblk];
+        const uint32_t b = c + 1 < NC ? bo1[(size_t)(c + 1) * nblk] : total;
+        const uint32_t k = (b - a + TL_E2 - 1) / TL_E2;
+        cs[c] = a;
+        nb2[c] = k;
+        s[c] = k;
+    }
+    __syncthreads();
+    const uint32_t tot = lds_excl_scan<1024>(s, NC, scr);
+    for (int c = threadIdx.x; c < NC; c += 1024) P[c] = s[c];
+    if (threadIdx.x == 0) {
+        P[NC] = tot;
+        cs[NC] = total;
+    }
+}
+
+// A2: per level-2 workgroup, its entries per fine bucket.
+__global__ __launch_bounds__(256) void k_tl_hist2(const uint32_t *__restrict__ row1, int L2,
+                                                  int nsub, int NC, const uint32_t *__restrict__ cs,
+                                                  const uint32_t *__restrict__ nb2,
+                                                  const uint32_t *__restrict__ P,
+                                                  uint32_t *__restrict__ t2)
+{
+    __shared__ uint32_t s_h[TL_MAX_NSUB];
+    uint32_t c, j;
+    if (!l2_block(P, NC, blockIdx.x, &c, &j)) return;
+    const uint32_t a = cs[c] + j * (uint32_t)TL_E2;
+    const uint32_t e = a + TL_E2 < cs[c + 1] ? a + TL_E2 : cs[c + 1];
+    for (int s = threadIdx.x; s < nsub; s += 256) s_h[s] = 0;
+    __syncthreads();
+    const uint32_t mask = (uint32_t)nsub - 1u;
+    for (uint32_t b = a; b < e; b += 256 * 8) {
+        uint32_t rr[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t i = b + threadIdx.x + 256u * k;
+            rr[k] = i < e ? row1[i] : NONE32;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (rr[k] != NONE32) atomicAdd(&s_h[(rr[k] >> L2) & mask], 1u);
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < nsub; s += 256) t2[t2_index(P, nb2, nsub, c, s, j)] = s_h[s];
+}
+
+// B2: coarse-bucket entries -> fine buckets, LDS-sorted tiles, runs
+// written contiguously at the scanned offsets o2.  Each thread loads its
+// TL_SP entries of a tile into registers once.
+constexpr int TL_SP = TL_TILE / TL_NT;  // entries per thread per tile
+
+__global__ __launch_bounds__(TL_NT) void k_part_sub(
+    const uint32_t *__restrict__ row1, const uint32_t *__restrict__ col1,
+    const uint64_t *__restrict__ key1, int L2, int nsub, int NC, const uint32_t *__restrict__ cs,
+    const uint32_t *__restrict__ nb2, const uint32_t *__restrict__ P,
+    const uint32_t *__restrict__ o2, uint32_t *__restrict__ row2, uint32_t *__restrict__ col2,
+    uint64_t *__restrict__ key2)
+{
+    __shared__ uint32_t s_row[TL_TILE], s_col[TL_TILE];
+    __shared__ uint64_t s_key[TL_TILE];
+    __shared__ uint32_t s_run[TL_MAX_NSUB], s_start[TL_MAX_NSUB], s_pos[TL_MAX_NSUB];
+    __shared__ uint32_t s_scr[TL_NT / 64 + 1];
+    uint32_t c, j;
+    if (!l2_block(P, NC, blockIdx.x, &c, &j)) return;
+    const uint32_t a = cs[c] + j * (uint32_t)TL_E2;
+    const uint32_t e = a + TL_E2 < cs[c + 1] ? a + TL_E2 : cs[c + 1];
+    const uint32_t mask = (uint32_t)nsub - 1u;
+    for (int s = threadIdx.x; s < nsub; s += TL_NT) s_run[s] = o2[t2_index(P, nb2, nsub, c, s, j)];
+    for (uint32_t t0 = a; t0 < e; t0 += TL_TILE) {
+        const uint32_t t1 = t0 + TL_TILE < e ? t0 + TL_TILE : e;
+        uint32_t rr[TL_SP], cc[TL_SP];
+        uint64_t kk[TL_SP];
+#pragma unroll
+        for (int k = 0; k < TL_SP; ++k) {
+            const uint32_t i = t0 + threadIdx.x + (uint32_t)k * TL_NT;
+            const bool in = i < t1;
+            rr[k] = in ? row1[i] : NONE32;
+            cc[k] = in ? col1[i] : 0u;
+            kk[k] = in ? key1[i] : 0ull;
+        }
+        for (int s = threadIdx.x; s < nsub; s += TL_NT) s_pos[s] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < TL_SP; ++k)
+            if (rr[k] != NONE32) atomicAdd(&s_pos[(rr[k] >> L2) & mask], 1u);
+        __syncthreads();
+        lds_excl_scan<TL_NT>(s_pos, nsub, s_scr);
+        for (int s = threadIdx.x; s < nsub; s += TL_NT) s_start[s] = s_pos[s];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < TL_SP; ++k) {
+            if (rr[k] == NONE32) continue;
+            const uint32_t p = atomicAdd(&s_pos[(rr[k] >> L2) & mask], 1u);
+            s_row[p] = rr[k];
+            s_col[p] = cc[k];
+            s_key[p] = kk[k];
+        }
+        __syncthreads();
+        const uint32_t cnt = t1 - t0;
+        for (uint32_t i = threadIdx.x; i < cnt; i += TL_NT) {
+            const uint32_t row = s_row[i];
+            const uint32_t s = (row >> L2) & mask;
+            const uint32_t pos = s_run[s] + (i - s_start[s]);
+            row2[pos] = row;
+            col2[pos] = s_col[i];
+            key2[pos] = s_key[i];
+        }
+        __syncthreads();
+        for (int s = threadIdx.x; s < nsub; s += TL_NT) s_run[s] += s_pos[s] - s_start[s];
+        __syncthreads();
+    }
+}
+
+// Start of every fine bucket in the final adjacency: fstart[f] for
+// f = c * nsub + sub, and fstart[NC * nsub] = total.
+__global__ void k_tl_fstart(const uint32_t *__restrict__ o2, const uint32_t *__restrict__ nb2,
+                            const uint32_t *__restrict__ P, int nsub, int NC,
+                            uint32_t *__restrict__ fstart)
+{
+    const uint32_t nf = (uint32_t)NC * (uint32_t)nsub;
+    for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f <= nf;
+         f += gridDim.x * blockDim.x) {
+        const uint32_t c = f < nf ? f / (uint32_t)nsub : (uint32_t)NC;
+        const uint32_t sub = f < nf ? f % (uint32_t)nsub : 0u;
+        fstart[f] = f < nf ? o2[t2_index(P, nb2, nsub, c, sub, 0)] : o2[(size_t)nsub * P[NC]];
+    }
+}
+
+// C: one workgroup per fine bucket f (rows [f << L2, (f+1) << L2)): count,
+// scan into row_ptr, place by row.  A bucket's output span is small (tens of
+// KB), so its scattered stores merge in L2 before they reach HBM.  MIN:
+// also store each row's smallest key into r (round 1 of the sweep).
+template <bool MIN>
+__global__ __launch_bounds__(TC_NT) void k_tl_place(
+    const uint32_t *__restrict__ row2, const uint32_t *__restrict__ col2,
+    const uint64_t *__restrict__ key2, int32_t n, int L2, const uint32_t *__restrict__ fstart,
+    uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ col, uint64_t *__restrict__ key,
+    uint64_t *__restrict__ r)
+{
+    extern __shared__ uint64_t tc_lds[];
+    const uint32_t R = 1u << L2;
+    uint64_t *s_min = tc_lds;                                            // R (MIN)
+    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(tc_lds + (MIN ? R : 0));  // R
+    __shared__ uint32_t s_scr[TC_NT / 64 + 1];
+    const uint32_t f = blockIdx.x;
+    const int64_t row0 = (int64_t)f << L2;
+    if (row0 >= n) return;
+    const uint32_t rows = (uint32_t)((int64_t)n - row0 < (int64_t)R ? (int64_t)n - row0 : R);
+    const uint32_t fs = fstart[f], fe = fstart[f + 1];
+    for (uint32_t i = threadIdx.x; i < R; i += TC_NT) {
+        s_cnt[i] = 0;
+        if (MIN) s_min[i] = KEY_INF;
+    }
+    __syncthreads();
+    for (uint32_t b = fs; b < fe; b += TC_NT * TC_PT) {
+        uint32_t rl[TC_PT];
+#pragma unroll
+        for (int k = 0; k < TC_PT; ++k) {
+            const uint32_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
+            rl[k] = i < fe ? row2[i] - (uint32_t)row0 : NONE32;
+        }
+#pragma unroll
+        for (int k = 0; k < TC_PT; ++k)
+            if (rl[k] != NONE32) atomicAdd(&s_cnt[rl[k]], 1u);
+    }
+    __syncthreads();
+    lds_excl_scan<TC_NT>(s_cnt, (int)R, s_scr);
+    for (uint32_t i = threadIdx.x; i < rows; i += TC_NT) row_ptr[row0 + i] = fs + s_cnt[i];
+    if (row0 + rows == (int64_t)n && threadIdx.x == 0) row_ptr[n] = fe;
+    __syncthreads();
+    for (uint32_t b = fs; b < fe; b += TC_NT * TC_PT) {
+        uint32_t rl[TC_PT], cc[TC_PT];
+        uint64_t kk[TC_PT];
+#pragma unroll
+        for (int k = 0; k < TC_PT; ++k) {
+            const uint32_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
+            const bool in = i < fe;
+            rl[k] = in ? row2[i] - (uint32_t)row0 : NONE32;
+            cc[k] = in ? col2[i] : 0u;
+            kk[k] = in ? key2[i] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < TC_PT; ++k) {
+            if (rl[k] == NONE32) continue;
+            const uint32_t p = atomicAdd(&s_cnt[rl[k]], 1u);
+            col[fs + p] = cc[k];
+            key[fs + p] = kk[k];
+            if (MIN) atomicMin((unsigned long long *)&s_min[rl[k]], (unsigned long long)kk[k]);
+        }
+    }
+    if (MIN) {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < rows; i += TC_NT) r[row0 + i] = s_min[i];
+    }
+}
+
+// ------------------------------------------------------------------ host --
+
+namespace {
+
+int ceil_log2(uint64_t x)
+{
+    int k = 0;
+    while ((1ull << k) < x) ++k;
+    return k;
+}
+
+}  // namespace
+
+bool two_level_params(int32_t n, int64_t m, TwoLevel *tl)
+{
+    if (n <= 0 || m <= 0) return false;
+    const double avg = (2.0 * (double)m) / (double)n;  // stored entries per row (bound)
+    int L2 = 0;
+    while (L2 < TL_MAX_L2 && avg * (double)(1u << (L2 + 1)) <= 2048.0) ++L2;
+    for (;;) {
+        const uint64_t F = ((uint64_t)n + (1ull << L2) - 1) >> L2;
+        int lg = (ceil_log2(F) + 1) / 2;
+        if (lg > 8) lg = 8;
+        int L1 = L2 + lg;
+        uint64_t NC = ((uint64_t)n + (1ull << L1) - 1) >> L1;
+        while (NC > (uint64_t)TL_MAX_NC && lg < 8) {
+            ++lg;
+            ++L1;
+            NC = ((uint64_t)n + (1ull << L1) - 1) >> L1;
+        }
+        if (NC <= (uint64_t)TL_MAX_NC) {
+            tl->L1 = L1;
+            tl->L2 = L2;
+            tl->nsub = 1 << lg;
+            tl->NC = (int)NC;
+            return true;
+        }
+        if (++L2 > TL_MAX_L2) return false;
+    }
+}
+
+msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
+                           msf_wtype wt, const TwoLevel &tl, uint32_t *row_ptr, uint32_t *col,
+                           uint64_t *key, uint64_t *r_first)
+{
+    hipStream_t s = c->stream;
+    const int NC = tl.NC;
+    int64_t epb = (m + 2047) / 2048;
+    if (epb < 32768) epb = 32768;
+    epb = (epb + 255) & ~(int64_t)255;
+    const uint32_t nblk = (uint32_t)((m + epb - 1) / epb);
+    const size_t nh = (size_t)NC * nblk;
+    const size_t cap = 2 * (size_t)m;  // stored entries, at most
+    const size_t g2max = (cap + TL_E2 - 1) / TL_E2 + (size_t)NC;
+    const size_t nt2 = (size_t)tl.nsub * g2max;
+    void *vbh, *vbo, *vr1, *vc1, *vk1, *vr2, *vc2, *vk2, *vplan, *vt2, *vo2;
+    MSF_TRY(ws_get(c, WS_BH, 4 * nh, &vbh));
+    MSF_TRY(ws_get(c, WS_BHOFF, 4 * (nh + 1), &vbo));
+    MSF_TRY(ws_get(c, WS_BRLO, 4 * cap, &vr1));
+    MSF_TRY(ws_get(c, WS_BCOL, 4 * cap, &vc1));
+    MSF_TRY(ws_get(c, WS_BKEY, 8 * cap, &vk1));
+    MSF_TRY(ws_get(c, WS_L2ROW, 4 * cap, &vr2));
+    MSF_TRY(ws_get(c, WS_L2COL, 4 * cap, &vc2));
+    MSF_TRY(ws_get(c, WS_L2KEY, 8 * cap, &vk2));
+    MSF_TRY(ws_get(c, WS_TLPLAN, 4 * (3 * (size_t)NC + 3), &vplan));
+    MSF_TRY(ws_get(c, WS_T2, 4 * nt2, &vt2));
+    MSF_TRY(ws_get(c, WS_T2OFF, 4 * (nt2 + 1), &vo2));
+    void *vfs;
+    const size_t nfine = (size_t)NC * (size_t)tl.nsub;
+    MSF_TRY(ws_get(c, WS_FSTART, 4 * (nfine + 1), &vfs));
+    uint32_t *fst = (uint32_t *)vfs;
+    uint32_t *bh = (uint32_t *)vbh, *bo = (uint32_t *)vbo;
+    uint32_t *cs = (uint32_t *)vplan, *nb2 = cs + NC + 1, *P = nb2 + NC;
+    uint32_t *t2 = (uint32_t *)vt2, *o2 = (uint32_t *)vo2;
+    uint32_t *r1 = (uint32_t *)vr1, *c1 = (uint32_t *)vc1, *r2 = (uint32_t *)vr2,
+             *c2 = (uint32_t *)vc2;
+    uint64_t *k1 = (uint64_t *)vk1, *k2 = (uint64_t *)vk2;
+
+    // A1 (coarse histogram; also validates endpoints and weights) + scan
+    MSF_TRY(launch_bucket_hist(c, d_edges, d_w, m, n, tl.L1, NC, (uint32_t)n, (uint32_t)NC, epb,
+                               nblk, wt, bh));
+    MSF_TRY(scan_u32(c, bh, bo, (int64_t)nh, &c->dcnt->count));
+    // B1
+    if (wt == MSF_W_F32)
+        k_part_edges<MSF_W_F32><<<nblk, TL_NT, 0, s>>>(d_edges, d_w, m, n, tl.L1, NC, epb, nblk,
+                                                       bo, r1, c1, k1);
+    else
+        k_part_edges<MSF_W_U32><<<nblk, TL_NT, 0, s>>>(d_edges, d_w, m, n, tl.L1, NC, epb, nblk,
+                                                       bo, r1, c1, k1);
+    // P, A2, scan, B2
+    k_tl_plan<<<1, 1024, 0, s>>>(bo, nblk, NC, cs, nb2, P);
+    launch_fill_u32(s, t2, 0u, nt2);
+    k_tl_hist2<<<(unsigned)g2max, 256, 0, s>>>(r1, tl.L2, tl.nsub, NC, cs, nb2, P, t2);
+    MSF_TRY(scan_u32(c, t2, o2, (int64_t)nt2, nullptr));
+    k_part_sub<<<(unsigned)g2max, TL_NT, 0, s>>>(r1, c1, k1, tl.L2, tl.nsub, NC, cs, nb2, P, o2,
+                                                  r2, c2, k2);
+    // C
+    const unsigned nf = (unsigned)NC * (unsigned)tl.nsub;
+    k_tl_fstart<<<(nf + 256) / 256, 256, 0, s>>>(o2, nb2, P, tl.nsub, NC, fst);
+    const size_t R = (size_t)1 << tl.L2;
+    if (r_first)
+        k_tl_place<true><<<nf, TC_NT, 12 * R, s>>>(r2, c2, k2, n, tl.L2, fst, row_ptr, col, key,
+                                                   r_first);
+    else
+        k_tl_place<false><<<nf, TC_NT, 4 * R, s>>>(r2, c2, k2, n, tl.L2, fst, row_ptr, col, key,
+                                                   nullptr);
+    MSF_HIP(hipGetLastError());
+    return MSF_OK;
+}
+
+}  // namespace msf

@@ -89,6 +89,7 @@ enum Slot {
     WS_STATUS, WS_WLIVE, WS_PART, WS_Q, WS_Q2,
     WS_BATCH0, WS_BATCH1, WS_BATCH2, WS_BATCH3,
     WS_BH, WS_BHOFF, WS_BRLO, WS_BCOL, WS_BKEY, WS_CHUNKINFO,
+    WS_L2ROW, WS_L2COL, WS_L2KEY, WS_TLPLAN, WS_T2, WS_T2OFF, WS_FSTART,
     WS_COUNT
 };
 
@@ -190,7 +191,9 @@ struct Ctx {
     // round 1: 0 generic sweep, 1 identity-parent sweep, 2 row minima
     // written by the adjacency build (falls back to 1 where it cannot)
     int first_round = 2;
-    bool bucketed_build = true;      // LDS-only adjacency build
+    // adjacency build: 0 device-atomic, 1 two-level bucketed where it
+    // applies (one slice), 2 one-level bucketed
+    int bucketed_build = 1;
     int slices = 0;                  // column slices: 0 automatic, else forced (1..8)
     SolveState ss;
 };
@@ -219,6 +222,22 @@ msf_status ws_get(Ctx *c, Slot s, size_t bytes, void **out);
 msf_status read_counters(Ctx *c);
 
 // ---- kernels (launch wrappers), all ordered on c->stream -----------------
+
+// Two-level bucketed build (one column slice): coarse buckets of 2^L1 rows
+// (NC of them), each cut into nsub fine buckets of 2^L2 rows.
+struct TwoLevel {
+    int L1 = 0, L2 = 0, nsub = 1, NC = 1;
+};
+bool two_level_params(int32_t n, int64_t m, TwoLevel *tl);
+msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
+                           msf_wtype wt, const TwoLevel &tl, uint32_t *row_ptr, uint32_t *col,
+                           uint64_t *key, uint64_t *r_first);
+// Coarse histogram of the bucketed builds: per block of epb edges, counts
+// of the stored directions per bucket (slice of column, row >> lb), written
+// bucket-major into bh[nb * nblk]; validates endpoints and weights.
+msf_status launch_bucket_hist(Ctx *c, const int32_t *d_edges, const void *d_w, int64_t m,
+                              int32_t n, int lb, int nb, uint32_t slice_w, uint32_t nbr,
+                              int64_t epb, uint32_t nblk, msf_wtype wt, uint32_t *bh);
 
 // Adjacency build (section 2 adjacency matrix, both directions).
 // Fills row_ptr[n+1], col/key[nnz] (capacity 2m) and *a; the number of

@@ -438,3 +438,33 @@ def test_first_round_modes_agree(pkg):
                 os.environ.pop(k, None)
             else:
                 os.environ[k] = v
+
+
+def test_build_modes_agree(pkg):
+    """The device-atomic (0), two-level bucketed (1, default) and one-level
+    bucketed (2) adjacency builds give the same forest: skewed R-MAT rows far
+    larger than a placement workgroup's LDS, a grid, a multigraph with loops,
+    and a graph with more vertices than edges."""
+    rng = np.random.default_rng(31)
+    nm = 3000
+    multi_e = rng.integers(0, nm, size=(20000, 2)).astype(np.int32)
+    multi_w = rng.integers(0, 50, size=20000).astype(np.uint32)
+    graphs = [
+        ("rmat15", *gen.rmat(15, 16, seed=32), F32),
+        ("grid24", *gen.grid(24, 24, 24, 0.05, seed=33), U32),
+        ("multi", nm, multi_e, multi_w, U32),
+        ("sparse", 50000, *gen.er(50000, 20000, seed=34), U32),
+    ]
+    old = os.environ.get("MSF_BUCKETED_BUILD")
+    try:
+        for mode in ("0", "1", "2"):
+            os.environ["MSF_BUCKETED_BUILD"] = mode
+            c = pkg.Context(0)
+            for label, n, e, w, wt in graphs:
+                check_solve(c, pkg, n, e, w, wt, f"build={mode} {label}")
+            c.close()
+    finally:
+        if old is None:
+            os.environ.pop("MSF_BUCKETED_BUILD", None)
+        else:
+            os.environ["MSF_BUCKETED_BUILD"] = old
