@@ -105,7 +105,7 @@ __global__ __launch_bounds__(TL_NT) void k_part_edges(
 {
     __shared__ uint32_t s_row[TL_TILE], s_col[TL_TILE];
     __shared__ uint64_t s_key[TL_TILE];
-    __shared__ uint32_t s_run[TL_MAX_NC], s_start[TL_MAX_NC], s_pos[TL_MAX_NC];
+    __shared__ uint32_t s_run[TL_MAX_NC], s_pos[TL_MAX_NC];
     __shared__ uint32_t s_scr[TL_NT / 64 + 1];
     for (int c = threadIdx.x; c < NC; c += TL_NT) s_run[c] = bo1[(size_t)c * nblk + blockIdx.x];
     const int64_t e0 = (int64_t)blockIdx.x * epb;
@@ -127,16 +127,18 @@ __global__ __launch_bounds__(TL_NT) void k_part_edges(
         }
         for (int c = threadIdx.x; c < NC; c += TL_NT) s_pos[c] = 0;
         __syncthreads();
+        // one LDS atomic per entry: its return value is the entry's rank in
+        // its bucket within the tile
+        uint32_t ru[TL_EP], rv[TL_EP];
 #pragma unroll
         for (int k = 0; k < TL_EP; ++k) {
+            ru[k] = rv[k] = 0;
             if (!ok[k]) continue;
-            atomicAdd(&s_pos[(uint32_t)eu[k] >> L1], 1u);
-            atomicAdd(&s_pos[(uint32_t)ev[k] >> L1], 1u);
+            ru[k] = atomicAdd(&s_pos[(uint32_t)eu[k] >> L1], 1u);
+            rv[k] = atomicAdd(&s_pos[(uint32_t)ev[k] >> L1], 1u);
         }
         __syncthreads();
-        lds_excl_scan<TL_NT>(s_pos, NC, s_scr);
-        for (int c = threadIdx.x; c < NC; c += TL_NT) s_start[c] = s_pos[c];
-        __syncthreads();
+        const uint32_t cnt = lds_excl_scan<TL_NT>(s_pos, NC, s_scr);  // s_pos: starts
 #pragma unroll
         for (int k = 0; k < TL_EP; ++k) {
             if (!ok[k]) continue;
@@ -145,27 +147,29 @@ __global__ __launch_bounds__(TL_NT) void k_part_edges(
             if (WT == MSF_W_F32) wk = wkey_f32_bits(wk);
             const uint64_t key = ((uint64_t)wk << 32) | (uint64_t)(uint32_t)e;
             const uint32_t u = (uint32_t)eu[k], v = (uint32_t)ev[k];
-            const uint32_t pu = atomicAdd(&s_pos[u >> L1], 1u);
+            const uint32_t pu = s_pos[u >> L1] + ru[k];
             s_row[pu] = u;
             s_col[pu] = v;
             s_key[pu] = key;
-            const uint32_t pv = atomicAdd(&s_pos[v >> L1], 1u);
+            const uint32_t pv = s_pos[v >> L1] + rv[k];
             s_row[pv] = v;
             s_col[pv] = u;
             s_key[pv] = key;
         }
         __syncthreads();
-        const uint32_t cnt = s_pos[NC - 1];  // end of the last bucket = tile size
         for (uint32_t i = threadIdx.x; i < cnt; i += TL_NT) {
             const uint32_t row = s_row[i];
             const uint32_t c = row >> L1;
-            const uint32_t pos = s_run[c] + (i - s_start[c]);
+            const uint32_t pos = s_run[c] + (i - s_pos[c]);
             orow[pos] = row;
             ocol[pos] = s_col[i];
             okey[pos] = s_key[i];
         }
         __syncthreads();
-        for (int c = threadIdx.x; c < NC; c += TL_NT) s_run[c] += s_pos[c] - s_start[c];
+        for (int c = threadIdx.x; c < NC; c += TL_NT) {
+            const uint32_t end = c + 1 < NC ? s_pos[c + 1] : cnt;
+            s_run[c] += end - s_pos[c];
+        }
         __syncthreads();
     }
 }
@@ -241,7 +245,7 @@ __global__ __launch_bounds__(TL_NT) void k_part_sub(
 {
     __shared__ uint32_t s_row[TL_TILE], s_col[TL_TILE];
     __shared__ uint64_t s_key[TL_TILE];
-    __shared__ uint32_t s_run[TL_MAX_NSUB], s_start[TL_MAX_NSUB], s_pos[TL_MAX_NSUB];
+    __shared__ uint32_t s_run[TL_MAX_NSUB], s_pos[TL_MAX_NSUB];
     __shared__ uint32_t s_scr[TL_NT / 64 + 1];
     uint32_t c, j;
     if (!l2_block(P, NC, blockIdx.x, &c, &j)) return;
@@ -263,33 +267,34 @@ __global__ __launch_bounds__(TL_NT) void k_part_sub(
         }
         for (int s = threadIdx.x; s < nsub; s += TL_NT) s_pos[s] = 0;
         __syncthreads();
+        uint32_t rk[TL_SP];  // rank in the fine bucket within the tile
 #pragma unroll
         for (int k = 0; k < TL_SP; ++k)
-            if (rr[k] != NONE32) atomicAdd(&s_pos[(rr[k] >> L2) & mask], 1u);
+            rk[k] = rr[k] != NONE32 ? atomicAdd(&s_pos[(rr[k] >> L2) & mask], 1u) : 0u;
         __syncthreads();
-        lds_excl_scan<TL_NT>(s_pos, nsub, s_scr);
-        for (int s = threadIdx.x; s < nsub; s += TL_NT) s_start[s] = s_pos[s];
-        __syncthreads();
+        const uint32_t cnt = lds_excl_scan<TL_NT>(s_pos, nsub, s_scr);  // s_pos: starts
 #pragma unroll
         for (int k = 0; k < TL_SP; ++k) {
             if (rr[k] == NONE32) continue;
-            const uint32_t p = atomicAdd(&s_pos[(rr[k] >> L2) & mask], 1u);
+            const uint32_t p = s_pos[(rr[k] >> L2) & mask] + rk[k];
             s_row[p] = rr[k];
             s_col[p] = cc[k];
             s_key[p] = kk[k];
         }
         __syncthreads();
-        const uint32_t cnt = t1 - t0;
         for (uint32_t i = threadIdx.x; i < cnt; i += TL_NT) {
             const uint32_t row = s_row[i];
             const uint32_t s = (row >> L2) & mask;
-            const uint32_t pos = s_run[s] + (i - s_start[s]);
+            const uint32_t pos = s_run[s] + (i - s_pos[s]);
             row2[pos] = row;
             col2[pos] = s_col[i];
             key2[pos] = s_key[i];
         }
         __syncthreads();
-        for (int s = threadIdx.x; s < nsub; s += TL_NT) s_run[s] += s_pos[s] - s_start[s];
+        for (int s = threadIdx.x; s < nsub; s += TL_NT) {
+            const uint32_t end = s + 1 < nsub ? s_pos[s + 1] : cnt;
+            s_run[s] += end - s_pos[s];
+        }
         __syncthreads();
     }
 }
@@ -335,28 +340,14 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
         if (MIN) s_min[i] = KEY_INF;
     }
     __syncthreads();
-    for (uint32_t b = fs; b < fe; b += TC_NT * TC_PT) {
-        uint32_t rl[TC_PT];
-#pragma unroll
-        for (int k = 0; k < TC_PT; ++k) {
-            const uint32_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
-            rl[k] = i < fe ? row2[i] - (uint32_t)row0 : NONE32;
-        }
-#pragma unroll
-        for (int k = 0; k < TC_PT; ++k)
-            if (rl[k] != NONE32) atomicAdd(&s_cnt[rl[k]], 1u);
-    }
-    __syncthreads();
-    lds_excl_scan<TC_NT>(s_cnt, (int)R, s_scr);
-    for (uint32_t i = threadIdx.x; i < rows; i += TC_NT) row_ptr[row0 + i] = fs + s_cnt[i];
-    if (row0 + rows == (int64_t)n && threadIdx.x == 0) row_ptr[n] = fe;
-    __syncthreads();
-    for (uint32_t b = fs; b < fe; b += TC_NT * TC_PT) {
-        uint32_t rl[TC_PT], cc[TC_PT];
+    if (fe - fs <= (uint32_t)(TC_NT * TC_PT)) {
+        // one batch: the counting atomic's return value is the entry's rank
+        // in its row, so every entry takes a single LDS atomic
+        uint32_t rl[TC_PT], cc[TC_PT], rk[TC_PT];
         uint64_t kk[TC_PT];
 #pragma unroll
         for (int k = 0; k < TC_PT; ++k) {
-            const uint32_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
+            const uint32_t i = fs + threadIdx.x + (uint32_t)k * TC_NT;
             const bool in = i < fe;
             rl[k] = in ? row2[i] - (uint32_t)row0 : NONE32;
             cc[k] = in ? col2[i] : 0u;
@@ -364,11 +355,58 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
         }
 #pragma unroll
         for (int k = 0; k < TC_PT; ++k) {
+            rk[k] = 0;
             if (rl[k] == NONE32) continue;
-            const uint32_t p = atomicAdd(&s_cnt[rl[k]], 1u);
+            rk[k] = atomicAdd(&s_cnt[rl[k]], 1u);
+            if (MIN) atomicMin((unsigned long long *)&s_min[rl[k]], (unsigned long long)kk[k]);
+        }
+        __syncthreads();
+        lds_excl_scan<TC_NT>(s_cnt, (int)R, s_scr);
+        for (uint32_t i = threadIdx.x; i < rows; i += TC_NT) row_ptr[row0 + i] = fs + s_cnt[i];
+        if (row0 + rows == (int64_t)n && threadIdx.x == 0) row_ptr[n] = fe;
+#pragma unroll
+        for (int k = 0; k < TC_PT; ++k) {
+            if (rl[k] == NONE32) continue;
+            const uint32_t p = s_cnt[rl[k]] + rk[k];
             col[fs + p] = cc[k];
             key[fs + p] = kk[k];
-            if (MIN) atomicMin((unsigned long long *)&s_min[rl[k]], (unsigned long long)kk[k]);
+        }
+    } else {
+        for (uint32_t b = fs; b < fe; b += TC_NT * TC_PT) {
+            uint32_t rl[TC_PT];
+#pragma unroll
+            for (int k = 0; k < TC_PT; ++k) {
+                const uint32_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
+                rl[k] = i < fe ? row2[i] - (uint32_t)row0 : NONE32;
+            }
+#pragma unroll
+            for (int k = 0; k < TC_PT; ++k)
+                if (rl[k] != NONE32) atomicAdd(&s_cnt[rl[k]], 1u);
+        }
+        __syncthreads();
+        lds_excl_scan<TC_NT>(s_cnt, (int)R, s_scr);
+        for (uint32_t i = threadIdx.x; i < rows; i += TC_NT) row_ptr[row0 + i] = fs + s_cnt[i];
+        if (row0 + rows == (int64_t)n && threadIdx.x == 0) row_ptr[n] = fe;
+        __syncthreads();
+        for (uint32_t b = fs; b < fe; b += TC_NT * TC_PT) {
+            uint32_t rl[TC_PT], cc[TC_PT];
+            uint64_t kk[TC_PT];
+#pragma unroll
+            for (int k = 0; k < TC_PT; ++k) {
+                const uint32_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
+                const bool in = i < fe;
+                rl[k] = in ? row2[i] - (uint32_t)row0 : NONE32;
+                cc[k] = in ? col2[i] : 0u;
+                kk[k] = in ? key2[i] : 0ull;
+            }
+#pragma unroll
+            for (int k = 0; k < TC_PT; ++k) {
+                if (rl[k] == NONE32) continue;
+                const uint32_t p = atomicAdd(&s_cnt[rl[k]], 1u);
+                col[fs + p] = cc[k];
+                key[fs + p] = kk[k];
+                if (MIN) atomicMin((unsigned long long *)&s_min[rl[k]], (unsigned long long)kk[k]);
+            }
         }
     }
     if (MIN) {

@@ -174,7 +174,7 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     int32_t n, const uint32_t *__restrict__ p, uint64_t *__restrict__ r,
     uint32_t *__restrict__ chunk_wpre, uint32_t *__restrict__ chunk_mask,
     uint32_t *__restrict__ col_out, uint64_t *__restrict__ key_out, uint64_t *status,
-    Counters *cnt, uint32_t *__restrict__ wave_live)
+    Counters *cnt, uint32_t *__restrict__ wave_live, int read_filter)
 {
     constexpr int E = SWEEP_E;
     __shared__ uint32_t s_ticket;
@@ -322,13 +322,13 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     const uint32_t wave_lo = base - lane * E;
     const uint32_t wave_hi = wave_lo + 64 * E;  // exclusive
     auto flush = [&](uint32_t rt, uint64_t v) {
-        if (FIRST && S == 1 && win) {
-            if (v == KEY_INF) return;
-            if (s_rp[rt - lo] >= wave_lo && s_rp[rt + 1 - lo] <= wave_hi) r[rt] = v;
-            else min_into(r, rt, v);
-        } else {
+        if (v == KEY_INF) return;
+        if (FIRST && S == 1 && win && s_rp[rt - lo] >= wave_lo && s_rp[rt + 1 - lo] <= wave_hi)
+            r[rt] = v;
+        else if (read_filter)
             min_into(r, rt, v);
-        }
+        else  // many live roots: few runs share one, so the read would not pay
+            __hip_atomic_fetch_min(r + rt, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
 
     // lane-local runs by root; interior runs are complete and flushed now
@@ -478,18 +478,18 @@ __global__ void k_reduce_live(const uint32_t *__restrict__ wave_live, size_t cou
 }
 
 void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r, Counters *dcnt,
-                  bool first, uint32_t *wave_live)
+                  bool first, uint32_t *wave_live, bool read_filter)
 {
     if (a.nnz == 0) return;
     const unsigned grid = a.sl.maxch * (unsigned)a.sl.S;  // slice = workgroup % S
     if (first)
         k_sweep<false, true><<<grid, SWEEP_BLOCK, 0, s>>>(
             a.row_ptr, a.col, a.key, a.chunk_row, a.sl, a.n, p, r, nullptr, nullptr, nullptr,
-            nullptr, nullptr, dcnt, wave_live);
+            nullptr, nullptr, dcnt, wave_live, read_filter ? 1 : 0);
     else
         k_sweep<false, false><<<grid, SWEEP_BLOCK, 0, s>>>(
             a.row_ptr, a.col, a.key, a.chunk_row, a.sl, a.n, p, r, nullptr, nullptr, nullptr,
-            nullptr, nullptr, dcnt, wave_live);
+            nullptr, nullptr, dcnt, wave_live, read_filter ? 1 : 0);
     if (wave_live) {
         launch_fill_u64(s, &dcnt->live, 0ull, 1);
         const size_t count = (size_t)a.nchunks * (SWEEP_BLOCK / 64);
@@ -499,7 +499,8 @@ void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r, C
 
 void launch_sweep_compact(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
                           uint32_t *row_ptr_out, uint32_t *col_out, uint64_t *key_out,
-                          uint32_t *chunk_info, uint64_t *status, Counters *dcnt)
+                          uint32_t *chunk_info, uint64_t *status, Counters *dcnt,
+                          bool read_filter)
 {
     if (a.nnz == 0) return;
     uint32_t *wpre = chunk_info;
@@ -508,7 +509,7 @@ void launch_sweep_compact(hipStream_t s, const Adj &a, const uint32_t *p, uint64
     launch_fill_u32(s, &dcnt->ticket, 0u, 1);
     k_sweep<true, false><<<a.nchunks, SWEEP_BLOCK, 0, s>>>(
         a.row_ptr, a.col, a.key, a.chunk_row, a.sl, a.n, p, r, wpre, mask, col_out, key_out,
-        status, dcnt, nullptr);
+        status, dcnt, nullptr, read_filter ? 1 : 0);
     size_t g = ((size_t)a.sl.S * ((size_t)a.n + 1) + 255) / 256;
     if (g > 8192) g = 8192;
     k_rowptr_compact<<<(unsigned)g, 256, 0, s>>>(a.row_ptr, a.n, a.sl, wpre, mask, dcnt,

@@ -186,7 +186,7 @@ struct Ctx {
     hipEvent_t sev[2 * 64] = {};  // sweep start/end events, per round
     msf_stats stats{};
     int filter_mode = 1;        // 0 never, 1 adaptive, 2 every round
-    double filter_threshold = 0.80;
+    double filter_threshold = 0.30;
     bool check_rounds = false;  // read back error flags after every shortcut
     // round 1: 0 generic sweep, 1 identity-parent sweep, 2 row minima
     // written by the adjacency build (falls back to 1 where it cannot)
@@ -265,14 +265,17 @@ void launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, size_t n);
 void launch_iota_u32(hipStream_t s, uint32_t *p, size_t n);
 // With wave_live (SWEEP_BLOCK/64 u32 per chunk), dcnt->live receives the
 // number of live entries (p_i != p_j).
+// read_filter: read r before each atomic and skip non-improving updates
+// (needed when many runs share a root); otherwise atomics go straight out.
 void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r, Counters *dcnt,
-                  bool first = false, uint32_t *wave_live = nullptr);
+                  bool first = false, uint32_t *wave_live = nullptr, bool read_filter = true);
 // Sweep that also writes the surviving entries (p_i != p_j) in order to
 // col_out/key_out and their row pointers to row_ptr_out; chunk_info holds
 // chunk_info_words(a.nchunks) u32 of per-chunk survivor masks and prefixes.
 void launch_sweep_compact(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
                           uint32_t *row_ptr_out, uint32_t *col_out, uint64_t *key_out,
-                          uint32_t *chunk_info, uint64_t *status, Counters *dcnt);
+                          uint32_t *chunk_info, uint64_t *status, Counters *dcnt,
+                          bool read_filter = true);
 size_t chunk_info_words(uint32_t nchunks);
 
 // Round kernels.  `status` is a look-back status array (>= tiles entries);
