@@ -48,6 +48,19 @@ __device__ __forceinline__ RunAgg combine(const RunAgg &a, const RunAgg &b)
     return r;
 }
 
+// One step of the wave-wide segmented scan: every field moved by the same
+// DPP control; lanes whose source exists combine it in front of their own.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void scan_step(RunAgg &agg, bool recv)
+{
+    RunAgg o;
+    o.first_root = dpp_u32<CTRL, ROW_MASK>(agg.first_root);
+    o.last_root = dpp_u32<CTRL, ROW_MASK>(agg.last_root);
+    o.hib = dpp_u32<CTRL, ROW_MASK>(agg.hib);
+    o.lrm = dpp_u64<CTRL, ROW_MASK>(agg.lrm);
+    if (recv) agg = combine(o, agg);
+}
+
 }  // namespace
 
 // Rows of a chunk staged in LDS (two per lane); a chunk that spans more
@@ -359,19 +372,18 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     agg.last_root = lroot;
     agg.hib = single ? 0u : 1u;
     agg.lrm = single ? fmin : lmin;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        RunAgg o;
-        o.first_root = __shfl_up(agg.first_root, d, 64);
-        o.last_root = __shfl_up(agg.last_root, d, 64);
-        o.hib = __shfl_up(agg.hib, d, 64);
-        o.lrm = __shfl_up(agg.lrm, d, 64);
-        if (lane >= (uint32_t)d) agg = combine(o, agg);
-    }
-    const uint32_t prev_last = __shfl_up(agg.last_root, 1, 64);
-    const uint64_t prev_lrm = __shfl_up(agg.lrm, 1, 64);
-    uint32_t next_first = __shfl_down(froot, 1, 64);
-    if (lane == 63) next_first = NONE32;
+    // DPP steps (VALU lane moves, no LDS): within rows of 16, then the row
+    // aggregates carried across rows; a lane combines only when its source
+    // lane exists
+    scan_step<DPP_ROW_SHR1, 0xF>(agg, (lane & 15u) >= 1u);
+    scan_step<DPP_ROW_SHR2, 0xF>(agg, (lane & 15u) >= 2u);
+    scan_step<DPP_ROW_SHR4, 0xF>(agg, (lane & 15u) >= 4u);
+    scan_step<DPP_ROW_SHR8, 0xF>(agg, (lane & 15u) >= 8u);
+    scan_step<DPP_ROW_BCAST15, 0xA>(agg, ((lane >> 4) & 1u) != 0u);
+    scan_step<DPP_ROW_BCAST31, 0xC>(agg, (lane >> 4) >= 2u);
+    const uint32_t prev_last = dpp_u32<DPP_WAVE_SHR1>(agg.last_root);
+    const uint64_t prev_lrm = dpp_u64<DPP_WAVE_SHR1>(agg.lrm);
+    const uint32_t next_first = dpp_u32<DPP_WAVE_SHL1>(froot, NONE32);  // lane 63: none
     if (started) {
         uint64_t ffull = fmin;
         if (lane > 0 && prev_last == froot) ffull = ffull < prev_lrm ? ffull : prev_lrm;

@@ -13,23 +13,90 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
+// ---- DPP lane moves (GFX9 encodings; no LDS traffic) -----------------------
+// row_shr:n = 0x110 + n (within rows of 16 lanes), row_bcast:15 = 0x142 (lane
+// 15 of a row to the next row), row_bcast:31 = 0x143 (lane 31 to rows 2-3),
+// wave_shl:1 = 0x130 (lane l reads l+1), wave_shr:1 = 0x138 (lane l reads
+// l-1).  Lanes without a source, or in rows outside ROW_MASK, read `old`.
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114,
+              DPP_ROW_SHR8 = 0x118, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143,
+              DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138;
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v, uint32_t old = 0)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v, uint64_t old = 0)
+{
+    const uint32_t lo = dpp_u32<CTRL, ROW_MASK>((uint32_t)v, (uint32_t)old);
+    const uint32_t hi = dpp_u32<CTRL, ROW_MASK>((uint32_t)(v >> 32), (uint32_t)(old >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// The same for any 4- or 8-byte type (bits moved unchanged).
+template <int CTRL, int ROW_MASK = 0xF, typename T>
+__device__ __forceinline__ T dpp_move(T v)
+{
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte lanes only");
+    T r;
+    if constexpr (sizeof(T) == 4) {
+        uint32_t u;
+        __builtin_memcpy(&u, &v, 4);
+        u = dpp_u32<CTRL, ROW_MASK>(u);
+        __builtin_memcpy(&r, &u, 4);
+    } else {
+        uint64_t u;
+        __builtin_memcpy(&u, &v, 8);
+        u = dpp_u64<CTRL, ROW_MASK>(u);
+        __builtin_memcpy(&r, &u, 8);
+    }
+    return r;
+}
+
+// Inclusive prefix sum over the 64 lanes (all lanes active): Hillis-Steele
+// inside each row of 16, then the row totals carried by row broadcasts.
 template <typename T>
 __device__ __forceinline__ T wave_incl_sum(T v)
 {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        T o = __shfl_up(v, d, 64);
-        if (__lane_id() >= d) v += o;
-    }
+    v += dpp_move<DPP_ROW_SHR1>(v);
+    v += dpp_move<DPP_ROW_SHR2>(v);
+    v += dpp_move<DPP_ROW_SHR4>(v);
+    v += dpp_move<DPP_ROW_SHR8>(v);
+    v += dpp_move<DPP_ROW_BCAST15, 0xA>(v);
+    v += dpp_move<DPP_ROW_BCAST31, 0xC>(v);
     return v;
 }
 
+// Lane 63's value, in every lane.
+template <typename T>
+__device__ __forceinline__ T lane63(T v)
+{
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte lanes only");
+    T r;
+    if constexpr (sizeof(T) == 4) {
+        uint32_t u;
+        __builtin_memcpy(&u, &v, 4);
+        u = (uint32_t)__builtin_amdgcn_readlane((int)u, 63);
+        __builtin_memcpy(&r, &u, 4);
+    } else {
+        uint64_t u;
+        __builtin_memcpy(&u, &v, 8);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+        u = ((uint64_t)hi << 32) | lo;
+        __builtin_memcpy(&r, &u, 8);
+    }
+    return r;
+}
+
+// Sum over the 64 lanes, in every lane (all lanes active).
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
 {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
+    return lane63(wave_incl_sum(v));
 }
 
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
