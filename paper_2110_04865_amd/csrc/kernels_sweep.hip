@@ -63,6 +63,12 @@ __device__ __forceinline__ void scan_step(RunAgg &agg, bool recv)
 
 }  // namespace
 
+// Lazy gathers: entries per lane and root whose column parent is gathered
+// up front (the smallest keys); the rest only if all of those are internal.
+#ifndef SWEEP_LAZY
+#define SWEEP_LAZY 1
+#endif
+
 // Rows of a chunk staged in LDS (two per lane); a chunk that spans more
 // rows (long runs of rows without entries in its slice) searches row_ptr in
 // global memory instead.
@@ -277,16 +283,17 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
         // larger keys than a live one of the same root, so the minima are
         // exact.  Loads are unconditional: lanes with nothing to gather read
         // p[lo], a line the whole wave shares.
+        // am: among the SWEEP_LAZY smallest entries of its root in this lane
         bool am[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            bool m = e >= kb && e < ke;
+            int below = 0;
 #pragma unroll
             for (int f = 0; f < E; ++f)
                 if (f != e && f >= kb && f < ke && root[f] == root[e] &&
                     (ky[f] < ky[e] || (ky[f] == ky[e] && f < e)))
-                    m = false;
-            am[e] = m;
+                    ++below;
+            am[e] = e >= kb && e < ke && below < SWEEP_LAZY;
         }
         uint32_t pa[E];
 #pragma unroll
@@ -298,13 +305,14 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
             live[e] = am[e] && root[e] != pa[e];
             dead_found += (am[e] && root[e] == pa[e]) ? 1u : 0u;
         }
+        // a root needs its other entries only if every gathered one is internal
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            bool nd = false;
+            bool has_live = false;
 #pragma unroll
             for (int f = 0; f < E; ++f)
-                if (am[f] && !live[f] && root[f] == root[e]) nd = true;
-            need[e] = nd && !am[e] && e >= kb && e < ke;
+                if (live[f] && root[f] == root[e]) has_live = true;
+            need[e] = !has_live && !am[e] && e >= kb && e < ke;
             any |= need[e];
         }
         if (__ballot(any)) {

@@ -29,7 +29,10 @@ constexpr uint32_t NONE32 = 0xFFFFFFFFu;
 
 // Sweep geometry: a workgroup of SWEEP_BLOCK lanes handles SWEEP_E
 // consecutive entries per lane (one chunk of SWEEP_BLOCK*SWEEP_E entries).
-constexpr int SWEEP_BLOCK = 256;
+#ifndef SWEEP_BLOCK_LANES
+#define SWEEP_BLOCK_LANES 256
+#endif
+constexpr int SWEEP_BLOCK = SWEEP_BLOCK_LANES;
 constexpr int SWEEP_E = 4;
 constexpr int SWEEP_CHUNK = SWEEP_BLOCK * SWEEP_E;
 // Column/key arrays are allocated SWEEP_PAD entries beyond their capacity:
