@@ -31,7 +31,7 @@
  *    the call is synchronous.  MSF_MEM_DEVICE: device memory on the context's
  *    device; work is ordered on the context's stream, and the call returns
  *    after its host scalar outputs are known (which synchronises the stream).
- *  - Errors: MSF_EINVAL for bad arguments (n < 0, m < 0, m > 2^31-1, an
+ *  - Errors: MSF_EINVAL for bad arguments (n < 0, m < 0, m > MSF_MAX_EDGES, an
  *    endpoint outside [0, n), a NaN weight, NULL with a nonzero size, a
  *    parent vector that is not a rooted forest), MSF_ENOMEM when device or
  *    host memory cannot be allocated, MSF_EDEVICE for a HIP runtime failure,
@@ -56,6 +56,14 @@ typedef enum {
     MSF_EBUDGET = 4,
     MSF_ENOTFOUND = 5
 } msf_status;
+
+/*
+ * Largest edge count per graph (per batch, in total): 2^31 - 2048.  Edge ids
+ * must stay below the 32-bit empty-key sentinel, and the adjacency stores
+ * both directions (2m entries) with 32-bit positions plus one 1024-entry
+ * sweep chunk of padding.
+ */
+#define MSF_MAX_EDGES 2147481600LL
 
 typedef enum { MSF_W_U32 = 0, MSF_W_F32 = 1 } msf_wtype;
 typedef enum { MSF_MEM_HOST = 0, MSF_MEM_DEVICE = 1 } msf_mem;
@@ -110,7 +118,7 @@ const char *msf_version(void);
 /*
  * Minimum spanning forest (section 2 problem statement; Algorithm 2 with
  * complete shortcutting, section 4.2).
- *   n, m            vertex and edge counts (n >= 0, 0 <= m <= 2^31-1)
+ *   n, m            vertex and edge counts (n >= 0, 0 <= m <= MSF_MAX_EDGES)
  *   edges           int32[2m] endpoint pairs        (host or device per mem)
  *   weights         uint32[m] or float32[m] per wtype (host or device)
  *   forest_ids      int32[>= max(n-1,0)] out: forest edge ids, ascending

@@ -215,7 +215,7 @@ static msf_status check_graph_args(msf_ctx *ctx, int32_t n, int64_t m, const int
         set_error("ctx is NULL");
         return MSF_EINVAL;
     }
-    if (n < 0 || m < 0 || m > 0x7FFFFFFFll) {
+    if (n < 0 || m < 0 || m > MSF_MAX_EDGES) {
         set_error("bad sizes n=%d m=%lld", (int)n, (long long)m);
         return MSF_EINVAL;
     }

@@ -227,7 +227,7 @@ extern "C" msf_status msf_solve_batched(msf_ctx *ctx, int32_t G, const int64_t *
         }
     }
     const int64_t N = vtx_off[G], M = edge_off[G];
-    if (N > 0x7FFFFFFFll || M > 0x7FFFFFFFll) {
+    if (N > 0x7FFFFFFFll || M > MSF_MAX_EDGES) {
         set_error("batch too large: %lld vertices, %lld edges", (long long)N, (long long)M);
         return MSF_EINVAL;
     }

@@ -212,15 +212,16 @@ __global__ __launch_bounds__(256) void k_tl_hist2(const uint32_t *__restrict__ r
     uint32_t c, j;
     if (!l2_block(P, NC, blockIdx.x, &c, &j)) return;
     const uint32_t a = cs[c] + j * (uint32_t)TL_E2;
-    const uint32_t e = a + TL_E2 < cs[c + 1] ? a + TL_E2 : cs[c + 1];
+    // 64-bit: a + TL_E2 can pass 2^32 near the largest adjacencies
+    const uint32_t e = (uint64_t)a + TL_E2 < (uint64_t)cs[c + 1] ? a + TL_E2 : cs[c + 1];
     for (int s = threadIdx.x; s < nsub; s += 256) s_h[s] = 0;
     __syncthreads();
     const uint32_t mask = (uint32_t)nsub - 1u;
-    for (uint32_t b = a; b < e; b += 256 * 8) {
+    for (uint64_t b = a; b < e; b += 256 * 8) {
         uint32_t rr[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const uint32_t i = b + threadIdx.x + 256u * k;
+            const uint64_t i = b + threadIdx.x + 256u * k;
             rr[k] = i < e ? row1[i] : NONE32;
         }
 #pragma unroll
@@ -250,17 +251,17 @@ __global__ __launch_bounds__(TL_NT) void k_part_sub(
     uint32_t c, j;
     if (!l2_block(P, NC, blockIdx.x, &c, &j)) return;
     const uint32_t a = cs[c] + j * (uint32_t)TL_E2;
-    const uint32_t e = a + TL_E2 < cs[c + 1] ? a + TL_E2 : cs[c + 1];
+    // 64-bit: a + TL_E2 can pass 2^32 near the largest adjacencies
+    const uint32_t e = (uint64_t)a + TL_E2 < (uint64_t)cs[c + 1] ? a + TL_E2 : cs[c + 1];
     const uint32_t mask = (uint32_t)nsub - 1u;
     for (int s = threadIdx.x; s < nsub; s += TL_NT) s_run[s] = o2[t2_index(P, nb2, nsub, c, s, j)];
-    for (uint32_t t0 = a; t0 < e; t0 += TL_TILE) {
-        const uint32_t t1 = t0 + TL_TILE < e ? t0 + TL_TILE : e;
+    for (uint64_t t0 = a; t0 < e; t0 += TL_TILE) {
         uint32_t rr[TL_SP], cc[TL_SP];
         uint64_t kk[TL_SP];
 #pragma unroll
         for (int k = 0; k < TL_SP; ++k) {
-            const uint32_t i = t0 + threadIdx.x + (uint32_t)k * TL_NT;
-            const bool in = i < t1;
+            const uint64_t i = t0 + threadIdx.x + (uint32_t)k * TL_NT;
+            const bool in = i < e;
             rr[k] = in ? row1[i] : NONE32;
             cc[k] = in ? col1[i] : 0u;
             kk[k] = in ? key1[i] : 0ull;
@@ -347,7 +348,7 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
         uint64_t kk[TC_PT];
 #pragma unroll
         for (int k = 0; k < TC_PT; ++k) {
-            const uint32_t i = fs + threadIdx.x + (uint32_t)k * TC_NT;
+            const uint64_t i = (uint64_t)fs + threadIdx.x + (uint32_t)k * TC_NT;
             const bool in = i < fe;
             rl[k] = in ? row2[i] - (uint32_t)row0 : NONE32;
             cc[k] = in ? col2[i] : 0u;
@@ -372,11 +373,11 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
             key[fs + p] = kk[k];
         }
     } else {
-        for (uint32_t b = fs; b < fe; b += TC_NT * TC_PT) {
+        for (uint64_t b = fs; b < fe; b += TC_NT * TC_PT) {
             uint32_t rl[TC_PT];
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k) {
-                const uint32_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
+                const uint64_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
                 rl[k] = i < fe ? row2[i] - (uint32_t)row0 : NONE32;
             }
 #pragma unroll
@@ -388,12 +389,12 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
         for (uint32_t i = threadIdx.x; i < rows; i += TC_NT) row_ptr[row0 + i] = fs + s_cnt[i];
         if (row0 + rows == (int64_t)n && threadIdx.x == 0) row_ptr[n] = fe;
         __syncthreads();
-        for (uint32_t b = fs; b < fe; b += TC_NT * TC_PT) {
+        for (uint64_t b = fs; b < fe; b += TC_NT * TC_PT) {
             uint32_t rl[TC_PT], cc[TC_PT];
             uint64_t kk[TC_PT];
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k) {
-                const uint32_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
+                const uint64_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
                 const bool in = i < fe;
                 rl[k] = in ? row2[i] - (uint32_t)row0 : NONE32;
                 cc[k] = in ? col2[i] : 0u;

@@ -407,7 +407,7 @@ void msf_server_destroy(msf_server *s)
 msf_status msf_server_submit(msf_server *s, int32_t n, int64_t m, const int32_t *edges,
                              const void *weights, msf_wtype wt, uint64_t *ticket)
 {
-    if (!s || !ticket || n < 0 || m < 0 || m > 0x7FFFFFFFll || (m > 0 && (!edges || !weights)) ||
+    if (!s || !ticket || n < 0 || m < 0 || m > MSF_MAX_EDGES || (m > 0 && (!edges || !weights)) ||
         (wt != MSF_W_U32 && wt != MSF_W_F32)) {
         set_error("bad arguments");
         return MSF_EINVAL;

@@ -21,6 +21,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 U32, F32 = oracle.W_U32, oracle.W_F32
+MSF_MAX_EDGES = 2 ** 31 - 2048  # include/msf.h
 
 
 def say(*a):
@@ -173,6 +174,17 @@ def test_invalid_inputs_leave_outputs_untouched(ctx, pkg):
         assert cnt.value == -9 and (ids == -5).all() and tot.u64 == 123
     with pytest.raises(pkg.MSFError):
         ctx.solve(-1, np.zeros((0, 2), np.int32), np.zeros(0, np.uint32), wtype=U32)
+    # edge counts above the limit are rejected before any array is touched
+    e = np.zeros((1, 2), np.int32)
+    w = np.zeros(1, np.uint32)
+    for m in (MSF_MAX_EDGES + 1, 2 ** 31 - 1, 2 ** 31):
+        say("invalid m", m)
+        ids = np.full(4, -5, np.int32)
+        cnt = ctypes.c_int64(-9)
+        rc = L.msf_solve(ctx._h, 3, m, ctypes.c_void_p(e.ctypes.data),
+                         ctypes.c_void_p(w.ctypes.data), U32, 0,
+                         ctypes.c_void_p(ids.ctypes.data), ctypes.byref(cnt), None)
+        assert rc == 1 and cnt.value == -9 and (ids == -5).all(), m
 
 
 # ---------------------------------------------------- per-round behaviour --
