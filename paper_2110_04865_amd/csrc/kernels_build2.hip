@@ -10,7 +10,7 @@
 //       (bucket, block) its offset (shared with the one-level build);
 //   B1. the same blocks expand each edge into its two stored directions,
 //       sort LDS tiles of them by coarse bucket and write each bucket's run
-//       of the tile contiguously (row, column, key as three arrays);
+//       of the tile contiguously;
 //   P.  a plan: per coarse bucket, how many level-2 workgroups (TL_E2
 //       entries each) cover it, and their prefix;
 //   A2. each level-2 workgroup counts its entries per fine bucket (rows
@@ -22,7 +22,9 @@
 //       in one coalesced sweep (buckets larger than LDS scatter directly).
 //       In the solve it also keeps each row's smallest key: round 1 of the
 //       multilinear sweep, where the parent vector is the identity.
-// Every atomic is an LDS atomic.
+// Every atomic is an LDS atomic.  Between the passes an entry is one
+// 16-byte record (row, column, key): one vector load or store per entry, and
+// one run per bucket in flight instead of three.
 #include "msf_internal.hpp"
 #include "wave.hpp"
 
@@ -89,6 +91,16 @@ __device__ __forceinline__ size_t t2_index(const uint32_t *__restrict__ P,
     return (size_t)nsub * P[c] + (size_t)sub * nb2[c] + j;
 }
 
+// An entry between the passes: x = row, y = column, (z, w) = key.
+__device__ __forceinline__ uint4 make_ent(uint32_t row, uint32_t col, uint64_t key)
+{
+    return make_uint4(row, col, (uint32_t)key, (uint32_t)(key >> 32));
+}
+__device__ __forceinline__ uint64_t ent_key(const uint4 &x)
+{
+    return ((uint64_t)x.w << 32) | x.z;
+}
+
 }  // namespace
 
 // B1: edges -> coarse buckets, LDS-sorted tiles, runs written contiguously.
@@ -101,10 +113,9 @@ template <int WT>
 __global__ __launch_bounds__(TL_NT) void k_part_edges(
     const int32_t *__restrict__ edges, const void *__restrict__ w, int64_t m, int32_t n, int L1,
     int NC, int64_t epb, uint32_t nblk, const uint32_t *__restrict__ bo1,
-    uint32_t *__restrict__ orow, uint32_t *__restrict__ ocol, uint64_t *__restrict__ okey)
+    uint4 *__restrict__ o1)
 {
-    __shared__ uint32_t s_row[TL_TILE], s_col[TL_TILE];
-    __shared__ uint64_t s_key[TL_TILE];
+    __shared__ uint4 s_ent[TL_TILE];
     __shared__ uint32_t s_run[TL_MAX_NC], s_pos[TL_MAX_NC];
     __shared__ uint32_t s_scr[TL_NT / 64 + 1];
     for (int c = threadIdx.x; c < NC; c += TL_NT) s_run[c] = bo1[(size_t)c * nblk + blockIdx.x];
@@ -147,23 +158,14 @@ __global__ __launch_bounds__(TL_NT) void k_part_edges(
             if (WT == MSF_W_F32) wk = wkey_f32_bits(wk);
             const uint64_t key = ((uint64_t)wk << 32) | (uint64_t)(uint32_t)e;
             const uint32_t u = (uint32_t)eu[k], v = (uint32_t)ev[k];
-            const uint32_t pu = s_pos[u >> L1] + ru[k];
-            s_row[pu] = u;
-            s_col[pu] = v;
-            s_key[pu] = key;
-            const uint32_t pv = s_pos[v >> L1] + rv[k];
-            s_row[pv] = v;
-            s_col[pv] = u;
-            s_key[pv] = key;
+            s_ent[s_pos[u >> L1] + ru[k]] = make_ent(u, v, key);
+            s_ent[s_pos[v >> L1] + rv[k]] = make_ent(v, u, key);
         }
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < cnt; i += TL_NT) {
-            const uint32_t row = s_row[i];
-            const uint32_t c = row >> L1;
-            const uint32_t pos = s_run[c] + (i - s_pos[c]);
-            orow[pos] = row;
-            ocol[pos] = s_col[i];
-            okey[pos] = s_key[i];
+            const uint4 x = s_ent[i];
+            const uint32_t c = x.x >> L1;
+            o1[s_run[c] + (i - s_pos[c])] = x;
         }
         __syncthreads();
         for (int c = threadIdx.x; c < NC; c += TL_NT) {
@@ -202,7 +204,7 @@ __global__ __launch_bounds__(1024) void k_tl_plan(const uint32_t *__restrict__ b
 }
 
 // A2: per level-2 workgroup, its entries per fine bucket.
-__global__ __launch_bounds__(256) void k_tl_hist2(const uint32_t *__restrict__ row1, int L2,
+__global__ __launch_bounds__(256) void k_tl_hist2(const uint4 *__restrict__ e1, int L2,
                                                   int nsub, int NC, const uint32_t *__restrict__ cs,
                                                   const uint32_t *__restrict__ nb2,
                                                   const uint32_t *__restrict__ P,
@@ -222,7 +224,7 @@ __global__ __launch_bounds__(256) void k_tl_hist2(const uint32_t *__restrict__ r
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const uint64_t i = b + threadIdx.x + 256u * k;
-            rr[k] = i < e ? row1[i] : NONE32;
+            rr[k] = i < e ? reinterpret_cast<const uint32_t *>(e1)[4 * i] : NONE32;
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k)
@@ -238,14 +240,11 @@ __global__ __launch_bounds__(256) void k_tl_hist2(const uint32_t *__restrict__ r
 constexpr int TL_SP = TL_TILE / TL_NT;  // entries per thread per tile
 
 __global__ __launch_bounds__(TL_NT) void k_part_sub(
-    const uint32_t *__restrict__ row1, const uint32_t *__restrict__ col1,
-    const uint64_t *__restrict__ key1, int L2, int nsub, int NC, const uint32_t *__restrict__ cs,
+    const uint4 *__restrict__ e1, int L2, int nsub, int NC, const uint32_t *__restrict__ cs,
     const uint32_t *__restrict__ nb2, const uint32_t *__restrict__ P,
-    const uint32_t *__restrict__ o2, uint32_t *__restrict__ row2, uint32_t *__restrict__ col2,
-    uint64_t *__restrict__ key2)
+    const uint32_t *__restrict__ o2, uint4 *__restrict__ e2)
 {
-    __shared__ uint32_t s_row[TL_TILE], s_col[TL_TILE];
-    __shared__ uint64_t s_key[TL_TILE];
+    __shared__ uint4 s_ent[TL_TILE];
     __shared__ uint32_t s_run[TL_MAX_NSUB], s_pos[TL_MAX_NSUB];
     __shared__ uint32_t s_scr[TL_NT / 64 + 1];
     uint32_t c, j;
@@ -256,40 +255,28 @@ __global__ __launch_bounds__(TL_NT) void k_part_sub(
     const uint32_t mask = (uint32_t)nsub - 1u;
     for (int s = threadIdx.x; s < nsub; s += TL_NT) s_run[s] = o2[t2_index(P, nb2, nsub, c, s, j)];
     for (uint64_t t0 = a; t0 < e; t0 += TL_TILE) {
-        uint32_t rr[TL_SP], cc[TL_SP];
-        uint64_t kk[TL_SP];
+        uint4 xx[TL_SP];
 #pragma unroll
         for (int k = 0; k < TL_SP; ++k) {
             const uint64_t i = t0 + threadIdx.x + (uint32_t)k * TL_NT;
-            const bool in = i < e;
-            rr[k] = in ? row1[i] : NONE32;
-            cc[k] = in ? col1[i] : 0u;
-            kk[k] = in ? key1[i] : 0ull;
+            xx[k] = i < e ? e1[i] : make_uint4(NONE32, 0u, 0u, 0u);
         }
         for (int s = threadIdx.x; s < nsub; s += TL_NT) s_pos[s] = 0;
         __syncthreads();
         uint32_t rk[TL_SP];  // rank in the fine bucket within the tile
 #pragma unroll
         for (int k = 0; k < TL_SP; ++k)
-            rk[k] = rr[k] != NONE32 ? atomicAdd(&s_pos[(rr[k] >> L2) & mask], 1u) : 0u;
+            rk[k] = xx[k].x != NONE32 ? atomicAdd(&s_pos[(xx[k].x >> L2) & mask], 1u) : 0u;
         __syncthreads();
         const uint32_t cnt = lds_excl_scan<TL_NT>(s_pos, nsub, s_scr);  // s_pos: starts
 #pragma unroll
-        for (int k = 0; k < TL_SP; ++k) {
-            if (rr[k] == NONE32) continue;
-            const uint32_t p = s_pos[(rr[k] >> L2) & mask] + rk[k];
-            s_row[p] = rr[k];
-            s_col[p] = cc[k];
-            s_key[p] = kk[k];
-        }
+        for (int k = 0; k < TL_SP; ++k)
+            if (xx[k].x != NONE32) s_ent[s_pos[(xx[k].x >> L2) & mask] + rk[k]] = xx[k];
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < cnt; i += TL_NT) {
-            const uint32_t row = s_row[i];
-            const uint32_t s = (row >> L2) & mask;
-            const uint32_t pos = s_run[s] + (i - s_pos[s]);
-            row2[pos] = row;
-            col2[pos] = s_col[i];
-            key2[pos] = s_key[i];
+            const uint4 x = s_ent[i];
+            const uint32_t s = (x.x >> L2) & mask;
+            e2[s_run[s] + (i - s_pos[s])] = x;
         }
         __syncthreads();
         for (int s = threadIdx.x; s < nsub; s += TL_NT) {
@@ -321,8 +308,7 @@ __global__ void k_tl_fstart(const uint32_t *__restrict__ o2, const uint32_t *__r
 // also store each row's smallest key into r (round 1 of the sweep).
 template <bool MIN>
 __global__ __launch_bounds__(TC_NT) void k_tl_place(
-    const uint32_t *__restrict__ row2, const uint32_t *__restrict__ col2,
-    const uint64_t *__restrict__ key2, int32_t n, int L2, const uint32_t *__restrict__ fstart,
+    const uint4 *__restrict__ e2, int32_t n, int L2, const uint32_t *__restrict__ fstart,
     uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ col, uint64_t *__restrict__ key,
     uint64_t *__restrict__ r)
 {
@@ -349,10 +335,10 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
 #pragma unroll
         for (int k = 0; k < TC_PT; ++k) {
             const uint64_t i = (uint64_t)fs + threadIdx.x + (uint32_t)k * TC_NT;
-            const bool in = i < fe;
-            rl[k] = in ? row2[i] - (uint32_t)row0 : NONE32;
-            cc[k] = in ? col2[i] : 0u;
-            kk[k] = in ? key2[i] : 0ull;
+            const uint4 x = i < fe ? e2[i] : make_uint4(NONE32, 0u, 0u, 0u);
+            rl[k] = x.x != NONE32 ? x.x - (uint32_t)row0 : NONE32;
+            cc[k] = x.y;
+            kk[k] = ent_key(x);
         }
 #pragma unroll
         for (int k = 0; k < TC_PT; ++k) {
@@ -378,7 +364,7 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k) {
                 const uint64_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
-                rl[k] = i < fe ? row2[i] - (uint32_t)row0 : NONE32;
+                rl[k] = i < fe ? e2[i].x - (uint32_t)row0 : NONE32;
             }
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k)
@@ -395,10 +381,10 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k) {
                 const uint64_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
-                const bool in = i < fe;
-                rl[k] = in ? row2[i] - (uint32_t)row0 : NONE32;
-                cc[k] = in ? col2[i] : 0u;
-                kk[k] = in ? key2[i] : 0ull;
+                const uint4 x = i < fe ? e2[i] : make_uint4(NONE32, 0u, 0u, 0u);
+                rl[k] = x.x != NONE32 ? x.x - (uint32_t)row0 : NONE32;
+                cc[k] = x.y;
+                kk[k] = ent_key(x);
             }
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k) {
@@ -471,15 +457,11 @@ msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
     const size_t cap = 2 * (size_t)m;  // stored entries, at most
     const size_t g2max = (cap + TL_E2 - 1) / TL_E2 + (size_t)NC;
     const size_t nt2 = (size_t)tl.nsub * g2max;
-    void *vbh, *vbo, *vr1, *vc1, *vk1, *vr2, *vc2, *vk2, *vplan, *vt2, *vo2;
+    void *vbh, *vbo, *ve1, *ve2, *vplan, *vt2, *vo2;
     MSF_TRY(ws_get(c, WS_BH, 4 * nh, &vbh));
     MSF_TRY(ws_get(c, WS_BHOFF, 4 * (nh + 1), &vbo));
-    MSF_TRY(ws_get(c, WS_BRLO, 4 * cap, &vr1));
-    MSF_TRY(ws_get(c, WS_BCOL, 4 * cap, &vc1));
-    MSF_TRY(ws_get(c, WS_BKEY, 8 * cap, &vk1));
-    MSF_TRY(ws_get(c, WS_L2ROW, 4 * cap, &vr2));
-    MSF_TRY(ws_get(c, WS_L2COL, 4 * cap, &vc2));
-    MSF_TRY(ws_get(c, WS_L2KEY, 8 * cap, &vk2));
+    MSF_TRY(ws_get(c, WS_TL1, 16 * cap, &ve1));
+    MSF_TRY(ws_get(c, WS_TL2, 16 * cap, &ve2));
     MSF_TRY(ws_get(c, WS_TLPLAN, 4 * (3 * (size_t)NC + 3), &vplan));
     MSF_TRY(ws_get(c, WS_T2, 4 * nt2, &vt2));
     MSF_TRY(ws_get(c, WS_T2OFF, 4 * (nt2 + 1), &vo2));
@@ -490,9 +472,7 @@ msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
     uint32_t *bh = (uint32_t *)vbh, *bo = (uint32_t *)vbo;
     uint32_t *cs = (uint32_t *)vplan, *nb2 = cs + NC + 1, *P = nb2 + NC;
     uint32_t *t2 = (uint32_t *)vt2, *o2 = (uint32_t *)vo2;
-    uint32_t *r1 = (uint32_t *)vr1, *c1 = (uint32_t *)vc1, *r2 = (uint32_t *)vr2,
-             *c2 = (uint32_t *)vc2;
-    uint64_t *k1 = (uint64_t *)vk1, *k2 = (uint64_t *)vk2;
+    uint4 *e1 = (uint4 *)ve1, *e2 = (uint4 *)ve2;
 
     // A1 (coarse histogram; also validates endpoints and weights) + scan
     MSF_TRY(launch_bucket_hist(c, d_edges, d_w, m, n, tl.L1, NC, (uint32_t)n, (uint32_t)NC, epb,
@@ -501,27 +481,24 @@ msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
     // B1
     if (wt == MSF_W_F32)
         k_part_edges<MSF_W_F32><<<nblk, TL_NT, 0, s>>>(d_edges, d_w, m, n, tl.L1, NC, epb, nblk,
-                                                       bo, r1, c1, k1);
+                                                       bo, e1);
     else
         k_part_edges<MSF_W_U32><<<nblk, TL_NT, 0, s>>>(d_edges, d_w, m, n, tl.L1, NC, epb, nblk,
-                                                       bo, r1, c1, k1);
+                                                       bo, e1);
     // P, A2, scan, B2
     k_tl_plan<<<1, 1024, 0, s>>>(bo, nblk, NC, cs, nb2, P);
     launch_fill_u32(s, t2, 0u, nt2);
-    k_tl_hist2<<<(unsigned)g2max, 256, 0, s>>>(r1, tl.L2, tl.nsub, NC, cs, nb2, P, t2);
+    k_tl_hist2<<<(unsigned)g2max, 256, 0, s>>>(e1, tl.L2, tl.nsub, NC, cs, nb2, P, t2);
     MSF_TRY(scan_u32(c, t2, o2, (int64_t)nt2, nullptr));
-    k_part_sub<<<(unsigned)g2max, TL_NT, 0, s>>>(r1, c1, k1, tl.L2, tl.nsub, NC, cs, nb2, P, o2,
-                                                  r2, c2, k2);
+    k_part_sub<<<(unsigned)g2max, TL_NT, 0, s>>>(e1, tl.L2, tl.nsub, NC, cs, nb2, P, o2, e2);
     // C
     const unsigned nf = (unsigned)NC * (unsigned)tl.nsub;
     k_tl_fstart<<<(nf + 256) / 256, 256, 0, s>>>(o2, nb2, P, tl.nsub, NC, fst);
     const size_t R = (size_t)1 << tl.L2;
     if (r_first)
-        k_tl_place<true><<<nf, TC_NT, 12 * R, s>>>(r2, c2, k2, n, tl.L2, fst, row_ptr, col, key,
-                                                   r_first);
+        k_tl_place<true><<<nf, TC_NT, 12 * R, s>>>(e2, n, tl.L2, fst, row_ptr, col, key, r_first);
     else
-        k_tl_place<false><<<nf, TC_NT, 4 * R, s>>>(r2, c2, k2, n, tl.L2, fst, row_ptr, col, key,
-                                                   nullptr);
+        k_tl_place<false><<<nf, TC_NT, 4 * R, s>>>(e2, n, tl.L2, fst, row_ptr, col, key, nullptr);
     MSF_HIP(hipGetLastError());
     return MSF_OK;
 }
