@@ -10,12 +10,13 @@
 //       (bucket, block) its offset (shared with the one-level build);
 //   B1. the same blocks expand each edge into its two stored directions,
 //       sort LDS tiles of them by coarse bucket and write each bucket's run
-//       of the tile contiguously;
+//       of the tile contiguously, and beside it each entry's fine bucket
+//       within its coarse bucket as one byte;
 //   P.  a plan: per coarse bucket, how many level-2 workgroups (TL_E2
 //       entries each) cover it, and their prefix;
 //   A2. each level-2 workgroup counts its entries per fine bucket (rows
-//       [f << L2, (f+1) << L2)); the counts are laid out so one scan makes
-//       each fine bucket contiguous, in row order;
+//       [f << L2, (f+1) << L2)) from those bytes; the counts are laid out
+//       so one scan makes each fine bucket contiguous, in row order;
 //   B2. the level-2 workgroups sort LDS tiles by fine bucket and write runs;
 //   C.  one workgroup per fine bucket counts its rows, scans them into
 //       row_ptr, places the entries in LDS by row and writes the bucket out
@@ -112,9 +113,10 @@ constexpr int TL_EP = TL_TILE / 2 / TL_NT;  // edges per thread per tile
 template <int WT>
 __global__ __launch_bounds__(TL_NT) void k_part_edges(
     const int32_t *__restrict__ edges, const void *__restrict__ w, int64_t m, int32_t n, int L1,
-    int NC, int64_t epb, uint32_t nblk, const uint32_t *__restrict__ bo1,
-    uint4 *__restrict__ o1)
+    int NC, int64_t epb, uint32_t nblk, const uint32_t *__restrict__ bo1, int L2,
+    uint4 *__restrict__ o1, uint8_t *__restrict__ sub1)
 {
+    const uint32_t smask = (1u << (L1 - L2)) - 1u;
     __shared__ uint4 s_ent[TL_TILE];
     __shared__ uint32_t s_run[TL_MAX_NC], s_pos[TL_MAX_NC];
     __shared__ uint32_t s_scr[TL_NT / 64 + 1];
@@ -165,7 +167,9 @@ __global__ __launch_bounds__(TL_NT) void k_part_edges(
         for (uint32_t i = threadIdx.x; i < cnt; i += TL_NT) {
             const uint4 x = s_ent[i];
             const uint32_t c = x.x >> L1;
-            o1[s_run[c] + (i - s_pos[c])] = x;
+            const uint32_t pos = s_run[c] + (i - s_pos[c]);
+            o1[pos] = x;
+            sub1[pos] = (uint8_t)((x.x >> L2) & smask);
         }
         __syncthreads();
         for (int c = threadIdx.x; c < NC; c += TL_NT) {
@@ -203,8 +207,9 @@ __global__ __launch_bounds__(1024) void k_tl_plan(const uint32_t *__restrict__ b
     }
 }
 
-// A2: per level-2 workgroup, its entries per fine bucket.
-__global__ __launch_bounds__(256) void k_tl_hist2(const uint4 *__restrict__ e1, int L2,
+// A2: per level-2 workgroup, its entries per fine bucket, read from the
+// fine-bucket bytes four at a time (the byte array is padded to whole words).
+__global__ __launch_bounds__(256) void k_tl_hist2(const uint8_t *__restrict__ sub1,
                                                   int nsub, int NC, const uint32_t *__restrict__ cs,
                                                   const uint32_t *__restrict__ nb2,
                                                   const uint32_t *__restrict__ P,
@@ -218,17 +223,25 @@ __global__ __launch_bounds__(256) void k_tl_hist2(const uint4 *__restrict__ e1, 
     const uint32_t e = (uint64_t)a + TL_E2 < (uint64_t)cs[c + 1] ? a + TL_E2 : cs[c + 1];
     for (int s = threadIdx.x; s < nsub; s += 256) s_h[s] = 0;
     __syncthreads();
-    const uint32_t mask = (uint32_t)nsub - 1u;
-    for (uint64_t b = a; b < e; b += 256 * 8) {
-        uint32_t rr[8];
+    const uint32_t *sw = reinterpret_cast<const uint32_t *>(sub1);
+    const uint32_t w0 = a >> 2, w1 = (uint32_t)(((uint64_t)e + 3) >> 2);
+    for (uint64_t b = w0; b < w1; b += 256 * 4) {
+        uint32_t ww[4];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < 4; ++k) {
             const uint64_t i = b + threadIdx.x + 256u * k;
-            rr[k] = i < e ? reinterpret_cast<const uint32_t *>(e1)[4 * i] : NONE32;
+            ww[k] = i < w1 ? sw[i] : 0u;
         }
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-            if (rr[k] != NONE32) atomicAdd(&s_h[(rr[k] >> L2) & mask], 1u);
+        for (int k = 0; k < 4; ++k) {
+            const uint64_t i = b + threadIdx.x + 256u * k;
+            if (i >= w1) continue;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint64_t pos = 4 * i + t;
+                if (pos >= a && pos < e) atomicAdd(&s_h[(ww[k] >> (8 * t)) & 0xFFu], 1u);
+            }
+        }
     }
     __syncthreads();
     for (int s = threadIdx.x; s < nsub; s += 256) t2[t2_index(P, nb2, nsub, c, s, j)] = s_h[s];
@@ -457,11 +470,12 @@ msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
     const size_t cap = 2 * (size_t)m;  // stored entries, at most
     const size_t g2max = (cap + TL_E2 - 1) / TL_E2 + (size_t)NC;
     const size_t nt2 = (size_t)tl.nsub * g2max;
-    void *vbh, *vbo, *ve1, *ve2, *vplan, *vt2, *vo2;
+    void *vbh, *vbo, *ve1, *ve2, *vsub, *vplan, *vt2, *vo2;
     MSF_TRY(ws_get(c, WS_BH, 4 * nh, &vbh));
     MSF_TRY(ws_get(c, WS_BHOFF, 4 * (nh + 1), &vbo));
     MSF_TRY(ws_get(c, WS_TL1, 16 * cap, &ve1));
     MSF_TRY(ws_get(c, WS_TL2, 16 * cap, &ve2));
+    MSF_TRY(ws_get(c, WS_TLSUB, cap + 4, &vsub));
     MSF_TRY(ws_get(c, WS_TLPLAN, 4 * (3 * (size_t)NC + 3), &vplan));
     MSF_TRY(ws_get(c, WS_T2, 4 * nt2, &vt2));
     MSF_TRY(ws_get(c, WS_T2OFF, 4 * (nt2 + 1), &vo2));
@@ -473,6 +487,7 @@ msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
     uint32_t *cs = (uint32_t *)vplan, *nb2 = cs + NC + 1, *P = nb2 + NC;
     uint32_t *t2 = (uint32_t *)vt2, *o2 = (uint32_t *)vo2;
     uint4 *e1 = (uint4 *)ve1, *e2 = (uint4 *)ve2;
+    uint8_t *sub1 = (uint8_t *)vsub;
 
     // A1 (coarse histogram; also validates endpoints and weights) + scan
     MSF_TRY(launch_bucket_hist(c, d_edges, d_w, m, n, tl.L1, NC, (uint32_t)n, (uint32_t)NC, epb,
@@ -481,14 +496,14 @@ msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
     // B1
     if (wt == MSF_W_F32)
         k_part_edges<MSF_W_F32><<<nblk, TL_NT, 0, s>>>(d_edges, d_w, m, n, tl.L1, NC, epb, nblk,
-                                                       bo, e1);
+                                                       bo, tl.L2, e1, sub1);
     else
         k_part_edges<MSF_W_U32><<<nblk, TL_NT, 0, s>>>(d_edges, d_w, m, n, tl.L1, NC, epb, nblk,
-                                                       bo, e1);
+                                                       bo, tl.L2, e1, sub1);
     // P, A2, scan, B2
     k_tl_plan<<<1, 1024, 0, s>>>(bo, nblk, NC, cs, nb2, P);
     launch_fill_u32(s, t2, 0u, nt2);
-    k_tl_hist2<<<(unsigned)g2max, 256, 0, s>>>(e1, tl.L2, tl.nsub, NC, cs, nb2, P, t2);
+    k_tl_hist2<<<(unsigned)g2max, 256, 0, s>>>(sub1, tl.nsub, NC, cs, nb2, P, t2);
     MSF_TRY(scan_u32(c, t2, o2, (int64_t)nt2, nullptr));
     k_part_sub<<<(unsigned)g2max, TL_NT, 0, s>>>(e1, tl.L2, tl.nsub, NC, cs, nb2, P, o2, e2);
     // C

@@ -455,14 +455,23 @@ def test_first_round_modes_agree(pkg):
 def test_build_modes_agree(pkg):
     """The device-atomic (0), two-level bucketed (1, default) and one-level
     bucketed (2) adjacency builds give the same forest: skewed R-MAT rows far
-    larger than a placement workgroup's LDS, a grid, a multigraph with loops,
-    and a graph with more vertices than edges."""
+    larger than a placement workgroup's LDS, the same kind of graph with ids
+    sorted by degree (the first coarse bucket then holds over a million
+    entries, more level-2 windows than a placement workgroup gathers at
+    once), a grid, a multigraph with loops, and a graph with more vertices
+    than edges."""
     rng = np.random.default_rng(31)
     nm = 3000
     multi_e = rng.integers(0, nm, size=(20000, 2)).astype(np.int32)
     multi_w = rng.integers(0, 50, size=20000).astype(np.uint32)
+    ns, es, ws = gen.rmat(16, 32, seed=35)
+    deg = np.bincount(es.reshape(-1), minlength=ns)
+    newid = np.empty(ns, dtype=np.int32)
+    newid[np.argsort(-deg, kind="stable")] = np.arange(ns, dtype=np.int32)
+    es = newid[es]
     graphs = [
         ("rmat15", *gen.rmat(15, 16, seed=32), F32),
+        ("rmat16 degree-sorted", ns, es, ws, F32),
         ("grid24", *gen.grid(24, 24, 24, 0.05, seed=33), U32),
         ("multi", nm, multi_e, multi_w, U32),
         ("sparse", 50000, *gen.er(50000, 20000, seed=34), U32),
