@@ -36,8 +36,20 @@ namespace {
 constexpr int TL_NT = 512;         // partition workgroup
 constexpr int TL_TILE = 4096;      // entries per LDS tile
 constexpr int TL_E2 = 8192;        // level-1 entries per level-2 workgroup
-constexpr int TC_NT = 256;         // placement workgroup
-constexpr int TC_PT = 8;           // entries per thread per pass of a placement
+#ifndef TL_PLACE_THREADS
+#define TL_PLACE_THREADS 256
+#endif
+constexpr int TC_NT = TL_PLACE_THREADS;  // placement workgroup
+#ifndef TL_PLACE_PER_THREAD
+#define TL_PLACE_PER_THREAD 8
+#endif
+constexpr int TC_PT = TL_PLACE_PER_THREAD;  // entries per thread per pass of a placement
+constexpr int TC_CAP = TC_NT * TC_PT;        // entries of a one-pass placement
+// average entries per fine bucket the levels are sized for (at most this
+// many, at least half)
+#ifndef TL_FINE_ENTRIES
+#define TL_FINE_ENTRIES 2048
+#endif
 constexpr int TL_MAX_NC = 1024;    // coarse buckets
 constexpr int TL_MAX_NSUB = 256;   // fine buckets per coarse bucket
 constexpr int TL_MAX_L2 = 10;      // log2 rows per fine bucket
@@ -340,7 +352,7 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
         if (MIN) s_min[i] = KEY_INF;
     }
     __syncthreads();
-    if (fe - fs <= (uint32_t)(TC_NT * TC_PT)) {
+    if (fe - fs <= (uint32_t)TC_CAP) {
         // one batch: the counting atomic's return value is the entry's rank
         // in its row, so every entry takes a single LDS atomic
         uint32_t rl[TC_PT], cc[TC_PT], rk[TC_PT];
@@ -433,7 +445,7 @@ bool two_level_params(int32_t n, int64_t m, TwoLevel *tl)
     if (n <= 0 || m <= 0) return false;
     const double avg = (2.0 * (double)m) / (double)n;  // stored entries per row (bound)
     int L2 = 0;
-    while (L2 < TL_MAX_L2 && avg * (double)(1u << (L2 + 1)) <= 2048.0) ++L2;
+    while (L2 < TL_MAX_L2 && avg * (double)(1u << (L2 + 1)) <= (double)TL_FINE_ENTRIES) ++L2;
     for (;;) {
         const uint64_t F = ((uint64_t)n + (1ull << L2) - 1) >> L2;
         int lg = (ceil_log2(F) + 1) / 2;

@@ -105,19 +105,31 @@ __device__ __forceinline__ ChunkGeom chunk_geom(const SliceInfo &sl,
 }
 
 // Streamed entry loads (non-temporal: each entry is read once per sweep).
-// The lane's whole 4-entry group is always loaded (the arrays are padded),
+// The lane's whole group of entries is always loaded (the arrays are padded),
 // so the number of loads does not depend on the chunk; entries outside
 // [kb, ke) are masked to column 0 / the empty key.
 __device__ __forceinline__ void load_entries(const uint32_t *__restrict__ col,
                                              const uint64_t *__restrict__ key, const ChunkGeom &g,
                                              uint32_t (&cl)[SWEEP_E], uint64_t (&ky)[SWEEP_E])
 {
-    const u32x4 c4 = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(col + g.base));
-    const u64x2 k01 = __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(key + g.base));
-    const u64x2 k23 =
-        __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(key + g.base + 2));
-    const uint32_t cv[SWEEP_E] = {c4.x, c4.y, c4.z, c4.w};
-    const uint64_t kv[SWEEP_E] = {k01.x, k01.y, k23.x, k23.y};
+    uint32_t cv[SWEEP_E];
+    uint64_t kv[SWEEP_E];
+#pragma unroll
+    for (int h = 0; h < SWEEP_E / 4; ++h) {
+        const uint32_t b = g.base + 4 * h;
+        const u32x4 c4 = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(col + b));
+        const u64x2 k01 = __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(key + b));
+        const u64x2 k23 =
+            __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(key + b + 2));
+        cv[4 * h] = c4.x;
+        cv[4 * h + 1] = c4.y;
+        cv[4 * h + 2] = c4.z;
+        cv[4 * h + 3] = c4.w;
+        kv[4 * h] = k01.x;
+        kv[4 * h + 1] = k01.y;
+        kv[4 * h + 2] = k23.x;
+        kv[4 * h + 3] = k23.y;
+    }
 #pragma unroll
     for (int e = 0; e < SWEEP_E; ++e) {
         const bool v = e >= g.kb && e < g.ke;
@@ -164,16 +176,22 @@ __device__ __forceinline__ void entry_roots(RpAt rp_at, PRow p_row, uint32_t lo,
 // Kept out of line: merged with the LDS variant, the compiler would select
 // between an LDS and a global pointer and load through the generic address
 // space.
+struct LaneRoots {
+    uint32_t v[SWEEP_E];
+};
+
 template <bool FIRST>
-__device__ __attribute__((noinline)) u32x4 entry_roots_global(const uint32_t *__restrict__ rp,
-                                                              const uint32_t *__restrict__ p,
-                                                              uint32_t lo, uint32_t hi,
-                                                              uint32_t base, int kb, int ke)
+__device__ __attribute__((noinline)) LaneRoots entry_roots_global(const uint32_t *__restrict__ rp,
+                                                                  const uint32_t *__restrict__ p,
+                                                                  uint32_t lo, uint32_t hi,
+                                                                  uint32_t base, int kb, int ke)
 {
-    uint32_t root[SWEEP_E] = {NONE32, NONE32, NONE32, NONE32};
+    LaneRoots out;
+#pragma unroll
+    for (int e = 0; e < SWEEP_E; ++e) out.v[e] = NONE32;
     entry_roots<FIRST>([&](uint32_t rw) { return rp[rw]; }, [&](uint32_t rw) { return p[rw]; },
-                       lo, hi, base, kb, ke, root);
-    return u32x4{root[0], root[1], root[2], root[3]};
+                       lo, hi, base, kb, ke, out.v);
+    return out;
 }
 
 // FIRST: the parent vector is the identity (round 1), so every stored entry
@@ -270,8 +288,9 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
                                [&](uint32_t rw) { return s_p[rw - lo]; }, lo, hi, base, kb, ke,
                                root);
         } else {
-            const u32x4 v = entry_roots_global<FIRST>(rp, p, lo, hi, base, kb, ke);
-            root[0] = v.x; root[1] = v.y; root[2] = v.z; root[3] = v.w;
+            const LaneRoots v = entry_roots_global<FIRST>(rp, p, lo, hi, base, kb, ke);
+#pragma unroll
+            for (int e = 0; e < E; ++e) root[e] = v.v[e];
         }
     }
     uint32_t dead_found = 0;  // lazy: gathered entries found internal
@@ -439,12 +458,12 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     uint32_t nib = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) nib |= (live[e] ? 1u : 0u) << e;
-    uint32_t word = nib << ((lane & 7u) * 4u);
-    word |= __shfl_xor(word, 1, 64);
-    word |= __shfl_xor(word, 2, 64);
-    word |= __shfl_xor(word, 4, 64);
-    if ((lane & 7u) == 0) {
-        const size_t wi = (size_t)c * (SWEEP_CHUNK / 32) + (threadIdx.x >> 3);
+    constexpr uint32_t LPW = 32 / E;  // lanes per 32-entry mask word
+    uint32_t word = nib << ((lane % LPW) * E);
+#pragma unroll
+    for (uint32_t d = 1; d < LPW; d <<= 1) word |= __shfl_xor(word, (int)d, 64);
+    if (lane % LPW == 0) {
+        const size_t wi = (size_t)c * (SWEEP_CHUNK / 32) + threadIdx.x / LPW;
         chunk_mask[wi] = word;
         chunk_wpre[wi] = pos;
     }

@@ -32,11 +32,15 @@ constexpr uint32_t NONE32 = 0xFFFFFFFFu;
 #ifndef SWEEP_BLOCK_LANES
 #define SWEEP_BLOCK_LANES 256
 #endif
+#ifndef SWEEP_LANE_ENTRIES
+#define SWEEP_LANE_ENTRIES 4
+#endif
 constexpr int SWEEP_BLOCK = SWEEP_BLOCK_LANES;
-constexpr int SWEEP_E = 4;
+constexpr int SWEEP_E = SWEEP_LANE_ENTRIES;
+static_assert(SWEEP_E == 4 || SWEEP_E == 8, "a lane owns one or two 16-byte column loads");
 constexpr int SWEEP_CHUNK = SWEEP_BLOCK * SWEEP_E;
 // Column/key arrays are allocated SWEEP_PAD entries beyond their capacity:
-// the sweep loads whole 4-entry groups past the last stored entry (without
+// the sweep loads whole lane groups past the last stored entry (without
 // a branch, so the compiler can count outstanding loads exactly).
 constexpr size_t SWEEP_PAD = SWEEP_CHUNK;
 
