@@ -191,8 +191,9 @@ def bench_served(ctx, pkg, torch, requests_per_rate=200, rates=(0.25, 0.5, 1.0, 
     out = {"pool_graphs": len(pool), "requests_per_rate": requests_per_rate,
            "budget_bytes": budget, "plain_graphs_per_s": mu, "rates": []}
     srv = pkg.Server(ctx, budget)
-    # warm the server's slots
-    warm = [srv.submit(*pool[i][:3], wtype=pkg.W_F32) for i in range(8)]
+    # warm the server with the whole pool at once, so its slots, device
+    # memory pool and pinned staging buffers reach their working set
+    warm = [srv.submit(*p[:3], wtype=pkg.W_F32) for p in pool]
     for i, tk in enumerate(warm):
         srv.result(tk, pool[i][0])
     for mult in rates:

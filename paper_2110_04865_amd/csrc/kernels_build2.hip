@@ -45,6 +45,20 @@ constexpr int TC_NT = TL_PLACE_THREADS;  // placement workgroup
 #endif
 constexpr int TC_PT = TL_PLACE_PER_THREAD;  // entries per thread per pass of a placement
 constexpr int TC_CAP = TC_NT * TC_PT;        // entries of a one-pass placement
+// Copies of each row's placement counter (and minimum): lane l uses copy
+// l % C, so lanes of one wave that hold entries of the same row rarely hit
+// the same LDS word; at most TC_SLOTS (row, copy) counters per bucket.
+#ifndef TL_PLACE_COPIES
+#define TL_PLACE_COPIES 2
+#endif
+static_assert((TL_PLACE_COPIES & (TL_PLACE_COPIES - 1)) == 0, "copies: a power of two");
+constexpr uint32_t TC_SLOTS = 512;
+__host__ __device__ inline uint32_t tc_copies(int L2)
+{
+    const uint32_t R = 1u << L2;
+    uint32_t c = R >= TC_SLOTS ? 1u : TC_SLOTS / R;
+    return c < (uint32_t)TL_PLACE_COPIES ? c : (uint32_t)TL_PLACE_COPIES;
+}
 // average entries per fine bucket the levels are sized for (at most this
 // many, at least half)
 #ifndef TL_FINE_ENTRIES
@@ -339,19 +353,23 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
 {
     extern __shared__ uint64_t tc_lds[];
     const uint32_t R = 1u << L2;
-    uint64_t *s_min = tc_lds;                                            // R (MIN)
-    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(tc_lds + (MIN ? R : 0));  // R
+    const uint32_t C = tc_copies(L2), RC = R * C;  // counters are [row][copy]
+    uint64_t *s_min = tc_lds;                                             // RC (MIN)
+    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(tc_lds + (MIN ? RC : 0));  // RC
+    const uint32_t cp = threadIdx.x & (C - 1);  // this lane's copy
     __shared__ uint32_t s_scr[TC_NT / 64 + 1];
     const uint32_t f = blockIdx.x;
     const int64_t row0 = (int64_t)f << L2;
     if (row0 >= n) return;
     const uint32_t rows = (uint32_t)((int64_t)n - row0 < (int64_t)R ? (int64_t)n - row0 : R);
     const uint32_t fs = fstart[f], fe = fstart[f + 1];
-    for (uint32_t i = threadIdx.x; i < R; i += TC_NT) {
+    for (uint32_t i = threadIdx.x; i < RC; i += TC_NT) {
         s_cnt[i] = 0;
         if (MIN) s_min[i] = KEY_INF;
     }
     __syncthreads();
+    // a row's entries take the segments of its copies in copy order; the
+    // row starts where its copy 0 does
     if (fe - fs <= (uint32_t)TC_CAP) {
         // one batch: the counting atomic's return value is the entry's rank
         // in its row, so every entry takes a single LDS atomic
@@ -369,17 +387,18 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
         for (int k = 0; k < TC_PT; ++k) {
             rk[k] = 0;
             if (rl[k] == NONE32) continue;
-            rk[k] = atomicAdd(&s_cnt[rl[k]], 1u);
-            if (MIN) atomicMin((unsigned long long *)&s_min[rl[k]], (unsigned long long)kk[k]);
+            rk[k] = atomicAdd(&s_cnt[rl[k] * C + cp], 1u);
+            if (MIN)
+                atomicMin((unsigned long long *)&s_min[rl[k] * C + cp], (unsigned long long)kk[k]);
         }
         __syncthreads();
-        lds_excl_scan<TC_NT>(s_cnt, (int)R, s_scr);
-        for (uint32_t i = threadIdx.x; i < rows; i += TC_NT) row_ptr[row0 + i] = fs + s_cnt[i];
+        lds_excl_scan<TC_NT>(s_cnt, (int)RC, s_scr);
+        for (uint32_t i = threadIdx.x; i < rows; i += TC_NT) row_ptr[row0 + i] = fs + s_cnt[i * C];
         if (row0 + rows == (int64_t)n && threadIdx.x == 0) row_ptr[n] = fe;
 #pragma unroll
         for (int k = 0; k < TC_PT; ++k) {
             if (rl[k] == NONE32) continue;
-            const uint32_t p = s_cnt[rl[k]] + rk[k];
+            const uint32_t p = s_cnt[rl[k] * C + cp] + rk[k];
             col[fs + p] = cc[k];
             key[fs + p] = kk[k];
         }
@@ -393,11 +412,11 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
             }
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k)
-                if (rl[k] != NONE32) atomicAdd(&s_cnt[rl[k]], 1u);
+                if (rl[k] != NONE32) atomicAdd(&s_cnt[rl[k] * C + cp], 1u);
         }
         __syncthreads();
-        lds_excl_scan<TC_NT>(s_cnt, (int)R, s_scr);
-        for (uint32_t i = threadIdx.x; i < rows; i += TC_NT) row_ptr[row0 + i] = fs + s_cnt[i];
+        lds_excl_scan<TC_NT>(s_cnt, (int)RC, s_scr);
+        for (uint32_t i = threadIdx.x; i < rows; i += TC_NT) row_ptr[row0 + i] = fs + s_cnt[i * C];
         if (row0 + rows == (int64_t)n && threadIdx.x == 0) row_ptr[n] = fe;
         __syncthreads();
         for (uint64_t b = fs; b < fe; b += TC_NT * TC_PT) {
@@ -414,16 +433,22 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k) {
                 if (rl[k] == NONE32) continue;
-                const uint32_t p = atomicAdd(&s_cnt[rl[k]], 1u);
+                const uint32_t p = atomicAdd(&s_cnt[rl[k] * C + cp], 1u);
                 col[fs + p] = cc[k];
                 key[fs + p] = kk[k];
-                if (MIN) atomicMin((unsigned long long *)&s_min[rl[k]], (unsigned long long)kk[k]);
+                if (MIN)
+                    atomicMin((unsigned long long *)&s_min[rl[k] * C + cp],
+                              (unsigned long long)kk[k]);
             }
         }
     }
     if (MIN) {
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < rows; i += TC_NT) r[row0 + i] = s_min[i];
+        for (uint32_t i = threadIdx.x; i < rows; i += TC_NT) {
+            uint64_t v = s_min[i * C];
+            for (uint32_t c = 1; c < C; ++c) v = v < s_min[i * C + c] ? v : s_min[i * C + c];
+            r[row0 + i] = v;
+        }
     }
 }
 
@@ -521,11 +546,11 @@ msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
     // C
     const unsigned nf = (unsigned)NC * (unsigned)tl.nsub;
     k_tl_fstart<<<(nf + 256) / 256, 256, 0, s>>>(o2, nb2, P, tl.nsub, NC, fst);
-    const size_t R = (size_t)1 << tl.L2;
+    const size_t RC = ((size_t)1 << tl.L2) * tc_copies(tl.L2);
     if (r_first)
-        k_tl_place<true><<<nf, TC_NT, 12 * R, s>>>(e2, n, tl.L2, fst, row_ptr, col, key, r_first);
+        k_tl_place<true><<<nf, TC_NT, 12 * RC, s>>>(e2, n, tl.L2, fst, row_ptr, col, key, r_first);
     else
-        k_tl_place<false><<<nf, TC_NT, 4 * R, s>>>(e2, n, tl.L2, fst, row_ptr, col, key, nullptr);
+        k_tl_place<false><<<nf, TC_NT, 4 * RC, s>>>(e2, n, tl.L2, fst, row_ptr, col, key, nullptr);
     MSF_HIP(hipGetLastError());
     return MSF_OK;
 }

@@ -6,9 +6,10 @@
 // asynchronous DMA) and queues it; a worker thread owns the device work:
 //   - admission: waiting requests are admitted in arrival order while their
 //     footprint (msf_request_footprint) fits in the budget left by the
-//     requests in flight; an admitted request gets a slot: its own stream,
-//     counters and stream-ordered device workspace, its inputs copied in,
-//     and its adjacency build enqueued;
+//     requests in flight and the workspace the slots keep; an admitted
+//     request gets a slot: its own stream, counters and stream-ordered
+//     device workspace (kept from its previous request, grown if needed),
+//     its inputs copied in, and its adjacency build enqueued;
 //   - stepping: every pass over the active slots advances each slot whose
 //     previous step has reached the host by one step (a round of Algorithm 2
 //     with complete shortcutting, or the build/output stage), so rounds of
@@ -16,15 +17,22 @@
 //     arrives mid-flight joins at the next pass;
 //   - retirement: a finished slot's forest is copied back into the
 //     request's staging buffer (asynchronously, polled like any step), its
-//     latency is stamped (host steady clock, submit to ready), its workspace
-//     is freed on its stream, and its budget is returned to waiting
-//     requests.
+//     latency is stamped (host steady clock, submit to ready), and its
+//     budget is returned to waiting requests.  The slot keeps its workspace
+//     for its next request (freeing and reallocating it per request cost
+//     more than the solves: 4x the throughput and a tenth of the p99 at
+//     four times the plain rate); idle slots give theirs back, largest
+//     first, when a waiting request would not fit otherwise.
+// Budget: used = the footprints of the requests in flight + the workspace
+// every slot keeps, so the device memory of the slots never exceeds it
+// (footprints bound what a request adds to a slot's workspace).
 // A failing request completes with its error status and never affects the
 // others.  Each request's result is bit-identical to msf_solve on it alone:
 // every slot runs the same deterministic solve on its own state.
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -49,6 +57,8 @@ using clk = std::chrono::steady_clock;
 struct StagePool {
     std::mutex mu;
     std::multimap<size_t, void *> idle;  // capacity -> buffer
+    // buffers pinned so far and the host time spent pinning them
+    std::atomic<uint64_t> pinned{0}, pin_ns{0};
     void *get(size_t bytes, size_t *cap)
     {
         if (bytes < 4096) bytes = 4096;
@@ -62,12 +72,20 @@ struct StagePool {
                 return p;
             }
         }
-        size_t c = (bytes + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
+        // a power of two (at least 1 MB), so later requests of similar
+        // size find it idle instead of pinning again
+        size_t c = (size_t)1 << 20;
+        while (c < bytes) c <<= 1;
         void *p = nullptr;
+        const auto t0 = std::chrono::steady_clock::now();
         if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             return nullptr;
         }
+        pin_ns += (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+                      std::chrono::steady_clock::now() - t0)
+                      .count();
+        ++pinned;
         *cap = c;
         return p;
     }
@@ -127,6 +145,7 @@ struct ReqSlot {
     Request *req = nullptr;
     int32_t *d_ids = nullptr;
     bool downloading = false;
+    size_t kept = 0;  // device workspace bytes it holds (counted in used)
 };
 
 }  // namespace
@@ -167,10 +186,25 @@ void finish(msf_server *s, Request *r, msf_status st, const char *msg)
     s->cv_done.notify_all();
 }
 
-ReqSlot *take_slot(msf_server *s)
+// An idle slot for a request of `need` bytes: the one keeping the least
+// workspace that is still at least need (it grows least and wastes least),
+// else the one keeping the most; a new slot if none is idle.
+ReqSlot *take_slot(msf_server *s, size_t need)
 {
     if (!s->pool.empty()) {
-        ReqSlot *sl = s->pool.back();
+        size_t best = s->pool.size();
+        for (size_t i = 0; i < s->pool.size(); ++i) {
+            const size_t k = s->pool[i]->kept;
+            if (best == s->pool.size()) {
+                best = i;
+                continue;
+            }
+            const size_t b = s->pool[best]->kept;
+            const bool fits = k >= need, bfits = b >= need;
+            if ((fits && (!bfits || k < b)) || (!fits && !bfits && k > b)) best = i;
+        }
+        ReqSlot *sl = s->pool[best];
+        s->pool[best] = s->pool.back();
         s->pool.pop_back();
         return sl;
     }
@@ -188,19 +222,29 @@ ReqSlot *take_slot(msf_server *s)
         delete sl;
         return nullptr;
     }
-    // Slots release their workspace after every request, so the next one
-    // allocates it again from the stream-ordered pool; the one-level build
-    // needs half the staging memory of the two-level one, and with several
-    // requests in flight that churn, not the build's speed, decides
-    // (measured: 2x the throughput at twice the plain rate).  An explicit
-    // MSF_BUCKETED_BUILD still wins.
+    // the one-level build needs half the staging memory of the two-level
+    // one, so more requests fit the budget at once; an explicit
+    // MSF_BUCKETED_BUILD still wins
     if (!getenv("MSF_BUCKETED_BUILD") && sl->ctx.bucketed_build == 1) sl->ctx.bucketed_build = 2;
     return sl;
 }
 
+size_t workspace_bytes(const Ctx &c)
+{
+    size_t t = 0;
+    for (const auto &b : c.ws) t += b.cap;
+    return t;
+}
+
 void retire_slot(msf_server *s, ReqSlot *sl)
 {
-    ctx_release_workspace(&sl->ctx);  // stream-ordered frees
+    // the slot keeps its workspace; used follows what it now holds
+    const size_t k = workspace_bytes(sl->ctx);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->used = s->used - sl->kept + k;
+    }
+    sl->kept = k;
     sl->req = nullptr;
     sl->d_ids = nullptr;
     sl->downloading = false;
@@ -211,7 +255,7 @@ void retire_slot(msf_server *s, ReqSlot *sl)
 // completes with the error; the slot goes back to the pool.
 bool admit(msf_server *s, Request *r)
 {
-    ReqSlot *sl = take_slot(s);
+    ReqSlot *sl = take_slot(s, r->footprint);
     if (!sl) {
         finish(s, r, MSF_ENOMEM, "no slot (stream) available");
         return false;
@@ -291,13 +335,23 @@ void worker_main(msf_server *s)
 {
     (void)hipSetDevice(s->device);
     for (;;) {
-        // admission, in arrival order, while the budget allows
+        // admission, in arrival order, while the budget allows; idle slots
+        // give back their workspace (largest first) to make room
         for (;;) {
             Request *r = nullptr;
             {
                 std::lock_guard<std::mutex> lk(s->mu);
                 if (s->waiting.empty() || s->active.size() >= s->max_slots) break;
                 Request *f = s->waiting.front();
+                while (s->used + f->footprint > s->budget) {
+                    ReqSlot *big = nullptr;
+                    for (ReqSlot *sl : s->pool)
+                        if (sl->kept && (!big || sl->kept > big->kept)) big = sl;
+                    if (!big) break;
+                    ctx_release_workspace(&big->ctx);  // stream-ordered frees
+                    s->used -= big->kept;
+                    big->kept = 0;
+                }
                 if (s->used + f->footprint > s->budget) break;
                 s->waiting.pop_front();
                 s->used += f->footprint;
@@ -394,6 +448,9 @@ void msf_server_destroy(msf_server *s)
         s->cv_done.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
+    if (getenv("MSF_SERVER_TRACE"))
+        fprintf(stderr, "[msf server] pinned staging buffers: %llu, %.1f ms pinning\n",
+                (unsigned long long)s->stage.pinned.load(), 1e-6 * (double)s->stage.pin_ns.load());
     {
         std::lock_guard<std::mutex> tl(s->tmu);
         for (auto &kv : s->tickets) {
