@@ -67,6 +67,14 @@ __host__ __device__ inline uint32_t tc_copies(int L2)
 constexpr int TL_MAX_NC = 1024;    // coarse buckets
 constexpr int TL_MAX_NSUB = 256;   // fine buckets per coarse bucket
 constexpr int TL_MAX_L2 = 10;      // log2 rows per fine bucket
+// Copies of each bucket's tile counter in the partition passes: lane l
+// counts in copy l % TP_C, so fewer lanes of a wave hit the same LDS word;
+// a bucket's entries fill its copies' segments in order.
+#ifndef TL_PART_COPIES
+#define TL_PART_COPIES 2
+#endif
+constexpr uint32_t TP_C = TL_PART_COPIES;
+static_assert((TP_C & (TP_C - 1)) == 0, "copies: a power of two");
 
 // In-place exclusive scan of a[0..N) in LDS by an NT-thread workgroup;
 // returns the total.  Every thread must call it.
@@ -144,8 +152,10 @@ __global__ __launch_bounds__(TL_NT) void k_part_edges(
 {
     const uint32_t smask = (1u << (L1 - L2)) - 1u;
     __shared__ uint4 s_ent[TL_TILE];
-    __shared__ uint32_t s_run[TL_MAX_NC], s_pos[TL_MAX_NC];
+    __shared__ uint32_t s_run[TL_MAX_NC], s_pos[TL_MAX_NC * TP_C];  // s_pos: [bucket][copy]
     __shared__ uint32_t s_scr[TL_NT / 64 + 1];
+    const uint32_t cp = threadIdx.x & (TP_C - 1);
+    const int NCC = NC * (int)TP_C;
     for (int c = threadIdx.x; c < NC; c += TL_NT) s_run[c] = bo1[(size_t)c * nblk + blockIdx.x];
     const int64_t e0 = (int64_t)blockIdx.x * epb;
     const int64_t e1 = e0 + epb < m ? e0 + epb : m;
@@ -164,7 +174,7 @@ __global__ __launch_bounds__(TL_NT) void k_part_edges(
             ok[k] = in && (uint32_t)eu[k] < (uint32_t)n && (uint32_t)ev[k] < (uint32_t)n &&
                     eu[k] != ev[k];
         }
-        for (int c = threadIdx.x; c < NC; c += TL_NT) s_pos[c] = 0;
+        for (int c = threadIdx.x; c < NCC; c += TL_NT) s_pos[c] = 0;
         __syncthreads();
         // one LDS atomic per entry: its return value is the entry's rank in
         // its bucket within the tile
@@ -173,11 +183,11 @@ __global__ __launch_bounds__(TL_NT) void k_part_edges(
         for (int k = 0; k < TL_EP; ++k) {
             ru[k] = rv[k] = 0;
             if (!ok[k]) continue;
-            ru[k] = atomicAdd(&s_pos[(uint32_t)eu[k] >> L1], 1u);
-            rv[k] = atomicAdd(&s_pos[(uint32_t)ev[k] >> L1], 1u);
+            ru[k] = atomicAdd(&s_pos[((uint32_t)eu[k] >> L1) * TP_C + cp], 1u);
+            rv[k] = atomicAdd(&s_pos[((uint32_t)ev[k] >> L1) * TP_C + cp], 1u);
         }
         __syncthreads();
-        const uint32_t cnt = lds_excl_scan<TL_NT>(s_pos, NC, s_scr);  // s_pos: starts
+        const uint32_t cnt = lds_excl_scan<TL_NT>(s_pos, NCC, s_scr);  // s_pos: starts
 #pragma unroll
         for (int k = 0; k < TL_EP; ++k) {
             if (!ok[k]) continue;
@@ -186,21 +196,21 @@ __global__ __launch_bounds__(TL_NT) void k_part_edges(
             if (WT == MSF_W_F32) wk = wkey_f32_bits(wk);
             const uint64_t key = ((uint64_t)wk << 32) | (uint64_t)(uint32_t)e;
             const uint32_t u = (uint32_t)eu[k], v = (uint32_t)ev[k];
-            s_ent[s_pos[u >> L1] + ru[k]] = make_ent(u, v, key);
-            s_ent[s_pos[v >> L1] + rv[k]] = make_ent(v, u, key);
+            s_ent[s_pos[(u >> L1) * TP_C + cp] + ru[k]] = make_ent(u, v, key);
+            s_ent[s_pos[(v >> L1) * TP_C + cp] + rv[k]] = make_ent(v, u, key);
         }
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < cnt; i += TL_NT) {
             const uint4 x = s_ent[i];
             const uint32_t c = x.x >> L1;
-            const uint32_t pos = s_run[c] + (i - s_pos[c]);
+            const uint32_t pos = s_run[c] + (i - s_pos[c * TP_C]);
             o1[pos] = x;
             sub1[pos] = (uint8_t)((x.x >> L2) & smask);
         }
         __syncthreads();
         for (int c = threadIdx.x; c < NC; c += TL_NT) {
-            const uint32_t end = c + 1 < NC ? s_pos[c + 1] : cnt;
-            s_run[c] += end - s_pos[c];
+            const uint32_t end = c + 1 < NC ? s_pos[(c + 1) * TP_C] : cnt;
+            s_run[c] += end - s_pos[c * TP_C];
         }
         __syncthreads();
     }
@@ -284,7 +294,7 @@ __global__ __launch_bounds__(TL_NT) void k_part_sub(
     const uint32_t *__restrict__ o2, uint4 *__restrict__ e2)
 {
     __shared__ uint4 s_ent[TL_TILE];
-    __shared__ uint32_t s_run[TL_MAX_NSUB], s_pos[TL_MAX_NSUB];
+    __shared__ uint32_t s_run[TL_MAX_NSUB], s_pos[TL_MAX_NSUB * TP_C];  // s_pos: [fine][copy]
     __shared__ uint32_t s_scr[TL_NT / 64 + 1];
     uint32_t c, j;
     if (!l2_block(P, NC, blockIdx.x, &c, &j)) return;
@@ -293,6 +303,8 @@ __global__ __launch_bounds__(TL_NT) void k_part_sub(
     const uint32_t e = (uint64_t)a + TL_E2 < (uint64_t)cs[c + 1] ? a + TL_E2 : cs[c + 1];
     const uint32_t mask = (uint32_t)nsub - 1u;
     for (int s = threadIdx.x; s < nsub; s += TL_NT) s_run[s] = o2[t2_index(P, nb2, nsub, c, s, j)];
+    const uint32_t cp = threadIdx.x & (TP_C - 1);
+    const int nsc = nsub * (int)TP_C;
     for (uint64_t t0 = a; t0 < e; t0 += TL_TILE) {
         uint4 xx[TL_SP];
 #pragma unroll
@@ -300,27 +312,30 @@ __global__ __launch_bounds__(TL_NT) void k_part_sub(
             const uint64_t i = t0 + threadIdx.x + (uint32_t)k * TL_NT;
             xx[k] = i < e ? e1[i] : make_uint4(NONE32, 0u, 0u, 0u);
         }
-        for (int s = threadIdx.x; s < nsub; s += TL_NT) s_pos[s] = 0;
+        for (int s = threadIdx.x; s < nsc; s += TL_NT) s_pos[s] = 0;
         __syncthreads();
-        uint32_t rk[TL_SP];  // rank in the fine bucket within the tile
+        uint32_t rk[TL_SP];  // rank in the fine bucket's copy within the tile
 #pragma unroll
         for (int k = 0; k < TL_SP; ++k)
-            rk[k] = xx[k].x != NONE32 ? atomicAdd(&s_pos[(xx[k].x >> L2) & mask], 1u) : 0u;
+            rk[k] = xx[k].x != NONE32
+                        ? atomicAdd(&s_pos[((xx[k].x >> L2) & mask) * TP_C + cp], 1u)
+                        : 0u;
         __syncthreads();
-        const uint32_t cnt = lds_excl_scan<TL_NT>(s_pos, nsub, s_scr);  // s_pos: starts
+        const uint32_t cnt = lds_excl_scan<TL_NT>(s_pos, nsc, s_scr);  // s_pos: starts
 #pragma unroll
         for (int k = 0; k < TL_SP; ++k)
-            if (xx[k].x != NONE32) s_ent[s_pos[(xx[k].x >> L2) & mask] + rk[k]] = xx[k];
+            if (xx[k].x != NONE32)
+                s_ent[s_pos[((xx[k].x >> L2) & mask) * TP_C + cp] + rk[k]] = xx[k];
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < cnt; i += TL_NT) {
             const uint4 x = s_ent[i];
             const uint32_t s = (x.x >> L2) & mask;
-            e2[s_run[s] + (i - s_pos[s])] = x;
+            e2[s_run[s] + (i - s_pos[s * TP_C])] = x;
         }
         __syncthreads();
         for (int s = threadIdx.x; s < nsub; s += TL_NT) {
-            const uint32_t end = s + 1 < nsub ? s_pos[s + 1] : cnt;
-            s_run[s] += end - s_pos[s];
+            const uint32_t end = s + 1 < nsub ? s_pos[(s + 1) * TP_C] : cnt;
+            s_run[s] += end - s_pos[s * TP_C];
         }
         __syncthreads();
     }
