@@ -297,6 +297,10 @@ void launch_slice_info(hipStream_t s, const Adj &a, Counters *dcnt)
 
 constexpr int BK_MAX_NB = 16384;  // pass A/B keep one LDS counter per bucket
 constexpr int BKA_NT = 256;
+// most counter copies of the coarse histogram (a power of two)
+#ifndef BKA_COPIES
+#define BKA_COPIES 8
+#endif
 constexpr int BKC_NT = 1024;
 constexpr int BK_MIN_LB = 12;  // fewer, larger buckets keep pass B's writes in long runs
 constexpr int BK_MAX_LB = 15;  // pass C keeps 2^LB row counters in LDS
@@ -320,10 +324,15 @@ __global__ __launch_bounds__(BKA_NT) void k_bucket_hist(const int32_t *__restric
                                                         const void *__restrict__ w, int64_t m,
                                                         int32_t n, int lb, int nb, uint32_t slice_w,
                                                         uint32_t nbr, int64_t epb, uint32_t nblk,
-                                                        uint32_t *__restrict__ bh, Counters *cnt)
+                                                        int C, uint32_t *__restrict__ bh,
+                                                        Counters *cnt)
 {
+    // C copies of every counter, [bucket][copy]: lane l counts in copy
+    // l % C, so lanes of a wave with the same bucket rarely hit the same
+    // LDS word; the copies are summed at the end
     extern __shared__ uint32_t hist[];
-    for (int i = threadIdx.x; i < nb; i += BKA_NT) hist[i] = 0;
+    const uint32_t cp = threadIdx.x & (uint32_t)(C - 1);
+    for (int i = threadIdx.x; i < nb * C; i += BKA_NT) hist[i] = 0;
     __syncthreads();
     const int64_t e0 = (int64_t)blockIdx.x * epb;
     const int64_t e1 = e0 + epb < m ? e0 + epb : m;
@@ -355,12 +364,16 @@ __global__ __launch_bounds__(BKA_NT) void k_bucket_hist(const int32_t *__restric
                 continue;
             }
             if (u == v) continue;
-            atomicAdd(&hist[bucket_of((uint32_t)u, (uint32_t)v, lb, slice_w, nbr)], 1u);
-            atomicAdd(&hist[bucket_of((uint32_t)v, (uint32_t)u, lb, slice_w, nbr)], 1u);
+            atomicAdd(&hist[bucket_of((uint32_t)u, (uint32_t)v, lb, slice_w, nbr) * C + cp], 1u);
+            atomicAdd(&hist[bucket_of((uint32_t)v, (uint32_t)u, lb, slice_w, nbr) * C + cp], 1u);
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nb; i += BKA_NT) bh[(size_t)i * nblk + blockIdx.x] = hist[i];
+    for (int i = threadIdx.x; i < nb; i += BKA_NT) {
+        uint32_t t = 0;
+        for (int q = 0; q < C; ++q) t += hist[i * C + q];
+        bh[(size_t)i * nblk + blockIdx.x] = t;
+    }
     if (__ballot(err != 0)) {
         uint32_t any = err;
         for (int d = 32; d >= 1; d >>= 1) any |= __shfl_xor(any, d, 64);
@@ -501,13 +514,16 @@ msf_status launch_bucket_hist(Ctx *c, const int32_t *d_edges, const void *d_w, i
                               int32_t n, int lb, int nb, uint32_t slice_w, uint32_t nbr,
                               int64_t epb, uint32_t nblk, msf_wtype wt, uint32_t *bh)
 {
-    const size_t lds_a = 4 * (size_t)nb;
+    // counter copies while the histogram stays within 32 KB of LDS
+    int C = 1;
+    while (C < BKA_COPIES && (size_t)nb * 2 * C * 4 <= ((size_t)32 << 10)) C *= 2;
+    const size_t lds_a = 4 * (size_t)nb * C;
     if (wt == MSF_W_F32)
         k_bucket_hist<MSF_W_F32><<<nblk, BKA_NT, lds_a, c->stream>>>(
-            d_edges, d_w, m, n, lb, nb, slice_w, nbr, epb, nblk, bh, c->dcnt);
+            d_edges, d_w, m, n, lb, nb, slice_w, nbr, epb, nblk, C, bh, c->dcnt);
     else
         k_bucket_hist<MSF_W_U32><<<nblk, BKA_NT, lds_a, c->stream>>>(
-            d_edges, d_w, m, n, lb, nb, slice_w, nbr, epb, nblk, bh, c->dcnt);
+            d_edges, d_w, m, n, lb, nb, slice_w, nbr, epb, nblk, C, bh, c->dcnt);
     MSF_HIP(hipGetLastError());
     return MSF_OK;
 }

@@ -74,6 +74,10 @@ constexpr int TL_MAX_L2 = 10;      // log2 rows per fine bucket
 #define TL_PART_COPIES 2
 #endif
 constexpr uint32_t TP_C = TL_PART_COPIES;
+// copies of the fine histogram's counters (a power of two)
+#ifndef TL_HIST2_COPIES
+#define TL_HIST2_COPIES 8
+#endif
 static_assert((TP_C & (TP_C - 1)) == 0, "copies: a power of two");
 
 // In-place exclusive scan of a[0..N) in LDS by an NT-thread workgroup;
@@ -251,13 +255,16 @@ __global__ __launch_bounds__(256) void k_tl_hist2(const uint8_t *__restrict__ su
                                                   const uint32_t *__restrict__ P,
                                                   uint32_t *__restrict__ t2)
 {
-    __shared__ uint32_t s_h[TL_MAX_NSUB];
+    // TH_C copies of every counter, [fine][copy]; summed at the end
+    constexpr uint32_t TH_C = TL_HIST2_COPIES;
+    __shared__ uint32_t s_h[TL_MAX_NSUB * TH_C];
+    const uint32_t cp = threadIdx.x & (TH_C - 1);
     uint32_t c, j;
     if (!l2_block(P, NC, blockIdx.x, &c, &j)) return;
     const uint32_t a = cs[c] + j * (uint32_t)TL_E2;
     // 64-bit: a + TL_E2 can pass 2^32 near the largest adjacencies
     const uint32_t e = (uint64_t)a + TL_E2 < (uint64_t)cs[c + 1] ? a + TL_E2 : cs[c + 1];
-    for (int s = threadIdx.x; s < nsub; s += 256) s_h[s] = 0;
+    for (int s = threadIdx.x; s < nsub * (int)TH_C; s += 256) s_h[s] = 0;
     __syncthreads();
     const uint32_t *sw = reinterpret_cast<const uint32_t *>(sub1);
     const uint32_t w0 = a >> 2, w1 = (uint32_t)(((uint64_t)e + 3) >> 2);
@@ -275,12 +282,17 @@ __global__ __launch_bounds__(256) void k_tl_hist2(const uint8_t *__restrict__ su
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const uint64_t pos = 4 * i + t;
-                if (pos >= a && pos < e) atomicAdd(&s_h[(ww[k] >> (8 * t)) & 0xFFu], 1u);
+                if (pos >= a && pos < e)
+                    atomicAdd(&s_h[((ww[k] >> (8 * t)) & 0xFFu) * TH_C + cp], 1u);
             }
         }
     }
     __syncthreads();
-    for (int s = threadIdx.x; s < nsub; s += 256) t2[t2_index(P, nb2, nsub, c, s, j)] = s_h[s];
+    for (int s = threadIdx.x; s < nsub; s += 256) {
+        uint32_t t = 0;
+        for (uint32_t q = 0; q < TH_C; ++q) t += s_h[s * TH_C + q];
+        t2[t2_index(P, nb2, nsub, c, s, j)] = t;
+    }
 }
 
 // B2: coarse-bucket entries -> fine buckets, LDS-sorted tiles, runs
