@@ -28,6 +28,7 @@ unsigned grid_for(size_t n, unsigned block = 256, unsigned cap = 8192)
 constexpr int CT_NT = 256;                 // compaction tile: threads
 constexpr int CT_IT = 16;                  // items per thread
 constexpr int CT_TILE = CT_NT * CT_IT;     // items per tile
+static_assert(CT_IT <= 32, "a thread's items are kept in 32-bit masks");
 constexpr uint64_t M31 = (1ull << 31) - 1ull;
 
 uint32_t ct_tiles(uint64_t n) { return (uint32_t)((n + CT_TILE - 1) / CT_TILE); }
