@@ -368,6 +368,50 @@ __global__ void k_tl_fstart(const uint32_t *__restrict__ o2, const uint32_t *__r
     }
 }
 
+// Order of the placement workgroups: fine buckets above the one-pass
+// capacity first (from the front, ascending), the rest after them (from the
+// back).  A bucket with a hub row can hold 10^5 entries and keeps one
+// workgroup busy for a long time; started first, it overlaps the many small
+// buckets instead of running alone at the end.
+constexpr int TO_NT = 256, TO_IT = 16, TO_TILE = TO_NT * TO_IT;
+
+__global__ __launch_bounds__(TO_NT) void k_tl_order(const uint32_t *__restrict__ fstart,
+                                                    uint32_t nf, uint32_t cap,
+                                                    uint32_t *__restrict__ order,
+                                                    uint64_t *status, uint32_t *ticket)
+{
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_lds[TO_NT / 64 + 1];
+    __shared__ uint64_t s_pre;
+    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t base = tile * TO_TILE + threadIdx.x * TO_IT;
+    uint32_t big = 0, ca = 0, cb = 0;
+#pragma unroll
+    for (int k = 0; k < TO_IT; ++k) {
+        const uint32_t f = base + k;
+        if (f < nf) {
+            if (fstart[f + 1] - fstart[f] > cap) {
+                big |= 1u << k;
+                ++ca;
+            } else {
+                ++cb;
+            }
+        }
+    }
+    uint32_t oa, ob;
+    uint64_t tot;
+    tile_offsets2<TO_NT>(tile, ca, cb, status, s_lds, &s_pre, &oa, &ob, &tot);
+#pragma unroll
+    for (int k = 0; k < TO_IT; ++k) {
+        const uint32_t f = base + k;
+        if (f >= nf) continue;
+        if (big & (1u << k)) order[oa++] = f;
+        else order[nf - 1 - ob++] = f;
+    }
+}
+
 // C: one workgroup per fine bucket f (rows [f << L2, (f+1) << L2)): count,
 // scan into row_ptr, place by row.  A bucket's output span is small (tens of
 // KB), so its scattered stores merge in L2 before they reach HBM.  MIN:
@@ -375,8 +419,8 @@ __global__ void k_tl_fstart(const uint32_t *__restrict__ o2, const uint32_t *__r
 template <bool MIN>
 __global__ __launch_bounds__(TC_NT) void k_tl_place(
     const uint4 *__restrict__ e2, int32_t n, int L2, const uint32_t *__restrict__ fstart,
-    uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ col, uint64_t *__restrict__ key,
-    uint64_t *__restrict__ r)
+    const uint32_t *__restrict__ order, uint32_t *__restrict__ row_ptr,
+    uint32_t *__restrict__ col, uint64_t *__restrict__ key, uint64_t *__restrict__ r)
 {
     extern __shared__ uint64_t tc_lds[];
     const uint32_t R = 1u << L2;
@@ -385,7 +429,7 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
     uint32_t *s_cnt = reinterpret_cast<uint32_t *>(tc_lds + (MIN ? RC : 0));  // RC
     const uint32_t cp = threadIdx.x & (C - 1);  // this lane's copy
     __shared__ uint32_t s_scr[TC_NT / 64 + 1];
-    const uint32_t f = blockIdx.x;
+    const uint32_t f = order[blockIdx.x];
     const int64_t row0 = (int64_t)f << L2;
     if (row0 >= n) return;
     const uint32_t rows = (uint32_t)((int64_t)n - row0 < (int64_t)R ? (int64_t)n - row0 : R);
@@ -547,6 +591,12 @@ msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
     const size_t nfine = (size_t)NC * (size_t)tl.nsub;
     MSF_TRY(ws_get(c, WS_FSTART, 4 * (nfine + 1), &vfs));
     uint32_t *fst = (uint32_t *)vfs;
+    // placement order (nfine u32) and its look-back status (one u64 per tile)
+    const uint32_t otiles = (uint32_t)((nfine + TO_TILE - 1) / TO_TILE);
+    void *vord;
+    MSF_TRY(ws_get(c, WS_TLORDER, 4 * nfine + 8 * (size_t)otiles + 8, &vord));
+    uint32_t *order = (uint32_t *)vord;
+    uint64_t *ostat = (uint64_t *)(((uintptr_t)(order + nfine) + 7) & ~(uintptr_t)7);
     uint32_t *bh = (uint32_t *)vbh, *bo = (uint32_t *)vbo;
     uint32_t *cs = (uint32_t *)vplan, *nb2 = cs + NC + 1, *P = nb2 + NC;
     uint32_t *t2 = (uint32_t *)vt2, *o2 = (uint32_t *)vo2;
@@ -573,11 +623,16 @@ msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
     // C
     const unsigned nf = (unsigned)NC * (unsigned)tl.nsub;
     k_tl_fstart<<<(nf + 256) / 256, 256, 0, s>>>(o2, nb2, P, tl.nsub, NC, fst);
+    launch_fill_u64(s, ostat, 0ull, otiles);
+    launch_fill_u32(s, &c->dcnt->ticket, 0u, 1);
+    k_tl_order<<<otiles, TO_NT, 0, s>>>(fst, nf, (uint32_t)TC_CAP, order, ostat, &c->dcnt->ticket);
     const size_t RC = ((size_t)1 << tl.L2) * tc_copies(tl.L2);
     if (r_first)
-        k_tl_place<true><<<nf, TC_NT, 12 * RC, s>>>(e2, n, tl.L2, fst, row_ptr, col, key, r_first);
+        k_tl_place<true><<<nf, TC_NT, 12 * RC, s>>>(e2, n, tl.L2, fst, order, row_ptr, col, key,
+                                                    r_first);
     else
-        k_tl_place<false><<<nf, TC_NT, 4 * RC, s>>>(e2, n, tl.L2, fst, row_ptr, col, key, nullptr);
+        k_tl_place<false><<<nf, TC_NT, 4 * RC, s>>>(e2, n, tl.L2, fst, order, row_ptr, col, key,
+                                                     nullptr);
     MSF_HIP(hipGetLastError());
     return MSF_OK;
 }

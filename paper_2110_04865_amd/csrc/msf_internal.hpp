@@ -96,7 +96,7 @@ enum Slot {
     WS_STATUS, WS_WLIVE, WS_PART, WS_Q, WS_Q2,
     WS_BATCH0, WS_BATCH1, WS_BATCH2, WS_BATCH3,
     WS_BH, WS_BHOFF, WS_BRLO, WS_BCOL, WS_BKEY, WS_CHUNKINFO,
-    WS_TL1, WS_TL2, WS_TLSUB, WS_TLPLAN, WS_T2, WS_T2OFF, WS_FSTART,
+    WS_TL1, WS_TL2, WS_TLSUB, WS_TLORDER, WS_TLPLAN, WS_T2, WS_T2OFF, WS_FSTART,
     WS_COUNT
 };
 
