@@ -26,6 +26,8 @@
 // Every atomic is an LDS atomic.  Between the passes an entry is one
 // 16-byte record (row, column, key): one vector load or store per entry, and
 // one run per bucket in flight instead of three.
+#include <type_traits>
+
 #include "msf_internal.hpp"
 #include "wave.hpp"
 
@@ -74,6 +76,11 @@ constexpr int TL_MAX_L2 = 10;      // log2 rows per fine bucket
 #define TL_PART_COPIES 2
 #endif
 constexpr uint32_t TP_C = TL_PART_COPIES;
+// packed 12-byte records between the passes when the bits allow: bit 0 for
+// the level-1 records, bit 1 for the level-2 ones
+#ifndef TL_PACK
+#define TL_PACK 1
+#endif
 // copies of the fine histogram's counters (a power of two)
 #ifndef TL_HIST2_COPIES
 #define TL_HIST2_COPIES 8
@@ -140,6 +147,57 @@ __device__ __forceinline__ uint64_t ent_key(const uint4 &x)
     return ((uint64_t)x.w << 32) | x.z;
 }
 
+// In HBM an entry is either that 16-byte record or, when the bits allow
+// (edge id bits + column bits + rb <= 64), a packed 12-byte one:
+// x = weight key, (y, z) = edge id << (cb + rb) | column << rb | the row's
+// low rb bits; the row's high bits are its bucket, known to the reader.
+template <bool PK>
+using RecT = typename std::conditional<PK, uint3, uint4>::type;
+
+template <bool PK>
+__device__ __forceinline__ RecT<PK> rec_pack(const uint4 &x, uint32_t rb, uint32_t cb)
+{
+    if constexpr (PK) {
+        const uint64_t v = ((uint64_t)x.z << (cb + rb)) | ((uint64_t)x.y << rb) |
+                           (uint64_t)(x.x & ((1u << rb) - 1u));
+        return make_uint3(x.w, (uint32_t)v, (uint32_t)(v >> 32));
+    } else {
+        (void)rb;
+        (void)cb;
+        return x;
+    }
+}
+
+// The row of record i alone (one 4-byte load): packed, its low rb bits are
+// the low bits of the second word.
+template <bool PK>
+__device__ __forceinline__ uint32_t rec_row(const RecT<PK> *a, uint64_t i, uint32_t rowhi,
+                                            uint32_t rb)
+{
+    if constexpr (PK)
+        return rowhi | (reinterpret_cast<const uint32_t *>(a)[3 * i + 1] & ((1u << rb) - 1u));
+    else
+        return a[i].x;
+}
+
+// rowhi: the bucket's first row (its low rb bits are zero)
+template <bool PK>
+__device__ __forceinline__ uint4 rec_unpack(const RecT<PK> &p, uint32_t rowhi, uint32_t rb,
+                                            uint32_t cb)
+{
+    if constexpr (PK) {
+        const uint64_t v = ((uint64_t)p.z << 32) | p.y;
+        const uint32_t row = rowhi | (uint32_t)(v & ((1ull << rb) - 1ull));
+        const uint32_t col = (uint32_t)((v >> rb) & ((1ull << cb) - 1ull));
+        return make_uint4(row, col, (uint32_t)(v >> (rb + cb)), p.x);
+    } else {
+        (void)rowhi;
+        (void)rb;
+        (void)cb;
+        return p;
+    }
+}
+
 }  // namespace
 
 // B1: edges -> coarse buckets, LDS-sorted tiles, runs written contiguously.
@@ -148,11 +206,11 @@ __device__ __forceinline__ uint64_t ent_key(const uint4 &x)
 // places them through LDS.
 constexpr int TL_EP = TL_TILE / 2 / TL_NT;  // edges per thread per tile
 
-template <int WT>
+template <int WT, bool PK1>
 __global__ __launch_bounds__(TL_NT) void k_part_edges(
     const int32_t *__restrict__ edges, const void *__restrict__ w, int64_t m, int32_t n, int L1,
-    int NC, int64_t epb, uint32_t nblk, const uint32_t *__restrict__ bo1, int L2,
-    uint4 *__restrict__ o1, uint8_t *__restrict__ sub1)
+    int NC, int64_t epb, uint32_t nblk, const uint32_t *__restrict__ bo1, int L2, uint32_t cb,
+    RecT<PK1> *__restrict__ o1, uint8_t *__restrict__ sub1)
 {
     const uint32_t smask = (1u << (L1 - L2)) - 1u;
     __shared__ uint4 s_ent[TL_TILE];
@@ -208,7 +266,7 @@ __global__ __launch_bounds__(TL_NT) void k_part_edges(
             const uint4 x = s_ent[i];
             const uint32_t c = x.x >> L1;
             const uint32_t pos = s_run[c] + (i - s_pos[c * TP_C]);
-            o1[pos] = x;
+            o1[pos] = rec_pack<PK1>(x, (uint32_t)L1, cb);
             sub1[pos] = (uint8_t)((x.x >> L2) & smask);
         }
         __syncthreads();
@@ -300,10 +358,11 @@ __global__ __launch_bounds__(256) void k_tl_hist2(const uint8_t *__restrict__ su
 // TL_SP entries of a tile into registers once.
 constexpr int TL_SP = TL_TILE / TL_NT;  // entries per thread per tile
 
+template <bool PK1, bool PK2>
 __global__ __launch_bounds__(TL_NT) void k_part_sub(
-    const uint4 *__restrict__ e1, int L2, int nsub, int NC, const uint32_t *__restrict__ cs,
+    const RecT<PK1> *__restrict__ e1, int L2, int nsub, int NC, const uint32_t *__restrict__ cs,
     const uint32_t *__restrict__ nb2, const uint32_t *__restrict__ P,
-    const uint32_t *__restrict__ o2, uint4 *__restrict__ e2)
+    const uint32_t *__restrict__ o2, uint32_t cb, RecT<PK2> *__restrict__ e2)
 {
     __shared__ uint4 s_ent[TL_TILE];
     __shared__ uint32_t s_run[TL_MAX_NSUB], s_pos[TL_MAX_NSUB * TP_C];  // s_pos: [fine][copy]
@@ -317,12 +376,15 @@ __global__ __launch_bounds__(TL_NT) void k_part_sub(
     for (int s = threadIdx.x; s < nsub; s += TL_NT) s_run[s] = o2[t2_index(P, nb2, nsub, c, s, j)];
     const uint32_t cp = threadIdx.x & (TP_C - 1);
     const int nsc = nsub * (int)TP_C;
+    int lg = 0;
+    while ((1 << lg) < nsub) ++lg;
+    const uint32_t L1 = (uint32_t)(L2 + lg), rowhi = c << L1;
     for (uint64_t t0 = a; t0 < e; t0 += TL_TILE) {
         uint4 xx[TL_SP];
 #pragma unroll
         for (int k = 0; k < TL_SP; ++k) {
             const uint64_t i = t0 + threadIdx.x + (uint32_t)k * TL_NT;
-            xx[k] = i < e ? e1[i] : make_uint4(NONE32, 0u, 0u, 0u);
+            xx[k] = i < e ? rec_unpack<PK1>(e1[i], rowhi, L1, cb) : make_uint4(NONE32, 0u, 0u, 0u);
         }
         for (int s = threadIdx.x; s < nsc; s += TL_NT) s_pos[s] = 0;
         __syncthreads();
@@ -342,7 +404,7 @@ __global__ __launch_bounds__(TL_NT) void k_part_sub(
         for (uint32_t i = threadIdx.x; i < cnt; i += TL_NT) {
             const uint4 x = s_ent[i];
             const uint32_t s = (x.x >> L2) & mask;
-            e2[s_run[s] + (i - s_pos[s * TP_C])] = x;
+            e2[s_run[s] + (i - s_pos[s * TP_C])] = rec_pack<PK2>(x, (uint32_t)L2, cb);
         }
         __syncthreads();
         for (int s = threadIdx.x; s < nsub; s += TL_NT) {
@@ -416,9 +478,10 @@ __global__ __launch_bounds__(TO_NT) void k_tl_order(const uint32_t *__restrict__
 // scan into row_ptr, place by row.  A bucket's output span is small (tens of
 // KB), so its scattered stores merge in L2 before they reach HBM.  MIN:
 // also store each row's smallest key into r (round 1 of the sweep).
-template <bool MIN>
+template <bool MIN, bool PK2>
 __global__ __launch_bounds__(TC_NT) void k_tl_place(
-    const uint4 *__restrict__ e2, int32_t n, int L2, const uint32_t *__restrict__ fstart,
+    const RecT<PK2> *__restrict__ e2, int32_t n, int L2, uint32_t cb,
+    const uint32_t *__restrict__ fstart,
     const uint32_t *__restrict__ order, uint32_t *__restrict__ row_ptr,
     uint32_t *__restrict__ col, uint64_t *__restrict__ key, uint64_t *__restrict__ r)
 {
@@ -449,7 +512,8 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
 #pragma unroll
         for (int k = 0; k < TC_PT; ++k) {
             const uint64_t i = (uint64_t)fs + threadIdx.x + (uint32_t)k * TC_NT;
-            const uint4 x = i < fe ? e2[i] : make_uint4(NONE32, 0u, 0u, 0u);
+            const uint4 x = i < fe ? rec_unpack<PK2>(e2[i], (uint32_t)row0, (uint32_t)L2, cb)
+                                   : make_uint4(NONE32, 0u, 0u, 0u);
             rl[k] = x.x != NONE32 ? x.x - (uint32_t)row0 : NONE32;
             cc[k] = x.y;
             kk[k] = ent_key(x);
@@ -479,7 +543,8 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k) {
                 const uint64_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
-                rl[k] = i < fe ? e2[i].x - (uint32_t)row0 : NONE32;
+                rl[k] = i < fe ? rec_row<PK2>(e2, i, (uint32_t)row0, (uint32_t)L2) - (uint32_t)row0
+                               : NONE32;
             }
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k)
@@ -496,7 +561,8 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k) {
                 const uint64_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
-                const uint4 x = i < fe ? e2[i] : make_uint4(NONE32, 0u, 0u, 0u);
+                const uint4 x = i < fe ? rec_unpack<PK2>(e2[i], (uint32_t)row0, (uint32_t)L2, cb)
+                                       : make_uint4(NONE32, 0u, 0u, 0u);
                 rl[k] = x.x != NONE32 ? x.x - (uint32_t)row0 : NONE32;
                 cc[k] = x.y;
                 kk[k] = ent_key(x);
@@ -564,11 +630,74 @@ bool two_level_params(int32_t n, int64_t m, TwoLevel *tl)
     }
 }
 
+namespace {
+
+int bits_for(uint64_t max_value)
+{
+    int b = 1;
+    while (b < 64 && (max_value >> b)) ++b;
+    return b;
+}
+
+// Everything of the build after the coarse histogram, for one pair of
+// record formats (level 1, level 2).
+struct TLBufs {
+    const uint32_t *bo;
+    uint32_t *cs, *nb2, *P, *t2, *o2, *fst, *order;
+    uint64_t *ostat;
+    void *e1, *e2;
+    uint8_t *sub1;
+};
+
+template <bool PK1, bool PK2>
+msf_status two_level_passes(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
+                            const void *d_w, msf_wtype wt, const TwoLevel &tl, int64_t epb,
+                            uint32_t nblk, size_t g2max, size_t nt2, uint32_t otiles,
+                            uint32_t cb, const TLBufs &B, uint32_t *row_ptr, uint32_t *col,
+                            uint64_t *key, uint64_t *r_first)
+{
+    hipStream_t s = c->stream;
+    const int NC = tl.NC;
+    auto *e1 = (RecT<PK1> *)B.e1;
+    auto *e2 = (RecT<PK2> *)B.e2;
+    // B1
+    if (wt == MSF_W_F32)
+        k_part_edges<MSF_W_F32, PK1><<<nblk, TL_NT, 0, s>>>(d_edges, d_w, m, n, tl.L1, NC, epb,
+                                                            nblk, B.bo, tl.L2, cb, e1, B.sub1);
+    else
+        k_part_edges<MSF_W_U32, PK1><<<nblk, TL_NT, 0, s>>>(d_edges, d_w, m, n, tl.L1, NC, epb,
+                                                            nblk, B.bo, tl.L2, cb, e1, B.sub1);
+    // P, A2, scan, B2
+    k_tl_plan<<<1, 1024, 0, s>>>(B.bo, nblk, NC, B.cs, B.nb2, B.P);
+    launch_fill_u32(s, B.t2, 0u, nt2);
+    k_tl_hist2<<<(unsigned)g2max, 256, 0, s>>>(B.sub1, tl.nsub, NC, B.cs, B.nb2, B.P, B.t2);
+    MSF_TRY(scan_u32(c, B.t2, B.o2, (int64_t)nt2, nullptr));
+    k_part_sub<PK1, PK2><<<(unsigned)g2max, TL_NT, 0, s>>>(e1, tl.L2, tl.nsub, NC, B.cs, B.nb2,
+                                                           B.P, B.o2, cb, e2);
+    // C
+    const unsigned nf = (unsigned)NC * (unsigned)tl.nsub;
+    k_tl_fstart<<<(nf + 256) / 256, 256, 0, s>>>(B.o2, B.nb2, B.P, tl.nsub, NC, B.fst);
+    launch_fill_u64(s, B.ostat, 0ull, otiles);
+    launch_fill_u32(s, &c->dcnt->ticket, 0u, 1);
+    k_tl_order<<<otiles, TO_NT, 0, s>>>(B.fst, nf, (uint32_t)TC_CAP, B.order, B.ostat,
+                                       &c->dcnt->ticket);
+    const size_t RC = ((size_t)1 << tl.L2) * tc_copies(tl.L2);
+    if (r_first)
+        k_tl_place<true, PK2><<<nf, TC_NT, 12 * RC, s>>>(e2, n, tl.L2, cb, B.fst, B.order, row_ptr,
+                                                         col, key, r_first);
+    else
+        k_tl_place<false, PK2><<<nf, TC_NT, 4 * RC, s>>>(e2, n, tl.L2, cb, B.fst, B.order, row_ptr,
+                                                          col, key, nullptr);
+    MSF_HIP(hipGetLastError());
+    return MSF_OK;
+}
+
+}  // namespace
+
 msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
                            msf_wtype wt, const TwoLevel &tl, uint32_t *row_ptr, uint32_t *col,
                            uint64_t *key, uint64_t *r_first)
 {
-    hipStream_t s = c->stream;
     const int NC = tl.NC;
     int64_t epb = (m + 2047) / 2048;
     if (epb < 32768) epb = 32768;
@@ -578,11 +707,17 @@ msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
     const size_t cap = 2 * (size_t)m;  // stored entries, at most
     const size_t g2max = (cap + TL_E2 - 1) / TL_E2 + (size_t)NC;
     const size_t nt2 = (size_t)tl.nsub * g2max;
+    // packed 12-byte records where edge id, column and the row's low bits
+    // fit in 64 bits
+    const uint32_t cb = (uint32_t)bits_for((uint64_t)(n > 1 ? n - 1 : 1));
+    const int eb = bits_for((uint64_t)(m > 1 ? m - 1 : 1));
+    const bool pk1 = (TL_PACK & 1) && eb + (int)cb + tl.L1 <= 64;
+    const bool pk2 = (TL_PACK & 2) && eb + (int)cb + tl.L2 <= 64;
     void *vbh, *vbo, *ve1, *ve2, *vsub, *vplan, *vt2, *vo2;
     MSF_TRY(ws_get(c, WS_BH, 4 * nh, &vbh));
     MSF_TRY(ws_get(c, WS_BHOFF, 4 * (nh + 1), &vbo));
-    MSF_TRY(ws_get(c, WS_TL1, 16 * cap, &ve1));
-    MSF_TRY(ws_get(c, WS_TL2, 16 * cap, &ve2));
+    MSF_TRY(ws_get(c, WS_TL1, (pk1 ? 12 : 16) * cap, &ve1));
+    MSF_TRY(ws_get(c, WS_TL2, (pk2 ? 12 : 16) * cap, &ve2));
     MSF_TRY(ws_get(c, WS_TLSUB, cap + 4, &vsub));
     MSF_TRY(ws_get(c, WS_TLPLAN, 4 * (3 * (size_t)NC + 3), &vplan));
     MSF_TRY(ws_get(c, WS_T2, 4 * nt2, &vt2));
@@ -590,51 +725,40 @@ msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
     void *vfs;
     const size_t nfine = (size_t)NC * (size_t)tl.nsub;
     MSF_TRY(ws_get(c, WS_FSTART, 4 * (nfine + 1), &vfs));
-    uint32_t *fst = (uint32_t *)vfs;
     // placement order (nfine u32) and its look-back status (one u64 per tile)
     const uint32_t otiles = (uint32_t)((nfine + TO_TILE - 1) / TO_TILE);
     void *vord;
     MSF_TRY(ws_get(c, WS_TLORDER, 4 * nfine + 8 * (size_t)otiles + 8, &vord));
-    uint32_t *order = (uint32_t *)vord;
-    uint64_t *ostat = (uint64_t *)(((uintptr_t)(order + nfine) + 7) & ~(uintptr_t)7);
-    uint32_t *bh = (uint32_t *)vbh, *bo = (uint32_t *)vbo;
-    uint32_t *cs = (uint32_t *)vplan, *nb2 = cs + NC + 1, *P = nb2 + NC;
-    uint32_t *t2 = (uint32_t *)vt2, *o2 = (uint32_t *)vo2;
-    uint4 *e1 = (uint4 *)ve1, *e2 = (uint4 *)ve2;
-    uint8_t *sub1 = (uint8_t *)vsub;
+    TLBufs B;
+    B.order = (uint32_t *)vord;
+    B.ostat = (uint64_t *)(((uintptr_t)(B.order + nfine) + 7) & ~(uintptr_t)7);
+    B.fst = (uint32_t *)vfs;
+    uint32_t *bh = (uint32_t *)vbh;
+    B.bo = (const uint32_t *)vbo;
+    B.cs = (uint32_t *)vplan;
+    B.nb2 = B.cs + NC + 1;
+    B.P = B.nb2 + NC;
+    B.t2 = (uint32_t *)vt2;
+    B.o2 = (uint32_t *)vo2;
+    B.e1 = ve1;
+    B.e2 = ve2;
+    B.sub1 = (uint8_t *)vsub;
 
     // A1 (coarse histogram; also validates endpoints and weights) + scan
     MSF_TRY(launch_bucket_hist(c, d_edges, d_w, m, n, tl.L1, NC, (uint32_t)n, (uint32_t)NC, epb,
                                nblk, wt, bh));
-    MSF_TRY(scan_u32(c, bh, bo, (int64_t)nh, &c->dcnt->count));
-    // B1
-    if (wt == MSF_W_F32)
-        k_part_edges<MSF_W_F32><<<nblk, TL_NT, 0, s>>>(d_edges, d_w, m, n, tl.L1, NC, epb, nblk,
-                                                       bo, tl.L2, e1, sub1);
-    else
-        k_part_edges<MSF_W_U32><<<nblk, TL_NT, 0, s>>>(d_edges, d_w, m, n, tl.L1, NC, epb, nblk,
-                                                       bo, tl.L2, e1, sub1);
-    // P, A2, scan, B2
-    k_tl_plan<<<1, 1024, 0, s>>>(bo, nblk, NC, cs, nb2, P);
-    launch_fill_u32(s, t2, 0u, nt2);
-    k_tl_hist2<<<(unsigned)g2max, 256, 0, s>>>(sub1, tl.nsub, NC, cs, nb2, P, t2);
-    MSF_TRY(scan_u32(c, t2, o2, (int64_t)nt2, nullptr));
-    k_part_sub<<<(unsigned)g2max, TL_NT, 0, s>>>(e1, tl.L2, tl.nsub, NC, cs, nb2, P, o2, e2);
-    // C
-    const unsigned nf = (unsigned)NC * (unsigned)tl.nsub;
-    k_tl_fstart<<<(nf + 256) / 256, 256, 0, s>>>(o2, nb2, P, tl.nsub, NC, fst);
-    launch_fill_u64(s, ostat, 0ull, otiles);
-    launch_fill_u32(s, &c->dcnt->ticket, 0u, 1);
-    k_tl_order<<<otiles, TO_NT, 0, s>>>(fst, nf, (uint32_t)TC_CAP, order, ostat, &c->dcnt->ticket);
-    const size_t RC = ((size_t)1 << tl.L2) * tc_copies(tl.L2);
-    if (r_first)
-        k_tl_place<true><<<nf, TC_NT, 12 * RC, s>>>(e2, n, tl.L2, fst, order, row_ptr, col, key,
-                                                    r_first);
-    else
-        k_tl_place<false><<<nf, TC_NT, 4 * RC, s>>>(e2, n, tl.L2, fst, order, row_ptr, col, key,
-                                                     nullptr);
-    MSF_HIP(hipGetLastError());
-    return MSF_OK;
+    MSF_TRY(scan_u32(c, bh, (uint32_t *)vbo, (int64_t)nh, &c->dcnt->count));
+    if (pk1 && pk2)
+        return two_level_passes<true, true>(c, n, m, d_edges, d_w, wt, tl, epb, nblk, g2max, nt2,
+                                            otiles, cb, B, row_ptr, col, key, r_first);
+    if (pk2)
+        return two_level_passes<false, true>(c, n, m, d_edges, d_w, wt, tl, epb, nblk, g2max, nt2,
+                                             otiles, cb, B, row_ptr, col, key, r_first);
+    if (pk1)
+        return two_level_passes<true, false>(c, n, m, d_edges, d_w, wt, tl, epb, nblk, g2max, nt2,
+                                             otiles, cb, B, row_ptr, col, key, r_first);
+    return two_level_passes<false, false>(c, n, m, d_edges, d_w, wt, tl, epb, nblk, g2max, nt2,
+                                          otiles, cb, B, row_ptr, col, key, r_first);
 }
 
 }  // namespace msf
