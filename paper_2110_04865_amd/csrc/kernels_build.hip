@@ -26,6 +26,16 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n)
     size_t stride = (size_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) p[i] = v;
 }
+// Look-back preparation in one launch: status[0..tiles) and two short runs
+// of u32 counters (z1[0..n1), z2[0..n2)) set to zero.
+__global__ void k_zero_lookback(uint64_t *status, uint32_t tiles, uint32_t *z1, uint32_t n1,
+                                uint32_t *z2, uint32_t n2)
+{
+    const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint32_t i = i0; i < tiles; i += gridDim.x * blockDim.x) status[i] = 0;
+    if (i0 < n1) z1[i0] = 0;
+    if (i0 < n2) z2[i0] = 0;
+}
 __global__ void k_iota_u32(uint32_t *p, size_t n)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -48,6 +58,12 @@ void launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t v, size_t n)
 void launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, size_t n)
 {
     if (n) k_fill_u32<<<grid_for(n), 256, 0, s>>>(p, v, n);
+}
+void launch_zero_lookback(hipStream_t s, uint64_t *status, uint32_t tiles, uint32_t *z1,
+                          uint32_t n1, uint32_t *z2, uint32_t n2)
+{
+    const uint32_t need = tiles > n1 ? (tiles > n2 ? tiles : n2) : (n1 > n2 ? n1 : n2);
+    k_zero_lookback<<<grid_for(need > 0 ? need : 1), 256, 0, s>>>(status, tiles, z1, n1, z2, n2);
 }
 void launch_iota_u32(hipStream_t s, uint32_t *p, size_t n)
 {
@@ -148,8 +164,8 @@ msf_status scan_u32(Ctx *c, const uint32_t *in, uint32_t *out, int64_t N, uint32
     void *st;
     msf_status rc = ws_get(c, WS_STATUS, sizeof(uint64_t) * (size_t)ntiles, &st);
     if (rc) return rc;
-    launch_fill_u64(c->stream, (uint64_t *)st, 0ull, (size_t)ntiles);
-    launch_fill_u32(c->stream, &c->dcnt->ticket, 0u, 1);
+    launch_zero_lookback(c->stream, (uint64_t *)st, (uint32_t)ntiles, &c->dcnt->ticket, 1,
+                         nullptr, 0);
     k_scan_u32<<<(unsigned)ntiles, SCAN_NT, 0, c->stream>>>(in, out, N, (uint64_t *)st, c->dcnt,
                                                           total_out);
     return MSF_OK;

@@ -677,8 +677,7 @@ msf_status two_level_passes(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges
     // C
     const unsigned nf = (unsigned)NC * (unsigned)tl.nsub;
     k_tl_fstart<<<(nf + 256) / 256, 256, 0, s>>>(B.o2, B.nb2, B.P, tl.nsub, NC, B.fst);
-    launch_fill_u64(s, B.ostat, 0ull, otiles);
-    launch_fill_u32(s, &c->dcnt->ticket, 0u, 1);
+    launch_zero_lookback(s, B.ostat, otiles, &c->dcnt->ticket, 1, nullptr, 0);
     k_tl_order<<<otiles, TO_NT, 0, s>>>(B.fst, nf, (uint32_t)TC_CAP, B.order, B.ostat,
                                        &c->dcnt->ticket);
     const size_t RC = ((size_t)1 << tl.L2) * tc_copies(tl.L2);

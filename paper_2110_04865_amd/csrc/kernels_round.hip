@@ -37,11 +37,10 @@ uint32_t ct_tiles(uint64_t n) { return (uint32_t)((n + CT_TILE - 1) / CT_TILE); 
 
 uint32_t compaction_tiles(uint64_t n) { return ct_tiles(n); }
 
-// Zero the look-back status of `tiles` tiles and the ticket.
+// Zero the look-back status of `tiles` tiles and the ticket (one launch).
 static void prep_lookback(hipStream_t s, uint64_t *status, uint32_t tiles, Counters *dcnt)
 {
-    launch_fill_u64(s, status, 0ull, tiles);
-    launch_fill_u32(s, &dcnt->ticket, 0u, 1);
+    launch_zero_lookback(s, status, tiles, &dcnt->ticket, 1, nullptr, 0);
 }
 
 // ----------------------------------------------------------- root list --
@@ -193,8 +192,9 @@ void launch_tiebreak(hipStream_t s, const uint32_t *R, uint32_t nR, uint32_t *h,
                      uint64_t *status, Counters *dcnt)
 {
     const uint32_t tiles = ct_tiles(nR);
+    // one launch clears the look-back status, the ticket and nR, nF, hooks
+    launch_zero_lookback(s, status, tiles, &dcnt->ticket, 1, &dcnt->nR, 3);
     if (!tiles) return;
-    prep_lookback(s, status, tiles, dcnt);
     k_tiebreak<<<tiles, CT_NT, 0, s>>>(R, nR, h, hedge, in_forest, Rnext, F, status, dcnt);
 }
 

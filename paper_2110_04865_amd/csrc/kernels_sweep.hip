@@ -229,6 +229,8 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
         __syncthreads();
         c = s_ticket;
     } else {
+        // the sum k_reduce_live adds into, cleared before any workgroup leaves
+        if (wave_live && blockIdx.x == 0 && threadIdx.x == 0) cnt->live = 0;
         const uint32_t q = blockIdx.x % S, k = blockIdx.x / S;
         if (k >= sl.cbase[q + 1] - sl.cbase[q]) return;  // slice q has fewer chunks
         c = sl.cbase[q] + k;
@@ -504,6 +506,7 @@ __global__ void k_rowptr_compact(const uint32_t *__restrict__ row_ptr, int32_t n
     }
 }
 
+// Sum of the per-wave live counts into cnt->live (cleared by the sweep).
 __global__ void k_reduce_live(const uint32_t *__restrict__ wave_live, size_t count,
                               Counters *cnt)
 {
@@ -530,7 +533,6 @@ void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r, C
             a.row_ptr, a.col, a.key, a.chunk_row, a.sl, a.n, p, r, nullptr, nullptr, nullptr,
             nullptr, nullptr, dcnt, wave_live, read_filter ? 1 : 0);
     if (wave_live) {
-        launch_fill_u64(s, &dcnt->live, 0ull, 1);
         const size_t count = (size_t)a.nchunks * (SWEEP_BLOCK / 64);
         k_reduce_live<<<64, 256, 0, s>>>(wave_live, count, dcnt);
     }
@@ -544,8 +546,7 @@ void launch_sweep_compact(hipStream_t s, const Adj &a, const uint32_t *p, uint64
     if (a.nnz == 0) return;
     uint32_t *wpre = chunk_info;
     uint32_t *mask = chunk_info + (size_t)a.nchunks * (SWEEP_CHUNK / 32);
-    launch_fill_u64(s, status, 0ull, a.nchunks);
-    launch_fill_u32(s, &dcnt->ticket, 0u, 1);
+    launch_zero_lookback(s, status, a.nchunks, &dcnt->ticket, 1, nullptr, 0);
     k_sweep<true, false><<<a.nchunks, SWEEP_BLOCK, 0, s>>>(
         a.row_ptr, a.col, a.key, a.chunk_row, a.sl, a.n, p, r, wpre, mask, col_out, key_out,
         status, dcnt, nullptr, read_filter ? 1 : 0);

@@ -270,6 +270,10 @@ void launch_chunk_rows(hipStream_t s, const uint32_t *row_ptr, int32_t n, uint32
 void launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t v, size_t n);
 void launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, size_t n);
 void launch_iota_u32(hipStream_t s, uint32_t *p, size_t n);
+// status[0..tiles) = 0, z1[0..n1) = 0, z2[0..n2) = 0 in one launch (n1, n2
+// at most a few hundred)
+void launch_zero_lookback(hipStream_t s, uint64_t *status, uint32_t tiles, uint32_t *z1,
+                          uint32_t n1, uint32_t *z2, uint32_t n2);
 // With wave_live (SWEEP_BLOCK/64 u32 per chunk), dcnt->live receives the
 // number of live entries (p_i != p_j).
 // read_filter: read r before each atomic and skip non-improving updates
@@ -292,6 +296,7 @@ void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S,
                        uint64_t *status, Counters *dcnt);
 void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, const uint32_t *p,
                  const int32_t *edges, uint32_t *h, uint32_t *hedge);
+// Also zeroes dcnt->nR, nF and hooks before counting them.
 void launch_tiebreak(hipStream_t s, const uint32_t *R, uint32_t nR, uint32_t *h,
                      const uint32_t *hedge, uint8_t *in_forest, uint32_t *Rnext, uint32_t *F,
                      uint64_t *status, Counters *dcnt);
