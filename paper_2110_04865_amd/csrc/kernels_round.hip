@@ -6,10 +6,13 @@
 // start of every round; R lists the roots that may still have an outgoing
 // edge; r[i] holds root i's minimum outgoing key after the sweep.
 //
-// Lists (R, F, output ids) are built by ordered tile compaction: each
+// The root lists (R, F) are built by ordered tile compaction: each
 // workgroup takes a tile from a ticket, counts, and gets its output offset
 // from a decoupled look-back, so one counter atomic is issued per tile
-// rather than per wave, and list order is deterministic.
+// rather than per wave, and list order is deterministic.  The output ids
+// (up to m/8192 tiles) are counted, scanned and written in separate passes
+// instead: a long chain of tickets and look-backs costs more there than a
+// second read of the flags.
 #include "msf_internal.hpp"
 #include "wave.hpp"
 
@@ -97,7 +100,8 @@ void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S,
 
 __global__ void k_hook(const uint32_t *__restrict__ R, uint32_t nR, uint64_t *__restrict__ r,
                        const uint32_t *__restrict__ p, const int32_t *__restrict__ edges,
-                       uint32_t *__restrict__ h, uint32_t *__restrict__ hedge)
+                       uint32_t *__restrict__ h, uint32_t *__restrict__ hedge,
+                       uint32_t *__restrict__ hwk)
 {
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nR; k += stride) {
@@ -110,6 +114,7 @@ __global__ void k_hook(const uint32_t *__restrict__ R, uint32_t nR, uint64_t *__
             const uint32_t b = p[edges[2 * (size_t)e + 1]];
             h[i] = (a == i) ? b : a;
             hedge[i] = e;
+            hwk[i] = (uint32_t)(key >> 32);  // the hooked edge's weight key
         } else {
             h[i] = i;
             hedge[i] = NONE32;
@@ -118,9 +123,98 @@ __global__ void k_hook(const uint32_t *__restrict__ R, uint32_t nR, uint64_t *__
 }
 
 void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, const uint32_t *p,
-                 const int32_t *edges, uint32_t *h, uint32_t *hedge)
+                 const int32_t *edges, uint32_t *h, uint32_t *hedge, uint32_t *hwk)
 {
-    if (nR) k_hook<<<grid_for(nR), 256, 0, s>>>(R, nR, r, p, edges, h, hedge);
+    if (nR) k_hook<<<grid_for(nR), 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk);
+}
+
+// ------------------------------------------------------- forest weight --
+// The forest weight is summed exactly as the hooks are kept: uint32 weights
+// in u64; float32 weights as integers in units of 2^-149 (the smallest
+// float32 subnormal) split over 32-bit digits held in int64 lanes, so the
+// sum does not depend on the order of additions; infinities are counted
+// separately.  The shortcut chase visits every kept hook once; each of its
+// workgroups adds its partial sums to the counters with one atomic per
+// digit in use, and k_total rounds once at the end.  The weight comes back
+// from the key's high word: for float32 the key map is undone.
+
+constexpr int ACC_DIGITS = 10;
+
+struct WSum {
+    uint64_t su = 0;
+    int64_t acc[ACC_DIGITS] = {};
+    uint32_t pinf = 0, ninf = 0;
+};
+
+template <int WT>
+__device__ __forceinline__ void wsum_add(WSum &ws, uint32_t wkey)
+{
+    if (WT == MSF_W_U32) {
+        ws.su += wkey;
+        return;
+    }
+    // undo the order-preserving map: keys >= 2^31 were non-negative floats
+    const uint32_t b = (wkey & 0x80000000u) ? (wkey & 0x7FFFFFFFu) : ~wkey;
+    const uint32_t ex = (b >> 23) & 0xFFu;
+    const bool neg = (b >> 31) != 0;
+    if (ex == 0xFFu) {
+        if (neg) ++ws.ninf;
+        else ++ws.pinf;
+        return;
+    }
+    const uint64_t mant = ex ? ((b & 0x7FFFFFu) | 0x800000u) : (b & 0x7FFFFFu);
+    const uint32_t sh = ex ? ex - 1u : 0u;  // value = mant * 2^(sh-149)
+    const uint64_t x = mant << (sh & 31u);
+    const uint32_t di = sh >> 5;
+    const int64_t lo = (int64_t)(x & 0xFFFFFFFFull), hi = (int64_t)(x >> 32);
+#pragma unroll
+    for (int d = 0; d < ACC_DIGITS; ++d) {
+        const int64_t add = (d == (int)di) ? lo : ((d == (int)di + 1) ? hi : 0);
+        ws.acc[d] += neg ? -add : add;
+    }
+}
+
+// Most blocks a chase launch uses (each leaves one partial).
+constexpr unsigned CHASE_BLOCKS = 2048;
+
+// Workgroup sum of every thread's WSum into out[j * stride], j < WS_WORDS
+// (thread 0 writes: u64 sum, ACC_DIGITS digits, +inf and -inf counts).  `lds` holds
+// (NT/64) * (ACC_DIGITS + 1) int64; contains __syncthreads().
+constexpr int WS_WORDS = ACC_DIGITS + 3;
+
+template <int NT, int WT>
+__device__ __forceinline__ void wsum_block(WSum &ws, int64_t *lds, int64_t *out, uint32_t stride)
+{
+    constexpr int W = ACC_DIGITS + 1;
+    const int wv = threadIdx.x >> 6;
+    if (WT == MSF_W_U32) {
+        const uint64_t v = wave_sum(ws.su);
+        if (__lane_id() == 0) lds[wv * W] = (int64_t)v;
+    } else {
+        // a weight touches two adjacent digits: reduce only digits some
+        // lane uses (the ballot is uniform across the wave)
+#pragma unroll
+        for (int d = 0; d < ACC_DIGITS; ++d) {
+            const int64_t v = __ballot(ws.acc[d] != 0) ? wave_sum(ws.acc[d]) : 0;
+            if (__lane_id() == 0) lds[wv * W + d] = v;
+        }
+        const uint32_t pi = __ballot(ws.pinf != 0) ? wave_sum(ws.pinf) : 0u;
+        const uint32_t ni = __ballot(ws.ninf != 0) ? wave_sum(ws.ninf) : 0u;
+        if (__lane_id() == 0) lds[wv * W + ACC_DIGITS] = ((int64_t)pi << 32) | ni;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    int64_t o[WS_WORDS] = {};
+    for (int i = 0; i < NT / 64; ++i) {
+        if (WT == MSF_W_U32) {
+            o[0] += lds[i * W];
+        } else {
+            for (int d = 0; d < ACC_DIGITS; ++d) o[1 + d] += lds[i * W + d];
+            o[1 + ACC_DIGITS] += (int64_t)(uint32_t)(lds[i * W + ACC_DIGITS] >> 32);
+            o[2 + ACC_DIGITS] += lds[i * W + ACC_DIGITS] & 0xFFFFFFFFll;
+        }
+    }
+    for (int j = 0; j < WS_WORDS; ++j) out[(size_t)j * stride] = o[j];
 }
 
 // ----------------------------------------------------------- tie break --
@@ -205,16 +299,23 @@ void launch_tiebreak(hipStream_t s, const uint32_t *R, uint32_t nR, uint32_t *h,
 // read of h[x] is an ancestor of x (or x itself for a final root, which is
 // never written), and the hook forest is acyclic after tie breaking, so each
 // chase ends after at most the height of its tree; a hard cap of nF steps
-// turns a (theoretically impossible) cycle into an error flag.
+// turns a (theoretically impossible) cycle into an error flag.  F lists the
+// kept hooks, so the chase also adds their edges' weights to the forest
+// weight (hwk: the hook's weight key).
 
+template <int WT>
 __global__ __launch_bounds__(256) void k_chase(const uint32_t *__restrict__ F, uint32_t nF,
-                                               uint32_t *h, uint32_t *part)
+                                               uint32_t *h, const uint32_t *__restrict__ hwk,
+                                               uint32_t *part, int64_t *wpart)
 {
     __shared__ uint32_t s_lds[256 / 64 + 1];
+    __shared__ int64_t s_sum[(256 / 64) * (ACC_DIGITS + 1)];
     const uint32_t stride = gridDim.x * blockDim.x;
     uint32_t longest = 0, broken = 0;
+    WSum ws;
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nF; k += stride) {
         const uint32_t i = F[k];
+        wsum_add<WT>(ws, hwk[i]);
         uint32_t x = load_relaxed_u32(h + i);
         uint32_t steps = 0;
         for (;;) {
@@ -245,37 +346,67 @@ __global__ __launch_bounds__(256) void k_chase(const uint32_t *__restrict__ F, u
         }
         part[blockIdx.x] = v | (br << 31);
     }
+    wsum_block<256, WT>(ws, s_sum, wpart + blockIdx.x, CHASE_BLOCKS);
 }
 
-// Fold per-block chase results into the counters.
-__global__ void k_chase_fold(const uint32_t *__restrict__ part, uint32_t nb, Counters *cnt)
+// Fold per-block chase results into the counters: the longest chase, the
+// cycle flag and the kept hooks' weight sums (wpart[j * CHASE_BLOCKS + b]).
+__global__ __launch_bounds__(256) void k_chase_fold(const uint32_t *__restrict__ part,
+                                                    const int64_t *__restrict__ wpart,
+                                                    uint32_t nb, Counters *cnt)
 {
+    __shared__ int64_t s_w[4][WS_WORDS + 1];
     uint32_t v = 0, br = 0;
-    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) {
+    int64_t w[WS_WORDS] = {};
+    for (uint32_t i = threadIdx.x; i < nb; i += 256) {
         const uint32_t o = part[i];
         v = (o & 0x7FFFFFFFu) > v ? (o & 0x7FFFFFFFu) : v;
         br |= o >> 31;
+#pragma unroll
+        for (int j = 0; j < WS_WORDS; ++j) w[j] += wpart[(size_t)j * CHASE_BLOCKS + i];
     }
     for (int d = 32; d >= 1; d >>= 1) {
         const uint32_t o = __shfl_xor(v, d, 64);
         v = o > v ? o : v;
         br |= __shfl_xor(br, d, 64);
     }
-    if (__lane_id() == 0) {
-        atomicMax(&cnt->max_chase, v);
-        if (br) atomicOr(&cnt->err, ERR_CYCLE);
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < WS_WORDS; ++j) {
+        const int64_t t = wave_sum(w[j]);
+        if (__lane_id() == 0) s_w[wv][j] = t;
     }
+    if (__lane_id() == 0) s_w[wv][WS_WORDS] = (int64_t)(v | (br << 31));
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int i = 1; i < 4; ++i) {
+        for (int j = 0; j < WS_WORDS; ++j) s_w[0][j] += s_w[i][j];
+        const uint32_t o = (uint32_t)s_w[i][WS_WORDS];
+        v = (o & 0x7FFFFFFFu) > v ? (o & 0x7FFFFFFFu) : v;
+        br |= o >> 31;
+    }
+    atomicMax(&cnt->max_chase, v);
+    if (br) atomicOr(&cnt->err, ERR_CYCLE);
+    cnt->total_u64 += (uint64_t)s_w[0][0];
+    for (int d = 0; d < ACC_DIGITS; ++d) cnt->acc[d] += s_w[0][1 + d];
+    cnt->inf_pos += (uint32_t)s_w[0][1 + ACC_DIGITS];
+    cnt->inf_neg += (uint32_t)s_w[0][2 + ACC_DIGITS];
 }
 
-constexpr unsigned CHASE_BLOCKS = 2048;
 
-void launch_chase(hipStream_t s, const uint32_t *F, uint32_t nF, uint32_t *h, uint32_t *part,
-                  Counters *dcnt)
+void launch_chase(hipStream_t s, const uint32_t *F, uint32_t nF, uint32_t *h,
+                  const uint32_t *hwk, msf_wtype wt, uint32_t *part, Counters *dcnt)
 {
     if (!nF) return;
     const unsigned g = grid_for(nF, 256, CHASE_BLOCKS);
-    k_chase<<<g, 256, 0, s>>>(F, nF, h, part);
-    k_chase_fold<<<1, 256, 0, s>>>(part, g, dcnt);
+    // part: the per-block chase words, then per-block weight sums (aligned)
+    int64_t *wpart = reinterpret_cast<int64_t *>(
+        ((uintptr_t)(part + CHASE_BLOCKS) + 7) & ~(uintptr_t)7);
+    if (wt == MSF_W_F32)
+        k_chase<MSF_W_F32><<<g, 256, 0, s>>>(F, nF, h, hwk, part, wpart);
+    else
+        k_chase<MSF_W_U32><<<g, 256, 0, s>>>(F, nF, h, hwk, part, wpart);
+    k_chase_fold<<<1, 256, 0, s>>>(part, wpart, g, dcnt);
 }
 
 // p[v] <- h[p[v]] for every vertex that still has stored entries: p[v] is an
@@ -304,40 +435,18 @@ void launch_update_parents(hipStream_t s, const uint32_t *row_ptr, int32_t n, in
 }
 
 // --------------------------------------------------------------- output --
-// Forest flags -> ascending edge ids (ordered tile compaction), the count,
-// and the forest weight.  uint32 weights sum exactly in u64; float32 weights
-// are added exactly as integers in units of 2^-149 (the smallest float32
-// subnormal) split over 32-bit digits held in int64 lanes, so the result is
-// independent of the order of additions; infinities are counted
-// separately.  Each tile writes its partial sums to part[tile]; k_total
-// folds them and rounds once.
+// Forest flags -> ascending edge ids and their count (count per tile, scan,
+// write); the forest weight was summed by the tie breaks and is rounded once
+// by k_total.
 
 constexpr int OUT_NT = 256;
 constexpr int OUT_IT = 32;
 constexpr int OUT_TILE = OUT_NT * OUT_IT;
-constexpr int ACC_DIGITS = 10;
 
-struct TilePart {
-    int64_t acc[ACC_DIGITS];
-    uint64_t u64;
-    uint32_t pinf, ninf;
-};
-
-template <int WT>
-__global__ __launch_bounds__(OUT_NT) void k_output(const uint8_t *__restrict__ flags, int64_t m,
-                                                  const void *__restrict__ w,
-                                                  int32_t *__restrict__ ids, uint64_t *status,
-                                                  TilePart *__restrict__ part, Counters *cnt)
+// A thread's OUT_IT flags as OUT_IT/4 words (one byte per flag).
+__device__ __forceinline__ void load_flags(const uint8_t *__restrict__ flags, int64_t m,
+                                           int64_t base, uint32_t (&fw)[OUT_IT / 4])
 {
-    __shared__ uint32_t s_tile;
-    __shared__ uint64_t s_lds[OUT_NT / 64 + 1];
-    __shared__ uint64_t s_pre;
-    __shared__ int64_t s_acc[OUT_NT / 64][ACC_DIGITS + 1];
-    if (threadIdx.x == 0) s_tile = atomicAdd(&cnt->ticket, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const int64_t base = (int64_t)tile * OUT_TILE + (int64_t)threadIdx.x * OUT_IT;
-    uint32_t fw[OUT_IT / 4];
     if (base + OUT_IT <= m) {
 #pragma unroll
         for (int q = 0; q < OUT_IT / 16; ++q) {
@@ -358,119 +467,61 @@ __global__ __launch_bounds__(OUT_NT) void k_output(const uint8_t *__restrict__ f
             fw[q] = x;
         }
     }
+}
+
+__device__ __forceinline__ uint32_t count_flags(const uint32_t (&fw)[OUT_IT / 4])
+{
     uint32_t c = 0;
 #pragma unroll
     for (int q = 0; q < OUT_IT / 4; ++q)
         for (int b = 0; b < 4; ++b) c += ((fw[q] >> (8 * b)) & 0xFFu) ? 1u : 0u;
-    uint32_t pos, unused;
-    uint64_t tot;
-    tile_offsets2<OUT_NT>(tile, c, 0u, status, s_lds, &s_pre, &pos, &unused, &tot);
-    uint64_t su = 0;
-    int64_t acc[ACC_DIGITS];
-#pragma unroll
-    for (int d = 0; d < ACC_DIGITS; ++d) acc[d] = 0;
-    uint32_t pinf = 0, ninf = 0;
+    return c;
+}
+
+// Pass 1 (tile = workgroup): the tile's forest-edge count.
+__global__ __launch_bounds__(OUT_NT) void k_output_count(const uint8_t *__restrict__ flags,
+                                                        int64_t m,
+                                                        uint32_t *__restrict__ tile_cnt)
+{
+    __shared__ uint64_t s_lds[OUT_NT / 64 + 1];
+    const uint32_t tile = blockIdx.x;
+    const int64_t base = (int64_t)tile * OUT_TILE + (int64_t)threadIdx.x * OUT_IT;
+    uint32_t fw[OUT_IT / 4];
+    load_flags(flags, m, base, fw);
+    const uint64_t tot = block_sum<OUT_NT>((uint64_t)count_flags(fw), s_lds);
+    if (threadIdx.x == 0) tile_cnt[tile] = (uint32_t)tot;
+}
+
+// Pass 2: the tile's ids, ascending, from its scanned offset.
+__global__ __launch_bounds__(OUT_NT) void k_output_ids(const uint8_t *__restrict__ flags,
+                                                      int64_t m,
+                                                      const uint32_t *__restrict__ tile_off,
+                                                      int32_t *__restrict__ ids)
+{
+    __shared__ uint32_t s_lds[OUT_NT / 64 + 1];
+    const uint32_t tile = blockIdx.x;
+    const int64_t base = (int64_t)tile * OUT_TILE + (int64_t)threadIdx.x * OUT_IT;
+    uint32_t fw[OUT_IT / 4];
+    load_flags(flags, m, base, fw);
+    const uint32_t c = count_flags(fw);
+    uint32_t tot;
+    uint32_t pos = tile_off[tile] + block_excl_sum<OUT_NT>(c, s_lds, &tot);
     if (c) {
         for (int k = 0; k < OUT_IT; ++k) {
             if (!((fw[k >> 2] >> (8 * (k & 3))) & 0xFFu)) continue;
-            const int64_t e = base + k;
-            ids[pos++] = (int32_t)e;
-            const uint32_t b = ((const uint32_t *)w)[e];
-            if (WT == MSF_W_U32) {
-                su += b;
-            } else {
-                const uint32_t ex = (b >> 23) & 0xFFu;
-                const bool neg = (b >> 31) != 0;
-                if (ex == 0xFFu) {
-                    if (neg) ++ninf;
-                    else ++pinf;
-                    continue;
-                }
-                const uint64_t mant = ex ? ((b & 0x7FFFFFu) | 0x800000u) : (b & 0x7FFFFFu);
-                const uint32_t sh = ex ? ex - 1u : 0u;  // value = mant * 2^(sh-149)
-                const uint64_t x = mant << (sh & 31u);
-                const uint32_t di = sh >> 5;
-                const int64_t lo = (int64_t)(x & 0xFFFFFFFFull), hi = (int64_t)(x >> 32);
-#pragma unroll
-                for (int d = 0; d < ACC_DIGITS; ++d) {
-                    const int64_t add = (d == (int)di) ? lo : ((d == (int)di + 1) ? hi : 0);
-                    acc[d] += neg ? -add : add;
-                }
-            }
+            ids[pos++] = (int32_t)(base + k);
         }
-    }
-    // tile partials: wave sums, then one record per tile
-    const int wv = threadIdx.x >> 6;
-    if (WT == MSF_W_U32) {
-        su = wave_sum(su);
-        if (__lane_id() == 0) s_acc[wv][0] = (int64_t)su;
-    } else {
-#pragma unroll
-        for (int d = 0; d < ACC_DIGITS; ++d) {
-            const int64_t v = wave_sum(acc[d]);
-            if (__lane_id() == 0) s_acc[wv][d] = v;
-        }
-        pinf = wave_sum(pinf);
-        ninf = wave_sum(ninf);
-        if (__lane_id() == 0) s_acc[wv][ACC_DIGITS] = ((int64_t)pinf << 32) | ninf;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        TilePart tp{};
-        for (int i = 0; i < OUT_NT / 64; ++i) {
-            if (WT == MSF_W_U32) {
-                tp.u64 += (uint64_t)s_acc[i][0];
-            } else {
-                for (int d = 0; d < ACC_DIGITS; ++d) tp.acc[d] += s_acc[i][d];
-                tp.pinf += (uint32_t)(s_acc[i][ACC_DIGITS] >> 32);
-                tp.ninf += (uint32_t)(s_acc[i][ACC_DIGITS] & 0xFFFFFFFFll);
-            }
-        }
-        part[tile] = tp;
-        if (tile == gridDim.x - 1) cnt->count = (uint32_t)(tot >> 31);
     }
 }
 
-// Fold tile partials (exact integer sums, any order) and round once.
-__global__ __launch_bounds__(256) void k_total(const TilePart *__restrict__ part, uint32_t ntiles,
-                                               Counters *cnt, int wt)
+// Round the exact forest weight once (one thread).
+__global__ void k_total(Counters *cnt, int wt)
 {
-    __shared__ int64_t s[256 / 64][ACC_DIGITS + 3];
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint64_t su = cnt->total_u64;
+    const uint32_t pinf = cnt->inf_pos, ninf = cnt->inf_neg;
     int64_t acc[ACC_DIGITS];
-    for (int d = 0; d < ACC_DIGITS; ++d) acc[d] = 0;
-    uint64_t su = 0;
-    uint32_t pinf = 0, ninf = 0;
-    for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
-        const TilePart &tp = part[t];
-        su += tp.u64;
-        pinf += tp.pinf;
-        ninf += tp.ninf;
-        for (int d = 0; d < ACC_DIGITS; ++d) acc[d] += tp.acc[d];
-    }
-    const int wv = threadIdx.x >> 6;
-    su = wave_sum(su);
-    pinf = wave_sum(pinf);
-    ninf = wave_sum(ninf);
-    for (int d = 0; d < ACC_DIGITS; ++d) {
-        const int64_t v = wave_sum(acc[d]);
-        if (__lane_id() == 0) s[wv][d] = v;
-    }
-    if (__lane_id() == 0) {
-        s[wv][ACC_DIGITS] = (int64_t)su;
-        s[wv][ACC_DIGITS + 1] = pinf;
-        s[wv][ACC_DIGITS + 2] = ninf;
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    for (int d = 0; d < ACC_DIGITS + 3; ++d) {
-        int64_t v = 0;
-        for (int i = 0; i < 4; ++i) v += s[i][d];
-        if (d < ACC_DIGITS) acc[d] = v;
-        else if (d == ACC_DIGITS) su = (uint64_t)v;
-        else if (d == ACC_DIGITS + 1) pinf = (uint32_t)v;
-        else ninf = (uint32_t)v;
-    }
-    cnt->total_u64 = su;
+    for (int d = 0; d < ACC_DIGITS; ++d) acc[d] = cnt->acc[d];
     if (wt == MSF_W_U32) {
         cnt->total_f64 = (double)su;  // correctly rounded conversion
         return;
@@ -529,22 +580,33 @@ __global__ __launch_bounds__(256) void k_total(const TilePart *__restrict__ part
 }
 
 int64_t output_tiles(int64_t m) { return (m + OUT_TILE - 1) / OUT_TILE; }
-size_t output_part_bytes(int64_t m) { return sizeof(TilePart) * (size_t)(output_tiles(m) + 1); }
+size_t chase_part_bytes()
+{
+    return 4 * (size_t)CHASE_BLOCKS + 8 + 8 * (size_t)CHASE_BLOCKS * WS_WORDS;
+}
 
-void launch_output(hipStream_t s, const uint8_t *in_forest, int64_t m, const void *w, msf_wtype wt,
-                   int32_t *ids, uint64_t *status, void *part, Counters *dcnt)
+size_t output_part_bytes(int64_t m)
+{
+    // per-tile counts and their scan
+    return 4 * (2 * (size_t)output_tiles(m) + 2);
+}
+
+msf_status launch_output(Ctx *c, const uint8_t *in_forest, int64_t m, const void *w,
+                         msf_wtype wt, int32_t *ids, void *part)
 {
     const int64_t ntiles = output_tiles(m);
-    if (ntiles == 0) return;
-    prep_lookback(s, status, (uint32_t)ntiles, dcnt);
-    TilePart *tp = (TilePart *)part;
-    if (wt == MSF_W_F32)
-        k_output<MSF_W_F32><<<(unsigned)ntiles, OUT_NT, 0, s>>>(in_forest, m, w, ids, status, tp,
-                                                               dcnt);
-    else
-        k_output<MSF_W_U32><<<(unsigned)ntiles, OUT_NT, 0, s>>>(in_forest, m, w, ids, status, tp,
-                                                               dcnt);
-    k_total<<<1, 256, 0, s>>>(tp, (uint32_t)ntiles, dcnt, (int)wt);
+    if (ntiles == 0) return MSF_OK;
+    hipStream_t s = c->stream;
+    (void)w;
+    // per-tile counts, then their exclusive scan
+    uint32_t *tcnt = reinterpret_cast<uint32_t *>(part);
+    uint32_t *toff = tcnt + ntiles;
+    k_output_count<<<(unsigned)ntiles, OUT_NT, 0, s>>>(in_forest, m, tcnt);
+    MSF_TRY(scan_u32(c, tcnt, toff, ntiles, &c->dcnt->count));
+    k_output_ids<<<(unsigned)ntiles, OUT_NT, 0, s>>>(in_forest, m, toff, ids);
+    k_total<<<1, 64, 0, s>>>(c->dcnt, (int)wt);
+    MSF_HIP(hipGetLastError());
+    return MSF_OK;
 }
 
 // ------------------------------------------- shortcut of arbitrary p ----

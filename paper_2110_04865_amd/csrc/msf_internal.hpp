@@ -91,7 +91,7 @@ struct DevBuf {
 // Workspace slots cached per context (grow-only).
 enum Slot {
     WS_EDGES, WS_W, WS_SLOT, WS_DEG, WS_ROWPTR, WS_COL, WS_KEY, WS_CHUNKROW,
-    WS_ROWPTR2, WS_COL2, WS_KEY2, WS_CHUNKROW2,
+    WS_ROWPTR2, WS_COL2, WS_KEY2, WS_CHUNKROW2, WS_HWK,
     WS_P, WS_R, WS_H, WS_HEDGE, WS_RL, WS_RL2, WS_FL, WS_FLAGS, WS_IDS,
     WS_STATUS, WS_WLIVE, WS_PART, WS_Q, WS_Q2,
     WS_BATCH0, WS_BATCH1, WS_BATCH2, WS_BATCH3,
@@ -122,7 +122,7 @@ struct Counters {
 };
 
 struct SolveBufs {
-    uint32_t *rp[2], *col[2], *crow[2], *p, *h, *hedge, *R[2], *F, *wlive, *cinfo;
+    uint32_t *rp[2], *col[2], *crow[2], *p, *h, *hedge, *hwk, *R[2], *F, *wlive, *cinfo;
     uint64_t *key[2], *r, *status;
     uint8_t *flags;
     void *part;
@@ -290,26 +290,32 @@ void launch_sweep_compact(hipStream_t s, const Adj &a, const uint32_t *p, uint64
 size_t chunk_info_words(uint32_t nchunks);
 
 // Round kernels.  `status` is a look-back status array (>= tiles entries);
-// `part` holds per-block partials (>= 4096 u32, or output_part_bytes(m)).
+// `part` holds per-block partials (>= 4096 u32, chase_part_bytes() or
+// output_part_bytes(m)).
 uint32_t compaction_tiles(uint64_t n);
 void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S, uint32_t *R,
                        uint64_t *status, Counters *dcnt);
+// hwk[i]: the weight key (high word of the edge key) of root i's hook
 void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, const uint32_t *p,
-                 const int32_t *edges, uint32_t *h, uint32_t *hedge);
+                 const int32_t *edges, uint32_t *h, uint32_t *hedge, uint32_t *hwk);
 // Also zeroes dcnt->nR, nF and hooks before counting them.
 void launch_tiebreak(hipStream_t s, const uint32_t *R, uint32_t nR, uint32_t *h,
                      const uint32_t *hedge, uint8_t *in_forest, uint32_t *Rnext, uint32_t *F,
                      uint64_t *status, Counters *dcnt);
-void launch_chase(hipStream_t s, const uint32_t *F, uint32_t nF, uint32_t *h, uint32_t *part,
-                  Counters *dcnt);
+// Also adds the weights of the kept hooks F (from hwk) exactly to dcnt's
+// forest-weight sums.
+void launch_chase(hipStream_t s, const uint32_t *F, uint32_t nF, uint32_t *h,
+                  const uint32_t *hwk, msf_wtype wt, uint32_t *part, Counters *dcnt);
 // S > 1: every vertex is updated (stale parents of vertices without
 // entries are never read); S == 1: only rows that still have entries.
 void launch_update_parents(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S, uint32_t *p,
                            const uint32_t *h, uint32_t *part, Counters *dcnt);
 int64_t output_tiles(int64_t m);
 size_t output_part_bytes(int64_t m);
-void launch_output(hipStream_t s, const uint8_t *in_forest, int64_t m, const void *w,
-                   msf_wtype wt, int32_t *ids, uint64_t *status, void *part, Counters *dcnt);
+// bytes `part` needs for launch_chase
+size_t chase_part_bytes();
+msf_status launch_output(Ctx *c, const uint8_t *in_forest, int64_t m, const void *w,
+                         msf_wtype wt, int32_t *ids, void *part);
 
 // Shortcut of an arbitrary parent vector (msf_shortcut).
 void launch_check_parents(hipStream_t s, const uint32_t *p, int32_t n, Counters *dcnt);

@@ -34,7 +34,8 @@ static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, int S, SolveBufs 
     const size_t nch = chunk_cap(nnz_cap);
     size_t st = std::max<size_t>(nch, (size_t)output_tiles((int64_t)mm) + 1);
     st = std::max<size_t>(st, nn / 2048 + 2);
-    const size_t part_bytes = std::max<size_t>(output_part_bytes((int64_t)mm), 4 * 4096 + 256);
+    const size_t part_bytes = std::max<size_t>(
+        {output_part_bytes((int64_t)mm), chase_part_bytes(), 4 * 4096 + 256});
     struct Req {
         Slot s;
         size_t bytes;
@@ -45,7 +46,7 @@ static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, int S, SolveBufs 
         {WS_H, 4 * nn},            {WS_HEDGE, 4 * nn},    {WS_RL, 4 * nn},
         {WS_RL2, 4 * nn},          {WS_FL, 4 * nn},       {WS_FLAGS, (mm + 16) & ~(size_t)3},
         {WS_STATUS, 8 * st},       {WS_WLIVE, 4 * (SWEEP_BLOCK / 64) * nch},
-        {WS_PART, part_bytes},
+        {WS_PART, part_bytes},     {WS_HWK, 4 * nn},
     };
     void *v[sizeof(req) / sizeof(req[0])];
     for (size_t i = 0; i < sizeof(req) / sizeof(req[0]); ++i)
@@ -65,6 +66,7 @@ static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, int S, SolveBufs 
     b->status = (uint64_t *)v[12];
     b->wlive = (uint32_t *)v[13];
     b->part = v[14];
+    b->hwk = (uint32_t *)v[15];
     b->rp[1] = b->col[1] = b->crow[1] = nullptr;
     b->key[1] = nullptr;
     return MSF_OK;
@@ -164,7 +166,7 @@ static msf_status enqueue_round(Ctx *c)
                      S.b.wlive, read_filter);
     }
     if (ev_k >= 0) MSF_HIP(hipEventRecord(c->sev[2 * ev_k + 1], s));
-    launch_hook(s, S.b.R[S.ri], S.nR, S.b.r, S.b.p, S.edges, S.b.h, S.b.hedge);
+    launch_hook(s, S.b.R[S.ri], S.nR, S.b.r, S.b.p, S.edges, S.b.h, S.b.hedge, S.b.hwk);
     launch_tiebreak(s, S.b.R[S.ri], S.nR, S.b.h, S.b.hedge, S.b.flags, S.b.R[S.ri ^ 1], S.b.F,
                     S.b.status, c->dcnt);
     return end_step(c, 3);
@@ -174,7 +176,7 @@ static msf_status enqueue_output(Ctx *c)
 {
     SolveState &S = c->ss;
     S.st.rounds = S.rounds;
-    launch_output(c->stream, S.b.flags, S.m, S.w, S.wt, S.ids, S.b.status, S.b.part, c->dcnt);
+    MSF_TRY(launch_output(c, S.b.flags, S.m, S.w, S.wt, S.ids, S.b.part));
     MSF_HIP(hipEventRecord(c->ev[2], c->stream));
     return end_step(c, 4);
 }
@@ -237,7 +239,7 @@ msf_status solve_advance(Ctx *c)
             S.live_frac = S.a.nnz ? (double)h->live / (double)S.a.nnz : 0.0;
         }
         if (nF == 0) return enqueue_output(c);
-        launch_chase(s, S.b.F, nF, S.b.h, (uint32_t *)S.b.part, c->dcnt);
+        launch_chase(s, S.b.F, nF, S.b.h, S.b.hwk, S.wt, (uint32_t *)S.b.part, c->dcnt);
         if (c->check_rounds) {
             MSF_TRY(read_counters(c));
             if (c->hcnt->err) {
