@@ -94,6 +94,10 @@ typedef struct {
                                 stored entry (column + key), 8 per row with
                                 entries (row pointer + p of the row), 8 per
                                 live root (its minimum slot)                 */
+    int32_t head_sweeps;     /* rounds swept over key-sorted runs (heads
+                                only; their sweep_bytes are 0)               */
+    int32_t reserved;
+    int64_t runs;            /* key-sorted runs of the adjacency (0: none)   */
 } msf_stats;
 
 typedef struct msf_ctx msf_ctx;

@@ -52,7 +52,9 @@ class Stats(ctypes.Structure):
                 ("max_chase", ctypes.c_int32), ("filtered", ctypes.c_int32),
                 ("hooks", ctypes.c_int64 * 64), ("active_nnz", ctypes.c_int64 * 64),
                 ("build_ms", ctypes.c_double), ("rounds_ms", ctypes.c_double),
-                ("sweep_ms", ctypes.c_double * 64), ("sweep_bytes", ctypes.c_double * 64)]
+                ("sweep_ms", ctypes.c_double * 64), ("sweep_bytes", ctypes.c_double * 64),
+                ("head_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("runs", ctypes.c_int64)]
 
 
 _lib = None
@@ -207,7 +209,8 @@ class Context:
                     filtered=s.filtered, hooks=list(s.hooks[:k]),
                     active_nnz=list(s.active_nnz[:k]), build_ms=s.build_ms,
                     rounds_ms=s.rounds_ms, sweep_ms=list(s.sweep_ms[:k]),
-                    sweep_bytes=list(s.sweep_bytes[:k]))
+                    sweep_bytes=list(s.sweep_bytes[:k]), head_sweeps=s.head_sweeps,
+                    runs=s.runs)
 
     # ------------------------------------------------------- primitives --
     def graph(self, n: int, edges, weights, wtype: int | None = None) -> "Graph":

@@ -138,6 +138,7 @@ msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc)
     if (const char *f = getenv("MSF_FIRST_ROUND")) c->first_round = atoi(f);
     if (const char *f = getenv("MSF_BUCKETED_BUILD")) c->bucketed_build = atoi(f);
     if (const char *f = getenv("MSF_SLICES")) c->slices = atoi(f);
+    if (const char *f = getenv("MSF_HEADS")) c->heads = atoi(f);
     return MSF_OK;
 }
 

@@ -1,0 +1,405 @@
+// Head sweep: the multilinear projection evaluated over key-sorted runs.
+//
+// For a star root k the projection of section 3.2 keeps the smallest key
+// over stored entries i->j with p_i == k != p_j; the multilinear function of
+// section 3.1 gives the empty key when p_i == p_j.  Trees only merge, so an
+// entry found with p_i == p_j (internal) stays internal for the rest of the
+// solve.  When a row's entries are in ascending key order, the row's
+// smallest outgoing key is the key of its first entry that is not internal,
+// and every internal entry in front of it can be passed over for good.
+//
+// Layout.  Once per solve, every 64-entry chunk of the adjacency (entries
+// [64c, 64c + 64)) is sorted by (row, key): rows keep their places and each
+// row's part of the chunk (a run, at most 64 entries) is in ascending key
+// order.  A run is described by {cur, end, row, hcol, hkey}: cur is its
+// head (first entry not yet known to be internal), hcol and hkey the head's
+// column and key (hkey = UINT64_MAX once the run is exhausted).  A sweep
+// visits runs, not entries:
+//   phase A, one lane per run: gathers p[hcol]; an outgoing head gives the
+//     run's minimum; an internal one makes the lane probe the next
+//     HEAD_PROBE entries with independent loads; a run still internal after
+//     that is queued;
+//   phase B, one wave per queued run: the rest of the run at once, first
+//     outgoing entry by ballot.
+// Both phases move the head past the internal entries they saw and fold
+// their minima into r[root] like the full sweep (read filter, 64-bit
+// atomicMin), after a wave-wide segmented minimum over lanes of the same
+// root.  While the read filter is on (few live roots), phase A first
+// compares the head's key with r[root]: runs hold ascending keys and r only
+// falls during a sweep, so a head no smaller than r[root] is passed over
+// without a gather.  A round reads 16 bytes and gathers one parent per live run plus
+// the entries that became internal, instead of every entry; the result
+// equals the full sweep's, element by element of r.
+#include "msf_internal.hpp"
+#include "wave.hpp"
+
+namespace msf {
+
+namespace {
+
+constexpr int HEAD_PROBE = 4;
+
+// 1: read r before every atomic whatever the number of live roots.
+#ifndef HEADS_READ_FILTER
+#define HEADS_READ_FILTER 0
+#endif
+
+// v from lane (lane ^ J): DPP quad permutations for 1 and 2, swizzles
+// within 32 lanes for 4..16, a permute for 32.
+template <int J>
+__device__ __forceinline__ uint32_t xor_move(uint32_t v)
+{
+    if constexpr (J == 1)
+        return dpp_u32<0xB1>(v);  // quad_perm [1,0,3,2]
+    else if constexpr (J == 2)
+        return dpp_u32<0x4E>(v);  // quad_perm [2,3,0,1]
+    else if constexpr (J <= 16)
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (J << 10));
+    else
+        return (uint32_t)__builtin_amdgcn_ds_bpermute((int)((__lane_id() ^ (uint32_t)J) << 2),
+                                                      (int)v);
+}
+
+template <int J>
+__device__ __forceinline__ uint64_t xor_move64(uint64_t v)
+{
+    return ((uint64_t)xor_move<J>((uint32_t)(v >> 32)) << 32) | xor_move<J>((uint32_t)v);
+}
+
+// One compare-exchange step of the bitonic network over 64 lanes (block
+// size KK, partner distance J): the lower lane of an ascending pair keeps
+// the smaller element.  Elements are (pi, k, payload); with PACKED the run
+// index is folded into k and pi is unused.
+template <bool PACKED, int KK, int J>
+__device__ __forceinline__ void bitonic_step(uint32_t lane, uint32_t &pi, uint64_t &k,
+                                             uint32_t &pl)
+{
+    const uint64_t ok = xor_move64<J>(k);
+    const uint32_t opl = xor_move<J>(pl);
+    bool other_less;
+    uint32_t opi = 0;
+    if constexpr (PACKED) {
+        other_less = ok < k;
+    } else {
+        opi = xor_move<J>(pi);
+        other_less = (opi < pi) | ((opi == pi) & (ok < k));
+    }
+    const bool keep_min = (((lane / (uint32_t)KK) ^ (lane / (uint32_t)J)) & 1u) == 0u;
+    const bool take = keep_min == other_less;
+    k = take ? ok : k;
+    pl = take ? opl : pl;
+    if constexpr (!PACKED) pi = take ? opi : pi;
+}
+
+template <bool PACKED, int KK, int J>
+__device__ __forceinline__ void bitonic_merge(uint32_t lane, uint32_t &pi, uint64_t &k,
+                                              uint32_t &pl)
+{
+    bitonic_step<PACKED, KK, J>(lane, pi, k, pl);
+    if constexpr (J > 1) bitonic_merge<PACKED, KK, J / 2>(lane, pi, k, pl);
+}
+
+template <bool PACKED, int KK>
+__device__ __forceinline__ void bitonic_sort(uint32_t lane, uint32_t &pi, uint64_t &k,
+                                             uint32_t &pl)
+{
+    bitonic_merge<PACKED, KK, KK / 2>(lane, pi, k, pl);
+    if constexpr (KK < 64) bitonic_sort<PACKED, KK * 2>(lane, pi, k, pl);
+}
+
+// Wave-wide minimum per run of consecutive lanes holding the same root; the
+// last lane of each run folds it into r (lanes without a root hold NONE32).
+__device__ __forceinline__ void flush_by_root(uint64_t *r, uint32_t root, uint64_t v,
+                                              int read_filter)
+{
+    const uint32_t lane = __lane_id();
+    const uint32_t prev = __shfl_up(root, 1);
+    bool head = lane == 0 || prev != root;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t ov = __shfl_up(v, d);
+        const bool oh = __shfl_up(head ? 1 : 0, d) != 0;
+        if (lane >= (uint32_t)d && !head) {
+            v = ov < v ? ov : v;
+            head = oh;
+        }
+    }
+    const uint32_t next = __shfl_down(root, 1);
+    const bool last = lane == 63 || next != root;
+    if (!last || root == NONE32 || v == KEY_INF) return;
+    if (read_filter)
+        min_into(r, root, v);
+    else
+        __hip_atomic_fetch_min(r + root, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace
+
+// Runs per row (a row's entries cut at multiples of 64).  One lane per row.
+__global__ __launch_bounds__(256) void k_runs_count(const uint32_t *__restrict__ row_ptr,
+                                                    int32_t n, uint32_t *__restrict__ rc)
+{
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= (uint32_t)n) return;
+    const uint32_t s = row_ptr[r], e = row_ptr[r + 1];
+    rc[r] = e > s ? ((e - 1u) >> 6) - (s >> 6) + 1u : 0u;
+}
+
+// Run descriptors {cur, end, row} in entry order (run roff[r] + t is row r's
+// t-th run) and the first run of every chunk.  Rows with few runs are
+// written by their lane, longer ones by the whole wave.
+__global__ __launch_bounds__(256) void k_runs_write(const uint32_t *__restrict__ row_ptr,
+                                                    int32_t n, const uint32_t *__restrict__ roff,
+                                                    uint32_t *__restrict__ cur,
+                                                    uint32_t *__restrict__ end,
+                                                    uint32_t *__restrict__ row,
+                                                    uint32_t *__restrict__ cfirst)
+{
+    const uint32_t lane = __lane_id();
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t s = 0, e = 0, o = 0;
+    if (r < (uint32_t)n) {
+        s = row_ptr[r];
+        e = row_ptr[r + 1];
+    }
+    const uint32_t nk = e > s ? ((e - 1u) >> 6) - (s >> 6) + 1u : 0u;
+    if (nk) o = roff[r];
+    auto put = [&](uint32_t rs, uint32_t re, uint32_t rr, uint32_t ro, uint32_t t) {
+        const uint32_t c0 = rs >> 6;
+        const uint32_t q = t == 0 ? rs : (c0 + t) << 6;
+        const uint32_t qe = (c0 + t + 1u) << 6 < re ? (c0 + t + 1u) << 6 : re;
+        cur[ro + t] = q;
+        end[ro + t] = qe;
+        row[ro + t] = rr;
+        if ((q & 63u) == 0) cfirst[q >> 6] = ro + t;
+    };
+    constexpr uint32_t LANE_RUNS = 8;
+    if (nk && nk <= LANE_RUNS)
+        for (uint32_t t = 0; t < nk; ++t) put(s, e, r, o, t);
+    uint64_t lm = __ballot(nk > LANE_RUNS);
+    while (lm) {
+        const int src = __ffsll((unsigned long long)lm) - 1;
+        lm &= lm - 1;
+        const uint32_t ls = __shfl(s, src), le = __shfl(e, src), lo = __shfl(o, src);
+        const uint32_t lr = __shfl(r, src), lk = __shfl(nk, src);
+        for (uint32_t t = lane; t < lk; t += 64) put(ls, le, lr, lo, t);
+    }
+}
+
+// Sort every 64-entry chunk by (run, key) in place with a bitonic network
+// over the lanes (one wave per chunk; keys are distinct within a row, and
+// runs keep their places) and store each run's head (its smallest key) into
+// its descriptor.  The chunk's runs are cfirst[c] .. cfirst[c + 1] - 1 (the
+// last chunk ends at *nruns); their starts are ORed across the lanes.  With
+// PACKED (edge ids of at most 26 bits) the sort key is one 64-bit word: run
+// index inside the chunk, weight key, edge id.
+template <bool PACKED>
+__global__ __launch_bounds__(256) void k_sort_chunks(uint32_t *__restrict__ col,
+                                                     uint64_t *__restrict__ key, uint32_t nnz,
+                                                     const uint32_t *__restrict__ cfirst,
+                                                     const uint32_t *__restrict__ nruns,
+                                                     const uint32_t *__restrict__ run_cur, int eb,
+                                                     uint32_t *__restrict__ hcol,
+                                                     uint64_t *__restrict__ hkey)
+{
+    const uint32_t lane = __lane_id();
+    const uint32_t nch = (nnz + 63u) / 64u;
+    const uint32_t c = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (c >= nch) return;  // whole waves
+    const uint32_t pos = c * 64u + lane;
+    const bool valid = pos < nnz;
+    uint64_t k = valid ? key[pos] : KEY_INF;
+    uint32_t pl = valid ? col[pos] : 0u;
+    // run starts of the chunk, from the run descriptors (OR over the lanes)
+    const uint32_t r0 = cfirst[c];
+    const uint32_t r1 = c + 1u < nch ? cfirst[c + 1u] : *nruns;
+    uint64_t sm = r0 + lane < r1 ? 1ull << (run_cur[r0 + lane] & 63u) : 0ull;
+    sm |= xor_move64<1>(sm);
+    sm |= xor_move64<2>(sm);
+    sm |= xor_move64<4>(sm);
+    sm |= xor_move64<8>(sm);
+    sm |= xor_move64<16>(sm);
+    sm |= xor_move64<32>(sm);
+    const uint64_t vmask = nnz - c * 64u >= 64u ? ~0ull : (1ull << (nnz - c * 64u)) - 1ull;
+    const uint64_t starts = sm & vmask;
+    const uint32_t below = (uint32_t)__popcll(starts & lanemask_lt());
+    const bool is_start = (starts >> lane) & 1ull;
+    uint32_t pi = valid ? below + (is_start ? 1u : 0u) - 1u : 63u;  // run inside the chunk
+    const uint64_t emask = (1ull << eb) - 1ull;
+    if constexpr (PACKED)
+        k = valid ? ((uint64_t)pi << 58) | ((k >> 32) << eb) | (k & emask) : ~0ull;
+    bitonic_sort<PACKED, 2>(lane, pi, k, pl);
+    if constexpr (PACKED) k = (((k >> eb) & 0xFFFFFFFFull) << 32) | (k & emask);
+    if (valid) {
+        col[pos] = pl;
+        key[pos] = k;
+        if (is_start) {
+            const uint32_t ri = r0 + below;
+            hcol[ri] = pl;
+            hkey[ri] = k;
+        }
+    }
+}
+
+// Phase A (see the top of the file).  Queued runs go to queue[*qn ...].
+__global__ __launch_bounds__(256) void k_heads(const uint32_t *__restrict__ run_row,
+                                               uint32_t *__restrict__ run_cur,
+                                               const uint32_t *__restrict__ run_end,
+                                               uint32_t *__restrict__ run_hcol,
+                                               uint64_t *__restrict__ run_hkey, uint32_t nruns,
+                                               const uint32_t *__restrict__ col,
+                                               const uint64_t *__restrict__ key,
+                                               const uint32_t *__restrict__ p,
+                                               uint64_t *__restrict__ r,
+                                               uint32_t *__restrict__ queue, uint32_t *qn,
+                                               int read_filter)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t hk = i < nruns ? run_hkey[i] : KEY_INF;
+    uint32_t root = NONE32;
+    uint64_t cand = KEY_INF;
+    bool push = false;
+    if (hk != KEY_INF) {
+        const uint32_t hc = run_hcol[i];
+        root = p[run_row[i]];
+        // with the read filter on, a run whose head is no smaller than the
+        // root's current minimum cannot lower it (its keys only grow and r
+        // only falls): it is passed over without a gather
+        if (read_filter && hk >= load_relaxed_u64(r + root)) {
+            root = NONE32;
+        } else if (p[hc] != root) {
+            cand = hk;
+        } else {
+            // the head is internal: probe the next entries together
+            const uint32_t cur = run_cur[i], end = run_end[i];
+            const uint32_t b = cur + 1u;
+            uint32_t cc[HEAD_PROBE], pc[HEAD_PROBE];
+#pragma unroll
+            for (int t = 0; t < HEAD_PROBE; ++t) {
+                const uint32_t q = b + (uint32_t)t < end ? b + (uint32_t)t : end - 1u;
+                cc[t] = col[q];
+            }
+#pragma unroll
+            for (int t = 0; t < HEAD_PROBE; ++t) pc[t] = p[cc[t]];
+            uint32_t f = (uint32_t)HEAD_PROBE, fc = 0;
+#pragma unroll
+            for (int t = HEAD_PROBE - 1; t >= 0; --t)
+                if (b + (uint32_t)t < end && pc[t] != root) {
+                    f = (uint32_t)t;
+                    fc = cc[t];
+                }
+            if (f < (uint32_t)HEAD_PROBE) {
+                const uint32_t nc = b + f;
+                cand = key[nc];
+                run_cur[i] = nc;
+                run_hcol[i] = fc;
+                run_hkey[i] = cand;
+            } else {
+                const uint32_t nc = b + (uint32_t)HEAD_PROBE < end ? b + (uint32_t)HEAD_PROBE : end;
+                run_cur[i] = nc;
+                push = nc < end;
+                if (!push) run_hkey[i] = KEY_INF;
+            }
+        }
+    }
+    const uint64_t bal = __ballot(push);
+    if (bal) {
+        uint32_t base = 0;
+        if (__lane_id() == 0) base = atomicAdd(qn, (uint32_t)__popcll(bal));
+        base = __shfl(base, 0);
+        if (push) queue[base + (uint32_t)__popcll(bal & lanemask_lt())] = i;
+    }
+    flush_by_root(r, root, cand, read_filter);
+}
+
+// Phase B: one wave per queued run (at most 64 - 1 - HEAD_PROBE entries
+// remain).  The grid is fixed; each wave strides over the queue and stops at
+// its length.  Also clears the other queue counter for the next round.
+__global__ __launch_bounds__(256) void k_heads_rest(
+    const uint32_t *__restrict__ queue, const uint32_t *qn, uint32_t *qn_next, uint32_t nruns,
+    const uint32_t *__restrict__ run_row, uint32_t *__restrict__ run_cur,
+    const uint32_t *__restrict__ run_end, uint32_t *__restrict__ run_hcol,
+    uint64_t *__restrict__ run_hkey, const uint32_t *__restrict__ col,
+    const uint64_t *__restrict__ key, const uint32_t *__restrict__ p, uint64_t *__restrict__ r)
+{
+    const uint32_t lane = __lane_id();
+    uint32_t n = load_relaxed_u32(qn);
+    n = n < nruns ? n : nruns;  // every run is queued at most once
+    if (blockIdx.x == 0 && threadIdx.x == 0) *qn_next = 0u;
+    const uint32_t nw = gridDim.x * (blockDim.x / 64u);
+    for (uint32_t w = blockIdx.x * (blockDim.x / 64u) + (threadIdx.x >> 6); w < n; w += nw) {
+        const uint32_t i = queue[w];
+        const uint32_t cur = run_cur[i], end = run_end[i];
+        const uint32_t root = p[run_row[i]];
+        const uint32_t q = cur + lane;
+        uint32_t c = 0;
+        bool ext = false;
+        if (q < end) {
+            c = col[q];
+            ext = p[c] != root;
+        }
+        const uint64_t b = __ballot(ext);
+        if (b) {
+            if (lane == (uint32_t)__ffsll((unsigned long long)b) - 1u) {
+                const uint64_t kq = key[q];
+                run_cur[i] = q;
+                run_hcol[i] = c;
+                run_hkey[i] = kq;
+                min_into(r, root, kq);
+            }
+        } else if (lane == 0) {
+            run_cur[i] = end;
+            run_hkey[i] = KEY_INF;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host --
+
+size_t heads_runs_cap(size_t nnz_cap, int32_t n)
+{
+    return (nnz_cap + 63) / 64 + (size_t)(n > 0 ? n : 0) + 1;
+}
+
+msf_status build_runs(Ctx *c, const Runs &R, const uint32_t *row_ptr, int32_t n, uint32_t *col,
+                      uint64_t *key, uint32_t nnz, int eb)
+{
+    hipStream_t s = c->stream;
+    const uint32_t nch = (nnz + 63u) / 64u;
+    if (nch == 0 || n <= 0) {
+        launch_fill_u32(s, &c->dcnt->nruns, 0u, 1);
+        return MSF_OK;
+    }
+    const unsigned gr = (unsigned)(((uint32_t)n + 255u) / 256u);
+    k_runs_count<<<gr, 256, 0, s>>>(row_ptr, n, R.rc);
+    MSF_TRY(scan_u32(c, R.rc, R.roff, (int64_t)n, &c->dcnt->nruns));
+    k_runs_write<<<gr, 256, 0, s>>>(row_ptr, n, R.roff, R.cur, R.end, R.row, R.cfirst);
+    const unsigned gs = (nch + 3u) / 4u;
+    const uint32_t *total = R.roff + n;  // the scan's total: the number of runs
+    if (eb <= 26)
+        k_sort_chunks<true><<<gs, 256, 0, s>>>(col, key, nnz, R.cfirst, total, R.cur, eb, R.hcol,
+                                               R.hkey);
+    else
+        k_sort_chunks<false><<<gs, 256, 0, s>>>(col, key, nnz, R.cfirst, total, R.cur, eb,
+                                                R.hcol, R.hkey);
+    MSF_HIP(hipGetLastError());
+    return MSF_OK;
+}
+
+// Blocks of the phase-B grid (4 waves each).
+constexpr uint32_t HEADS_REST_BLOCKS = 1024;
+
+void launch_heads(hipStream_t s, const Runs &R, uint32_t nruns, const uint32_t *col,
+                  const uint64_t *key, const uint32_t *p, uint64_t *r, Counters *dcnt, int parity,
+                  bool read_filter)
+{
+    if (nruns == 0) return;
+    uint32_t *qn = &dcnt->qn[parity & 1], *qn_next = &dcnt->qn[(parity & 1) ^ 1];
+    k_heads<<<(nruns + 255u) / 256u, 256, 0, s>>>(R.row, R.cur, R.end, R.hcol, R.hkey, nruns, col,
+                                                  key, p, r, R.queue, qn,
+                                                  (read_filter || HEADS_READ_FILTER) ? 1 : 0);
+    k_heads_rest<<<HEADS_REST_BLOCKS, 256, 0, s>>>(R.queue, qn, qn_next, nruns, R.row, R.cur,
+                                                   R.end, R.hcol, R.hkey, col, key, p, r);
+}
+
+}  // namespace msf

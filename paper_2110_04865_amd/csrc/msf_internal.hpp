@@ -97,6 +97,7 @@ enum Slot {
     WS_BATCH0, WS_BATCH1, WS_BATCH2, WS_BATCH3,
     WS_BH, WS_BHOFF, WS_BRLO, WS_BCOL, WS_BKEY, WS_CHUNKINFO,
     WS_TL1, WS_TL2, WS_TLSUB, WS_TLORDER, WS_TLPLAN, WS_T2, WS_T2OFF, WS_FSTART,
+    WS_RUNCHUNK, WS_RUNROW, WS_RUNS,
     WS_COUNT
 };
 
@@ -119,6 +120,22 @@ struct Counters {
     uint32_t rows;        // rows with stored entries (counted by update)
     uint32_t segs;        // non-empty (row, slice) segments of an adjacency
     uint32_t sstart[MAX_SLICES + 1];  // slice boundaries of an adjacency
+    uint32_t nruns;       // key-sorted runs of the adjacency (head sweep)
+    uint32_t qn[2];       // head sweep queue lengths (alternating rounds)
+};
+
+// Key-sorted runs for the head sweep: every 64-entry chunk of the
+// adjacency sorted by (row, key); a run is one row's part of one chunk.
+struct Runs {
+    uint32_t *cfirst = nullptr;  // per chunk: index of its first run
+    uint32_t *rc = nullptr;      // per row: runs
+    uint32_t *roff = nullptr;    // per row: exclusive prefix of rc (n + 1 entries)
+    uint32_t *cur = nullptr;     // per run: its head (first entry not known internal)
+    uint32_t *end = nullptr;     // per run: one past its last entry
+    uint32_t *row = nullptr;     // per run: its row
+    uint32_t *hcol = nullptr;    // per run: column of the head
+    uint64_t *hkey = nullptr;    // per run: key of the head (UINT64_MAX: run exhausted)
+    uint32_t *queue = nullptr;   // runs left to phase B of a sweep
 };
 
 struct SolveBufs {
@@ -177,6 +194,9 @@ struct SolveState {
     uint32_t nR = 0, rows = 0;
     bool rows_pending = false, compact = false;
     bool first_done = false;  // the build wrote round 1's minima into r
+    bool heads = false;       // rounds use the head sweep over key-sorted runs
+    Runs runs;
+    uint32_t nruns = 0;
     int ri = 0, ai = 0, rounds = 0;
     double live_frac = 1.0;
     msf_stats st{};
@@ -202,6 +222,10 @@ struct Ctx {
     // applies (one slice), 2 one-level bucketed
     int bucketed_build = 1;
     int slices = 0;                  // column slices: 0 automatic, else forced (1..8)
+    // rounds after the first on one-slice adjacencies: head sweep over
+    // key-sorted runs (1 from a size on, 2 always) or full sweep with the
+    // filtering policy (0)
+    int heads = 1;
     SolveState ss;
 };
 
@@ -314,6 +338,19 @@ int64_t output_tiles(int64_t m);
 size_t output_part_bytes(int64_t m);
 // bytes `part` needs for launch_chase
 size_t chase_part_bytes();
+
+// Head sweep (kernels_heads.hip).  heads_runs_cap: runs of an adjacency of
+// at most nnz_cap entries over n rows.  build_runs derives the runs of a
+// one-slice adjacency from row_ptr, sorts every chunk of col/key in place
+// and fills the run arrays (keys' edge ids take eb bits); the run count
+// lands in dcnt->nruns.  launch_heads runs one sweep (queue counter
+// dcnt->qn[parity], clearing the other one).
+size_t heads_runs_cap(size_t nnz_cap, int32_t n);
+msf_status build_runs(Ctx *c, const Runs &R, const uint32_t *row_ptr, int32_t n, uint32_t *col,
+                      uint64_t *key, uint32_t nnz, int eb);
+void launch_heads(hipStream_t s, const Runs &R, uint32_t nruns, const uint32_t *col,
+                  const uint64_t *key, const uint32_t *p, uint64_t *r, Counters *dcnt, int parity,
+                  bool read_filter);
 msf_status launch_output(Ctx *c, const uint8_t *in_forest, int64_t m, const void *w,
                          msf_wtype wt, int32_t *ids, void *part);
 

@@ -226,6 +226,8 @@ ReqSlot *take_slot(msf_server *s, size_t need)
     // one, so more requests fit the budget at once; an explicit
     // MSF_BUCKETED_BUILD still wins
     if (!getenv("MSF_BUCKETED_BUILD") && sl->ctx.bucketed_build == 1) sl->ctx.bucketed_build = 2;
+    // requests are budgeted without the head sweep's run arrays
+    if (!getenv("MSF_HEADS")) sl->ctx.heads = 0;
     return sl;
 }
 

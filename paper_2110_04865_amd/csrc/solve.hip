@@ -92,6 +92,34 @@ static msf_status get_filter_bufs(Ctx *c, int32_t n, int64_t m, int S, SolveBufs
     return MSF_OK;
 }
 
+// Buffers of the head sweep: per-chunk first runs,
+// per-row run counts and offsets, run descriptors and the phase-B queue.
+static msf_status get_runs_bufs(Ctx *c, int32_t n, int64_t m, Runs *R)
+{
+    const size_t mm = (size_t)std::max<int64_t>(m, 1), nn = (size_t)std::max(n, 1);
+    const size_t nnz_cap = 2 * mm;
+    const size_t nch = (nnz_cap + 63) / 64 + 1;
+    const size_t rc = heads_runs_cap(nnz_cap, n);
+    void *v[3];
+    MSF_TRY(ws_get(c, WS_RUNCHUNK, 4 * nch + 8, &v[0]));
+    MSF_TRY(ws_get(c, WS_RUNROW, 4 * nn + 4 * (nn + 1), &v[1]));  // roff: nn + 1 (scan total)
+    MSF_TRY(ws_get(c, WS_RUNS, 28 * rc + 8, &v[2]));
+    R->cfirst = (uint32_t *)v[0];
+    R->rc = (uint32_t *)v[1];
+    R->roff = R->rc + nn;
+    R->hkey = (uint64_t *)v[2];
+    R->cur = (uint32_t *)(R->hkey + rc);
+    R->end = R->cur + rc;
+    R->row = R->end + rc;
+    R->hcol = R->row + rc;
+    R->queue = R->hcol + rc;
+    return MSF_OK;
+}
+
+// Stored entries from which the head sweep is used by default: below, the
+// run set-up (five launches) costs more than it saves.
+constexpr int64_t HEADS_MIN_NNZ = (int64_t)1 << 20;
+
 // End a step: counters to pinned host memory, then the step event.
 static msf_status end_step(Ctx *c, int next_phase)
 {
@@ -115,11 +143,17 @@ msf_status solve_start(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, con
     S.ids = d_ids;
     const int slices = choose_slices(n, m, c->slices);
     MSF_TRY(get_solve_bufs(c, n, m, slices, &S.b));
+    // head sweep: 1 from HEADS_MIN_NNZ stored entries on, 2 always
+    S.heads = slices == 1 && m > 0 && n > 0 &&
+              (c->heads == 2 || (c->heads == 1 && 2 * m >= HEADS_MIN_NNZ));
+    if (S.heads) MSF_TRY(get_runs_bufs(c, n, m, &S.runs));
     MSF_HIP(hipEventRecord(c->ev[0], c->stream));
     zero_counters(c);
     MSF_TRY(build_adjacency(c, n, m, d_edges, d_w, wt, slices, &S.a, S.b.rp[0], S.b.col[0],
                             S.b.key[0], S.b.crow[0], c->first_round == 2 ? S.b.r : nullptr,
                             &S.first_done));
+    // the build may have fallen back to another slice count
+    if (S.a.sl.S != 1) S.heads = false;
     return end_step(c, 1);
 }
 
@@ -137,12 +171,13 @@ static msf_status enqueue_round(Ctx *c)
     SolveState &S = c->ss;
     hipStream_t s = c->stream;
     S.compact = false;
-    if (c->filter_mode == 2) S.compact = true;
+    if (S.heads) S.compact = false;  // the head sweep passes internal entries over by itself
+    else if (c->filter_mode == 2) S.compact = true;
     else if (c->filter_mode == 1) S.compact = S.live_frac < c->filter_threshold;
     const int ev_k = S.rounds < 64 ? S.rounds : -1;
     if (ev_k >= 0) {
         MSF_HIP(hipEventRecord(c->sev[2 * ev_k], s));
-        S.st.sweep_bytes[ev_k] = (S.rounds == 0 && S.first_done)
+        S.st.sweep_bytes[ev_k] = (S.rounds == 0 && S.first_done) || S.heads
                                      ? 0.0
                                      : 12.0 * S.a.nnz + 8.0 * S.a.segs + 8.0 * S.nR;
     }
@@ -160,6 +195,10 @@ static msf_status enqueue_round(Ctx *c)
     } else if (S.rounds == 0 && S.first_done) {
         // round 1's minima were written by the build; every entry is live
         launch_fill_u64(s, &c->dcnt->live, (uint64_t)S.a.nnz, 1);
+    } else if (S.heads) {
+        ++S.st.head_sweeps;
+        launch_heads(s, S.runs, S.nruns, S.a.col, S.a.key, S.b.p, S.b.r, c->dcnt, S.rounds,
+                     read_filter);
     } else {
         // round 1: p is the identity and nothing has been filtered
         launch_sweep(s, S.a, S.b.p, S.b.r, c->dcnt, S.rounds == 0 && c->first_round >= 1,
@@ -198,6 +237,11 @@ msf_status solve_advance(Ctx *c)
         for (int q = 0; q <= S.a.sl.S; ++q) S.a.sl.sstart[q] = h->sstart[q];
         set_chunks(&S.a);
         S.a.segs = h->segs;
+        if (S.heads) {
+            int eb = 1;
+            while (eb < 64 && ((uint64_t)(S.m > 1 ? S.m - 1 : 1) >> eb)) ++eb;
+            MSF_TRY(build_runs(c, S.runs, S.a.row_ptr, S.n, S.a.col, S.a.key, S.a.nnz, eb));
+        }
         if (S.a.nnz) launch_chunk_rows_sliced(s, S.a);
         MSF_HIP(hipEventRecord(c->ev[1], s));
         launch_iota_u32(s, S.b.p, (size_t)S.n);
@@ -209,6 +253,8 @@ msf_status solve_advance(Ctx *c)
     }
     case 2: {  // root list ready
         S.nR = h->nR;
+        S.nruns = h->nruns;
+        S.st.runs = S.heads ? (int64_t)S.nruns : 0;
         return more_rounds(S) ? enqueue_round(c) : enqueue_output(c);
     }
     case 3: {  // round counters ready

@@ -205,9 +205,13 @@ def test_rounds_match_algorithm2_oracle(ctx, pkg):
 
 
 def test_filter_policies_are_result_invariant(pkg):
+    """The filtering policies belong to the full sweep (the head sweep passes
+    internal entries over by itself), so the head sweep is off here."""
     n, e, w = gen.grid(24, 24, 24, 0.05, seed=3)
     n2, e2, w2 = gen.rmat(13, 16, seed=2)
     old = os.environ.get("MSF_FILTER")
+    old_heads = os.environ.get("MSF_HEADS")
+    os.environ["MSF_HEADS"] = "0"
     try:
         for mode in ("0", "1", "2"):
             os.environ["MSF_FILTER"] = mode
@@ -222,6 +226,64 @@ def test_filter_policies_are_result_invariant(pkg):
             os.environ.pop("MSF_FILTER", None)
         else:
             os.environ["MSF_FILTER"] = old
+        if old_heads is None:
+            os.environ.pop("MSF_HEADS", None)
+        else:
+            os.environ["MSF_HEADS"] = old_heads
+
+
+def test_head_sweep_matches_oracle_and_full_sweep(pkg):
+    """Rounds after the first sweep key-sorted runs and pass internal
+    entries over (head sweep; MSF_HEADS=2 forces it at any size) or sweep
+    every entry (MSF_HEADS=0):
+    both give the oracle's forest and the oracle's hook count in every round
+    (so every round's minima agree).  Cases: a grid (entries turn internal
+    round by round, so long internal stretches reach the per-run second
+    phase), skewed R-MAT (rows of thousands of entries split into many runs),
+    equal weights (order by edge id), a multigraph with loops and repeated
+    pairs, more vertices than edges, a path (one run per row, many rounds),
+    and entry counts off the 64-entry chunk grid."""
+    rng = np.random.default_rng(41)
+    nm = 2000
+    multi_e = rng.integers(0, nm, size=(15000, 2)).astype(np.int32)
+    multi_w = rng.integers(0, 20, size=15000).astype(np.uint32)
+    npath = 3001
+    path_e = np.stack([np.arange(npath - 1), np.arange(1, npath)], 1).astype(np.int32)
+    path_w = rng.permutation(npath - 1).astype(np.uint32)
+    eq_e, _ = gen.er(3000, 20000, seed=43)
+    eq_w = np.full(len(eq_e), 7, dtype=np.uint32)
+    graphs = [
+        ("grid20", *gen.grid(20, 20, 20, 0.05, seed=42), U32),
+        ("rmat15", *gen.rmat(15, 16, seed=44), F32),
+        ("equal weights", 3000, eq_e, eq_w, U32),
+        ("multi", nm, multi_e, multi_w, U32),
+        ("sparse", 40000, *gen.er(40000, 15000, seed=45), U32),
+        ("path", npath, path_e, path_w, U32),
+        ("ragged 37", 40, *gen.er(40, 37, seed=46), U32),
+        ("ragged 1000", 300, *gen.er(300, 1000, seed=47, wtype=F32), F32),
+    ]
+    old = os.environ.get("MSF_HEADS")
+    try:
+        for heads in ("2", "0"):
+            os.environ["MSF_HEADS"] = heads
+            c = pkg.Context(0)
+            for label, n, e, w, wt in graphs:
+                st = check_solve(c, pkg, n, e, w, wt, f"heads={heads} {label}")
+                ref = oracle.as_rounds(n, e, w, wt)
+                hooks = [h for h in ref["hooks"] if h]
+                assert st["hooks"][:len(hooks)] == hooks, (label, st["hooks"], hooks)
+                if heads == "2":
+                    assert st["runs"] > 0, label
+                    assert st["head_sweeps"] in (st["rounds"], max(st["rounds"] - 1, 0)), \
+                        (label, st["rounds"], st["head_sweeps"])
+                else:
+                    assert st["runs"] == 0 and st["head_sweeps"] == 0, label
+            c.close()
+    finally:
+        if old is None:
+            os.environ.pop("MSF_HEADS", None)
+        else:
+            os.environ["MSF_HEADS"] = old
 
 
 # ---------------------------------------------------------- multilinear --
