@@ -8,13 +8,15 @@ device-resident COO edges to device-resident forest ids (adjacency build,
 every round, output compaction and the exact total).
 
 Also reported on the same JSON line:
-  roofline      the multilinear sweep kernel (the dominant kernel): its
-                algorithmic bytes per launch over its average launch time,
-                both taken inside the timed steps from device events that the
-                library records on the stream the sweeps run on; `traffic` is
-                the counter-measured bytes per launch from the committed
-                profile, reported only when the sweep sources built here are
-                the ones that profile was taken on (else null);
+  roofline      the dominant kernel (most device time per step among the
+                build's placement, the run sort, the full sweep and the head
+                sweep): its algorithmic bytes per launch over its average
+                launch time, both taken inside the timed steps from device
+                events that the library records on the stream those kernels
+                run on; `traffic` is the counter-measured bytes per launch
+                from the committed profile, reported only when the sources
+                built here are the ones that profile was taken on (else
+                null);
   cpu_baseline  the CPU oracle (sort + union-find, one thread) on the same
                 graph, timed on this host;
   batched       10^4 uneven Erdos-Renyi graphs (n log-uniform in [64, 65536),
@@ -38,38 +40,49 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
-SWEEP_SOURCES = ("kernels_sweep.hip", "msf_internal.hpp", "wave.hpp")
 PROFILE = os.path.join(ROOT, "profiles", "rmat_s22_solve.md")
+# timed kernels: label -> (kernel name, sources its code comes from)
+KERNELS = {
+    "place": ("k_tl_place (two-level build, placement)",
+              ("kernels_build2.hip", "msf_internal.hpp", "wave.hpp")),
+    "sort": ("k_sort_chunks (run sort of the head sweep)",
+             ("kernels_heads.hip", "msf_internal.hpp", "wave.hpp")),
+    "sweep": ("k_sweep (multilinear + projection)",
+              ("kernels_sweep.hip", "msf_internal.hpp", "wave.hpp")),
+    "heads": ("k_heads + k_heads_rest (head sweep)",
+              ("kernels_heads.hip", "msf_internal.hpp", "wave.hpp")),
+}
 
 
-def sweep_source_hash():
+def source_hash(label):
     import hashlib
 
     h = hashlib.sha256()
-    for f in SWEEP_SOURCES:
+    for f in KERNELS[label][1]:
         with open(os.path.join(ROOT, "paper_2110_04865_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per sweep launch from the committed counter profile
-    (calibrated FETCH_SIZE + WRITE_SIZE), or None when the profile was taken
-    on different sweep sources than the ones built here."""
+def measured_traffic(label):
+    """HBM bytes per launch of the kernel `label` from the committed counter
+    profile (calibrated FETCH_SIZE + WRITE_SIZE), or None when the profile
+    holds none or was taken on different sources than the ones built here."""
     try:
         with open(PROFILE) as fh:
             lines = fh.read().splitlines()
     except OSError:
         return None
+    keys = (f"{label}_traffic_bytes:", f"{label}_source_sha256:")
     vals = {}
     for ln in lines:
-        for k in ("sweep_traffic_bytes:", "sweep_source_sha256:"):
+        for k in keys:
             if ln.strip().startswith(k):
                 vals[k] = ln.strip()[len(k):].strip().strip("`")
-    if vals.get("sweep_source_sha256:") != sweep_source_hash():
+    if vals.get(keys[1]) != source_hash(label):
         return None
     try:
-        return float(vals["sweep_traffic_bytes:"])
+        return float(vals[keys[0]])
     except (KeyError, ValueError):
         return None
 
@@ -93,18 +106,30 @@ def bench_rmat(ctx, pkg, torch, steps, warmup):
         ctx.solve(n, de, dw, wtype=pkg.W_F32, out=out)
         log(f"warmup {i + 1}/{warmup} done")
     torch.cuda.synchronize()
-    sweep_ms = sweep_bytes = 0.0
-    sweeps = 0
+    # per timed kernel: [device ms, algorithmic bytes, launches] over the steps
+    kt = {k: [0.0, 0.0, 0] for k in KERNELS}
     build_ms = rounds_ms = 0.0
     t0 = time.perf_counter()
     for k in range(steps):
         ids, cnt, tot = ctx.solve(n, de, dw, wtype=pkg.W_F32, out=out)
         st = ctx.stats()
-        for t_ms, b in zip(st["sweep_ms"], st["sweep_bytes"]):
+        first = st["rounds"] - st["head_sweeps"]  # rounds before the head sweep takes over
+        for i, (t_ms, b) in enumerate(zip(st["sweep_ms"], st["sweep_bytes"])):
             if b > 0:  # round 1's minima come from the build: no sweep launch
-                sweep_ms += t_ms
-                sweep_bytes += b
-                sweeps += 1
+                kt["sweep"][0] += t_ms
+                kt["sweep"][1] += b
+                kt["sweep"][2] += 1
+            elif st["head_sweeps"] and i >= first:
+                # descriptors: head key, column and row (16), p of the row and
+                # of the head column (8) per run
+                kt["heads"][0] += t_ms
+                kt["heads"][1] += 24.0 * st["runs"]
+                kt["heads"][2] += 1
+        for lab in ("place", "sort"):
+            if st[f"{lab}_ms"] > 0:
+                kt[lab][0] += st[f"{lab}_ms"]
+                kt[lab][1] += st[f"{lab}_bytes"]
+                kt[lab][2] += 1
         build_ms += st["build_ms"]
         rounds_ms += st["rounds_ms"]
     torch.cuda.synchronize()
@@ -113,8 +138,7 @@ def bench_rmat(ctx, pkg, torch, steps, warmup):
     ms = (t1 - t0) * 1000.0 / steps
     res = dict(n=n, m=m, e=e, w=w, ms=ms, count=cnt, total=tot, stats=st,
                ids_sum=int(ids.to(torch.int64).sum().item()),
-               sweep_ms=sweep_ms, sweep_bytes=sweep_bytes, sweeps=sweeps,
-               build_ms=build_ms / steps, rounds_ms=rounds_ms / steps)
+               kernels=kt, build_ms=build_ms / steps, rounds_ms=rounds_ms / steps)
     return res
 
 
@@ -294,8 +318,10 @@ def main():
     r = bench_rmat(ctx, pkg, torch, args.steps, args.warmup)
     m = r["m"]
     value = m / (r["ms"] / 1000.0)
-    avg_sweep_ms = r["sweep_ms"] / max(1, r["sweeps"])
-    achieved = (r["sweep_bytes"] / 1e9) / (r["sweep_ms"] / 1e3) if r["sweep_ms"] > 0 else 0.0
+    kt = r["kernels"]
+    dom = max(kt, key=lambda k: kt[k][0])
+    d_ms, d_bytes, d_n = kt[dom]
+    achieved = (d_bytes / 1e9) / (d_ms / 1e3) if d_ms > 0 else 0.0
     line = {
         "metric": "MSF edges/s at R-MAT s22 (% HBM peak); batched graphs/s vs plain; p99 latency",
         "value": value,
@@ -313,12 +339,13 @@ def main():
                                "permuted ids, simple graph, float32 weights",
                    "n": r["n"], "m": m, "nnz": 2 * m, "rounds": r["stats"]["rounds"],
                    "build_ms": r["build_ms"], "rounds_ms": r["rounds_ms"]},
-        "roofline": {"bound": "hbm", "kernel": "k_sweep (multilinear + projection)",
+        "roofline": {"bound": "hbm", "kernel": KERNELS[dom][0],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "avg_launch_ms": avg_sweep_ms,
-                     "bytes_per_launch": r["sweep_bytes"] / max(1, r["sweeps"]),
-                     "launches": r["sweeps"]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+                     "avg_launch_ms": d_ms / max(1, d_n),
+                     "bytes_per_launch": d_bytes / max(1, d_n),
+                     "launches": d_n,
+                     "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()}},
     }
     if not args.no_cpu:
         log("timing the CPU oracle on the same graph")

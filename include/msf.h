@@ -98,6 +98,17 @@ typedef struct {
                                 only; their sweep_bytes are 0)               */
     int32_t reserved;
     int64_t runs;            /* key-sorted runs of the adjacency (0: none)   */
+    double place_ms;         /* two-level build's placement kernel (device
+                                events; 0 when that build was not used)      */
+    double place_bytes;      /* its algorithmic bytes: per stored entry the
+                                level-2 record read + column and key written;
+                                per vertex its row pointer (+ round 1's
+                                minimum when the build keeps it)             */
+    double sort_ms;          /* run sort of the head sweep (device events)   */
+    double sort_bytes;       /* its algorithmic bytes: 24 per stored entry
+                                (column + key read and written), 16 per run
+                                (start read, head column + key written), 4
+                                per 64-entry chunk (its first run)           */
 } msf_stats;
 
 typedef struct msf_ctx msf_ctx;

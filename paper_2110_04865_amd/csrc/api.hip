@@ -132,6 +132,11 @@ msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc)
             set_error("event creation failed");
             return MSF_EDEVICE;
         }
+    for (auto &ev : c->kev)
+        if (hipEventCreate(&ev) != hipSuccess) {
+            set_error("event creation failed");
+            return MSF_EDEVICE;
+        }
     if (const char *f = getenv("MSF_FILTER")) c->filter_mode = atoi(f);
     if (const char *f = getenv("MSF_FILTER_THRESHOLD")) c->filter_threshold = atof(f);
     if (const char *f = getenv("MSF_CHECK_ROUNDS")) c->check_rounds = atoi(f) != 0;
@@ -162,6 +167,8 @@ void ctx_release(Ctx *c)
     for (auto &ev : c->ev)
         if (ev) (void)hipEventDestroy(ev), ev = nullptr;
     for (auto &ev : c->sev)
+        if (ev) (void)hipEventDestroy(ev), ev = nullptr;
+    for (auto &ev : c->kev)
         if (ev) (void)hipEventDestroy(ev), ev = nullptr;
     if (c->dcnt) (void)hipFree(c->dcnt), c->dcnt = nullptr;
     if (c->hcnt) (void)hipHostFree(c->hcnt), c->hcnt = nullptr;

@@ -681,12 +681,15 @@ msf_status two_level_passes(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges
     k_tl_order<<<otiles, TO_NT, 0, s>>>(B.fst, nf, (uint32_t)TC_CAP, B.order, B.ostat,
                                        &c->dcnt->ticket);
     const size_t RC = ((size_t)1 << tl.L2) * tc_copies(tl.L2);
+    MSF_HIP(hipEventRecord(c->kev[0], s));
     if (r_first)
         k_tl_place<true, PK2><<<nf, TC_NT, 12 * RC, s>>>(e2, n, tl.L2, cb, B.fst, B.order, row_ptr,
                                                          col, key, r_first);
     else
         k_tl_place<false, PK2><<<nf, TC_NT, 4 * RC, s>>>(e2, n, tl.L2, cb, B.fst, B.order, row_ptr,
                                                           col, key, nullptr);
+    MSF_HIP(hipEventRecord(c->kev[1], s));
+    c->place_rec = PK2 ? 12 : 16;
     MSF_HIP(hipGetLastError());
     return MSF_OK;
 }

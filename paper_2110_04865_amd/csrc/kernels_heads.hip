@@ -376,12 +376,15 @@ msf_status build_runs(Ctx *c, const Runs &R, const uint32_t *row_ptr, int32_t n,
     k_runs_write<<<gr, 256, 0, s>>>(row_ptr, n, R.roff, R.cur, R.end, R.row, R.cfirst);
     const unsigned gs = (nch + 3u) / 4u;
     const uint32_t *total = R.roff + n;  // the scan's total: the number of runs
+    MSF_HIP(hipEventRecord(c->kev[2], s));
     if (eb <= 26)
         k_sort_chunks<true><<<gs, 256, 0, s>>>(col, key, nnz, R.cfirst, total, R.cur, eb, R.hcol,
                                                R.hkey);
     else
         k_sort_chunks<false><<<gs, 256, 0, s>>>(col, key, nnz, R.cfirst, total, R.cur, eb,
                                                 R.hcol, R.hkey);
+    MSF_HIP(hipEventRecord(c->kev[3], s));
+    c->sort_timed = true;
     MSF_HIP(hipGetLastError());
     return MSF_OK;
 }
