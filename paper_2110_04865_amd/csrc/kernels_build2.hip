@@ -168,18 +168,6 @@ __device__ __forceinline__ RecT<PK> rec_pack(const uint4 &x, uint32_t rb, uint32
     }
 }
 
-// The row of record i alone (one 4-byte load): packed, its low rb bits are
-// the low bits of the second word.
-template <bool PK>
-__device__ __forceinline__ uint32_t rec_row(const RecT<PK> *a, uint64_t i, uint32_t rowhi,
-                                            uint32_t rb)
-{
-    if constexpr (PK)
-        return rowhi | (reinterpret_cast<const uint32_t *>(a)[3 * i + 1] & ((1u << rb) - 1u));
-    else
-        return a[i].x;
-}
-
 // rowhi: the bucket's first row (its low rb bits are zero)
 template <bool PK>
 __device__ __forceinline__ uint4 rec_unpack(const RecT<PK> &p, uint32_t rowhi, uint32_t rb,
@@ -362,7 +350,8 @@ template <bool PK1, bool PK2>
 __global__ __launch_bounds__(TL_NT) void k_part_sub(
     const RecT<PK1> *__restrict__ e1, int L2, int nsub, int NC, const uint32_t *__restrict__ cs,
     const uint32_t *__restrict__ nb2, const uint32_t *__restrict__ P,
-    const uint32_t *__restrict__ o2, uint32_t cb, RecT<PK2> *__restrict__ e2)
+    const uint32_t *__restrict__ o2, uint32_t cb, RecT<PK2> *__restrict__ e2,
+    uint16_t *__restrict__ sub2)
 {
     __shared__ uint4 s_ent[TL_TILE];
     __shared__ uint32_t s_run[TL_MAX_NSUB], s_pos[TL_MAX_NSUB * TP_C];  // s_pos: [fine][copy]
@@ -404,7 +393,9 @@ __global__ __launch_bounds__(TL_NT) void k_part_sub(
         for (uint32_t i = threadIdx.x; i < cnt; i += TL_NT) {
             const uint4 x = s_ent[i];
             const uint32_t s = (x.x >> L2) & mask;
-            e2[s_run[s] + (i - s_pos[s * TP_C])] = rec_pack<PK2>(x, (uint32_t)L2, cb);
+            const uint32_t q = s_run[s] + (i - s_pos[s * TP_C]);
+            e2[q] = rec_pack<PK2>(x, (uint32_t)L2, cb);
+            sub2[q] = (uint16_t)(x.x & ((1u << L2) - 1u));  // row inside the fine bucket
         }
         __syncthreads();
         for (int s = threadIdx.x; s < nsub; s += TL_NT) {
@@ -483,7 +474,8 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
     const RecT<PK2> *__restrict__ e2, int32_t n, int L2, uint32_t cb,
     const uint32_t *__restrict__ fstart,
     const uint32_t *__restrict__ order, uint32_t *__restrict__ row_ptr,
-    uint32_t *__restrict__ col, uint64_t *__restrict__ key, uint64_t *__restrict__ r)
+    uint32_t *__restrict__ col, uint64_t *__restrict__ key, uint64_t *__restrict__ r,
+    const uint16_t *__restrict__ sub2)
 {
     extern __shared__ uint64_t tc_lds[];
     const uint32_t R = 1u << L2;
@@ -543,8 +535,7 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k) {
                 const uint64_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
-                rl[k] = i < fe ? rec_row<PK2>(e2, i, (uint32_t)row0, (uint32_t)L2) - (uint32_t)row0
-                               : NONE32;
+                rl[k] = i < fe ? (uint32_t)sub2[i] : NONE32;
             }
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k)
@@ -672,8 +663,11 @@ msf_status two_level_passes(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges
     launch_fill_u32(s, B.t2, 0u, nt2);
     k_tl_hist2<<<(unsigned)g2max, 256, 0, s>>>(B.sub1, tl.nsub, NC, B.cs, B.nb2, B.P, B.t2);
     MSF_TRY(scan_u32(c, B.t2, B.o2, (int64_t)nt2, nullptr));
+    // the level-1 bytes are dead once the fine histogram has read them:
+    // their buffer takes each level-2 entry's row inside its fine bucket
+    uint16_t *sub2 = reinterpret_cast<uint16_t *>(B.sub1);
     k_part_sub<PK1, PK2><<<(unsigned)g2max, TL_NT, 0, s>>>(e1, tl.L2, tl.nsub, NC, B.cs, B.nb2,
-                                                           B.P, B.o2, cb, e2);
+                                                           B.P, B.o2, cb, e2, sub2);
     // C
     const unsigned nf = (unsigned)NC * (unsigned)tl.nsub;
     k_tl_fstart<<<(nf + 256) / 256, 256, 0, s>>>(B.o2, B.nb2, B.P, tl.nsub, NC, B.fst);
@@ -684,10 +678,10 @@ msf_status two_level_passes(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges
     MSF_HIP(hipEventRecord(c->kev[0], s));
     if (r_first)
         k_tl_place<true, PK2><<<nf, TC_NT, 12 * RC, s>>>(e2, n, tl.L2, cb, B.fst, B.order, row_ptr,
-                                                         col, key, r_first);
+                                                         col, key, r_first, sub2);
     else
         k_tl_place<false, PK2><<<nf, TC_NT, 4 * RC, s>>>(e2, n, tl.L2, cb, B.fst, B.order, row_ptr,
-                                                          col, key, nullptr);
+                                                          col, key, nullptr, sub2);
     MSF_HIP(hipEventRecord(c->kev[1], s));
     c->place_rec = PK2 ? 12 : 16;
     MSF_HIP(hipGetLastError());
@@ -720,7 +714,7 @@ msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
     MSF_TRY(ws_get(c, WS_BHOFF, 4 * (nh + 1), &vbo));
     MSF_TRY(ws_get(c, WS_TL1, (pk1 ? 12 : 16) * cap, &ve1));
     MSF_TRY(ws_get(c, WS_TL2, (pk2 ? 12 : 16) * cap, &ve2));
-    MSF_TRY(ws_get(c, WS_TLSUB, cap + 4, &vsub));
+    MSF_TRY(ws_get(c, WS_TLSUB, 2 * cap + 8, &vsub));  // level-1 u8, then level-2 u16
     MSF_TRY(ws_get(c, WS_TLPLAN, 4 * (3 * (size_t)NC + 3), &vplan));
     MSF_TRY(ws_get(c, WS_T2, 4 * nt2, &vt2));
     MSF_TRY(ws_get(c, WS_T2OFF, 4 * (nt2 + 1), &vo2));
