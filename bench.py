@@ -9,8 +9,9 @@ every round, output compaction and the exact total).
 
 Also reported on the same JSON line:
   roofline      the dominant kernel (most device time per step among the
-                build's placement, the run sort, the full sweep and the head
-                sweep): its algorithmic bytes per launch over its average
+                build's placement, the run sort, the full sweep, the head
+                sweep, the level-1 and level-2 partitions): its algorithmic
+                bytes per launch over its average
                 launch time, both taken inside the timed steps from device
                 events that the library records on the stream those kernels
                 run on; `traffic` is the counter-measured bytes per launch
@@ -47,6 +48,10 @@ KERNELS = {
               ("kernels_build2.hip", "msf_internal.hpp", "wave.hpp")),
     "sort": ("k_sort_chunks (run sort of the head sweep)",
              ("kernels_heads.hip", "msf_internal.hpp", "wave.hpp")),
+    "part2": ("k_part_sub (two-level build, level-2 partition)",
+              ("kernels_build2.hip", "msf_internal.hpp", "wave.hpp")),
+    "part1": ("k_part_edges (two-level build, level-1 partition)",
+              ("kernels_build2.hip", "msf_internal.hpp", "wave.hpp")),
     "sweep": ("k_sweep (multilinear + projection)",
               ("kernels_sweep.hip", "msf_internal.hpp", "wave.hpp")),
     "heads": ("k_heads + k_heads_rest (head sweep)",
@@ -125,10 +130,10 @@ def bench_rmat(ctx, pkg, torch, steps, warmup):
                 kt["heads"][0] += t_ms
                 kt["heads"][1] += 24.0 * st["runs"]
                 kt["heads"][2] += 1
-        for lab in ("place", "sort"):
-            if st[f"{lab}_ms"] > 0:
-                kt[lab][0] += st[f"{lab}_ms"]
-                kt[lab][1] += st[f"{lab}_bytes"]
+        for q, lab in enumerate(("place", "sort", "part2", "part1")):
+            if st["pass_ms"][q] > 0:
+                kt[lab][0] += st["pass_ms"][q]
+                kt[lab][1] += st["pass_bytes"][q]
                 kt[lab][2] += 1
         build_ms += st["build_ms"]
         rounds_ms += st["rounds_ms"]

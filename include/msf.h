@@ -98,17 +98,18 @@ typedef struct {
                                 only; their sweep_bytes are 0)               */
     int32_t reserved;
     int64_t runs;            /* key-sorted runs of the adjacency (0: none)   */
-    double place_ms;         /* two-level build's placement kernel (device
-                                events; 0 when that build was not used)      */
-    double place_bytes;      /* its algorithmic bytes: per stored entry the
-                                level-2 record read + column and key written;
-                                per vertex its row pointer (+ round 1's
-                                minimum when the build keeps it)             */
-    double sort_ms;          /* run sort of the head sweep (device events)   */
-    double sort_bytes;       /* its algorithmic bytes: 24 per stored entry
-                                (column + key read and written), 16 per run
-                                (start read, head column + key written), 4
-                                per 64-entry chunk (its first run)           */
+    /* Device time (events) and algorithmic bytes of one-launch passes, 0
+       when not run.  Index 0: placement of the two-level build (per stored
+       entry its level-2 record read, column and key written; per vertex its
+       row pointer, + round 1's minimum when the build keeps it).  1: run
+       sort of the head sweep (24 per stored entry: column and key read and
+       written; 16 per run: start read, head written; 4 per 64-entry
+       chunk).  2: level-2 partition (per stored entry its level-1 record
+       read, level-2 record and 2-byte row written).  3: level-1 partition
+       (12 per edge read: endpoints and weight; per stored entry its level-1
+       record and 1-byte fine bucket written). */
+    double pass_ms[4];
+    double pass_bytes[4];
 } msf_stats;
 
 typedef struct msf_ctx msf_ctx;

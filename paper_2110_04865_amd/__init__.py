@@ -54,9 +54,8 @@ class Stats(ctypes.Structure):
                 ("build_ms", ctypes.c_double), ("rounds_ms", ctypes.c_double),
                 ("sweep_ms", ctypes.c_double * 64), ("sweep_bytes", ctypes.c_double * 64),
                 ("head_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("runs", ctypes.c_int64), ("place_ms", ctypes.c_double),
-                ("place_bytes", ctypes.c_double), ("sort_ms", ctypes.c_double),
-                ("sort_bytes", ctypes.c_double)]
+                ("runs", ctypes.c_int64), ("pass_ms", ctypes.c_double * 4),
+                ("pass_bytes", ctypes.c_double * 4)]
 
 
 _lib = None
@@ -212,8 +211,7 @@ class Context:
                     active_nnz=list(s.active_nnz[:k]), build_ms=s.build_ms,
                     rounds_ms=s.rounds_ms, sweep_ms=list(s.sweep_ms[:k]),
                     sweep_bytes=list(s.sweep_bytes[:k]), head_sweeps=s.head_sweeps,
-                    runs=s.runs, place_ms=s.place_ms, place_bytes=s.place_bytes,
-                    sort_ms=s.sort_ms, sort_bytes=s.sort_bytes)
+                    runs=s.runs, pass_ms=list(s.pass_ms), pass_bytes=list(s.pass_bytes))
 
     # ------------------------------------------------------- primitives --
     def graph(self, n: int, edges, weights, wtype: int | None = None) -> "Graph":

@@ -652,12 +652,14 @@ msf_status two_level_passes(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges
     auto *e1 = (RecT<PK1> *)B.e1;
     auto *e2 = (RecT<PK2> *)B.e2;
     // B1
+    MSF_HIP(hipEventRecord(c->kev[6], s));
     if (wt == MSF_W_F32)
         k_part_edges<MSF_W_F32, PK1><<<nblk, TL_NT, 0, s>>>(d_edges, d_w, m, n, tl.L1, NC, epb,
                                                             nblk, B.bo, tl.L2, cb, e1, B.sub1);
     else
         k_part_edges<MSF_W_U32, PK1><<<nblk, TL_NT, 0, s>>>(d_edges, d_w, m, n, tl.L1, NC, epb,
                                                             nblk, B.bo, tl.L2, cb, e1, B.sub1);
+    MSF_HIP(hipEventRecord(c->kev[7], s));
     // P, A2, scan, B2
     k_tl_plan<<<1, 1024, 0, s>>>(B.bo, nblk, NC, B.cs, B.nb2, B.P);
     launch_fill_u32(s, B.t2, 0u, nt2);
@@ -666,8 +668,10 @@ msf_status two_level_passes(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges
     // the level-1 bytes are dead once the fine histogram has read them:
     // their buffer takes each level-2 entry's row inside its fine bucket
     uint16_t *sub2 = reinterpret_cast<uint16_t *>(B.sub1);
+    MSF_HIP(hipEventRecord(c->kev[4], s));
     k_part_sub<PK1, PK2><<<(unsigned)g2max, TL_NT, 0, s>>>(e1, tl.L2, tl.nsub, NC, B.cs, B.nb2,
                                                            B.P, B.o2, cb, e2, sub2);
+    MSF_HIP(hipEventRecord(c->kev[5], s));
     // C
     const unsigned nf = (unsigned)NC * (unsigned)tl.nsub;
     k_tl_fstart<<<(nf + 256) / 256, 256, 0, s>>>(B.o2, B.nb2, B.P, tl.nsub, NC, B.fst);
@@ -683,7 +687,9 @@ msf_status two_level_passes(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges
         k_tl_place<false, PK2><<<nf, TC_NT, 4 * RC, s>>>(e2, n, tl.L2, cb, B.fst, B.order, row_ptr,
                                                           col, key, nullptr, sub2);
     MSF_HIP(hipEventRecord(c->kev[1], s));
-    c->place_rec = PK2 ? 12 : 16;
+    c->pass_done |= 1u | 4u | 8u;
+    c->rec1 = PK1 ? 12 : 16;
+    c->rec2 = PK2 ? 12 : 16;
     MSF_HIP(hipGetLastError());
     return MSF_OK;
 }

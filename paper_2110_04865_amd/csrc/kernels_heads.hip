@@ -384,7 +384,7 @@ msf_status build_runs(Ctx *c, const Runs &R, const uint32_t *row_ptr, int32_t n,
         k_sort_chunks<false><<<gs, 256, 0, s>>>(col, key, nnz, R.cfirst, total, R.cur, eb,
                                                 R.hcol, R.hkey);
     MSF_HIP(hipEventRecord(c->kev[3], s));
-    c->sort_timed = true;
+    c->pass_done |= 2u;
     MSF_HIP(hipGetLastError());
     return MSF_OK;
 }

@@ -211,10 +211,11 @@ struct Ctx {
     Counters *hcnt = nullptr;   // pinned host mirror
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t sev[2 * 64] = {};  // sweep start/end events, per round
-    // placement kernel of the two-level build and run sort: start/end
-    hipEvent_t kev[4] = {nullptr, nullptr, nullptr, nullptr};
-    int place_rec = 0;            // level-2 record bytes of the last timed placement (0: none)
-    bool sort_timed = false;
+    // one-launch passes (placement, run sort, level-2 and level-1
+    // partitions): start/end events, which ran, record bytes per level
+    hipEvent_t kev[8] = {};
+    unsigned pass_done = 0;
+    int rec1 = 0, rec2 = 0;
     msf_stats stats{};
     int filter_mode = 1;        // 0 never, 1 adaptive, 2 every round
     double filter_threshold = 0.30;

@@ -16,6 +16,7 @@
 // then unchanged, the paper's termination test), or earlier when fewer than
 // two roots can still have an outgoing edge.
 #include <algorithm>
+#include <cmath>
 
 #include "msf_internal.hpp"
 
@@ -149,8 +150,7 @@ msf_status solve_start(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, con
     if (S.heads) MSF_TRY(get_runs_bufs(c, n, m, &S.runs));
     MSF_HIP(hipEventRecord(c->ev[0], c->stream));
     zero_counters(c);
-    c->place_rec = 0;
-    c->sort_timed = false;
+    c->pass_done = 0;
     MSF_TRY(build_adjacency(c, n, m, d_edges, d_w, wt, slices, &S.a, S.b.rp[0], S.b.col[0],
                             S.b.key[0], S.b.crow[0], c->first_round == 2 ? S.b.r : nullptr,
                             &S.first_done));
@@ -316,18 +316,19 @@ msf_status solve_advance(Ctx *c)
             (void)hipEventElapsedTime(&ms, c->sev[2 * k], c->sev[2 * k + 1]);
             S.st.sweep_ms[k] = ms;
         }
-        if (c->place_rec) {
+        const double nnz = (double)S.a.nnz;
+        const double pass_bytes[4] = {
+            nnz * (c->rec2 + 12) + (double)S.n * (4.0 + (S.first_done ? 8.0 : 0.0)),
+            24.0 * nnz + 16.0 * S.nruns + 4.0 * std::ceil(nnz / 64.0),
+            nnz * (c->rec1 + c->rec2 + 2),
+            12.0 * (double)S.m + nnz * (c->rec1 + 1),
+        };
+        for (int q = 0; q < 4; ++q) {
+            if (!(c->pass_done & (1u << q))) continue;
             float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, c->kev[0], c->kev[1]);
-            S.st.place_ms = ms;
-            S.st.place_bytes = (double)S.a.nnz * (c->place_rec + 12) +
-                               (double)S.n * (4.0 + (S.first_done ? 8.0 : 0.0));
-        }
-        if (c->sort_timed) {
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, c->kev[2], c->kev[3]);
-            S.st.sort_ms = ms;
-            S.st.sort_bytes = 24.0 * S.a.nnz + 16.0 * S.nruns + 4.0 * ((S.a.nnz + 63) / 64);
+            (void)hipEventElapsedTime(&ms, c->kev[2 * q], c->kev[2 * q + 1]);
+            S.st.pass_ms[q] = ms;
+            S.st.pass_bytes[q] = pass_bytes[q];
         }
         S.st.max_chase = (int32_t)h->max_chase;
         c->stats = S.st;
