@@ -22,12 +22,12 @@
 //   phase B, one wave per queued run: the rest of the run at once, first
 //     outgoing entry by ballot.
 // Both phases move the head past the internal entries they saw and fold
-// their minima into r[root] like the full sweep (read filter, 64-bit
-// atomicMin), after a wave-wide segmented minimum over lanes of the same
-// root.  While the read filter is on (few live roots), phase A first
-// compares the head's key with r[root]: runs hold ascending keys and r only
-// falls during a sweep, so a head no smaller than r[root] is passed over
-// without a gather.  A round reads 16 bytes and gathers one parent per live run plus
+// their minima into r[root] (a read, then a 64-bit atomicMin only when it
+// improves), after a wave-wide segmented minimum over lanes of the same
+// root.  Phase A first compares the head's key with r[root]: runs hold
+// ascending keys and r only falls during a sweep, so a head no smaller than
+// r[root] is passed over without a gather (with ~97K live roots on R-MAT
+// s22 this still pays: 0.56 -> 0.47 ms over the solve's head sweeps).  A round reads 16 bytes and gathers one parent per live run plus
 // the entries that became internal, instead of every entry; the result
 // equals the full sweep's, element by element of r.
 #include "msf_internal.hpp"
@@ -39,20 +39,17 @@ namespace {
 
 constexpr int HEAD_PROBE = 4;
 
-// 1: read r before every atomic whatever the number of live roots.
-#ifndef HEADS_READ_FILTER
-#define HEADS_READ_FILTER 0
-#endif
 
 // v from lane (lane ^ J): DPP quad permutations for 1 and 2, swizzles
 // within 32 lanes for 4..16, a permute for 32.
 template <int J>
 __device__ __forceinline__ uint32_t xor_move(uint32_t v)
 {
+    // quad permutations give every lane a source: no old value needed
     if constexpr (J == 1)
-        return dpp_u32<0xB1>(v);  // quad_perm [1,0,3,2]
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);  // [1,0,3,2]
     else if constexpr (J == 2)
-        return dpp_u32<0x4E>(v);  // quad_perm [2,3,0,1]
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);  // [2,3,0,1]
     else if constexpr (J <= 16)
         return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (J << 10));
     else
@@ -66,12 +63,15 @@ __device__ __forceinline__ uint64_t xor_move64(uint64_t v)
     return ((uint64_t)xor_move<J>((uint32_t)(v >> 32)) << 32) | xor_move<J>((uint32_t)v);
 }
 
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
 // One compare-exchange step of the bitonic network over 64 lanes (block
 // size KK, partner distance J): the lower lane of an ascending pair keeps
 // the smaller element.  Elements are (pi, k, payload); with PACKED the run
-// index is folded into k and pi is unused.
+// index is folded into k and pi is unused.  lb[t] is bit t of the lane id
+// (computed once: the direction of a step is then lane-mask arithmetic).
 template <bool PACKED, int KK, int J>
-__device__ __forceinline__ void bitonic_step(uint32_t lane, uint32_t &pi, uint64_t &k,
+__device__ __forceinline__ void bitonic_step(const bool (&lb)[7], uint32_t &pi, uint64_t &k,
                                              uint32_t &pl)
 {
     const uint64_t ok = xor_move64<J>(k);
@@ -84,7 +84,7 @@ __device__ __forceinline__ void bitonic_step(uint32_t lane, uint32_t &pi, uint64
         opi = xor_move<J>(pi);
         other_less = (opi < pi) | ((opi == pi) & (ok < k));
     }
-    const bool keep_min = (((lane / (uint32_t)KK) ^ (lane / (uint32_t)J)) & 1u) == 0u;
+    const bool keep_min = lb[ilog2(KK)] == lb[ilog2(J)];
     const bool take = keep_min == other_less;
     k = take ? ok : k;
     pl = take ? opl : pl;
@@ -92,25 +92,24 @@ __device__ __forceinline__ void bitonic_step(uint32_t lane, uint32_t &pi, uint64
 }
 
 template <bool PACKED, int KK, int J>
-__device__ __forceinline__ void bitonic_merge(uint32_t lane, uint32_t &pi, uint64_t &k,
+__device__ __forceinline__ void bitonic_merge(const bool (&lb)[7], uint32_t &pi, uint64_t &k,
                                               uint32_t &pl)
 {
-    bitonic_step<PACKED, KK, J>(lane, pi, k, pl);
-    if constexpr (J > 1) bitonic_merge<PACKED, KK, J / 2>(lane, pi, k, pl);
+    bitonic_step<PACKED, KK, J>(lb, pi, k, pl);
+    if constexpr (J > 1) bitonic_merge<PACKED, KK, J / 2>(lb, pi, k, pl);
 }
 
 template <bool PACKED, int KK>
-__device__ __forceinline__ void bitonic_sort(uint32_t lane, uint32_t &pi, uint64_t &k,
+__device__ __forceinline__ void bitonic_sort(const bool (&lb)[7], uint32_t &pi, uint64_t &k,
                                              uint32_t &pl)
 {
-    bitonic_merge<PACKED, KK, KK / 2>(lane, pi, k, pl);
-    if constexpr (KK < 64) bitonic_sort<PACKED, KK * 2>(lane, pi, k, pl);
+    bitonic_merge<PACKED, KK, KK / 2>(lb, pi, k, pl);
+    if constexpr (KK < 64) bitonic_sort<PACKED, KK * 2>(lb, pi, k, pl);
 }
 
 // Wave-wide minimum per run of consecutive lanes holding the same root; the
 // last lane of each run folds it into r (lanes without a root hold NONE32).
-__device__ __forceinline__ void flush_by_root(uint64_t *r, uint32_t root, uint64_t v,
-                                              int read_filter)
+__device__ __forceinline__ void flush_by_root(uint64_t *r, uint32_t root, uint64_t v)
 {
     const uint32_t lane = __lane_id();
     const uint32_t prev = __shfl_up(root, 1);
@@ -127,10 +126,7 @@ __device__ __forceinline__ void flush_by_root(uint64_t *r, uint32_t root, uint64
     const uint32_t next = __shfl_down(root, 1);
     const bool last = lane == 63 || next != root;
     if (!last || root == NONE32 || v == KEY_INF) return;
-    if (read_filter)
-        min_into(r, root, v);
-    else
-        __hip_atomic_fetch_min(r + root, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    min_into(r, root, v);
 }
 
 }  // namespace
@@ -228,7 +224,10 @@ __global__ __launch_bounds__(256) void k_sort_chunks(uint32_t *__restrict__ col,
     const uint64_t emask = (1ull << eb) - 1ull;
     if constexpr (PACKED)
         k = valid ? ((uint64_t)pi << 58) | ((k >> 32) << eb) | (k & emask) : ~0ull;
-    bitonic_sort<PACKED, 2>(lane, pi, k, pl);
+    bool lb[7];
+#pragma unroll
+    for (int t = 0; t < 7; ++t) lb[t] = (lane >> t) & 1u;
+    bitonic_sort<PACKED, 2>(lb, pi, k, pl);
     if constexpr (PACKED) k = (((k >> eb) & 0xFFFFFFFFull) << 32) | (k & emask);
     if (valid) {
         col[pos] = pl;
@@ -251,8 +250,7 @@ __global__ __launch_bounds__(256) void k_heads(const uint32_t *__restrict__ run_
                                                const uint64_t *__restrict__ key,
                                                const uint32_t *__restrict__ p,
                                                uint64_t *__restrict__ r,
-                                               uint32_t *__restrict__ queue, uint32_t *qn,
-                                               int read_filter)
+                                               uint32_t *__restrict__ queue, uint32_t *qn)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t hk = i < nruns ? run_hkey[i] : KEY_INF;
@@ -262,10 +260,10 @@ __global__ __launch_bounds__(256) void k_heads(const uint32_t *__restrict__ run_
     if (hk != KEY_INF) {
         const uint32_t hc = run_hcol[i];
         root = p[run_row[i]];
-        // with the read filter on, a run whose head is no smaller than the
-        // root's current minimum cannot lower it (its keys only grow and r
-        // only falls): it is passed over without a gather
-        if (read_filter && hk >= load_relaxed_u64(r + root)) {
+        // a run whose head is no smaller than the root's current minimum
+        // cannot lower it (its keys only grow and r only falls): it is
+        // passed over without a gather
+        if (hk >= load_relaxed_u64(r + root)) {
             root = NONE32;
         } else if (p[hc] != root) {
             cand = hk;
@@ -309,7 +307,7 @@ __global__ __launch_bounds__(256) void k_heads(const uint32_t *__restrict__ run_
         base = __shfl(base, 0);
         if (push) queue[base + (uint32_t)__popcll(bal & lanemask_lt())] = i;
     }
-    flush_by_root(r, root, cand, read_filter);
+    flush_by_root(r, root, cand);
 }
 
 // Phase B: one wave per queued run (at most 64 - 1 - HEAD_PROBE entries
@@ -393,14 +391,12 @@ msf_status build_runs(Ctx *c, const Runs &R, const uint32_t *row_ptr, int32_t n,
 constexpr uint32_t HEADS_REST_BLOCKS = 1024;
 
 void launch_heads(hipStream_t s, const Runs &R, uint32_t nruns, const uint32_t *col,
-                  const uint64_t *key, const uint32_t *p, uint64_t *r, Counters *dcnt, int parity,
-                  bool read_filter)
+                  const uint64_t *key, const uint32_t *p, uint64_t *r, Counters *dcnt, int parity)
 {
     if (nruns == 0) return;
     uint32_t *qn = &dcnt->qn[parity & 1], *qn_next = &dcnt->qn[(parity & 1) ^ 1];
     k_heads<<<(nruns + 255u) / 256u, 256, 0, s>>>(R.row, R.cur, R.end, R.hcol, R.hkey, nruns, col,
-                                                  key, p, r, R.queue, qn,
-                                                  (read_filter || HEADS_READ_FILTER) ? 1 : 0);
+                                                  key, p, r, R.queue, qn);
     k_heads_rest<<<HEADS_REST_BLOCKS, 256, 0, s>>>(R.queue, qn, qn_next, nruns, R.row, R.cur,
                                                    R.end, R.hcol, R.hkey, col, key, p, r);
 }

@@ -354,8 +354,7 @@ size_t heads_runs_cap(size_t nnz_cap, int32_t n);
 msf_status build_runs(Ctx *c, const Runs &R, const uint32_t *row_ptr, int32_t n, uint32_t *col,
                       uint64_t *key, uint32_t nnz, int eb);
 void launch_heads(hipStream_t s, const Runs &R, uint32_t nruns, const uint32_t *col,
-                  const uint64_t *key, const uint32_t *p, uint64_t *r, Counters *dcnt, int parity,
-                  bool read_filter);
+                  const uint64_t *key, const uint32_t *p, uint64_t *r, Counters *dcnt, int parity);
 msf_status launch_output(Ctx *c, const uint8_t *in_forest, int64_t m, const void *w,
                          msf_wtype wt, int32_t *ids, void *part);
 

@@ -199,8 +199,7 @@ static msf_status enqueue_round(Ctx *c)
         launch_fill_u64(s, &c->dcnt->live, (uint64_t)S.a.nnz, 1);
     } else if (S.heads) {
         ++S.st.head_sweeps;
-        launch_heads(s, S.runs, S.nruns, S.a.col, S.a.key, S.b.p, S.b.r, c->dcnt, S.rounds,
-                     read_filter);
+        launch_heads(s, S.runs, S.nruns, S.a.col, S.a.key, S.b.p, S.b.r, c->dcnt, S.rounds);
     } else {
         // round 1: p is the identity and nothing has been filtered
         launch_sweep(s, S.a, S.b.p, S.b.r, c->dcnt, S.rounds == 0 && c->first_round >= 1,
