@@ -228,8 +228,8 @@ struct Ctx {
     int bucketed_build = 1;
     int slices = 0;                  // column slices: 0 automatic, else forced (1..8)
     // rounds after the first on one-slice adjacencies: head sweep over
-    // key-sorted runs (1 from a size on, 2 always) or full sweep with the
-    // filtering policy (0)
+    // key-sorted runs (1 from a size and an average degree on, 2 always) or
+    // full sweep with the filtering policy (0)
     int heads = 1;
     SolveState ss;
 };

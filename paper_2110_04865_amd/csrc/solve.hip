@@ -117,9 +117,15 @@ static msf_status get_runs_bufs(Ctx *c, int32_t n, int64_t m, Runs *R)
     return MSF_OK;
 }
 
-// Stored entries from which the head sweep is used by default: below, the
-// run set-up (five launches) costs more than it saves.
+// Default use of the head sweep: from HEADS_MIN_NNZ stored entries (below,
+// the run set-up's five launches cost more than they save) and from
+// HEADS_MIN_DEG stored entries per vertex on average (a run then covers
+// enough entries: R-MAT s22 has 30.6 per vertex and the head sweep takes a
+// solve from 7.5 to 5.6 ms; the 256^3 grid, 5.7, is even (10.3 vs 10.6 ms);
+// the 10^4-graph Erdos-Renyi batch, 8, loses (139 vs 104 ms): one gather
+// and one descriptor per run cost about what 14 streamed entries do).
 constexpr int64_t HEADS_MIN_NNZ = (int64_t)1 << 20;
+constexpr int64_t HEADS_MIN_DEG = 16;
 
 // End a step: counters to pinned host memory, then the step event.
 static msf_status end_step(Ctx *c, int next_phase)
@@ -146,7 +152,8 @@ msf_status solve_start(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, con
     MSF_TRY(get_solve_bufs(c, n, m, slices, &S.b));
     // head sweep: 1 from HEADS_MIN_NNZ stored entries on, 2 always
     S.heads = slices == 1 && m > 0 && n > 0 &&
-              (c->heads == 2 || (c->heads == 1 && 2 * m >= HEADS_MIN_NNZ));
+              (c->heads == 2 || (c->heads == 1 && 2 * m >= HEADS_MIN_NNZ &&
+                                 2 * m >= HEADS_MIN_DEG * (int64_t)n));
     if (S.heads) MSF_TRY(get_runs_bufs(c, n, m, &S.runs));
     MSF_HIP(hipEventRecord(c->ev[0], c->stream));
     zero_counters(c);
