@@ -98,6 +98,7 @@ void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S,
 // Writes go to h, never to p, so concurrent readers of p see one version.
 // r[i] is reset to empty for the next round.
 
+template <bool IDENTITY>
 __global__ void k_hook(const uint32_t *__restrict__ R, uint32_t nR, uint64_t *__restrict__ r,
                        const uint32_t *__restrict__ p, const int32_t *__restrict__ edges,
                        uint32_t *__restrict__ h, uint32_t *__restrict__ hedge,
@@ -110,8 +111,11 @@ __global__ void k_hook(const uint32_t *__restrict__ R, uint32_t nR, uint64_t *__
         if (key != KEY_INF) {
             r[i] = KEY_INF;
             const uint32_t e = (uint32_t)key;
-            const uint32_t a = p[edges[2 * (size_t)e]];
-            const uint32_t b = p[edges[2 * (size_t)e + 1]];
+            // with p the identity (round 1) the endpoints are their own roots
+            const uint32_t ea = (uint32_t)edges[2 * (size_t)e];
+            const uint32_t eb = (uint32_t)edges[2 * (size_t)e + 1];
+            const uint32_t a = IDENTITY ? ea : p[ea];
+            const uint32_t b = IDENTITY ? eb : p[eb];
             h[i] = (a == i) ? b : a;
             hedge[i] = e;
             hwk[i] = (uint32_t)(key >> 32);  // the hooked edge's weight key
@@ -123,9 +127,14 @@ __global__ void k_hook(const uint32_t *__restrict__ R, uint32_t nR, uint64_t *__
 }
 
 void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, const uint32_t *p,
-                 const int32_t *edges, uint32_t *h, uint32_t *hedge, uint32_t *hwk)
+                 const int32_t *edges, uint32_t *h, uint32_t *hedge, uint32_t *hwk,
+                 bool identity)
 {
-    if (nR) k_hook<<<grid_for(nR), 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk);
+    if (!nR) return;
+    if (identity)
+        k_hook<true><<<grid_for(nR), 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk);
+    else
+        k_hook<false><<<grid_for(nR), 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk);
 }
 
 // ------------------------------------------------------- forest weight --

@@ -324,9 +324,11 @@ size_t chunk_info_words(uint32_t nchunks);
 uint32_t compaction_tiles(uint64_t n);
 void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S, uint32_t *R,
                        uint64_t *status, Counters *dcnt);
-// hwk[i]: the weight key (high word of the edge key) of root i's hook
+// hwk[i]: the weight key (high word of the edge key) of root i's hook;
+// identity: p is the identity (round 1), so endpoints need no lookup
 void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, const uint32_t *p,
-                 const int32_t *edges, uint32_t *h, uint32_t *hedge, uint32_t *hwk);
+                 const int32_t *edges, uint32_t *h, uint32_t *hedge, uint32_t *hwk,
+                 bool identity = false);
 // Also zeroes dcnt->nR, nF and hooks before counting them.
 void launch_tiebreak(hipStream_t s, const uint32_t *R, uint32_t nR, uint32_t *h,
                      const uint32_t *hedge, uint8_t *in_forest, uint32_t *Rnext, uint32_t *F,

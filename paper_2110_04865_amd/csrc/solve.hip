@@ -213,7 +213,8 @@ static msf_status enqueue_round(Ctx *c)
                      S.b.wlive, read_filter);
     }
     if (ev_k >= 0) MSF_HIP(hipEventRecord(c->sev[2 * ev_k + 1], s));
-    launch_hook(s, S.b.R[S.ri], S.nR, S.b.r, S.b.p, S.edges, S.b.h, S.b.hedge, S.b.hwk);
+    launch_hook(s, S.b.R[S.ri], S.nR, S.b.r, S.b.p, S.edges, S.b.h, S.b.hedge, S.b.hwk,
+                S.rounds == 0);
     launch_tiebreak(s, S.b.R[S.ri], S.nR, S.b.h, S.b.hedge, S.b.flags, S.b.R[S.ri ^ 1], S.b.F,
                     S.b.status, c->dcnt);
     return end_step(c, 3);
@@ -250,7 +251,8 @@ msf_status solve_advance(Ctx *c)
             while (eb < 64 && ((uint64_t)(S.m > 1 ? S.m - 1 : 1) >> eb)) ++eb;
             MSF_TRY(build_runs(c, S.runs, S.a.row_ptr, S.n, S.a.col, S.a.key, S.a.nnz, eb));
         }
-        if (S.a.nnz) launch_chunk_rows_sliced(s, S.a);
+        // the chunk-row table serves the full sweep only
+        if (S.a.nnz && !S.heads) launch_chunk_rows_sliced(s, S.a);
         MSF_HIP(hipEventRecord(c->ev[1], s));
         launch_iota_u32(s, S.b.p, (size_t)S.n);
         launch_iota_u32(s, S.b.h, (size_t)S.n);
