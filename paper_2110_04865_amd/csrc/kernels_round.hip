@@ -143,9 +143,9 @@ void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, con
 // float32 subnormal) split over 32-bit digits held in int64 lanes, so the
 // sum does not depend on the order of additions; infinities are counted
 // separately.  The shortcut chase visits every kept hook once; each of its
-// workgroups adds its partial sums to the counters with one atomic per
-// digit in use, and k_total rounds once at the end.  The weight comes back
-// from the key's high word: for float32 the key map is undone.
+// workgroups writes its partial sums to its own slot, k_chase_fold adds the
+// slots into the counters, and k_total rounds once at the end.  The weight
+// comes back from the key's high word: for float32 the key map is undone.
 
 constexpr int ACC_DIGITS = 10;
 

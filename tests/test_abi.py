@@ -68,3 +68,24 @@ def test_context_without_gpu_fails_cleanly():
     rc = L.msf_ctx_create(0, None, ctypes.byref(h))
     assert rc in (3, 1)  # MSF_EDEVICE (no device) or MSF_EINVAL
     assert not h.value
+
+
+def test_stats_struct_matches_header(tmp_path):
+    """The binding's msf_stats mirror has the header's size and field offsets
+    (the library writes sizeof(msf_stats) bytes into it)."""
+    fields = [f[0] for f in pkg.Stats._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text(
+        "#include <stddef.h>\n#include <stdio.h>\n#include \"msf.h\"\n"
+        "int main(void) {\n"
+        "  printf(\"size %zu\\n\", sizeof(msf_stats));\n"
+        + "".join(f"  printf(\"{f} %zu\\n\", offsetof(msf_stats, {f}));\n" for f in fields)
+        + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = dict((k, int(v)) for k, v in (ln.split() for ln in out.splitlines()))
+    assert got["size"] == ctypes.sizeof(pkg.Stats)
+    for f in fields:
+        assert got[f] == getattr(pkg.Stats, f).offset, f
