@@ -39,6 +39,13 @@ namespace {
 
 constexpr int HEAD_PROBE = 4;
 
+// Runs of rows longer than LONG_ROW entries carry RUN_LONG in their row
+// word (rows are below 2^31).  A sweep visits them first: their heads are
+// the smallest keys of 64-entry pieces of hub rows, so their roots' minima
+// fall early and prune more of the short rows' heads after them.
+constexpr uint32_t LONG_ROW = 512;
+constexpr uint32_t RUN_LONG = 0x80000000u;
+
 
 // v from lane (lane ^ J): DPP quad permutations for 1 and 2, swizzles
 // within 32 lanes for 4..16, a permute for 32.
@@ -166,7 +173,7 @@ __global__ __launch_bounds__(256) void k_runs_write(const uint32_t *__restrict__
         const uint32_t qe = (c0 + t + 1u) << 6 < re ? (c0 + t + 1u) << 6 : re;
         cur[ro + t] = q;
         end[ro + t] = qe;
-        row[ro + t] = rr;
+        row[ro + t] = rr | (((re - rs) > LONG_ROW) ? RUN_LONG : 0u);
         if ((q & 63u) == 0) cfirst[q >> 6] = ro + t;
     };
     constexpr uint32_t LANE_RUNS = 8;
@@ -250,16 +257,22 @@ __global__ __launch_bounds__(256) void k_heads(const uint32_t *__restrict__ run_
                                                const uint64_t *__restrict__ key,
                                                const uint32_t *__restrict__ p,
                                                uint64_t *__restrict__ r,
-                                               uint32_t *__restrict__ queue, uint32_t *qn)
+                                               uint32_t *__restrict__ queue, uint32_t *qn,
+                                               uint32_t want_long)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t hk = i < nruns ? run_hkey[i] : KEY_INF;
+    uint64_t hk = i < nruns ? run_hkey[i] : KEY_INF;
+    uint32_t rw = 0;
+    if (hk != KEY_INF) {
+        rw = run_row[i];
+        if ((rw & RUN_LONG) != want_long) hk = KEY_INF;  // the other launch's run
+    }
     uint32_t root = NONE32;
     uint64_t cand = KEY_INF;
     bool push = false;
     if (hk != KEY_INF) {
         const uint32_t hc = run_hcol[i];
-        root = p[run_row[i]];
+        root = p[rw & ~RUN_LONG];
         // a run whose head is no smaller than the root's current minimum
         // cannot lower it (its keys only grow and r only falls): it is
         // passed over without a gather
@@ -328,7 +341,7 @@ __global__ __launch_bounds__(256) void k_heads_rest(
     for (uint32_t w = blockIdx.x * (blockDim.x / 64u) + (threadIdx.x >> 6); w < n; w += nw) {
         const uint32_t i = queue[w];
         const uint32_t cur = run_cur[i], end = run_end[i];
-        const uint32_t root = p[run_row[i]];
+        const uint32_t root = p[run_row[i] & ~RUN_LONG];
         const uint32_t q = cur + lane;
         uint32_t c = 0;
         bool ext = false;
@@ -395,8 +408,9 @@ void launch_heads(hipStream_t s, const Runs &R, uint32_t nruns, const uint32_t *
 {
     if (nruns == 0) return;
     uint32_t *qn = &dcnt->qn[parity & 1], *qn_next = &dcnt->qn[(parity & 1) ^ 1];
-    k_heads<<<(nruns + 255u) / 256u, 256, 0, s>>>(R.row, R.cur, R.end, R.hcol, R.hkey, nruns, col,
-                                                  key, p, r, R.queue, qn);
+    for (uint32_t want_long : {RUN_LONG, 0u})
+        k_heads<<<(nruns + 255u) / 256u, 256, 0, s>>>(R.row, R.cur, R.end, R.hcol, R.hkey, nruns,
+                                                      col, key, p, r, R.queue, qn, want_long);
     k_heads_rest<<<HEADS_REST_BLOCKS, 256, 0, s>>>(R.queue, qn, qn_next, nruns, R.row, R.cur,
                                                    R.end, R.hcol, R.hkey, col, key, p, r);
 }
