@@ -36,7 +36,10 @@ namespace msf {
 namespace {
 
 constexpr int TL_NT = 512;         // partition workgroup
-constexpr int TL_TILE = 4096;      // entries per LDS tile
+#ifndef TL_TILE_ENTRIES
+#define TL_TILE_ENTRIES 4096
+#endif
+constexpr int TL_TILE = TL_TILE_ENTRIES;  // entries per LDS tile
 constexpr int TL_E2 = 8192;        // level-1 entries per level-2 workgroup
 #ifndef TL_PLACE_THREADS
 #define TL_PLACE_THREADS 256
