@@ -243,15 +243,11 @@ __global__ __launch_bounds__(CT_NT) void k_tiebreak(const uint32_t *__restrict__
                                                     uint32_t *h, const uint32_t *__restrict__ hedge,
                                                     uint8_t *__restrict__ in_forest,
                                                     uint32_t *__restrict__ Rnext,
-                                                    uint32_t *__restrict__ F, uint64_t *status,
-                                                    Counters *cnt)
+                                                    uint32_t *__restrict__ F, Counters *cnt)
 {
-    __shared__ uint32_t s_tile;
     __shared__ uint64_t s_lds[CT_NT / 64 + 1];
     __shared__ uint64_t s_pre;
-    if (threadIdx.x == 0) s_tile = atomicAdd(&cnt->ticket, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
+    const uint32_t tile = blockIdx.x;
     const uint32_t base = tile * CT_TILE + threadIdx.x * CT_IT;
     uint32_t id[CT_IT];
     uint32_t stay = 0, hooked = 0, ca = 0, cb = 0;
@@ -276,17 +272,29 @@ __global__ __launch_bounds__(CT_NT) void k_tiebreak(const uint32_t *__restrict__
             }
         }
     }
-    uint32_t oa, ob;
-    uint64_t tot;
-    tile_offsets2<CT_NT>(tile, ca, cb, status, s_lds, &s_pre, &oa, &ob, &tot);
+    // both lists are sets (no later step depends on their order): a block
+    // takes its slots with one atomic on the packed (roots << 31 | hooks)
+    // count instead of an ordered look-back over the tiles; the last block
+    // to finish publishes the totals (each block's slot atomic has returned
+    // before it counts itself done)
+    uint64_t btot;
+    const uint64_t ex = block_excl_sum<CT_NT>(((uint64_t)ca << 31) | cb, s_lds, &btot);
+    if (threadIdx.x == 0) {
+        const uint64_t pre = atomicAdd((unsigned long long *)&cnt->rf, (unsigned long long)btot);
+        s_pre = pre;
+        if (atomicAdd(&cnt->tdone, pre == ~0ull ? 0u : 1u) == gridDim.x - 1) {
+            const uint64_t tot = atomicAdd((unsigned long long *)&cnt->rf, 0ull);
+            cnt->nR = (uint32_t)(tot >> 31);
+            cnt->nF = (uint32_t)(tot & M31);
+        }
+    }
+    __syncthreads();
+    uint32_t oa = (uint32_t)((s_pre >> 31) + (ex >> 31));
+    uint32_t ob = (uint32_t)((s_pre & M31) + (ex & M31));
 #pragma unroll
     for (int k = 0; k < CT_IT; ++k) {
         if (stay & (1u << k)) Rnext[oa++] = id[k];
         else if (hooked & (1u << k)) F[ob++] = id[k];
-    }
-    if (tile == gridDim.x - 1 && threadIdx.x == 0) {
-        cnt->nR = (uint32_t)(tot >> 31);
-        cnt->nF = (uint32_t)(tot & M31);
     }
 }
 
@@ -295,10 +303,11 @@ void launch_tiebreak(hipStream_t s, const uint32_t *R, uint32_t nR, uint32_t *h,
                      uint64_t *status, Counters *dcnt)
 {
     const uint32_t tiles = ct_tiles(nR);
-    // one launch clears the look-back status, the ticket and nR, nF, hooks
-    launch_zero_lookback(s, status, tiles, &dcnt->ticket, 1, &dcnt->nR, 3);
+    (void)status;
+    // one launch clears the slot count, the done count and nR, nF, hooks
+    launch_zero_lookback(s, nullptr, 0, reinterpret_cast<uint32_t *>(&dcnt->rf), 4, &dcnt->nR, 3);
     if (!tiles) return;
-    k_tiebreak<<<tiles, CT_NT, 0, s>>>(R, nR, h, hedge, in_forest, Rnext, F, status, dcnt);
+    k_tiebreak<<<tiles, CT_NT, 0, s>>>(R, nR, h, hedge, in_forest, Rnext, F, dcnt);
 }
 
 // ------------------------------------------------------------- shortcut --

@@ -122,6 +122,9 @@ struct Counters {
     uint32_t sstart[MAX_SLICES + 1];  // slice boundaries of an adjacency
     uint32_t nruns;       // key-sorted runs of the adjacency (head sweep)
     uint32_t qn[2];       // head sweep queue lengths (alternating rounds)
+    uint64_t rf;          // tie break: slots taken, roots << 31 | hooks
+    uint32_t tdone;       // tie break: workgroups done
+    uint32_t rf_pad;
 };
 
 // Key-sorted runs for the head sweep: every 64-entry chunk of the
