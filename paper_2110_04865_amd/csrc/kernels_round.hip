@@ -98,11 +98,16 @@ void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S,
 // Writes go to h, never to p, so concurrent readers of p see one version.
 // r[i] is reset to empty for the next round.
 
+// IDENTITY: p is the identity (round 1); with row_ptr and col (rows sorted
+// by key inside every 64-entry chunk), a root whose row lies in one chunk
+// takes its hook target from the row's first entry (its smallest key)
+// instead of gathering the edge's endpoints.
 template <bool IDENTITY>
 __global__ void k_hook(const uint32_t *__restrict__ R, uint32_t nR, uint64_t *__restrict__ r,
                        const uint32_t *__restrict__ p, const int32_t *__restrict__ edges,
                        uint32_t *__restrict__ h, uint32_t *__restrict__ hedge,
-                       uint32_t *__restrict__ hwk)
+                       uint32_t *__restrict__ hwk, const uint32_t *__restrict__ row_ptr,
+                       const uint32_t *__restrict__ col)
 {
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nR; k += stride) {
@@ -111,12 +116,22 @@ __global__ void k_hook(const uint32_t *__restrict__ R, uint32_t nR, uint64_t *__
         if (key != KEY_INF) {
             r[i] = KEY_INF;
             const uint32_t e = (uint32_t)key;
-            // with p the identity (round 1) the endpoints are their own roots
-            const uint32_t ea = (uint32_t)edges[2 * (size_t)e];
-            const uint32_t eb = (uint32_t)edges[2 * (size_t)e + 1];
-            const uint32_t a = IDENTITY ? ea : p[ea];
-            const uint32_t b = IDENTITY ? eb : p[eb];
-            h[i] = (a == i) ? b : a;
+            bool done = false;
+            if (IDENTITY && row_ptr) {
+                const uint32_t rs = row_ptr[i], re = row_ptr[i + 1];
+                if ((rs >> 6) == ((re - 1u) >> 6)) {
+                    h[i] = col[rs];
+                    done = true;
+                }
+            }
+            if (!done) {
+                // with p the identity (round 1) the endpoints are their own roots
+                const uint32_t ea = (uint32_t)edges[2 * (size_t)e];
+                const uint32_t eb = (uint32_t)edges[2 * (size_t)e + 1];
+                const uint32_t a = IDENTITY ? ea : p[ea];
+                const uint32_t b = IDENTITY ? eb : p[eb];
+                h[i] = (a == i) ? b : a;
+            }
             hedge[i] = e;
             hwk[i] = (uint32_t)(key >> 32);  // the hooked edge's weight key
         } else {
@@ -128,13 +143,15 @@ __global__ void k_hook(const uint32_t *__restrict__ R, uint32_t nR, uint64_t *__
 
 void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, const uint32_t *p,
                  const int32_t *edges, uint32_t *h, uint32_t *hedge, uint32_t *hwk,
-                 bool identity)
+                 bool identity, const uint32_t *sorted_row_ptr, const uint32_t *sorted_col)
 {
     if (!nR) return;
     if (identity)
-        k_hook<true><<<grid_for(nR), 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk);
+        k_hook<true><<<grid_for(nR), 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk,
+                                                  sorted_row_ptr, sorted_col);
     else
-        k_hook<false><<<grid_for(nR), 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk);
+        k_hook<false><<<grid_for(nR), 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk, nullptr,
+                                                   nullptr);
 }
 
 // ------------------------------------------------------- forest weight --

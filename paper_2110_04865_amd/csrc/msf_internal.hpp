@@ -328,10 +328,13 @@ uint32_t compaction_tiles(uint64_t n);
 void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S, uint32_t *R,
                        uint64_t *status, Counters *dcnt);
 // hwk[i]: the weight key (high word of the edge key) of root i's hook;
-// identity: p is the identity (round 1), so endpoints need no lookup
+// identity: p is the identity (round 1), so endpoints need no lookup; with
+// sorted_row_ptr/sorted_col (one-slice adjacency sorted into the head
+// sweep's runs) a row inside one 64-entry chunk gives its target directly.
 void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, const uint32_t *p,
                  const int32_t *edges, uint32_t *h, uint32_t *hedge, uint32_t *hwk,
-                 bool identity = false);
+                 bool identity = false, const uint32_t *sorted_row_ptr = nullptr,
+                 const uint32_t *sorted_col = nullptr);
 // Also zeroes dcnt->nR, nF and hooks before counting them.
 void launch_tiebreak(hipStream_t s, const uint32_t *R, uint32_t nR, uint32_t *h,
                      const uint32_t *hedge, uint8_t *in_forest, uint32_t *Rnext, uint32_t *F,
