@@ -72,6 +72,29 @@ __device__ __forceinline__ uint64_t xor_move64(uint64_t v)
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
+#ifndef BITONIC_SGPR_SELECT
+#define BITONIC_SGPR_SELECT 1
+#endif
+
+// Lanes l of a wave for which bit log2(KK) of l equals bit log2(J): in a
+// bitonic step they keep the smaller element of their pair.
+constexpr uint64_t keep_min_lanes(int KK, int J)
+{
+    uint64_t m = 0;
+    for (int l = 0; l < 64; ++l)
+        if (((l / KK) & 1) == ((l / J) & 1)) m |= 1ull << l;
+    return m;
+}
+
+// Per lane: mask bit set ? if_set : if_clear (one v_cndmask on a scalar
+// lane mask; register operands only).
+__device__ __forceinline__ uint32_t select_lanes(uint64_t mask, uint32_t if_set, uint32_t if_clear)
+{
+    uint32_t r;
+    asm volatile("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(if_clear), "v"(if_set), "s"(mask));
+    return r;
+}
+
 // One compare-exchange step of the bitonic network over 64 lanes (block
 // size KK, partner distance J): the lower lane of an ascending pair keeps
 // the smaller element.  Elements are (pi, k, payload); with PACKED the run
@@ -91,11 +114,23 @@ __device__ __forceinline__ void bitonic_step(const bool (&lb)[7], uint32_t &pi, 
         opi = xor_move<J>(pi);
         other_less = (opi < pi) | ((opi == pi) & (ok < k));
     }
+#if BITONIC_SGPR_SELECT
+    (void)lb;
+    // the lanes that keep the smaller element are a fixed pattern; the
+    // selection mask is then scalar arithmetic on the comparison's lane mask
+    constexpr uint64_t KEEP_MIN = keep_min_lanes(KK, J);
+    const uint64_t take = ~(__ballot(other_less) ^ KEEP_MIN);
+    k = ((uint64_t)select_lanes(take, (uint32_t)(ok >> 32), (uint32_t)(k >> 32)) << 32) |
+        select_lanes(take, (uint32_t)ok, (uint32_t)k);
+    pl = select_lanes(take, opl, pl);
+    if constexpr (!PACKED) pi = select_lanes(take, opi, pi);
+#else
     const bool keep_min = lb[ilog2(KK)] == lb[ilog2(J)];
     const bool take = keep_min == other_less;
     k = take ? ok : k;
     pl = take ? opl : pl;
     if constexpr (!PACKED) pi = take ? opi : pi;
+#endif
 }
 
 template <bool PACKED, int KK, int J>
