@@ -37,13 +37,19 @@ namespace msf {
 
 namespace {
 
-constexpr int HEAD_PROBE = 4;
+#ifndef HEAD_PROBE_ENTRIES
+#define HEAD_PROBE_ENTRIES 4
+#endif
+constexpr int HEAD_PROBE = HEAD_PROBE_ENTRIES;
 
 // Runs of rows longer than LONG_ROW entries carry RUN_LONG in their row
 // word (rows are below 2^31).  A sweep visits them first: their heads are
 // the smallest keys of 64-entry pieces of hub rows, so their roots' minima
 // fall early and prune more of the short rows' heads after them.
-constexpr uint32_t LONG_ROW = 512;
+#ifndef HEAD_LONG_ROW
+#define HEAD_LONG_ROW 2048
+#endif
+constexpr uint32_t LONG_ROW = HEAD_LONG_ROW;
 constexpr uint32_t RUN_LONG = 0x80000000u;
 
 

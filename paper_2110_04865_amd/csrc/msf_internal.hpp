@@ -135,7 +135,7 @@ struct Runs {
     uint32_t *roff = nullptr;    // per row: exclusive prefix of rc (n + 1 entries)
     uint32_t *cur = nullptr;     // per run: its head (first entry not known internal)
     uint32_t *end = nullptr;     // per run: one past its last entry
-    uint32_t *row = nullptr;     // per run: its row (bit 31: a row of over 512 entries)
+    uint32_t *row = nullptr;     // per run: its row (bit 31: a long row, swept first)
     uint32_t *hcol = nullptr;    // per run: column of the head
     uint64_t *hkey = nullptr;    // per run: key of the head (UINT64_MAX: run exhausted)
     uint32_t *queue = nullptr;   // runs left to phase B of a sweep
