@@ -107,8 +107,14 @@ __global__ void k_hook(const uint32_t *__restrict__ R, uint32_t nR, uint64_t *__
                        const uint32_t *__restrict__ p, const int32_t *__restrict__ edges,
                        uint32_t *__restrict__ h, uint32_t *__restrict__ hedge,
                        uint32_t *__restrict__ hwk, const uint32_t *__restrict__ row_ptr,
-                       const uint32_t *__restrict__ col)
+                       const uint32_t *__restrict__ col, Counters *tb_cnt)
 {
+    // the tie break that follows counts into these (no kernel between reads them)
+    if (tb_cnt && blockIdx.x == 0 && threadIdx.x == 0) {
+        tb_cnt->rf = 0;
+        tb_cnt->tdone = 0;
+        tb_cnt->nR = tb_cnt->nF = tb_cnt->hooks = 0;
+    }
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nR; k += stride) {
         const uint32_t i = R[k];
@@ -143,15 +149,16 @@ __global__ void k_hook(const uint32_t *__restrict__ R, uint32_t nR, uint64_t *__
 
 void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, const uint32_t *p,
                  const int32_t *edges, uint32_t *h, uint32_t *hedge, uint32_t *hwk,
-                 bool identity, const uint32_t *sorted_row_ptr, const uint32_t *sorted_col)
+                 bool identity, const uint32_t *sorted_row_ptr, const uint32_t *sorted_col,
+                 Counters *tb_cnt)
 {
     if (!nR) return;
     if (identity)
         k_hook<true><<<grid_for(nR), 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk,
-                                                  sorted_row_ptr, sorted_col);
+                                                  sorted_row_ptr, sorted_col, tb_cnt);
     else
         k_hook<false><<<grid_for(nR), 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk, nullptr,
-                                                   nullptr);
+                                                   nullptr, tb_cnt);
 }
 
 // ------------------------------------------------------- forest weight --
@@ -317,12 +324,15 @@ __global__ __launch_bounds__(CT_NT) void k_tiebreak(const uint32_t *__restrict__
 
 void launch_tiebreak(hipStream_t s, const uint32_t *R, uint32_t nR, uint32_t *h,
                      const uint32_t *hedge, uint8_t *in_forest, uint32_t *Rnext, uint32_t *F,
-                     uint64_t *status, Counters *dcnt)
+                     uint64_t *status, Counters *dcnt, bool counts_cleared)
 {
     const uint32_t tiles = ct_tiles(nR);
     (void)status;
-    // one launch clears the slot count, the done count and nR, nF, hooks
-    launch_zero_lookback(s, nullptr, 0, reinterpret_cast<uint32_t *>(&dcnt->rf), 4, &dcnt->nR, 3);
+    // the slot count, the done count and nR, nF, hooks start at zero: cleared
+    // by the hook launched just before (it runs whenever nR > 0), else here
+    if (!counts_cleared)
+        launch_zero_lookback(s, nullptr, 0, reinterpret_cast<uint32_t *>(&dcnt->rf), 4,
+                             &dcnt->nR, 3);
     if (!tiles) return;
     k_tiebreak<<<tiles, CT_NT, 0, s>>>(R, nR, h, hedge, in_forest, Rnext, F, dcnt);
 }

@@ -334,11 +334,13 @@ void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S,
 void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, const uint32_t *p,
                  const int32_t *edges, uint32_t *h, uint32_t *hedge, uint32_t *hwk,
                  bool identity = false, const uint32_t *sorted_row_ptr = nullptr,
-                 const uint32_t *sorted_col = nullptr);
-// Also zeroes dcnt->nR, nF and hooks before counting them.
+                 const uint32_t *sorted_col = nullptr, Counters *tb_cnt = nullptr);
+// Counts into dcnt->nR, nF; they (and the slot counts) start at zero: the
+// hook launched just before with tb_cnt clears them (counts_cleared), else
+// this call does.
 void launch_tiebreak(hipStream_t s, const uint32_t *R, uint32_t nR, uint32_t *h,
                      const uint32_t *hedge, uint8_t *in_forest, uint32_t *Rnext, uint32_t *F,
-                     uint64_t *status, Counters *dcnt);
+                     uint64_t *status, Counters *dcnt, bool counts_cleared = false);
 // Also adds the weights of the kept hooks F (from hwk) exactly to dcnt's
 // forest-weight sums.
 void launch_chase(hipStream_t s, const uint32_t *F, uint32_t nF, uint32_t *h,

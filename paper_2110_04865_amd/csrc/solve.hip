@@ -214,9 +214,10 @@ static msf_status enqueue_round(Ctx *c)
     }
     if (ev_k >= 0) MSF_HIP(hipEventRecord(c->sev[2 * ev_k + 1], s));
     launch_hook(s, S.b.R[S.ri], S.nR, S.b.r, S.b.p, S.edges, S.b.h, S.b.hedge, S.b.hwk,
-                S.rounds == 0, S.heads ? S.a.row_ptr : nullptr, S.heads ? S.a.col : nullptr);
+                S.rounds == 0, S.heads ? S.a.row_ptr : nullptr, S.heads ? S.a.col : nullptr,
+                c->dcnt);
     launch_tiebreak(s, S.b.R[S.ri], S.nR, S.b.h, S.b.hedge, S.b.flags, S.b.R[S.ri ^ 1], S.b.F,
-                    S.b.status, c->dcnt);
+                    S.b.status, c->dcnt, S.nR > 0);
     return end_step(c, 3);
 }
 
