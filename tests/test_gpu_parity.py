@@ -551,3 +551,35 @@ def test_build_modes_agree(pkg):
             os.environ.pop("MSF_BUCKETED_BUILD", None)
         else:
             os.environ["MSF_BUCKETED_BUILD"] = old
+
+
+def test_head_sweep_with_every_build_and_first_round(pkg):
+    """The head sweep forced on after the device-atomic (0) and one-level (2)
+    builds (runs set up from row_ptr by their own kernels) and with round 1
+    swept instead of taken from the build (first round 0 and 1): the
+    oracle's forest and per-round hooks."""
+    graphs = [
+        ("rmat14", *gen.rmat(14, 16, seed=51), F32),
+        ("grid12", *gen.grid(12, 12, 12, 0.05, seed=52), U32),
+    ]
+    keys = ("MSF_HEADS", "MSF_BUCKETED_BUILD", "MSF_FIRST_ROUND")
+    old = {k: os.environ.get(k) for k in keys}
+    try:
+        for build, first in (("0", "2"), ("2", "2"), ("1", "0"), ("1", "1")):
+            os.environ["MSF_HEADS"] = "2"
+            os.environ["MSF_BUCKETED_BUILD"] = build
+            os.environ["MSF_FIRST_ROUND"] = first
+            c = pkg.Context(0)
+            for label, n, e, w, wt in graphs:
+                st = check_solve(c, pkg, n, e, w, wt, f"heads build={build} first={first} {label}")
+                ref = oracle.as_rounds(n, e, w, wt)
+                hooks = [h for h in ref["hooks"] if h]
+                assert st["hooks"][:len(hooks)] == hooks, (label, st["hooks"], hooks)
+                assert st["runs"] > 0 and st["head_sweeps"] >= 1, (label, st["runs"])
+            c.close()
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
