@@ -27,9 +27,10 @@
 // root.  Phase A first compares the head's key with r[root]: runs hold
 // ascending keys and r only falls during a sweep, so a head no smaller than
 // r[root] is passed over without a gather (with ~97K live roots on R-MAT
-// s22 this still pays: 0.56 -> 0.47 ms over the solve's head sweeps).  A round reads 16 bytes and gathers one parent per live run plus
-// the entries that became internal, instead of every entry; the result
-// equals the full sweep's, element by element of r.
+// s22 this still pays: 0.56 -> 0.47 ms over the solve's head sweeps).  A
+// round reads 16 bytes and gathers one parent per live run plus the entries
+// that became internal, instead of every entry; the result equals the full
+// sweep's, element by element of r.
 #include "msf_internal.hpp"
 #include "wave.hpp"
 
