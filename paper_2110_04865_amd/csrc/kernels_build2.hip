@@ -212,6 +212,21 @@ __global__ __launch_bounds__(TL_NT) void k_part_edges(
     for (int c = threadIdx.x; c < NC; c += TL_NT) s_run[c] = bo1[(size_t)c * nblk + blockIdx.x];
     const int64_t e0 = (int64_t)blockIdx.x * epb;
     const int64_t e1 = e0 + epb < m ? e0 + epb : m;
+    // the next tile's edges are loaded while the current one is ranked and
+    // written (the barriers below wait for LDS only); indices are clamped to
+    // the block's last edge so the loads are unconditional (two 4-byte loads
+    // per edge: the edge array is only guaranteed 4-byte aligned)
+    const int64_t elast = e1 - 1;
+    int32_t pu[TL_EP], pv[TL_EP];
+    uint32_t pw[TL_EP];
+#pragma unroll
+    for (int k = 0; k < TL_EP; ++k) {
+        int64_t e = e0 + threadIdx.x + (int64_t)k * TL_NT;
+        e = e < elast ? e : elast;
+        pu[k] = edges[2 * e];
+        pv[k] = edges[2 * e + 1];
+        pw[k] = ((const uint32_t *)w)[e];
+    }
     for (int64_t t0 = e0; t0 < e1; t0 += TL_TILE / 2) {
         int32_t eu[TL_EP], ev[TL_EP];
         uint32_t ew[TL_EP];
@@ -220,12 +235,19 @@ __global__ __launch_bounds__(TL_NT) void k_part_edges(
         for (int k = 0; k < TL_EP; ++k) {
             const int64_t e = t0 + threadIdx.x + (int64_t)k * TL_NT;
             const bool in = e < e1;
-            // two 4-byte loads: the edge array is only guaranteed 4-byte aligned
-            eu[k] = in ? edges[2 * e] : 0;
-            ev[k] = in ? edges[2 * e + 1] : 0;
-            ew[k] = in ? ((const uint32_t *)w)[e] : 0u;
+            eu[k] = in ? pu[k] : 0;
+            ev[k] = in ? pv[k] : 0;
+            ew[k] = in ? pw[k] : 0u;
             ok[k] = in && (uint32_t)eu[k] < (uint32_t)n && (uint32_t)ev[k] < (uint32_t)n &&
                     eu[k] != ev[k];
+        }
+#pragma unroll
+        for (int k = 0; k < TL_EP; ++k) {
+            int64_t e = t0 + TL_TILE / 2 + threadIdx.x + (int64_t)k * TL_NT;
+            e = e < elast ? e : elast;
+            pu[k] = edges[2 * e];
+            pv[k] = edges[2 * e + 1];
+            pw[k] = ((const uint32_t *)w)[e];
         }
         for (int c = threadIdx.x; c < NCC; c += TL_NT) s_pos[c] = 0;
         __syncthreads();
@@ -371,12 +393,29 @@ __global__ __launch_bounds__(TL_NT) void k_part_sub(
     int lg = 0;
     while ((1 << lg) < nsub) ++lg;
     const uint32_t L1 = (uint32_t)(L2 + lg), rowhi = c << L1;
+    // the next tile's records are loaded while the current one is ranked and
+    // written (the barriers below wait for LDS only, so the loads stay in
+    // flight across them)
+    // (indices clamped to the last entry: unconditional loads keep the
+    // compiler from waiting for each one in its own branch)
+    RecT<PK1> raw[TL_SP];
+    const uint64_t last = (uint64_t)e - 1u;
+#pragma unroll
+    for (int k = 0; k < TL_SP; ++k) {
+        const uint64_t i = (uint64_t)a + threadIdx.x + (uint32_t)k * TL_NT;
+        raw[k] = e1[i < last ? i : last];
+    }
     for (uint64_t t0 = a; t0 < e; t0 += TL_TILE) {
         uint4 xx[TL_SP];
 #pragma unroll
         for (int k = 0; k < TL_SP; ++k) {
             const uint64_t i = t0 + threadIdx.x + (uint32_t)k * TL_NT;
-            xx[k] = i < e ? rec_unpack<PK1>(e1[i], rowhi, L1, cb) : make_uint4(NONE32, 0u, 0u, 0u);
+            xx[k] = i < e ? rec_unpack<PK1>(raw[k], rowhi, L1, cb) : make_uint4(NONE32, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int k = 0; k < TL_SP; ++k) {
+            const uint64_t i = t0 + TL_TILE + threadIdx.x + (uint32_t)k * TL_NT;
+            raw[k] = e1[i < last ? i : last];
         }
         for (int s = threadIdx.x; s < nsc; s += TL_NT) s_pos[s] = 0;
         __syncthreads();
