@@ -25,9 +25,16 @@ Also reported on the same JSON line:
                 graph;
   served        continuous-batching server: p50/p99 latency and graphs/s of
                 a Poisson stream of mixed graphs at several rates, vs a plain
-                one-at-a-time FIFO.
+                one-at-a-time FIFO;
+  multilinear_ablation
+                the all-at-once multilinear kernel vs the pairwise
+                formulation (pairs (a_ij, p_j) stored first, then reduced) on
+                R-MAT scale 17 edge factor 8 and on the scale-22 graph, for
+                the identity parent vector (round 1) and a forest of stars;
+                wall time per call, both forms paying the same parent check.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
+                       [--no-ablation] [--ablation-only]
 """
 from __future__ import annotations
 
@@ -145,6 +152,42 @@ def bench_rmat(ctx, pkg, torch, steps, warmup):
                ids_sum=int(ids.to(torch.int64).sum().item()),
                kernels=kt, build_ms=build_ms / steps, rounds_ms=rounds_ms / steps)
     return res
+
+
+def bench_multilinear(ctx, pkg, torch, graphs, reps=10):
+    """All-at-once vs pairwise multilinear kernel, per graph and parent vector."""
+    import numpy as np
+
+    out = {}
+    for label, (n, e, w) in graphs.items():
+        g = pkg.Graph(ctx, n, e, w, wtype=pkg.W_F32)
+        rng = np.random.default_rng(17)
+        roots = rng.choice(n, size=max(1, n // 16), replace=False).astype(np.uint32)
+        star = roots[rng.integers(0, len(roots), n)]
+        star[roots] = roots
+        parents = {"identity": np.arange(n, dtype=np.uint32), "stars_n/16": star}
+        r1 = torch.empty(n, dtype=torch.int64, device="cuda:0")
+        r2 = torch.empty(n, dtype=torch.int64, device="cuda:0")
+        res = {"n": n, "m": len(w)}
+        for pk, p in parents.items():
+            dp = torch.from_numpy(p.view(np.int32)).to("cuda:0")
+            row = {}
+            for form, fn, r in (("all_at_once", ctx.multilinear, r1),
+                                ("pairwise", ctx.multilinear_pairwise, r2)):
+                fn(g, dp, r)  # warm-up (and the pair array's allocation)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(reps):
+                    fn(g, dp, r)
+                torch.cuda.synchronize()
+                row[form + "_ms"] = (time.perf_counter() - t) * 1000.0 / reps
+            row["pairwise_over_all_at_once"] = row["pairwise_ms"] / row["all_at_once_ms"]
+            row["same_r"] = bool(torch.equal(r1, r2))
+            res[pk] = row
+        g.close()
+        out[label] = res
+        log(f"multilinear ablation {label}: {res}")
+    return out
 
 
 def cpu_baseline(n, e, w):
@@ -290,7 +333,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched (10^4 graphs) and served (Poisson stream) legs")
+                    help="skip the batched (10^4 graphs), served (Poisson stream) and "
+                         "multilinear comparison legs")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the all-at-once vs pairwise multilinear comparison")
+    ap.add_argument("--ablation-only", action="store_true",
+                    help="run only the multilinear comparison (prints its JSON alone)")
     ap.add_argument("--served-requests", type=int, default=200,
                     help="requests per arrival rate in the served leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -320,6 +368,15 @@ def main():
         log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
     ctx = pkg.Context(0)
+    if args.ablation_only:
+        import gen
+
+        n17, e17, w17 = gen.rmat(17, 8)
+        n22, e22, w22 = gen.workload_rmat_s22()
+        ab = bench_multilinear(ctx, pkg, torch, {"rmat_s17_e8": (n17, e17, w17),
+                                                 "rmat_s22_e16": (n22, e22, w22)})
+        print(json.dumps({"multilinear_ablation": ab}), flush=True)
+        return
     r = bench_rmat(ctx, pkg, torch, args.steps, args.warmup)
     m = r["m"]
     value = m / (r["ms"] / 1000.0)
@@ -371,6 +428,14 @@ def main():
         at1 = [r for r in sv["rates"] if r["rate_x_plain"] == 1.0]
         if at1:
             line["served_p99_ms_at_plain_rate"] = at1[0]["served_p99_ms"]
+    if not args.no_extras and not args.no_ablation:
+        import gen
+
+        log("multilinear: all-at-once vs pairwise")
+        n17, e17, w17 = gen.rmat(17, 8)
+        line["multilinear_ablation"] = bench_multilinear(
+            ctx, pkg, torch, {"rmat_s17_e8": (n17, e17, w17),
+                              "rmat_s22_e16": (r["n"], r["e"], r["w"])})
     print(json.dumps(line), flush=True)
 
 

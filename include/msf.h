@@ -173,6 +173,18 @@ void msf_graph_destroy(msf_graph *g);
 msf_status msf_multilinear(msf_ctx *ctx, const msf_graph *g, const uint32_t *p, uint64_t *r);
 
 /*
+ * The same r by the pairwise formulation of section 4.1, for comparing the
+ * two: a first pass stores the pair (a_ij, p_j) of every stored entry (the
+ * column parent p_j beside the entry's key: nnz extra writes of 4 bytes), a
+ * second computes f(p_i, (a_ij, p_j)) and the projection from those pairs.
+ * Arguments, result and errors as for msf_multilinear.  The pair array lives
+ * in the context's workspace (grown, never shrunk: 4 bytes per slot of the
+ * graph's padded column array, about 8 bytes per edge).
+ */
+msf_status msf_multilinear_pairwise(msf_ctx *ctx, const msf_graph *g, const uint32_t *p,
+                                    uint64_t *r);
+
+/*
  * Complete shortcutting (section 4.2): p[i] <- the root of i's tree in the
  * parent forest p (p[root] == root).  p is device uint32[n], in/out.
  * sub_iters (host, nullable) receives the number of pointer-jumping passes.

@@ -31,6 +31,7 @@ STATUS_NAMES = {0: "MSF_OK", 1: "MSF_EINVAL", 2: "MSF_ENOMEM", 3: "MSF_EDEVICE",
 EXPORTS = [
     "msf_ctx_create", "msf_ctx_destroy", "msf_last_error", "msf_version", "msf_solve",
     "msf_get_stats", "msf_graph_create", "msf_graph_destroy", "msf_multilinear",
+    "msf_multilinear_pairwise",
     "msf_shortcut", "msf_solve_batched", "msf_server_create", "msf_server_destroy",
     "msf_server_submit", "msf_server_poll", "msf_server_latency", "msf_server_result",
     "msf_request_footprint",
@@ -89,6 +90,8 @@ def lib():
     L.msf_graph_destroy.restype = None
     L.msf_multilinear.argtypes = [P, P, P, P]
     L.msf_multilinear.restype = st
+    L.msf_multilinear_pairwise.argtypes = [P, P, P, P]
+    L.msf_multilinear_pairwise.restype = st
     L.msf_shortcut.argtypes = [P, I32, P, ctypes.POINTER(I32)]
     L.msf_shortcut.restype = st
     L.msf_solve_batched.argtypes = [P, I32, P, P, P, P, ctypes.c_int, ctypes.c_int, P, P, P]
@@ -224,6 +227,12 @@ class Context:
         (bit pattern of uint64 keys).  Stream-ordered."""
         _check(lib().msf_multilinear(self._h, g._h, ctypes.c_void_p(p.data_ptr()),
                                      ctypes.c_void_p(r.data_ptr())))
+
+    def multilinear_pairwise(self, g: "Graph", p, r):
+        """The same r by the pairwise formulation (pairs (a_ij, p_j) stored
+        first, then reduced).  Arguments as for multilinear."""
+        _check(lib().msf_multilinear_pairwise(self._h, g._h, ctypes.c_void_p(p.data_ptr()),
+                                              ctypes.c_void_p(r.data_ptr())))
 
     def shortcut(self, p) -> int:
         """p <- root of each vertex (device int32/uint32 tensor, in place);

@@ -396,6 +396,36 @@ msf_status msf_multilinear(msf_ctx *ctx, const msf_graph *g, const uint32_t *p, 
     return MSF_OK;
 }
 
+msf_status msf_multilinear_pairwise(msf_ctx *ctx, const msf_graph *g, const uint32_t *p,
+                                    uint64_t *r)
+{
+    if (!ctx || !g || g->ctx != ctx) {
+        set_error("bad ctx/graph");
+        return MSF_EINVAL;
+    }
+    const int32_t n = g->a.n;
+    if (n > 0 && (!p || !r)) {
+        set_error("NULL p/r");
+        return MSF_EINVAL;
+    }
+    if (n == 0) return MSF_OK;
+    Ctx *c = &ctx->c;
+    MSF_HIP(hipSetDevice(c->device));
+    // the padded length the graph's column array was allocated with
+    const size_t extent = 2 * (size_t)std::max<int64_t>(g->a.m, 1) + SWEEP_PAD;
+    void *vpj;
+    msf_status rc = ws_get(c, WS_PAIR, 4 * extent, &vpj);
+    if (rc) return rc;
+    launch_fill_u32(c->stream, &c->dcnt->err, 0u, 1);
+    launch_check_parents(c->stream, p, n, c->dcnt);
+    if ((rc = read_counters(c))) return rc;
+    if ((rc = decode_err(c->hcnt->err))) return rc;
+    launch_fill_u64(c->stream, r, KEY_INF, (size_t)n);
+    launch_sweep_pairwise(c->stream, g->a, p, r, (uint32_t *)vpj, extent, c->dcnt);
+    MSF_HIP(hipGetLastError());
+    return MSF_OK;
+}
+
 msf_status msf_shortcut(msf_ctx *ctx, int32_t n, uint32_t *p, int32_t *sub_iters)
 {
     if (!ctx || n < 0 || (n > 0 && !p)) {

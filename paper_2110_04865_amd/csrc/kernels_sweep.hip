@@ -199,12 +199,16 @@ __device__ __attribute__((noinline)) LaneRoots entry_roots_global(const uint32_t
 // slice a row that lies wholly inside one wave has a single writer and is
 // stored without an atomic.
 //
+// PAIR: the second pass of the pairwise formulation; col then holds each
+// stored entry's column parent p_j, written by k_pair_attach, so no parent
+// is gathered.
+//
 // One chunk per workgroup.  Plain sweep: workgroup b serves chunk b / S of
 // slice b % S (workgroups are dealt to the XCDs round-robin, so a slice's
 // parents stay in one XCD's L2).  Compacting sweep: chunks are taken by
 // ticket in increasing order, so every chunk an earlier one waits on in the
 // look-back is held by a running workgroup.
-template <bool COMPACT, bool FIRST>
+template <bool COMPACT, bool FIRST, bool PAIR = false>
 __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
     const uint64_t *__restrict__ key, const uint32_t *__restrict__ chunk_row, SliceInfo sl,
@@ -213,6 +217,7 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     uint32_t *__restrict__ col_out, uint64_t *__restrict__ key_out, uint64_t *status,
     Counters *cnt, uint32_t *__restrict__ wave_live, int read_filter)
 {
+    static_assert(!(PAIR && (COMPACT || FIRST)), "pairs: the plain sweep of a parent vector");
     constexpr int E = SWEEP_E;
     __shared__ uint32_t s_ticket;
     __shared__ uint32_t s_lds[SWEEP_BLOCK / 64 + 1];
@@ -261,10 +266,10 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     }
     // eager variants gather every column parent now, overlapping the
     // window loads; the lazy plain sweep gathers after the row search
-    constexpr bool LAZY = !COMPACT && !FIRST;
+    constexpr bool LAZY = !COMPACT && !FIRST && !PAIR;
     uint32_t pc[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) pc[e] = (FIRST || LAZY) ? 0u : p[cl[e]];
+    for (int e = 0; e < E; ++e) pc[e] = PAIR ? cl[e] : (FIRST || LAZY) ? 0u : p[cl[e]];
 
     // 2. stage the window
     if (win) {
@@ -554,6 +559,62 @@ void launch_sweep_compact(hipStream_t s, const Adj &a, const uint32_t *p, uint64
     if (g > 8192) g = 8192;
     k_rowptr_compact<<<(unsigned)g, 256, 0, s>>>(a.row_ptr, a.n, a.sl, wpre, mask, dcnt,
                                                  row_ptr_out);
+}
+
+// First pass of the pairwise formulation (section 4.1): the pair
+// (a_ij, p_j) of every stored entry, kept as p_j beside the entry's key.
+// Covers the whole padded extent of the column array; slots outside the
+// stored entries hold no column, so the gather index is clamped (their
+// values are never used).
+// Four entries per 16-byte load and store, two groups per thread and step
+// (eight gathers in flight); the last extent % 4 entries one by one.
+__device__ __forceinline__ u32x4 pair_gather(u32x4 c, const uint32_t *__restrict__ p, uint32_t n)
+{
+    u32x4 o;
+    o.x = p[c.x < n ? c.x : 0u];
+    o.y = p[c.y < n ? c.y : 0u];
+    o.z = p[c.z < n ? c.z : 0u];
+    o.w = p[c.w < n ? c.w : 0u];
+    return o;
+}
+
+__global__ __launch_bounds__(256) void k_pair_attach(const uint32_t *__restrict__ col,
+                                                     size_t extent, int32_t n,
+                                                     const uint32_t *__restrict__ p,
+                                                     uint32_t *__restrict__ pj)
+{
+    const size_t nv = extent / 4;
+    const u32x4 *__restrict__ c4 = reinterpret_cast<const u32x4 *>(col);
+    u32x4 *__restrict__ o4 = reinterpret_cast<u32x4 *>(pj);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (size_t v = t0; v < nv; v += 2 * stride) {
+        const size_t v1 = v + stride < nv ? v + stride : v;
+        const u32x4 a = __builtin_nontemporal_load(c4 + v);
+        const u32x4 b = __builtin_nontemporal_load(c4 + v1);
+        const u32x4 oa = pair_gather(a, p, (uint32_t)n);
+        const u32x4 ob = pair_gather(b, p, (uint32_t)n);
+        o4[v] = oa;
+        if (v + stride < nv) o4[v1] = ob;
+    }
+    for (size_t t = nv * 4 + t0; t < extent; t += stride) {
+        const uint32_t j = col[t];
+        pj[t] = p[j < (uint32_t)n ? j : 0u];
+    }
+}
+
+void launch_sweep_pairwise(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
+                           uint32_t *pj, size_t extent, Counters *dcnt)
+{
+    if (a.nnz == 0) return;
+    size_t g = (extent / 8 + 255) / 256;  // one thread per two groups of four
+    if (g < 1) g = 1;
+    if (g > 16384) g = 16384;
+    k_pair_attach<<<(unsigned)g, 256, 0, s>>>(a.col, extent, a.n, p, pj);
+    const unsigned grid = a.sl.maxch * (unsigned)a.sl.S;
+    k_sweep<false, false, true><<<grid, SWEEP_BLOCK, 0, s>>>(
+        a.row_ptr, pj, a.key, a.chunk_row, a.sl, a.n, p, r, nullptr, nullptr, nullptr, nullptr,
+        nullptr, dcnt, nullptr, 0);
 }
 
 size_t chunk_info_words(uint32_t nchunks) { return 2 * (size_t)nchunks * (SWEEP_CHUNK / 32); }

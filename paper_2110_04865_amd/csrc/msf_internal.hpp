@@ -97,7 +97,7 @@ enum Slot {
     WS_BATCH0, WS_BATCH1, WS_BATCH2, WS_BATCH3,
     WS_BH, WS_BHOFF, WS_BRLO, WS_BCOL, WS_BKEY, WS_CHUNKINFO,
     WS_TL1, WS_TL2, WS_TLSUB, WS_TLORDER, WS_TLPLAN, WS_T2, WS_T2OFF, WS_FSTART,
-    WS_RUNCHUNK, WS_RUNROW, WS_RUNS,
+    WS_RUNCHUNK, WS_RUNROW, WS_RUNS, WS_PAIR,
     WS_COUNT
 };
 
@@ -312,6 +312,11 @@ void launch_zero_lookback(hipStream_t s, uint64_t *status, uint32_t tiles, uint3
 // (needed when many runs share a root); otherwise atomics go straight out.
 void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r, Counters *dcnt,
                   bool first = false, uint32_t *wave_live = nullptr, bool read_filter = true);
+// The same minima by the pairwise formulation: k_pair_attach writes every
+// stored entry's column parent to pj (extent entries: the padded length of
+// a.col), then the sweep reads those instead of gathering.
+void launch_sweep_pairwise(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r,
+                           uint32_t *pj, size_t extent, Counters *dcnt);
 // Sweep that also writes the surviving entries (p_i != p_j) in order to
 // col_out/key_out and their row pointers to row_ptr_out; chunk_info holds
 // chunk_info_words(a.nchunks) u32 of per-chunk survivor masks and prefixes.

@@ -298,6 +298,11 @@ def multilinear_case(ctx, pkg, n, e, w, wt, p, label):
     got = dr.cpu().numpy()[:n].view(np.uint64)
     want = oracle.multilinear(n, e, w, wt, p)
     assert np.array_equal(got, want), label
+    # the pairwise formulation (pairs stored, then reduced) gives the same r
+    dr2 = torch.empty(max(n, 1), dtype=torch.int64, device="cuda:0")
+    ctx.multilinear_pairwise(g, dp, dr2)
+    torch.cuda.synchronize()
+    assert np.array_equal(dr2.cpu().numpy()[:n].view(np.uint64), want), label + " pairwise"
     g.close()
 
 
@@ -329,6 +334,8 @@ def test_multilinear_rejects_bad_parent(ctx, pkg):
     dr = torch.zeros(n, dtype=torch.int64, device="cuda:0")
     with pytest.raises(pkg.MSFError):
         ctx.multilinear(g, dev(p), dr)
+    with pytest.raises(pkg.MSFError):
+        ctx.multilinear_pairwise(g, dev(p), dr)
     torch.cuda.synchronize()
     assert (dr.cpu().numpy() == 0).all()
     g.close()
@@ -472,6 +479,16 @@ def test_column_slices_are_result_invariant(pkg):
                     c.multilinear(g, dev(np.arange(n, dtype=np.uint32)), dr)
                     torch.cuda.synchronize()
                     assert np.array_equal(dr.cpu().numpy().view(np.uint64), ref), label
+                    # pairwise, with a parent vector of stars
+                    rng = np.random.default_rng(int(slices))
+                    roots = rng.choice(n, size=max(1, n // 20), replace=False).astype(np.uint32)
+                    star = roots[rng.integers(0, len(roots), n)]
+                    star[roots] = roots
+                    dr.fill_(0)
+                    c.multilinear_pairwise(g, dev(star), dr)
+                    torch.cuda.synchronize()
+                    assert np.array_equal(dr.cpu().numpy().view(np.uint64),
+                                          oracle.multilinear(n, e, w, wt, star)), label + " pair"
                     g.close()
                 c.close()
     finally:
