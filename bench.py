@@ -31,10 +31,15 @@ Also reported on the same JSON line:
                 formulation (pairs (a_ij, p_j) stored first, then reduced) on
                 R-MAT scale 17 edge factor 8 and on the scale-22 graph, for
                 the identity parent vector (round 1) and a forest of stars;
-                wall time per call, both forms paying the same parent check.
+                wall time per call, both forms paying the same parent check;
+  shortcut_study
+                complete shortcutting by full passes, by the frontier and by a
+                switch between them, on the parent forest of round 1's hooks
+                on the 256^3 grid and on a random recursive tree of the same
+                size: wall time per call and passes.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
-                       [--no-ablation] [--ablation-only]
+                       [--no-ablation] [--ablation-only] [--shortcut-only]
 """
 from __future__ import annotations
 
@@ -190,6 +195,68 @@ def bench_multilinear(ctx, pkg, torch, graphs, reps=10):
     return out
 
 
+def round1_forest(ctx, pkg, torch, n, e, w, wtype):
+    """Parent forest after round 1's hooks and tie break: every vertex hooks
+    to the other end of its minimum-key edge; of a mutual pair the smaller id
+    stays root.  Minima from msf_multilinear with the identity; the rest on
+    the host."""
+    import numpy as np
+
+    g = pkg.Graph(ctx, n, e, w, wtype=wtype)
+    r = torch.empty(n, dtype=torch.int64, device="cuda:0")
+    ctx.multilinear(g, torch.arange(n, dtype=torch.int32, device="cuda:0"), r)
+    torch.cuda.synchronize()
+    g.close()
+    key = r.cpu().numpy().view(np.uint64)
+    ids = np.arange(n, dtype=np.int64)
+    has = key != np.uint64(0xFFFFFFFFFFFFFFFF)
+    eid = (key & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    a = np.where(has, e[np.where(has, eid, 0), 0], ids)
+    b = np.where(has, e[np.where(has, eid, 0), 1], ids)
+    h = np.where(a == ids, b, a).astype(np.int64)
+    mutual = (h[h] == ids) & (ids < h)
+    h[mutual] = ids[mutual]
+    return h.astype(np.uint32)
+
+
+def bench_shortcut(ctx, pkg, torch, reps=5):
+    """Shortcut strategies on round 1's forest of the 256^3 grid and on a
+    random recursive tree of the same size."""
+    import numpy as np
+    import gen
+
+    n, e, w = gen.workload_grid_256()
+    forests = {"grid256_round1": round1_forest(ctx, pkg, torch, n, e, w, pkg.W_U32)}
+    rng = np.random.default_rng(23)
+    par = (rng.random(n) * np.arange(n)).astype(np.int64)  # parent uniform below
+    perm = rng.permutation(n)
+    rrt = np.empty(n, dtype=np.uint32)
+    rrt[perm] = perm[par]
+    forests["random_recursive_tree"] = rrt
+    strategies = [("frontier", pkg.SHORTCUT_FRONTIER, 0.0), ("full", pkg.SHORTCUT_FULL, 0.0),
+                  ("switch_0.25", pkg.SHORTCUT_SWITCH, 0.25),
+                  ("switch_0.05", pkg.SHORTCUT_SWITCH, 0.05)]
+    out = {}
+    for fname, p in forests.items():
+        src = torch.from_numpy(p.view(np.int32)).to("cuda:0")
+        dp = torch.empty_like(src)
+        res = {"n": n, "non_roots": int((p != np.arange(n)).sum())}
+        for sname, st, frac in strategies:
+            dp.copy_(src)
+            ctx.shortcut_strategy(dp, st, frac)  # warm-up (workspace)
+            total = 0.0
+            for _ in range(reps):
+                dp.copy_(src)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                passes = ctx.shortcut_strategy(dp, st, frac)
+                total += time.perf_counter() - t
+            res[sname] = {"ms": total * 1000.0 / reps, "passes": passes}
+        out[fname] = res
+        log(f"shortcut study {fname}: {res}")
+    return out
+
+
 def cpu_baseline(n, e, w):
     import oracle
 
@@ -339,6 +406,8 @@ def main():
                     help="skip the all-at-once vs pairwise multilinear comparison")
     ap.add_argument("--ablation-only", action="store_true",
                     help="run only the multilinear comparison (prints its JSON alone)")
+    ap.add_argument("--shortcut-only", action="store_true",
+                    help="run only the shortcut-strategy study (prints its JSON alone)")
     ap.add_argument("--served-requests", type=int, default=200,
                     help="requests per arrival rate in the served leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -376,6 +445,9 @@ def main():
         ab = bench_multilinear(ctx, pkg, torch, {"rmat_s17_e8": (n17, e17, w17),
                                                  "rmat_s22_e16": (n22, e22, w22)})
         print(json.dumps({"multilinear_ablation": ab}), flush=True)
+        return
+    if args.shortcut_only:
+        print(json.dumps({"shortcut_study": bench_shortcut(ctx, pkg, torch)}), flush=True)
         return
     r = bench_rmat(ctx, pkg, torch, args.steps, args.warmup)
     m = r["m"]
@@ -436,6 +508,8 @@ def main():
         line["multilinear_ablation"] = bench_multilinear(
             ctx, pkg, torch, {"rmat_s17_e8": (n17, e17, w17),
                               "rmat_s22_e16": (r["n"], r["e"], r["w"])})
+        log("shortcut strategies on the 256^3 grid")
+        line["shortcut_study"] = bench_shortcut(ctx, pkg, torch)
     print(json.dumps(line), flush=True)
 
 

@@ -194,6 +194,28 @@ msf_status msf_multilinear_pairwise(msf_ctx *ctx, const msf_graph *g, const uint
 msf_status msf_shortcut(msf_ctx *ctx, int32_t n, uint32_t *p, int32_t *sub_iters);
 
 /*
+ * Complete shortcutting by a chosen strategy, for the shortcut study of
+ * section 7.1 in single-device form.  A pass (a sub-iteration of section 7.1)
+ * moves each taking part vertex to its grandparent:
+ *   MSF_SHORTCUT_FRONTIER  only vertices whose parent is not yet a root take
+ *                          part (the counterpart of CSP, which shortcuts only
+ *                          the data it gathered once); msf_shortcut does this;
+ *   MSF_SHORTCUT_FULL      every vertex takes part in every pass (the
+ *                          baseline: each vertex queries its parent in every
+ *                          sub-iteration);
+ *   MSF_SHORTCUT_SWITCH    full passes until at most switch_fraction * n
+ *                          vertices are unfinished, then the frontier (OS,
+ *                          with its threshold taken per pass instead of per
+ *                          iteration).
+ * switch_fraction (in [0, 1]) is read by MSF_SHORTCUT_SWITCH only.  Result,
+ * sub_iters (passes of either kind) and errors as for msf_shortcut;
+ * MSF_EINVAL for an unknown strategy or a fraction outside [0, 1].
+ */
+enum { MSF_SHORTCUT_FRONTIER = 0, MSF_SHORTCUT_FULL = 1, MSF_SHORTCUT_SWITCH = 2 };
+msf_status msf_shortcut_strategy(msf_ctx *ctx, int32_t n, uint32_t *p, int32_t strategy,
+                                 double switch_fraction, int32_t *sub_iters);
+
+/*
  * Minimum spanning forests of G independent graphs in one batched solve.
  * Graph g has vtx_off[g+1]-vtx_off[g] vertices and edge_off[g+1]-edge_off[g]
  * edges stored from edges[2*edge_off[g]] (local vertex ids) and

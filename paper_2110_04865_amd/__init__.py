@@ -25,13 +25,15 @@ W_U32 = 0
 W_F32 = 1
 MEM_HOST = 0
 MEM_DEVICE = 1
+# shortcut strategies (msf_shortcut_strategy)
+SHORTCUT_FRONTIER, SHORTCUT_FULL, SHORTCUT_SWITCH = 0, 1, 2
 STATUS_NAMES = {0: "MSF_OK", 1: "MSF_EINVAL", 2: "MSF_ENOMEM", 3: "MSF_EDEVICE",
                 4: "MSF_EBUDGET", 5: "MSF_ENOTFOUND"}
 
 EXPORTS = [
     "msf_ctx_create", "msf_ctx_destroy", "msf_last_error", "msf_version", "msf_solve",
     "msf_get_stats", "msf_graph_create", "msf_graph_destroy", "msf_multilinear",
-    "msf_multilinear_pairwise",
+    "msf_multilinear_pairwise", "msf_shortcut_strategy",
     "msf_shortcut", "msf_solve_batched", "msf_server_create", "msf_server_destroy",
     "msf_server_submit", "msf_server_poll", "msf_server_latency", "msf_server_result",
     "msf_request_footprint",
@@ -94,6 +96,8 @@ def lib():
     L.msf_multilinear_pairwise.restype = st
     L.msf_shortcut.argtypes = [P, I32, P, ctypes.POINTER(I32)]
     L.msf_shortcut.restype = st
+    L.msf_shortcut_strategy.argtypes = [P, I32, P, I32, ctypes.c_double, ctypes.POINTER(I32)]
+    L.msf_shortcut_strategy.restype = st
     L.msf_solve_batched.argtypes = [P, I32, P, P, P, P, ctypes.c_int, ctypes.c_int, P, P, P]
     L.msf_solve_batched.restype = st
     L.msf_server_create.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(P)]
@@ -233,6 +237,14 @@ class Context:
         first, then reduced).  Arguments as for multilinear."""
         _check(lib().msf_multilinear_pairwise(self._h, g._h, ctypes.c_void_p(p.data_ptr()),
                                               ctypes.c_void_p(r.data_ptr())))
+
+    def shortcut_strategy(self, p, strategy: int, switch_fraction: float = 0.0) -> int:
+        """shortcut() by a chosen strategy (SHORTCUT_FRONTIER / _FULL / _SWITCH);
+        returns the number of passes."""
+        it = ctypes.c_int32()
+        _check(lib().msf_shortcut_strategy(self._h, p.numel(), ctypes.c_void_p(p.data_ptr()),
+                                           strategy, switch_fraction, ctypes.byref(it)))
+        return it.value
 
     def shortcut(self, p) -> int:
         """p <- root of each vertex (device int32/uint32 tensor, in place);

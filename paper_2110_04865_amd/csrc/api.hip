@@ -428,8 +428,23 @@ msf_status msf_multilinear_pairwise(msf_ctx *ctx, const msf_graph *g, const uint
 
 msf_status msf_shortcut(msf_ctx *ctx, int32_t n, uint32_t *p, int32_t *sub_iters)
 {
+    return msf_shortcut_strategy(ctx, n, p, MSF_SHORTCUT_FRONTIER, 0.0, sub_iters);
+}
+
+msf_status msf_shortcut_strategy(msf_ctx *ctx, int32_t n, uint32_t *p, int32_t strategy,
+                                 double switch_fraction, int32_t *sub_iters)
+{
     if (!ctx || n < 0 || (n > 0 && !p)) {
         set_error("bad arguments");
+        return MSF_EINVAL;
+    }
+    if (strategy != MSF_SHORTCUT_FRONTIER && strategy != MSF_SHORTCUT_FULL &&
+        strategy != MSF_SHORTCUT_SWITCH) {
+        set_error("unknown shortcut strategy");
+        return MSF_EINVAL;
+    }
+    if (!(switch_fraction >= 0.0 && switch_fraction <= 1.0)) {
+        set_error("switch_fraction outside [0, 1]");
         return MSF_EINVAL;
     }
     if (n == 0) {
@@ -452,12 +467,31 @@ msf_status msf_shortcut(msf_ctx *ctx, int32_t n, uint32_t *p, int32_t *sub_iters
     if ((rc = read_counters(c))) return rc;
     if ((rc = decode_err(c->hcnt->err))) return rc;
     MSF_HIP(hipMemcpyAsync(q, p, 4 * (size_t)n, hipMemcpyDeviceToDevice, s));
-    launch_jump_init(s, q, n, F[0], status, c->dcnt);
-    if ((rc = read_counters(c))) return rc;
-    uint32_t nF = c->hcnt->nF;
+    // every pass at least halves each vertex's distance to its root, whatever
+    // the kind of pass, so both kinds share one bound
     int cap = 2;
     while ((1ll << (cap - 1)) < (long long)n) ++cap;  // ceil(log2 n) + 1
     int passes = 0, fi = 0;
+    bool done = false;
+    if (strategy != MSF_SHORTCUT_FRONTIER) {
+        // full passes while more than `limit` vertices are unfinished
+        const double limit = strategy == MSF_SHORTCUT_FULL ? 0.0 : switch_fraction * (double)n;
+        while (passes < cap) {
+            launch_fill_u32(s, &c->dcnt->nR, 0u, 1);
+            launch_jump_full(s, q, n, c->dcnt);
+            if ((rc = read_counters(c))) return rc;
+            ++passes;
+            const uint32_t left = c->hcnt->nR;
+            done = left == 0;
+            if (done || (double)left <= limit) break;
+        }
+    }
+    uint32_t nF = 0;
+    if (!done && strategy != MSF_SHORTCUT_FULL) {
+        launch_jump_init(s, q, n, F[0], status, c->dcnt);
+        if ((rc = read_counters(c))) return rc;
+        nF = c->hcnt->nF;
+    }
     while (nF > 0 && passes < cap) {
         launch_fill_u32(s, &c->dcnt->nR, 0u, 1);
         launch_jump_pass(s, F[fi], nF, q, F[fi ^ 1], status, c->dcnt);

@@ -763,6 +763,35 @@ void launch_jump_pass(hipStream_t s, const uint32_t *Fin, uint32_t nF, uint32_t 
     k_jump_pass<<<tiles, CT_NT, 0, s>>>(Fin, nF, q, Fout, status, dcnt);
 }
 
+// One full pass of pointer jumping: every vertex takes q[i] <- q[q[i]] in
+// place (the baseline of the shortcut study, section 7.1); vertices whose
+// new parent is still not a root are counted into cnt->nR, one atomic per
+// workgroup.  In-place jumps only move a pointer up its own tree, so any
+// interleaving of the relaxed loads and stores gets at least as far as a
+// synchronous pass.
+__global__ __launch_bounds__(256) void k_jump_full(uint32_t *q, int32_t n, Counters *cnt)
+{
+    __shared__ uint64_t s_lds[256 / 64 + 1];
+    uint64_t c = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t x = load_relaxed_u32(q + i);
+        const uint32_t y = load_relaxed_u32(q + x);
+        if (y != x) store_relaxed_u32(q + i, y);
+        if (load_relaxed_u32(q + y) != y) ++c;
+    }
+    c = block_sum<256>(c, s_lds);
+    if (threadIdx.x == 0 && c) atomicAdd(&cnt->nR, (uint32_t)c);
+}
+
+void launch_jump_full(hipStream_t s, uint32_t *q, int32_t n, Counters *dcnt)
+{
+    if (n <= 0) return;
+    size_t g = ((size_t)n + 255) / 256;
+    if (g > 8192) g = 8192;
+    k_jump_full<<<(unsigned)g, 256, 0, s>>>(q, n, dcnt);
+}
+
 __global__ void k_check_roots(const uint32_t *__restrict__ p, const uint32_t *__restrict__ q,
                               int32_t n, Counters *cnt)
 {

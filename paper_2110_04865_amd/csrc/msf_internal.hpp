@@ -381,6 +381,9 @@ void launch_jump_pass(hipStream_t s, const uint32_t *Fin, uint32_t nF, uint32_t 
                       uint32_t *Fout, uint64_t *status, Counters *dcnt);
 void launch_check_roots(hipStream_t s, const uint32_t *p, const uint32_t *q, int32_t n,
                         Counters *dcnt);
+// One full pointer-jumping pass over all n vertices; adds the vertices left
+// unfinished into dcnt->nR.
+void launch_jump_full(hipStream_t s, uint32_t *q, int32_t n, Counters *dcnt);
 
 void zero_counters(Ctx *c);
 msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc);

@@ -58,6 +58,8 @@ def test_null_arguments_are_rejected_without_device():
     assert b"ctx" in L.msf_last_error()
     rc = L.msf_shortcut(None, 3, None, None)
     assert rc == 1
+    rc = L.msf_shortcut_strategy(None, 3, None, pkg.SHORTCUT_FULL, 0.0, None)
+    assert rc == 1
 
 
 @pytest.mark.skipif(os.path.exists("/dev/kfd") and os.access("/dev/kfd", os.R_OK),

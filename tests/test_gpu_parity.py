@@ -382,6 +382,52 @@ def test_shortcut_rejects_cycles(ctx, pkg):
         assert np.array_equal(dp.cpu().numpy().view(np.uint32), p)  # untouched
 
 
+def test_shortcut_strategies_match_find_roots(ctx, pkg):
+    """Full passes, the frontier and the switch between them give the same roots."""
+    rng = np.random.default_rng(5)
+    cases = []
+    for n in (1, 2, 1000, 65537, 1 << 20):
+        par = np.minimum(np.arange(n), rng.integers(0, n, n)).astype(np.uint32)
+        perm = rng.permutation(n).astype(np.uint32)
+        inv = np.empty_like(perm)
+        inv[perm] = np.arange(n, dtype=np.uint32)
+        cases.append((f"random forest n={n}", perm[par[inv]]))
+    n = 1 << 18
+    p = np.arange(n, dtype=np.uint32)
+    order = rng.permutation(n)
+    p[order[1:]] = order[:-1]
+    cases.append(("chain", p))
+    strategies = [("frontier", pkg.SHORTCUT_FRONTIER, 0.0), ("full", pkg.SHORTCUT_FULL, 0.0),
+                  ("switch 0", pkg.SHORTCUT_SWITCH, 0.0),
+                  ("switch .25", pkg.SHORTCUT_SWITCH, 0.25),
+                  ("switch 1", pkg.SHORTCUT_SWITCH, 1.0)]
+    for label, p in cases:
+        want = oracle.find_roots(p)
+        cap = max(1, math.ceil(math.log2(max(len(p), 2)))) + 1
+        for sname, st, frac in strategies:
+            say("shortcut strategy", sname, label)
+            dp = dev(p)
+            passes = ctx.shortcut_strategy(dp, st, frac)
+            torch.cuda.synchronize()
+            assert np.array_equal(dp.cpu().numpy().view(np.uint32), want), (sname, label)
+            assert passes <= cap, (sname, label, passes)
+    for bad in ([1, 0, 2], [1, 2, 0, 3], [0, 2, 3, 1, 4, 4]):
+        p = np.array(bad, np.uint32)
+        for sname, st, frac in strategies:
+            say("shortcut strategy cycle", sname, bad)
+            dp = dev(p)
+            with pytest.raises(pkg.MSFError):
+                ctx.shortcut_strategy(dp, st, frac)
+            torch.cuda.synchronize()
+            assert np.array_equal(dp.cpu().numpy().view(np.uint32), p)
+    dp = dev(np.array([0, 0, 1], np.uint32))
+    for st, frac in ((7, 0.0), (pkg.SHORTCUT_SWITCH, 1.5), (pkg.SHORTCUT_SWITCH, float("nan"))):
+        with pytest.raises(pkg.MSFError):
+            ctx.shortcut_strategy(dp, st, frac)
+    torch.cuda.synchronize()
+    assert np.array_equal(dp.cpu().numpy().view(np.uint32), [0, 0, 1])
+
+
 # --------------------------------------------------------------- batched --
 
 def test_batched_equals_oracle_per_graph(ctx, pkg):
