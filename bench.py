@@ -36,10 +36,14 @@ Also reported on the same JSON line:
                 complete shortcutting by full passes, by the frontier and by a
                 switch between them, on the parent forest of round 1's hooks
                 on the 256^3 grid and on a random recursive tree of the same
-                size: wall time per call and passes.
+                size: wall time per call and passes;
+  components    connected components by the connectivity variant on the
+                same kernels, on R-MAT scale 22 and the 256^3 grid: wall time
+                per call (from a built graph) and rounds.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
                        [--no-ablation] [--ablation-only] [--shortcut-only]
+                       [--components-only]
 """
 from __future__ import annotations
 
@@ -257,6 +261,26 @@ def bench_shortcut(ctx, pkg, torch, reps=5):
     return out
 
 
+def bench_components(ctx, pkg, torch, graphs, reps=3):
+    """msf_components on built graphs: wall time per call and rounds."""
+    out = {}
+    for label, (n, e, w, wt) in graphs.items():
+        g = pkg.Graph(ctx, n, e, w, wtype=wt)
+        lab = torch.empty(n, dtype=torch.int32, device="cuda:0")
+        rounds = ctx.components(g, lab)  # warm-up (workspace)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            rounds = ctx.components(g, lab)
+        ms = (time.perf_counter() - t) * 1000.0 / reps
+        ncomp = int(torch.unique(lab).numel())
+        g.close()
+        out[label] = {"n": n, "m": len(w), "ms": ms, "rounds": rounds, "components": ncomp,
+                      "edges_per_s": len(w) / (ms / 1000.0)}
+        log(f"components {label}: {out[label]}")
+    return out
+
+
 def cpu_baseline(n, e, w):
     import oracle
 
@@ -408,6 +432,8 @@ def main():
                     help="run only the multilinear comparison (prints its JSON alone)")
     ap.add_argument("--shortcut-only", action="store_true",
                     help="run only the shortcut-strategy study (prints its JSON alone)")
+    ap.add_argument("--components-only", action="store_true",
+                    help="run only the connected-components leg (prints its JSON alone)")
     ap.add_argument("--served-requests", type=int, default=200,
                     help="requests per arrival rate in the served leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -445,6 +471,15 @@ def main():
         ab = bench_multilinear(ctx, pkg, torch, {"rmat_s17_e8": (n17, e17, w17),
                                                  "rmat_s22_e16": (n22, e22, w22)})
         print(json.dumps({"multilinear_ablation": ab}), flush=True)
+        return
+    if args.components_only:
+        import gen
+
+        n22, e22, w22 = gen.workload_rmat_s22()
+        ng, eg, wg = gen.workload_grid_256()
+        print(json.dumps({"components": bench_components(
+            ctx, pkg, torch, {"rmat_s22_e16": (n22, e22, w22, pkg.W_F32),
+                              "grid256": (ng, eg, wg, pkg.W_U32)})}), flush=True)
         return
     if args.shortcut_only:
         print(json.dumps({"shortcut_study": bench_shortcut(ctx, pkg, torch)}), flush=True)
@@ -510,6 +545,11 @@ def main():
                               "rmat_s22_e16": (r["n"], r["e"], r["w"])})
         log("shortcut strategies on the 256^3 grid")
         line["shortcut_study"] = bench_shortcut(ctx, pkg, torch)
+        log("connected components")
+        ng, eg, wg = gen.workload_grid_256()
+        line["components"] = bench_components(
+            ctx, pkg, torch, {"rmat_s22_e16": (r["n"], r["e"], r["w"], pkg.W_F32),
+                              "grid256": (ng, eg, wg, pkg.W_U32)})
     print(json.dumps(line), flush=True)
 
 

@@ -216,6 +216,21 @@ msf_status msf_shortcut_strategy(msf_ctx *ctx, int32_t n, uint32_t *p, int32_t s
                                  double switch_fraction, int32_t *sub_iters);
 
 /*
+ * Connected components by the same rounds, in the connectivity variant of
+ * the Awerbuch-Shiloach algorithm (section 2.4): each star root hooks along
+ * an edge leaving its star (here the minimum-key one, from the multilinear
+ * kernel), the smaller of two roots that hooked onto each other stays root,
+ * and full pointer-jumping passes make every tree a star again.
+ *   labels  device uint32[n] out: labels[i] == labels[j] iff i and j are
+ *           connected; each label is a vertex of its component (the root
+ *           its tree ended at, not necessarily the smallest id)
+ *   rounds  (host, nullable) receives the number of hooking rounds
+ * Ordered on the context's stream; returns after synchronising.  Uses the
+ * context's workspace (12 bytes per vertex).
+ */
+msf_status msf_components(msf_ctx *ctx, const msf_graph *g, uint32_t *labels, int32_t *rounds);
+
+/*
  * Minimum spanning forests of G independent graphs in one batched solve.
  * Graph g has vtx_off[g+1]-vtx_off[g] vertices and edge_off[g+1]-edge_off[g]
  * edges stored from edges[2*edge_off[g]] (local vertex ids) and

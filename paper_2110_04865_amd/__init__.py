@@ -33,7 +33,7 @@ STATUS_NAMES = {0: "MSF_OK", 1: "MSF_EINVAL", 2: "MSF_ENOMEM", 3: "MSF_EDEVICE",
 EXPORTS = [
     "msf_ctx_create", "msf_ctx_destroy", "msf_last_error", "msf_version", "msf_solve",
     "msf_get_stats", "msf_graph_create", "msf_graph_destroy", "msf_multilinear",
-    "msf_multilinear_pairwise", "msf_shortcut_strategy",
+    "msf_multilinear_pairwise", "msf_shortcut_strategy", "msf_components",
     "msf_shortcut", "msf_solve_batched", "msf_server_create", "msf_server_destroy",
     "msf_server_submit", "msf_server_poll", "msf_server_latency", "msf_server_result",
     "msf_request_footprint",
@@ -98,6 +98,8 @@ def lib():
     L.msf_shortcut.restype = st
     L.msf_shortcut_strategy.argtypes = [P, I32, P, I32, ctypes.c_double, ctypes.POINTER(I32)]
     L.msf_shortcut_strategy.restype = st
+    L.msf_components.argtypes = [P, P, P, ctypes.POINTER(I32)]
+    L.msf_components.restype = st
     L.msf_solve_batched.argtypes = [P, I32, P, P, P, P, ctypes.c_int, ctypes.c_int, P, P, P]
     L.msf_solve_batched.restype = st
     L.msf_server_create.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(P)]
@@ -244,6 +246,14 @@ class Context:
         it = ctypes.c_int32()
         _check(lib().msf_shortcut_strategy(self._h, p.numel(), ctypes.c_void_p(p.data_ptr()),
                                            strategy, switch_fraction, ctypes.byref(it)))
+        return it.value
+
+    def components(self, g: "Graph", labels) -> int:
+        """Connected-component labels of g into a device int32/uint32 tensor
+        [n] (equal labels iff connected); returns the number of rounds."""
+        it = ctypes.c_int32()
+        _check(lib().msf_components(self._h, g._h, ctypes.c_void_p(labels.data_ptr()),
+                                    ctypes.byref(it)))
         return it.value
 
     def shortcut(self, p) -> int:

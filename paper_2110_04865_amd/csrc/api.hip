@@ -509,6 +509,66 @@ msf_status msf_shortcut_strategy(msf_ctx *ctx, int32_t n, uint32_t *p, int32_t s
     return MSF_OK;
 }
 
+msf_status msf_components(msf_ctx *ctx, const msf_graph *g, uint32_t *labels, int32_t *rounds)
+{
+    if (!ctx || !g || g->ctx != ctx) {
+        set_error("bad ctx/graph");
+        return MSF_EINVAL;
+    }
+    const int32_t n = g->a.n;
+    if (n > 0 && !labels) {
+        set_error("NULL labels");
+        return MSF_EINVAL;
+    }
+    if (n == 0) {
+        if (rounds) *rounds = 0;
+        return MSF_OK;
+    }
+    Ctx *c = &ctx->c;
+    MSF_HIP(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    void *vr, *vh;
+    msf_status rc;
+    if ((rc = ws_get(c, WS_R, 8 * (size_t)n, &vr)) || (rc = ws_get(c, WS_H, 4 * (size_t)n, &vh)))
+        return rc;
+    uint64_t *r = (uint64_t *)vr;
+    uint32_t *h = (uint32_t *)vh, *p = labels;
+    zero_counters(c);
+    launch_iota_u32(s, p, (size_t)n);
+    // the number of stars at least halves in a round that hooks, and each
+    // pointer-jumping pass halves every distance to a root
+    int cap = 2;
+    while ((1ll << (cap - 1)) < (long long)n) ++cap;  // ceil(log2 n) + 1
+    int done_rounds = 0;
+    for (;;) {
+        launch_fill_u64(s, r, KEY_INF, (size_t)n);
+        launch_sweep(s, g->a, p, r, c->dcnt);
+        launch_fill_u32(s, &c->dcnt->nR, 0u, 1);
+        launch_cc_hook(s, p, r, g->a.edges, n, h, c->dcnt);
+        if ((rc = read_counters(c))) return rc;
+        if (c->hcnt->nR == 0) break;
+        if (done_rounds >= cap) {
+            set_error("components: no convergence");
+            return MSF_EDEVICE;
+        }
+        launch_cc_apply(s, h, n, p);
+        for (int pass = 0;; ++pass) {
+            if (pass > cap) {
+                set_error("components: shortcut did not converge");
+                return MSF_EDEVICE;
+            }
+            launch_fill_u32(s, &c->dcnt->nR, 0u, 1);
+            launch_jump_full(s, p, n, c->dcnt);
+            if ((rc = read_counters(c))) return rc;
+            if (c->hcnt->nR == 0) break;
+        }
+        ++done_rounds;
+    }
+    MSF_HIP(hipStreamSynchronize(s));
+    if (rounds) *rounds = done_rounds;
+    return MSF_OK;
+}
+
 size_t msf_request_footprint(int32_t n, int64_t m)
 {
     // per edge: input copy (12), bucketed build staging (28), adjacency and

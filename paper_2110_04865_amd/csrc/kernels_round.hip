@@ -792,6 +792,63 @@ void launch_jump_full(hipStream_t s, uint32_t *q, int32_t n, Counters *dcnt)
     k_jump_full<<<(unsigned)g, 256, 0, s>>>(q, n, dcnt);
 }
 
+// Connected components by the same rounds (the connectivity variant of
+// section 2.4: a star root hooks along any edge leaving its star; the
+// minimum-key one found by the sweep is such an edge).  p is a star forest,
+// so r[k] is set only for roots.  Hooked roots are counted into cnt->nR,
+// one atomic per workgroup.
+__global__ __launch_bounds__(256) void k_cc_hook(const uint32_t *__restrict__ p,
+                                                 const uint64_t *__restrict__ r,
+                                                 const int32_t *__restrict__ edges, int32_t n,
+                                                 uint32_t *__restrict__ h, Counters *cnt)
+{
+    __shared__ uint64_t s_lds[256 / 64 + 1];
+    uint64_t c = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        uint32_t t = (uint32_t)k;
+        const uint64_t rk = r[k];
+        if (rk != KEY_INF && p[k] == (uint32_t)k) {
+            // one endpoint lies in k's star, the other outside it
+            const size_t e = (size_t)(uint32_t)rk;
+            const uint32_t a = p[edges[2 * e]], b = p[edges[2 * e + 1]];
+            t = a == (uint32_t)k ? b : a;
+            ++c;
+        }
+        h[k] = t;
+    }
+    c = block_sum<256>(c, s_lds);
+    if (threadIdx.x == 0 && c) atomicAdd(&cnt->nR, (uint32_t)c);
+}
+
+// Apply the hooks; of two roots that hooked onto each other (they chose the
+// same edge) the smaller stays root.  Minimum keys leave no longer cycles.
+__global__ void k_cc_apply(const uint32_t *__restrict__ h, int32_t n, uint32_t *__restrict__ p)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const uint32_t t = h[k];
+        if (t != (uint32_t)k && !(h[t] == (uint32_t)k && (uint32_t)k < t)) p[k] = t;
+    }
+}
+
+void launch_cc_hook(hipStream_t s, const uint32_t *p, const uint64_t *r, const int32_t *edges,
+                    int32_t n, uint32_t *h, Counters *dcnt)
+{
+    if (n <= 0) return;
+    size_t g = ((size_t)n + 255) / 256;
+    if (g > 8192) g = 8192;
+    k_cc_hook<<<(unsigned)g, 256, 0, s>>>(p, r, edges, n, h, dcnt);
+}
+
+void launch_cc_apply(hipStream_t s, const uint32_t *h, int32_t n, uint32_t *p)
+{
+    if (n <= 0) return;
+    size_t g = ((size_t)n + 255) / 256;
+    if (g > 8192) g = 8192;
+    k_cc_apply<<<(unsigned)g, 256, 0, s>>>(h, n, p);
+}
+
 __global__ void k_check_roots(const uint32_t *__restrict__ p, const uint32_t *__restrict__ q,
                               int32_t n, Counters *cnt)
 {

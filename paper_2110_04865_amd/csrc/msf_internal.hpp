@@ -384,6 +384,11 @@ void launch_check_roots(hipStream_t s, const uint32_t *p, const uint32_t *q, int
 // One full pointer-jumping pass over all n vertices; adds the vertices left
 // unfinished into dcnt->nR.
 void launch_jump_full(hipStream_t s, uint32_t *q, int32_t n, Counters *dcnt);
+// Connected components: hooks of the star roots along the edges of r (h,
+// hooked roots added into dcnt->nR), then their application to p.
+void launch_cc_hook(hipStream_t s, const uint32_t *p, const uint64_t *r, const int32_t *edges,
+                    int32_t n, uint32_t *h, Counters *dcnt);
+void launch_cc_apply(hipStream_t s, const uint32_t *h, int32_t n, uint32_t *p);
 
 void zero_counters(Ctx *c);
 msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc);

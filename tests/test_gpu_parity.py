@@ -428,6 +428,45 @@ def test_shortcut_strategies_match_find_roots(ctx, pkg):
     assert np.array_equal(dp.cpu().numpy().view(np.uint32), [0, 0, 1])
 
 
+# ------------------------------------------------------------ components --
+
+def test_components_match_bfs(ctx, pkg):
+    """Connectivity variant: the partition equals BFS components (scipy)."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    cases = {
+        "er4096": (4096, *gen.er(4096, 32768, seed=1)),
+        "sparse many components": (20000, *gen.er(20000, 9000, seed=3)),
+        "rmat14": (*gen.rmat(14, 16, seed=2, wtype=U32),),
+        "grid20": (*gen.grid(20, 20, 20, 0.3, seed=3),),
+        "isolated runs": (3000000, np.array([[0, 1], [1, 2], [2000000, 2000001], [0, 2],
+                                             [2000001, 1999999]], np.int32),
+                          np.array([5, 3, 9, 1, 2], np.uint32)),
+        "one vertex": (1, np.zeros((0, 2), np.int32), np.zeros(0, np.uint32)),
+        "loops and parallel edges": (5, np.array([[0, 0], [1, 2], [2, 1], [3, 3], [1, 2]],
+                                                 np.int32), np.array([1, 1, 1, 1, 1], np.uint32)),
+    }
+    for label, (n, e, w) in cases.items():
+        say("components", label, f"n={n} m={len(e)}")
+        g = pkg.Graph(ctx, n, e, w, wtype=U32)
+        lab = torch.empty(max(n, 1), dtype=torch.int32, device="cuda:0")
+        rounds = ctx.components(g, lab)
+        torch.cuda.synchronize()
+        g.close()
+        got = lab.cpu().numpy()[:n].view(np.uint32).astype(np.int64)
+        a = coo_matrix((np.ones(len(e)), (e[:, 0], e[:, 1])), shape=(n, n))
+        ncomp, want = connected_components(a, directed=False)
+        # the same partition: labels are roots of their own component, and the
+        # smallest vertex of each component maps one-to-one onto the labels
+        assert (got < n).all() and np.array_equal(got[got], got), label
+        first = np.full(ncomp, n, np.int64)
+        np.minimum.at(first, want, np.arange(n))
+        assert np.array_equal(got, got[first][want]), label
+        assert len(np.unique(got)) == ncomp, label
+        assert rounds <= max(1, math.ceil(math.log2(max(n, 2)))) + 1, (label, rounds)
+
+
 # --------------------------------------------------------------- batched --
 
 def test_batched_equals_oracle_per_graph(ctx, pkg):
