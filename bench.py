@@ -39,11 +39,14 @@ Also reported on the same JSON line:
                 size: wall time per call and passes;
   components    connected components by the connectivity variant on the
                 same kernels, on R-MAT scale 22 and the 256^3 grid: wall time
-                per call (from a built graph) and rounds.
+                per call (from a built graph) and rounds;
+  starcheck     the original AS rounds (star check, one-step shortcut) on the
+                same graphs: wall time per call and rounds, beside msf_solve's
+                rounds with complete shortcutting.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
                        [--no-ablation] [--ablation-only] [--shortcut-only]
-                       [--components-only]
+                       [--components-only] [--starcheck-only]
 """
 from __future__ import annotations
 
@@ -281,6 +284,30 @@ def bench_components(ctx, pkg, torch, graphs, reps=3):
     return out
 
 
+def bench_starcheck(ctx, pkg, torch, graphs, reps=3):
+    """msf_solve_starcheck on built graphs vs the rounds of msf_solve."""
+    out = {}
+    for label, (n, e, w, wt) in graphs.items():
+        de = torch.from_numpy(e.reshape(-1).copy()).to("cuda:0")
+        dw = torch.from_numpy(w.copy()).to("cuda:0")
+        ctx.solve(n, de, dw, wtype=wt)
+        solve_rounds = ctx.stats()["rounds"]
+        del de, dw
+        g = pkg.Graph(ctx, n, e, w, wtype=wt)
+        flags = torch.empty(len(w), dtype=torch.uint8, device="cuda:0")
+        rounds = ctx.solve_starcheck(g, flags)  # warm-up (workspace)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            rounds = ctx.solve_starcheck(g, flags)
+        ms = (time.perf_counter() - t) * 1000.0 / reps
+        g.close()
+        out[label] = {"n": n, "m": len(w), "ms": ms, "rounds": rounds,
+                      "complete_shortcut_rounds": solve_rounds}
+        log(f"starcheck {label}: {out[label]}")
+    return out
+
+
 def cpu_baseline(n, e, w):
     import oracle
 
@@ -434,6 +461,8 @@ def main():
                     help="run only the shortcut-strategy study (prints its JSON alone)")
     ap.add_argument("--components-only", action="store_true",
                     help="run only the connected-components leg (prints its JSON alone)")
+    ap.add_argument("--starcheck-only", action="store_true",
+                    help="run only the original-AS-rounds leg (prints its JSON alone)")
     ap.add_argument("--served-requests", type=int, default=200,
                     help="requests per arrival rate in the served leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -478,6 +507,15 @@ def main():
         n22, e22, w22 = gen.workload_rmat_s22()
         ng, eg, wg = gen.workload_grid_256()
         print(json.dumps({"components": bench_components(
+            ctx, pkg, torch, {"rmat_s22_e16": (n22, e22, w22, pkg.W_F32),
+                              "grid256": (ng, eg, wg, pkg.W_U32)})}), flush=True)
+        return
+    if args.starcheck_only:
+        import gen
+
+        n22, e22, w22 = gen.workload_rmat_s22()
+        ng, eg, wg = gen.workload_grid_256()
+        print(json.dumps({"starcheck": bench_starcheck(
             ctx, pkg, torch, {"rmat_s22_e16": (n22, e22, w22, pkg.W_F32),
                               "grid256": (ng, eg, wg, pkg.W_U32)})}), flush=True)
         return
@@ -548,6 +586,10 @@ def main():
         log("connected components")
         ng, eg, wg = gen.workload_grid_256()
         line["components"] = bench_components(
+            ctx, pkg, torch, {"rmat_s22_e16": (r["n"], r["e"], r["w"], pkg.W_F32),
+                              "grid256": (ng, eg, wg, pkg.W_U32)})
+        log("original AS rounds (star check)")
+        line["starcheck"] = bench_starcheck(
             ctx, pkg, torch, {"rmat_s22_e16": (r["n"], r["e"], r["w"], pkg.W_F32),
                               "grid256": (ng, eg, wg, pkg.W_U32)})
     print(json.dumps(line), flush=True)

@@ -231,6 +231,23 @@ msf_status msf_shortcut_strategy(msf_ctx *ctx, int32_t n, uint32_t *p, int32_t s
 msf_status msf_components(msf_ctx *ctx, const msf_graph *g, uint32_t *labels, int32_t *rounds);
 
 /*
+ * The minimum spanning forest by the original Awerbuch-Shiloach rounds
+ * (section 2.3, Algorithm 1), for comparison with complete shortcutting:
+ * each round flags the stars (star check), lets every star root hook along
+ * its star's minimum-key outgoing edge onto the parent of the outside
+ * endpoint (the smaller of two roots that hooked onto each other stays
+ * root), then shortcuts every vertex by one step.  Stops after a round with
+ * no hook and no change.
+ *   in_forest  device uint8[m] out: 1 for the edges of the forest (the same
+ *              forest as msf_solve), 0 otherwise
+ *   rounds     (host, nullable) receives the number of rounds
+ * Ordered on the context's stream; returns after synchronising.  Uses the
+ * context's workspace (24 bytes per vertex).
+ */
+msf_status msf_solve_starcheck(msf_ctx *ctx, const msf_graph *g, uint8_t *in_forest,
+                               int32_t *rounds);
+
+/*
  * Minimum spanning forests of G independent graphs in one batched solve.
  * Graph g has vtx_off[g+1]-vtx_off[g] vertices and edge_off[g+1]-edge_off[g]
  * edges stored from edges[2*edge_off[g]] (local vertex ids) and

@@ -34,6 +34,7 @@ EXPORTS = [
     "msf_ctx_create", "msf_ctx_destroy", "msf_last_error", "msf_version", "msf_solve",
     "msf_get_stats", "msf_graph_create", "msf_graph_destroy", "msf_multilinear",
     "msf_multilinear_pairwise", "msf_shortcut_strategy", "msf_components",
+    "msf_solve_starcheck",
     "msf_shortcut", "msf_solve_batched", "msf_server_create", "msf_server_destroy",
     "msf_server_submit", "msf_server_poll", "msf_server_latency", "msf_server_result",
     "msf_request_footprint",
@@ -100,6 +101,8 @@ def lib():
     L.msf_shortcut_strategy.restype = st
     L.msf_components.argtypes = [P, P, P, ctypes.POINTER(I32)]
     L.msf_components.restype = st
+    L.msf_solve_starcheck.argtypes = [P, P, P, ctypes.POINTER(I32)]
+    L.msf_solve_starcheck.restype = st
     L.msf_solve_batched.argtypes = [P, I32, P, P, P, P, ctypes.c_int, ctypes.c_int, P, P, P]
     L.msf_solve_batched.restype = st
     L.msf_server_create.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(P)]
@@ -254,6 +257,14 @@ class Context:
         it = ctypes.c_int32()
         _check(lib().msf_components(self._h, g._h, ctypes.c_void_p(labels.data_ptr()),
                                     ctypes.byref(it)))
+        return it.value
+
+    def solve_starcheck(self, g: "Graph", in_forest) -> int:
+        """Forest flags (device uint8 tensor [m]) by the original AS rounds
+        with star check and one-step shortcut; returns the number of rounds."""
+        it = ctypes.c_int32()
+        _check(lib().msf_solve_starcheck(self._h, g._h, ctypes.c_void_p(in_forest.data_ptr()),
+                                         ctypes.byref(it)))
         return it.value
 
     def shortcut(self, p) -> int:

@@ -569,6 +569,71 @@ msf_status msf_components(msf_ctx *ctx, const msf_graph *g, uint32_t *labels, in
     return MSF_OK;
 }
 
+msf_status msf_solve_starcheck(msf_ctx *ctx, const msf_graph *g, uint8_t *in_forest,
+                               int32_t *rounds)
+{
+    if (!ctx || !g || g->ctx != ctx) {
+        set_error("bad ctx/graph");
+        return MSF_EINVAL;
+    }
+    const int32_t n = g->a.n;
+    const int64_t m = g->a.m;
+    if (m > 0 && !in_forest) {
+        set_error("NULL in_forest");
+        return MSF_EINVAL;
+    }
+    Ctx *c = &ctx->c;
+    MSF_HIP(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    if (m > 0) MSF_HIP(hipMemsetAsync(in_forest, 0, (size_t)m, s));
+    if (n == 0 || m == 0) {
+        MSF_HIP(hipStreamSynchronize(s));
+        if (rounds) *rounds = 0;
+        return MSF_OK;
+    }
+    void *vr, *vh, *vp0, *vp1, *vst;
+    msf_status rc;
+    if ((rc = ws_get(c, WS_R, 8 * (size_t)n, &vr)) || (rc = ws_get(c, WS_H, 4 * (size_t)n, &vh)) ||
+        (rc = ws_get(c, WS_P, 4 * (size_t)n, &vp0)) || (rc = ws_get(c, WS_Q, 4 * (size_t)n, &vp1)) ||
+        (rc = ws_get(c, WS_FLAGS, 4 * (size_t)n, &vst)))
+        return rc;
+    uint64_t *r = (uint64_t *)vr;
+    uint32_t *h = (uint32_t *)vh, *star = (uint32_t *)vst;
+    uint32_t *P[2] = {(uint32_t *)vp0, (uint32_t *)vp1};
+    zero_counters(c);
+    launch_iota_u32(s, P[0], (size_t)n);
+    // O(log n) rounds for AS; the cap only guards against a defect
+    int lg = 1;
+    while ((1ll << lg) < (long long)n) ++lg;
+    const int cap = 8 * lg + 16;
+    int cur = 0, done_rounds = 0;
+    for (;;) {
+        if (done_rounds >= cap) {
+            set_error("starcheck: no convergence");
+            return MSF_EDEVICE;
+        }
+        uint32_t *p = P[cur];
+        launch_star_check(s, p, n, star);
+        launch_fill_u64(s, r, KEY_INF, (size_t)n);
+        launch_sweep(s, g->a, p, r, c->dcnt);
+        launch_fill_u32(s, &c->dcnt->nR, 0u, 1);
+        launch_cc_hook(s, p, r, g->a.edges, n, h, c->dcnt, star, in_forest);
+        if ((rc = read_counters(c))) return rc;
+        const uint32_t hooks = c->hcnt->nR;
+        if (hooks) launch_cc_apply(s, h, n, p);
+        launch_fill_u32(s, &c->dcnt->nR, 0u, 1);
+        launch_jump_once(s, p, n, P[cur ^ 1], c->dcnt);
+        if ((rc = read_counters(c))) return rc;
+        const uint32_t changed = c->hcnt->nR;
+        cur ^= 1;
+        ++done_rounds;
+        if (hooks == 0 && changed == 0) break;
+    }
+    MSF_HIP(hipStreamSynchronize(s));
+    if (rounds) *rounds = done_rounds;
+    return MSF_OK;
+}
+
 size_t msf_request_footprint(int32_t n, int64_t m)
 {
     // per edge: input copy (12), bucketed build staging (28), adjacency and

@@ -797,10 +797,15 @@ void launch_jump_full(hipStream_t s, uint32_t *q, int32_t n, Counters *dcnt)
 // minimum-key one found by the sweep is such an edge).  p is a star forest,
 // so r[k] is set only for roots.  Hooked roots are counted into cnt->nR,
 // one atomic per workgroup.
+// With star (original AS rounds, section 2.3): only roots of stars hook, the
+// target is the parent of the outside endpoint (a vertex of its tree, not
+// necessarily the root), and the hooking edge is marked in in_forest.
 __global__ __launch_bounds__(256) void k_cc_hook(const uint32_t *__restrict__ p,
                                                  const uint64_t *__restrict__ r,
                                                  const int32_t *__restrict__ edges, int32_t n,
-                                                 uint32_t *__restrict__ h, Counters *cnt)
+                                                 uint32_t *__restrict__ h, Counters *cnt,
+                                                 const uint32_t *__restrict__ star,
+                                                 uint8_t *__restrict__ in_forest)
 {
     __shared__ uint64_t s_lds[256 / 64 + 1];
     uint64_t c = 0;
@@ -808,11 +813,12 @@ __global__ __launch_bounds__(256) void k_cc_hook(const uint32_t *__restrict__ p,
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
         uint32_t t = (uint32_t)k;
         const uint64_t rk = r[k];
-        if (rk != KEY_INF && p[k] == (uint32_t)k) {
+        if (rk != KEY_INF && p[k] == (uint32_t)k && (!star || star[k])) {
             // one endpoint lies in k's star, the other outside it
             const size_t e = (size_t)(uint32_t)rk;
             const uint32_t a = p[edges[2 * e]], b = p[edges[2 * e + 1]];
             t = a == (uint32_t)k ? b : a;
+            if (in_forest) in_forest[e] = 1;
             ++c;
         }
         h[k] = t;
@@ -833,12 +839,72 @@ __global__ void k_cc_apply(const uint32_t *__restrict__ h, int32_t n, uint32_t *
 }
 
 void launch_cc_hook(hipStream_t s, const uint32_t *p, const uint64_t *r, const int32_t *edges,
-                    int32_t n, uint32_t *h, Counters *dcnt)
+                    int32_t n, uint32_t *h, Counters *dcnt, const uint32_t *star,
+                    uint8_t *in_forest)
 {
     if (n <= 0) return;
     size_t g = ((size_t)n + 255) / 256;
     if (g > 8192) g = 8192;
-    k_cc_hook<<<(unsigned)g, 256, 0, s>>>(p, r, edges, n, h, dcnt);
+    k_cc_hook<<<(unsigned)g, 256, 0, s>>>(p, r, edges, n, h, dcnt, star, in_forest);
+}
+
+// Star check (section 2.3): star[i] = 1 iff i's tree has depth at most one.
+// Pass 1 clears i and its grandparent where i is two levels down; pass 2
+// takes the parent's flag (a vertex still flagged after pass 1 has a root
+// for parent, whose flag pass 2 does not change).
+__global__ void k_star_clear(const uint32_t *__restrict__ p, int32_t n, uint32_t *star)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t x = p[i], y = p[x];
+        if (y != x) {
+            star[i] = 0u;
+            star[y] = 0u;
+        }
+    }
+}
+
+__global__ void k_star_parent(const uint32_t *__restrict__ p, int32_t n, uint32_t *star)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        if (star[i] && !star[p[i]]) star[i] = 0u;
+}
+
+// One synchronous shortcut step (section 2.3): dst[i] = src[src[i]];
+// changed entries are counted into cnt->nR.
+__global__ __launch_bounds__(256) void k_jump_once(const uint32_t *__restrict__ src, int32_t n,
+                                                   uint32_t *__restrict__ dst, Counters *cnt)
+{
+    __shared__ uint64_t s_lds[256 / 64 + 1];
+    uint64_t c = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t x = src[i], y = src[x];
+        dst[i] = y;
+        c += y != x ? 1u : 0u;
+    }
+    c = block_sum<256>(c, s_lds);
+    if (threadIdx.x == 0 && c) atomicAdd(&cnt->nR, (uint32_t)c);
+}
+
+void launch_star_check(hipStream_t s, const uint32_t *p, int32_t n, uint32_t *star)
+{
+    if (n <= 0) return;
+    size_t g = ((size_t)n + 255) / 256;
+    if (g > 8192) g = 8192;
+    launch_fill_u32(s, star, 1u, (size_t)n);
+    k_star_clear<<<(unsigned)g, 256, 0, s>>>(p, n, star);
+    k_star_parent<<<(unsigned)g, 256, 0, s>>>(p, n, star);
+}
+
+void launch_jump_once(hipStream_t s, const uint32_t *src, int32_t n, uint32_t *dst,
+                      Counters *dcnt)
+{
+    if (n <= 0) return;
+    size_t g = ((size_t)n + 255) / 256;
+    if (g > 8192) g = 8192;
+    k_jump_once<<<(unsigned)g, 256, 0, s>>>(src, n, dst, dcnt);
 }
 
 void launch_cc_apply(hipStream_t s, const uint32_t *h, int32_t n, uint32_t *p)

@@ -386,8 +386,16 @@ void launch_check_roots(hipStream_t s, const uint32_t *p, const uint32_t *q, int
 void launch_jump_full(hipStream_t s, uint32_t *q, int32_t n, Counters *dcnt);
 // Connected components: hooks of the star roots along the edges of r (h,
 // hooked roots added into dcnt->nR), then their application to p.
+// With star non-null only star roots hook (original AS rounds); in_forest
+// (nullable) gets the hooking edges marked.
 void launch_cc_hook(hipStream_t s, const uint32_t *p, const uint64_t *r, const int32_t *edges,
-                    int32_t n, uint32_t *h, Counters *dcnt);
+                    int32_t n, uint32_t *h, Counters *dcnt, const uint32_t *star = nullptr,
+                    uint8_t *in_forest = nullptr);
+// Original AS rounds: star flags of p, and one synchronous shortcut step
+// (changes added into dcnt->nR).
+void launch_star_check(hipStream_t s, const uint32_t *p, int32_t n, uint32_t *star);
+void launch_jump_once(hipStream_t s, const uint32_t *src, int32_t n, uint32_t *dst,
+                      Counters *dcnt);
 void launch_cc_apply(hipStream_t s, const uint32_t *h, int32_t n, uint32_t *p);
 
 void zero_counters(Ctx *c);

@@ -467,6 +467,33 @@ def test_components_match_bfs(ctx, pkg):
         assert rounds <= max(1, math.ceil(math.log2(max(n, 2)))) + 1, (label, rounds)
 
 
+def test_starcheck_rounds_give_the_msf(ctx, pkg):
+    """Original AS rounds (star check, one-step shortcut): the oracle's forest."""
+    cases = {
+        "er4096": (4096, *gen.er(4096, 32768, seed=1), U32),
+        "rmat14": (*gen.rmat(14, 16, seed=2), F32),
+        "grid20": (*gen.grid(20, 20, 20, 0.05, seed=3), U32),
+        "sparse": (20000, *gen.er(20000, 9000, seed=3), U32),
+        "equal weights": (3000, gen.er(3000, 12000, seed=9)[0], np.ones(12000, np.uint32), U32),
+        "loops and parallel": (5, np.array([[0, 0], [1, 2], [2, 1], [3, 3], [1, 2], [4, 1]],
+                                           np.int32), np.array([1, 7, 7, 1, 3, 2], np.uint32),
+                               U32),
+        "no edges": (7, np.zeros((0, 2), np.int32), np.zeros(0, np.uint32), U32),
+    }
+    for label, (n, e, w, wt) in cases.items():
+        say("starcheck", label, f"n={n} m={len(e)}")
+        g = pkg.Graph(ctx, n, e, w, wtype=wt)
+        flags = torch.full((max(len(e), 1),), 9, dtype=torch.uint8, device="cuda:0")
+        rounds = ctx.solve_starcheck(g, flags)
+        torch.cuda.synchronize()
+        g.close()
+        got = np.nonzero(flags.cpu().numpy()[:len(e)])[0]
+        ids, cnt, _ = oracle.msf(n, e, w, wt)
+        assert np.array_equal(got, np.asarray(ids, np.int64)), label
+        assert len(got) == cnt, label
+        assert (len(e) == 0) == (rounds == 0), (label, rounds)
+
+
 # --------------------------------------------------------------- batched --
 
 def test_batched_equals_oracle_per_graph(ctx, pkg):
