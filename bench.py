@@ -75,6 +75,8 @@ KERNELS = {
               ("kernels_sweep.hip", "msf_internal.hpp", "wave.hpp")),
     "heads": ("k_heads + k_heads_rest (head sweep)",
               ("kernels_heads.hip", "msf_internal.hpp", "wave.hpp")),
+    "build": ("adjacency build (two-level)",
+              ("kernels_build2.hip", "kernels_build.hip", "msf_internal.hpp", "wave.hpp")),
 }
 
 
@@ -161,7 +163,7 @@ def bench_rmat(ctx, pkg, torch, steps, warmup):
     log(f"timed {steps} steps in {t1 - t0:.3f}s; last stats {st}")
     ms = (t1 - t0) * 1000.0 / steps
     res = dict(n=n, m=m, e=e, w=w, ms=ms, count=cnt, total=tot, stats=st,
-               ids_sum=int(ids.to(torch.int64).sum().item()),
+               ids=ids.cpu().numpy().astype(np.int64),
                kernels=kt, build_ms=build_ms / steps, rounds_ms=rounds_ms / steps)
     return res
 
@@ -308,16 +310,124 @@ def bench_starcheck(ctx, pkg, torch, graphs, reps=3):
     return out
 
 
-def cpu_baseline(n, e, w):
+def cpu_baseline(n, e, w, wtype=1):
     import oracle
 
     t = time.perf_counter()
-    ids, cnt, tot = oracle.msf(n, e, w, oracle.W_F32)
+    ids, cnt, tot = oracle.msf(n, e, w, wtype)
     dt = time.perf_counter() - t
-    return dict(seconds=dt, count=cnt, total=tot, ids_sum=int(ids.sum()))
+    return dict(seconds=dt, count=cnt, total=tot, ids=ids)
 
 
-def bench_batched(ctx, pkg, torch, G=10000):
+def same_forest(gpu_ids, cnt, tot, cb, wtype):
+    """Element-wise parity of a GPU result with the oracle's: ids, count,
+    and the totals (exact)."""
+    import numpy as np
+
+    return (cnt == cb["count"] and np.array_equal(np.asarray(gpu_ids, dtype=np.int64), cb["ids"])
+            and tot[1] == cb["total"][1] and (wtype == 1 or tot[0] == cb["total"][0]))
+
+
+def host_info():
+    """CPU model and the cores this process may use (for the CPU baseline)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "os_cpu_count": os.cpu_count()}
+
+
+def bench_plain(ctx, pkg, torch, label, n, e, w, wt, steps=5, cpu=True):
+    """One configuration's plain msf_solve from device-resident COO: time
+    per solve, edges/s, rounds, element-wise parity with the oracle and the
+    oracle's own time on the host (one thread)."""
+    import numpy as np
+
+    de = torch.from_numpy(e.reshape(-1).copy()).to("cuda:0")
+    dw = torch.from_numpy(w.view(np.int32).copy()).to("cuda:0")
+    out = torch.empty(max(n, 1), dtype=torch.int32, device="cuda:0")
+    for _ in range(2):
+        ctx.solve(n, de, dw, wtype=wt, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ids, cnt, tot = ctx.solve(n, de, dw, wtype=wt, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / steps
+    st = ctx.stats()
+    res = {"workload": label, "n": n, "m": len(w), "ms_per_solve": ms,
+           "edges_per_s": len(w) / (ms / 1000.0), "rounds": st["rounds"],
+           "hooks_per_round": st["hooks"], "build_ms": st["build_ms"],
+           "rounds_ms": st["rounds_ms"], "head_sweeps": st["head_sweeps"]}
+    if cpu:
+        cb = cpu_baseline(n, e, w, wt)
+        res["parity"] = bool(same_forest(ids.cpu().numpy(), cnt, tot, cb, wt))
+        res["cpu_oracle_s"] = cb["seconds"]
+        res["cpu_oracle_edges_per_s"] = len(w) / cb["seconds"]
+    log(f"plain {label}: {res}")
+    return res
+
+
+def parents_after_round1(ctx, pkg, torch, n, e, w, wtype):
+    """The parent vector at the start of round 2 of msf_solve: round 1's
+    hooks and tie break (round1_forest), completed by msf_shortcut."""
+    import numpy as np
+
+    h = round1_forest(ctx, pkg, torch, n, e, w, wtype)
+    p = torch.from_numpy(h.view(np.int32)).to("cuda:0")
+    ctx.shortcut(p)
+    torch.cuda.synchronize()
+    return p
+
+
+def bench_multilinear_round1(ctx, pkg, torch, n, e, w, wtype, reps=25):
+    """msf_multilinear on the full adjacency with the parents after round 1:
+    median device time of the sweep kernel (events the library records on
+    its stream around that launch) over `reps` calls, against the streamed
+    bytes 12 nnz + 4 (rows + 1) + 4 rows + 8 roots written."""
+    import numpy as np
+
+    p = parents_after_round1(ctx, pkg, torch, n, e, w, wtype)
+    g = pkg.Graph(ctx, n, e, w, wtype=wtype)
+    r = torch.empty(n, dtype=torch.int64, device="cuda:0")
+    for _ in range(3):
+        ctx.multilinear(g, p, r)
+    times = []
+    for _ in range(reps):
+        ctx.multilinear(g, p, r)
+        st = ctx.stats()  # waits for the sweep's end event
+        times.append(st["sweep_ms"][0])
+    torch.cuda.synchronize()
+    rk = r.cpu().numpy().view(np.uint64)
+    roots_written = int((rk != np.uint64(0xFFFFFFFFFFFFFFFF)).sum())
+    deg = np.bincount(e[e[:, 0] != e[:, 1]].reshape(-1), minlength=n)
+    rows = int((deg > 0).sum())
+    nnz = int(deg.sum())
+    pn = p.cpu().numpy()
+    g.close()
+    med = float(np.median(times))
+    b = 12.0 * nnz + 4.0 * (rows + 1) + 4.0 * rows + 8.0 * roots_written
+    gb_s = b / 1e9 / (med / 1e3)
+    return {"kernel": "k_sweep (msf_multilinear: multilinear kernel + projection)",
+            "parents": "after round 1 of msf_solve (hooks, tie break, complete shortcut)",
+            "roots": int((pn == np.arange(n)).sum()), "roots_written": roots_written,
+            "nnz": nnz, "rows": rows, "reps": reps, "median_ms": med,
+            "min_ms": float(np.min(times)), "max_ms": float(np.max(times)),
+            "bytes": b, "achieved": gb_s, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gb_s / HBM_PEAK_GBS, "target_frac": 0.40,
+            "gather_bytes_if_every_entry": 4.0 * nnz}
+
+
+def bench_batched(ctx, pkg, torch, G=10000, cpu=True):
     import numpy as np
     import gen
 
@@ -346,20 +456,117 @@ def bench_batched(ctx, pkg, torch, G=10000):
         ctx.solve(int(vo[g + 1] - vo[g]), ee[g_i], ww[g_i], wtype=pkg.W_U32, out=one)
     torch.cuda.synchronize()
     tp = (time.perf_counter() - t) / len(sample)  # seconds per graph
-    return {"graphs": G, "vertices": int(vo[-1]), "edges": int(eo[-1]),
-            "batched_s": tb, "batched_graphs_per_s": G / tb,
-            "plain_graphs_per_s": 1.0 / tp, "plain_sample_graphs": len(sample),
-            "speedup": (G / tb) * tp}
+    res = {"graphs": G, "vertices": int(vo[-1]), "edges": int(eo[-1]),
+           "batched_s": tb, "batched_graphs_per_s": G / tb,
+           "plain_graphs_per_s": 1.0 / tp, "plain_sample_graphs": len(sample),
+           "speedup": (G / tb) * tp}
+    if cpu:
+        res.update(batched_cpu(vo, eo, e, w, ids.cpu().numpy(), counts, totals, sample))
+    return res
 
 
-def bench_served(ctx, pkg, torch, requests_per_rate=200, rates=(0.25, 0.5, 1.0, 2.0, 4.0),
-                 budget=32 << 30, seed=5):
+def batched_cpu(vo, eo, e, w, ids, counts, totals, sample):
+    """The oracle on the batch's graphs: one thread over a sample (graphs/s,
+    and element-wise parity of the batched result on those graphs), and
+    every graph spread over the host's cores by a thread pool (the oracle's
+    sort and union-find run outside the interpreter lock)."""
+    import concurrent.futures as cf
+    import numpy as np
+    import oracle
+
+    def one(g):
+        n = int(vo[g + 1] - vo[g])
+        return oracle.msf(n, e[eo[g]:eo[g + 1]], w[eo[g]:eo[g + 1]], oracle.W_U32)
+
+    t = time.perf_counter()
+    ok = True
+    for g in sample:
+        wi, wc, wt = one(g)
+        ok &= bool(counts[g] == wc and np.array_equal(ids[vo[g]:vo[g] + wc].astype(np.int64), wi)
+                   and totals[g][0] == wt[0])
+    t1 = time.perf_counter() - t
+    G = len(vo) - 1
+    workers = min(16, len(os.sched_getaffinity(0)))
+    t = time.perf_counter()
+    with cf.ThreadPoolExecutor(workers) as ex:
+        for _ in ex.map(one, range(G), chunksize=16):
+            pass
+    tall = time.perf_counter() - t
+    return {"cpu_baseline": {"value": len(sample) / t1, "unit": "graphs/s", "cores": 1,
+                             "kind": "oracle",
+                             "sample": f"{len(sample)} of the {G} graphs (every "
+                                       f"{sample[1] - sample[0]}th), one thread"},
+            "cpu_parallel": {"value": G / tall, "unit": "graphs/s", "cores": workers,
+                             "kind": "oracle", "sample": f"all {G} graphs, {workers} threads"},
+            "parity_sample": ok}
+
+
+def run_fifo(ctx, pkg, pool, arrivals, picks):
+    """The plain FIFO actually run: one msf_solve at a time (host arrays in
+    and out, as a served request), each request starting when it has
+    arrived and the previous one is done.  Returns the latencies (s) and
+    the time the last one finished."""
+    import numpy as np
+
+    lat = []
+    t0 = time.perf_counter()
+    for a, g in zip(arrivals, picks):
+        now = time.perf_counter() - t0
+        if now < a:
+            time.sleep(a - now)
+        n, e, w, kind = pool[g]
+        ctx.solve(n, e, w, wtype=pkg.W_F32)
+        lat.append(time.perf_counter() - t0 - a)
+    return np.array(lat), time.perf_counter() - t0
+
+
+def serve_stream(srv, pkg, pool, arrivals, picks):
+    """Submit a Poisson stream to a server, collecting each result as soon
+    as it is ready (while submitting), as a serving front end would.
+    Returns the latencies (s, submit to ready) and the elapsed time."""
+    import numpy as np
+
+    pending = []
+    lat = []
+
+    def collect():
+        keep = []
+        for tk, n in pending:
+            if srv.poll(tk):
+                lat.append(srv.latency(tk))
+                srv.result(tk, n)
+            else:
+                keep.append((tk, n))
+        pending[:] = keep
+
+    t0 = time.perf_counter()
+    for a, g in zip(arrivals, picks):
+        while True:
+            collect()
+            now = time.perf_counter() - t0
+            if a <= now:
+                break
+            time.sleep(min(a - now, 0.0005))
+        n, e, w, kind = pool[g]
+        pending.append((srv.submit(n, e, w, wtype=pkg.W_F32), n))
+    while pending:
+        collect()
+        if pending:
+            time.sleep(0.0005)
+    return np.array(lat), time.perf_counter() - t0
+
+
+def bench_served(ctx, pkg, torch, requests_per_rate=2000, warm_requests=100,
+                 rates=(0.25, 0.5, 1.0, 2.0, 4.0), budget=32 << 30,
+                 budget_sweep=(8 << 30, 128 << 30), seed=5):
     """Poisson request stream over a pool of mixed graphs (half R-MAT with
     edge factor 16, half cubic grids with 5% of edges dropped, n log-uniform
     in [2^10, 2^22], float32 weights).  The rate is a multiple of the plain
     sequential throughput mu (one msf_solve per request, host arrays in and
-    out, timed here); the plain FIFO's latencies under the same arrivals are
-    computed from those measured per-graph service times."""
+    out, timed here).  At every rate the same arrivals also go through a
+    plain FIFO that is actually run (one msf_solve at a time); the first
+    `warm_requests` of each stream are not counted.  At the plain rate the
+    server also runs under the budgets of `budget_sweep`."""
     import numpy as np
     import gen
 
@@ -367,7 +574,6 @@ def bench_served(ctx, pkg, torch, requests_per_rate=200, rates=(0.25, 0.5, 1.0, 
     pool = gen.serve_pool(64, seed=seed)
     log(f"served pool generated in {time.perf_counter() - t:.1f}s "
         f"({sum(len(p[1]) for p in pool)} edges)")
-    # plain sequential service time per pool graph
     svc = []
     for n, e, w, kind in pool:
         ctx.solve(n, e, w, wtype=pkg.W_F32)  # warm the workspace
@@ -375,72 +581,60 @@ def bench_served(ctx, pkg, torch, requests_per_rate=200, rates=(0.25, 0.5, 1.0, 
         t = time.perf_counter()
         ctx.solve(n, e, w, wtype=pkg.W_F32)
         svc.append(time.perf_counter() - t)
-    svc = np.array(svc)
-    mu = 1.0 / svc.mean()
+    mu = 1.0 / float(np.mean(svc))
     rng = np.random.default_rng(seed)
+    total = warm_requests + requests_per_rate
     out = {"pool_graphs": len(pool), "requests_per_rate": requests_per_rate,
-           "budget_bytes": budget, "plain_graphs_per_s": mu, "rates": []}
-    srv = pkg.Server(ctx, budget)
-    # warm the server with the whole pool at once, so its slots, device
-    # memory pool and pinned staging buffers reach their working set
-    warm = [srv.submit(*p[:3], wtype=pkg.W_F32) for p in pool]
-    for i, tk in enumerate(warm):
-        srv.result(tk, pool[i][0])
+           "warm_requests_not_counted": warm_requests, "budget_bytes": budget,
+           "plain_graphs_per_s": mu, "rates": [], "budgets": []}
+
+    def stats(lat, elapsed, arrivals):
+        lat = lat[warm_requests:]
+        span = elapsed - arrivals[warm_requests]
+        return {"p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                "graphs_per_s": requests_per_rate / span}
+
+    servers = {}
+
+    def server(b):
+        if b not in servers:
+            srv = pkg.Server(ctx, b)
+            # warm: the whole pool at once, so slots, the device memory pool
+            # and the pinned staging buffers reach their working set
+            warm = [srv.submit(*p[:3], wtype=pkg.W_F32) for p in pool]
+            for i, tk in enumerate(warm):
+                srv.result(tk, pool[i][0])
+            servers[b] = srv
+        return servers[b]
+
     for mult in rates:
         lam = mult * mu
-        gaps = rng.exponential(1.0 / lam, requests_per_rate)
-        arrivals = np.cumsum(gaps)
-        picks = rng.integers(0, len(pool), requests_per_rate)
-        # the client collects each result as soon as it is ready (while it
-        # keeps submitting), as a serving front end would; that returns the
-        # request's pinned staging buffer to the server's pool
-        pending = []
-        lat = []
-
-        def collect(block):
-            keep = []
-            for tk, n in pending:
-                if srv.poll(tk):
-                    lat.append(srv.latency(tk))
-                    srv.result(tk, n)
-                else:
-                    keep.append((tk, n))
-            pending[:] = keep
-            if block and pending:
-                time.sleep(0.0005)
-
-        t0 = time.perf_counter()
-        for a, g in zip(arrivals, picks):
-            while True:
-                collect(False)
-                now = time.perf_counter() - t0
-                if a <= now:
-                    break
-                time.sleep(min(a - now, 0.0005))
-            n, e, w, kind = pool[g]
-            pending.append((srv.submit(n, e, w, wtype=pkg.W_F32), n))
-        while pending:
-            collect(True)
-        t_end = time.perf_counter() - t0
-        lat = np.array(lat)
-        # plain FIFO under the same arrivals with the measured service times
-        fin = 0.0
-        fifo = []
-        for a, g in zip(arrivals, picks):
-            fin = max(fin, a) + svc[g]
-            fifo.append(fin - a)
-        fifo = np.array(fifo)
-        out["rates"].append({
-            "rate_x_plain": mult, "arrival_per_s": lam,
-            "served_p50_ms": 1e3 * float(np.percentile(lat, 50)),
-            "served_p99_ms": 1e3 * float(np.percentile(lat, 99)),
-            "served_graphs_per_s": requests_per_rate / t_end,
-            "fifo_p50_ms": 1e3 * float(np.percentile(fifo, 50)),
-            "fifo_p99_ms": 1e3 * float(np.percentile(fifo, 99)),
-            "fifo_graphs_per_s": requests_per_rate / max(fin, arrivals[-1]),
-        })
-        log(f"served x{mult}: {out['rates'][-1]}")
-    srv.close()
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, total))
+        picks = rng.integers(0, len(pool), total)
+        lat, el = serve_stream(server(budget), pkg, pool, arrivals, picks)
+        sv = stats(lat, el, arrivals)
+        flat, fel = run_fifo(ctx, pkg, pool, arrivals, picks)
+        fv = stats(flat, fel, arrivals)
+        row = {"rate_x_plain": mult, "arrival_per_s": lam,
+               "served_p50_ms": sv["p50_ms"], "served_p99_ms": sv["p99_ms"],
+               "served_graphs_per_s": sv["graphs_per_s"],
+               "fifo_p50_ms": fv["p50_ms"], "fifo_p99_ms": fv["p99_ms"],
+               "fifo_graphs_per_s": fv["graphs_per_s"]}
+        out["rates"].append(row)
+        log(f"served x{mult}: {row}")
+        if mult == 1.0:
+            for b in budget_sweep:
+                lat, el = serve_stream(server(b), pkg, pool, arrivals, picks)
+                bv = stats(lat, el, arrivals)
+                out["budgets"].append({"budget_bytes": b, "rate_x_plain": mult,
+                                       "served_p50_ms": bv["p50_ms"],
+                                       "served_p99_ms": bv["p99_ms"],
+                                       "served_graphs_per_s": bv["graphs_per_s"]})
+                log(f"served x{mult} budget {b >> 30} GiB: {out['budgets'][-1]}")
+                servers.pop(b).close()
+    for srv in servers.values():
+        srv.close()
     return out
 
 
@@ -463,8 +657,8 @@ def main():
                     help="run only the connected-components leg (prints its JSON alone)")
     ap.add_argument("--starcheck-only", action="store_true",
                     help="run only the original-AS-rounds leg (prints its JSON alone)")
-    ap.add_argument("--served-requests", type=int, default=200,
-                    help="requests per arrival rate in the served leg")
+    ap.add_argument("--served-requests", type=int, default=2000,
+                    help="requests per arrival rate in the served leg (after 100 not counted)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (a reference kernel "
                          "of known traffic for hardware byte counters)")
@@ -524,10 +718,33 @@ def main():
         return
     r = bench_rmat(ctx, pkg, torch, args.steps, args.warmup)
     m = r["m"]
+    n = r["n"]
     value = m / (r["ms"] / 1000.0)
     kt = r["kernels"]
-    dom = max(kt, key=lambda k: kt[k][0])
-    d_ms, d_bytes, d_n = kt[dom]
+    steps = args.steps
+    # the adjacency build is the dominant unit (most device time per step);
+    # its bytes are what the method must move to build A (both directions
+    # of every edge with its key): the edge list and weights read once
+    # (12 m), column and key of every stored entry written once (12 nnz),
+    # the row pointers (4 (n + 1)) and round 1's minima kept by the build
+    # (8 n); its time is the build's device time less the run sort of the
+    # head sweep, which is timed as a unit of its own
+    nnz = 2 * m
+    build_bytes = 12.0 * m + 12.0 * nnz + 4.0 * (n + 1) + 8.0 * n
+    sort_ms = kt["sort"][0] / steps
+    build_only_ms = r["build_ms"] - sort_ms
+    units = {
+        "build": (build_only_ms, build_bytes,
+                  "adjacency build (k_bucket_hist, k_scan_u32, k_part_edges, k_tl_plan, "
+                  "k_tl_hist2, k_part_sub, k_tl_fstart, k_tl_place, k_tl_order)"),
+        "sort": (sort_ms, kt["sort"][1] / max(1, kt["sort"][2]),
+                 "k_sort_chunks (run sort of the head sweep; 24 B per stored entry read + "
+                 "written, 16 B per run, 4 B per chunk)"),
+        "heads": (kt["heads"][0] / steps, kt["heads"][1] / steps,
+                  "k_heads + k_heads_rest (head sweeps of one solve; 24 B per run and sweep)"),
+    }
+    dom = max(units, key=lambda k: units[k][0])
+    d_ms, d_bytes, d_name = units[dom]
     achieved = (d_bytes / 1e9) / (d_ms / 1e3) if d_ms > 0 else 0.0
     line = {
         "metric": "MSF edges/s at R-MAT s22 (% HBM peak); batched graphs/s vs plain; p99 latency",
@@ -544,29 +761,44 @@ def main():
         "data": "synthetic",
         "config": {"workload": "R-MAT scale 22, edge factor 16, a/b/c/d=.57/.19/.19/.05, "
                                "permuted ids, simple graph, float32 weights",
-                   "n": r["n"], "m": m, "nnz": 2 * m, "rounds": r["stats"]["rounds"],
+                   "n": n, "m": m, "nnz": nnz, "rounds": r["stats"]["rounds"],
                    "build_ms": r["build_ms"], "rounds_ms": r["rounds_ms"]},
-        "roofline": {"bound": "hbm", "kernel": KERNELS[dom][0],
+        "roofline": {"bound": "hbm", "kernel": d_name,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
-                     "avg_launch_ms": d_ms / max(1, d_n),
-                     "bytes_per_launch": d_bytes / max(1, d_n),
-                     "launches": d_n,
-                     "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()}},
+                     "avg_launch_ms": d_ms, "bytes_per_launch": d_bytes,
+                     "units_ms_per_step": {k: v[0] for k, v in units.items()},
+                     "kernel_ms_per_step": {k: v[0] / steps for k, v in kt.items()}},
+        "host": host_info(),
     }
+    log("multilinear kernel with the parents after round 1")
+    line["multilinear"] = bench_multilinear_round1(ctx, pkg, torch, n, r["e"], r["w"], pkg.W_F32)
+    log(f"multilinear: {line['multilinear']}")
     if not args.no_cpu:
         log("timing the CPU oracle on the same graph")
-        cb = cpu_baseline(r["n"], r["e"], r["w"])
+        cb = cpu_baseline(n, r["e"], r["w"])
         line["cpu_baseline"] = {"value": m / cb["seconds"], "unit": "edges/s", "cores": 1,
                                 "kind": "oracle",
                                 "sample": f"the full R-MAT s22 graph ({m} edges), one "
                                           "sort + union-find solve, single thread",
                                 "seconds": cb["seconds"]}
-        line["parity"] = (cb["count"] == r["count"] and cb["total"][1] == r["total"][1]
-                          and cb["ids_sum"] == r["ids_sum"])
+        line["parity"] = bool(same_forest(r["ids"], r["count"], r["total"], cb, 1))
+    import gen
+
+    log("plain solves of the other single-graph configurations")
+    n1, e1, w1 = gen.workload_er_4096()
+    plain = {"er4096": bench_plain(ctx, pkg, torch, "Erdos-Renyi n=4096 m=32768, uint32 "
+                                   "weights", n1, e1, w1, pkg.W_U32, steps=50,
+                                   cpu=not args.no_cpu)}
+    n3, e3, w3 = gen.workload_grid_256()
+    plain["grid256"] = bench_plain(ctx, pkg, torch, "3D grid 256^3, 5% of edges dropped, "
+                                   "uint32 weights", n3, e3, w3, pkg.W_U32, steps=5,
+                                   cpu=not args.no_cpu)
+    del e3, w3
+    line["plain"] = plain
     if not args.no_extras:
         log("batched: 10^4 Erdos-Renyi graphs")
-        line["batched"] = bench_batched(ctx, pkg, torch)
+        line["batched"] = bench_batched(ctx, pkg, torch, cpu=not args.no_cpu)
         log("served: Poisson stream of mixed graphs")
         sv = bench_served(ctx, pkg, torch, args.served_requests)
         line["served"] = sv

@@ -169,6 +169,11 @@ void msf_graph_destroy(msf_graph *g);
  *   p   device uint32[n], every entry < n (MSF_EINVAL otherwise)
  *   r   device uint64[n] out
  * Ordered on the context's stream; returns without synchronising.
+ * msf_get_stats afterwards describes this call as one round: sweep_ms[0] is
+ * the sweep kernel's device time (events on the context's stream around that
+ * one launch; msf_get_stats waits for them) and sweep_bytes[0] its streamed
+ * bytes (12 per stored entry, 8 per row with entries, 4; the written slots
+ * of r are not counted).
  */
 msf_status msf_multilinear(msf_ctx *ctx, const msf_graph *g, const uint32_t *p, uint64_t *r);
 

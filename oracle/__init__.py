@@ -26,6 +26,10 @@ Functions and what each follows
                      (section 4.2), numpy vectorised, for per-round
                      statistics: multilinear kernel, projection, hooking,
                      tie-breaking, shortcutting until every tree is a star.
+``components``       connected components (section 2.4, the result of the
+                     connectivity variant): union-find over every edge in C
+                     (``oracle.c``); each vertex is labelled with the
+                     smallest vertex id of its component.
 ``total``            forest weight: exact integer sum for uint32 weights; the
                      exact real sum rounded once to float64 for float32
                      weights (``math.fsum``), so it is independent of
@@ -75,6 +79,8 @@ def _load():
     lib.oracle_multilinear.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P]
     lib.oracle_find_roots.restype = ctypes.c_int
     lib.oracle_find_roots.argtypes = [ctypes.c_int32, P, P]
+    lib.oracle_components.restype = ctypes.c_int64
+    lib.oracle_components.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P]
     _lib = lib
     return lib
 
@@ -180,6 +186,19 @@ def find_roots(p) -> np.ndarray:
     if rc != 0:
         raise MemoryError("oracle_find_roots")
     return root[:n]
+
+
+def components(n: int, edges):
+    """(labels int32[n], count): labels[i] is the smallest vertex id of the
+    connected component of i (section 2.4 computes this partition)."""
+    e = _edges2(edges)
+    lab = np.empty(max(n, 1), dtype=np.int32)
+    c = _load().oracle_components(n, len(e), _ptr(e), _ptr(lab))
+    if c == -1:
+        raise ValueError("endpoint out of range")
+    if c < 0:
+        raise MemoryError("oracle_components")
+    return lab[:n], int(c)
 
 
 # ------------------------------------------------- Algorithm 2, by rounds --

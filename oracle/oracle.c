@@ -23,6 +23,11 @@
  *
  *  - oracle_find_roots: the result of complete shortcutting (section 4.2):
  *    every vertex points at the root of its tree in the parent forest.
+ *
+ *  - oracle_components: the connected components that the connectivity
+ *    variant of the Awerbuch-Shiloach algorithm computes (section 2.4),
+ *    by their plain definition: union-find over every edge, each vertex
+ *    labelled with the smallest vertex id of its component.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -157,4 +162,43 @@ done:
     free(state);
     free(stack);
     return rc;
+}
+
+/* ------------------------------------------------ connected components -- */
+
+/*
+ * label[i] = the smallest vertex id in i's connected component (edges taken
+ * as undirected, self-loops and parallel edges allowed).  Union-find with
+ * path halving; every union keeps the smaller root, so each final root is
+ * its component's smallest vertex.  Returns the number of components, or -1
+ * if an endpoint is outside [0, n).
+ */
+int64_t oracle_components(int32_t n, int64_t m, const int32_t *edges, int32_t *label)
+{
+    int32_t *parent = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t e, comps = 0;
+    int32_t i;
+    if (!parent)
+        return -2;
+    for (i = 0; i < n; ++i)
+        parent[i] = i;
+    for (e = 0; e < m; ++e) {
+        int32_t u = edges[2 * e], v = edges[2 * e + 1];
+        if (u < 0 || v < 0 || u >= n || v >= n) {
+            free(parent);
+            return -1;
+        }
+        int32_t a = dsu_find(parent, u), b = dsu_find(parent, v);
+        if (a < b)
+            parent[b] = a;
+        else if (b < a)
+            parent[a] = b;
+    }
+    for (i = 0; i < n; ++i) {
+        label[i] = dsu_find(parent, i);
+        if (label[i] == i)
+            ++comps;
+    }
+    free(parent);
+    return comps;
 }

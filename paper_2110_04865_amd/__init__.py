@@ -141,6 +141,24 @@ def _wtype_of(w) -> int:
     raise TypeError(f"weights must be uint32 or float32, got {w.dtype}")
 
 
+def _dev(t, name: str, numel: int, elem: int):
+    """Check a device tensor before its pointer reaches the library: on the
+    GPU, contiguous, `elem`-byte elements, at least `numel` of them.  The
+    kernels write every one of those elements, so anything smaller would be
+    an out-of-bounds device write."""
+    if not _is_torch(t):
+        raise MSFError(1, f"{name} must be a device tensor")
+    if not t.is_cuda:
+        raise MSFError(1, f"{name} must be on the GPU")
+    if not t.is_contiguous():
+        raise MSFError(1, f"{name} must be contiguous")
+    if t.element_size() != elem:
+        raise MSFError(1, f"{name} must have {elem}-byte elements, got {t.dtype}")
+    if t.numel() < numel:
+        raise MSFError(1, f"{name} holds {t.numel()} elements, needs {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
 def _host(a, dtype) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=dtype))
 
@@ -195,12 +213,12 @@ class Context:
         if _is_torch(edges):
             import torch
             m = edges.numel() // 2
-            assert edges.is_contiguous() and weights.is_contiguous()
             ids = out if out is not None else torch.empty(max(n - 1, 1), dtype=torch.int32,
                                                           device=edges.device)
-            _check(L.msf_solve(self._h, n, m, ctypes.c_void_p(edges.data_ptr()),
-                               ctypes.c_void_p(weights.data_ptr()), wt, MEM_DEVICE,
-                               ctypes.c_void_p(ids.data_ptr()), ctypes.byref(cnt),
+            pe = _dev(edges, "edges", 2 * m, 4)
+            pw = _dev(weights, "weights", m, 4)
+            pi = _dev(ids, "out", max(n - 1, 1) if m > 0 else 0, 4)
+            _check(L.msf_solve(self._h, n, m, pe, pw, wt, MEM_DEVICE, pi, ctypes.byref(cnt),
                                ctypes.byref(tot)))
             return ids[:cnt.value], cnt.value, (tot.u64, tot.f64)
         e = _host(edges, np.int32).reshape(-1)
@@ -234,20 +252,20 @@ class Context:
 
         p: device int32/uint32 tensor [n]; r: device int64 tensor [n]
         (bit pattern of uint64 keys).  Stream-ordered."""
-        _check(lib().msf_multilinear(self._h, g._h, ctypes.c_void_p(p.data_ptr()),
-                                     ctypes.c_void_p(r.data_ptr())))
+        _check(lib().msf_multilinear(self._h, g._h, _dev(p, "p", g.n, 4),
+                                     _dev(r, "r", g.n, 8)))
 
     def multilinear_pairwise(self, g: "Graph", p, r):
         """The same r by the pairwise formulation (pairs (a_ij, p_j) stored
         first, then reduced).  Arguments as for multilinear."""
-        _check(lib().msf_multilinear_pairwise(self._h, g._h, ctypes.c_void_p(p.data_ptr()),
-                                              ctypes.c_void_p(r.data_ptr())))
+        _check(lib().msf_multilinear_pairwise(self._h, g._h, _dev(p, "p", g.n, 4),
+                                              _dev(r, "r", g.n, 8)))
 
     def shortcut_strategy(self, p, strategy: int, switch_fraction: float = 0.0) -> int:
         """shortcut() by a chosen strategy (SHORTCUT_FRONTIER / _FULL / _SWITCH);
         returns the number of passes."""
         it = ctypes.c_int32()
-        _check(lib().msf_shortcut_strategy(self._h, p.numel(), ctypes.c_void_p(p.data_ptr()),
+        _check(lib().msf_shortcut_strategy(self._h, p.numel(), _dev(p, "p", p.numel(), 4),
                                            strategy, switch_fraction, ctypes.byref(it)))
         return it.value
 
@@ -255,7 +273,7 @@ class Context:
         """Connected-component labels of g into a device int32/uint32 tensor
         [n] (equal labels iff connected); returns the number of rounds."""
         it = ctypes.c_int32()
-        _check(lib().msf_components(self._h, g._h, ctypes.c_void_p(labels.data_ptr()),
+        _check(lib().msf_components(self._h, g._h, _dev(labels, "labels", g.n, 4),
                                     ctypes.byref(it)))
         return it.value
 
@@ -263,7 +281,7 @@ class Context:
         """Forest flags (device uint8 tensor [m]) by the original AS rounds
         with star check and one-step shortcut; returns the number of rounds."""
         it = ctypes.c_int32()
-        _check(lib().msf_solve_starcheck(self._h, g._h, ctypes.c_void_p(in_forest.data_ptr()),
+        _check(lib().msf_solve_starcheck(self._h, g._h, _dev(in_forest, "in_forest", g.m, 1),
                                          ctypes.byref(it)))
         return it.value
 
@@ -271,7 +289,7 @@ class Context:
         """p <- root of each vertex (device int32/uint32 tensor, in place);
         returns the number of pointer-jumping passes."""
         it = ctypes.c_int32()
-        _check(lib().msf_shortcut(self._h, p.numel(), ctypes.c_void_p(p.data_ptr()),
+        _check(lib().msf_shortcut(self._h, p.numel(), _dev(p, "p", p.numel(), 4),
                                   ctypes.byref(it)))
         return it.value
 
@@ -293,11 +311,12 @@ class Context:
             import torch
             ids = out if out is not None else torch.empty(max(N, 1), dtype=torch.int32,
                                                           device=edges.device)
+            M = int(eo[-1]) if G > 0 else 0
             _check(L.msf_solve_batched(self._h, G, ctypes.c_void_p(vo.ctypes.data),
                                        ctypes.c_void_p(eo.ctypes.data),
-                                       ctypes.c_void_p(edges.data_ptr()),
-                                       ctypes.c_void_p(weights.data_ptr()), wt, MEM_DEVICE,
-                                       ctypes.c_void_p(ids.data_ptr()),
+                                       _dev(edges, "edges", 2 * M, 4),
+                                       _dev(weights, "weights", M, 4), wt, MEM_DEVICE,
+                                       _dev(ids, "out", N, 4),
                                        ctypes.c_void_p(counts.ctypes.data), totals))
         else:
             e = _host(edges, np.int32).reshape(-1)
@@ -321,17 +340,21 @@ class Graph:
         h = ctypes.c_void_p()
         if _is_torch(edges):
             m = edges.numel() // 2
-            _check(L.msf_graph_create(ctx._h, n, m, ctypes.c_void_p(edges.data_ptr()),
-                                      ctypes.c_void_p(weights.data_ptr()), wt, MEM_DEVICE,
+            _check(L.msf_graph_create(ctx._h, n, m, _dev(edges, "edges", 2 * m, 4),
+                                      _dev(weights, "weights", m, 4), wt, MEM_DEVICE,
                                       ctypes.byref(h)))
         else:
             e = _host(edges, np.int32).reshape(-1)
             w = _host(weights, np.float32 if wt == W_F32 else np.uint32)
-            _check(L.msf_graph_create(ctx._h, n, len(w), ctypes.c_void_p(e.ctypes.data),
+            m = len(w)
+            if e.size != 2 * m:
+                raise ValueError("edges must hold 2*m int32 values")
+            _check(L.msf_graph_create(ctx._h, n, m, ctypes.c_void_p(e.ctypes.data),
                                       ctypes.c_void_p(w.ctypes.data), wt, MEM_HOST,
                                       ctypes.byref(h)))
         self._h = h
         self.n = n
+        self.m = m
         self.ctx = ctx
 
     def close(self):

@@ -290,7 +290,17 @@ msf_status msf_get_stats(const msf_ctx *ctx, msf_stats *out)
         set_error("NULL argument");
         return MSF_EINVAL;
     }
-    *out = ctx->c.stats;
+    Ctx *c = const_cast<Ctx *>(&ctx->c);
+    if (c->ml_pending) {
+        // the sweep of the last msf_multilinear: wait for its end event
+        MSF_HIP(hipSetDevice(c->device));
+        MSF_HIP(hipEventSynchronize(c->sev[1]));
+        float ms = 0.f;
+        MSF_HIP(hipEventElapsedTime(&ms, c->sev[0], c->sev[1]));
+        c->stats.sweep_ms[0] = ms;
+        c->ml_pending = false;
+    }
+    *out = c->stats;
     return MSF_OK;
 }
 
@@ -391,8 +401,17 @@ msf_status msf_multilinear(msf_ctx *ctx, const msf_graph *g, const uint32_t *p, 
     if (rc) return rc;
     if ((rc = decode_err(c->hcnt->err))) return rc;
     launch_fill_u64(c->stream, r, KEY_INF, (size_t)n);
+    // device events around the sweep alone (statistics: one round whose
+    // sweep_ms / sweep_bytes describe this kernel)
+    MSF_HIP(hipEventRecord(c->sev[0], c->stream));
     launch_sweep(c->stream, g->a, p, r, c->dcnt);
+    MSF_HIP(hipEventRecord(c->sev[1], c->stream));
     MSF_HIP(hipGetLastError());
+    c->stats = msf_stats{};
+    c->stats.rounds = 1;
+    c->stats.active_nnz[0] = g->a.nnz;
+    c->stats.sweep_bytes[0] = 12.0 * g->a.nnz + 8.0 * g->a.segs + 4.0;
+    c->ml_pending = true;
     return MSF_OK;
 }
 

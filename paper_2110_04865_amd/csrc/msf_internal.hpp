@@ -220,6 +220,9 @@ struct Ctx {
     unsigned pass_done = 0;
     int rec1 = 0, rec2 = 0;
     msf_stats stats{};
+    // msf_multilinear recorded sev[0..1] around its sweep; msf_get_stats
+    // turns them into sweep_ms[0] once they have completed
+    bool ml_pending = false;
     int filter_mode = 1;        // 0 never, 1 adaptive, 2 every round
     double filter_threshold = 0.30;
     bool check_rounds = false;  // read back error flags after every shortcut

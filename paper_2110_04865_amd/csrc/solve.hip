@@ -142,6 +142,7 @@ msf_status solve_start(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, con
 {
     SolveState &S = c->ss;
     S = SolveState{};
+    c->ml_pending = false;  // this solve's statistics replace the last sweep's
     S.n = n;
     S.m = m;
     S.edges = d_edges;

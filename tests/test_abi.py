@@ -91,3 +91,43 @@ def test_stats_struct_matches_header(tmp_path):
     assert got["size"] == ctypes.sizeof(pkg.Stats)
     for f in fields:
         assert got[f] == getattr(pkg.Stats, f).offset, f
+
+
+def test_binding_rejects_bad_device_tensors():
+    """The binding checks every device tensor before its pointer reaches the
+    library (placement, layout, element size, length); no GPU needed."""
+    torch = pytest.importorskip("torch")
+    import numpy as np
+
+    with pytest.raises(pkg.MSFError, match="device tensor"):
+        pkg._dev(np.zeros(4, np.int32), "p", 4, 4)
+    with pytest.raises(pkg.MSFError, match="on the GPU"):
+        pkg._dev(torch.zeros(4, dtype=torch.int32), "p", 4, 4)
+
+    class FakeCuda:  # stands in for a GPU tensor on a machine without one
+        __module__ = "torch.fake"
+
+        def __init__(self, n, elem, contiguous=True):
+            self.n, self.elem, self.c = n, elem, contiguous
+            self.is_cuda = True
+            self.dtype = f"{elem}-byte"
+
+        def is_contiguous(self):
+            return self.c
+
+        def element_size(self):
+            return self.elem
+
+        def numel(self):
+            return self.n
+
+        def data_ptr(self):
+            return 4096
+
+    with pytest.raises(pkg.MSFError, match="contiguous"):
+        pkg._dev(FakeCuda(8, 4, contiguous=False), "r", 8, 4)
+    with pytest.raises(pkg.MSFError, match="8-byte"):
+        pkg._dev(FakeCuda(8, 4), "r", 8, 8)
+    with pytest.raises(pkg.MSFError, match="needs 9"):
+        pkg._dev(FakeCuda(8, 8), "r", 9, 8)
+    assert pkg._dev(FakeCuda(9, 8), "r", 9, 8).value == 4096

@@ -79,13 +79,36 @@ def test_er4096_many_seeds(ctx, pkg):
         check_solve(ctx, pkg, 4096, e, w, U32, f"er4096 seed={seed}", device=seed % 2 == 0)
 
 
-def test_er4096_golden(ctx, pkg):
-    import json
-    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "er4096_seed1.json")))
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def golden_cases():
+    """(file, n, e, w, wt) of every stored expected value (tests/golden/)."""
     n, e, w = gen.workload_er_4096()
-    ids, cnt, tot = ctx.solve(n, e, w, wtype=U32)
-    assert cnt == g["count"] and tot[0] == g["total_u64"]
-    assert int(np.asarray(ids, dtype=np.int64).sum()) == g["id_sum"]
+    yield "er4096_seed1.json", n, e, w, U32
+    n, e, w = gen.grid(16, 16, 16, 0.05, seed=3)
+    yield "grid16_seed3.json", n, e, w, U32
+    n, e, w = gen.rmat(12, 16, seed=2)
+    yield "rmat12_seed2.json", n, e, w, F32
+
+
+def test_stored_goldens(ctx, pkg):
+    import json
+    for fname, n, e, w, wt in golden_cases():
+        g = json.load(open(os.path.join(GOLDEN, fname)))
+        ids, cnt, tot = ctx.solve(n, e, w, wtype=wt)
+        ids = np.asarray(ids, dtype=np.int64)
+        assert cnt == g["count"], fname
+        assert int(ids.sum()) == g["id_sum"], fname
+        if "total_u64" in g:
+            assert tot[0] == g["total_u64"], fname
+        else:
+            assert tot[1] == g["total_f64"], fname
+        if "first_ids" in g:
+            assert list(ids[:len(g["first_ids"])]) == g["first_ids"], fname
+        if "hooks_per_round" in g:
+            hooks = [h for h in g["hooks_per_round"] if h]
+            assert ctx.stats()["hooks"][:len(hooks)] == hooks, fname
 
 
 def test_tiny_random_graphs(ctx, pkg):
@@ -430,11 +453,9 @@ def test_shortcut_strategies_match_find_roots(ctx, pkg):
 
 # ------------------------------------------------------------ components --
 
-def test_components_match_bfs(ctx, pkg):
-    """Connectivity variant: the partition equals BFS components (scipy)."""
-    from scipy.sparse import coo_matrix
-    from scipy.sparse.csgraph import connected_components
-
+def test_components_match_oracle(ctx, pkg):
+    """Connectivity variant: the partition equals the oracle's components
+    (union-find; the oracle is itself pinned against BFS and scipy)."""
     cases = {
         "er4096": (4096, *gen.er(4096, 32768, seed=1)),
         "sparse many components": (20000, *gen.er(20000, 9000, seed=3)),
@@ -455,14 +476,13 @@ def test_components_match_bfs(ctx, pkg):
         torch.cuda.synchronize()
         g.close()
         got = lab.cpu().numpy()[:n].view(np.uint32).astype(np.int64)
-        a = coo_matrix((np.ones(len(e)), (e[:, 0], e[:, 1])), shape=(n, n))
-        ncomp, want = connected_components(a, directed=False)
-        # the same partition: labels are roots of their own component, and the
-        # smallest vertex of each component maps one-to-one onto the labels
+        want, ncomp = oracle.components(n, e)
+        want = want.astype(np.int64)
+        # the same partition: labels are roots of their own component, and
+        # the oracle's label (the component's smallest vertex) maps one-to-one
+        # onto the GPU's labels
         assert (got < n).all() and np.array_equal(got[got], got), label
-        first = np.full(ncomp, n, np.int64)
-        np.minimum.at(first, want, np.arange(n))
-        assert np.array_equal(got, got[first][want]), label
+        assert np.array_equal(got, got[want]), label
         assert len(np.unique(got)) == ncomp, label
         assert rounds <= max(1, math.ceil(math.log2(max(n, 2)))) + 1, (label, rounds)
 
@@ -551,21 +571,86 @@ def test_full_grid_256(ctx, pkg):
     say("grid stats", st)
 
 
-def test_full_batch_sampled(ctx, pkg):
+def test_full_batch_every_graph(ctx, pkg):
+    """All 10^4 graphs of the full batch against the oracle, one by one."""
     vo, eo, e, w = gen.workload_batch_10k()
     say("batch 10k full", int(vo[-1]), int(eo[-1]))
     ids, counts, totals = ctx.solve_batched(vo, eo, dev(e), dev(w), wtype=U32)
     torch.cuda.synchronize()
     ids = ids.cpu().numpy()
-    for g in list(range(0, 10000, 97)) + [9999]:
+    for g in range(10000):
         n = int(vo[g + 1] - vo[g])
         ee, ww = e[eo[g]:eo[g + 1]], w[eo[g]:eo[g + 1]]
         wi, wc, wtot = oracle.msf(n, ee, ww, U32)
         assert counts[g] == wc, g
         assert np.array_equal(ids[vo[g]:vo[g] + wc].astype(np.int64), wi), g
-        assert totals[g][0] == wtot[0], g
-    # every graph: count = n - components is implied by the forest; check sums
-    assert int(counts.sum()) == int(sum(counts))
+        assert totals[g][0] == wtot[0] and totals[g][1] == wtot[1], g
+
+
+class env_set:
+    """Set MSF_* environment variables for contexts created inside."""
+
+    def __init__(self, **kv):
+        self.kv = kv
+
+    def __enter__(self):
+        self.old = {k: os.environ.get(k) for k in self.kv}
+        os.environ.update(self.kv)
+
+    def __exit__(self, *a):
+        for k, v in self.old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+_FULL = {}
+
+
+def full_case(label):
+    """(n, e, w, wt, oracle result) of a full-size workload, kept for reuse."""
+    if label not in _FULL:
+        if label == "rmat s22":
+            n, e, w = gen.workload_rmat_s22()
+            wt = F32
+        else:
+            n, e, w = gen.workload_grid_256()
+            wt = U32
+        _FULL.clear()  # one full-size graph in host memory at a time
+        _FULL[label] = (n, e, w, wt, oracle.msf(n, e, w, wt))
+    return _FULL[label]
+
+
+def check_full(c, label, mode):
+    n, e, w, wt, (want_ids, want_cnt, want_tot) = full_case(label)
+    say(label, mode, f"n={n} m={len(e)}")
+    ids, cnt, tot = c.solve(n, dev(e), dev(w), wtype=wt)
+    torch.cuda.synchronize()
+    assert cnt == want_cnt, (label, mode)
+    assert np.array_equal(ids.cpu().numpy().astype(np.int64), want_ids), (label, mode)
+    assert tot[1] == want_tot[1] and (wt == F32 or tot[0] == want_tot[0]), (label, mode)
+    return c.stats()
+
+
+@pytest.mark.parametrize("label", ["rmat s22", "grid 256"])
+def test_full_size_server_slot_path(pkg, label):
+    """The path every server slot takes (one-level build, full sweep with
+    the filtering policy, no head sweep) at full size."""
+    with env_set(MSF_BUCKETED_BUILD="2", MSF_HEADS="0"):
+        c = pkg.Context(0)
+    st = check_full(c, label, "one-level build, full sweep")
+    assert st["head_sweeps"] == 0 and st["runs"] == 0
+    c.close()
+
+
+@pytest.mark.parametrize("label", ["rmat s22", "grid 256"])
+def test_full_size_device_atomic_build(pkg, label):
+    """The device-atomic adjacency build at full size."""
+    with env_set(MSF_BUCKETED_BUILD="0"):
+        c = pkg.Context(0)
+    check_full(c, label, "device-atomic build")
+    c.close()
 
 
 def test_column_slices_are_result_invariant(pkg):

@@ -136,3 +136,34 @@ def test_concurrent_submitters(ctx, pkg):
         ids, cnt, tot = out[k]
         assert np.array_equal(ids.astype(np.int64), oracle.msf(n, e, w, F32)[0])
     srv.close()
+
+
+def test_full_pool_at_real_sizes(ctx, pkg):
+    """The whole served pool at its real sizes (R-MAT up to scale 21 with
+    edge factor 16, grids up to about 148^3), submitted with overlapping
+    arrivals under a 32 GiB budget: every result equals the oracle's forest
+    (ids, count, totals) and the solo msf_solve of the same request."""
+    t0 = time.time()
+    pool = gen.serve_pool(64, seed=5)
+    say("full served pool generated", len(pool), f"{time.time() - t0:.1f}s",
+        sum(len(p[1]) for p in pool), "edges")
+    srv = pkg.Server(ctx, 32 << 30)
+    order = list(range(len(pool)))
+    np.random.default_rng(3).shuffle(order)
+    tickets = []
+    for i, k in enumerate(order):
+        n, e, w, kind = pool[k]
+        tickets.append((srv.submit(n, e, w, wtype=F32), k))
+        if i % 4 == 3:
+            time.sleep(0.003)  # later requests arrive while earlier ones run
+    for t, k in tickets:
+        n, e, w, kind = pool[k]
+        ids, cnt, tot = srv.result(t, n)
+        want_ids, want_cnt, want_tot = oracle.msf(n, e, w, F32)
+        assert cnt == want_cnt, (k, kind, n)
+        assert np.array_equal(ids.astype(np.int64), want_ids), (k, kind, n)
+        assert tot[1] == want_tot[1], (k, kind, n)
+        sids, scnt, stot = ctx.solve(n, e, w, wtype=F32)
+        assert scnt == cnt and np.array_equal(sids, ids) and stot == tot, (k, kind, n)
+    say("full served pool checked", f"{time.time() - t0:.1f}s")
+    srv.close()

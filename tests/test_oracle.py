@@ -495,3 +495,96 @@ def test_batch_sizes():
     for g in range(0, 300, 37):
         loc = e[eo[g]:eo[g + 1]]
         assert loc.min() >= 0 and loc.max() < nn[g]
+
+
+# ------------------------------------------------ connected components --
+# oracle.components is pinned by breadth-first search (test-local, above),
+# by scipy's connected_components (a library routine of its own) and by
+# closed forms: the labels must give exactly the same partition, and each
+# label must be the smallest vertex of its component.
+
+def _same_partition_min_labels(n, lab, comp):
+    lab = np.asarray(lab, dtype=np.int64)
+    comp = np.asarray(comp, dtype=np.int64)
+    # label -> component and component -> label are both functions
+    pairs = set(zip(lab.tolist(), comp.tolist()))
+    assert len(pairs) == len(set(lab.tolist())) == len(set(comp.tolist()))
+    # each label is the smallest vertex of its component
+    smallest = {}
+    for v in range(n):
+        smallest.setdefault(int(comp[v]), v)
+    assert all(lab[v] == smallest[int(comp[v])] for v in range(n))
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_components_equal_bfs_tiny(seed):
+    rng = random.Random(1000 + seed)
+    n = rng.randint(0, 30)
+    m = rng.randint(0, 40) if n else 0
+    edges = [(rng.randrange(n), rng.randrange(n)) for _ in range(m)]
+    lab, cnt = oracle.components(n, np.array(edges, dtype=np.int32).reshape(-1, 2))
+    c, comp = components(n, edges)
+    assert cnt == c
+    _same_partition_min_labels(n, lab, comp)
+
+
+@pytest.mark.parametrize("kind", ["rmat", "grid", "sparse"])
+def test_components_equal_scipy(kind):
+    if kind == "rmat":
+        n, e, _ = gen.rmat(14, 4, seed=9)
+    elif kind == "grid":
+        n, e, _ = gen.grid(20, 20, 20, 0.4, seed=5)
+    else:
+        n, m = 20000, 9000
+        e, _ = gen.er(n, m, seed=8)
+    lab, cnt = oracle.components(n, e)
+    A = sp.coo_matrix((np.ones(len(e)), (e[:, 0], e[:, 1])), shape=(n, n))
+    c, comp = connected_components(A, directed=False)
+    assert cnt == c
+    # same partition: the pairs (label, scipy label) form a bijection
+    pairs = np.unique(np.stack([lab.astype(np.int64), comp.astype(np.int64)]), axis=1)
+    assert pairs.shape[1] == c == len(np.unique(lab))
+    # labels are component minima: the smallest vertex carrying each label is that label
+    first = np.full(n, -1, dtype=np.int64)
+    order = np.arange(n)[::-1]
+    first[lab[order]] = order
+    assert np.all(first[np.unique(lab)] == np.unique(lab))
+
+
+def test_components_closed_forms():
+    # no edges: every vertex alone
+    lab, c = oracle.components(5, np.zeros((0, 2), np.int32))
+    assert c == 5 and list(lab) == [0, 1, 2, 3, 4]
+    # a path in reverse order is one component labelled 0
+    n = 50
+    e = np.array([[i + 1, i] for i in reversed(range(n - 1))], np.int32)
+    lab, c = oracle.components(n, e)
+    assert c == 1 and np.all(lab == 0)
+    # k disjoint copies of a triangle plus a loop: k components labelled 3j
+    k = 7
+    e = np.array([[3 * j + a, 3 * j + b] for j in range(k)
+                  for a, b in ((0, 1), (1, 2), (2, 2))], np.int32)
+    lab, c = oracle.components(3 * k, e)
+    assert c == k and list(lab) == [3 * (i // 3) for i in range(3 * k)]
+    with pytest.raises(ValueError):
+        oracle.components(3, np.array([[0, 3]], np.int32))
+
+
+def test_oracle_reproduces_stored_goldens():
+    """The stored expected values under tests/golden/ (written by
+    make_golden.py from this oracle) still come out of it unchanged."""
+    import json
+    import os
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    cases = [("er4096_seed1.json", *gen.workload_er_4096(), U32),
+             ("grid16_seed3.json", *gen.grid(16, 16, 16, 0.05, seed=3), U32),
+             ("rmat12_seed2.json", *gen.rmat(12, 16, seed=2), F32)]
+    for fname, n, e, w, wt in cases:
+        g = json.load(open(os.path.join(here, fname)))
+        ids, cnt, tot = oracle.msf(n, e, w, wt)
+        assert cnt == g["count"] and int(ids.sum()) == g["id_sum"], fname
+        assert (tot[0] == g["total_u64"]) if "total_u64" in g else (tot[1] == g["total_f64"])
+        if "first_ids" in g:
+            assert list(ids[:16]) == g["first_ids"]
+        if "hooks_per_round" in g:
+            assert oracle.as_rounds(n, e, w, wt)["hooks"] == g["hooks_per_round"]
