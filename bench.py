@@ -435,12 +435,35 @@ def bench_batched(ctx, pkg, torch, G=10000, cpu=True):
     de = torch.from_numpy(e.reshape(-1).copy()).to("cuda:0")
     dw = torch.from_numpy(w.view(np.int32).copy()).to("cuda:0")
     out = torch.empty(int(vo[-1]), dtype=torch.int32, device="cuda:0")
-    ctx.solve_batched(vo, eo, de, dw, wtype=pkg.W_U32, out=out)  # warm
+    ctx.solve_batched(vo, eo, de, dw, wtype=pkg.W_U32, out=out)  # warm (and tune)
+    torch.cuda.synchronize()
+    reps = 5
+    t = time.perf_counter()
+    for _ in range(reps):
+        ids, counts, totals = ctx.solve_batched(vo, eo, de, dw, wtype=pkg.W_U32, out=out)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t) / reps
+    st = ctx.stats()
+    cfgs = pkg.batch_configs()
+    kernel_ms = st["batch_ms"]
+    # the same batch through the disjoint union and the round loop
+    old = os.environ.get("MSF_BATCH_MODE")
+    os.environ["MSF_BATCH_MODE"] = "0"
+    try:
+        cu = pkg.Context(0)
+    finally:
+        if old is None:
+            os.environ.pop("MSF_BATCH_MODE", None)
+        else:
+            os.environ["MSF_BATCH_MODE"] = old
+    cu.solve_batched(vo, eo, de, dw, wtype=pkg.W_U32, out=out)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    ids, counts, totals = ctx.solve_batched(vo, eo, de, dw, wtype=pkg.W_U32, out=out)
+    cu.solve_batched(vo, eo, de, dw, wtype=pkg.W_U32, out=out)
     torch.cuda.synchronize()
-    tb = time.perf_counter() - t
+    t_union = time.perf_counter() - t
+    cu.close()
+    ids, counts, totals = ctx.solve_batched(vo, eo, de, dw, wtype=pkg.W_U32, out=out)
     # plain: one msf_solve per graph on the same context and stream (sample
     # of graphs, scaled to the batch by its edge share)
     step = max(1, G // 500)
@@ -456,8 +479,15 @@ def bench_batched(ctx, pkg, torch, G=10000, cpu=True):
         ctx.solve(int(vo[g + 1] - vo[g]), ee[g_i], ww[g_i], wtype=pkg.W_U32, out=one)
     torch.cuda.synchronize()
     tp = (time.perf_counter() - t) / len(sample)  # seconds per graph
+    ci = st["batch_config"]
     res = {"graphs": G, "vertices": int(vo[-1]), "edges": int(eo[-1]),
            "batched_s": tb, "batched_graphs_per_s": G / tb,
+           "batched_edges_per_s": float(eo[-1]) / tb,
+           "persistent_kernel_ms": kernel_ms,
+           "config": {"index": ci, "threads": cfgs[ci][0], "edges_per_thread": cfgs[ci][1],
+                      "lds_bytes": cfgs[ci][2], "workgroups": st["batch_grid"]}
+           if ci >= 0 else None,
+           "union_path_s": t_union, "union_path_graphs_per_s": G / t_union,
            "plain_graphs_per_s": 1.0 / tp, "plain_sample_graphs": len(sample),
            "speedup": (G / tb) * tp}
     if cpu:

@@ -96,7 +96,10 @@ typedef struct {
                                 live root (its minimum slot)                 */
     int32_t head_sweeps;     /* rounds swept over key-sorted runs (heads
                                 only; their sweep_bytes are 0)               */
-    int32_t reserved;
+    int32_t path;            /* msf_solve: 0 rounds of device-wide launches,
+                                1 one workgroup solved the whole graph in
+                                LDS (small graphs; rounds and hooks are set,
+                                rounds_ms is its kernel time)                */
     int64_t runs;            /* key-sorted runs of the adjacency (0: none)   */
     /* Device time (events) and algorithmic bytes of one-launch passes, 0
        when not run.  Index 0: placement of the two-level build (per stored
@@ -110,6 +113,15 @@ typedef struct {
        record and 1-byte fine bucket written). */
     double pass_ms[4];
     double pass_bytes[4];
+    /* msf_solve_batched only: the persistent launch's candidate
+       configuration (msf_batch_configs index; -1 when none ran), its
+       workgroups, the graphs it solved, the graphs solved one by one
+       instead (too large for one workgroup), and its device time. */
+    int32_t batch_config;
+    int32_t batch_grid;
+    int64_t batch_graphs;
+    int64_t batch_large;
+    double batch_ms;
 } msf_stats;
 
 typedef struct msf_ctx msf_ctx;
@@ -262,6 +274,17 @@ msf_status msf_solve_starcheck(msf_ctx *ctx, const msf_graph *g, uint8_t *in_for
  * vtx_off[g]; counts int64[G] (host) and totals msf_total[G] (host,
  * nullable).  Each graph's result equals msf_solve on that graph alone.
  */
+/*
+ * Launch configurations the batched solve chooses from (its tuner times
+ * each on a sample of a batch and caches the fastest per batch shape; the
+ * environment variable MSF_BATCH_CONFIG=<index> forces one).  Writes up to
+ * cap entries: threads per workgroup, edges each thread loads per step of a
+ * sweep, and dynamic LDS bytes per workgroup (graphs whose state fits it
+ * are solved in LDS).  Returns the number of candidates; arrays may be NULL
+ * to query the count.  Every candidate gives bit-identical results.
+ */
+int msf_batch_configs(int32_t *nt, int32_t *ept, int32_t *lds_bytes, int32_t cap);
+
 msf_status msf_solve_batched(msf_ctx *ctx, int32_t G, const int64_t *vtx_off,
                              const int64_t *edge_off, const int32_t *edges, const void *weights,
                              msf_wtype wtype, msf_mem mem, int32_t *forest_ids, int64_t *counts,

@@ -37,7 +37,7 @@ EXPORTS = [
     "msf_solve_starcheck",
     "msf_shortcut", "msf_solve_batched", "msf_server_create", "msf_server_destroy",
     "msf_server_submit", "msf_server_poll", "msf_server_latency", "msf_server_result",
-    "msf_request_footprint",
+    "msf_request_footprint", "msf_batch_configs",
 ]
 
 
@@ -57,9 +57,11 @@ class Stats(ctypes.Structure):
                 ("hooks", ctypes.c_int64 * 64), ("active_nnz", ctypes.c_int64 * 64),
                 ("build_ms", ctypes.c_double), ("rounds_ms", ctypes.c_double),
                 ("sweep_ms", ctypes.c_double * 64), ("sweep_bytes", ctypes.c_double * 64),
-                ("head_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("head_sweeps", ctypes.c_int32), ("path", ctypes.c_int32),
                 ("runs", ctypes.c_int64), ("pass_ms", ctypes.c_double * 4),
-                ("pass_bytes", ctypes.c_double * 4)]
+                ("pass_bytes", ctypes.c_double * 4), ("batch_config", ctypes.c_int32),
+                ("batch_grid", ctypes.c_int32), ("batch_graphs", ctypes.c_int64),
+                ("batch_large", ctypes.c_int64), ("batch_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -119,6 +121,8 @@ def lib():
     L.msf_server_result.restype = st
     L.msf_request_footprint.argtypes = [I32, I64]
     L.msf_request_footprint.restype = ctypes.c_size_t
+    L.msf_batch_configs.argtypes = [P, P, P, I32]
+    L.msf_batch_configs.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -161,6 +165,18 @@ def _dev(t, name: str, numel: int, elem: int):
 
 def _host(a, dtype) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def batch_configs() -> list:
+    """The batched solve's launch configurations: (threads per workgroup,
+    edges per thread and step, dynamic LDS bytes), in index order."""
+    L = lib()
+    k = L.msf_batch_configs(None, None, None, 0)
+    a = (ctypes.c_int32 * k)()
+    b = (ctypes.c_int32 * k)()
+    c = (ctypes.c_int32 * k)()
+    L.msf_batch_configs(a, b, c, k)
+    return [(a[i], b[i], c[i]) for i in range(k)]
 
 
 def footprint(n: int, m: int) -> int:
@@ -239,9 +255,12 @@ class Context:
         return dict(rounds=s.rounds, hook_rounds=s.hook_rounds, max_chase=s.max_chase,
                     filtered=s.filtered, hooks=list(s.hooks[:k]),
                     active_nnz=list(s.active_nnz[:k]), build_ms=s.build_ms,
-                    rounds_ms=s.rounds_ms, sweep_ms=list(s.sweep_ms[:k]),
+                    rounds_ms=s.rounds_ms, sweep_ms=list(s.sweep_ms[:k]), path=s.path,
                     sweep_bytes=list(s.sweep_bytes[:k]), head_sweeps=s.head_sweeps,
-                    runs=s.runs, pass_ms=list(s.pass_ms), pass_bytes=list(s.pass_bytes))
+                    runs=s.runs, pass_ms=list(s.pass_ms), pass_bytes=list(s.pass_bytes),
+                    batch_config=s.batch_config, batch_grid=s.batch_grid,
+                    batch_graphs=s.batch_graphs, batch_large=s.batch_large,
+                    batch_ms=s.batch_ms)
 
     # ------------------------------------------------------- primitives --
     def graph(self, n: int, edges, weights, wtype: int | None = None) -> "Graph":

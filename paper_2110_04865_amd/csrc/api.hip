@@ -9,6 +9,7 @@
 #include <new>
 
 #include "msf_internal.hpp"
+#include "persist.hpp"
 
 namespace msf {
 
@@ -144,6 +145,8 @@ msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc)
     if (const char *f = getenv("MSF_BUCKETED_BUILD")) c->bucketed_build = atoi(f);
     if (const char *f = getenv("MSF_SLICES")) c->slices = atoi(f);
     if (const char *f = getenv("MSF_HEADS")) c->heads = atoi(f);
+    if (const char *f = getenv("MSF_BATCH_MODE")) c->batch_mode = atoi(f);
+    if (const char *f = getenv("MSF_SMALL_M")) c->small_m = atoll(f);
     return MSF_OK;
 }
 
@@ -272,7 +275,8 @@ msf_status msf_solve(msf_ctx *ctx, int32_t n, int64_t m, const int32_t *edges, c
     }
     int64_t cnt = 0;
     msf_total tot{0, 0.0};
-    rc = solve_device(c, n, m, d_edges, d_w, wt, d_ids, &cnt, &tot);
+    rc = small_eligible(c, n, m) ? solve_small(c, n, m, d_edges, d_w, wt, d_ids, &cnt, &tot)
+                                 : solve_device(c, n, m, d_edges, d_w, wt, d_ids, &cnt, &tot);
     if (rc) return rc;
     if (mem == MSF_MEM_HOST && cnt > 0) {
         MSF_HIP(hipMemcpyAsync(forest_ids, d_ids, 4 * (size_t)cnt, hipMemcpyDeviceToHost,

@@ -12,7 +12,9 @@
 #include <vector>
 #include <cstring>
 
+#include "exact_sum.hpp"
 #include "msf_internal.hpp"
+#include "persist.hpp"
 #include "wave.hpp"
 
 namespace msf {
@@ -65,10 +67,8 @@ __global__ __launch_bounds__(256) void k_split(const int32_t *__restrict__ gids,
                                                uint64_t *__restrict__ tot_u64,
                                                double *__restrict__ tot_f64)
 {
-    constexpr int D = 10;
-    __shared__ int64_t s_acc[D][4];
-    __shared__ uint64_t s_u[4];
-    __shared__ uint32_t s_inf[2];
+    __shared__ int64_t s_sum[(256 / 64) * (ACC_DIGITS + 1)];
+    __shared__ int64_t s_tot[WS_WORDS];
     const int32_t g = blockIdx.x;
     const int64_t e0 = edge_off[g], e1 = edge_off[g + 1];
     // lower bounds of e0 and e1 in gids[0..count)
@@ -83,115 +83,238 @@ __global__ __launch_bounds__(256) void k_split(const int32_t *__restrict__ gids,
     };
     const int64_t a = lb(e0), b = lb(e1);
     const int64_t base = vtx_off[g];
-    uint64_t su = 0;
-    int64_t acc[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) acc[d] = 0;
-    uint32_t pinf = 0, ninf = 0;
+    WSum ws;
     for (int64_t k = a + threadIdx.x; k < b; k += blockDim.x) {
         const int64_t e = gids[k];
         out[base + (k - a)] = (int32_t)(e - e0);
         const uint32_t bits = ((const uint32_t *)w)[e];
-        if (WT == MSF_W_U32) {
-            su += bits;
-        } else {
-            const uint32_t ex = (bits >> 23) & 0xFFu;
-            const bool neg = (bits >> 31) != 0;
-            if (ex == 0xFFu) {
-                if (neg) ++ninf;
-                else ++pinf;
-                continue;
-            }
-            const uint64_t mant = ex ? ((bits & 0x7FFFFFu) | 0x800000u) : (bits & 0x7FFFFFu);
-            const uint32_t sh = ex ? ex - 1u : 0u;
-            const uint64_t x = mant << (sh & 31u);
-            const uint32_t di = sh >> 5;
-            const int64_t lo = (int64_t)(x & 0xFFFFFFFFull), hi = (int64_t)(x >> 32);
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                int64_t add = (d == (int)di) ? lo : ((d == (int)di + 1) ? hi : 0);
-                acc[d] += neg ? -add : add;
-            }
-        }
+        if (WT == MSF_W_U32) ws.su += bits;
+        else wsum_add_bits(ws, bits);
     }
-    const int wv = threadIdx.x >> 6;
-    if (WT == MSF_W_U32) {
-        su = wave_sum(su);
-        if (__lane_id() == 0) s_u[wv] = su;
-    } else {
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const int64_t v = wave_sum(acc[d]);
-            if (__lane_id() == 0) s_acc[d][wv] = v;
-        }
-        pinf = wave_sum(pinf);
-        ninf = wave_sum(ninf);
-        if (threadIdx.x == 0) s_inf[0] = s_inf[1] = 0;
-    }
-    __syncthreads();
-    if (WT != MSF_W_U32 && __lane_id() == 0 && (pinf | ninf)) {
-        atomicAdd(&s_inf[0], pinf);
-        atomicAdd(&s_inf[1], ninf);
-    }
-    __syncthreads();
+    wsum_block<256, WT>(ws, s_sum, s_tot, 1);
     if (threadIdx.x != 0) return;
     counts[g] = b - a;
-    if (WT == MSF_W_U32) {
-        const uint64_t s = s_u[0] + s_u[1] + s_u[2] + s_u[3];
-        tot_u64[g] = s;
-        tot_f64[g] = (double)s;
-        return;
-    }
-    tot_u64[g] = 0;
-    if (s_inf[0] || s_inf[1]) {
-        tot_f64[g] = (s_inf[0] && s_inf[1]) ? __builtin_nan("")
-                     : (s_inf[0] ? __builtin_inf() : -__builtin_inf());
-        return;
-    }
-    uint32_t dig[D];
-    int64_t carry = 0;
-    for (int d = 0; d < D; ++d) {
-        const int64_t v = s_acc[d][0] + s_acc[d][1] + s_acc[d][2] + s_acc[d][3] + carry;
-        dig[d] = (uint32_t)(v & 0xFFFFFFFFll);
-        carry = v >> 32;
-    }
-    const bool neg = carry < 0;
-    if (neg) {
-        uint64_t c = 1;
-        for (int d = 0; d < D; ++d) {
-            const uint64_t v = (uint64_t)(uint32_t)~dig[d] + c;
-            dig[d] = (uint32_t)v;
-            c = v >> 32;
-        }
-    }
-    int top = -1;
-    for (int d = D - 1; d >= 0 && top < 0; --d)
-        if (dig[d]) top = d * 32 + 31 - __builtin_clz(dig[d]);
-    double outv = 0.0;
-    if (top >= 0) {
-        auto bit = [&](int i) -> uint32_t { return i < 0 ? 0u : (dig[i >> 5] >> (i & 31)) & 1u; };
-        uint64_t q = 0;
-        const int lo = top - 52;
-        int scale = lo;
-        if (lo < 0) {
-            scale = 0;
-            for (int i = top; i >= 0; --i) q = (q << 1) | bit(i);
+    tot_u64[g] = WT == MSF_W_U32 ? (uint64_t)s_tot[0] : 0;
+    tot_f64[g] = exact_total_f64((uint64_t)s_tot[0], s_tot + 1, (uint32_t)s_tot[1 + ACC_DIGITS],
+                                 (uint32_t)s_tot[2 + ACC_DIGITS], WT);
+}
+
+
+// Batched solve by the persistent kernel (kernels_persist.hip) for every
+// graph it takes, and one msf_solve-equivalent per graph for the rest.
+// Writes each graph's ids into d_stage (device, at vtx_off[g]) and its
+// count and totals into hres (host: counts, then u64 totals, then f64
+// totals as bits); on any error nothing outside the workspace is written.
+msf_status batched_persistent(Ctx *c, int32_t G, const int64_t *vtx_off, const int64_t *edge_off,
+                              const int64_t *d_voff, const int64_t *d_eoff,
+                              const int32_t *d_edges, const void *d_w, msf_wtype wt,
+                              int32_t *d_stage, int64_t *d_counts, uint64_t *d_tu,
+                              double *d_tf, int64_t *hres)
+{
+    hipStream_t s = c->stream;
+    std::vector<uint32_t> order, large;
+    uint32_t n_cap = 1, m_cap = 1;
+    double sum_n = 0.0, sum_m = 0.0;
+    for (int32_t g = 0; g < G; ++g) {
+        const int64_t n = vtx_off[g + 1] - vtx_off[g], m = edge_off[g + 1] - edge_off[g];
+        if (n <= (int64_t)PERSIST_MAX_N && m <= (int64_t)PERSIST_MAX_M) {
+            order.push_back((uint32_t)g);
+            n_cap = std::max(n_cap, (uint32_t)n);
+            m_cap = std::max(m_cap, (uint32_t)m);
+            sum_n += (double)n;
+            sum_m += (double)m;
         } else {
-            for (int i = top; i >= lo; --i) q = (q << 1) | bit(i);
-            const uint32_t rb = bit(lo - 1);
-            uint32_t sticky = 0;
-            for (int i = lo - 2; i >= 0 && !sticky; --i) sticky |= bit(i);
-            if (rb && (sticky || (q & 1u))) {
-                ++q;
-                if (q == (1ull << 53)) {
-                    q >>= 1;
-                    ++scale;
-                }
-            }
+            large.push_back((uint32_t)g);
         }
-        outv = ldexp((double)q, scale - 149);
     }
-    tot_f64[g] = neg ? -outv : outv;
+    c->stats = msf_stats{};
+    c->stats.batch_config = -1;
+    c->stats.batch_graphs = (int64_t)order.size();
+    c->stats.batch_large = (int64_t)large.size();
+    const uint32_t Gs = (uint32_t)order.size();
+    msf_status rc;
+    if (Gs > 0) {
+        // largest first, so the last graphs to start are the small ones
+        std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+            const int64_t mx = edge_off[x + 1] - edge_off[x], my = edge_off[y + 1] - edge_off[y];
+            if (mx != my) return mx > my;
+            return vtx_off[x + 1] - vtx_off[x] > vtx_off[y + 1] - vtx_off[y];
+        });
+        // a sample with the batch's size mix for the tuner: every k-th graph
+        std::vector<uint32_t> sample;
+        const uint32_t step = std::max<uint32_t>(1, Gs / 256);
+        for (uint32_t i = 0; i < Gs; i += step) sample.push_back(order[i]);
+        int cus = 0;
+        MSF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+        int ncand = 0;
+        const PersistCfg *cand = persist_candidates(&ncand);
+        std::vector<int> bpc(ncand, 0);
+        uint32_t slots = 1;
+        for (int i = 0; i < ncand; ++i) {
+            if (!persist_cfg_fits(c->device, cand[i])) continue;
+            bpc[i] = persist_blocks_per_cu(cand[i], wt);
+            slots = std::max<uint32_t>(slots, (uint32_t)std::max(1, cus * bpc[i]));
+        }
+        // at most four workgroups per compute unit keep a slot (a slot holds
+        // two live-edge lists of the largest graph: 32 bytes per edge)
+        slots = std::min({slots, Gs, (uint32_t)std::max(1, 4 * cus)});
+        const size_t slot_bytes = persist_slot_bytes(n_cap, m_cap);
+        void *vord, *vctl, *vscr;
+        if ((rc = ws_get(c, WS_PORDER, 4 * ((size_t)Gs + sample.size()), &vord))) return rc;
+        if ((rc = ws_get(c, WS_PCTL, 256, &vctl))) return rc;
+        if ((rc = ws_get(c, WS_PSCRATCH, slot_bytes * slots, &vscr))) return rc;
+        uint32_t *d_order = (uint32_t *)vord, *d_sample = d_order + Gs;
+        uint32_t *d_ctl = (uint32_t *)vctl;
+        MSF_HIP(hipMemcpyAsync(d_order, order.data(), 4 * (size_t)Gs, hipMemcpyHostToDevice, s));
+        MSF_HIP(hipMemcpyAsync(d_sample, sample.data(), 4 * sample.size(), hipMemcpyHostToDevice,
+                               s));
+        PersistArgs A;
+        A.queue = d_ctl;
+        A.err = d_ctl + 1;
+        A.vtx_off = d_voff;
+        A.edge_off = d_eoff;
+        A.edges = d_edges;
+        A.w = (const uint32_t *)d_w;
+        A.out = d_stage;
+        A.counts = d_counts;
+        A.tot_u64 = d_tu;
+        A.tot_f64 = d_tf;
+        A.scratch = (uint8_t *)vscr;
+        A.slot_bytes = slot_bytes;
+        A.m_cap = m_cap;
+        auto grid_of = [&](int i, uint32_t graphs) {
+            return (unsigned)std::max<uint32_t>(
+                1, std::min<uint32_t>({graphs, slots, (uint32_t)std::max(1, cus * bpc[i])}));
+        };
+        auto run = [&](int i, float *ms) -> msf_status {
+            PersistArgs T = A;
+            T.G = (int32_t)sample.size();
+            T.order = d_sample;
+            T.lds_bytes = cand[i].lds;
+            if (ms) MSF_HIP(hipEventRecord(c->ev[0], s));
+            MSF_HIP(launch_persist(s, T, cand[i], (int)wt, grid_of(i, T.G)));
+            if (ms) {
+                MSF_HIP(hipEventRecord(c->ev[1], s));
+                MSF_HIP(hipEventSynchronize(c->ev[1]));
+                MSF_HIP(hipEventElapsedTime(ms, c->ev[0], c->ev[1]));
+            }
+            return MSF_OK;
+        };
+        BatchShape shape;
+        shape.mean_n = sum_n / Gs;
+        shape.mean_deg = sum_n > 0 ? 2.0 * sum_m / sum_n : 0.0;
+        int ci = 0;
+        if ((rc = persist_pick(c, shape, (int)wt, run, &ci))) return rc;
+        A.G = (int32_t)Gs;
+        A.order = d_order;
+        A.lds_bytes = cand[ci].lds;
+        const unsigned grid = grid_of(ci, Gs);
+        MSF_HIP(hipEventRecord(c->ev[0], s));
+        MSF_HIP(launch_persist(s, A, cand[ci], (int)wt, grid));
+        MSF_HIP(hipEventRecord(c->ev[1], s));
+        c->stats.batch_config = ci;
+        c->stats.batch_grid = (int32_t)grid;
+    }
+    MSF_HIP(hipMemcpyAsync(hres, d_counts, 24 * (size_t)G, hipMemcpyDeviceToHost, s));
+    uint32_t herr = 0;
+    if (Gs > 0) {
+        void *vctl;
+        if ((rc = ws_get(c, WS_PCTL, 256, &vctl))) return rc;
+        MSF_HIP(hipMemcpyAsync(&herr, (uint32_t *)vctl + 1, 4, hipMemcpyDeviceToHost, s));
+    }
+    MSF_HIP(hipStreamSynchronize(s));
+    if (Gs > 0) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+        c->stats.batch_ms = ms;
+    }
+    if ((rc = decode_err(herr))) return rc;
+    // graphs too large for one workgroup: one solve each, into the staging
+    for (uint32_t g : large) {
+        const int64_t v0 = vtx_off[g], e0 = edge_off[g];
+        int64_t cnt = 0;
+        msf_total tot{0, 0.0};
+        const msf_stats keep = c->stats;
+        rc = solve_device(c, (int32_t)(vtx_off[g + 1] - v0), edge_off[g + 1] - e0,
+                          d_edges + 2 * e0, (const uint32_t *)d_w + e0, wt, d_stage + v0, &cnt,
+                          &tot);
+        c->stats = keep;
+        if (rc) return rc;
+        hres[g] = cnt;
+        hres[G + g] = (int64_t)tot.u64;
+        std::memcpy(&hres[2 * (size_t)G + g], &tot.f64, sizeof(double));
+    }
+    return MSF_OK;
+}
+
+
+bool small_eligible(const Ctx *c, int32_t n, int64_t m)
+{
+    return c->small_m > 0 && m > 0 && m <= c->small_m && (uint32_t)n <= PERSIST_MAX_N &&
+           persist_state_bytes((uint32_t)n, (uint32_t)m) <= SMALL_LDS &&
+           persist_cfg_fits(c->device, PersistCfg{1024, 4, SMALL_LDS});
+}
+
+msf_status solve_small(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
+                       msf_wtype wt, int32_t *d_ids, int64_t *count, msf_total *total)
+{
+    hipStream_t s = c->stream;
+    c->ml_pending = false;
+    void *vctl, *vscr;
+    msf_status rc;
+    if ((rc = ws_get(c, WS_PCTL, 512, &vctl))) return rc;
+    if ((rc = ws_get(c, WS_PSCRATCH, persist_slot_bytes((uint32_t)n, (uint32_t)m), &vscr)))
+        return rc;
+    // control block: queue, error word; at byte 64 the offsets, then the
+    // count, totals, the order and the per-round hooks
+    uint8_t *ctl = (uint8_t *)vctl;
+    PersistArgs A;
+    A.G = 1;
+    A.queue = (uint32_t *)ctl;
+    A.err = (uint32_t *)ctl + 1;
+    A.vtx_off = (int64_t *)(ctl + 64);
+    A.edge_off = (int64_t *)(ctl + 80);
+    A.counts = (int64_t *)(ctl + 96);
+    A.tot_u64 = (uint64_t *)(ctl + 104);
+    A.tot_f64 = (double *)(ctl + 112);
+    A.order = (uint32_t *)(ctl + 120);
+    A.round_hooks = (uint32_t *)(ctl + 128);
+    A.edges = d_edges;
+    A.w = (const uint32_t *)d_w;
+    A.out = d_ids;
+    A.scratch = (uint8_t *)vscr;
+    A.slot_bytes = persist_slot_bytes((uint32_t)n, (uint32_t)m);
+    A.m_cap = (uint32_t)m;
+    A.lds_bytes = SMALL_LDS;
+    launch_small_setup(s, (int64_t *)A.vtx_off, (int64_t *)A.edge_off, (uint32_t *)A.order, n, m);
+    MSF_HIP(hipEventRecord(c->ev[0], s));
+    MSF_HIP(launch_persist(s, A, PersistCfg{1024, 4, SMALL_LDS}, (int)wt, 1));
+    MSF_HIP(hipEventRecord(c->ev[1], s));
+    alignas(8) uint8_t h[512];
+    MSF_HIP(hipMemcpyAsync(h, ctl, 512, hipMemcpyDeviceToHost, s));
+    MSF_HIP(hipStreamSynchronize(s));
+    uint32_t err;
+    std::memcpy(&err, h + 4, 4);
+    if ((rc = decode_err(err))) return rc;
+    const uint32_t *hooks = (const uint32_t *)(h + 128);
+    msf_stats st{};
+    st.batch_config = -1;
+    st.path = 1;
+    st.rounds = (int32_t)hooks[64];
+    for (int k = 0; k < st.rounds && k < 64; ++k) {
+        st.hooks[k] = hooks[k];
+        st.hook_rounds += hooks[k] != 0;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+    st.rounds_ms = ms;
+    c->stats = st;
+    std::memcpy(count, h + 96, 8);
+    if (total) {
+        std::memcpy(&total->u64, h + 104, 8);
+        std::memcpy(&total->f64, h + 112, 8);
+    }
+    return MSF_OK;
 }
 
 }  // namespace msf
@@ -243,10 +366,9 @@ extern "C" msf_status msf_solve_batched(msf_ctx *ctx, int32_t G, const int64_t *
     MSF_HIP(hipSetDevice(c->device));
     hipStream_t s = c->stream;
     const size_t mm = (size_t)std::max<int64_t>(M, 1), nn = (size_t)std::max<int64_t>(N, 1);
-    void *voff, *vge, *vgid, *vout, *vw = nullptr, *vin = nullptr, *vres;
+    void *voff, *vge = nullptr, *vgid, *vout = nullptr, *vw = nullptr, *vin = nullptr, *vres;
     msf_status rc;
     if ((rc = ws_get(c, WS_BATCH0, 8 * 2 * (size_t)(G + 1), &voff))) return rc;
-    if ((rc = ws_get(c, WS_BATCH1, 8 * mm, &vge))) return rc;
     if ((rc = ws_get(c, WS_BATCH2, 4 * nn, &vgid))) return rc;
     if ((rc = ws_get(c, WS_BATCH3, (8 + 8 + 8) * (size_t)G, &vres))) return rc;
     int64_t *d_voff = (int64_t *)voff, *d_eoff = d_voff + (G + 1);
@@ -258,7 +380,7 @@ extern "C" msf_status msf_solve_batched(msf_ctx *ctx, int32_t G, const int64_t *
     if (mem == MSF_MEM_HOST) {
         if ((rc = ws_get(c, WS_EDGES, 8 * mm, &vin))) return rc;
         if ((rc = ws_get(c, WS_W, 4 * mm, &vw))) return rc;
-        if ((rc = ws_get(c, WS_IDS, 4 * nn, &vout))) return rc;
+        if (c->batch_mode == 0 && (rc = ws_get(c, WS_IDS, 4 * nn, &vout))) return rc;
         if (M > 0) {
             MSF_HIP(hipMemcpyAsync(vin, edges, 8 * (size_t)M, hipMemcpyHostToDevice, s));
             MSF_HIP(hipMemcpyAsync(vw, weights, 4 * (size_t)M, hipMemcpyHostToDevice, s));
@@ -267,34 +389,50 @@ extern "C" msf_status msf_solve_batched(msf_ctx *ctx, int32_t G, const int64_t *
         d_w = vw;
         d_out = (int32_t *)vout;
     }
-    launch_fill_u32(s, &c->dcnt->err, 0u, 1);
-    if (M > 0) {
-        size_t g = (size_t)(M + 255) / 256;
-        k_globalize<<<(unsigned)std::min<size_t>(g, 16384), 256, 0, s>>>(
-            d_edges, M, d_voff, d_eoff, G, (int32_t *)vge, c->dcnt);
-    }
-    MSF_HIP(hipGetLastError());
-    if ((rc = read_counters(c))) return rc;
-    if (c->hcnt->err & ERR_ENDPOINT) {
-        set_error("edge endpoint outside its graph's vertex range");
-        return MSF_EINVAL;
-    }
-    int64_t cnt = 0;
-    msf_total tot;
-    rc = solve_device(c, (int32_t)N, M, (const int32_t *)vge, d_w, wt, (int32_t *)vgid, &cnt, &tot);
-    if (rc) return rc;
     int64_t *d_counts = (int64_t *)vres;
     uint64_t *d_tu = (uint64_t *)(d_counts + G);
     double *d_tf = (double *)(d_tu + G);
-    if (wt == MSF_W_F32)
-        k_split<MSF_W_F32><<<G, 256, 0, s>>>((const int32_t *)vgid, cnt, d_voff, d_eoff, d_w, d_out,
-                                             d_counts, d_tu, d_tf);
-    else
-        k_split<MSF_W_U32><<<G, 256, 0, s>>>((const int32_t *)vgid, cnt, d_voff, d_eoff, d_w, d_out,
-                                             d_counts, d_tu, d_tf);
-    MSF_HIP(hipGetLastError());
     std::vector<int64_t> hres(3 * (size_t)G);
-    MSF_HIP(hipMemcpyAsync(hres.data(), vres, 24 * (size_t)G, hipMemcpyDeviceToHost, s));
+    if (c->batch_mode == 0) {
+        // the disjoint union through the round loop of msf_solve
+        if ((rc = ws_get(c, WS_BATCH1, 8 * mm, &vge))) return rc;
+        launch_fill_u32(s, &c->dcnt->err, 0u, 1);
+        if (M > 0) {
+            size_t g = (size_t)(M + 255) / 256;
+            k_globalize<<<(unsigned)std::min<size_t>(g, 16384), 256, 0, s>>>(
+                d_edges, M, d_voff, d_eoff, G, (int32_t *)vge, c->dcnt);
+        }
+        MSF_HIP(hipGetLastError());
+        if ((rc = read_counters(c))) return rc;
+        if (c->hcnt->err & ERR_ENDPOINT) {
+            set_error("edge endpoint outside its graph's vertex range");
+            return MSF_EINVAL;
+        }
+        int64_t cnt = 0;
+        msf_total tot;
+        rc = solve_device(c, (int32_t)N, M, (const int32_t *)vge, d_w, wt, (int32_t *)vgid, &cnt,
+                          &tot);
+        if (rc) return rc;
+        if (wt == MSF_W_F32)
+            k_split<MSF_W_F32><<<G, 256, 0, s>>>((const int32_t *)vgid, cnt, d_voff, d_eoff, d_w,
+                                                 d_out, d_counts, d_tu, d_tf);
+        else
+            k_split<MSF_W_U32><<<G, 256, 0, s>>>((const int32_t *)vgid, cnt, d_voff, d_eoff, d_w,
+                                                 d_out, d_counts, d_tu, d_tf);
+        MSF_HIP(hipGetLastError());
+        MSF_HIP(hipMemcpyAsync(hres.data(), vres, 24 * (size_t)G, hipMemcpyDeviceToHost, s));
+        c->stats = msf_stats{};
+        c->stats.batch_config = -1;
+    } else {
+        // persistent launch into the staging buffer (vgid); the caller's
+        // forest ids are written only once every graph has succeeded
+        rc = batched_persistent(c, G, vtx_off, edge_off, d_voff, d_eoff, d_edges, d_w, wt,
+                                (int32_t *)vgid, d_counts, d_tu, d_tf, hres.data());
+        if (rc) return rc;
+        if (mem == MSF_MEM_HOST) d_out = (int32_t *)vgid;  // downloaded from there below
+        else if (N > 0)
+            MSF_HIP(hipMemcpyAsync(d_out, vgid, 4 * (size_t)N, hipMemcpyDeviceToDevice, s));
+    }
     if (mem == MSF_MEM_HOST && N > 0)
         MSF_HIP(hipMemcpyAsync(forest_ids, d_out, 4 * (size_t)N, hipMemcpyDeviceToHost, s));
     MSF_HIP(hipStreamSynchronize(s));

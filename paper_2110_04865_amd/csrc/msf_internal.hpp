@@ -98,6 +98,7 @@ enum Slot {
     WS_BH, WS_BHOFF, WS_BRLO, WS_BCOL, WS_BKEY, WS_CHUNKINFO,
     WS_TL1, WS_TL2, WS_TLSUB, WS_TLORDER, WS_TLPLAN, WS_T2, WS_T2OFF, WS_FSTART,
     WS_RUNCHUNK, WS_RUNROW, WS_RUNS, WS_PAIR,
+    WS_PORDER, WS_PCTL, WS_PSCRATCH,
     WS_COUNT
 };
 
@@ -237,6 +238,13 @@ struct Ctx {
     // key-sorted runs (1 from a size and an average degree on, 2 always) or
     // full sweep with the filtering policy (0)
     int heads = 1;
+    // batched solve: 1 persistent kernel (graphs up to its size limits;
+    // larger ones solved one by one), 0 the disjoint union through the
+    // round loop
+    int batch_mode = 1;
+    // msf_solve of graphs with at most this many edges (and state that fits
+    // LDS) by one workgroup of the persistent kernel; 0 turns it off
+    int64_t small_m = (int64_t)1 << 17;
     SolveState ss;
 };
 

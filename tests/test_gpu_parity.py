@@ -45,6 +45,19 @@ def ctx(pkg):
     c.close()
 
 
+@pytest.fixture
+def wide_path():
+    """Keep small graphs on the device-wide round loop (tests of its
+    internals: filtering, head sweep, slices, first round, builds)."""
+    old = os.environ.get("MSF_SMALL_M")
+    os.environ["MSF_SMALL_M"] = "0"
+    yield
+    if old is None:
+        os.environ.pop("MSF_SMALL_M", None)
+    else:
+        os.environ["MSF_SMALL_M"] = old
+
+
 def dev(a):
     a = np.ascontiguousarray(a)
     if a.dtype == np.uint32:
@@ -227,6 +240,7 @@ def test_rounds_match_algorithm2_oracle(ctx, pkg):
         assert st["hook_rounds"] <= max(1, int(math.floor(math.log2(max(n, 2)))))
 
 
+@pytest.mark.usefixtures("wide_path")
 def test_filter_policies_are_result_invariant(pkg):
     """The filtering policies belong to the full sweep (the head sweep passes
     internal entries over by itself), so the head sweep is off here."""
@@ -255,6 +269,7 @@ def test_filter_policies_are_result_invariant(pkg):
             os.environ["MSF_HEADS"] = old_heads
 
 
+@pytest.mark.usefixtures("wide_path")
 def test_head_sweep_matches_oracle_and_full_sweep(pkg):
     """Rounds after the first sweep key-sorted runs and pass internal
     entries over (head sweep; MSF_HEADS=2 forces it at any size) or sweep
@@ -451,6 +466,53 @@ def test_shortcut_strategies_match_find_roots(ctx, pkg):
     assert np.array_equal(dp.cpu().numpy().view(np.uint32), [0, 0, 1])
 
 
+# ------------------------------------------------- one-workgroup solves --
+
+def test_small_graphs_take_one_workgroup(ctx, pkg):
+    """msf_solve of small graphs runs in one workgroup (state in LDS); the
+    same graphs on the device-wide round loop give the same forests, and
+    both equal the oracle's, with the oracle's hooks per round."""
+    rng = np.random.default_rng(61)
+    cases = [("er4096", 4096, *gen.er(4096, 32768, seed=3), U32),
+             ("rmat12", *gen.rmat(12, 16, seed=4), F32),
+             ("grid16", *gen.grid(16, 16, 16, 0.05, seed=5), U32),
+             ("path", 3000, np.array([[i, i + 1] for i in range(2999)], np.int32),
+              np.full(2999, 5, np.uint32), U32),
+             ("multi", 300, rng.integers(0, 300, size=(5000, 2)).astype(np.int32),
+              rng.integers(0, 4, size=5000).astype(np.uint32), U32),
+             ("two vertices", 2, np.array([[0, 1], [1, 0], [0, 0]], np.int32),
+              np.array([3, 3, 1], np.uint32), U32),
+             ("limit", 8000, *gen.er(8000, 60000, seed=6), U32)]
+    for label, n, e, w, wt in cases:
+        st = check_solve(ctx, pkg, n, e, w, wt, "small " + label, device=len(e) % 2 == 0)
+        assert st["path"] == 1, (label, st)
+        hooks = [h for h in oracle.as_rounds(n, e, w, wt)["hooks"] if h]
+        assert st["hooks"][:len(hooks)] == hooks, (label, st["hooks"], hooks)
+    with env_set(MSF_SMALL_M="0"):
+        c = pkg.Context(0)
+    for label, n, e, w, wt in cases:
+        st = check_solve(c, pkg, n, e, w, wt, "wide " + label)
+        assert st["path"] == 0, label
+    c.close()
+
+
+def test_small_path_rejects_bad_input_untouched(ctx, pkg):
+    n = 100
+    e = np.array([[0, 1], [1, 2], [2, 100]], np.int32)  # 100 is out of range
+    w = np.array([1.0, 2.0, 3.0], np.float32)
+    out = torch.full((n,), -5, dtype=torch.int32, device="cuda:0")
+    with pytest.raises(pkg.MSFError) as ex:
+        ctx.solve(n, dev(e), dev(w), wtype=F32, out=out)
+    assert ex.value.status == 1
+    e[2, 1] = 3
+    w[1] = np.nan
+    with pytest.raises(pkg.MSFError) as ex:
+        ctx.solve(n, dev(e), dev(w), wtype=F32, out=out)
+    assert ex.value.status == 1
+    torch.cuda.synchronize()
+    assert bool((out == -5).all())
+
+
 # ------------------------------------------------------------ components --
 
 def test_components_match_oracle(ctx, pkg):
@@ -546,6 +608,121 @@ def test_batched_device_float_and_solo_agree(ctx, pkg):
         assert np.array_equal(si.astype(np.int64), wi)
         assert np.array_equal(ids[vo[g]:vo[g] + wc].astype(np.int64), wi)
         assert totals[g][1] == stot[1] == wtot[1]
+
+
+def mixed_batch(seed=41):
+    """Graphs of every kind the batched solve meets: empty, single vertex,
+    loops and parallel edges, tiny and large ones (state in LDS and in the
+    global slot for every candidate), a path, equal weights, float specials."""
+    rng = np.random.default_rng(seed)
+    graphs = [(0, np.zeros((0, 2), np.int32)), (1, np.zeros((0, 2), np.int32)),
+              (5, np.array([[0, 0], [1, 2], [2, 1], [3, 3], [1, 2], [4, 0]], np.int32)),
+              (3000, np.array([[i, i + 1] for i in range(2999)], np.int32))]
+    for n in list(rng.integers(2, 200, 40)) + list(rng.integers(200, 6000, 20)) + \
+            [9000, 17000, 33000, 65536]:
+        n = int(n)
+        m = int(rng.integers(0, 5 * n))
+        graphs.append((n, rng.integers(0, n, size=(m, 2)).astype(np.int32)))
+    vo = np.zeros(len(graphs) + 1, np.int64)
+    eo = np.zeros(len(graphs) + 1, np.int64)
+    for g, (n, e) in enumerate(graphs):
+        vo[g + 1] = vo[g] + n
+        eo[g + 1] = eo[g] + len(e)
+    e = np.concatenate([x[1] for x in graphs]).astype(np.int32)
+    w_u = rng.integers(0, 1 << 32, size=len(e), dtype=np.uint64).astype(np.uint32)
+    w_u[eo[3]:eo[4]] = 7  # the path: equal weights
+    w_f = (rng.integers(1, 1 << 24, size=len(e)) * 2.0 ** -24).astype(np.float32)
+    w_f[::17] = -w_f[::17]
+    w_f[5] = np.inf
+    w_f[6] = -0.0
+    return vo, eo, e, w_u, w_f
+
+
+def check_batched(ctx, vo, eo, e, w, wt, label, device=False):
+    G = len(vo) - 1
+    if device:
+        ids, counts, totals = ctx.solve_batched(vo, eo, dev(e), dev(w), wtype=wt)
+        torch.cuda.synchronize()
+        ids = ids.cpu().numpy()
+    else:
+        ids, counts, totals = ctx.solve_batched(vo, eo, e, w, wtype=wt)
+    for g in range(G):
+        n = int(vo[g + 1] - vo[g])
+        wi, wc, wtot = oracle.msf(n, e[eo[g]:eo[g + 1]], w[eo[g]:eo[g + 1]], wt)
+        assert counts[g] == wc, (label, g)
+        assert np.array_equal(ids[vo[g]:vo[g] + wc].astype(np.int64), wi), (label, g)
+        assert totals[g][1] == wtot[1] or (math.isnan(totals[g][1]) and math.isnan(wtot[1])), \
+            (label, g, totals[g], wtot)
+        if wt == U32:
+            assert totals[g][0] == wtot[0], (label, g)
+    return ctx.stats()
+
+
+def test_batched_every_candidate_is_result_invariant(ctx, pkg):
+    """Every launch configuration of the persistent batched kernel gives the
+    oracle's forests (the tuner's choice cannot change a result)."""
+    vo, eo, e, w_u, w_f = mixed_batch()
+    cands = pkg.batch_configs()
+    with env_set(MSF_BATCH_CONFIG="0"):
+        for i, cfg in enumerate(cands):
+            os.environ["MSF_BATCH_CONFIG"] = str(i)
+            say("batched candidate", i, cfg)
+            st = check_batched(ctx, vo, eo, e, w_u, U32, f"cand {i} u32", device=i % 2 == 0)
+            assert st["batch_config"] == i and st["batch_graphs"] == len(vo) - 1, st
+            check_batched(ctx, vo, eo, e, w_f, F32, f"cand {i} f32", device=i % 2 == 1)
+
+
+def test_batched_large_graphs_go_one_by_one(ctx, pkg):
+    """Graphs above the persistent kernel's limits (over 2^20 vertices) are
+    solved one by one in the same call, beside the persistent ones."""
+    rng = np.random.default_rng(5)
+    graphs = [(1500, rng.integers(0, 1500, size=(4000, 2))),
+              ((1 << 20) + 77, rng.integers(0, (1 << 20) + 77, size=(900000, 2))),
+              (700, rng.integers(0, 700, size=(2000, 2)))]
+    vo = np.cumsum([0] + [n for n, _ in graphs]).astype(np.int64)
+    eo = np.cumsum([0] + [len(x) for _, x in graphs]).astype(np.int64)
+    e = np.concatenate([x for _, x in graphs]).astype(np.int32)
+    w = rng.integers(0, 1000, size=len(e)).astype(np.uint32)
+    st = check_batched(ctx, vo, eo, e, w, U32, "one large", device=True)
+    assert st["batch_large"] == 1 and st["batch_graphs"] == 2, st
+
+
+def test_batched_union_mode_matches(pkg):
+    """The disjoint-union path (MSF_BATCH_MODE=0) gives the same forests."""
+    vo, eo, e, w_u, w_f = mixed_batch(seed=43)
+    with env_set(MSF_BATCH_MODE="0"):
+        c = pkg.Context(0)
+    st = check_batched(c, vo, eo, e, w_u, U32, "union u32")
+    assert st["batch_config"] == -1
+    check_batched(c, vo, eo, e, w_f, F32, "union f32", device=True)
+    c.close()
+
+
+def test_batched_rejects_nan_and_leaves_outputs(ctx, pkg):
+    vo, eo, e, w_u, w_f = mixed_batch(seed=44)
+    w_f[int(eo[-2]) + 3] = np.nan  # in the last (largest) graph
+    out = torch.full((int(vo[-1]),), -7, dtype=torch.int32, device="cuda:0")
+    with pytest.raises(pkg.MSFError) as ex:
+        ctx.solve_batched(vo, eo, dev(e), dev(w_f), wtype=F32, out=out)
+    assert ex.value.status == 1
+    torch.cuda.synchronize()
+    assert bool((out == -7).all())
+
+
+def test_batched_tuning_cache(ctx, pkg, tmp_path):
+    """The tuner stores its choice per batch shape in MSF_TUNE_CACHE and a
+    later call (here: a fresh process state is not needed, the file is read
+    on first use) keeps using it."""
+    vo, eo, e, w_u, _ = mixed_batch(seed=45)
+    path = tmp_path / "tune.txt"
+    with env_set(MSF_TUNE_CACHE=str(path)):
+        os.environ.pop("MSF_BATCH_CONFIG", None)
+        st1 = check_batched(ctx, vo, eo, e, w_u, U32, "tuned")
+        st2 = check_batched(ctx, vo, eo, e, w_u, U32, "cached")
+    assert st1["batch_config"] == st2["batch_config"] >= 0
+    if path.exists():  # written when this process tuned the shape itself
+        arch, nb, db, wt, idx = path.read_text().split()[:5]
+        assert arch.startswith("gfx") and int(idx) == st1["batch_config"]
 
 
 def test_batched_rejects_out_of_graph_endpoint(ctx, pkg):
@@ -653,6 +830,7 @@ def test_full_size_device_atomic_build(pkg, label):
     c.close()
 
 
+@pytest.mark.usefixtures("wide_path")
 def test_column_slices_are_result_invariant(pkg):
     graphs = [
         ("er", 5000, *gen.er(5000, 40000, seed=12), U32),
@@ -696,6 +874,7 @@ def test_column_slices_are_result_invariant(pkg):
                 os.environ[k] = v
 
 
+@pytest.mark.usefixtures("wide_path")
 def test_first_round_modes_agree(pkg):
     """Round 1 from the generic sweep (0), the identity-parent sweep (1) and
     the minima kept by the adjacency build (2) give the same forest, with one
@@ -728,6 +907,7 @@ def test_first_round_modes_agree(pkg):
                 os.environ[k] = v
 
 
+@pytest.mark.usefixtures("wide_path")
 def test_build_modes_agree(pkg):
     """The device-atomic (0), two-level bucketed (1, default) and one-level
     bucketed (2) adjacency builds give the same forest: skewed R-MAT rows far
@@ -767,6 +947,7 @@ def test_build_modes_agree(pkg):
             os.environ["MSF_BUCKETED_BUILD"] = old
 
 
+@pytest.mark.usefixtures("wide_path")
 def test_head_sweep_with_every_build_and_first_round(pkg):
     """The head sweep forced on after the device-atomic (0) and one-level (2)
     builds (runs set up from row_ptr by their own kernels) and with round 1
