@@ -25,9 +25,11 @@
 //             star (complete shortcutting, section 4.2), then p <- h[p];
 //   stop      after a round in which nothing hooks.
 //
-// State of a graph with n vertices and m edges: r u64[n], p u32[n],
-// h u32[n] and the forest flags as a bitmask u32[ceil(m/32)], in LDS when
-// 16 n + 4 ceil(m/32) bytes fit the launch's dynamic LDS, else in the
+// State of a graph with n vertices and m edges: r u64[n], p u32[n] (a
+// parent chain: a vertex that stops being a root points to the root that
+// absorbed it), h u32[n], the list of roots that can still hook u32[n] and
+// the forest flags as a bitmask u32[ceil(m/32)], in LDS when
+// 20 n + 4 ceil(m/32) bytes fit the launch's dynamic LDS, else in the
 // workgroup's slot of a global scratch area (same code, the address space
 // is fixed per instantiation).  The live-edge lists of the later rounds
 // (16 bytes per edge, two buffers) are always in the slot.  Keys use the
@@ -56,10 +58,13 @@ __device__ __forceinline__ uint64_t ld_min_u64(uint64_t *p, uint64_t v)
     return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ void lower(uint64_t *r, uint32_t i, uint64_t key)
+// r[i] <- min(r[i], key) where a read of r[i] (cur) shows that the key can
+// lower it: r only decreases during a sweep, so a stale read can cost an
+// atomic, never a miss, and most atomics are skipped (measured: sending
+// every atomic to global memory made the sweep 3x slower).
+__device__ __forceinline__ void lower(uint64_t *r, uint32_t i, uint64_t cur, uint64_t key)
 {
-    // r only decreases during a sweep: a stale read can cost an atomic, never a miss
-    if (key < r[i]) ld_min_u64(r + i, key);
+    if (key < cur) ld_min_u64(r + i, key);
 }
 
 __device__ __forceinline__ uint32_t weight_key(uint32_t bits, int wt)
@@ -88,17 +93,23 @@ __device__ __forceinline__ void solve_graph(const PersistArgs &A, uint32_t g, ui
     const int64_t e0 = A.edge_off[g];
     const uint32_t m = (uint32_t)(A.edge_off[g + 1] - e0);
     const uint32_t nw = (m + 31) / 32;
+    // r: root minima; p: parent chain (a root points to itself; a vertex
+    // that stopped being a root points to the root that absorbed it, after
+    // that round's shortcut); h: hook targets; L: the current roots
     uint64_t *r = reinterpret_cast<uint64_t *>(state);
     uint32_t *p = reinterpret_cast<uint32_t *>(state + 8 * (size_t)n);
     uint32_t *h = p + n;
-    uint32_t *fb = h + n;
+    uint32_t *L = h + n;
+    uint32_t *fb = L + n;
     const int2 *E = reinterpret_cast<const int2 *>(A.edges) + e0;
     const uint32_t *W = A.w + e0;
 
     for (uint32_t i = tid; i < n; i += NT) {
         r[i] = KEY_INF;
         p[i] = i;
+        L[i] = i;
     }
+    uint32_t nroots = n;
     for (uint32_t k = tid; k < nw; k += NT) fb[k] = 0u;
     if (tid == 0) ctl.gerr = 0;
     uint32_t err = 0;
@@ -115,6 +126,11 @@ __device__ __forceinline__ void solve_graph(const PersistArgs &A, uint32_t g, ui
         // ---- sweep -------------------------------------------------------
         LiveEdge *dst = (round & 1) ? buf0 : buf1;
         const LiveEdge *src = (round & 1) ? buf1 : buf0;
+        // Each step of a sweep runs in phases over the thread's EPT edges:
+        // every load first, then the parent lookups, then the minima, so
+        // the loads of all EPT edges are in flight together.  Indices past
+        // the end are clamped (the loads stay in bounds) and the edge is
+        // masked off.
         if (round <= 1) {
             for (uint32_t base = 0; base < m; base += NT * EPT) {
                 int2 uv[EPT];
@@ -126,30 +142,45 @@ __device__ __forceinline__ void solve_graph(const PersistArgs &A, uint32_t g, ui
                     uv[k] = E[ec];
                     wb[k] = W[ec];
                 }
+                uint32_t a[EPT], b[EPT];
+                bool ok[EPT];
 #pragma unroll
                 for (int k = 0; k < EPT; ++k) {
                     const uint32_t e = base + k * NT + tid;
-                    const uint32_t u = (uint32_t)uv[k].x, v = (uint32_t)uv[k].y;
-                    bool ok = e < m;
-                    if (ok && (u >= n || v >= n)) {
+                    a[k] = (uint32_t)uv[k].x;
+                    b[k] = (uint32_t)uv[k].y;
+                    ok[k] = e < m;
+                    if (ok[k] && (a[k] >= n || b[k] >= n)) {
                         err |= ERR_ENDPOINT;
-                        ok = false;
+                        ok[k] = false;
                     }
-                    if (ok && WT == MSF_W_F32 && (wb[k] & 0x7FFFFFFFu) > 0x7F800000u) {
+                    if (ok[k] && WT == MSF_W_F32 && (wb[k] & 0x7FFFFFFFu) > 0x7F800000u) {
                         err |= ERR_NAN;
-                        ok = false;
+                        ok[k] = false;
                     }
+                    if (!ok[k]) a[k] = b[k] = 0;
+                }
+                if (round == 1) {
+#pragma unroll
+                    for (int k = 0; k < EPT; ++k) {
+                        a[k] = p[a[k]];
+                        b[k] = p[b[k]];
+                    }
+                }
+                uint64_t ra[EPT], rb[EPT];
+#pragma unroll
+                for (int k = 0; k < EPT; ++k) {
+                    ra[k] = r[a[k]];
+                    rb[k] = r[b[k]];
+                }
+#pragma unroll
+                for (int k = 0; k < EPT; ++k) {
+                    const uint32_t e = base + k * NT + tid;
                     const uint64_t key = ((uint64_t)weight_key(wb[k], WT) << 32) | e;
-                    uint32_t a = 0, b = 0;
-                    bool live = false;
-                    if (ok) {
-                        a = round == 0 ? u : p[u];
-                        b = round == 0 ? v : p[v];
-                        live = a != b;
-                    }
+                    const bool live = ok[k] && a[k] != b[k];
                     if (live) {
-                        lower(r, a, key);
-                        lower(r, b, key);
+                        lower(r, a[k], ra[k], key);
+                        lower(r, b[k], rb[k], key);
                     }
                     if (round == 1) {
                         // keep the live edges for the next round
@@ -158,7 +189,8 @@ __device__ __forceinline__ void solve_graph(const PersistArgs &A, uint32_t g, ui
                         if (__lane_id() == 0 && mask)
                             at = atomicAdd(&ctl.live, (uint32_t)__popcll(mask));
                         at = __shfl(at, 0, 64);
-                        if (live) dst[at + __popcll(mask & lanemask_lt())] = LiveEdge{a, b, key};
+                        if (live)
+                            dst[at + __popcll(mask & lanemask_lt())] = LiveEdge{a[k], b[k], key};
                     }
                 }
             }
@@ -170,34 +202,51 @@ __device__ __forceinline__ void solve_graph(const PersistArgs &A, uint32_t g, ui
                     const uint32_t j = base + k * NT + tid;
                     x[k] = src[j < nlive ? j : nlive - 1];
                 }
+                uint32_t a[EPT], b[EPT];
+#pragma unroll
+                for (int k = 0; k < EPT; ++k) {
+                    a[k] = p[x[k].a];
+                    b[k] = p[x[k].b];
+                }
+                uint64_t ra[EPT], rb[EPT];
+#pragma unroll
+                for (int k = 0; k < EPT; ++k) {
+                    ra[k] = r[a[k]];
+                    rb[k] = r[b[k]];
+                }
 #pragma unroll
                 for (int k = 0; k < EPT; ++k) {
                     const uint32_t j = base + k * NT + tid;
-                    const uint32_t a = p[x[k].a], b = p[x[k].b];
-                    const bool live = j < nlive && a != b;
+                    const bool live = j < nlive && a[k] != b[k];
                     if (live) {
-                        lower(r, a, x[k].key);
-                        lower(r, b, x[k].key);
+                        lower(r, a[k], ra[k], x[k].key);
+                        lower(r, b[k], rb[k], x[k].key);
                     }
                     const uint64_t mask = __ballot(live);
                     uint32_t at = 0;
                     if (__lane_id() == 0 && mask)
                         at = atomicAdd(&ctl.live, (uint32_t)__popcll(mask));
                     at = __shfl(at, 0, 64);
-                    if (live) dst[at + __popcll(mask & lanemask_lt())] = LiveEdge{a, b, x[k].key};
+                    if (live)
+                        dst[at + __popcll(mask & lanemask_lt())] = LiveEdge{a[k], b[k], x[k].key};
                 }
             }
         }
         __syncthreads();
         if (round >= 1) nlive = ctl.live;
         // ---- hook: every root onto the root across its minimum edge ------
-        for (uint32_t i = tid; i < n; i += NT) {
-            if (p[i] != i) continue;
+        // The other endpoint's root at the start of this round is the end
+        // of its parent chain (one step per round since it stopped being a
+        // root); p is not written in this step, so the chains are stable.
+        for (uint32_t k = tid; k < nroots; k += NT) {
+            const uint32_t i = L[k];
             const uint64_t key = r[i];
             uint32_t t = i;
             if (key != KEY_INF) {
                 const int2 uv = E[(uint32_t)key];
-                const uint32_t a = p[(uint32_t)uv.x], b = p[(uint32_t)uv.y];
+                uint32_t a = (uint32_t)uv.x, b = (uint32_t)uv.y;
+                while (p[a] != a) a = p[a];
+                while (p[b] != b) b = p[b];
                 t = a == i ? b : a;
             }
             h[i] = t;
@@ -207,11 +256,11 @@ __device__ __forceinline__ void solve_graph(const PersistArgs &A, uint32_t g, ui
         // The larger root of a mutual pair never reverts, whatever it reads,
         // so reverting the smaller one in place is race-free.
         uint32_t kept = 0;
-        for (uint32_t i = tid; i < n; i += NT) {
-            if (p[i] != i) continue;
-            const uint32_t k = h[i];
-            if (k == i) continue;
-            if (i < k && h[k] == i) {
+        for (uint32_t k = tid; k < nroots; k += NT) {
+            const uint32_t i = L[k];
+            const uint32_t t = h[i];
+            if (t == i) continue;
+            if (i < t && h[t] == i) {
                 h[i] = i;
                 continue;
             }
@@ -235,13 +284,13 @@ __device__ __forceinline__ void solve_graph(const PersistArgs &A, uint32_t g, ui
             err |= ERR_CYCLE;
             break;
         }
-        // ---- complete shortcutting over the old roots -------------------
+        // ---- complete shortcutting over the roots ------------------------
         for (uint32_t pass = 0;; ++pass) {
             if (tid == 0) ctl.changed[pass & 1] = 0;
             __syncthreads();
             uint32_t any = 0;
-            for (uint32_t i = tid; i < n; i += NT) {
-                if (p[i] != i) continue;
+            for (uint32_t k = tid; k < nroots; k += NT) {
+                const uint32_t i = L[k];
                 const uint32_t x = h[i];
                 const uint32_t y = h[x];
                 if (y != x) {
@@ -257,13 +306,35 @@ __device__ __forceinline__ void solve_graph(const PersistArgs &A, uint32_t g, ui
                 break;
             }
         }
-        // ---- p <- h[p], minima reset for the next round ------------------
-        for (uint32_t i = tid; i < n; i += NT) {
-            p[i] = h[p[i]];
-            r[i] = KEY_INF;
+        if (err & ERR_CYCLE) break;
+        // ---- p <- h at the old roots; the roots that stay, compacted -----
+        // in place, one tile at a time: every read of a tile happens before
+        // the barrier, and writes land below the tile's end (at most as
+        // many roots stay as were read so far)
+        if (tid == 0) ctl.live = 0;
+        __syncthreads();
+        for (uint32_t base = 0; base < nroots; base += NT) {
+            const uint32_t k = base + tid;
+            const uint32_t i = k < nroots ? L[k] : NONE32;
+            bool stay = false;
+            if (i != NONE32) {
+                const uint32_t t = h[i];
+                p[i] = t;
+                // a root without an outgoing edge spans its whole component:
+                // no edge can reach it again, so it leaves the list
+                stay = t == i && r[i] != KEY_INF;
+                r[i] = KEY_INF;
+            }
+            __syncthreads();
+            const uint64_t mask = __ballot(stay);
+            uint32_t at = 0;
+            if (__lane_id() == 0 && mask) at = atomicAdd(&ctl.live, (uint32_t)__popcll(mask));
+            at = __shfl(at, 0, 64);
+            if (stay) L[at + __popcll(mask & lanemask_lt())] = i;
         }
         __syncthreads();
-        if (err & ERR_CYCLE) break;
+        nroots = ctl.live;
+        __syncthreads();
     }
 
     // ---- output: ascending forest ids, count, totals ----------------------

@@ -57,7 +57,7 @@ constexpr uint32_t SMALL_LDS = 150u << 10;
 
 __host__ __device__ inline size_t persist_state_bytes(uint32_t n, uint32_t m)
 {
-    return 16 * (size_t)n + 4 * (((size_t)m + 31) / 32);
+    return 20 * (size_t)n + 4 * (((size_t)m + 31) / 32);
 }
 
 __host__ inline size_t persist_slot_bytes(uint32_t n_cap, uint32_t m_cap)

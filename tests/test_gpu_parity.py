@@ -482,7 +482,7 @@ def test_small_graphs_take_one_workgroup(ctx, pkg):
               rng.integers(0, 4, size=5000).astype(np.uint32), U32),
              ("two vertices", 2, np.array([[0, 1], [1, 0], [0, 0]], np.int32),
               np.array([3, 3, 1], np.uint32), U32),
-             ("limit", 8000, *gen.er(8000, 60000, seed=6), U32)]
+             ("limit", 7000, *gen.er(7000, 50000, seed=6), U32)]
     for label, n, e, w, wt in cases:
         st = check_solve(ctx, pkg, n, e, w, wt, "small " + label, device=len(e) % 2 == 0)
         assert st["path"] == 1, (label, st)
