@@ -291,6 +291,34 @@ msf_status msf_solve_batched(msf_ctx *ctx, int32_t G, const int64_t *vtx_off,
                              msf_total *totals);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * batched solve with every array in device memory and every scratch buffer
+ * in a fixed array of MSF_NOALLOC_SCRATCH_BYTES that the library holds on
+ * each GPU it runs on until the process ends.  The call allocates nothing.
+ *   vtx_off, edge_off  device int64[G+1], starting at 0, non-decreasing
+ *   edges, weights     device, as for msf_solve_batched (local vertex ids)
+ *   forest_ids         device int32[vtx_off[G]] out: graph g's forest
+ *                      (local edge ids, ascending) from index vtx_off[g]
+ *   counts             device int64[G] out
+ *   totals             device msf_total[G] out
+ * Every graph must have at most 2^20 vertices and 2^22 edges, and its
+ * working set (32 bytes per edge + 20 per vertex + flags) must fit the
+ * array (MSF_EINVAL otherwise); the array holds as many graphs in flight as
+ * fit (fewer for larger graphs).  Offsets, endpoints and weights are checked
+ * in a first pass, so on any error nothing is written.  The call returns
+ * once that check is done (it synchronises the context's stream); the solve
+ * itself stays ordered on the stream.  Every call on one GPU uses the same
+ * array: calls that overlap in time on a GPU race.  Each graph's result
+ * equals msf_solve_batched's (and msf_solve's on that graph alone).
+ */
+#define MSF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+msf_status msf_solve_batched_noalloc(msf_ctx *ctx, int32_t G, const int64_t *vtx_off,
+                                     const int64_t *edge_off, const int32_t *edges,
+                                     const void *weights, msf_wtype wtype, int32_t *forest_ids,
+                                     int64_t *counts, msf_total *totals);
+
+/*
  * Serving: a request loop with continuous batching.  Requests are admitted
  * while their device footprint fits mem_budget_bytes; admitted requests keep
  * their adjacency, parent and edge state resident on the device and advance

@@ -37,7 +37,7 @@ EXPORTS = [
     "msf_solve_starcheck",
     "msf_shortcut", "msf_solve_batched", "msf_server_create", "msf_server_destroy",
     "msf_server_submit", "msf_server_poll", "msf_server_latency", "msf_server_result",
-    "msf_request_footprint", "msf_batch_configs",
+    "msf_request_footprint", "msf_batch_configs", "msf_solve_batched_noalloc",
 ]
 
 
@@ -123,6 +123,8 @@ def lib():
     L.msf_request_footprint.restype = ctypes.c_size_t
     L.msf_batch_configs.argtypes = [P, P, P, I32]
     L.msf_batch_configs.restype = ctypes.c_int
+    L.msf_solve_batched_noalloc.argtypes = [P, I32, P, P, P, P, ctypes.c_int, P, P, P]
+    L.msf_solve_batched_noalloc.restype = st
     _lib = L
     return L
 
@@ -348,6 +350,20 @@ class Context:
                                        ctypes.c_void_p(ids.ctypes.data),
                                        ctypes.c_void_p(counts.ctypes.data), totals))
         return ids, counts[:G], [(totals[g].u64, totals[g].f64) for g in range(G)]
+
+
+def solve_batched_noalloc(ctx: "Context", vtx_off, edge_off, edges, weights, wtype: int,
+                          out, counts, totals):
+    """msf_solve_batched_noalloc: every argument a device tensor (offsets and
+    counts int64, totals int64 [G, 2] holding msf_total's u64 and f64 bits);
+    the library allocates nothing.  Stream-ordered after its checks."""
+    G = vtx_off.numel() - 1
+    N = int(vtx_off[-1].item()) if G > 0 else 0
+    M = int(edge_off[-1].item()) if G > 0 else 0
+    _check(lib().msf_solve_batched_noalloc(
+        ctx._h, G, _dev(vtx_off, "vtx_off", G + 1, 8), _dev(edge_off, "edge_off", G + 1, 8),
+        _dev(edges, "edges", 2 * M, 4), _dev(weights, "weights", M, 4), wtype,
+        _dev(out, "out", N, 4), _dev(counts, "counts", G, 8), _dev(totals, "totals", 2 * G, 8)))
 
 
 class Graph:

@@ -117,6 +117,7 @@ msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc)
     c->device = device;
     c->stream = stream;
     c->async_alloc = async_alloc;
+    MSF_TRY(noalloc_init(device));
     if (hipMalloc(&c->dcnt, sizeof(Counters)) != hipSuccess ||
         hipHostMalloc(&c->hcnt, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();

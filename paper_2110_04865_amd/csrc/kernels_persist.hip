@@ -362,8 +362,8 @@ __device__ __forceinline__ void solve_graph(const PersistArgs &A, uint32_t g, ui
     if (err) atomicOr(&ctl.err, err);
     if (tid == 0) {
         A.counts[g] = total;
-        A.tot_u64[g] = WT == MSF_W_U32 ? (uint64_t)s_tot[0] : 0;
-        A.tot_f64[g] = exact_total_f64((uint64_t)s_tot[0], s_tot + 1,
+        A.tot_u64[(size_t)g * A.tot_stride] = WT == MSF_W_U32 ? (uint64_t)s_tot[0] : 0;
+        A.tot_f64[(size_t)g * A.tot_stride] = exact_total_f64((uint64_t)s_tot[0], s_tot + 1,
                                        (uint32_t)s_tot[1 + ACC_DIGITS],
                                        (uint32_t)s_tot[2 + ACC_DIGITS], WT);
     }
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(NT) void k_persist(PersistArgs A)
     for (;;) {
         if (threadIdx.x == 0) {
             const uint32_t k = atomicAdd(A.queue, 1u);
-            ctl.g = k < (uint32_t)A.G ? A.order[k] : NONE32;
+            ctl.g = k < (uint32_t)A.G ? (A.order ? A.order[k] : k) : NONE32;
         }
         __syncthreads();
         const uint32_t g = ctl.g;

@@ -411,6 +411,9 @@ void launch_cc_apply(hipStream_t s, const uint32_t *h, int32_t n, uint32_t *p);
 
 void zero_counters(Ctx *c);
 msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc);
+// Device address of the static scratch array of msf_solve_batched_noalloc
+// on `device` (taken once per device; the device must be current).
+msf_status noalloc_init(int device);
 void ctx_release_workspace(Ctx *c);
 void ctx_release(Ctx *c);
 msf_status decode_err(uint32_t err);

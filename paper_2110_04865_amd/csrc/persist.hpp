@@ -14,8 +14,8 @@ namespace msf {
 
 // Arguments of one persistent launch.  Graph g has vtx_off[g+1]-vtx_off[g]
 // vertices and edge_off[g+1]-edge_off[g] edges (local endpoint ids, weight
-// bits); order lists the graphs to solve (largest first), queue is the
-// shared cursor into it.  Each workgroup owns slot_bytes of scratch: two
+// bits); order lists the graphs to solve (largest first; null: every graph
+// in index order), queue is the shared cursor into it.  Each workgroup owns slot_bytes of scratch: two
 // live-edge buffers of m_cap entries (16 bytes each), then the state of a
 // graph too large for LDS (persist_state_bytes(n_cap, m_cap)).
 struct PersistArgs {
@@ -38,6 +38,9 @@ struct PersistArgs {
     // nullable: kept hooks of rounds 0..63 and, at [64], the rounds run
     // (for a launch that solves one graph)
     uint32_t *round_hooks = nullptr;
+    // graph g's totals go to tot_u64[g * tot_stride], tot_f64[g * tot_stride]
+    // (2 when they are the fields of an msf_total array)
+    uint32_t tot_stride = 1;
 };
 
 // A launch configuration: threads per workgroup, edges each thread loads per
