@@ -687,6 +687,10 @@ def main():
                     help="run only the connected-components leg (prints its JSON alone)")
     ap.add_argument("--starcheck-only", action="store_true",
                     help="run only the original-AS-rounds leg (prints its JSON alone)")
+    ap.add_argument("--served-only", action="store_true",
+                    help="run only the served leg (prints its JSON alone)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched leg (prints its JSON alone)")
     ap.add_argument("--served-requests", type=int, default=2000,
                     help="requests per arrival rate in the served leg (after 100 not counted)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -742,6 +746,14 @@ def main():
         print(json.dumps({"starcheck": bench_starcheck(
             ctx, pkg, torch, {"rmat_s22_e16": (n22, e22, w22, pkg.W_F32),
                               "grid256": (ng, eg, wg, pkg.W_U32)})}), flush=True)
+        return
+    if args.served_only:
+        print(json.dumps({"served": bench_served(ctx, pkg, torch, args.served_requests)}),
+              flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": bench_batched(ctx, pkg, torch, cpu=not args.no_cpu)}),
+              flush=True)
         return
     if args.shortcut_only:
         print(json.dumps({"shortcut_study": bench_shortcut(ctx, pkg, torch)}), flush=True)

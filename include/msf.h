@@ -341,7 +341,8 @@ msf_status msf_server_latency(msf_server *s, uint64_t ticket, double *seconds);
 msf_status msf_server_result(msf_server *s, uint64_t ticket, int32_t *forest_ids,
                              int64_t *forest_count, msf_total *total);
 
-/* Device bytes a request of this size occupies while resident. */
+/* Device bytes a request of this size occupies while resident (an upper
+   bound over every path a solve takes: builds, full or head sweep). */
 size_t msf_request_footprint(int32_t n, int64_t m);
 
 #ifdef __cplusplus

@@ -660,12 +660,15 @@ msf_status msf_solve_starcheck(msf_ctx *ctx, const msf_graph *g, uint8_t *in_for
 
 size_t msf_request_footprint(int32_t n, int64_t m)
 {
-    // per edge: input copy (12), bucketed build staging (28), adjacency and
-    // its filtered twin (2 x 24), forest flags (1) -> 89 bytes, rounded up;
-    // per vertex: row pointers x2 (8), p, h, hedge, three lists, ids (28),
-    // r (8) -> 44 bytes; plus chunk tables, partials and allocation slack
+    // the most any path of a solve holds, per edge: input copy (12),
+    // two-level build staging (two 16-byte records and a 2-byte row per
+    // stored direction: 68), adjacency (24), the filtered twin of the full
+    // sweep or the head sweep's run arrays (at most 24.2), forest flags (1)
+    // -> 131; per vertex: row pointers (8), p, h, hedge, three lists, hook
+    // weights, ids (32), r (8), the head sweep's per-row runs and counts
+    // (36) -> 84; plus chunk tables, partials and allocation slack
     const size_t nn = (size_t)std::max(n, 1), mm = (size_t)std::max<int64_t>(m, 1);
-    return 90 * mm + 44 * nn + ((size_t)32 << 20);
+    return 131 * mm + 84 * nn + ((size_t)32 << 20);
 }
 
 }  // extern "C"

@@ -338,8 +338,9 @@ __device__ __forceinline__ void solve_graph(const PersistArgs &A, uint32_t g, ui
     }
 
     // ---- output: ascending forest ids, count, totals ----------------------
-    // a graph that failed validation writes no ids (the call fails)
-    if (__ballot(err != 0) && __lane_id() == 0) atomicOr(&ctl.gerr, 1u);
+    // a graph that failed validation writes no ids (the call fails); its
+    // count is minus its error flags
+    if (err) atomicOr(&ctl.gerr, err);
     __syncthreads();
     const bool bad = ctl.gerr != 0;
     // each thread owns a contiguous range of flag words
@@ -361,7 +362,7 @@ __device__ __forceinline__ void solve_graph(const PersistArgs &A, uint32_t g, ui
     wsum_block<NT, WT>(ws, s_sum, s_tot, 1);
     if (err) atomicOr(&ctl.err, err);
     if (tid == 0) {
-        A.counts[g] = total;
+        A.counts[g] = bad ? -(int64_t)ctl.gerr : (int64_t)total;
         A.tot_u64[(size_t)g * A.tot_stride] = WT == MSF_W_U32 ? (uint64_t)s_tot[0] : 0;
         A.tot_f64[(size_t)g * A.tot_stride] = exact_total_f64((uint64_t)s_tot[0], s_tot + 1,
                                        (uint32_t)s_tot[1 + ACC_DIGITS],

@@ -4,6 +4,11 @@
 // submit() copies a request into a pinned host staging buffer (reused from a
 // pool, so the copy touches no fresh pages and the upload is a true
 // asynchronous DMA) and queues it; a worker thread owns the device work:
+//   - shared launches: the waiting requests whose state fits one
+//     workgroup's LDS (at most 2^17 edges) are taken together, while the
+//     budget allows, into one launch of the persistent kernel (each request
+//     one graph of the batch); two such jobs alternate, so requests that
+//     arrive while one runs go into the next;
 //   - admission: waiting requests are admitted in arrival order while their
 //     footprint (msf_request_footprint) fits in the budget left by the
 //     requests in flight and the workspace the slots keep; an admitted
@@ -44,6 +49,7 @@
 #include <vector>
 
 #include "msf_internal.hpp"
+#include "persist.hpp"
 
 using namespace msf;
 
@@ -148,6 +154,30 @@ struct ReqSlot {
     size_t kept = 0;  // device workspace bytes it holds (counted in used)
 };
 
+// Small requests (state that fits one workgroup's LDS) admitted together
+// are solved by one launch of the persistent kernel: their inputs are
+// copied into one concatenated buffer, each becomes one graph of the batch,
+// and their forests go back to their staging buffers.  Step 1 waits for the
+// solve and the counts, step 2 for the forest ids.
+struct BatchJob {
+    Ctx ctx;
+    std::vector<Request *> reqs;
+    int step = 0;          // 0 idle, 1 solving, 2 downloading ids
+    size_t kept = 0;       // device workspace bytes it holds (counted in used)
+    int64_t *hres = nullptr;  // pinned: offsets (2 (G+1)), then counts, u64 and f64 totals
+    uint32_t *hctl = nullptr; // pinned: error word
+    size_t hcap = 0;          // graphs hres has room for
+};
+
+// Most graphs one shared launch takes.
+constexpr size_t BATCH_MAX_GRAPHS = 1024;
+
+bool small_request(int32_t n, int64_t m)
+{
+    return m > 0 && n > 0 && (uint32_t)n <= PERSIST_MAX_N && m <= ((int64_t)1 << 17) &&
+           persist_state_bytes((uint32_t)n, (uint32_t)m) <= SMALL_LDS;
+}
+
 }  // namespace
 
 struct msf_server {
@@ -167,6 +197,8 @@ struct msf_server {
     std::unordered_map<uint64_t, Request *> tickets;
     std::vector<ReqSlot *> active;   // worker-only
     std::vector<ReqSlot *> pool;     // worker-only: idle slots with streams
+    BatchJob *jobs[2] = {nullptr, nullptr};  // worker-only: shared launches
+    bool batch_small = true;         // MSF_SERVER_BATCH=0 sends every request to a slot
     std::thread worker;
     std::atomic<bool> stop{false};
     uint64_t next_ticket = 1;
@@ -222,12 +254,6 @@ ReqSlot *take_slot(msf_server *s, size_t need)
         delete sl;
         return nullptr;
     }
-    // the one-level build needs half the staging memory of the two-level
-    // one, so more requests fit the budget at once; an explicit
-    // MSF_BUCKETED_BUILD still wins
-    if (!getenv("MSF_BUCKETED_BUILD") && sl->ctx.bucketed_build == 1) sl->ctx.bucketed_build = 2;
-    // requests are budgeted without the head sweep's run arrays
-    if (!getenv("MSF_HEADS")) sl->ctx.heads = 0;
     return sl;
 }
 
@@ -333,35 +359,285 @@ bool step_slot(msf_server *s, ReqSlot *sl)
     return false;
 }
 
+BatchJob *job_new(msf_server *s)
+{
+    BatchJob *j = new (std::nothrow) BatchJob();
+    if (!j) return nullptr;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        delete j;
+        return nullptr;
+    }
+    if (ctx_init(&j->ctx, s->device, st, true) != MSF_OK) {
+        ctx_release(&j->ctx);
+        (void)hipStreamDestroy(st);
+        delete j;
+        return nullptr;
+    }
+    return j;
+}
+
+void job_free(BatchJob *j)
+{
+    hipStream_t st = j->ctx.stream;
+    ctx_release(&j->ctx);
+    (void)hipStreamDestroy(st);
+    if (j->hres) (void)hipHostFree(j->hres);
+    delete j;
+}
+
+void job_fail(msf_server *s, BatchJob *j, msf_status st, const char *msg)
+{
+    for (Request *r : j->reqs) finish(s, r, st, msg);
+    j->reqs.clear();
+    (void)hipStreamSynchronize(j->ctx.stream);
+    j->step = 0;
+}
+
+// Pinned host arrays of a job for G graphs: offsets (2 (G + 1) int64), the
+// results (counts, u64 totals, f64 totals: 3 G), the order (G u32) and the
+// error word.
+bool job_host(BatchJob *j, size_t G)
+{
+    if (j->hcap >= G) return true;
+    if (j->hres) (void)hipHostFree(j->hres);
+    j->hres = nullptr;
+    j->hcap = 0;
+    const size_t bytes = 8 * (2 * (G + 1) + 3 * G) + 4 * G + 64;
+    if (hipHostMalloc((void **)&j->hres, bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        j->hres = nullptr;
+        return false;
+    }
+    j->hcap = G;
+    return true;
+}
+
+// Copy the requests in and enqueue one persistent launch over all of them.
+void job_start(msf_server *s, BatchJob *j, std::vector<Request *> &&reqs)
+{
+    Ctx *c = &j->ctx;
+    hipStream_t st = c->stream;
+    j->reqs = std::move(reqs);
+    const size_t G = j->reqs.size();
+    const msf_wtype wt = j->reqs[0]->wt;
+    if (!job_host(j, G)) {
+        job_fail(s, j, MSF_ENOMEM, "pinned host allocation failed");
+        return;
+    }
+    int64_t *vo = j->hres, *eo = vo + (G + 1), *res = eo + (G + 1);
+    uint32_t *order = (uint32_t *)(res + 3 * G);
+    j->hctl = order + G;
+    vo[0] = eo[0] = 0;
+    uint32_t nmax = 1, mmax = 1;
+    for (size_t g = 0; g < G; ++g) {
+        const Request *r = j->reqs[g];
+        vo[g + 1] = vo[g] + r->n;
+        eo[g + 1] = eo[g] + r->m;
+        nmax = std::max(nmax, (uint32_t)r->n);
+        mmax = std::max(mmax, (uint32_t)r->m);
+        order[g] = (uint32_t)g;
+    }
+    std::stable_sort(order, order + G, [&](uint32_t x, uint32_t y) {
+        return j->reqs[x]->m > j->reqs[y]->m;
+    });
+    const size_t N = (size_t)vo[G], M = (size_t)eo[G];
+    int cus = 1;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
+    const PersistCfg cfg{1024, 4, SMALL_LDS};
+    const int bpc = std::max(1, persist_blocks_per_cu(cfg, (int)wt));
+    const size_t slots = std::min<size_t>(G, (size_t)cus * bpc);
+    const size_t slot_bytes = persist_slot_bytes(nmax, mmax);
+    void *ve, *vw, *voff, *vids, *vres, *vord, *vctl, *vscr;
+    msf_status rc = ws_get(c, WS_EDGES, 8 * M, &ve);
+    if (!rc) rc = ws_get(c, WS_W, 4 * M, &vw);
+    if (!rc) rc = ws_get(c, WS_BATCH0, 16 * (G + 1), &voff);
+    if (!rc) rc = ws_get(c, WS_IDS, 4 * std::max<size_t>(N, 1), &vids);
+    if (!rc) rc = ws_get(c, WS_BATCH3, 24 * G, &vres);
+    if (!rc) rc = ws_get(c, WS_PORDER, 4 * G, &vord);
+    if (!rc) rc = ws_get(c, WS_PCTL, 256, &vctl);
+    if (!rc) rc = ws_get(c, WS_PSCRATCH, slots * slot_bytes, &vscr);
+    if (rc) {
+        job_fail(s, j, rc, msf_last_error());
+        return;
+    }
+    bool ok = hipMemcpyAsync(voff, vo, 16 * (G + 1), hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(vord, order, 4 * G, hipMemcpyHostToDevice, st) == hipSuccess;
+    for (size_t g = 0; ok && g < G; ++g) {
+        const Request *r = j->reqs[g];
+        const char *stg = (const char *)r->stage;
+        ok = hipMemcpyAsync((int32_t *)ve + 2 * eo[g], stg, 8 * (size_t)r->m,
+                            hipMemcpyHostToDevice, st) == hipSuccess &&
+             hipMemcpyAsync((uint32_t *)vw + eo[g], stg + 8 * (size_t)r->m, 4 * (size_t)r->m,
+                            hipMemcpyHostToDevice, st) == hipSuccess;
+    }
+    PersistArgs A;
+    A.G = (int32_t)G;
+    A.order = (const uint32_t *)vord;
+    A.queue = (uint32_t *)vctl;
+    A.err = (uint32_t *)vctl + 1;
+    A.vtx_off = (const int64_t *)voff;
+    A.edge_off = (const int64_t *)voff + (G + 1);
+    A.edges = (const int32_t *)ve;
+    A.w = (const uint32_t *)vw;
+    A.out = (int32_t *)vids;
+    A.counts = (int64_t *)vres;
+    A.tot_u64 = (uint64_t *)vres + G;
+    A.tot_f64 = (double *)vres + 2 * G;
+    A.scratch = (uint8_t *)vscr;
+    A.slot_bytes = slot_bytes;
+    A.m_cap = mmax;
+    A.lds_bytes = cfg.lds;
+    ok = ok && launch_persist(st, A, cfg, (int)wt, (unsigned)slots) == hipSuccess &&
+         hipMemcpyAsync(res, vres, 24 * G, hipMemcpyDeviceToHost, st) == hipSuccess &&
+         hipEventRecord(c->ev[3], st) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        job_fail(s, j, MSF_EDEVICE, "shared launch failed");
+        return;
+    }
+    j->step = 1;
+}
+
+const char *err_text(int64_t flags)
+{
+    if (flags & ERR_ENDPOINT) return "edge endpoint outside [0, n)";
+    if (flags & ERR_NAN) return "NaN edge weight";
+    return "internal error in the batched solve";
+}
+
+// Advance a job whose step has landed; returns true when it is idle again.
+bool job_step(msf_server *s, BatchJob *j)
+{
+    Ctx *c = &j->ctx;
+    hipStream_t st = c->stream;
+    const size_t G = j->reqs.size();
+    int64_t *vo = j->hres, *res = vo + 2 * (G + 1);
+    if (j->step == 1) {
+        // counts and totals are here: fetch each forest into its staging
+        void *vids = c->ws[WS_IDS].ptr;
+        bool ok = true;
+        for (size_t g = 0; g < G && ok; ++g) {
+            Request *r = j->reqs[g];
+            const int64_t cnt = res[g];
+            if (cnt > 0)
+                ok = hipMemcpyAsync(r->stage, (const int32_t *)vids + vo[g], 4 * (size_t)cnt,
+                                    hipMemcpyDeviceToHost, st) == hipSuccess;
+        }
+        if (!ok || hipEventRecord(c->ev[3], st) != hipSuccess) {
+            (void)hipGetLastError();
+            job_fail(s, j, MSF_EDEVICE, "result download failed");
+            return true;
+        }
+        j->step = 2;
+        return false;
+    }
+    for (size_t g = 0; g < G; ++g) {
+        Request *r = j->reqs[g];
+        const int64_t cnt = res[g];
+        if (cnt < 0) {
+            finish(s, r, MSF_EINVAL, err_text(-cnt));
+            continue;
+        }
+        r->count = cnt;
+        r->total.u64 = (uint64_t)res[G + g];
+        std::memcpy(&r->total.f64, &res[2 * G + g], sizeof(double));
+        finish(s, r, MSF_OK, nullptr);
+    }
+    j->reqs.clear();
+    j->step = 0;
+    const size_t k = workspace_bytes(j->ctx);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->used = s->used - j->kept + k;
+    }
+    j->kept = k;
+    return true;
+}
+
+// Gives back the workspace of idle slots and jobs, largest first, until
+// `need` more bytes fit the budget (called with s->mu held).
+bool make_room(msf_server *s, size_t need)
+{
+    while (s->used + need > s->budget) {
+        ReqSlot *big = nullptr;
+        for (ReqSlot *sl : s->pool)
+            if (sl->kept && (!big || sl->kept > big->kept)) big = sl;
+        BatchJob *bj = nullptr;
+        for (BatchJob *j : s->jobs)
+            if (j && j->step == 0 && j->kept && (!bj || j->kept > bj->kept)) bj = j;
+        if (bj && (!big || bj->kept > big->kept)) {
+            ctx_release_workspace(&bj->ctx);
+            s->used -= bj->kept;
+            bj->kept = 0;
+            continue;
+        }
+        if (!big) return false;
+        ctx_release_workspace(&big->ctx);  // stream-ordered frees
+        s->used -= big->kept;
+        big->kept = 0;
+    }
+    return true;
+}
+
 void worker_main(msf_server *s)
 {
     (void)hipSetDevice(s->device);
     for (;;) {
-        // admission, in arrival order, while the budget allows; idle slots
-        // give back their workspace (largest first) to make room
+        // small requests: one shared launch of the persistent kernel for
+        // all waiting ones (same weight type), when a job is idle
+        if (s->batch_small) {
+            BatchJob *j = nullptr;
+            for (BatchJob *&x : s->jobs) {
+                if (!x) x = job_new(s);
+                if (x && x->step == 0) {
+                    j = x;
+                    break;
+                }
+            }
+            // no job could be set up: every request goes to a slot
+            if (!s->jobs[0] && !s->jobs[1]) s->batch_small = false;
+            if (j) {
+                std::vector<Request *> take;
+                {
+                    std::lock_guard<std::mutex> lk(s->mu);
+                    for (auto it = s->waiting.begin();
+                         it != s->waiting.end() && take.size() < BATCH_MAX_GRAPHS;) {
+                        Request *r = *it;
+                        if (!small_request(r->n, r->m) || (!take.empty() && r->wt != take[0]->wt)) {
+                            ++it;
+                            continue;
+                        }
+                        if (!make_room(s, r->footprint)) break;
+                        s->used += r->footprint;
+                        take.push_back(r);
+                        it = s->waiting.erase(it);
+                    }
+                }
+                if (!take.empty()) job_start(s, j, std::move(take));
+            }
+        }
+        // the others (all of them with batching off): one slot each, in
+        // arrival order, while the budget allows
         for (;;) {
             Request *r = nullptr;
             {
                 std::lock_guard<std::mutex> lk(s->mu);
-                if (s->waiting.empty() || s->active.size() >= s->max_slots) break;
-                Request *f = s->waiting.front();
-                while (s->used + f->footprint > s->budget) {
-                    ReqSlot *big = nullptr;
-                    for (ReqSlot *sl : s->pool)
-                        if (sl->kept && (!big || sl->kept > big->kept)) big = sl;
-                    if (!big) break;
-                    ctx_release_workspace(&big->ctx);  // stream-ordered frees
-                    s->used -= big->kept;
-                    big->kept = 0;
-                }
-                if (s->used + f->footprint > s->budget) break;
-                s->waiting.pop_front();
+                if (s->active.size() >= s->max_slots) break;
+                auto it = s->waiting.begin();
+                while (it != s->waiting.end() && s->batch_small && small_request((*it)->n, (*it)->m))
+                    ++it;
+                if (it == s->waiting.end()) break;
+                Request *f = *it;
+                if (!make_room(s, f->footprint)) break;
+                s->waiting.erase(it);
                 s->used += f->footprint;
                 r = f;
             }
             admit(s, r);
         }
-        // one pass over the slots in flight
+        // one pass over the slots and jobs in flight
         bool progressed = false;
         for (size_t i = 0; i < s->active.size();) {
             ReqSlot *sl = s->active[i];
@@ -375,13 +651,25 @@ void worker_main(msf_server *s)
             }
             ++i;
         }
+        bool jobs_busy = false;
+        for (BatchJob *j : s->jobs) {
+            if (!j || j->step == 0) continue;
+            if (hipEventQuery(j->ctx.ev[3]) == hipSuccess) {
+                progressed = true;
+                job_step(s, j);
+            }
+            jobs_busy |= j->step != 0;
+        }
         std::unique_lock<std::mutex> lk(s->mu);
-        if (s->stop && s->active.empty() && s->waiting.empty()) break;
+        if (s->stop && s->active.empty() && s->waiting.empty() && !jobs_busy) break;
         if (!progressed) {
-            if (s->active.empty())
+            if (s->active.empty() && !jobs_busy)
                 s->cv_work.wait_for(lk, std::chrono::milliseconds(5));
-            else
-                s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+            else {
+                // work in flight: poll again soon (a step is tens of us)
+                lk.unlock();
+                std::this_thread::yield();
+            }
         }
     }
     for (ReqSlot *sl : s->pool) {
@@ -391,6 +679,10 @@ void worker_main(msf_server *s)
         delete sl;
     }
     s->pool.clear();
+    for (BatchJob *&j : s->jobs) {
+        if (j) job_free(j);
+        j = nullptr;
+    }
 }
 
 }  // namespace
@@ -410,6 +702,7 @@ msf_status msf_server_create(msf_ctx *ctx, size_t mem_budget_bytes, msf_server *
     }
     s->device = ctx->c.device;
     s->budget = mem_budget_bytes;
+    if (const char *v = getenv("MSF_SERVER_BATCH")) s->batch_small = atoi(v) != 0;
     if (const char *v = getenv("MSF_SERVER_SLOTS")) {
         const long k = atol(v);
         if (k > 0) s->max_slots = (size_t)k;

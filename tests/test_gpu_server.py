@@ -167,3 +167,49 @@ def test_full_pool_at_real_sizes(ctx, pkg):
         assert scnt == cnt and np.array_equal(sids, ids) and stot == tot, (k, kind, n)
     say("full served pool checked", f"{time.time() - t0:.1f}s")
     srv.close()
+
+
+def test_shared_launches_equal_slots(ctx, pkg):
+    """Small requests solved together in shared persistent launches give the
+    same forests as with every request in its own slot (MSF_SERVER_BATCH=0),
+    and both equal solo msf_solve; a failing small request fails alone."""
+    import os
+    pool = gen.serve_pool(24, seed=13, log2_lo=6.0, log2_hi=13.5)
+    bad = (10, np.array([[0, 1], [3, 99]], np.int32), np.array([1.0, 2.0], np.float32), "bad")
+    results = {}
+    for mode in ("1", "0"):
+        old = os.environ.get("MSF_SERVER_BATCH")
+        os.environ["MSF_SERVER_BATCH"] = mode
+        try:
+            srv = pkg.Server(ctx, 8 << 30)
+        finally:
+            if old is None:
+                os.environ.pop("MSF_SERVER_BATCH", None)
+            else:
+                os.environ["MSF_SERVER_BATCH"] = old
+        reqs = pool * 3
+        reqs.insert(17, bad)
+        tickets = [(srv.submit(n, e, w, wtype=F32), n, kind) for n, e, w, kind in reqs]
+        out = []
+        for t, n, kind in tickets:
+            if kind == "bad":
+                with pytest.raises(pkg.MSFError) as ex:
+                    srv.result(t, n)
+                assert ex.value.status == 1
+                continue
+            out.append(srv.result(t, n))
+        srv.close()
+        results[mode] = out
+    good = [p for p in pool * 3]
+    for (a, b, (n, e, w, kind)) in zip(results["1"], results["0"], good):
+        assert a[1] == b[1] and np.array_equal(a[0], b[0]) and a[2] == b[2], (kind, n)
+    for n, e, w, kind in pool:
+        si, sc, st = ctx.solve(n, e, w, wtype=F32)
+        wi, wc, wt = oracle.msf(n, e, w, F32)
+        assert sc == wc and np.array_equal(si.astype(np.int64), wi) and st[1] == wt[1]
+    k = 0
+    for n, e, w, kind in good:
+        ids, cnt, tot = results["1"][k]
+        k += 1
+        wi, wc, wt = oracle.msf(n, e, w, F32)
+        assert cnt == wc and np.array_equal(ids.astype(np.int64), wi) and tot[1] == wt[1]
