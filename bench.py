@@ -401,11 +401,12 @@ def bench_multilinear_round1(ctx, pkg, torch, n, e, w, wtype, reps=25):
     r = torch.empty(n, dtype=torch.int64, device="cuda:0")
     for _ in range(3):
         ctx.multilinear(g, p, r)
-    times = []
+    times, gtimes = [], []
     for _ in range(reps):
         ctx.multilinear(g, p, r)
         st = ctx.stats()  # waits for the sweep's end event
         times.append(st["sweep_ms"][0])
+        gtimes.append(st["pass_ms"][0])
     torch.cuda.synchronize()
     rk = r.cpu().numpy().view(np.uint64)
     roots_written = int((rk != np.uint64(0xFFFFFFFFFFFFFFFF)).sum())
@@ -424,7 +425,11 @@ def bench_multilinear_round1(ctx, pkg, torch, n, e, w, wtype, reps=25):
             "min_ms": float(np.min(times)), "max_ms": float(np.max(times)),
             "bytes": b, "achieved": gb_s, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": gb_s / HBM_PEAK_GBS, "target_frac": 0.40,
-            "gather_bytes_if_every_entry": 4.0 * nnz}
+            "gather_bytes_if_every_entry": 4.0 * nnz,
+            "order_gather_ms": float(np.median(gtimes)),
+            "call_frac": b / 1e9 / ((med + float(np.median(gtimes))) / 1e3) / HBM_PEAK_GBS,
+            "note": "median_ms is the sweep kernel alone; order_gather_ms is the kernel that "
+                    "gathers p into the graph's degree order before it (12 B per vertex)"}
 
 
 def bench_batched(ctx, pkg, torch, G=10000, cpu=True):
@@ -687,6 +692,8 @@ def main():
                     help="run only the connected-components leg (prints its JSON alone)")
     ap.add_argument("--starcheck-only", action="store_true",
                     help="run only the original-AS-rounds leg (prints its JSON alone)")
+    ap.add_argument("--multilinear-only", action="store_true",
+                    help="run only msf_multilinear on R-MAT s22 with the parents after round 1")
     ap.add_argument("--served-only", action="store_true",
                     help="run only the served leg (prints its JSON alone)")
     ap.add_argument("--batched-only", action="store_true",
@@ -746,6 +753,13 @@ def main():
         print(json.dumps({"starcheck": bench_starcheck(
             ctx, pkg, torch, {"rmat_s22_e16": (n22, e22, w22, pkg.W_F32),
                               "grid256": (ng, eg, wg, pkg.W_U32)})}), flush=True)
+        return
+    if args.multilinear_only:
+        import gen
+
+        n22, e22, w22 = gen.workload_rmat_s22()
+        print(json.dumps({"multilinear": bench_multilinear_round1(ctx, pkg, torch, n22, e22, w22,
+                                                                  pkg.W_F32)}), flush=True)
         return
     if args.served_only:
         print(json.dumps({"served": bench_served(ctx, pkg, torch, args.served_requests)}),

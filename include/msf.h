@@ -165,7 +165,12 @@ msf_status msf_get_stats(const msf_ctx *ctx, msf_stats *out);
  * Build and keep the device adjacency structure of a graph: the symmetric
  * adjacency matrix A of section 2 (a_ij = w(i,j), both directions stored,
  * each carrying its edge's key).  Arguments as for msf_solve; the arrays are
- * copied.  *out receives a handle released by msf_graph_destroy.
+ * copied.  *out receives a handle released by msf_graph_destroy.  The
+ * vertices are stored in order of decreasing degree class (bit length of
+ * the degree, ties by id), so the parents the multilinear kernel gathers
+ * most share cache lines; every call on the graph takes and returns vectors
+ * in the caller's vertex order (environment MSF_GRAPH_ORDER=0 keeps the
+ * caller's order inside as well).
  */
 msf_status msf_graph_create(msf_ctx *ctx, int32_t n, int64_t m, const int32_t *edges,
                             const void *weights, msf_wtype wtype, msf_mem mem,
@@ -185,7 +190,9 @@ void msf_graph_destroy(msf_graph *g);
  * the sweep kernel's device time (events on the context's stream around that
  * one launch; msf_get_stats waits for them) and sweep_bytes[0] its streamed
  * bytes (12 per stored entry, 8 per row with entries, 4; the written slots
- * of r are not counted).
+ * of r are not counted).  A graph stores its vertices by decreasing degree
+ * class (msf_graph_create); p is first gathered into that order by a kernel
+ * of its own, timed in pass_ms[0] with pass_bytes[0] = 12 per vertex.
  */
 msf_status msf_multilinear(msf_ctx *ctx, const msf_graph *g, const uint32_t *p, uint64_t *r);
 

@@ -148,6 +148,7 @@ msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc)
     if (const char *f = getenv("MSF_HEADS")) c->heads = atoi(f);
     if (const char *f = getenv("MSF_BATCH_MODE")) c->batch_mode = atoi(f);
     if (const char *f = getenv("MSF_SMALL_M")) c->small_m = atoll(f);
+    if (const char *f = getenv("MSF_GRAPH_ORDER")) c->graph_order = atoi(f);
     return MSF_OK;
 }
 
@@ -300,9 +301,11 @@ msf_status msf_get_stats(const msf_ctx *ctx, msf_stats *out)
         // the sweep of the last msf_multilinear: wait for its end event
         MSF_HIP(hipSetDevice(c->device));
         MSF_HIP(hipEventSynchronize(c->sev[1]));
-        float ms = 0.f;
+        float ms = 0.f, gms = 0.f;
         MSF_HIP(hipEventElapsedTime(&ms, c->sev[0], c->sev[1]));
+        MSF_HIP(hipEventElapsedTime(&gms, c->kev[0], c->sev[0]));
         c->stats.sweep_ms[0] = ms;
+        c->stats.pass_ms[0] = c->stats.pass_bytes[0] > 0 ? gms : 0.0;
         c->ml_pending = false;
     }
     *out = c->stats;
@@ -343,12 +346,44 @@ msf_status msf_graph_create(msf_ctx *ctx, int32_t n, int64_t m, const int32_t *e
         }
     }
     const hipMemcpyKind kind = mem == MSF_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const bool order = c->graph_order != 0 && n > 0;
     if (m > 0) {
-        hipError_t e1 = hipMemcpyAsync(g->bufs[0], edges, 8 * (size_t)m, kind, c->stream);
+        // with the degree order the caller's edges are renumbered into the
+        // graph's copy; host edges go through the workspace first
+        void *src = (void *)edges;
+        hipError_t e1 = hipSuccess;
+        if (order && mem == MSF_MEM_HOST) {
+            if ((rc = ws_get(c, WS_EDGES, 8 * (size_t)m, &src))) {
+                msf_graph_destroy(g);
+                return rc;
+            }
+            e1 = hipMemcpyAsync(src, edges, 8 * (size_t)m, hipMemcpyHostToDevice, c->stream);
+        } else if (!order) {
+            e1 = hipMemcpyAsync(g->bufs[0], edges, 8 * (size_t)m, kind, c->stream);
+        }
         hipError_t e2 = hipMemcpyAsync(g->bufs[1], weights, 4 * (size_t)m, kind, c->stream);
         if (e1 != hipSuccess || e2 != hipSuccess) {
             msf_graph_destroy(g);
             return hip_fail(e1 != hipSuccess ? e1 : e2, "hipMemcpyAsync");
+        }
+        if (order) {
+            void *vdeg, *vtab, *vinv;
+            if (hipMalloc(&g->perm, 4 * nn) != hipSuccess) {
+                (void)hipGetLastError();
+                g->perm = nullptr;
+                msf_graph_destroy(g);
+                set_error("device allocation failed");
+                return MSF_ENOMEM;
+            }
+            if ((rc = ws_get(c, WS_DEG, 4 * nn, &vdeg)) ||
+                (rc = ws_get(c, WS_T2, 4 * relabel_table_words(n), &vtab)) ||
+                (rc = ws_get(c, WS_Q2, 4 * nn, &vinv)) ||
+                (rc = relabel_by_degree(c, n, m, (const int32_t *)src, (uint32_t *)vdeg,
+                                        (uint32_t *)vtab, g->perm, (uint32_t *)vinv,
+                                        (int32_t *)g->bufs[0]))) {
+                msf_graph_destroy(g);
+                return rc;
+            }
         }
     }
     zero_counters(c);
@@ -383,6 +418,7 @@ void msf_graph_destroy(msf_graph *g)
     }
     for (auto &p : g->bufs)
         if (p) (void)hipFree(p);
+    if (g->perm) (void)hipFree(g->perm);
     delete g;
 }
 
@@ -406,16 +442,26 @@ msf_status msf_multilinear(msf_ctx *ctx, const msf_graph *g, const uint32_t *p, 
     if (rc) return rc;
     if ((rc = decode_err(c->hcnt->err))) return rc;
     launch_fill_u64(c->stream, r, KEY_INF, (size_t)n);
-    // device events around the sweep alone (statistics: one round whose
-    // sweep_ms / sweep_bytes describe this kernel)
+    // device events around the gather of p into the graph's vertex order
+    // and around the sweep kernel (statistics: one round whose sweep_ms /
+    // sweep_bytes describe the sweep; pass_ms[0] / pass_bytes[0] the gather)
+    const uint32_t *pg = p;
+    MSF_HIP(hipEventRecord(c->kev[0], c->stream));
+    if (g->perm) {
+        void *vq;
+        if ((rc = ws_get(c, WS_Q, 4 * (size_t)n, &vq))) return rc;
+        launch_relabel_gather(c->stream, p, g->perm, n, (uint32_t *)vq);
+        pg = (const uint32_t *)vq;
+    }
     MSF_HIP(hipEventRecord(c->sev[0], c->stream));
-    launch_sweep(c->stream, g->a, p, r, c->dcnt);
+    launch_sweep(c->stream, g->a, pg, r, c->dcnt);
     MSF_HIP(hipEventRecord(c->sev[1], c->stream));
     MSF_HIP(hipGetLastError());
     c->stats = msf_stats{};
     c->stats.rounds = 1;
     c->stats.active_nnz[0] = g->a.nnz;
     c->stats.sweep_bytes[0] = 12.0 * g->a.nnz + 8.0 * g->a.segs + 4.0;
+    c->stats.pass_bytes[0] = g->perm ? 12.0 * n : 0.0;
     c->ml_pending = true;
     return MSF_OK;
 }
@@ -445,7 +491,14 @@ msf_status msf_multilinear_pairwise(msf_ctx *ctx, const msf_graph *g, const uint
     if ((rc = read_counters(c))) return rc;
     if ((rc = decode_err(c->hcnt->err))) return rc;
     launch_fill_u64(c->stream, r, KEY_INF, (size_t)n);
-    launch_sweep_pairwise(c->stream, g->a, p, r, (uint32_t *)vpj, extent, c->dcnt);
+    const uint32_t *pg = p;
+    if (g->perm) {
+        void *vq;
+        if ((rc = ws_get(c, WS_Q, 4 * (size_t)n, &vq))) return rc;
+        launch_relabel_gather(c->stream, p, g->perm, n, (uint32_t *)vq);
+        pg = (const uint32_t *)vq;
+    }
+    launch_sweep_pairwise(c->stream, g->a, pg, r, (uint32_t *)vpj, extent, c->dcnt);
     MSF_HIP(hipGetLastError());
     return MSF_OK;
 }
@@ -551,12 +604,14 @@ msf_status msf_components(msf_ctx *ctx, const msf_graph *g, uint32_t *labels, in
     Ctx *c = &ctx->c;
     MSF_HIP(hipSetDevice(c->device));
     hipStream_t s = c->stream;
-    void *vr, *vh;
+    void *vr, *vh, *vp = labels;
     msf_status rc;
-    if ((rc = ws_get(c, WS_R, 8 * (size_t)n, &vr)) || (rc = ws_get(c, WS_H, 4 * (size_t)n, &vh)))
+    if ((rc = ws_get(c, WS_R, 8 * (size_t)n, &vr)) || (rc = ws_get(c, WS_H, 4 * (size_t)n, &vh)) ||
+        (g->perm && (rc = ws_get(c, WS_Q2, 4 * (size_t)n, &vp))))
         return rc;
     uint64_t *r = (uint64_t *)vr;
-    uint32_t *h = (uint32_t *)vh, *p = labels;
+    // in the graph's vertex order; labels are translated back at the end
+    uint32_t *h = (uint32_t *)vh, *p = (uint32_t *)vp;
     zero_counters(c);
     launch_iota_u32(s, p, (size_t)n);
     // the number of stars at least halves in a round that hooks, and each
@@ -588,6 +643,8 @@ msf_status msf_components(msf_ctx *ctx, const msf_graph *g, uint32_t *labels, in
         }
         ++done_rounds;
     }
+    if (g->perm) launch_relabel_labels(s, p, g->perm, n, labels);
+    MSF_HIP(hipGetLastError());
     MSF_HIP(hipStreamSynchronize(s));
     if (rounds) *rounds = done_rounds;
     return MSF_OK;

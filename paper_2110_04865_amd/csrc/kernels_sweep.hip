@@ -68,6 +68,15 @@ __device__ __forceinline__ void scan_step(RunAgg &agg, bool recv)
 #ifndef SWEEP_LAZY
 #define SWEEP_LAZY 1
 #endif
+// Gathers and row-window loads issued only by the lanes that need them (1;
+// measured 2.7% faster on R-MAT s22 with the parents after round 1) or by
+// every lane with a clamped index (0).
+#ifndef SWEEP_MASKED_GATHER
+#define SWEEP_MASKED_GATHER 1
+#endif
+#ifndef SWEEP_MASKED_WINDOW
+#define SWEEP_MASKED_WINDOW 1
+#endif
 
 // Rows of a chunk staged in LDS (two per lane); a chunk that spans more
 // rows (long runs of rows without entries in its slice) searches row_ptr in
@@ -256,13 +265,21 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     const int kb = g.kb, ke = g.ke;
     const uint32_t base = g.base;
     const uint32_t t0 = threadIdx.x, t1 = threadIdx.x + SWEEP_BLOCK;
-    const uint32_t wr0 = rp[lo + min(t0, nrows)];
-    const uint32_t wr1 = rp[lo + min(t1, nrows)];
-    const uint32_t wr2 = rp[lo + min((uint32_t)SWEEP_WIN, nrows)];
-    uint32_t wp0 = 0, wp1 = 0;
-    if (!FIRST) {
-        wp0 = p[lo + min(t0, nrows - 1)];
-        wp1 = p[lo + min(t1, nrows - 1)];
+    uint32_t wr0 = 0, wr1 = 0, wr2 = 0, wp0 = 0, wp1 = 0;
+    if (SWEEP_MASKED_WINDOW) {
+        if (t0 <= nrows) wr0 = rp[lo + t0];
+        if (t1 <= nrows) wr1 = rp[lo + t1];
+        if (t0 == 0) wr2 = rp[lo + min((uint32_t)SWEEP_WIN, nrows)];
+        if (!FIRST && t0 < nrows) wp0 = p[lo + t0];
+        if (!FIRST && t1 < nrows) wp1 = p[lo + t1];
+    } else {
+        wr0 = rp[lo + min(t0, nrows)];
+        wr1 = rp[lo + min(t1, nrows)];
+        wr2 = rp[lo + min((uint32_t)SWEEP_WIN, nrows)];
+        if (!FIRST) {
+            wp0 = p[lo + min(t0, nrows - 1)];
+            wp1 = p[lo + min(t1, nrows - 1)];
+        }
     }
     // eager variants gather every column parent now, overlapping the
     // window loads; the lazy plain sweep gathers after the row search
@@ -323,7 +340,10 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
         }
         uint32_t pa[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) pa[e] = p[am[e] ? cl[e] : lo];
+        for (int e = 0; e < E; ++e) {
+            if (SWEEP_MASKED_GATHER) pa[e] = am[e] ? p[cl[e]] : 0u;
+            else pa[e] = p[am[e] ? cl[e] : lo];
+        }
         bool need[E];
         bool any = false;
 #pragma unroll
@@ -344,7 +364,10 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
         if (__ballot(any)) {
             uint32_t pb[E];
 #pragma unroll
-            for (int e = 0; e < E; ++e) pb[e] = p[need[e] ? cl[e] : lo];
+            for (int e = 0; e < E; ++e) {
+                if (SWEEP_MASKED_GATHER) pb[e] = need[e] ? p[cl[e]] : 0u;
+                else pb[e] = p[need[e] ? cl[e] : lo];
+            }
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 if (need[e]) {

@@ -245,6 +245,9 @@ struct Ctx {
     // msf_solve of graphs with at most this many edges (and state that fits
     // LDS) by one workgroup of the persistent kernel; 0 turns it off
     int64_t small_m = (int64_t)1 << 17;
+    // kept graphs (msf_graph_create) store their vertices by decreasing
+    // degree class (1) or in the caller's order (0)
+    int graph_order = 1;
     SolveState ss;
 };
 
@@ -411,6 +414,19 @@ void launch_cc_apply(hipStream_t s, const uint32_t *h, int32_t n, uint32_t *p);
 
 void zero_counters(Ctx *c);
 msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc);
+// Vertex order of a kept graph by decreasing degree class (relabel.hip):
+// perm[new] = old, inv[old] = new, edges_out = the edges renumbered.  deg
+// holds n words, tab relabel_table_words(n).  MSF_EINVAL for an endpoint
+// outside [0, n) (nothing is renumbered then).
+msf_status relabel_by_degree(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, uint32_t *deg,
+                             uint32_t *tab, uint32_t *perm, uint32_t *inv, int32_t *edges_out);
+size_t relabel_table_words(int32_t n);
+// q[i] = p[perm[i]] (a caller's parent vector in the graph's order)
+void launch_relabel_gather(hipStream_t s, const uint32_t *p, const uint32_t *perm, int32_t n,
+                           uint32_t *q);
+// labels[perm[i]] = perm[q[i]] (labels in the graph's order back to caller ids)
+void launch_relabel_labels(hipStream_t s, const uint32_t *q, const uint32_t *perm, int32_t n,
+                           uint32_t *labels);
 // Device address of the static scratch array of msf_solve_batched_noalloc
 // on `device` (taken once per device; the device must be current).
 msf_status noalloc_init(int device);
@@ -446,4 +462,7 @@ struct msf_graph {
     msf_ctx *ctx = nullptr;
     msf::Adj a;
     void *bufs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // vertex order of the stored adjacency: perm[internal] = caller id
+    // (null: the caller's order)
+    uint32_t *perm = nullptr;
 };

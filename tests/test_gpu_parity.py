@@ -364,6 +364,49 @@ def test_multilinear_matches_definition(ctx, pkg):
         multilinear_case(ctx, pkg, n, e, w, wt, sorted_blocks, label + " blocks")
 
 
+def test_graph_vertex_order_is_invisible(pkg):
+    """Kept graphs store their vertices by decreasing degree class
+    (MSF_GRAPH_ORDER=1, the default) or in the caller's order (0): the
+    multilinear kernel (both forms), components and the original AS rounds
+    give identical results either way."""
+    graphs = [("rmat14", *gen.rmat(14, 16, seed=81), F32),
+              ("grid10", *gen.grid(10, 10, 10, 0.2, seed=82), U32),
+              ("er", 3000, *gen.er(3000, 9000, seed=83), U32)]
+    for order in ("1", "0"):
+        with env_set(MSF_GRAPH_ORDER=order):
+            c = pkg.Context(0)
+        res = []
+        for label, n, e, w, wt in graphs:
+            res.append((label, n, e, w, wt, pkg.Graph(c, n, e, w, wtype=wt)))
+        for label, n, e, w, wt, g in res:
+            r = torch.empty(n, dtype=torch.int64, device="cuda:0")
+            rs = np.random.default_rng(85)
+            roots = rs.choice(n, size=max(1, n // 9), replace=False).astype(np.uint32)
+            star = roots[rs.integers(0, len(roots), n)]
+            star[roots] = roots
+            c.multilinear(g, dev(star), r)
+            torch.cuda.synchronize()
+            r1 = r.cpu().numpy().view(np.uint64).copy()
+            assert np.array_equal(r1, oracle.multilinear(n, e, w, wt, star)), (order, label)
+            r.fill_(0)
+            c.multilinear_pairwise(g, dev(star), r)
+            torch.cuda.synchronize()
+            assert np.array_equal(r.cpu().numpy().view(np.uint64), r1), (order, label)
+            lab = torch.empty(n, dtype=torch.int32, device="cuda:0")
+            c.components(g, lab)
+            flags = torch.empty(len(e), dtype=torch.uint8, device="cuda:0")
+            c.solve_starcheck(g, flags)
+            torch.cuda.synchronize()
+            got = lab.cpu().numpy().view(np.uint32).astype(np.int64)
+            want, ncomp = oracle.components(n, e)
+            assert np.array_equal(got[got], got) and np.array_equal(got, got[want]), (order, label)
+            assert len(np.unique(got)) == ncomp, (order, label)
+            ids = np.nonzero(flags.cpu().numpy())[0]
+            assert np.array_equal(ids, oracle.msf(n, e, w, wt)[0]), (order, label)
+            g.close()
+        c.close()
+
+
 def test_multilinear_rejects_bad_parent(ctx, pkg):
     n, e, w = 100, *gen.er(100, 300, seed=1)
     g = pkg.Graph(ctx, n, e, w, wtype=U32)
