@@ -122,6 +122,12 @@ typedef struct {
     int64_t batch_graphs;
     int64_t batch_large;
     double batch_ms;
+    /* msf_solve on the device-wide path with MSF_CHECK_ROUNDS=1 only (0
+       otherwise): vertices that are roots (p[v] == v) at the start of each
+       round.  In that mode every round is checked: every tree is a star
+       after the shortcut, and the roots drop by exactly the kept hooks
+       (MSF_EDEVICE otherwise). */
+    int64_t roots[64];
 } msf_stats;
 
 typedef struct msf_ctx msf_ctx;

@@ -61,7 +61,8 @@ class Stats(ctypes.Structure):
                 ("runs", ctypes.c_int64), ("pass_ms", ctypes.c_double * 4),
                 ("pass_bytes", ctypes.c_double * 4), ("batch_config", ctypes.c_int32),
                 ("batch_grid", ctypes.c_int32), ("batch_graphs", ctypes.c_int64),
-                ("batch_large", ctypes.c_int64), ("batch_ms", ctypes.c_double)]
+                ("batch_large", ctypes.c_int64), ("batch_ms", ctypes.c_double),
+                ("roots", ctypes.c_int64 * 64)]
 
 
 _lib = None
@@ -262,7 +263,7 @@ class Context:
                     runs=s.runs, pass_ms=list(s.pass_ms), pass_bytes=list(s.pass_bytes),
                     batch_config=s.batch_config, batch_grid=s.batch_grid,
                     batch_graphs=s.batch_graphs, batch_large=s.batch_large,
-                    batch_ms=s.batch_ms)
+                    batch_ms=s.batch_ms, roots=list(s.roots[:k]))
 
     # ------------------------------------------------------- primitives --
     def graph(self, n: int, edges, weights, wtype: int | None = None) -> "Graph":

@@ -395,13 +395,13 @@ __global__ __launch_bounds__(256) void k_update_parents(const uint32_t *__restri
 }
 
 void launch_update_parents(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S, uint32_t *p,
-                           const uint32_t *h, uint32_t *part, Counters *dcnt)
+                           const uint32_t *h, uint32_t *part, Counters *dcnt, bool all)
 {
     (void)part;
     (void)dcnt;
     if (!n) return;
     const unsigned g = grid_for((size_t)n, 256, 4096);
-    k_update_parents<<<g, 256, 0, s>>>(row_ptr, n, S, p, h);
+    k_update_parents<<<g, 256, 0, s>>>(row_ptr, n, all ? 2 : S, p, h);
 }
 
 // --------------------------------------------------------------- output --
@@ -794,6 +794,44 @@ __global__ void k_check_roots(const uint32_t *__restrict__ p, const uint32_t *__
         bad |= p[x] != x;
     }
     if (__ballot(bad) && __lane_id() == 0) atomicOr(&cnt->err, ERR_CYCLE);
+}
+
+// ---------------------------------------------------------- round checks --
+// Invariants of a round, checked when MSF_CHECK_ROUNDS is set: every tree is
+// a star after complete shortcutting (section 4.2), and the number of roots
+// drops by exactly the number of kept hooks (the host compares the counts).
+
+__global__ __launch_bounds__(256) void k_count_roots(const uint32_t *__restrict__ p, int32_t n,
+                                                     Counters *cnt)
+{
+    __shared__ uint32_t s_lds[256 / 64 + 1];
+    uint32_t c = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        c += p[i] == (uint32_t)i ? 1u : 0u;
+    c = block_sum<256>(c, s_lds);
+    if (threadIdx.x == 0 && c) atomicAdd(&cnt->roots, c);
+}
+
+__global__ void k_check_stars(const uint32_t *__restrict__ p, int32_t n, Counters *cnt)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t x = p[i];
+        bad |= p[x] != x;
+    }
+    if (__ballot(bad) && __lane_id() == 0) atomicOr(&cnt->err, ERR_STAR);
+}
+
+void launch_count_roots(hipStream_t s, const uint32_t *p, int32_t n, Counters *dcnt)
+{
+    if (n) k_count_roots<<<grid_for((size_t)n, 256, 1024), 256, 0, s>>>(p, n, dcnt);
+}
+
+void launch_check_stars(hipStream_t s, const uint32_t *p, int32_t n, Counters *dcnt)
+{
+    if (n) k_check_stars<<<grid_for((size_t)n, 256, 1024), 256, 0, s>>>(p, n, dcnt);
 }
 
 void launch_check_roots(hipStream_t s, const uint32_t *p, const uint32_t *q, int32_t n,

@@ -45,7 +45,13 @@ constexpr int SWEEP_CHUNK = SWEEP_BLOCK * SWEEP_E;
 constexpr size_t SWEEP_PAD = SWEEP_CHUNK;
 
 // Device error flags raised by validation kernels.
-enum : uint32_t { ERR_ENDPOINT = 1u, ERR_NAN = 2u, ERR_PARENT = 4u, ERR_CYCLE = 8u };
+enum : uint32_t {
+    ERR_ENDPOINT = 1u,
+    ERR_NAN = 2u,
+    ERR_PARENT = 4u,
+    ERR_CYCLE = 8u,
+    ERR_STAR = 16u  // round check: a tree that is not a star after shortcutting
+};
 
 // ---------------------------------------------------------------- device --
 
@@ -125,7 +131,7 @@ struct Counters {
     uint32_t qn[2];       // head sweep queue lengths (alternating rounds)
     uint64_t rf;          // tie break: slots taken, roots << 31 | hooks
     uint32_t tdone;       // tie break: workgroups done
-    uint32_t rf_pad;
+    uint32_t roots;       // round check: vertices with p[v] == v at round start
 };
 
 // Key-sorted runs for the head sweep: every 64-entry chunk of the
@@ -366,8 +372,9 @@ void launch_chase(hipStream_t s, const uint32_t *F, uint32_t nF, uint32_t *h,
                   const uint32_t *hwk, msf_wtype wt, uint32_t *part, Counters *dcnt);
 // S > 1: every vertex is updated (stale parents of vertices without
 // entries are never read); S == 1: only rows that still have entries.
+// all: every vertex (as with S > 1), so p stays exact for every vertex.
 void launch_update_parents(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S, uint32_t *p,
-                           const uint32_t *h, uint32_t *part, Counters *dcnt);
+                           const uint32_t *h, uint32_t *part, Counters *dcnt, bool all = false);
 int64_t output_tiles(int64_t m);
 size_t output_part_bytes(int64_t m);
 // bytes `part` needs for launch_chase
@@ -393,6 +400,10 @@ void launch_jump_init(hipStream_t s, const uint32_t *q, int32_t n, uint32_t *F, 
                       Counters *dcnt);
 void launch_jump_pass(hipStream_t s, const uint32_t *Fin, uint32_t nF, uint32_t *q,
                       uint32_t *Fout, uint64_t *status, Counters *dcnt);
+// Round checks (MSF_CHECK_ROUNDS): dcnt->roots = #{v : p[v] == v} (the
+// caller clears it), and ERR_STAR if some p[p[v]] != p[v].
+void launch_count_roots(hipStream_t s, const uint32_t *p, int32_t n, Counters *dcnt);
+void launch_check_stars(hipStream_t s, const uint32_t *p, int32_t n, Counters *dcnt);
 void launch_check_roots(hipStream_t s, const uint32_t *p, const uint32_t *q, int32_t n,
                         Counters *dcnt);
 // One full pointer-jumping pass over all n vertices; adds the vertices left

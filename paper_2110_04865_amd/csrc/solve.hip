@@ -193,6 +193,12 @@ static msf_status enqueue_round(Ctx *c)
     }
     // with many live roots few runs share one: atomics without a read first
     const bool read_filter = S.nR < READ_FILTER_ROOTS;
+    if (c->check_rounds) {
+        // roots at the start of the round (p is exact for every vertex in
+        // this mode), compared on the host with the hooks of the last round
+        launch_fill_u32(s, &c->dcnt->roots, 0u, 1);
+        launch_count_roots(s, S.b.p, S.n, c->dcnt);
+    }
     if (S.compact) {
         MSF_TRY(get_filter_bufs(c, S.n, S.m, S.a.sl.S, &S.b));
         Adj nxt = S.a;
@@ -276,6 +282,19 @@ msf_status solve_advance(Ctx *c)
             S.st.hooks[k] = nF;
             S.st.active_nnz[k] = S.a.nnz;
         }
+        if (c->check_rounds) {
+            if (h->err & ERR_STAR) {
+                set_error("internal error: a tree is not a star at the start of round %d", k + 1);
+                return MSF_EDEVICE;
+            }
+            if (k < 64) S.st.roots[k] = h->roots;
+            // every kept hook removes exactly one root
+            if (k > 0 && k <= 64 && S.st.roots[k - 1] - S.st.hooks[k - 1] != (int64_t)h->roots) {
+                set_error("internal error: roots %lld -> %u over round %d with %lld hooks",
+                          (long long)S.st.roots[k - 1], h->roots, k, (long long)S.st.hooks[k - 1]);
+                return MSF_EDEVICE;
+            }
+        }
         ++S.rounds;
         if (nF) ++S.st.hook_rounds;
         if (S.compact) {
@@ -306,12 +325,17 @@ msf_status solve_advance(Ctx *c)
             }
         }
         launch_update_parents(s, S.a.row_ptr, S.n, S.a.sl.S, S.b.p, S.b.h, (uint32_t *)S.b.part,
-                              c->dcnt);
+                              c->dcnt, c->check_rounds);
+        if (c->check_rounds) launch_check_stars(s, S.b.p, S.n, c->dcnt);
         S.ri ^= 1;
         S.nR = nRn;
         return more_rounds(S) ? enqueue_round(c) : enqueue_output(c);
     }
     case 4: {  // output ready
+        if (h->err & ERR_STAR) {
+            set_error("internal error: a tree is not a star after the last round");
+            return MSF_EDEVICE;
+        }
         if (h->err) {
             set_error("internal error: hook cycle detected");
             return MSF_EDEVICE;

@@ -241,6 +241,30 @@ def test_rounds_match_algorithm2_oracle(ctx, pkg):
 
 
 @pytest.mark.usefixtures("wide_path")
+def test_round_invariants_checked_on_device(pkg):
+    """MSF_CHECK_ROUNDS=1: after every shortcut every tree is a star, and
+    the roots at the start of each round (counted on the device) equal the
+    oracle's Algorithm 2 run (as_rounds) round by round, so the roots drop by
+    exactly the kept hooks; with the head sweep, the full sweep and every
+    filtering policy."""
+    graphs = [("rmat14", *gen.rmat(14, 16, seed=91), F32),
+              ("grid14 40% dropped", *gen.grid(14, 14, 14, 0.4, seed=92), U32),
+              ("er", 5000, *gen.er(5000, 20000, seed=93), U32),
+              ("path", 3000, np.array([[i, i + 1] for i in range(2999)], np.int32),
+               np.arange(2999, 0, -1).astype(np.uint32), U32)]
+    for heads, filt in (("2", "1"), ("0", "0"), ("0", "2")):
+        with env_set(MSF_CHECK_ROUNDS="1", MSF_HEADS=heads, MSF_FILTER=filt):
+            c = pkg.Context(0)
+        for label, n, e, w, wt in graphs:
+            st = check_solve(c, pkg, n, e, w, wt, f"checked heads={heads} filter={filt} {label}")
+            ref = oracle.as_rounds(n, e, w, wt)
+            k = st["rounds"]
+            assert k >= 1 and st["roots"][:k] == ref["roots"][:k], (label, st["roots"], ref["roots"])
+            assert st["hooks"][:k] == ref["hooks"][:k], (label, st["hooks"], ref["hooks"])
+        c.close()
+
+
+@pytest.mark.usefixtures("wide_path")
 def test_filter_policies_are_result_invariant(pkg):
     """The filtering policies belong to the full sweep (the head sweep passes
     internal entries over by itself), so the head sweep is off here."""
