@@ -97,9 +97,14 @@ typedef struct {
     int32_t head_sweeps;     /* rounds swept over key-sorted runs (heads
                                 only; their sweep_bytes are 0)               */
     int32_t path;            /* msf_solve: 0 rounds of device-wide launches,
-                                1 one workgroup solved the whole graph in
-                                LDS (small graphs; rounds and hooks are set,
-                                rounds_ms is its kernel time)                */
+                                one host round trip per round; 1 one
+                                workgroup solved the whole graph in LDS
+                                (small graphs; rounds and hooks are set,
+                                rounds_ms is its kernel time); 2 rounds
+                                driven on the device, several per host
+                                round trip (full sweep, no filtering); 3
+                                the same, replayed from a captured HIP
+                                graph                                        */
     int64_t runs;            /* key-sorted runs of the adjacency (0: none)   */
     /* Device time (events) and algorithmic bytes of one-launch passes, 0
        when not run.  Index 0: placement of the two-level build (per stored

@@ -149,6 +149,8 @@ msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc)
     if (const char *f = getenv("MSF_BATCH_MODE")) c->batch_mode = atoi(f);
     if (const char *f = getenv("MSF_SMALL_M")) c->small_m = atoll(f);
     if (const char *f = getenv("MSF_GRAPH_ORDER")) c->graph_order = atoi(f);
+    if (const char *f = getenv("MSF_GRAPH_ROUNDS")) c->graph_rounds = atoi(f);
+    if (const char *f = getenv("MSF_GRAPH_ROUNDS_MAX_N")) c->graph_rounds_max_n = atoll(f);
     return MSF_OK;
 }
 
@@ -167,6 +169,8 @@ void ctx_release(Ctx *c)
 {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec), c->gexec = nullptr;
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream), c->cap_stream = nullptr;
     ctx_release_workspace(c);
     (void)hipStreamSynchronize(c->stream);
     for (auto &ev : c->ev)

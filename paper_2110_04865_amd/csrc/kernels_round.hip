@@ -325,6 +325,7 @@ __global__ __launch_bounds__(256) void k_chase_fold(const uint32_t *__restrict__
                                                     const int64_t *__restrict__ wpart,
                                                     uint32_t nb, Counters *cnt)
 {
+    if (cnt->gdone) return;  // rounds driven on the device: nothing was chased
     __shared__ int64_t s_w[4][WS_WORDS + 1];
     uint32_t v = 0, br = 0;
     int64_t w[WS_WORDS] = {};
@@ -363,6 +364,13 @@ __global__ __launch_bounds__(256) void k_chase_fold(const uint32_t *__restrict__
     cnt->inf_neg += (uint32_t)s_w[0][2 + ACC_DIGITS];
 }
 
+
+void launch_chase_fold(hipStream_t s, const uint32_t *part, uint32_t nb, Counters *dcnt)
+{
+    const int64_t *wpart = reinterpret_cast<const int64_t *>(
+        ((uintptr_t)(part + CHASE_BLOCKS) + 7) & ~(uintptr_t)7);
+    k_chase_fold<<<1, 256, 0, s>>>(part, wpart, nb, dcnt);
+}
 
 void launch_chase(hipStream_t s, const uint32_t *F, uint32_t nF, uint32_t *h,
                   const uint32_t *hwk, msf_wtype wt, uint32_t *part, Counters *dcnt)

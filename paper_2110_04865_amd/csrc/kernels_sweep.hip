@@ -234,6 +234,7 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     __shared__ uint32_t s_rp[SWEEP_WIN + 1];
     __shared__ uint32_t s_p[FIRST ? 1 : SWEEP_WIN];
 
+    if (cnt->gdone) return;  // rounds driven on the device: the solve is done
     const uint32_t lane = __lane_id();
     const uint32_t S = (uint32_t)sl.S;
     const uint32_t total = sl.cbase[S];

@@ -132,6 +132,14 @@ struct Counters {
     uint64_t rf;          // tie break: slots taken, roots << 31 | hooks
     uint32_t tdone;       // tie break: workgroups done
     uint32_t roots;       // round check: vertices with p[v] == v at round start
+    // rounds driven on the device (graph rounds): set once a round kept no
+    // hook (every later kernel of the round sequence returns at once), the
+    // kept hooks of the current round, the rounds run and their hooks
+    uint32_t gdone;
+    uint32_t ghooks;
+    uint32_t grounds;
+    uint32_t gpad;
+    uint32_t ghist[64];
 };
 
 // Key-sorted runs for the head sweep: every 64-entry chunk of the
@@ -205,9 +213,11 @@ struct SolveState {
     bool rows_pending = false, compact = false;
     bool first_done = false;  // the build wrote round 1's minima into r
     bool heads = false;       // rounds use the head sweep over key-sorted runs
+    bool graph = false;       // rounds driven on the device, GRAPH_K at a time
     Runs runs;
     uint32_t nruns = 0;
     int ri = 0, ai = 0, rounds = 0;
+    int sweep_events = 0;     // rounds whose sweep start/end events were recorded
     double live_frac = 1.0;
     msf_stats st{};
 };
@@ -254,6 +264,14 @@ struct Ctx {
     // kept graphs (msf_graph_create) store their vertices by decreasing
     // degree class (1) or in the caller's order (0)
     int graph_order = 1;
+    // rounds of the full sweep driven on the device, several per host round
+    // trip, for graphs of at most graph_rounds_max_n vertices: 0 off, 1 as
+    // direct launches, 2 replays of a HIP graph captured once per solve
+    int graph_rounds = 2;
+    int64_t graph_rounds_max_n = (int64_t)1 << 21;
+    hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
+    hipGraphExec_t gexec = nullptr;    // the captured rounds, for gkey
+    uint64_t gkey[16] = {};
     SolveState ss;
 };
 
@@ -379,6 +397,10 @@ int64_t output_tiles(int64_t m);
 size_t output_part_bytes(int64_t m);
 // bytes `part` needs for launch_chase
 size_t chase_part_bytes();
+// Fold nb per-block chase partials held in `part` (the layout launch_chase
+// uses) into dcnt; returns at once when dcnt->gdone is set.
+void launch_chase_fold(hipStream_t s, const uint32_t *part, uint32_t nb, Counters *dcnt);
+constexpr unsigned CHASE_MAX_BLOCKS = 2048;
 
 // Head sweep (kernels_heads.hip).  heads_runs_cap: runs of an adjacency of
 // at most nnz_cap entries over n rows.  build_runs derives the runs of a
@@ -400,6 +422,20 @@ void launch_jump_init(hipStream_t s, const uint32_t *q, int32_t n, uint32_t *F, 
                       Counters *dcnt);
 void launch_jump_pass(hipStream_t s, const uint32_t *Fin, uint32_t nF, uint32_t *q,
                       uint32_t *Fout, uint64_t *status, Counters *dcnt);
+// Rounds driven on the device (kernels_graphround.hip): one round of
+// Algorithm 2 over every vertex with fixed launch sizes, each kernel
+// returning at once when dcnt->gdone is set; sweep = false skips the
+// multilinear sweep (round 1 minima from the build).  Enqueued K rounds at
+// a time, directly or as a captured graph, without host round trips.
+struct GraphRound {
+    Adj a;
+    uint32_t *p, *h, *hedge, *hwk;
+    uint64_t *r;
+    uint8_t *flags;
+    uint32_t *part;
+    msf_wtype wt;
+};
+void enqueue_graph_round(hipStream_t s, const GraphRound &g, Counters *dcnt, bool sweep);
 // Round checks (MSF_CHECK_ROUNDS): dcnt->roots = #{v : p[v] == v} (the
 // caller clears it), and ERR_STAR if some p[p[v]] != p[v].
 void launch_count_roots(hipStream_t s, const uint32_t *p, int32_t n, Counters *dcnt);

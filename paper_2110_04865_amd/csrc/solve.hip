@@ -156,6 +156,9 @@ msf_status solve_start(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, con
               (c->heads == 2 || (c->heads == 1 && 2 * m >= HEADS_MIN_NNZ &&
                                  2 * m >= HEADS_MIN_DEG * (int64_t)n));
     if (S.heads) MSF_TRY(get_runs_bufs(c, n, m, &S.runs));
+    // rounds on the device: the full sweep without filtering, one slice
+    S.graph = !S.heads && slices == 1 && c->graph_rounds > 0 && m > 0 && n > 1 &&
+              (int64_t)n <= c->graph_rounds_max_n && c->filter_mode != 2 && !c->check_rounds;
     MSF_HIP(hipEventRecord(c->ev[0], c->stream));
     zero_counters(c);
     c->pass_done = 0;
@@ -163,7 +166,7 @@ msf_status solve_start(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, con
                             S.b.key[0], S.b.crow[0], c->first_round == 2 ? S.b.r : nullptr,
                             &S.first_done));
     // the build may have fallen back to another slice count
-    if (S.a.sl.S != 1) S.heads = false;
+    if (S.a.sl.S != 1) S.heads = S.graph = false;
     return end_step(c, 1);
 }
 
@@ -186,6 +189,7 @@ static msf_status enqueue_round(Ctx *c)
     else if (c->filter_mode == 1) S.compact = S.live_frac < c->filter_threshold;
     const int ev_k = S.rounds < 64 ? S.rounds : -1;
     if (ev_k >= 0) {
+        S.sweep_events = ev_k + 1;
         MSF_HIP(hipEventRecord(c->sev[2 * ev_k], s));
         S.st.sweep_bytes[ev_k] = (S.rounds == 0 && S.first_done) || S.heads
                                      ? 0.0
@@ -243,6 +247,74 @@ static bool more_rounds(const SolveState &S)
     return S.nR >= 2 && S.a.nnz > 0 && S.rounds < 1000;
 }
 
+// Rounds enqueued per host round trip on the device-driven path.
+constexpr int GRAPH_K = 4;
+
+static GraphRound graph_round_args(const Ctx *c)
+{
+    const SolveState &S = c->ss;
+    GraphRound g;
+    g.a = S.a;
+    g.p = S.b.p;
+    g.h = S.b.h;
+    g.hedge = S.b.hedge;
+    g.hwk = S.b.hwk;
+    g.r = S.b.r;
+    g.flags = S.b.flags;
+    g.part = (uint32_t *)S.b.part;
+    g.wt = S.wt;
+    return g;
+}
+
+// The captured K rounds for this solve's arguments (captured on a private
+// stream, instantiated, and kept in the context while the arguments stay
+// the same).
+static msf_status graph_rounds_exec(Ctx *c)
+{
+    const SolveState &S = c->ss;
+    const uint64_t key[16] = {(uint64_t)S.n, (uint64_t)S.m, (uint64_t)S.a.nnz,
+                              (uint64_t)S.a.nchunks, (uint64_t)(uintptr_t)S.a.row_ptr,
+                              (uint64_t)(uintptr_t)S.a.col, (uint64_t)(uintptr_t)S.a.key,
+                              (uint64_t)(uintptr_t)S.a.chunk_row, (uint64_t)(uintptr_t)S.b.p,
+                              (uint64_t)(uintptr_t)S.b.r, (uint64_t)(uintptr_t)S.b.part,
+                              (uint64_t)(uintptr_t)S.b.flags, (uint64_t)(uintptr_t)S.edges,
+                              (uint64_t)S.wt, (uint64_t)(uintptr_t)c->dcnt,
+                              (uint64_t)S.a.sl.sstart[1]};
+    if (c->gexec && std::equal(key, key + 16, c->gkey)) return MSF_OK;
+    if (c->gexec) {
+        MSF_HIP(hipGraphExecDestroy(c->gexec));
+        c->gexec = nullptr;
+    }
+    if (!c->cap_stream) MSF_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    const GraphRound g = graph_round_args(c);
+    MSF_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < GRAPH_K; ++k) enqueue_graph_round(c->cap_stream, g, c->dcnt, true);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
+    if (ec != hipSuccess || !graph) return hip_fail(ec, "hipStreamEndCapture");
+    const hipError_t ei = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        c->gexec = nullptr;
+        return hip_fail(ei, "hipGraphInstantiate");
+    }
+    std::copy(key, key + 16, c->gkey);
+    return MSF_OK;
+}
+
+// K more device-driven rounds on the context's stream.
+static msf_status enqueue_graph_rounds(Ctx *c)
+{
+    if (c->graph_rounds == 2) {
+        MSF_TRY(graph_rounds_exec(c));
+        MSF_HIP(hipGraphLaunch(c->gexec, c->stream));
+    } else {
+        const GraphRound g = graph_round_args(c);
+        for (int k = 0; k < GRAPH_K; ++k) enqueue_graph_round(c->stream, g, c->dcnt, true);
+    }
+    return end_step(c, 6);
+}
+
 msf_status solve_advance(Ctx *c)
 {
     SolveState &S = c->ss;
@@ -267,13 +339,34 @@ msf_status solve_advance(Ctx *c)
         if (!S.first_done) launch_fill_u64(s, S.b.r, KEY_INF, (size_t)S.n);
         launch_fill_u32(s, reinterpret_cast<uint32_t *>(S.b.flags), 0u, ((size_t)S.m + 3) / 4);
         launch_init_roots(s, S.a.row_ptr, S.n, S.a.sl.S, S.b.R[0], S.b.status, c->dcnt);
-        return end_step(c, 2);
+        MSF_TRY(end_step(c, 2));
+        // capture the device-driven rounds while the GPU runs the set-up
+        if (S.graph && c->graph_rounds == 2) MSF_TRY(graph_rounds_exec(c));
+        return MSF_OK;
     }
     case 2: {  // root list ready
         S.nR = h->nR;
         S.nruns = h->nruns;
         S.st.runs = S.heads ? (int64_t)S.nruns : 0;
-        return more_rounds(S) ? enqueue_round(c) : enqueue_output(c);
+        if (!more_rounds(S)) return enqueue_output(c);
+        if (S.graph) {
+            // round 1 (its minima from the build when it kept them), then
+            // the replays
+            enqueue_graph_round(s, graph_round_args(c), c->dcnt, !S.first_done);
+            return enqueue_graph_rounds(c);
+        }
+        return enqueue_round(c);
+    }
+    case 6: {  // device-driven rounds: counters after the last replay
+        if (!h->gdone && !h->err) return enqueue_graph_rounds(c);
+        S.rounds = (int)h->grounds;
+        for (int k = 0; k < S.rounds && k < 64; ++k) {
+            S.st.hooks[k] = h->ghist[k];
+            S.st.active_nnz[k] = S.a.nnz;
+            if (h->ghist[k]) ++S.st.hook_rounds;
+        }
+        S.st.path = c->graph_rounds == 2 ? 3 : 2;
+        return enqueue_output(c);
     }
     case 3: {  // round counters ready
         const uint32_t nF = h->nF, nRn = h->nR;
@@ -345,9 +438,11 @@ msf_status solve_advance(Ctx *c)
         (void)hipEventElapsedTime(&ms_rounds, c->ev[1], c->ev[2]);
         S.st.build_ms = ms_build;
         S.st.rounds_ms = ms_rounds;
-        for (int k = 0; k < S.rounds && k < 64; ++k) {
+        // only the rounds that recorded their sweep events (none when the
+        // rounds ran on the device)
+        for (int k = 0; k < S.sweep_events; ++k) {
             float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, c->sev[2 * k], c->sev[2 * k + 1]);
+            MSF_HIP(hipEventElapsedTime(&ms, c->sev[2 * k], c->sev[2 * k + 1]));
             S.st.sweep_ms[k] = ms;
         }
         const double nnz = (double)S.a.nnz;

@@ -241,6 +241,36 @@ def test_rounds_match_algorithm2_oracle(ctx, pkg):
 
 
 @pytest.mark.usefixtures("wide_path")
+def test_device_driven_rounds_match(pkg):
+    """Rounds driven on the device, as direct launches (1) and as replays of
+    a HIP graph captured once per solve (2), give the oracle's forests and
+    hooks per round, like the host-stepped loop (0); a second pass over the
+    same graphs replays the cached graph, and the graphs alternate so it is
+    captured again between them."""
+    rng = np.random.default_rng(95)
+    graphs = [("rmat14", *gen.rmat(14, 16, seed=96), F32),
+              ("grid16", *gen.grid(16, 16, 16, 0.05, seed=97), U32),
+              ("grid14 40% dropped", *gen.grid(14, 14, 14, 0.4, seed=98), U32),
+              ("er", 20000, *gen.er(20000, 80000, seed=99), U32),
+              ("path", 3000, np.array([[i, i + 1] for i in range(2999)], np.int32),
+               np.arange(2999, 0, -1).astype(np.uint32), U32),
+              ("multi", 300, rng.integers(0, 300, size=(5000, 2)).astype(np.int32),
+               rng.integers(0, 4, size=5000).astype(np.uint32), U32)]
+    want_path = {"2": 3, "1": 2, "0": 0}
+    for mode in ("2", "1", "0"):
+        with env_set(MSF_GRAPH_ROUNDS=mode):
+            c = pkg.Context(0)
+        for rep in range(2):
+            for label, n, e, w, wt in graphs:
+                st = check_solve(c, pkg, n, e, w, wt, f"rounds mode={mode} rep={rep} {label}",
+                                 device=rep == 0)
+                assert st["path"] == want_path[mode], (label, st["path"])
+                hooks = [h for h in oracle.as_rounds(n, e, w, wt)["hooks"] if h]
+                assert st["hooks"][:len(hooks)] == hooks, (label, st["hooks"], hooks)
+        c.close()
+
+
+@pytest.mark.usefixtures("wide_path")
 def test_round_invariants_checked_on_device(pkg):
     """MSF_CHECK_ROUNDS=1: after every shortcut every tree is a star, and
     the roots at the start of each round (counted on the device) equal the
