@@ -414,6 +414,7 @@ def bench_multilinear_round1(ctx, pkg, torch, n, e, w, wtype, reps=25):
     rows = int((deg > 0).sum())
     nnz = int(deg.sum())
     pn = p.cpu().numpy()
+    shares = bench_row_shares(ctx, pkg, torch, g, p, r, n, deg, reps)
     g.close()
     med = float(np.median(times))
     b = 12.0 * nnz + 4.0 * (rows + 1) + 4.0 * rows + 8.0 * roots_written
@@ -429,7 +430,48 @@ def bench_multilinear_round1(ctx, pkg, torch, n, e, w, wtype, reps=25):
             "order_gather_ms": float(np.median(gtimes)),
             "call_frac": b / 1e9 / ((med + float(np.median(gtimes))) / 1e3) / HBM_PEAK_GBS,
             "note": "median_ms is the sweep kernel alone; order_gather_ms is the kernel that "
-                    "gathers p into the graph's degree order before it (12 B per vertex)"}
+                    "gathers p into the graph's degree order before it (12 B per vertex)",
+            "row_shares": shares}
+
+
+def bench_row_shares(ctx, pkg, torch, g, p, r, n, deg, reps, parts=8):
+    """One device's share of the sweep when the rows of A are split `parts`
+    ways with the whole p on every device (the sharding of the design notes):
+    msf_multilinear_rows over entry-balanced ranges of stored rows, median
+    sweep time per range, bytes as for the whole kernel over the range."""
+    import numpy as np
+
+    od = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    ctx.graph_order(g, od)
+    order = od.cpu().numpy().astype(np.int64)
+    sdeg = deg[order]
+    pre = np.concatenate([[0], np.cumsum(sdeg)])
+    tot = int(pre[-1])
+    cuts = [0] + [int(np.searchsorted(pre, tot * k // parts)) for k in range(1, parts)] + [n]
+    out = []
+    for lo, hi in zip(cuts, cuts[1:]):
+        for _ in range(2):
+            ctx.multilinear_rows(g, p, r, lo, hi)
+        ts = []
+        for _ in range(reps):
+            ctx.multilinear_rows(g, p, r, lo, hi)
+            ts.append(ctx.stats()["sweep_ms"][0])
+        torch.cuda.synchronize()
+        rk = r.cpu().numpy().view(np.uint64)
+        written = int((rk != np.uint64(0xFFFFFFFFFFFFFFFF)).sum())
+        nnz_s = int(pre[hi] - pre[lo])
+        rows_s = int((sdeg[lo:hi] > 0).sum())
+        b = 12.0 * nnz_s + 4.0 * (rows_s + 1) + 4.0 * rows_s + 8.0 * written
+        med = float(np.median(ts))
+        out.append({"rows": [lo, hi], "nnz": nnz_s, "rows_with_entries": rows_s,
+                    "roots_written": written, "median_ms": med, "bytes": b,
+                    "achieved": b / 1e9 / (med / 1e3)})
+    slow = max(out, key=lambda x: x["median_ms"])
+    return {"parts": parts, "order": "stored (degree-class) order, ranges balanced by entries",
+            "slowest_ms": slow["median_ms"], "slowest_rows": slow["rows"],
+            "sum_ms": float(sum(x["median_ms"] for x in out)),
+            "frac_of_slowest": slow["achieved"] / HBM_PEAK_GBS, "unit": "GB/s",
+            "shares": out}
 
 
 def bench_batched(ctx, pkg, torch, G=10000, cpu=True):

@@ -146,6 +146,8 @@ typedef struct msf_server msf_server;
  * calls on one context must not overlap in time.
  */
 msf_status msf_ctx_create(int device, void *hip_stream, msf_ctx **out);
+/* Releases the context.  Every graph and server made on it must be
+ * destroyed first (they use its stream and workspace). */
 void msf_ctx_destroy(msf_ctx *ctx);
 
 /* Thread-local message describing the last error ("" if none). */
@@ -208,6 +210,34 @@ void msf_graph_destroy(msf_graph *g);
 msf_status msf_multilinear(msf_ctx *ctx, const msf_graph *g, const uint32_t *p, uint64_t *r);
 
 /*
+ * One owner's share of the multilinear kernel when the rows of A are split
+ * among several devices that each hold the whole parent vector (section 5
+ * distributes A; here one device computes the share of a contiguous block
+ * of stored rows): r as for msf_multilinear, but over the stored directions
+ * whose row is one of the stored rows row_lo .. row_hi - 1 only.  The
+ * shares of a partition of the rows combine by element-wise minimum into
+ * msf_multilinear's r.
+ *   row_lo, row_hi  0 <= row_lo <= row_hi <= n, positions in the graph's
+ *                   stored vertex order (msf_graph_order); MSF_EINVAL
+ *                   outside that range, or for a graph stored as several
+ *                   column slices (MSF_SLICES)
+ *   p, r            as for msf_multilinear (r is written for all n vertices)
+ * Ordered on the context's stream; synchronises once before the sweep (to
+ * read the range's entry bounds).  Statistics as for msf_multilinear, with
+ * sweep_bytes[0] counting the range's entries and rows.
+ */
+msf_status msf_multilinear_rows(msf_ctx *ctx, const msf_graph *g, const uint32_t *p, uint64_t *r,
+                                int32_t row_lo, int32_t row_hi);
+
+/*
+ * The graph's stored vertex order: order[k] = the caller's id of the vertex
+ * stored as row k (the identity for a graph kept in the caller's order).
+ *   order  device uint32[n] out
+ * Returns after synchronising.
+ */
+msf_status msf_graph_order(msf_ctx *ctx, const msf_graph *g, uint32_t *order);
+
+/*
  * The same r by the pairwise formulation of section 4.1, for comparing the
  * two: a first pass stores the pair (a_ij, p_j) of every stored entry (the
  * column parent p_j beside the entry's key: nnz extra writes of 4 bytes), a
@@ -255,13 +285,20 @@ msf_status msf_shortcut_strategy(msf_ctx *ctx, int32_t n, uint32_t *p, int32_t s
  * the Awerbuch-Shiloach algorithm (section 2.4): each star root hooks along
  * an edge leaving its star (here the minimum-key one, from the multilinear
  * kernel), the smaller of two roots that hooked onto each other stays root,
- * and full pointer-jumping passes make every tree a star again.
+ * and complete shortcutting over the hooked roots makes every tree a star
+ * again.  On a graph where msf_solve takes the head sweep (one column slice,
+ * at least 2^20 stored entries and 16 per vertex, or MSF_HEADS=2) the rounds
+ * are msf_solve's, over a copy of the graph's entries sorted by (row, key)
+ * in 64-entry chunks; otherwise they run on the device four at a time, with
+ * the host reading the termination flag between groups.  The graph is only
+ * read.
  *   labels  device uint32[n] out: labels[i] == labels[j] iff i and j are
  *           connected; each label is a vertex of its component (the root
  *           its tree ended at, not necessarily the smallest id)
  *   rounds  (host, nullable) receives the number of hooking rounds
  * Ordered on the context's stream; returns after synchronising.  Uses the
- * context's workspace (12 bytes per vertex).
+ * context's workspace (as msf_solve on the same graph, or 24 bytes per
+ * vertex and 1 per edge); msf_get_stats afterwards describes the rounds.
  */
 msf_status msf_components(msf_ctx *ctx, const msf_graph *g, uint32_t *labels, int32_t *rounds);
 

@@ -77,6 +77,8 @@ def _load():
     lib.oracle_kruskal.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P]
     lib.oracle_multilinear.restype = None
     lib.oracle_multilinear.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P]
+    lib.oracle_multilinear_rows.restype = None
+    lib.oracle_multilinear_rows.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P, P]
     lib.oracle_find_roots.restype = ctypes.c_int
     lib.oracle_find_roots.argtypes = [ctypes.c_int32, P, P]
     lib.oracle_components.restype = ctypes.c_int64
@@ -161,15 +163,34 @@ def msf(n: int, edges, w, wtype: int):
     return ids, int(cnt), total(w, ids, wtype)
 
 
-def multilinear(n: int, edges, w, wtype: int, p) -> np.ndarray:
-    """r[k] = min key over stored directions i->j with p[i]==k != p[j]."""
+def multilinear(n: int, edges, w, wtype: int, p, rows=None) -> np.ndarray:
+    """r[k] = min key over stored directions i->j with p[i]==k != p[j].
+
+    rows (optional): the row subset, as vertex ids or a boolean mask of
+    length n; only stored directions i->j with i in it count (one owner's
+    share when the rows of A are split, section 5)."""
     e = validate(n, edges, w, wtype)
     keys = np.ascontiguousarray(edge_keys(w, wtype))
     p = np.ascontiguousarray(np.asarray(p, dtype=np.uint32))
     if len(p) != n or (n and p.max() >= n):
         raise ValueError("bad parent vector")
     r = np.empty(max(n, 1), dtype=np.uint64)
-    _load().oracle_multilinear(n, len(e), _ptr(e), _ptr(keys), _ptr(p), _ptr(r))
+    if rows is None:
+        _load().oracle_multilinear(n, len(e), _ptr(e), _ptr(keys), _ptr(p), _ptr(r))
+        return r[:n]
+    rows = np.asarray(rows)
+    mask = np.zeros(max(n, 1), dtype=np.uint8)
+    if rows.dtype == np.bool_:
+        if len(rows) != n:
+            raise ValueError("row mask must have length n")
+        mask[:n] = rows
+    else:
+        rows = rows.astype(np.int64)
+        if len(rows) and (rows.min() < 0 or rows.max() >= n):
+            raise ValueError("row id out of range")
+        mask[rows] = 1
+    _load().oracle_multilinear_rows(n, len(e), _ptr(e), _ptr(keys), _ptr(p), _ptr(mask),
+                                    _ptr(r))
     return r[:n]
 
 

@@ -21,6 +21,10 @@
  *    vertex, projected onto its parent): for every stored direction i->j of
  *    every edge with p[i] != p[j], r[p[i]] = min(r[p[i]], key).
  *
+ *  - oracle_multilinear_rows: the same over the stored directions whose row
+ *    lies in a given subset of the vertices (one owner's share when the
+ *    rows of A are split, section 5).
+ *
  *  - oracle_find_roots: the result of complete shortcutting (section 4.2):
  *    every vertex points at the root of its tree in the parent forest.
  *
@@ -107,6 +111,31 @@ void oracle_multilinear(int32_t n, int64_t m, const int32_t *edges, const uint64
         if (keys[e] < r[pu]) /* direction u -> v */
             r[pu] = keys[e];
         if (keys[e] < r[pv]) /* direction v -> u */
+            r[pv] = keys[e];
+    }
+}
+
+/*
+ * The same kernel over the stored directions whose row is in a subset of the
+ * vertices (row_in[i] != 0): the share of the minima that one owner of
+ * those rows computes when the rows of A are split among several owners,
+ * each holding the whole parent vector (section 5).
+ */
+void oracle_multilinear_rows(int32_t n, int64_t m, const int32_t *edges, const uint64_t *keys,
+                             const uint32_t *p, const uint8_t *row_in, uint64_t *r)
+{
+    int64_t e;
+    int32_t i;
+    for (i = 0; i < n; ++i)
+        r[i] = UINT64_MAX;
+    for (e = 0; e < m; ++e) {
+        int32_t u = edges[2 * e], v = edges[2 * e + 1];
+        uint32_t pu = p[u], pv = p[v];
+        if (pu == pv)
+            continue;
+        if (row_in[u] && keys[e] < r[pu]) /* direction u -> v, row u */
+            r[pu] = keys[e];
+        if (row_in[v] && keys[e] < r[pv]) /* direction v -> u, row v */
             r[pv] = keys[e];
     }
 }

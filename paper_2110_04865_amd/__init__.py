@@ -10,8 +10,10 @@ raises :class:`MSFError` if ``libmsf.so`` has not been built.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -38,6 +40,7 @@ EXPORTS = [
     "msf_shortcut", "msf_solve_batched", "msf_server_create", "msf_server_destroy",
     "msf_server_submit", "msf_server_poll", "msf_server_latency", "msf_server_result",
     "msf_request_footprint", "msf_batch_configs", "msf_solve_batched_noalloc",
+    "msf_multilinear_rows", "msf_graph_order",
 ]
 
 
@@ -98,6 +101,10 @@ def lib():
     L.msf_multilinear.restype = st
     L.msf_multilinear_pairwise.argtypes = [P, P, P, P]
     L.msf_multilinear_pairwise.restype = st
+    L.msf_multilinear_rows.argtypes = [P, P, P, P, I32, I32]
+    L.msf_multilinear_rows.restype = st
+    L.msf_graph_order.argtypes = [P, P, P]
+    L.msf_graph_order.restype = st
     L.msf_shortcut.argtypes = [P, I32, P, ctypes.POINTER(I32)]
     L.msf_shortcut.restype = st
     L.msf_shortcut_strategy.argtypes = [P, I32, P, I32, ctypes.c_double, ctypes.POINTER(I32)]
@@ -187,6 +194,18 @@ def footprint(n: int, m: int) -> int:
     return int(lib().msf_request_footprint(n, m))
 
 
+# Live contexts, released (with their graphs and servers) at interpreter
+# exit, before module teardown: handles left open (by an exception, say)
+# are not freed by finalisers running in an unspecified order.
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _release_all():
+    for c in list(_LIVE):
+        c.close()
+
+
 class Context:
     """An ``msf_ctx`` on one HIP device, ordered on one stream."""
 
@@ -204,8 +223,13 @@ class Context:
         _check(L.msf_ctx_create(device, ctypes.c_void_p(stream or 0), ctypes.byref(h)))
         self._h = h
         self.device = device
+        # graphs and servers made on this context: released before it
+        self._children = weakref.WeakSet()
+        _LIVE.add(self)
 
     def close(self):
+        for ch in list(getattr(self, "_children", ())):
+            ch.close()
         if getattr(self, "_h", None) is not None and self._h.value and _lib is not None:
             _lib.msf_ctx_destroy(self._h)
         self._h = None
@@ -276,6 +300,18 @@ class Context:
         (bit pattern of uint64 keys).  Stream-ordered."""
         _check(lib().msf_multilinear(self._h, g._h, _dev(p, "p", g.n, 4),
                                      _dev(r, "r", g.n, 8)))
+
+    def multilinear_rows(self, g: "Graph", p, r, row_lo: int, row_hi: int):
+        """multilinear() over the stored rows row_lo .. row_hi - 1 only (one
+        owner's share when the rows are split); arguments as for
+        multilinear, rows in the graph's stored order (graph_order)."""
+        _check(lib().msf_multilinear_rows(self._h, g._h, _dev(p, "p", g.n, 4),
+                                          _dev(r, "r", g.n, 8), int(row_lo), int(row_hi)))
+
+    def graph_order(self, g: "Graph", order):
+        """order[k] = caller id of the vertex stored as row k, into a device
+        int32/uint32 tensor [n]."""
+        _check(lib().msf_graph_order(self._h, g._h, _dev(order, "order", g.n, 4)))
 
     def multilinear_pairwise(self, g: "Graph", p, r):
         """The same r by the pairwise formulation (pairs (a_ij, p_j) stored
@@ -392,6 +428,7 @@ class Graph:
         self.n = n
         self.m = m
         self.ctx = ctx
+        ctx._children.add(self)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value and _lib is not None:
@@ -409,6 +446,7 @@ class Server:
         _check(lib().msf_server_create(ctx._h, mem_budget_bytes, ctypes.byref(h)))
         self._h = h
         self.ctx = ctx
+        ctx._children.add(self)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value and _lib is not None:

@@ -75,6 +75,15 @@ void zero_counters(Ctx *c)
                     sizeof(Counters) / sizeof(uint32_t));
 }
 
+// The error word and the device-driven rounds' termination flag (which
+// the sweep and the chase fold test at entry), before a call that runs
+// those kernels outside a solve.
+static void clear_err_done(Ctx *c)
+{
+    launch_fill_u32(c->stream, &c->dcnt->err, 0u, 1);
+    launch_fill_u32(c->stream, &c->dcnt->gdone, 0u, 1);
+}
+
 msf_status decode_err(uint32_t err)
 {
     if (err & ERR_ENDPOINT) {
@@ -440,7 +449,7 @@ msf_status msf_multilinear(msf_ctx *ctx, const msf_graph *g, const uint32_t *p, 
     if (n == 0) return MSF_OK;
     Ctx *c = &ctx->c;
     MSF_HIP(hipSetDevice(c->device));
-    launch_fill_u32(c->stream, &c->dcnt->err, 0u, 1);
+    clear_err_done(c);
     launch_check_parents(c->stream, p, n, c->dcnt);
     msf_status rc = read_counters(c);
     if (rc) return rc;
@@ -470,6 +479,99 @@ msf_status msf_multilinear(msf_ctx *ctx, const msf_graph *g, const uint32_t *p, 
     return MSF_OK;
 }
 
+msf_status msf_multilinear_rows(msf_ctx *ctx, const msf_graph *g, const uint32_t *p, uint64_t *r,
+                                int32_t row_lo, int32_t row_hi)
+{
+    if (!ctx || !g || g->ctx != ctx) {
+        set_error("bad ctx/graph");
+        return MSF_EINVAL;
+    }
+    const int32_t n = g->a.n;
+    if (row_lo < 0 || row_hi < row_lo || row_hi > n) {
+        set_error("row range [%d, %d) outside [0, %d)", row_lo, row_hi, n);
+        return MSF_EINVAL;
+    }
+    if (g->a.sl.S != 1) {
+        set_error("row ranges need a graph stored as one column slice");
+        return MSF_EINVAL;
+    }
+    if (n > 0 && (!p || !r)) {
+        set_error("NULL p/r");
+        return MSF_EINVAL;
+    }
+    if (n == 0) return MSF_OK;
+    Ctx *c = &ctx->c;
+    MSF_HIP(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    // the range's entries [row_ptr[row_lo], row_ptr[row_hi]) and its rows
+    // with entries, then the parent check
+    Adj rows = g->a;
+    rows.row_ptr = g->a.row_ptr + row_lo;
+    rows.n = row_hi - row_lo;
+    zero_counters(c);
+    launch_slice_info(s, rows, c->dcnt);
+    launch_check_parents(s, p, n, c->dcnt);
+    msf_status rc = read_counters(c);
+    if (rc) return rc;
+    if ((rc = decode_err(c->hcnt->err))) return rc;
+    // the graph's adjacency with its entry range cut to the row range (the
+    // sweep takes the entries of a slice from its start and end), and the
+    // chunk-row table of that range
+    Adj a = g->a;
+    a.sl.sstart[0] = c->hcnt->sstart[0];
+    a.sl.sstart[1] = c->hcnt->sstart[1];
+    set_chunks(&a);
+    a.segs = c->hcnt->segs;
+    void *vcr;
+    if ((rc = ws_get(c, WS_CHUNKROW2, 4 * ((size_t)a.nchunks + 1), &vcr))) return rc;
+    a.chunk_row = (uint32_t *)vcr;
+    if (a.nnz) launch_chunk_rows_sliced(s, a);
+    launch_fill_u64(s, r, KEY_INF, (size_t)n);
+    // device events as in msf_multilinear
+    const uint32_t *pg = p;
+    MSF_HIP(hipEventRecord(c->kev[0], s));
+    if (g->perm) {
+        void *vq;
+        if ((rc = ws_get(c, WS_Q, 4 * (size_t)n, &vq))) return rc;
+        launch_relabel_gather(s, p, g->perm, n, (uint32_t *)vq);
+        pg = (const uint32_t *)vq;
+    }
+    MSF_HIP(hipEventRecord(c->sev[0], s));
+    launch_sweep(s, a, pg, r, c->dcnt);
+    MSF_HIP(hipEventRecord(c->sev[1], s));
+    MSF_HIP(hipGetLastError());
+    c->stats = msf_stats{};
+    c->stats.rounds = 1;
+    c->stats.active_nnz[0] = a.nnz;
+    c->stats.sweep_bytes[0] = 12.0 * a.nnz + 8.0 * a.segs + 4.0;
+    c->stats.pass_bytes[0] = g->perm ? 12.0 * n : 0.0;
+    c->ml_pending = true;
+    return MSF_OK;
+}
+
+msf_status msf_graph_order(msf_ctx *ctx, const msf_graph *g, uint32_t *order)
+{
+    if (!ctx || !g || g->ctx != ctx) {
+        set_error("bad ctx/graph");
+        return MSF_EINVAL;
+    }
+    const int32_t n = g->a.n;
+    if (n > 0 && !order) {
+        set_error("NULL order");
+        return MSF_EINVAL;
+    }
+    if (n == 0) return MSF_OK;
+    Ctx *c = &ctx->c;
+    MSF_HIP(hipSetDevice(c->device));
+    if (g->perm)
+        MSF_HIP(hipMemcpyAsync(order, g->perm, 4 * (size_t)n, hipMemcpyDeviceToDevice, c->stream));
+    else
+        launch_iota_u32(c->stream, order, (size_t)n);
+    MSF_HIP(hipGetLastError());
+    MSF_HIP(hipStreamSynchronize(c->stream));
+    return MSF_OK;
+}
+
 msf_status msf_multilinear_pairwise(msf_ctx *ctx, const msf_graph *g, const uint32_t *p,
                                     uint64_t *r)
 {
@@ -490,7 +592,7 @@ msf_status msf_multilinear_pairwise(msf_ctx *ctx, const msf_graph *g, const uint
     void *vpj;
     msf_status rc = ws_get(c, WS_PAIR, 4 * extent, &vpj);
     if (rc) return rc;
-    launch_fill_u32(c->stream, &c->dcnt->err, 0u, 1);
+    clear_err_done(c);
     launch_check_parents(c->stream, p, n, c->dcnt);
     if ((rc = read_counters(c))) return rc;
     if ((rc = decode_err(c->hcnt->err))) return rc;
@@ -608,49 +710,61 @@ msf_status msf_components(msf_ctx *ctx, const msf_graph *g, uint32_t *labels, in
     Ctx *c = &ctx->c;
     MSF_HIP(hipSetDevice(c->device));
     hipStream_t s = c->stream;
-    void *vr, *vh, *vp = labels;
     msf_status rc;
-    if ((rc = ws_get(c, WS_R, 8 * (size_t)n, &vr)) || (rc = ws_get(c, WS_H, 4 * (size_t)n, &vh)) ||
-        (g->perm && (rc = ws_get(c, WS_Q2, 4 * (size_t)n, &vp))))
-        return rc;
-    uint64_t *r = (uint64_t *)vr;
-    // in the graph's vertex order; labels are translated back at the end
-    uint32_t *h = (uint32_t *)vh, *p = (uint32_t *)vp;
-    zero_counters(c);
-    launch_iota_u32(s, p, (size_t)n);
-    // the number of stars at least halves in a round that hooks, and each
-    // pointer-jumping pass halves every distance to a root
-    int cap = 2;
-    while ((1ll << (cap - 1)) < (long long)n) ++cap;  // ceil(log2 n) + 1
-    int done_rounds = 0;
-    for (;;) {
-        launch_fill_u64(s, r, KEY_INF, (size_t)n);
-        launch_sweep(s, g->a, p, r, c->dcnt);
-        launch_fill_u32(s, &c->dcnt->nR, 0u, 1);
-        launch_cc_hook(s, p, r, g->a.edges, n, h, c->dcnt);
-        if ((rc = read_counters(c))) return rc;
-        if (c->hcnt->nR == 0) break;
-        if (done_rounds >= cap) {
-            set_error("components: no convergence");
-            return MSF_EDEVICE;
+    if (kept_heads_eligible(c, g->a)) {
+        // the host-stepped rounds with the head sweep (as msf_solve takes
+        // them on such a graph), over a sorted copy of the graph's entries
+        if ((rc = solve_start_kept(c, g->a, g->perm, labels))) return rc;
+        while (!solve_done(c)) {
+            MSF_HIP(hipEventSynchronize(c->ev[3]));
+            if ((rc = solve_advance(c))) return rc;
         }
-        launch_cc_apply(s, h, n, p);
-        for (int pass = 0;; ++pass) {
-            if (pass > cap) {
-                set_error("components: shortcut did not converge");
-                return MSF_EDEVICE;
-            }
-            launch_fill_u32(s, &c->dcnt->nR, 0u, 1);
-            launch_jump_full(s, p, n, c->dcnt);
-            if ((rc = read_counters(c))) return rc;
-            if (c->hcnt->nR == 0) break;
-        }
-        ++done_rounds;
+        MSF_HIP(hipStreamSynchronize(s));
+        if (rounds) *rounds = c->stats.hook_rounds;
+        return MSF_OK;
     }
-    if (g->perm) launch_relabel_labels(s, p, g->perm, n, labels);
+    const size_t nn = (size_t)n;
+    void *vr, *vh, *ve, *vw, *vf, *vpart, *vp = labels;
+    if ((rc = ws_get(c, WS_R, 8 * nn, &vr)) || (rc = ws_get(c, WS_H, 4 * nn, &vh)) ||
+        (rc = ws_get(c, WS_HEDGE, 4 * nn, &ve)) || (rc = ws_get(c, WS_HWK, 4 * nn, &vw)) ||
+        (rc = ws_get(c, WS_FLAGS, (size_t)std::max<int64_t>(g->a.m, 1) + 4, &vf)) ||
+        (rc = ws_get(c, WS_PART, chase_part_bytes(), &vpart)) ||
+        (g->perm && (rc = ws_get(c, WS_Q2, 4 * nn, &vp))))
+        return rc;
+    // otherwise the rounds of the forest solve, all on the device (fixed launch sizes,
+    // termination by the device flag): the forest flags and weight sums they
+    // keep are not read; p ends as the root of every vertex's tree, in the
+    // graph's vertex order, translated back at the end
+    GraphRound R;
+    R.a = g->a;
+    R.p = (uint32_t *)vp;
+    R.h = (uint32_t *)vh;
+    R.hedge = (uint32_t *)ve;
+    R.hwk = (uint32_t *)vw;
+    R.r = (uint64_t *)vr;
+    R.flags = (uint8_t *)vf;
+    R.part = (uint32_t *)vpart;
+    R.wt = MSF_W_U32;  // the weight sum is not read
+    zero_counters(c);
+    launch_iota_u32(s, R.p, nn);
+    launch_fill_u64(s, R.r, KEY_INF, nn);
+    for (;;) {
+        for (int k = 0; k < 4; ++k) enqueue_graph_round(s, R, c->dcnt, true);
+        if ((rc = read_counters(c))) return rc;
+        if ((rc = decode_err(c->hcnt->err))) return rc;
+        if (c->hcnt->gdone) break;
+    }
+    // the flag stays set only while device-driven rounds run
+    launch_fill_u32(s, &c->dcnt->gdone, 0u, 1);
+    if (g->perm) launch_relabel_labels(s, R.p, g->perm, n, labels);
     MSF_HIP(hipGetLastError());
     MSF_HIP(hipStreamSynchronize(s));
-    if (rounds) *rounds = done_rounds;
+    if (rounds) {
+        // rounds that kept a hook (the last round keeps none)
+        int32_t k = 0;
+        for (uint32_t i = 0; i < c->hcnt->grounds && i < 64; ++i) k += c->hcnt->ghist[i] != 0;
+        *rounds = k;
+    }
     return MSF_OK;
 }
 

@@ -231,16 +231,19 @@ __global__ __launch_bounds__(256) void k_runs_write(const uint32_t *__restrict__
     }
 }
 
-// Sort every 64-entry chunk by (run, key) in place with a bitonic network
-// over the lanes (one wave per chunk; keys are distinct within a row, and
-// runs keep their places) and store each run's head (its smallest key) into
-// its descriptor.  The chunk's runs are cfirst[c] .. cfirst[c + 1] - 1 (the
+// Sort every 64-entry chunk by (run, key) with a bitonic network over the
+// lanes (one wave per chunk; keys are distinct within a row, and runs keep
+// their places) and store each run's head (its smallest key) into its
+// descriptor.  The sorted chunk goes to col/key, in place when they are
+// col_in/key_in (each lane reads and writes only its own position, after
+// the whole wave has read).  The chunk's runs are cfirst[c] .. cfirst[c + 1] - 1 (the
 // last chunk ends at *nruns); their starts are ORed across the lanes.  With
 // PACKED (edge ids of at most 26 bits) the sort key is one 64-bit word: run
 // index inside the chunk, weight key, edge id.
 template <bool PACKED>
-__global__ __launch_bounds__(256) void k_sort_chunks(uint32_t *__restrict__ col,
-                                                     uint64_t *__restrict__ key, uint32_t nnz,
+__global__ __launch_bounds__(256) void k_sort_chunks(const uint32_t *col_in,
+                                                     const uint64_t *key_in, uint32_t *col,
+                                                     uint64_t *key, uint32_t nnz,
                                                      const uint32_t *__restrict__ cfirst,
                                                      const uint32_t *__restrict__ nruns,
                                                      const uint32_t *__restrict__ run_cur, int eb,
@@ -253,8 +256,8 @@ __global__ __launch_bounds__(256) void k_sort_chunks(uint32_t *__restrict__ col,
     if (c >= nch) return;  // whole waves
     const uint32_t pos = c * 64u + lane;
     const bool valid = pos < nnz;
-    uint64_t k = valid ? key[pos] : KEY_INF;
-    uint32_t pl = valid ? col[pos] : 0u;
+    uint64_t k = valid ? key_in[pos] : KEY_INF;
+    uint32_t pl = valid ? col_in[pos] : 0u;
     // run starts of the chunk, from the run descriptors (OR over the lanes)
     const uint32_t r0 = cfirst[c];
     const uint32_t r1 = c + 1u < nch ? cfirst[c + 1u] : *nruns;
@@ -414,7 +417,8 @@ size_t heads_runs_cap(size_t nnz_cap, int32_t n)
     return (nnz_cap + 63) / 64 + (size_t)(n > 0 ? n : 0) + 1;
 }
 
-msf_status build_runs(Ctx *c, const Runs &R, const uint32_t *row_ptr, int32_t n, uint32_t *col,
+msf_status build_runs(Ctx *c, const Runs &R, const uint32_t *row_ptr, int32_t n,
+                      const uint32_t *col_in, const uint64_t *key_in, uint32_t *col,
                       uint64_t *key, uint32_t nnz, int eb)
 {
     hipStream_t s = c->stream;
@@ -431,11 +435,11 @@ msf_status build_runs(Ctx *c, const Runs &R, const uint32_t *row_ptr, int32_t n,
     const uint32_t *total = R.roff + n;  // the scan's total: the number of runs
     MSF_HIP(hipEventRecord(c->kev[2], s));
     if (eb <= 26)
-        k_sort_chunks<true><<<gs, 256, 0, s>>>(col, key, nnz, R.cfirst, total, R.cur, eb, R.hcol,
-                                               R.hkey);
+        k_sort_chunks<true><<<gs, 256, 0, s>>>(col_in, key_in, col, key, nnz, R.cfirst, total,
+                                               R.cur, eb, R.hcol, R.hkey);
     else
-        k_sort_chunks<false><<<gs, 256, 0, s>>>(col, key, nnz, R.cfirst, total, R.cur, eb,
-                                                R.hcol, R.hkey);
+        k_sort_chunks<false><<<gs, 256, 0, s>>>(col_in, key_in, col, key, nnz, R.cfirst, total,
+                                                R.cur, eb, R.hcol, R.hkey);
     MSF_HIP(hipEventRecord(c->kev[3], s));
     c->pass_done |= 2u;
     MSF_HIP(hipGetLastError());

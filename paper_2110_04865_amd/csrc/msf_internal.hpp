@@ -214,6 +214,12 @@ struct SolveState {
     bool first_done = false;  // the build wrote round 1's minima into r
     bool heads = false;       // rounds use the head sweep over key-sorted runs
     bool graph = false;       // rounds driven on the device, GRAPH_K at a time
+    // rounds on a kept graph's adjacency (connected components): no build,
+    // and the final parent vector goes to labels (through perm, if set)
+    // instead of the forest output
+    bool kept = false;
+    uint32_t *labels = nullptr;
+    const uint32_t *perm = nullptr;
     Runs runs;
     uint32_t nruns = 0;
     int ri = 0, ai = 0, rounds = 0;
@@ -404,12 +410,13 @@ constexpr unsigned CHASE_MAX_BLOCKS = 2048;
 
 // Head sweep (kernels_heads.hip).  heads_runs_cap: runs of an adjacency of
 // at most nnz_cap entries over n rows.  build_runs derives the runs of a
-// one-slice adjacency from row_ptr, sorts every chunk of col/key in place
-// and fills the run arrays (keys' edge ids take eb bits); the run count
-// lands in dcnt->nruns.  launch_heads runs one sweep (queue counter
-// dcnt->qn[parity], clearing the other one).
+// one-slice adjacency from row_ptr, sorts every chunk of col_in/key_in into
+// col/key (the same arrays: in place) and fills the run arrays (keys' edge
+// ids take eb bits); the run count lands in dcnt->nruns.  launch_heads runs
+// one sweep (queue counter dcnt->qn[parity], clearing the other one).
 size_t heads_runs_cap(size_t nnz_cap, int32_t n);
-msf_status build_runs(Ctx *c, const Runs &R, const uint32_t *row_ptr, int32_t n, uint32_t *col,
+msf_status build_runs(Ctx *c, const Runs &R, const uint32_t *row_ptr, int32_t n,
+                      const uint32_t *col_in, const uint64_t *key_in, uint32_t *col,
                       uint64_t *key, uint32_t nnz, int eb);
 void launch_heads(hipStream_t s, const Runs &R, uint32_t nruns, const uint32_t *col,
                   const uint64_t *key, const uint32_t *p, uint64_t *r, Counters *dcnt, int parity);
@@ -489,6 +496,14 @@ msf_status decode_err(uint32_t err);
 // many contexts (each with its own stream) in flight at once.
 msf_status solve_start(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
                        msf_wtype wt, int32_t *d_ids);
+// The same rounds on a kept graph's adjacency a (connected components,
+// section 2.4), with the head sweep over a copy of a's entries sorted into
+// the workspace (a itself is only read); at the end the parent vector,
+// every vertex at its tree's root, goes to labels (device uint32[n], through
+// perm when the graph has one).  kept_heads_eligible: whether a qualifies
+// for the head sweep (the same rule as msf_solve).
+bool kept_heads_eligible(const Ctx *c, const Adj &a);
+msf_status solve_start_kept(Ctx *c, const Adj &a, const uint32_t *perm, uint32_t *labels);
 bool solve_ready(Ctx *c);
 msf_status solve_advance(Ctx *c);
 bool solve_done(const Ctx *c);

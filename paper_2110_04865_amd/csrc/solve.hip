@@ -170,6 +170,68 @@ msf_status solve_start(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, con
     return end_step(c, 1);
 }
 
+// Round state: p = identity, h = identity, r = empty (unless the build
+// wrote round 1's minima), forest flags cleared, R = the rows with entries.
+static msf_status enqueue_round_state(Ctx *c)
+{
+    SolveState &S = c->ss;
+    hipStream_t s = c->stream;
+    MSF_HIP(hipEventRecord(c->ev[1], s));
+    launch_iota_u32(s, S.b.p, (size_t)S.n);
+    launch_iota_u32(s, S.b.h, (size_t)S.n);
+    if (!S.first_done) launch_fill_u64(s, S.b.r, KEY_INF, (size_t)S.n);
+    launch_fill_u32(s, reinterpret_cast<uint32_t *>(S.b.flags), 0u, ((size_t)S.m + 3) / 4);
+    launch_init_roots(s, S.a.row_ptr, S.n, S.a.sl.S, S.b.R[0], S.b.status, c->dcnt);
+    return MSF_OK;
+}
+
+// Bits of the edge ids in the keys of a graph with m edges.
+static int edge_bits(int64_t m)
+{
+    int eb = 1;
+    while (eb < 64 && ((uint64_t)(m > 1 ? m - 1 : 1) >> eb)) ++eb;
+    return eb;
+}
+
+bool kept_heads_eligible(const Ctx *c, const Adj &a)
+{
+    const int64_t nnz = (int64_t)a.nnz;
+    return a.sl.S == 1 && nnz > 0 && a.n > 0 &&
+           (c->heads == 2 ||
+            (c->heads == 1 && nnz >= HEADS_MIN_NNZ && nnz >= HEADS_MIN_DEG * (int64_t)a.n));
+}
+
+msf_status solve_start_kept(Ctx *c, const Adj &a, const uint32_t *perm, uint32_t *labels)
+{
+    SolveState &S = c->ss;
+    S = SolveState{};
+    c->ml_pending = false;
+    if (a.sl.S != 1) {
+        set_error("internal error: the head sweep needs one column slice");
+        return MSF_EINVAL;
+    }
+    S.n = a.n;
+    S.m = a.m;
+    S.edges = a.edges;
+    S.wt = MSF_W_U32;  // the weight sum of the hooks is not read
+    S.kept = true;
+    S.labels = labels;
+    S.perm = perm;
+    MSF_TRY(get_solve_bufs(c, S.n, S.m, 1, &S.b));
+    MSF_TRY(get_runs_bufs(c, S.n, S.m, &S.runs));
+    S.heads = true;
+    S.a = a;
+    S.a.col = S.b.col[0];
+    S.a.key = S.b.key[0];
+    MSF_HIP(hipEventRecord(c->ev[0], c->stream));
+    zero_counters(c);
+    c->pass_done = 0;
+    MSF_TRY(build_runs(c, S.runs, a.row_ptr, S.n, a.col, a.key, S.a.col, S.a.key, a.nnz,
+                       edge_bits(S.m)));
+    MSF_TRY(enqueue_round_state(c));
+    return end_step(c, 2);
+}
+
 bool solve_ready(Ctx *c) { return hipEventQuery(c->ev[3]) == hipSuccess; }
 
 bool solve_done(const Ctx *c) { return c->ss.phase == 5; }
@@ -236,7 +298,13 @@ static msf_status enqueue_output(Ctx *c)
 {
     SolveState &S = c->ss;
     S.st.rounds = S.rounds;
-    MSF_TRY(launch_output(c, S.b.flags, S.m, S.w, S.wt, S.ids, S.b.part));
+    if (!S.kept)
+        MSF_TRY(launch_output(c, S.b.flags, S.m, S.w, S.wt, S.ids, S.b.part));
+    else if (S.perm)
+        launch_relabel_labels(c->stream, S.b.p, S.perm, S.n, S.labels);
+    else
+        MSF_HIP(hipMemcpyAsync(S.labels, S.b.p, 4 * (size_t)S.n, hipMemcpyDeviceToDevice,
+                               c->stream));
     MSF_HIP(hipEventRecord(c->ev[2], c->stream));
     return end_step(c, 4);
 }
@@ -326,19 +394,12 @@ msf_status solve_advance(Ctx *c)
         for (int q = 0; q <= S.a.sl.S; ++q) S.a.sl.sstart[q] = h->sstart[q];
         set_chunks(&S.a);
         S.a.segs = h->segs;
-        if (S.heads) {
-            int eb = 1;
-            while (eb < 64 && ((uint64_t)(S.m > 1 ? S.m - 1 : 1) >> eb)) ++eb;
-            MSF_TRY(build_runs(c, S.runs, S.a.row_ptr, S.n, S.a.col, S.a.key, S.a.nnz, eb));
-        }
+        if (S.heads)
+            MSF_TRY(build_runs(c, S.runs, S.a.row_ptr, S.n, S.a.col, S.a.key, S.a.col, S.a.key,
+                               S.a.nnz, edge_bits(S.m)));
         // the chunk-row table serves the full sweep only
         if (S.a.nnz && !S.heads) launch_chunk_rows_sliced(s, S.a);
-        MSF_HIP(hipEventRecord(c->ev[1], s));
-        launch_iota_u32(s, S.b.p, (size_t)S.n);
-        launch_iota_u32(s, S.b.h, (size_t)S.n);
-        if (!S.first_done) launch_fill_u64(s, S.b.r, KEY_INF, (size_t)S.n);
-        launch_fill_u32(s, reinterpret_cast<uint32_t *>(S.b.flags), 0u, ((size_t)S.m + 3) / 4);
-        launch_init_roots(s, S.a.row_ptr, S.n, S.a.sl.S, S.b.R[0], S.b.status, c->dcnt);
+        MSF_TRY(enqueue_round_state(c));
         MSF_TRY(end_step(c, 2));
         // capture the device-driven rounds while the GPU runs the set-up
         if (S.graph && c->graph_rounds == 2) MSF_TRY(graph_rounds_exec(c));
@@ -366,6 +427,9 @@ msf_status solve_advance(Ctx *c)
             if (h->ghist[k]) ++S.st.hook_rounds;
         }
         S.st.path = c->graph_rounds == 2 ? 3 : 2;
+        // the flag stays set only while device-driven rounds run (other
+        // calls on this context launch the sweep, which tests it)
+        launch_fill_u32(s, &c->dcnt->gdone, 0u, 1);
         return enqueue_output(c);
     }
     case 3: {  // round counters ready

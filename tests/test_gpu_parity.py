@@ -418,6 +418,182 @@ def test_multilinear_matches_definition(ctx, pkg):
         multilinear_case(ctx, pkg, n, e, w, wt, sorted_blocks, label + " blocks")
 
 
+def stored_row_cuts(n, e, order, parts):
+    """Cut positions of `parts` contiguous stored-row ranges balanced by
+    stored entries (both directions of every non-loop edge)."""
+    e = np.asarray(e, np.int64)
+    keep = e[:, 0] != e[:, 1]
+    deg = np.bincount(e[keep].reshape(-1), minlength=n)
+    pre = np.concatenate([[0], np.cumsum(deg[order])])
+    tot = int(pre[-1])
+    cuts = [0] + [int(np.searchsorted(pre, tot * k // parts, side="left")) for k in range(1, parts)]
+    return sorted(set(cuts + [n]))
+
+
+def test_multilinear_rows_shares(ctx, pkg):
+    """One owner's share of the multilinear kernel (rows of A split among
+    owners that all hold p, section 5): each share equals the oracle's
+    kernel over those rows, and the shares combine by minimum into the
+    whole kernel.  Ranges balanced by entries, plus empty, one-row and
+    whole ranges; both stored orders."""
+    rng = np.random.default_rng(91)
+    graphs = [("rmat14", *gen.rmat(14, 16, seed=92), F32),
+              ("grid18", *gen.grid(18, 18, 18, 0.05, seed=93), U32),
+              ("er ragged", 3001, *gen.er(3001, 7777, seed=94), U32)]
+    for order_env in ("1", "0"):
+        with env_set(MSF_GRAPH_ORDER=order_env):
+            c = pkg.Context(0)
+        for label, n, e, w, wt in graphs:
+            g = pkg.Graph(c, n, e, w, wtype=wt)
+            od = torch.empty(n, dtype=torch.int32, device="cuda:0")
+            c.graph_order(g, od)
+            order = od.cpu().numpy().astype(np.int64)
+            assert np.array_equal(np.sort(order), np.arange(n)), label
+            if order_env == "0":
+                assert np.array_equal(order, np.arange(n)), label
+            roots = rng.choice(n, size=max(1, n // 40), replace=False).astype(np.uint32)
+            star = roots[rng.integers(0, len(roots), n)]
+            star[roots] = roots
+            whole = oracle.multilinear(n, e, w, wt, star)
+            cuts = stored_row_cuts(n, e, order, 8)
+            ranges = list(zip(cuts, cuts[1:])) + [(0, 0), (n // 2, n // 2 + 1), (0, n)]
+            dr = torch.empty(n, dtype=torch.int64, device="cuda:0")
+            comb = np.full(n, np.iinfo(np.uint64).max, np.uint64)
+            for lo, hi in ranges:
+                say("multilinear rows", label, f"order={order_env} rows [{lo}, {hi})")
+                dr.fill_(0)
+                c.multilinear_rows(g, dev(star), dr, lo, hi)
+                torch.cuda.synchronize()
+                got = dr.cpu().numpy().view(np.uint64)
+                want = oracle.multilinear(n, e, w, wt, star, rows=order[lo:hi])
+                assert np.array_equal(got, want), (label, lo, hi)
+                if (lo, hi) in list(zip(cuts, cuts[1:])):
+                    comb = np.minimum(comb, got)
+            assert np.array_equal(comb, whole), label
+            for lo, hi in ((1, 0), (-1, 3), (0, n + 1)):
+                with pytest.raises(pkg.MSFError):
+                    c.multilinear_rows(g, dev(star), dr, lo, hi)
+            g.close()
+        c.close()
+
+
+def test_kernels_after_device_driven_rounds(pkg):
+    """A solve whose rounds ran on the device (and components on such a
+    path) leave nothing behind that the next call on the context sees: the
+    multilinear kernel, both forms, on a graph made before them."""
+    with env_set(MSF_SMALL_M="0", MSF_HEADS="0"):
+        c = pkg.Context(0)
+    n = 4096
+    e, w = gen.er(n, 32768, seed=97)
+    g = pkg.Graph(c, n, e, w, wtype=U32)
+    rng = np.random.default_rng(98)
+    roots = rng.choice(n, size=60, replace=False).astype(np.uint32)
+    star = roots[rng.integers(0, len(roots), n)]
+    star[roots] = roots
+    want = oracle.multilinear(n, e, w, U32, star)
+    dr = torch.empty(n, dtype=torch.int64, device="cuda:0")
+    lab = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    for step in ("solve", "components"):
+        if step == "solve":
+            st = check_solve(c, pkg, n, e, w, U32, "device-driven rounds")
+            assert st["path"] == 3, st["path"]
+        else:
+            c.components(g, lab)
+        for form in (c.multilinear, c.multilinear_pairwise):
+            dr.fill_(0)
+            form(g, dev(star), dr)
+            torch.cuda.synchronize()
+            assert np.array_equal(dr.cpu().numpy().view(np.uint64), want), (step, form)
+    g.close()
+    c.close()
+
+
+def test_context_close_releases_its_graphs(pkg):
+    """Closing a context first releases the graphs made on it, so a graph
+    object that outlives its context is inert (msf_graph_destroy needs the
+    context's stream)."""
+    c = pkg.Context(0)
+    e, w = gen.er(500, 2000, seed=96)
+    g = pkg.Graph(c, 500, e, w, wtype=U32)
+    c.close()
+    assert g._h is None
+    g.close()
+    del g
+    c2 = pkg.Context(0)
+    g2 = pkg.Graph(c2, 500, e, w, wtype=U32)
+    lab = torch.empty(500, dtype=torch.int32, device="cuda:0")
+    c2.components(g2, lab)
+    g2.close()
+    c2.close()
+
+
+def kernel_at(n, e, w, wt, p, sample, rows=None):
+    """The oracle's kernel at the roots in `sample` only: over the edges with
+    an end in one of their trees (the only edges that can reach them), with
+    each key's edge id mapped back from the sub-list to the whole list."""
+    INF = np.iinfo(np.uint64).max
+    in_s = np.isin(p, sample)
+    sel = in_s[e[:, 0]] | in_s[e[:, 1]]
+    ids = np.nonzero(sel)[0]
+    if len(ids) == 0:
+        return np.full(len(sample), INF, np.uint64)
+    want = oracle.multilinear(n, e[sel], w[sel], wt, p, rows=rows)[sample]
+    low = (want & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    mapped = ids[np.minimum(low, len(ids) - 1)].astype(np.uint64)
+    return np.where(want == INF, want, (want & ~np.uint64(0xFFFFFFFF)) | mapped)
+
+
+def test_multilinear_rows_full_size(ctx, pkg):
+    """R-MAT s22 cut into 8 entry-balanced stored-row ranges, p = the
+    parents after round 1 of the solve (its hooks and tie break, shortcut):
+    the shares combine by minimum into the whole kernel's r, no share is
+    below it, and sampled roots match the oracle's kernel over their rows."""
+    n, e, w, wt, _ = full_case("rmat s22")
+    say("multilinear rows", "rmat s22", f"n={n} m={len(e)}")
+    g = pkg.Graph(ctx, n, dev(e), dev(w), wtype=wt)
+    od = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    ctx.graph_order(g, od)
+    order = od.cpu().numpy().astype(np.int64)
+    # round-1 parents from the oracle's first round: each vertex's minimum
+    # edge hooks it (identity p), the smaller of a mutual pair stays root,
+    # then the roots of that forest
+    r1 = oracle.multilinear(n, e, w, wt, np.arange(n, dtype=np.uint32))
+    h = np.arange(n, dtype=np.int64)
+    has = r1 != np.iinfo(np.uint64).max
+    eid = (r1[has] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    v = np.nonzero(has)[0]
+    a, b = e[eid, 0].astype(np.int64), e[eid, 1].astype(np.int64)
+    h[v] = np.where(a == v, b, a)
+    mutual = has & (h[h] == np.arange(n)) & (np.arange(n) < h)
+    h[mutual] = np.nonzero(mutual)[0]
+    p = oracle.find_roots(h.astype(np.uint32))
+    dp = dev(p)
+    dr = torch.empty(n, dtype=torch.int64, device="cuda:0")
+    ctx.multilinear(g, dp, dr)
+    torch.cuda.synchronize()
+    whole = dr.cpu().numpy().view(np.uint64).copy()
+    comb = np.full(n, np.iinfo(np.uint64).max, np.uint64)
+    cuts = stored_row_cuts(n, e, order, 8)
+    rng = np.random.default_rng(95)
+    # roots of trees with edges (isolated vertices are roots of their own)
+    cand = np.unique(p[np.bincount(e.reshape(-1), minlength=n) > 0])
+    for lo, hi in zip(cuts, cuts[1:]):
+        ctx.multilinear_rows(g, dp, dr, lo, hi)
+        torch.cuda.synchronize()
+        got = dr.cpu().numpy().view(np.uint64).copy()
+        assert np.all(got >= whole), (lo, hi)
+        comb = np.minimum(comb, got)
+        rows = np.zeros(n, bool)
+        rows[order[lo:hi]] = True
+        sample = rng.choice(cand, size=20, replace=False)
+        assert np.array_equal(got[sample], kernel_at(n, e, w, wt, p, sample, rows)), (lo, hi)
+    assert np.array_equal(comb, whole)
+    # the whole kernel itself, at sampled roots
+    sample = rng.choice(cand, size=50, replace=False)
+    assert np.array_equal(whole[sample], kernel_at(n, e, w, wt, p, sample))
+    g.close()
+
+
 def test_graph_vertex_order_is_invisible(pkg):
     """Kept graphs store their vertices by decreasing degree class
     (MSF_GRAPH_ORDER=1, the default) or in the caller's order (0): the
@@ -589,7 +765,10 @@ def test_small_graphs_take_one_workgroup(ctx, pkg):
         c = pkg.Context(0)
     for label, n, e, w, wt in cases:
         st = check_solve(c, pkg, n, e, w, wt, "wide " + label)
-        assert st["path"] == 0, label
+        # the device-driven rounds, replayed from a captured graph
+        assert st["path"] == 3, (label, st["path"])
+        hooks = [h for h in oracle.as_rounds(n, e, w, wt)["hooks"] if h]
+        assert st["hooks"][:len(hooks)] == hooks, (label, st["hooks"], hooks)
     c.close()
 
 
@@ -627,23 +806,57 @@ def test_components_match_oracle(ctx, pkg):
         "loops and parallel edges": (5, np.array([[0, 0], [1, 2], [2, 1], [3, 3], [1, 2]],
                                                  np.int32), np.array([1, 1, 1, 1, 1], np.uint32)),
     }
-    for label, (n, e, w) in cases.items():
-        say("components", label, f"n={n} m={len(e)}")
-        g = pkg.Graph(ctx, n, e, w, wtype=U32)
-        lab = torch.empty(max(n, 1), dtype=torch.int32, device="cuda:0")
-        rounds = ctx.components(g, lab)
+    # the default choice, the head-sweep rounds over a sorted copy for every
+    # graph (MSF_HEADS=2) and the device-driven rounds for every graph
+    # (MSF_HEADS=0); kept graphs in degree order and in the caller's order
+    for heads, order in (("1", "1"), ("2", "1"), ("0", "1"), ("2", "0")):
+        with env_set(MSF_HEADS=heads, MSF_GRAPH_ORDER=order):
+            c = pkg.Context(0)
+        try:
+            for label, (n, e, w) in cases.items():
+                check_components(c, pkg, n, e, w, f"heads={heads} order={order} {label}")
+        finally:
+            c.close()
+
+
+def check_components(c, pkg, n, e, w, label):
+    say("components", label, f"n={n} m={len(e)}")
+    g = pkg.Graph(c, n, e, w, wtype=U32)
+    lab = torch.empty(max(n, 1), dtype=torch.int32, device="cuda:0")
+    rounds = c.components(g, lab)
+    torch.cuda.synchronize()
+    got = lab.cpu().numpy()[:n].view(np.uint32).astype(np.int64)
+    want, ncomp = oracle.components(n, e)
+    want = want.astype(np.int64)
+    # the same partition: labels are roots of their own component, and
+    # the oracle's label (the component's smallest vertex) maps one-to-one
+    # onto the GPU's labels
+    assert (got < n).all() and np.array_equal(got[got], got), label
+    assert np.array_equal(got, got[want]), label
+    assert len(np.unique(got)) == ncomp, label
+    assert rounds <= max(1, math.ceil(math.log2(max(n, 2)))) + 1, (label, rounds)
+    # the graph is only read: the kernel on it still gives the oracle's r
+    if 0 < n <= 100000 and len(e):
+        dr = torch.empty(n, dtype=torch.int64, device="cuda:0")
+        c.multilinear(g, dev(np.arange(n, dtype=np.uint32)), dr)
         torch.cuda.synchronize()
-        g.close()
-        got = lab.cpu().numpy()[:n].view(np.uint32).astype(np.int64)
-        want, ncomp = oracle.components(n, e)
-        want = want.astype(np.int64)
-        # the same partition: labels are roots of their own component, and
-        # the oracle's label (the component's smallest vertex) maps one-to-one
-        # onto the GPU's labels
-        assert (got < n).all() and np.array_equal(got[got], got), label
-        assert np.array_equal(got, got[want]), label
-        assert len(np.unique(got)) == ncomp, label
-        assert rounds <= max(1, math.ceil(math.log2(max(n, 2)))) + 1, (label, rounds)
+        assert np.array_equal(dr.cpu().numpy().view(np.uint64),
+                              oracle.multilinear(n, e, w, U32, np.arange(n))), label
+    g.close()
+    return rounds
+
+
+@pytest.mark.parametrize("label", ["rmat s22", "grid 256"])
+def test_components_full_size(ctx, pkg, label):
+    """msf_components on the full workloads (head-sweep rounds on R-MAT s22,
+    device-driven rounds on the grid) against the oracle's components."""
+    n, e, w, wt, _ = full_case(label)
+    if wt == F32:
+        w = w.view(np.uint32)  # any weights: components do not depend on them
+    rounds = check_components(ctx, pkg, n, e, w, label)
+    st = ctx.stats()
+    if label == "rmat s22":
+        assert st["head_sweeps"] == st["rounds"] and rounds == st["hook_rounds"], st
 
 
 def test_starcheck_rounds_give_the_msf(ctx, pkg):

@@ -393,6 +393,49 @@ def test_multilinear_matches_dense_formulation(seed):
     assert [int(x) for x in got] == want
 
 
+@pytest.mark.parametrize("seed", range(15))
+def test_multilinear_rows_matches_dense_row_block(seed):
+    """One owner's share (section 5): the dense two-step formulation over the
+    block of rows A[rows, :] only (q_i = empty outside it), and the shares of
+    a partition of the rows combine by minimum into the whole kernel."""
+    rng = random.Random(100 + seed)
+    n = rng.randint(1, 25)
+    m = rng.randint(0, 60)
+    edges, w = random_multigraph(rng, n, m, rng.choice([3, 10**9]))
+    w = np.array(w, dtype=np.uint32)
+    roots = [rng.randrange(n) for _ in range(max(1, n // 3))]
+    p = [rng.choice(roots) for _ in range(n)]
+    for r_ in roots:
+        p[r_] = r_
+    if seed % 2:
+        p = [rng.randrange(n) for _ in range(n)]
+    keys = oracle.edge_keys(w, U32)
+    INF = (1 << 64) - 1
+    # contiguous row ranges, as an owner of a row block holds them
+    cuts = sorted({0, n, *[rng.randint(0, n) for _ in range(3)]})
+    combined = [INF] * n
+    for lo, hi in zip(cuts, cuts[1:]):
+        rows = list(range(lo, hi))
+        got = [int(x) for x in oracle.multilinear(n, edges, w, U32, p, rows=rows)]
+        masked = np.zeros(n, bool)
+        masked[lo:hi] = True
+        assert got == [int(x) for x in oracle.multilinear(n, edges, w, U32, p, rows=masked)]
+        A = [[INF] * n for _ in range(n)]
+        for e, (a, b) in enumerate(edges.tolist()):
+            if a != b:
+                A[a][b] = min(A[a][b], int(keys[e]))
+                A[b][a] = min(A[b][a], int(keys[e]))
+        q = [min([A[i][j] if p[i] != p[j] else INF for j in range(n)] + [INF])
+             if lo <= i < hi else INF for i in range(n)]
+        want = [INF] * n
+        for i in range(n):
+            want[p[i]] = min(want[p[i]], q[i])
+        assert got == want
+        combined = [min(a, b) for a, b in zip(combined, got)]
+    assert combined == [int(x) for x in oracle.multilinear(n, edges, w, U32, p)]
+    assert all(int(x) == INF for x in oracle.multilinear(n, edges, w, U32, p, rows=[]))
+
+
 # -------------------------------------------------------------- roots --
 
 def test_find_roots_matches_pointer_doubling():
