@@ -403,6 +403,7 @@ msf_status msf_graph_create(msf_ctx *ctx, int32_t n, int64_t m, const int32_t *e
     rc = build_adjacency(c, n, m, (const int32_t *)g->bufs[0], g->bufs[1], wt, slices, &g->a,
                          (uint32_t *)g->bufs[2], (uint32_t *)g->bufs[3], (uint64_t *)g->bufs[4],
                          (uint32_t *)g->bufs[5]);
+    if (rc == MSF_OK && g->a.sl.S == 1) launch_long_entries(c->stream, g->a.row_ptr, n, c->dcnt);
     if (rc == MSF_OK) rc = read_counters(c);
     if (rc == MSF_OK) rc = decode_err(c->hcnt->err);
     if (rc) {
@@ -412,6 +413,8 @@ msf_status msf_graph_create(msf_ctx *ctx, int32_t n, int64_t m, const int32_t *e
     for (int q = 0; q <= g->a.sl.S; ++q) g->a.sl.sstart[q] = c->hcnt->sstart[q];
     set_chunks(&g->a);
     g->a.segs = c->hcnt->segs;
+    g->long_rows = g->a.sl.S == 1 && g->a.nnz > 0 &&
+                   4 * c->hcnt->long_entries >= (uint64_t)g->a.nnz;
     if (g->a.nnz) launch_chunk_rows_sliced(c->stream, g->a);
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -467,7 +470,7 @@ msf_status msf_multilinear(msf_ctx *ctx, const msf_graph *g, const uint32_t *p, 
         pg = (const uint32_t *)vq;
     }
     MSF_HIP(hipEventRecord(c->sev[0], c->stream));
-    launch_sweep(c->stream, g->a, pg, r, c->dcnt);
+    launch_sweep(c->stream, g->a, pg, r, c->dcnt, false, nullptr, true, g->long_rows);
     MSF_HIP(hipEventRecord(c->sev[1], c->stream));
     MSF_HIP(hipGetLastError());
     c->stats = msf_stats{};
@@ -537,7 +540,7 @@ msf_status msf_multilinear_rows(msf_ctx *ctx, const msf_graph *g, const uint32_t
         pg = (const uint32_t *)vq;
     }
     MSF_HIP(hipEventRecord(c->sev[0], s));
-    launch_sweep(s, a, pg, r, c->dcnt);
+    launch_sweep(s, a, pg, r, c->dcnt, false, nullptr, true, g->long_rows);
     MSF_HIP(hipEventRecord(c->sev[1], s));
     MSF_HIP(hipGetLastError());
     c->stats = msf_stats{};

@@ -295,6 +295,30 @@ void launch_slice_info(hipStream_t s, const Adj &a, Counters *dcnt)
     k_slice_info<<<(unsigned)g, 256, 0, s>>>(a.row_ptr, a.n, a.sl.S, dcnt);
 }
 
+// Stored entries in rows of at least min_len entries (one-slice row_ptr),
+// added into cnt->long_entries.
+__global__ __launch_bounds__(256) void k_long_entries(const uint32_t *__restrict__ row_ptr,
+                                                      int32_t n, uint32_t min_len, Counters *cnt)
+{
+    unsigned long long sum = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t len = row_ptr[i + 1] - row_ptr[i];
+        if (len >= min_len) sum += len;
+    }
+    for (int d = 32; d >= 1; d >>= 1) sum += __shfl_xor(sum, d, 64);
+    if (__lane_id() == 0 && sum)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&cnt->long_entries), sum);
+}
+
+void launch_long_entries(hipStream_t s, const uint32_t *row_ptr, int32_t n, Counters *dcnt)
+{
+    launch_fill_u32(s, reinterpret_cast<uint32_t *>(&dcnt->long_entries), 0u, 2);
+    if (n <= 0) return;
+    const unsigned g = (unsigned)std::min<int64_t>(std::max<int64_t>(((int64_t)n + 255) / 256, 1), 2048);
+    k_long_entries<<<g, 256, 0, s>>>(row_ptr, n, WAVE_ROW, dcnt);
+}
+
 // ------------------------------------------------- bucketed build ------
 // The same adjacency built without any global atomic: rows are grouped in
 // buckets of 2^LB consecutive ids (at most BK_MAX_NB buckets).

@@ -77,6 +77,22 @@ __device__ __forceinline__ void scan_step(RunAgg &agg, bool recv)
 #ifndef SWEEP_MASKED_WINDOW
 #define SWEEP_MASKED_WINDOW 1
 #endif
+// Lazy sweep with the read filter on (few live roots): read r of each
+// lane's roots before gathering, and gather only for entries whose key is
+// below it (1).  r only decreases during a sweep, so an entry with a key at
+// or above a value read earlier cannot lower it.  With many live roots the
+// values read are still mostly empty and the reads would not pay.
+#ifndef SWEEP_PRUNE
+#define SWEEP_PRUNE 1
+#endif
+// Bits of k_sweep's filter argument: read r before an atomic and skip
+// the ones that cannot lower it (FILTER_READ; with SWEEP_PRUNE also before
+// the gathers), and, where r was read before the gathers, go straight to the
+// atomic instead of reading r again (FILTER_KNOWN: pays on graphs where
+// long rows put many waves on one root, whose slot they would all read
+// twice; with many small roots the second read skips more atomics than it
+// costs).
+constexpr int FILTER_READ = 1, FILTER_KNOWN = 2;
 
 // Rows of a chunk staged in LDS (two per lane); a chunk that spans more
 // rows (long runs of rows without entries in its slice) searches row_ptr in
@@ -319,6 +335,11 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
         }
     }
     uint32_t dead_found = 0;  // lazy: gathered entries found internal
+    // r of each entry's root read before the gathers (pruned lazy sweep)
+    uint64_t rv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) rv[e] = KEY_INF;
+    const bool pruned = LAZY && SWEEP_PRUNE && (read_filter & FILTER_READ);
     if (LAZY) {
         // Lazy gathers: only the smallest entry of the lane for each root
         // can be the lane's contribution to that root, so its column parent
@@ -327,17 +348,36 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
         // larger keys than a live one of the same root, so the minima are
         // exact.  Loads are unconditional: lanes with nothing to gather read
         // p[lo], a line the whole wave shares.
-        // am: among the SWEEP_LAZY smallest entries of its root in this lane
+        // ok: the entry can still lower r of its root (with SWEEP_PRUNE, its
+        // key is below the value of r read now: one read per run of equal
+        // roots in the lane; the reads of a wave's shared root coalesce)
+        bool ok[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) ok[e] = e >= kb && e < ke;
+        if (pruned) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const bool fresh = ok[e] && (e == kb || root[e] != root[e > 0 ? e - 1 : 0]);
+                rv[e] = fresh ? load_relaxed_u64(r + root[e]) : KEY_INF;
+            }
+#pragma unroll
+            for (int e = 1; e < E; ++e)
+                if (ok[e] && e > kb && root[e] == root[e - 1]) rv[e] = rv[e - 1];
+#pragma unroll
+            for (int e = 0; e < E; ++e) ok[e] = ok[e] && ky[e] < rv[e];
+        }
+        // am: among the SWEEP_LAZY smallest such entries of its root in
+        // this lane
         bool am[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             int below = 0;
 #pragma unroll
             for (int f = 0; f < E; ++f)
-                if (f != e && f >= kb && f < ke && root[f] == root[e] &&
+                if (f != e && ok[f] && root[f] == root[e] &&
                     (ky[f] < ky[e] || (ky[f] == ky[e] && f < e)))
                     ++below;
-            am[e] = e >= kb && e < ke && below < SWEEP_LAZY;
+            am[e] = ok[e] && below < SWEEP_LAZY;
         }
         uint32_t pa[E];
 #pragma unroll
@@ -359,7 +399,7 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
 #pragma unroll
             for (int f = 0; f < E; ++f)
                 if (live[f] && root[f] == root[e]) has_live = true;
-            need[e] = !has_live && !am[e] && e >= kb && e < ke;
+            need[e] = !has_live && !am[e] && ok[e];
             any |= need[e];
         }
         if (__ballot(any)) {
@@ -392,11 +432,14 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
     // other writer; everything else goes through the atomic
     const uint32_t wave_lo = base - lane * E;
     const uint32_t wave_hi = wave_lo + 64 * E;  // exclusive
-    auto flush = [&](uint32_t rt, uint64_t v) {
+    auto flush = [&](uint32_t rt, uint64_t v, uint64_t known) {
         if (v == KEY_INF) return;
         if (FIRST && S == 1 && win && s_rp[rt - lo] >= wave_lo && s_rp[rt + 1 - lo] <= wave_hi)
             r[rt] = v;
-        else if (read_filter)
+        else if (pruned && (read_filter & FILTER_KNOWN)) {
+            if (v < known)
+                __hip_atomic_fetch_min(r + rt, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (read_filter & FILTER_READ)
             min_into(r, rt, v);
         else  // many live roots: few runs share one, so the read would not pay
             __hip_atomic_fetch_min(r + rt, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -404,22 +447,24 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
 
     // lane-local runs by root; interior runs are complete and flushed now
     uint32_t froot = NONE32, lroot = NONE32;
-    uint64_t fmin = KEY_INF, lmin = KEY_INF;
+    uint64_t fmin = KEY_INF, lmin = KEY_INF, frv = KEY_INF, lrv = KEY_INF;
     bool single = true, started = false;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         if (e < kb || e >= ke) continue;
         if (!started) {
             froot = lroot = root[e];
+            frv = lrv = rv[e];
             fmin = cand[e];
             started = true;
         } else if (root[e] == lroot) {
             if (single) fmin = fmin < cand[e] ? fmin : cand[e];
             else lmin = lmin < cand[e] ? lmin : cand[e];
         } else {
-            if (!single) flush(lroot, lmin);
+            if (!single) flush(lroot, lmin, lrv);
             single = false;
             lroot = root[e];
+            lrv = rv[e];
             lmin = cand[e];
         }
     }
@@ -446,10 +491,10 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(
         uint64_t ffull = fmin;
         if (lane > 0 && prev_last == froot) ffull = ffull < prev_lrm ? ffull : prev_lrm;
         if (single) {
-            if (next_first != froot) flush(froot, ffull);
+            if (next_first != froot) flush(froot, ffull, frv);
         } else {
-            flush(froot, ffull);
-            if (next_first != lroot) flush(lroot, lmin);
+            flush(froot, ffull, frv);
+            if (next_first != lroot) flush(lroot, lmin, lrv);
         }
     }
 
@@ -549,18 +594,19 @@ __global__ void k_reduce_live(const uint32_t *__restrict__ wave_live, size_t cou
 }
 
 void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r, Counters *dcnt,
-                  bool first, uint32_t *wave_live, bool read_filter)
+                  bool first, uint32_t *wave_live, bool read_filter, bool known_flush)
 {
+    const int filt = (read_filter ? FILTER_READ : 0) | (read_filter && known_flush ? FILTER_KNOWN : 0);
     if (a.nnz == 0) return;
     const unsigned grid = a.sl.maxch * (unsigned)a.sl.S;  // slice = workgroup % S
     if (first)
         k_sweep<false, true><<<grid, SWEEP_BLOCK, 0, s>>>(
             a.row_ptr, a.col, a.key, a.chunk_row, a.sl, a.n, p, r, nullptr, nullptr, nullptr,
-            nullptr, nullptr, dcnt, wave_live, read_filter ? 1 : 0);
+            nullptr, nullptr, dcnt, wave_live, filt);
     else
         k_sweep<false, false><<<grid, SWEEP_BLOCK, 0, s>>>(
             a.row_ptr, a.col, a.key, a.chunk_row, a.sl, a.n, p, r, nullptr, nullptr, nullptr,
-            nullptr, nullptr, dcnt, wave_live, read_filter ? 1 : 0);
+            nullptr, nullptr, dcnt, wave_live, filt);
     if (wave_live) {
         const size_t count = (size_t)a.nchunks * (SWEEP_BLOCK / 64);
         k_reduce_live<<<64, 256, 0, s>>>(wave_live, count, dcnt);

@@ -140,6 +140,7 @@ struct Counters {
     uint32_t grounds;
     uint32_t gpad;
     uint32_t ghist[64];
+    uint64_t long_entries;  // stored entries in rows of at least WAVE_ROW entries
 };
 
 // Key-sorted runs for the head sweep: every 64-entry chunk of the
@@ -336,6 +337,11 @@ uint32_t sweep_nchunks(uint32_t nnz);
 void launch_chunk_rows_sliced(hipStream_t s, const Adj &a);
 // Slice boundaries (rp_s[0], rp_{S-1}[n]) and non-empty segments into dcnt.
 void launch_slice_info(hipStream_t s, const Adj &a, Counters *dcnt);
+// Rows at least one wave of the sweep long (64 lanes of SWEEP_E entries).
+constexpr uint32_t WAVE_ROW = 64 * SWEEP_LANE_ENTRIES;
+// dcnt->long_entries = stored entries in rows of at least WAVE_ROW entries
+// (one-slice row_ptr of n rows).
+void launch_long_entries(hipStream_t s, const uint32_t *row_ptr, int32_t n, Counters *dcnt);
 // Exclusive scan of u32 in[0..N) -> out[0..N]; out[N] (and *total_out,
 // nullable, device) receive the total.
 msf_status scan_u32(Ctx *c, const uint32_t *in, uint32_t *out, int64_t N, uint32_t *total_out);
@@ -354,8 +360,11 @@ void launch_zero_lookback(hipStream_t s, uint64_t *status, uint32_t tiles, uint3
 // number of live entries (p_i != p_j).
 // read_filter: read r before each atomic and skip non-improving updates
 // (needed when many runs share a root); otherwise atomics go straight out.
+// known_flush (with read_filter): where r was read before the gathers, the
+// atomic follows without a second read (for graphs with many long rows).
 void launch_sweep(hipStream_t s, const Adj &a, const uint32_t *p, uint64_t *r, Counters *dcnt,
-                  bool first = false, uint32_t *wave_live = nullptr, bool read_filter = true);
+                  bool first = false, uint32_t *wave_live = nullptr, bool read_filter = true,
+                  bool known_flush = false);
 // The same minima by the pairwise formulation: k_pair_attach writes every
 // stored entry's column parent to pj (extent entries: the padded length of
 // a.col), then the sweep reads those instead of gathering.
@@ -523,6 +532,9 @@ struct msf_ctx {
 struct msf_graph {
     msf_ctx *ctx = nullptr;
     msf::Adj a;
+    // at least a quarter of the stored entries lie in rows of WAVE_ROW or
+    // more entries (the multilinear kernel then skips second reads of r)
+    bool long_rows = false;
     void *bufs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // vertex order of the stored adjacency: perm[internal] = caller id
     // (null: the caller's order)

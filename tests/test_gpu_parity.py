@@ -398,6 +398,17 @@ def multilinear_case(ctx, pkg, n, e, w, wt, p, label):
     g.close()
 
 
+def hub_graph(n, hubs, seed):
+    """A few hubs joined to every vertex, plus a sparse random graph: most
+    stored entries lie in rows longer than one wave of the sweep (the kernel
+    then reuses the value of r it read before gathering)."""
+    e2, _ = gen.er(n, 2 * n, seed=seed)
+    hub = np.stack([np.repeat(np.arange(hubs, dtype=np.int32), n - hubs),
+                    np.tile(np.arange(hubs, n, dtype=np.int32), hubs)], 1)
+    e = np.concatenate([hub, e2])
+    return e, gen.weights(len(e), gen.W_U32, seed=seed + 1)
+
+
 def test_multilinear_matches_definition(ctx, pkg):
     rng = np.random.default_rng(1)
     for label, (n, e, w, wt) in {
@@ -405,6 +416,7 @@ def test_multilinear_matches_definition(ctx, pkg):
         "rmat14": (*gen.rmat(14, 16, seed=2), F32),
         "grid20": (*gen.grid(20, 20, 20, 0.05, seed=3), U32),
         "ragged": (3001, *gen.er(3001, 7777, seed=8), U32),
+        "hubs": (5000, *hub_graph(5000, 6, seed=9), U32),
     }.items():
         ident = np.arange(n, dtype=np.uint32)
         multilinear_case(ctx, pkg, n, e, w, wt, ident, label + " identity")
