@@ -738,6 +738,12 @@ def main():
                     help="run only msf_multilinear on R-MAT s22 with the parents after round 1")
     ap.add_argument("--served-only", action="store_true",
                     help="run only the served leg (prints its JSON alone)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the R-MAT s22 solves and print the line without the "
+                         "multilinear, plain, CPU and other legs (for profiling)")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="run only the plain solves of the small Erdos-Renyi graph and the "
+                         "256^3 grid (prints their JSON alone)")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched leg (prints its JSON alone)")
     ap.add_argument("--served-requests", type=int, default=2000,
@@ -811,6 +817,19 @@ def main():
         print(json.dumps({"batched": bench_batched(ctx, pkg, torch, cpu=not args.no_cpu)}),
               flush=True)
         return
+    if args.plain_only:
+        import gen
+
+        n1, e1, w1 = gen.workload_er_4096()
+        plain = {"er4096": bench_plain(ctx, pkg, torch, "Erdos-Renyi n=4096 m=32768, uint32 "
+                                       "weights", n1, e1, w1, pkg.W_U32, steps=50,
+                                       cpu=not args.no_cpu)}
+        n3, e3, w3 = gen.workload_grid_256()
+        plain["grid256"] = bench_plain(ctx, pkg, torch, "3D grid 256^3, 5% of edges dropped, "
+                                       "uint32 weights", n3, e3, w3, pkg.W_U32, steps=5,
+                                       cpu=not args.no_cpu)
+        print(json.dumps({"plain": plain}), flush=True)
+        return
     if args.shortcut_only:
         print(json.dumps({"shortcut_study": bench_shortcut(ctx, pkg, torch)}), flush=True)
         return
@@ -869,6 +888,9 @@ def main():
                      "kernel_ms_per_step": {k: v[0] / steps for k, v in kt.items()}},
         "host": host_info(),
     }
+    if args.headline_only:
+        print(json.dumps(line), flush=True)
+        return
     log("multilinear kernel with the parents after round 1")
     line["multilinear"] = bench_multilinear_round1(ctx, pkg, torch, n, r["e"], r["w"], pkg.W_F32)
     log(f"multilinear: {line['multilinear']}")

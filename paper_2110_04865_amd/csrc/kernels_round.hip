@@ -103,12 +103,23 @@ void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S,
 // by key inside every 64-entry chunk), a root whose row lies in one chunk
 // takes its hook target from the row's first entry (its smallest key)
 // instead of gathering the edge's endpoints.
+// Items per thread of the hook (item k of a thread is entry
+// block * HK_TILE + k * 256 + thread of R: coalesced loads, issued in phases
+// so that the chains R -> r -> edge endpoints -> parents of different items
+// overlap).
+constexpr int HK_IT = 8;
+constexpr uint32_t HK_TILE = 256 * HK_IT;
+
 template <bool IDENTITY>
-__global__ void k_hook(const uint32_t *__restrict__ R, uint32_t nR, uint64_t *__restrict__ r,
-                       const uint32_t *__restrict__ p, const int32_t *__restrict__ edges,
-                       uint32_t *__restrict__ h, uint32_t *__restrict__ hedge,
-                       uint32_t *__restrict__ hwk, const uint32_t *__restrict__ row_ptr,
-                       const uint32_t *__restrict__ col, Counters *tb_cnt)
+__global__ __launch_bounds__(256) void k_hook(const uint32_t *__restrict__ R, uint32_t nR,
+                                              uint64_t *__restrict__ r,
+                                              const uint32_t *__restrict__ p,
+                                              const int32_t *__restrict__ edges,
+                                              uint32_t *__restrict__ h,
+                                              uint32_t *__restrict__ hedge,
+                                              uint32_t *__restrict__ hwk,
+                                              const uint32_t *__restrict__ row_ptr,
+                                              const uint32_t *__restrict__ col, Counters *tb_cnt)
 {
     // the tie break that follows counts into these (no kernel between reads them)
     if (tb_cnt && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -116,31 +127,64 @@ __global__ void k_hook(const uint32_t *__restrict__ R, uint32_t nR, uint64_t *__
         tb_cnt->tdone = 0;
         tb_cnt->nR = tb_cnt->nF = tb_cnt->hooks = 0;
     }
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nR; k += stride) {
-        const uint32_t i = R[k];
-        const uint64_t key = r[i];
-        if (key != KEY_INF) {
-            r[i] = KEY_INF;
-            const uint32_t e = (uint32_t)key;
-            bool done = false;
-            if (IDENTITY && row_ptr) {
-                const uint32_t rs = row_ptr[i], re = row_ptr[i + 1];
-                if ((rs >> 6) == ((re - 1u) >> 6)) {
-                    h[i] = col[rs];
-                    done = true;
-                }
-            }
-            if (!done) {
-                // with p the identity (round 1) the endpoints are their own roots
-                const uint32_t ea = (uint32_t)edges[2 * (size_t)e];
-                const uint32_t eb = (uint32_t)edges[2 * (size_t)e + 1];
-                const uint32_t a = IDENTITY ? ea : p[ea];
-                const uint32_t b = IDENTITY ? eb : p[eb];
-                h[i] = (a == i) ? b : a;
-            }
-            hedge[i] = e;
-            hwk[i] = (uint32_t)(key >> 32);  // the hooked edge's weight key
+    const uint32_t base = blockIdx.x * HK_TILE + threadIdx.x;
+    uint32_t id[HK_IT];
+    uint64_t key[HK_IT];
+#pragma unroll
+    for (int k = 0; k < HK_IT; ++k) {
+        const uint32_t j = base + (uint32_t)k * 256u;
+        id[k] = j < nR ? R[j] : NONE32;
+    }
+#pragma unroll
+    for (int k = 0; k < HK_IT; ++k) key[k] = id[k] != NONE32 ? r[id[k]] : KEY_INF;
+    // the target: with p the identity and the root's row inside one sorted
+    // chunk, the row's first entry; otherwise the endpoint of the edge that
+    // is not in the root's star
+    uint32_t tgt[HK_IT];
+    bool done[HK_IT];
+    if (IDENTITY && row_ptr) {
+        uint32_t rs[HK_IT], re[HK_IT];
+#pragma unroll
+        for (int k = 0; k < HK_IT; ++k) {
+            const bool v = key[k] != KEY_INF;
+            rs[k] = v ? row_ptr[id[k]] : 0u;
+            re[k] = v ? row_ptr[id[k] + 1] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < HK_IT; ++k) {
+            done[k] = key[k] != KEY_INF && (rs[k] >> 6) == ((re[k] - 1u) >> 6);
+            tgt[k] = done[k] ? col[rs[k]] : 0u;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < HK_IT; ++k) done[k] = false;
+    }
+    uint32_t ea[HK_IT], eb[HK_IT];
+#pragma unroll
+    for (int k = 0; k < HK_IT; ++k) {
+        const bool need = key[k] != KEY_INF && !done[k];
+        const uint32_t e = (uint32_t)key[k];
+        ea[k] = need ? (uint32_t)edges[2 * (size_t)e] : 0u;
+        eb[k] = need ? (uint32_t)edges[2 * (size_t)e + 1] : 0u;
+    }
+    if (!IDENTITY) {
+#pragma unroll
+        for (int k = 0; k < HK_IT; ++k) {
+            const bool need = key[k] != KEY_INF;
+            ea[k] = need ? p[ea[k]] : 0u;
+            eb[k] = need ? p[eb[k]] : 0u;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < HK_IT; ++k) {
+        const uint32_t i = id[k];
+        if (i == NONE32) continue;
+        if (key[k] != KEY_INF) {
+            r[i] = KEY_INF;  // empty again for the next round's sweep
+            // with p the identity (round 1) the endpoints are their own roots
+            h[i] = done[k] ? tgt[k] : (ea[k] == i ? eb[k] : ea[k]);
+            hedge[i] = (uint32_t)key[k];
+            hwk[i] = (uint32_t)(key[k] >> 32);  // the hooked edge's weight key
         } else {
             h[i] = i;
             hedge[i] = NONE32;
@@ -155,11 +199,11 @@ void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, con
 {
     if (!nR) return;
     if (identity)
-        k_hook<true><<<grid_for(nR), 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk,
-                                                  sorted_row_ptr, sorted_col, tb_cnt);
+        k_hook<true><<<(nR + HK_TILE - 1) / HK_TILE, 256, 0, s>>>(
+            R, nR, r, p, edges, h, hedge, hwk, sorted_row_ptr, sorted_col, tb_cnt);
     else
-        k_hook<false><<<grid_for(nR), 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk, nullptr,
-                                                   nullptr, tb_cnt);
+        k_hook<false><<<(nR + HK_TILE - 1) / HK_TILE, 256, 0, s>>>(
+            R, nR, r, p, edges, h, hedge, hwk, nullptr, nullptr, tb_cnt);
 }
 
 // ------------------------------------------------------- forest weight --
@@ -197,28 +241,38 @@ __global__ __launch_bounds__(CT_NT) void k_tiebreak(const uint32_t *__restrict__
     __shared__ uint64_t s_lds[CT_NT / 64 + 1];
     __shared__ uint64_t s_pre;
     const uint32_t tile = blockIdx.x;
-    const uint32_t base = tile * CT_TILE + threadIdx.x * CT_IT;
-    uint32_t id[CT_IT];
+    // item k of a thread is entry tile * CT_TILE + k * CT_NT + thread of R,
+    // so every load below is one coalesced access per wave; the loads come
+    // in phases (ids, targets, the targets' targets and hooked edges), all
+    // issued before any store, instead of one dependent chain per item
+    const uint32_t base = tile * CT_TILE + threadIdx.x;
+    uint32_t id[CT_IT], t[CT_IT], back[CT_IT], e[CT_IT];
+#pragma unroll
+    for (int k = 0; k < CT_IT; ++k) {
+        const uint32_t j = base + (uint32_t)k * CT_NT;
+        id[k] = j < nR ? R[j] : NONE32;
+    }
+#pragma unroll
+    for (int k = 0; k < CT_IT; ++k) t[k] = id[k] != NONE32 ? load_relaxed_u32(h + id[k]) : NONE32;
+#pragma unroll
+    for (int k = 0; k < CT_IT; ++k) {
+        const bool hk = id[k] != NONE32 && t[k] != id[k];
+        back[k] = hk ? load_relaxed_u32(h + t[k]) : NONE32;
+        e[k] = hk ? hedge[id[k]] : 0u;
+    }
     uint32_t stay = 0, hooked = 0, ca = 0, cb = 0;
 #pragma unroll
     for (int k = 0; k < CT_IT; ++k) {
-        id[k] = 0;
-        if (base + k < nR) {
-            const uint32_t i = R[base + k];
-            id[k] = i;
-            const uint32_t t = load_relaxed_u32(h + i);
-            if (t != i) {
-                const uint32_t back = load_relaxed_u32(h + t);
-                if (back == i && i < t) {
-                    store_relaxed_u32(h + i, i);
-                    stay |= 1u << k;
-                    ++ca;
-                } else {
-                    in_forest[hedge[i]] = 1;
-                    hooked |= 1u << k;
-                    ++cb;
-                }
-            }
+        const uint32_t i = id[k];
+        if (i == NONE32 || t[k] == i) continue;
+        if (back[k] == i && i < t[k]) {
+            store_relaxed_u32(h + i, i);
+            stay |= 1u << k;
+            ++ca;
+        } else {
+            in_forest[e[k]] = 1;
+            hooked |= 1u << k;
+            ++cb;
         }
     }
     // both lists are sets (no later step depends on their order): a block
