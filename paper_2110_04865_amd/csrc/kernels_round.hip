@@ -103,14 +103,14 @@ void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S,
 // by key inside every 64-entry chunk), a root whose row lies in one chunk
 // takes its hook target from the row's first entry (its smallest key)
 // instead of gathering the edge's endpoints.
-// Items per thread of the hook (item k of a thread is entry
-// block * HK_TILE + k * 256 + thread of R: coalesced loads, issued in phases
-// so that the chains R -> r -> edge endpoints -> parents of different items
-// overlap).
-constexpr int HK_IT = 8;
-constexpr uint32_t HK_TILE = 256 * HK_IT;
+// Items per thread of the hook: IT (item k of a thread is entry
+// block * 256 * IT + k * 256 + thread of R: coalesced loads, issued in
+// phases so that the chains R -> r -> edge endpoints -> parents of
+// different items overlap).  Several items per thread only pay with many
+// roots; with fewer, one item per thread keeps every compute unit busy.
+constexpr uint32_t HK_MANY = 1u << 22;
 
-template <bool IDENTITY>
+template <bool IDENTITY, int HK_IT>
 __global__ __launch_bounds__(256) void k_hook(const uint32_t *__restrict__ R, uint32_t nR,
                                               uint64_t *__restrict__ r,
                                               const uint32_t *__restrict__ p,
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void k_hook(const uint32_t *__restrict__ R, ui
         tb_cnt->tdone = 0;
         tb_cnt->nR = tb_cnt->nF = tb_cnt->hooks = 0;
     }
-    const uint32_t base = blockIdx.x * HK_TILE + threadIdx.x;
+    const uint32_t base = blockIdx.x * (256u * HK_IT) + threadIdx.x;
     uint32_t id[HK_IT];
     uint64_t key[HK_IT];
 #pragma unroll
@@ -198,12 +198,20 @@ void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, con
                  Counters *tb_cnt)
 {
     if (!nR) return;
-    if (identity)
-        k_hook<true><<<(nR + HK_TILE - 1) / HK_TILE, 256, 0, s>>>(
-            R, nR, r, p, edges, h, hedge, hwk, sorted_row_ptr, sorted_col, tb_cnt);
+    const bool many = nR >= HK_MANY;
+    const unsigned g4 = (nR + 1023u) / 1024u, g1 = (nR + 255u) / 256u;
+    if (identity && many)
+        k_hook<true, 4><<<g4, 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk, sorted_row_ptr,
+                                           sorted_col, tb_cnt);
+    else if (identity)
+        k_hook<true, 1><<<g1, 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk, sorted_row_ptr,
+                                           sorted_col, tb_cnt);
+    else if (many)
+        k_hook<false, 4><<<g4, 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk, nullptr, nullptr,
+                                            tb_cnt);
     else
-        k_hook<false><<<(nR + HK_TILE - 1) / HK_TILE, 256, 0, s>>>(
-            R, nR, r, p, edges, h, hedge, hwk, nullptr, nullptr, tb_cnt);
+        k_hook<false, 1><<<g1, 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk, nullptr, nullptr,
+                                            tb_cnt);
 }
 
 // ------------------------------------------------------- forest weight --
@@ -275,14 +283,40 @@ __global__ __launch_bounds__(CT_NT) void k_tiebreak(const uint32_t *__restrict__
             ++cb;
         }
     }
-    // both lists are sets (no later step depends on their order): a block
-    // takes its slots with one atomic on the packed (roots << 31 | hooks)
-    // count instead of an ordered look-back over the tiles; the last block
-    // to finish publishes the totals (each block's slot atomic has returned
-    // before it counts itself done)
-    uint64_t btot;
-    const uint64_t ex = block_excl_sum<CT_NT>(((uint64_t)ca << 31) | cb, s_lds, &btot);
+    // Both lists keep the tile's order of R (k-major, then wave, then lane:
+    // the order of the entries), so the shortcut and the next hook read h
+    // and r of nearby vertices together.  Per (item k, wave): counts by
+    // ballot, a scan of the 2 x CT_IT x waves counts in LDS, and ranks from
+    // the lane masks.  Across tiles the lists are sets: a block takes its
+    // slots with one atomic on the packed (roots << 31 | hooks) count; the
+    // last block to finish publishes the totals (each block's slot atomic
+    // has returned before it counts itself done).
+    constexpr int NW = CT_NT / 64;
+    __shared__ uint32_t s_off[2][CT_IT][NW];
+    const uint32_t w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < CT_IT; ++k) {
+        const uint64_t ma = __ballot((stay >> k) & 1u), mb = __ballot((hooked >> k) & 1u);
+        if (__lane_id() == 0) {
+            s_off[0][k][w] = (uint32_t)__popcll(ma);
+            s_off[1][k][w] = (uint32_t)__popcll(mb);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        // exclusive scan of one list's counts in (k, wave) order
+        uint32_t run = 0;
+        for (int k = 0; k < CT_IT; ++k)
+            for (int v = 0; v < NW; ++v) {
+                const uint32_t c = s_off[threadIdx.x][k][v];
+                s_off[threadIdx.x][k][v] = run;
+                run += c;
+            }
+        s_lds[threadIdx.x] = run;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        const uint64_t btot = (s_lds[0] << 31) | s_lds[1];
         const uint64_t pre = atomicAdd((unsigned long long *)&cnt->rf, (unsigned long long)btot);
         s_pre = pre;
         if (atomicAdd(&cnt->tdone, pre == ~0ull ? 0u : 1u) == gridDim.x - 1) {
@@ -292,13 +326,17 @@ __global__ __launch_bounds__(CT_NT) void k_tiebreak(const uint32_t *__restrict__
         }
     }
     __syncthreads();
-    uint32_t oa = (uint32_t)((s_pre >> 31) + (ex >> 31));
-    uint32_t ob = (uint32_t)((s_pre & M31) + (ex & M31));
+    const uint32_t pa = (uint32_t)(s_pre >> 31), pb = (uint32_t)(s_pre & M31);
+    const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int k = 0; k < CT_IT; ++k) {
-        if (stay & (1u << k)) Rnext[oa++] = id[k];
-        else if (hooked & (1u << k)) F[ob++] = id[k];
+        const bool a = (stay >> k) & 1u, b = (hooked >> k) & 1u;
+        const uint64_t ma = __ballot(a), mb = __ballot(b);
+        if (a) Rnext[pa + s_off[0][k][w] + (uint32_t)__popcll(ma & lt)] = id[k];
+        else if (b) F[pb + s_off[1][k][w] + (uint32_t)__popcll(mb & lt)] = id[k];
     }
+    (void)ca;
+    (void)cb;
 }
 
 void launch_tiebreak(hipStream_t s, const uint32_t *R, uint32_t nR, uint32_t *h,
