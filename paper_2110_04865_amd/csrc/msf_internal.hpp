@@ -273,9 +273,13 @@ struct Ctx {
     int graph_order = 1;
     // rounds of the full sweep driven on the device, several per host round
     // trip, for graphs of at most graph_rounds_max_n vertices: 0 off, 1 as
-    // direct launches, 2 replays of a HIP graph captured once per solve
+    // direct launches, 2 replays of a HIP graph captured once per solve.
+    // Their kernels cover all n vertices every round; measured, that pays
+    // up to about a million vertices (grid 64^3 1.09 -> 0.91 ms, ER with
+    // 10^5 vertices 0.89 -> 0.74 ms) and not at 2^21 (grid 128^3: 2.15 ms
+    // host-stepped over compacted root lists, 2.28 ms on the device).
     int graph_rounds = 2;
-    int64_t graph_rounds_max_n = (int64_t)1 << 21;
+    int64_t graph_rounds_max_n = (int64_t)1 << 20;
     hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
     hipGraphExec_t gexec = nullptr;    // the captured rounds, for gkey
     uint64_t gkey[16] = {};
