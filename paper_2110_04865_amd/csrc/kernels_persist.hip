@@ -37,11 +37,18 @@
 // on that graph alone.  Outputs: the forest's local edge ids in ascending
 // order from out + vtx_off[g], count and exact totals.
 #include <algorithm>
+#include <type_traits>
 
 #include "exact_sum.hpp"
 #include "msf_internal.hpp"
 #include "persist.hpp"
 #include "wave.hpp"
+
+// Graphs whose state does not fit the launch's LDS keep their parent
+// vector there as 16-bit ids when it fits (1).
+#ifndef PERSIST_P16
+#define PERSIST_P16 1
+#endif
 
 namespace msf {
 
@@ -82,11 +89,17 @@ struct Ctl {
     uint32_t gerr;       // the current graph failed validation
 };
 
-template <int NT, int EPT, int WT, bool IN_LDS>
+// P16: the state is in the workgroup's slot except p, which is kept in LDS
+// as 16-bit vertex ids (pstate; graphs of at most 2^16 vertices): the sweep
+// looks up p at both ends of every edge, and the hook follows p chains.
+template <int NT, int EPT, int WT, bool IN_LDS, bool P16>
 __device__ __forceinline__ void solve_graph(const PersistArgs &A, uint32_t g, uint8_t *state,
-                                            LiveEdge *buf0, LiveEdge *buf1, Ctl &ctl,
-                                            int64_t *s_sum, int64_t *s_tot, uint32_t *s_scan)
+                                            uint16_t *pstate, LiveEdge *buf0, LiveEdge *buf1,
+                                            Ctl &ctl, int64_t *s_sum, int64_t *s_tot,
+                                            uint32_t *s_scan)
 {
+    static_assert(!(IN_LDS && P16), "p in LDS on its own only when the rest is not");
+    using PT = typename std::conditional<P16, uint16_t, uint32_t>::type;
     const uint32_t tid = threadIdx.x;
     const int64_t v0 = A.vtx_off[g];
     const uint32_t n = (uint32_t)(A.vtx_off[g + 1] - v0);
@@ -97,8 +110,15 @@ __device__ __forceinline__ void solve_graph(const PersistArgs &A, uint32_t g, ui
     // that stopped being a root points to the root that absorbed it, after
     // that round's shortcut); h: hook targets; L: the current roots
     uint64_t *r = reinterpret_cast<uint64_t *>(state);
-    uint32_t *p = reinterpret_cast<uint32_t *>(state + 8 * (size_t)n);
-    uint32_t *h = p + n;
+    PT *p;
+    uint32_t *h;
+    if constexpr (P16) {
+        p = pstate;
+        h = reinterpret_cast<uint32_t *>(state + 8 * (size_t)n);
+    } else {
+        p = reinterpret_cast<PT *>(state + 8 * (size_t)n);
+        h = reinterpret_cast<uint32_t *>(p + n);
+    }
     uint32_t *L = h + n;
     uint32_t *fb = L + n;
     const int2 *E = reinterpret_cast<const int2 *>(A.edges) + e0;
@@ -106,7 +126,7 @@ __device__ __forceinline__ void solve_graph(const PersistArgs &A, uint32_t g, ui
 
     for (uint32_t i = tid; i < n; i += NT) {
         r[i] = KEY_INF;
-        p[i] = i;
+        p[i] = (PT)i;
         L[i] = i;
     }
     uint32_t nroots = n;
@@ -319,7 +339,7 @@ __device__ __forceinline__ void solve_graph(const PersistArgs &A, uint32_t g, ui
             bool stay = false;
             if (i != NONE32) {
                 const uint32_t t = h[i];
-                p[i] = t;
+                p[i] = (PT)t;
                 // a root without an outgoing edge spans its whole component:
                 // no edge can reach it again, so it leaves the list
                 stay = t == i && r[i] != KEY_INF;
@@ -397,9 +417,15 @@ __global__ __launch_bounds__(NT) void k_persist(PersistArgs A)
         const uint32_t n = (uint32_t)(A.vtx_off[g + 1] - A.vtx_off[g]);
         const uint32_t m = (uint32_t)(A.edge_off[g + 1] - A.edge_off[g]);
         if (persist_state_bytes(n, m) <= A.lds_bytes)
-            solve_graph<NT, EPT, WT, true>(A, g, smem, buf0, buf1, ctl, s_sum, s_tot, s_scan);
+            solve_graph<NT, EPT, WT, true, false>(A, g, smem, nullptr, buf0, buf1, ctl, s_sum,
+                                                  s_tot, s_scan);
+        else if (PERSIST_P16 && n <= 65536u && 2 * (size_t)n <= A.lds_bytes)
+            solve_graph<NT, EPT, WT, false, true>(A, g, gstate,
+                                                  reinterpret_cast<uint16_t *>(smem), buf0,
+                                                  buf1, ctl, s_sum, s_tot, s_scan);
         else
-            solve_graph<NT, EPT, WT, false>(A, g, gstate, buf0, buf1, ctl, s_sum, s_tot, s_scan);
+            solve_graph<NT, EPT, WT, false, false>(A, g, gstate, nullptr, buf0, buf1, ctl,
+                                                   s_sum, s_tot, s_scan);
     }
     if (threadIdx.x == 0 && ctl.err) atomicOr(A.err, ctl.err);
 }
