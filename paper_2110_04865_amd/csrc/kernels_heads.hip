@@ -9,11 +9,15 @@
 // and every internal entry in front of it can be passed over for good.
 //
 // Layout.  Once per solve, every 64-entry chunk of the adjacency (entries
-// [64c, 64c + 64)) is sorted by (row, key): rows keep their places and each
+// [64c, 64c + 64)) is ordered by (row, key): rows keep their places and each
 // row's part of the chunk (a run, at most 64 entries) is in ascending key
-// order.  A run is described by {cur, end, row, hcol, hkey}: cur is its
-// head (first entry not yet known to be internal), hcol and hkey the head's
-// column and key (hkey = UINT64_MAX once the run is exhausted).  A sweep
+// order.  The entries themselves do not move: the order is a permutation,
+// one byte per entry, perm[64c + j] = the chunk offset of the entry at
+// sorted position j (so the adjacency is only read and can belong to a kept
+// graph).  A run is described by {cur, end, row, hcol, hkey} in sorted
+// positions: cur is its head (first entry not yet known to be internal),
+// hcol and hkey the head's column and key (hkey = UINT64_MAX once the run
+// is exhausted).  A sweep
 // visits runs, not entries:
 //   phase A, one lane per run: gathers p[hcol]; an outgoing head gives the
 //     run's minimum; an internal one makes the lane probe the next
@@ -231,19 +235,27 @@ __global__ __launch_bounds__(256) void k_runs_write(const uint32_t *__restrict__
     }
 }
 
-// Sort every 64-entry chunk by (run, key) with a bitonic network over the
+// Order every 64-entry chunk by (run, key) with a bitonic network over the
 // lanes (one wave per chunk; keys are distinct within a row, and runs keep
-// their places) and store each run's head (its smallest key) into its
-// descriptor.  The sorted chunk goes to col/key, in place when they are
-// col_in/key_in (each lane reads and writes only its own position, after
-// the whole wave has read).  The chunk's runs are cfirst[c] .. cfirst[c + 1] - 1 (the
+// their places) carrying each entry's chunk offset, write the order to
+// perm and store each run's head (its smallest key, and its column, read at
+// the head's own position) into its descriptor.  Reads the keys (8 bytes
+// per entry) and writes one byte per entry.  The chunk's runs are cfirst[c] .. cfirst[c + 1] - 1 (the
 // last chunk ends at *nruns); their starts are ORed across the lanes.  With
 // PACKED (edge ids of at most 26 bits) the sort key is one 64-bit word: run
 // index inside the chunk, weight key, edge id.
+// Chunks one wave orders: their loads (keys, first runs, then the runs'
+// starts) are all issued before the first network runs, so the chains of
+// dependent loads of different chunks overlap.
+#ifndef SORT_CHUNKS_PER_WAVE
+#define SORT_CHUNKS_PER_WAVE 8
+#endif
+constexpr int SORT_CH = SORT_CHUNKS_PER_WAVE;
+
 template <bool PACKED>
-__global__ __launch_bounds__(256) void k_sort_chunks(const uint32_t *col_in,
-                                                     const uint64_t *key_in, uint32_t *col,
-                                                     uint64_t *key, uint32_t nnz,
+__global__ __launch_bounds__(256) void k_sort_chunks(const uint32_t *__restrict__ col,
+                                                     const uint64_t *__restrict__ key,
+                                                     uint8_t *__restrict__ perm, uint32_t nnz,
                                                      const uint32_t *__restrict__ cfirst,
                                                      const uint32_t *__restrict__ nruns,
                                                      const uint32_t *__restrict__ run_cur, int eb,
@@ -252,42 +264,58 @@ __global__ __launch_bounds__(256) void k_sort_chunks(const uint32_t *col_in,
 {
     const uint32_t lane = __lane_id();
     const uint32_t nch = (nnz + 63u) / 64u;
-    const uint32_t c = blockIdx.x * 4u + (threadIdx.x >> 6);
-    if (c >= nch) return;  // whole waves
-    const uint32_t pos = c * 64u + lane;
-    const bool valid = pos < nnz;
-    uint64_t k = valid ? key_in[pos] : KEY_INF;
-    uint32_t pl = valid ? col_in[pos] : 0u;
-    // run starts of the chunk, from the run descriptors (OR over the lanes)
-    const uint32_t r0 = cfirst[c];
-    const uint32_t r1 = c + 1u < nch ? cfirst[c + 1u] : *nruns;
-    uint64_t sm = r0 + lane < r1 ? 1ull << (run_cur[r0 + lane] & 63u) : 0ull;
-    sm |= xor_move64<1>(sm);
-    sm |= xor_move64<2>(sm);
-    sm |= xor_move64<4>(sm);
-    sm |= xor_move64<8>(sm);
-    sm |= xor_move64<16>(sm);
-    sm |= xor_move64<32>(sm);
-    const uint64_t vmask = nnz - c * 64u >= 64u ? ~0ull : (1ull << (nnz - c * 64u)) - 1ull;
-    const uint64_t starts = sm & vmask;
-    const uint32_t below = (uint32_t)__popcll(starts & lanemask_lt());
-    const bool is_start = (starts >> lane) & 1ull;
-    uint32_t pi = valid ? below + (is_start ? 1u : 0u) - 1u : 63u;  // run inside the chunk
-    const uint64_t emask = (1ull << eb) - 1ull;
-    if constexpr (PACKED)
-        k = valid ? ((uint64_t)pi << 58) | ((k >> 32) << eb) | (k & emask) : ~0ull;
+    const uint32_t c0 = (blockIdx.x * 4u + (threadIdx.x >> 6)) * (uint32_t)SORT_CH;
+    if (c0 >= nch) return;  // whole waves
+    const uint32_t total = *nruns;
+    uint64_t kk[SORT_CH];
+    uint32_t r0[SORT_CH], r1[SORT_CH], rc[SORT_CH];
+#pragma unroll
+    for (int t = 0; t < SORT_CH; ++t) {
+        const uint32_t c = c0 + (uint32_t)t;
+        const uint32_t pos = c * 64u + lane;
+        kk[t] = c < nch && pos < nnz ? key[pos] : KEY_INF;
+        r0[t] = c < nch ? cfirst[c] : 0u;
+        r1[t] = c + 1u < nch ? cfirst[c + 1u] : total;
+    }
+    // run starts of each chunk, from the run descriptors (OR over the lanes)
+#pragma unroll
+    for (int t = 0; t < SORT_CH; ++t)
+        rc[t] = c0 + (uint32_t)t < nch && r0[t] + lane < r1[t] ? run_cur[r0[t] + lane] : NONE32;
     bool lb[7];
 #pragma unroll
-    for (int t = 0; t < 7; ++t) lb[t] = (lane >> t) & 1u;
-    bitonic_sort<PACKED, 2>(lb, pi, k, pl);
-    if constexpr (PACKED) k = (((k >> eb) & 0xFFFFFFFFull) << 32) | (k & emask);
-    if (valid) {
-        col[pos] = pl;
-        key[pos] = k;
-        if (is_start) {
-            const uint32_t ri = r0 + below;
-            hcol[ri] = pl;
-            hkey[ri] = k;
+    for (int b = 0; b < 7; ++b) lb[b] = (lane >> b) & 1u;
+    const uint64_t emask = (1ull << eb) - 1ull;
+#pragma unroll
+    for (int t = 0; t < SORT_CH; ++t) {
+        const uint32_t c = c0 + (uint32_t)t;
+        if (c >= nch) break;  // uniform
+        const uint32_t pos = c * 64u + lane;
+        const bool valid = pos < nnz;
+        uint64_t k = kk[t];
+        uint32_t pl = lane;  // carried through the network: the entry's chunk offset
+        uint64_t sm = rc[t] != NONE32 ? 1ull << (rc[t] & 63u) : 0ull;
+        sm |= xor_move64<1>(sm);
+        sm |= xor_move64<2>(sm);
+        sm |= xor_move64<4>(sm);
+        sm |= xor_move64<8>(sm);
+        sm |= xor_move64<16>(sm);
+        sm |= xor_move64<32>(sm);
+        const uint64_t vmask = nnz - c * 64u >= 64u ? ~0ull : (1ull << (nnz - c * 64u)) - 1ull;
+        const uint64_t starts = sm & vmask;
+        const uint32_t below = (uint32_t)__popcll(starts & lanemask_lt());
+        const bool is_start = (starts >> lane) & 1ull;
+        uint32_t pi = valid ? below + (is_start ? 1u : 0u) - 1u : 63u;  // run inside the chunk
+        if constexpr (PACKED)
+            k = valid ? ((uint64_t)pi << 58) | ((k >> 32) << eb) | (k & emask) : ~0ull;
+        bitonic_sort<PACKED, 2>(lb, pi, k, pl);
+        if constexpr (PACKED) k = (((k >> eb) & 0xFFFFFFFFull) << 32) | (k & emask);
+        if (valid) {
+            perm[pos] = (uint8_t)pl;
+            if (is_start) {
+                const uint32_t ri = r0[t] + below;
+                hcol[ri] = col[c * 64u + pl];
+                hkey[ri] = k;
+            }
         }
     }
 }
@@ -300,6 +328,7 @@ __global__ __launch_bounds__(256) void k_heads(const uint32_t *__restrict__ run_
                                                uint64_t *__restrict__ run_hkey, uint32_t nruns,
                                                const uint32_t *__restrict__ col,
                                                const uint64_t *__restrict__ key,
+                                               const uint8_t *__restrict__ perm,
                                                const uint32_t *__restrict__ p,
                                                uint64_t *__restrict__ r,
                                                uint32_t *__restrict__ queue, uint32_t *qn,
@@ -329,24 +358,27 @@ __global__ __launch_bounds__(256) void k_heads(const uint32_t *__restrict__ run_
             // the head is internal: probe the next entries together
             const uint32_t cur = run_cur[i], end = run_end[i];
             const uint32_t b = cur + 1u;
-            uint32_t cc[HEAD_PROBE], pc[HEAD_PROBE];
+            uint32_t cc[HEAD_PROBE], pc[HEAD_PROBE], ce[HEAD_PROBE];
 #pragma unroll
             for (int t = 0; t < HEAD_PROBE; ++t) {
                 const uint32_t q = b + (uint32_t)t < end ? b + (uint32_t)t : end - 1u;
-                cc[t] = col[q];
+                ce[t] = (q & ~63u) | perm[q];
             }
 #pragma unroll
+            for (int t = 0; t < HEAD_PROBE; ++t) cc[t] = col[ce[t]];
+#pragma unroll
             for (int t = 0; t < HEAD_PROBE; ++t) pc[t] = p[cc[t]];
-            uint32_t f = (uint32_t)HEAD_PROBE, fc = 0;
+            uint32_t f = (uint32_t)HEAD_PROBE, fc = 0, fe = 0;
 #pragma unroll
             for (int t = HEAD_PROBE - 1; t >= 0; --t)
                 if (b + (uint32_t)t < end && pc[t] != root) {
                     f = (uint32_t)t;
                     fc = cc[t];
+                    fe = ce[t];
                 }
             if (f < (uint32_t)HEAD_PROBE) {
                 const uint32_t nc = b + f;
-                cand = key[nc];
+                cand = key[fe];
                 run_cur[i] = nc;
                 run_hcol[i] = fc;
                 run_hkey[i] = cand;
@@ -376,7 +408,8 @@ __global__ __launch_bounds__(256) void k_heads_rest(
     const uint32_t *__restrict__ run_row, uint32_t *__restrict__ run_cur,
     const uint32_t *__restrict__ run_end, uint32_t *__restrict__ run_hcol,
     uint64_t *__restrict__ run_hkey, const uint32_t *__restrict__ col,
-    const uint64_t *__restrict__ key, const uint32_t *__restrict__ p, uint64_t *__restrict__ r)
+    const uint64_t *__restrict__ key, const uint8_t *__restrict__ perm,
+    const uint32_t *__restrict__ p, uint64_t *__restrict__ r)
 {
     const uint32_t lane = __lane_id();
     uint32_t n = load_relaxed_u32(qn);
@@ -388,16 +421,17 @@ __global__ __launch_bounds__(256) void k_heads_rest(
         const uint32_t cur = run_cur[i], end = run_end[i];
         const uint32_t root = p[run_row[i] & ~RUN_LONG];
         const uint32_t q = cur + lane;
-        uint32_t c = 0;
+        uint32_t c = 0, qe = 0;
         bool ext = false;
         if (q < end) {
-            c = col[q];
+            qe = (q & ~63u) | perm[q];
+            c = col[qe];
             ext = p[c] != root;
         }
         const uint64_t b = __ballot(ext);
         if (b) {
             if (lane == (uint32_t)__ffsll((unsigned long long)b) - 1u) {
-                const uint64_t kq = key[q];
+                const uint64_t kq = key[qe];
                 run_cur[i] = q;
                 run_hcol[i] = c;
                 run_hkey[i] = kq;
@@ -418,8 +452,7 @@ size_t heads_runs_cap(size_t nnz_cap, int32_t n)
 }
 
 msf_status build_runs(Ctx *c, const Runs &R, const uint32_t *row_ptr, int32_t n,
-                      const uint32_t *col_in, const uint64_t *key_in, uint32_t *col,
-                      uint64_t *key, uint32_t nnz, int eb)
+                      const uint32_t *col, const uint64_t *key, uint32_t nnz, int eb)
 {
     hipStream_t s = c->stream;
     const uint32_t nch = (nnz + 63u) / 64u;
@@ -431,15 +464,15 @@ msf_status build_runs(Ctx *c, const Runs &R, const uint32_t *row_ptr, int32_t n,
     k_runs_count<<<gr, 256, 0, s>>>(row_ptr, n, R.rc);
     MSF_TRY(scan_u32(c, R.rc, R.roff, (int64_t)n, &c->dcnt->nruns));
     k_runs_write<<<gr, 256, 0, s>>>(row_ptr, n, R.roff, R.cur, R.end, R.row, R.cfirst);
-    const unsigned gs = (nch + 3u) / 4u;
+    const unsigned gs = (nch + 4u * SORT_CH - 1u) / (4u * SORT_CH);
     const uint32_t *total = R.roff + n;  // the scan's total: the number of runs
     MSF_HIP(hipEventRecord(c->kev[2], s));
     if (eb <= 26)
-        k_sort_chunks<true><<<gs, 256, 0, s>>>(col_in, key_in, col, key, nnz, R.cfirst, total,
-                                               R.cur, eb, R.hcol, R.hkey);
+        k_sort_chunks<true><<<gs, 256, 0, s>>>(col, key, R.perm, nnz, R.cfirst, total, R.cur,
+                                               eb, R.hcol, R.hkey);
     else
-        k_sort_chunks<false><<<gs, 256, 0, s>>>(col_in, key_in, col, key, nnz, R.cfirst, total,
-                                                R.cur, eb, R.hcol, R.hkey);
+        k_sort_chunks<false><<<gs, 256, 0, s>>>(col, key, R.perm, nnz, R.cfirst, total, R.cur,
+                                                eb, R.hcol, R.hkey);
     MSF_HIP(hipEventRecord(c->kev[3], s));
     c->pass_done |= 2u;
     MSF_HIP(hipGetLastError());
@@ -456,9 +489,10 @@ void launch_heads(hipStream_t s, const Runs &R, uint32_t nruns, const uint32_t *
     uint32_t *qn = &dcnt->qn[parity & 1], *qn_next = &dcnt->qn[(parity & 1) ^ 1];
     for (uint32_t want_long : {RUN_LONG, 0u})
         k_heads<<<(nruns + 255u) / 256u, 256, 0, s>>>(R.row, R.cur, R.end, R.hcol, R.hkey, nruns,
-                                                      col, key, p, r, R.queue, qn, want_long);
+                                                      col, key, R.perm, p, r, R.queue, qn,
+                                                      want_long);
     k_heads_rest<<<HEADS_REST_BLOCKS, 256, 0, s>>>(R.queue, qn, qn_next, nruns, R.row, R.cur,
-                                                   R.end, R.hcol, R.hkey, col, key, p, r);
+                                                   R.end, R.hcol, R.hkey, col, key, R.perm, p, r);
 }
 
 }  // namespace msf

@@ -99,9 +99,10 @@ void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S,
 // Writes go to h, never to p, so concurrent readers of p see one version.
 // r[i] is reset to empty for the next round.
 
-// IDENTITY: p is the identity (round 1); with row_ptr and col (rows sorted
-// by key inside every 64-entry chunk), a root whose row lies in one chunk
-// takes its hook target from the row's first entry (its smallest key)
+// IDENTITY: p is the identity (round 1); with row_ptr, col and perm (every
+// 64-entry chunk ordered by (row, key), perm[j] the chunk offset of the
+// entry at sorted position j), a root whose row lies in one chunk takes its
+// hook target from the row's first entry in that order (its smallest key)
 // instead of gathering the edge's endpoints.
 // Items per thread of the hook: IT (item k of a thread is entry
 // block * 256 * IT + k * 256 + thread of R: coalesced loads, issued in
@@ -119,7 +120,8 @@ __global__ __launch_bounds__(256) void k_hook(const uint32_t *__restrict__ R, ui
                                               uint32_t *__restrict__ hedge,
                                               uint32_t *__restrict__ hwk,
                                               const uint32_t *__restrict__ row_ptr,
-                                              const uint32_t *__restrict__ col, Counters *tb_cnt)
+                                              const uint32_t *__restrict__ col,
+                                              const uint8_t *__restrict__ perm, Counters *tb_cnt)
 {
     // the tie break that follows counts into these (no kernel between reads them)
     if (tb_cnt && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(256) void k_hook(const uint32_t *__restrict__ R, ui
 #pragma unroll
         for (int k = 0; k < HK_IT; ++k) {
             done[k] = key[k] != KEY_INF && (rs[k] >> 6) == ((re[k] - 1u) >> 6);
-            tgt[k] = done[k] ? col[rs[k]] : 0u;
+            tgt[k] = done[k] ? col[(rs[k] & ~63u) | perm[rs[k]]] : 0u;
         }
     } else {
 #pragma unroll
@@ -194,24 +196,26 @@ __global__ __launch_bounds__(256) void k_hook(const uint32_t *__restrict__ R, ui
 
 void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, const uint32_t *p,
                  const int32_t *edges, uint32_t *h, uint32_t *hedge, uint32_t *hwk,
-                 bool identity, const uint32_t *sorted_row_ptr, const uint32_t *sorted_col,
-                 Counters *tb_cnt)
+                 bool identity, const uint32_t *row_ptr, const uint32_t *col,
+                 const uint8_t *run_perm, Counters *tb_cnt)
 {
     if (!nR) return;
     const bool many = nR >= HK_MANY;
     const unsigned g4 = (nR + 1023u) / 1024u, g1 = (nR + 255u) / 256u;
+    // the shortcut through the ordered chunks needs all three
+    if (!row_ptr || !col || !run_perm) row_ptr = nullptr;
     if (identity && many)
-        k_hook<true, 4><<<g4, 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk, sorted_row_ptr,
-                                           sorted_col, tb_cnt);
+        k_hook<true, 4><<<g4, 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk, row_ptr, col,
+                                           run_perm, tb_cnt);
     else if (identity)
-        k_hook<true, 1><<<g1, 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk, sorted_row_ptr,
-                                           sorted_col, tb_cnt);
+        k_hook<true, 1><<<g1, 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk, row_ptr, col,
+                                           run_perm, tb_cnt);
     else if (many)
         k_hook<false, 4><<<g4, 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk, nullptr, nullptr,
-                                            tb_cnt);
+                                            nullptr, tb_cnt);
     else
         k_hook<false, 1><<<g1, 256, 0, s>>>(R, nR, r, p, edges, h, hedge, hwk, nullptr, nullptr,
-                                            tb_cnt);
+                                            nullptr, tb_cnt);
 }
 
 // ------------------------------------------------------- forest weight --

@@ -103,7 +103,7 @@ enum Slot {
     WS_BATCH0, WS_BATCH1, WS_BATCH2, WS_BATCH3,
     WS_BH, WS_BHOFF, WS_BRLO, WS_BCOL, WS_BKEY, WS_CHUNKINFO,
     WS_TL1, WS_TL2, WS_TLSUB, WS_TLORDER, WS_TLPLAN, WS_T2, WS_T2OFF, WS_FSTART,
-    WS_RUNCHUNK, WS_RUNROW, WS_RUNS, WS_PAIR,
+    WS_RUNCHUNK, WS_RUNROW, WS_RUNS, WS_RUNPERM, WS_PAIR,
     WS_PORDER, WS_PCTL, WS_PSCRATCH,
     WS_COUNT
 };
@@ -155,6 +155,7 @@ struct Runs {
     uint32_t *hcol = nullptr;    // per run: column of the head
     uint64_t *hkey = nullptr;    // per run: key of the head (UINT64_MAX: run exhausted)
     uint32_t *queue = nullptr;   // runs left to phase B of a sweep
+    uint8_t *perm = nullptr;     // per entry: chunk offset of the entry at this sorted position
 };
 
 struct SolveBufs {
@@ -391,12 +392,14 @@ void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S,
                        uint64_t *status, Counters *dcnt);
 // hwk[i]: the weight key (high word of the edge key) of root i's hook;
 // identity: p is the identity (round 1), so endpoints need no lookup; with
-// sorted_row_ptr/sorted_col (one-slice adjacency sorted into the head
-// sweep's runs) a row inside one 64-entry chunk gives its target directly.
+// row_ptr, col and run_perm (a one-slice adjacency whose 64-entry chunks
+// the head sweep ordered by (row, key)) a row inside one chunk gives its
+// target directly: the column of its first entry in that order.
 void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, const uint32_t *p,
                  const int32_t *edges, uint32_t *h, uint32_t *hedge, uint32_t *hwk,
-                 bool identity = false, const uint32_t *sorted_row_ptr = nullptr,
-                 const uint32_t *sorted_col = nullptr, Counters *tb_cnt = nullptr);
+                 bool identity = false, const uint32_t *row_ptr = nullptr,
+                 const uint32_t *col = nullptr, const uint8_t *run_perm = nullptr,
+                 Counters *tb_cnt = nullptr);
 // Counts into dcnt->nR, nF; they (and the slot counts) start at zero: the
 // hook launched just before with tb_cnt clears them (counts_cleared), else
 // this call does.
@@ -423,14 +426,14 @@ constexpr unsigned CHASE_MAX_BLOCKS = 2048;
 
 // Head sweep (kernels_heads.hip).  heads_runs_cap: runs of an adjacency of
 // at most nnz_cap entries over n rows.  build_runs derives the runs of a
-// one-slice adjacency from row_ptr, sorts every chunk of col_in/key_in into
-// col/key (the same arrays: in place) and fills the run arrays (keys' edge
-// ids take eb bits); the run count lands in dcnt->nruns.  launch_heads runs
-// one sweep (queue counter dcnt->qn[parity], clearing the other one).
+// one-slice adjacency from row_ptr, orders every 64-entry chunk of col/key
+// by (row, key) into R.perm (the entries stay where they are) and fills the
+// run arrays (keys' edge ids take eb bits); the run count lands in
+// dcnt->nruns.  launch_heads runs one sweep (queue counter
+// dcnt->qn[parity], clearing the other one).
 size_t heads_runs_cap(size_t nnz_cap, int32_t n);
 msf_status build_runs(Ctx *c, const Runs &R, const uint32_t *row_ptr, int32_t n,
-                      const uint32_t *col_in, const uint64_t *key_in, uint32_t *col,
-                      uint64_t *key, uint32_t nnz, int eb);
+                      const uint32_t *col, const uint64_t *key, uint32_t nnz, int eb);
 void launch_heads(hipStream_t s, const Runs &R, uint32_t nruns, const uint32_t *col,
                   const uint64_t *key, const uint32_t *p, uint64_t *r, Counters *dcnt, int parity);
 msf_status launch_output(Ctx *c, const uint8_t *in_forest, int64_t m, const void *w,

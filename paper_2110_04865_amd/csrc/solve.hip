@@ -28,7 +28,9 @@ static size_t chunk_cap(size_t nnz_cap)
     return sweep_nchunks((uint32_t)std::min<size_t>(nnz_cap, 0xFFFFFFFFull)) + 2 * MAX_SLICES + 2;
 }
 
-static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, int S, SolveBufs *b)
+// adj: also the buffers the adjacency is built into (not for a kept graph's)
+static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, int S, SolveBufs *b,
+                                 bool adj = true)
 {
     const size_t nn = (size_t)std::max(n, 1), mm = (size_t)std::max<int64_t>(m, 1);
     const size_t nnz_cap = 2 * mm;
@@ -50,8 +52,12 @@ static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, int S, SolveBufs 
         {WS_PART, part_bytes},     {WS_HWK, 4 * nn},
     };
     void *v[sizeof(req) / sizeof(req[0])];
-    for (size_t i = 0; i < sizeof(req) / sizeof(req[0]); ++i)
-        MSF_TRY(ws_get(c, req[i].s, req[i].bytes, &v[i]));
+    for (size_t i = 0; i < sizeof(req) / sizeof(req[0]); ++i) {
+        const bool adjacency = req[i].s == WS_ROWPTR || req[i].s == WS_COL ||
+                               req[i].s == WS_KEY || req[i].s == WS_CHUNKROW;
+        v[i] = nullptr;
+        if (adj || !adjacency) MSF_TRY(ws_get(c, req[i].s, req[i].bytes, &v[i]));
+    }
     b->rp[0] = (uint32_t *)v[0];
     b->col[0] = (uint32_t *)v[1];
     b->key[0] = (uint64_t *)v[2];
@@ -101,10 +107,12 @@ static msf_status get_runs_bufs(Ctx *c, int32_t n, int64_t m, Runs *R)
     const size_t nnz_cap = 2 * mm;
     const size_t nch = (nnz_cap + 63) / 64 + 1;
     const size_t rc = heads_runs_cap(nnz_cap, n);
-    void *v[3];
+    void *v[4];
     MSF_TRY(ws_get(c, WS_RUNCHUNK, 4 * nch + 8, &v[0]));
     MSF_TRY(ws_get(c, WS_RUNROW, 4 * nn + 4 * (nn + 1), &v[1]));  // roff: nn + 1 (scan total)
     MSF_TRY(ws_get(c, WS_RUNS, 28 * rc + 8, &v[2]));
+    MSF_TRY(ws_get(c, WS_RUNPERM, 64 * nch + 64, &v[3]));
+    R->perm = (uint8_t *)v[3];
     R->cfirst = (uint32_t *)v[0];
     R->rc = (uint32_t *)v[1];
     R->roff = R->rc + nn;
@@ -217,17 +225,14 @@ msf_status solve_start_kept(Ctx *c, const Adj &a, const uint32_t *perm, uint32_t
     S.kept = true;
     S.labels = labels;
     S.perm = perm;
-    MSF_TRY(get_solve_bufs(c, S.n, S.m, 1, &S.b));
+    MSF_TRY(get_solve_bufs(c, S.n, S.m, 1, &S.b, false));
     MSF_TRY(get_runs_bufs(c, S.n, S.m, &S.runs));
     S.heads = true;
-    S.a = a;
-    S.a.col = S.b.col[0];
-    S.a.key = S.b.key[0];
+    S.a = a;  // only read: the run order goes to the workspace
     MSF_HIP(hipEventRecord(c->ev[0], c->stream));
     zero_counters(c);
     c->pass_done = 0;
-    MSF_TRY(build_runs(c, S.runs, a.row_ptr, S.n, a.col, a.key, S.a.col, S.a.key, a.nnz,
-                       edge_bits(S.m)));
+    MSF_TRY(build_runs(c, S.runs, a.row_ptr, S.n, a.col, a.key, a.nnz, edge_bits(S.m)));
     MSF_TRY(enqueue_round_state(c));
     return end_step(c, 2);
 }
@@ -288,7 +293,7 @@ static msf_status enqueue_round(Ctx *c)
     if (ev_k >= 0) MSF_HIP(hipEventRecord(c->sev[2 * ev_k + 1], s));
     launch_hook(s, S.b.R[S.ri], S.nR, S.b.r, S.b.p, S.edges, S.b.h, S.b.hedge, S.b.hwk,
                 S.rounds == 0, S.heads ? S.a.row_ptr : nullptr, S.heads ? S.a.col : nullptr,
-                c->dcnt);
+                S.heads ? S.runs.perm : nullptr, c->dcnt);
     launch_tiebreak(s, S.b.R[S.ri], S.nR, S.b.h, S.b.hedge, S.b.flags, S.b.R[S.ri ^ 1], S.b.F,
                     S.b.status, c->dcnt, S.nR > 0);
     return end_step(c, 3);
@@ -395,8 +400,8 @@ msf_status solve_advance(Ctx *c)
         set_chunks(&S.a);
         S.a.segs = h->segs;
         if (S.heads)
-            MSF_TRY(build_runs(c, S.runs, S.a.row_ptr, S.n, S.a.col, S.a.key, S.a.col, S.a.key,
-                               S.a.nnz, edge_bits(S.m)));
+            MSF_TRY(build_runs(c, S.runs, S.a.row_ptr, S.n, S.a.col, S.a.key, S.a.nnz,
+                               edge_bits(S.m)));
         // the chunk-row table serves the full sweep only
         if (S.a.nnz && !S.heads) launch_chunk_rows_sliced(s, S.a);
         MSF_TRY(enqueue_round_state(c));
