@@ -84,6 +84,12 @@ constexpr uint32_t TP_C = TL_PART_COPIES;
 #ifndef TL_PACK
 #define TL_PACK 1
 #endif
+// level-2 entries as two arrays, columns (4 bytes) and keys (8 bytes), with
+// the row inside the fine bucket from the 2-byte array the level-2 pass
+// writes anyway (1), instead of 16-byte records that repeat the row (0)
+#ifndef TL_L2_SOA
+#define TL_L2_SOA 1
+#endif
 // copies of the fine histogram's counters (a power of two)
 #ifndef TL_HIST2_COPIES
 #define TL_HIST2_COPIES 8
@@ -371,12 +377,12 @@ __global__ __launch_bounds__(256) void k_tl_hist2(const uint8_t *__restrict__ su
 // TL_SP entries of a tile into registers once.
 constexpr int TL_SP = TL_TILE / TL_NT;  // entries per thread per tile
 
-template <bool PK1, bool PK2>
+template <bool PK1, bool PK2, bool SOA>
 __global__ __launch_bounds__(TL_NT) void k_part_sub(
     const RecT<PK1> *__restrict__ e1, int L2, int nsub, int NC, const uint32_t *__restrict__ cs,
     const uint32_t *__restrict__ nb2, const uint32_t *__restrict__ P,
     const uint32_t *__restrict__ o2, uint32_t cb, RecT<PK2> *__restrict__ e2,
-    uint16_t *__restrict__ sub2)
+    uint32_t *__restrict__ c2, uint64_t *__restrict__ k2, uint16_t *__restrict__ sub2)
 {
     __shared__ uint4 s_ent[TL_TILE];
     __shared__ uint32_t s_run[TL_MAX_NSUB], s_pos[TL_MAX_NSUB * TP_C];  // s_pos: [fine][copy]
@@ -436,7 +442,12 @@ __global__ __launch_bounds__(TL_NT) void k_part_sub(
             const uint4 x = s_ent[i];
             const uint32_t s = (x.x >> L2) & mask;
             const uint32_t q = s_run[s] + (i - s_pos[s * TP_C]);
-            e2[q] = rec_pack<PK2>(x, (uint32_t)L2, cb);
+            if constexpr (SOA) {
+                c2[q] = x.y;
+                k2[q] = ent_key(x);
+            } else {
+                e2[q] = rec_pack<PK2>(x, (uint32_t)L2, cb);
+            }
             sub2[q] = (uint16_t)(x.x & ((1u << L2) - 1u));  // row inside the fine bucket
         }
         __syncthreads();
@@ -511,13 +522,14 @@ __global__ __launch_bounds__(TO_NT) void k_tl_order(const uint32_t *__restrict__
 // scan into row_ptr, place by row.  A bucket's output span is small (tens of
 // KB), so its scattered stores merge in L2 before they reach HBM.  MIN:
 // also store each row's smallest key into r (round 1 of the sweep).
-template <bool MIN, bool PK2>
+template <bool MIN, bool PK2, bool SOA>
 __global__ __launch_bounds__(TC_NT) void k_tl_place(
     const RecT<PK2> *__restrict__ e2, int32_t n, int L2, uint32_t cb,
     const uint32_t *__restrict__ fstart,
     const uint32_t *__restrict__ order, uint32_t *__restrict__ row_ptr,
     uint32_t *__restrict__ col, uint64_t *__restrict__ key, uint64_t *__restrict__ r,
-    const uint16_t *__restrict__ sub2)
+    const uint16_t *__restrict__ sub2, const uint32_t *__restrict__ c2,
+    const uint64_t *__restrict__ k2)
 {
     extern __shared__ uint64_t tc_lds[];
     const uint32_t R = 1u << L2;
@@ -546,11 +558,17 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
 #pragma unroll
         for (int k = 0; k < TC_PT; ++k) {
             const uint64_t i = (uint64_t)fs + threadIdx.x + (uint32_t)k * TC_NT;
-            const uint4 x = i < fe ? rec_unpack<PK2>(e2[i], (uint32_t)row0, (uint32_t)L2, cb)
-                                   : make_uint4(NONE32, 0u, 0u, 0u);
-            rl[k] = x.x != NONE32 ? x.x - (uint32_t)row0 : NONE32;
-            cc[k] = x.y;
-            kk[k] = ent_key(x);
+            if constexpr (SOA) {
+                rl[k] = i < fe ? (uint32_t)sub2[i] : NONE32;
+                cc[k] = i < fe ? c2[i] : 0u;
+                kk[k] = i < fe ? k2[i] : KEY_INF;
+            } else {
+                const uint4 x = i < fe ? rec_unpack<PK2>(e2[i], (uint32_t)row0, (uint32_t)L2, cb)
+                                       : make_uint4(NONE32, 0u, 0u, 0u);
+                rl[k] = x.x != NONE32 ? x.x - (uint32_t)row0 : NONE32;
+                cc[k] = x.y;
+                kk[k] = ent_key(x);
+            }
         }
 #pragma unroll
         for (int k = 0; k < TC_PT; ++k) {
@@ -594,11 +612,18 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k) {
                 const uint64_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
-                const uint4 x = i < fe ? rec_unpack<PK2>(e2[i], (uint32_t)row0, (uint32_t)L2, cb)
-                                       : make_uint4(NONE32, 0u, 0u, 0u);
-                rl[k] = x.x != NONE32 ? x.x - (uint32_t)row0 : NONE32;
-                cc[k] = x.y;
-                kk[k] = ent_key(x);
+                if constexpr (SOA) {
+                    rl[k] = i < fe ? (uint32_t)sub2[i] : NONE32;
+                    cc[k] = i < fe ? c2[i] : 0u;
+                    kk[k] = i < fe ? k2[i] : KEY_INF;
+                } else {
+                    const uint4 x = i < fe ? rec_unpack<PK2>(e2[i], (uint32_t)row0, (uint32_t)L2,
+                                                             cb)
+                                           : make_uint4(NONE32, 0u, 0u, 0u);
+                    rl[k] = x.x != NONE32 ? x.x - (uint32_t)row0 : NONE32;
+                    cc[k] = x.y;
+                    kk[k] = ent_key(x);
+                }
             }
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k) {
@@ -682,7 +707,7 @@ struct TLBufs {
     uint8_t *sub1;
 };
 
-template <bool PK1, bool PK2>
+template <bool PK1, bool PK2, bool SOA>
 msf_status two_level_passes(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
                             const void *d_w, msf_wtype wt, const TwoLevel &tl, int64_t epb,
                             uint32_t nblk, size_t g2max, size_t nt2, uint32_t otiles,
@@ -693,6 +718,10 @@ msf_status two_level_passes(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges
     const int NC = tl.NC;
     auto *e1 = (RecT<PK1> *)B.e1;
     auto *e2 = (RecT<PK2> *)B.e2;
+    // level-2 columns, then keys (8-byte aligned), in the same buffer
+    const size_t cap = 2 * (size_t)m;
+    uint32_t *c2 = (uint32_t *)B.e2;
+    uint64_t *k2 = reinterpret_cast<uint64_t *>(((uintptr_t)(c2 + cap) + 7) & ~(uintptr_t)7);
     // B1
     MSF_HIP(hipEventRecord(c->kev[6], s));
     if (wt == MSF_W_F32)
@@ -711,8 +740,8 @@ msf_status two_level_passes(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges
     // their buffer takes each level-2 entry's row inside its fine bucket
     uint16_t *sub2 = reinterpret_cast<uint16_t *>(B.sub1);
     MSF_HIP(hipEventRecord(c->kev[4], s));
-    k_part_sub<PK1, PK2><<<(unsigned)g2max, TL_NT, 0, s>>>(e1, tl.L2, tl.nsub, NC, B.cs, B.nb2,
-                                                           B.P, B.o2, cb, e2, sub2);
+    k_part_sub<PK1, PK2, SOA><<<(unsigned)g2max, TL_NT, 0, s>>>(
+        e1, tl.L2, tl.nsub, NC, B.cs, B.nb2, B.P, B.o2, cb, e2, c2, k2, sub2);
     MSF_HIP(hipEventRecord(c->kev[5], s));
     // C
     const unsigned nf = (unsigned)NC * (unsigned)tl.nsub;
@@ -723,15 +752,15 @@ msf_status two_level_passes(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges
     const size_t RC = ((size_t)1 << tl.L2) * tc_copies(tl.L2);
     MSF_HIP(hipEventRecord(c->kev[0], s));
     if (r_first)
-        k_tl_place<true, PK2><<<nf, TC_NT, 12 * RC, s>>>(e2, n, tl.L2, cb, B.fst, B.order, row_ptr,
-                                                         col, key, r_first, sub2);
+        k_tl_place<true, PK2, SOA><<<nf, TC_NT, 12 * RC, s>>>(
+            e2, n, tl.L2, cb, B.fst, B.order, row_ptr, col, key, r_first, sub2, c2, k2);
     else
-        k_tl_place<false, PK2><<<nf, TC_NT, 4 * RC, s>>>(e2, n, tl.L2, cb, B.fst, B.order, row_ptr,
-                                                          col, key, nullptr, sub2);
+        k_tl_place<false, PK2, SOA><<<nf, TC_NT, 4 * RC, s>>>(
+            e2, n, tl.L2, cb, B.fst, B.order, row_ptr, col, key, nullptr, sub2, c2, k2);
     MSF_HIP(hipEventRecord(c->kev[1], s));
     c->pass_done |= 1u | 4u | 8u;
     c->rec1 = PK1 ? 12 : 16;
-    c->rec2 = PK2 ? 12 : 16;
+    c->rec2 = SOA ? 12 : PK2 ? 12 : 16;
     MSF_HIP(hipGetLastError());
     return MSF_OK;
 }
@@ -756,12 +785,12 @@ msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
     const uint32_t cb = (uint32_t)bits_for((uint64_t)(n > 1 ? n - 1 : 1));
     const int eb = bits_for((uint64_t)(m > 1 ? m - 1 : 1));
     const bool pk1 = (TL_PACK & 1) && eb + (int)cb + tl.L1 <= 64;
-    const bool pk2 = (TL_PACK & 2) && eb + (int)cb + tl.L2 <= 64;
+    const bool pk2 = !TL_L2_SOA && (TL_PACK & 2) && eb + (int)cb + tl.L2 <= 64;
     void *vbh, *vbo, *ve1, *ve2, *vsub, *vplan, *vt2, *vo2;
     MSF_TRY(ws_get(c, WS_BH, 4 * nh, &vbh));
     MSF_TRY(ws_get(c, WS_BHOFF, 4 * (nh + 1), &vbo));
     MSF_TRY(ws_get(c, WS_TL1, (pk1 ? 12 : 16) * cap, &ve1));
-    MSF_TRY(ws_get(c, WS_TL2, (pk2 ? 12 : 16) * cap, &ve2));
+    MSF_TRY(ws_get(c, WS_TL2, (TL_L2_SOA ? 12 * cap + 8 : (pk2 ? 12 : 16) * cap), &ve2));
     MSF_TRY(ws_get(c, WS_TLSUB, 2 * cap + 8, &vsub));  // level-1 u8, then level-2 u16
     MSF_TRY(ws_get(c, WS_TLPLAN, 4 * (3 * (size_t)NC + 3), &vplan));
     MSF_TRY(ws_get(c, WS_T2, 4 * nt2, &vt2));
@@ -792,17 +821,18 @@ msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
     MSF_TRY(launch_bucket_hist(c, d_edges, d_w, m, n, tl.L1, NC, (uint32_t)n, (uint32_t)NC, epb,
                                nblk, wt, bh));
     MSF_TRY(scan_u32(c, bh, (uint32_t *)vbo, (int64_t)nh, &c->dcnt->count));
+    constexpr bool SOA = TL_L2_SOA != 0;
     if (pk1 && pk2)
-        return two_level_passes<true, true>(c, n, m, d_edges, d_w, wt, tl, epb, nblk, g2max, nt2,
-                                            otiles, cb, B, row_ptr, col, key, r_first);
+        return two_level_passes<true, true, SOA>(c, n, m, d_edges, d_w, wt, tl, epb, nblk, g2max,
+                                                 nt2, otiles, cb, B, row_ptr, col, key, r_first);
     if (pk2)
-        return two_level_passes<false, true>(c, n, m, d_edges, d_w, wt, tl, epb, nblk, g2max, nt2,
-                                             otiles, cb, B, row_ptr, col, key, r_first);
+        return two_level_passes<false, true, SOA>(c, n, m, d_edges, d_w, wt, tl, epb, nblk, g2max,
+                                                  nt2, otiles, cb, B, row_ptr, col, key, r_first);
     if (pk1)
-        return two_level_passes<true, false>(c, n, m, d_edges, d_w, wt, tl, epb, nblk, g2max, nt2,
-                                             otiles, cb, B, row_ptr, col, key, r_first);
-    return two_level_passes<false, false>(c, n, m, d_edges, d_w, wt, tl, epb, nblk, g2max, nt2,
-                                          otiles, cb, B, row_ptr, col, key, r_first);
+        return two_level_passes<true, false, SOA>(c, n, m, d_edges, d_w, wt, tl, epb, nblk, g2max,
+                                                  nt2, otiles, cb, B, row_ptr, col, key, r_first);
+    return two_level_passes<false, false, SOA>(c, n, m, d_edges, d_w, wt, tl, epb, nblk, g2max,
+                                               nt2, otiles, cb, B, row_ptr, col, key, r_first);
 }
 
 }  // namespace msf
