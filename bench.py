@@ -61,22 +61,18 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 PROFILE = os.path.join(ROOT, "profiles", "rmat_s22_solve.md")
+PROFILE_ML = os.path.join(ROOT, "profiles", "multilinear_rmat_s22_round1.md")
 # timed kernels: label -> (kernel name, sources its code comes from)
+# (the sources are the files holding the kernels' code; a committed counter
+# profile counts only while they are unchanged)
 KERNELS = {
-    "place": ("k_tl_place (two-level build, placement)",
-              ("kernels_build2.hip", "msf_internal.hpp", "wave.hpp")),
-    "sort": ("k_sort_chunks (run sort of the head sweep)",
-             ("kernels_heads.hip", "msf_internal.hpp", "wave.hpp")),
-    "part2": ("k_part_sub (two-level build, level-2 partition)",
-              ("kernels_build2.hip", "msf_internal.hpp", "wave.hpp")),
-    "part1": ("k_part_edges (two-level build, level-1 partition)",
-              ("kernels_build2.hip", "msf_internal.hpp", "wave.hpp")),
-    "sweep": ("k_sweep (multilinear + projection)",
-              ("kernels_sweep.hip", "msf_internal.hpp", "wave.hpp")),
-    "heads": ("k_heads + k_heads_rest (head sweep)",
-              ("kernels_heads.hip", "msf_internal.hpp", "wave.hpp")),
-    "build": ("adjacency build (two-level)",
-              ("kernels_build2.hip", "kernels_build.hip", "msf_internal.hpp", "wave.hpp")),
+    "place": ("k_tl_place (two-level build, placement)", ("kernels_build2.hip",)),
+    "sort": ("k_sort_chunks (run sort of the head sweep)", ("kernels_heads.hip",)),
+    "part2": ("k_part_sub (two-level build, level-2 partition)", ("kernels_build2.hip",)),
+    "part1": ("k_part_edges (two-level build, level-1 partition)", ("kernels_build2.hip",)),
+    "sweep": ("k_sweep (multilinear + projection)", ("kernels_sweep.hip",)),
+    "heads": ("k_heads + k_heads_rest (head sweep)", ("kernels_heads.hip",)),
+    "build": ("adjacency build (two-level)", ("kernels_build2.hip", "kernels_build.hip")),
 }
 
 
@@ -90,12 +86,12 @@ def source_hash(label):
     return h.hexdigest()
 
 
-def measured_traffic(label):
-    """HBM bytes per launch of the kernel `label` from the committed counter
+def measured_traffic(label, profile=None):
+    """HBM bytes per launch of the kernel `label` from a committed counter
     profile (calibrated FETCH_SIZE + WRITE_SIZE), or None when the profile
     holds none or was taken on different sources than the ones built here."""
     try:
-        with open(PROFILE) as fh:
+        with open(profile or PROFILE) as fh:
             lines = fh.read().splitlines()
     except OSError:
         return None
@@ -426,6 +422,7 @@ def bench_multilinear_round1(ctx, pkg, torch, n, e, w, wtype, reps=25):
             "min_ms": float(np.min(times)), "max_ms": float(np.max(times)),
             "bytes": b, "achieved": gb_s, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": gb_s / HBM_PEAK_GBS, "target_frac": 0.40,
+            "traffic": measured_traffic("sweep", PROFILE_ML),
             "gather_bytes_if_every_entry": 4.0 * nnz,
             "order_gather_ms": float(np.median(gtimes)),
             "call_frac": b / 1e9 / ((med + float(np.median(gtimes))) / 1e3) / HBM_PEAK_GBS,

@@ -714,9 +714,10 @@ msf_status msf_components(msf_ctx *ctx, const msf_graph *g, uint32_t *labels, in
     MSF_HIP(hipSetDevice(c->device));
     hipStream_t s = c->stream;
     msf_status rc;
-    if (kept_heads_eligible(c, g->a)) {
-        // the host-stepped rounds with the head sweep (as msf_solve takes
-        // them on such a graph), over a sorted copy of the graph's entries
+    if (kept_heads_eligible(c, g->a) || (int64_t)n > c->graph_rounds_max_n ||
+        c->graph_rounds == 0) {
+        // the host-stepped rounds over compacted root lists, with the head
+        // sweep where msf_solve would take it (the graph is only read)
         if ((rc = solve_start_kept(c, g->a, g->perm, labels))) return rc;
         while (!solve_done(c)) {
             MSF_HIP(hipEventSynchronize(c->ev[3]));

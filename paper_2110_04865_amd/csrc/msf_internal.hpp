@@ -513,11 +513,11 @@ msf_status decode_err(uint32_t err);
 msf_status solve_start(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
                        msf_wtype wt, int32_t *d_ids);
 // The same rounds on a kept graph's adjacency a (connected components,
-// section 2.4), with the head sweep over a copy of a's entries sorted into
-// the workspace (a itself is only read); at the end the parent vector,
-// every vertex at its tree's root, goes to labels (device uint32[n], through
-// perm when the graph has one).  kept_heads_eligible: whether a qualifies
-// for the head sweep (the same rule as msf_solve).
+// section 2.4): the head sweep where a qualifies (kept_heads_eligible, the
+// same rule as msf_solve; the run order goes to the workspace), else the
+// full sweep without filtering; a itself is only read.  At the end the
+// parent vector, every vertex at its tree's root, goes to labels (device
+// uint32[n], through perm when the graph has one).
 bool kept_heads_eligible(const Ctx *c, const Adj &a);
 msf_status solve_start_kept(Ctx *c, const Adj &a, const uint32_t *perm, uint32_t *labels);
 bool solve_ready(Ctx *c);

@@ -214,10 +214,6 @@ msf_status solve_start_kept(Ctx *c, const Adj &a, const uint32_t *perm, uint32_t
     SolveState &S = c->ss;
     S = SolveState{};
     c->ml_pending = false;
-    if (a.sl.S != 1) {
-        set_error("internal error: the head sweep needs one column slice");
-        return MSF_EINVAL;
-    }
     S.n = a.n;
     S.m = a.m;
     S.edges = a.edges;
@@ -225,14 +221,18 @@ msf_status solve_start_kept(Ctx *c, const Adj &a, const uint32_t *perm, uint32_t
     S.kept = true;
     S.labels = labels;
     S.perm = perm;
-    MSF_TRY(get_solve_bufs(c, S.n, S.m, 1, &S.b, false));
-    MSF_TRY(get_runs_bufs(c, S.n, S.m, &S.runs));
-    S.heads = true;
-    S.a = a;  // only read: the run order goes to the workspace
+    MSF_TRY(get_solve_bufs(c, S.n, S.m, a.sl.S, &S.b, false));
+    // the head sweep where msf_solve would take it, else the full sweep
+    // without filtering; the graph is only read (the run order goes to the
+    // workspace)
+    S.heads = kept_heads_eligible(c, a);
+    if (S.heads) MSF_TRY(get_runs_bufs(c, S.n, S.m, &S.runs));
+    S.a = a;
     MSF_HIP(hipEventRecord(c->ev[0], c->stream));
     zero_counters(c);
     c->pass_done = 0;
-    MSF_TRY(build_runs(c, S.runs, a.row_ptr, S.n, a.col, a.key, a.nnz, edge_bits(S.m)));
+    if (S.heads)
+        MSF_TRY(build_runs(c, S.runs, a.row_ptr, S.n, a.col, a.key, a.nnz, edge_bits(S.m)));
     MSF_TRY(enqueue_round_state(c));
     return end_step(c, 2);
 }
@@ -252,6 +252,9 @@ static msf_status enqueue_round(Ctx *c)
     hipStream_t s = c->stream;
     S.compact = false;
     if (S.heads) S.compact = false;  // the head sweep passes internal entries over by itself
+    // a kept graph's rows all stay, so every vertex's parent is updated to
+    // the end (its final root is its label)
+    else if (S.kept) S.compact = false;
     else if (c->filter_mode == 2) S.compact = true;
     else if (c->filter_mode == 1) S.compact = S.live_frac < c->filter_threshold;
     const int ev_k = S.rounds < 64 ? S.rounds : -1;

@@ -818,15 +818,19 @@ def test_components_match_oracle(ctx, pkg):
         "loops and parallel edges": (5, np.array([[0, 0], [1, 2], [2, 1], [3, 3], [1, 2]],
                                                  np.int32), np.array([1, 1, 1, 1, 1], np.uint32)),
     }
-    # the default choice, the head-sweep rounds over a sorted copy for every
-    # graph (MSF_HEADS=2) and the device-driven rounds for every graph
-    # (MSF_HEADS=0); kept graphs in degree order and in the caller's order
-    for heads, order in (("1", "1"), ("2", "1"), ("0", "1"), ("2", "0")):
-        with env_set(MSF_HEADS=heads, MSF_GRAPH_ORDER=order):
+    # the default choice; the solve's rounds with the head sweep for every
+    # graph (MSF_HEADS=2); the device-driven rounds for every graph up to
+    # 2^20 vertices (MSF_HEADS=0); the solve's rounds with the full sweep
+    # (MSF_HEADS=0, MSF_GRAPH_ROUNDS=0); kept graphs in degree order and in
+    # the caller's order
+    for heads, order, gr in (("1", "1", "2"), ("2", "1", "2"), ("0", "1", "2"), ("2", "0", "2"),
+                             ("0", "1", "0"), ("0", "0", "0")):
+        with env_set(MSF_HEADS=heads, MSF_GRAPH_ORDER=order, MSF_GRAPH_ROUNDS=gr):
             c = pkg.Context(0)
         try:
             for label, (n, e, w) in cases.items():
-                check_components(c, pkg, n, e, w, f"heads={heads} order={order} {label}")
+                check_components(c, pkg, n, e, w,
+                                 f"heads={heads} order={order} graph_rounds={gr} {label}")
         finally:
             c.close()
 
