@@ -359,56 +359,76 @@ msf_status msf_graph_create(msf_ctx *ctx, int32_t n, int64_t m, const int32_t *e
         }
     }
     const hipMemcpyKind kind = mem == MSF_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-    const bool order = c->graph_order != 0 && n > 0;
     if (m > 0) {
-        // with the degree order the caller's edges are renumbered into the
-        // graph's copy; host edges go through the workspace first
-        void *src = (void *)edges;
-        hipError_t e1 = hipSuccess;
-        if (order && mem == MSF_MEM_HOST) {
-            if ((rc = ws_get(c, WS_EDGES, 8 * (size_t)m, &src))) {
-                msf_graph_destroy(g);
-                return rc;
-            }
-            e1 = hipMemcpyAsync(src, edges, 8 * (size_t)m, hipMemcpyHostToDevice, c->stream);
-        } else if (!order) {
-            e1 = hipMemcpyAsync(g->bufs[0], edges, 8 * (size_t)m, kind, c->stream);
-        }
+        hipError_t e1 = hipMemcpyAsync(g->bufs[0], edges, 8 * (size_t)m, kind, c->stream);
         hipError_t e2 = hipMemcpyAsync(g->bufs[1], weights, 4 * (size_t)m, kind, c->stream);
         if (e1 != hipSuccess || e2 != hipSuccess) {
             msf_graph_destroy(g);
             return hip_fail(e1 != hipSuccess ? e1 : e2, "hipMemcpyAsync");
         }
-        if (order) {
-            void *vdeg, *vtab, *vinv;
-            if (hipMalloc(&g->perm, 4 * nn) != hipSuccess) {
-                (void)hipGetLastError();
-                g->perm = nullptr;
-                msf_graph_destroy(g);
-                set_error("device allocation failed");
-                return MSF_ENOMEM;
-            }
-            if ((rc = ws_get(c, WS_DEG, 4 * nn, &vdeg)) ||
-                (rc = ws_get(c, WS_T2, 4 * relabel_table_words(n), &vtab)) ||
-                (rc = ws_get(c, WS_Q2, 4 * nn, &vinv)) ||
-                (rc = relabel_by_degree(c, n, m, (const int32_t *)src, (uint32_t *)vdeg,
-                                        (uint32_t *)vtab, g->perm, (uint32_t *)vinv,
-                                        (int32_t *)g->bufs[0]))) {
-                msf_graph_destroy(g);
-                return rc;
-            }
-        }
+    }
+    // the degree order (one slice): built in the caller's order into the
+    // workspace, then renumbered into the graph's buffers
+    const bool order = c->graph_order != 0 && n > 0 && m > 0 && slices == 1;
+    void *vrp0 = nullptr, *vcol0 = nullptr, *vkey0 = nullptr, *vcrow0 = nullptr;
+    if (order && ((rc = ws_get(c, WS_ROWPTR, 4 * (nn + 1), &vrp0)) ||
+                  (rc = ws_get(c, WS_COL, sizes[3], &vcol0)) ||
+                  (rc = ws_get(c, WS_KEY, sizes[4], &vkey0)) ||
+                  (rc = ws_get(c, WS_CHUNKROW, sizes[5], &vcrow0)))) {
+        msf_graph_destroy(g);
+        return rc;
     }
     zero_counters(c);
-    rc = build_adjacency(c, n, m, (const int32_t *)g->bufs[0], g->bufs[1], wt, slices, &g->a,
-                         (uint32_t *)g->bufs[2], (uint32_t *)g->bufs[3], (uint64_t *)g->bufs[4],
-                         (uint32_t *)g->bufs[5]);
-    if (rc == MSF_OK && g->a.sl.S == 1) launch_long_entries(c->stream, g->a.row_ptr, n, c->dcnt);
+    if (order)
+        rc = build_adjacency(c, n, m, (const int32_t *)g->bufs[0], g->bufs[1], wt, 1, &g->a,
+                             (uint32_t *)vrp0, (uint32_t *)vcol0, (uint64_t *)vkey0,
+                             (uint32_t *)vcrow0);
+    else
+        rc = build_adjacency(c, n, m, (const int32_t *)g->bufs[0], g->bufs[1], wt, slices, &g->a,
+                             (uint32_t *)g->bufs[2], (uint32_t *)g->bufs[3],
+                             (uint64_t *)g->bufs[4], (uint32_t *)g->bufs[5]);
     if (rc == MSF_OK) rc = read_counters(c);
     if (rc == MSF_OK) rc = decode_err(c->hcnt->err);
     if (rc) {
         msf_graph_destroy(g);
         return rc;
+    }
+    if (order) {
+        void *vdeg, *vtab, *vinv, *vseg, *vsr;
+        const int64_t nnz = (int64_t)c->hcnt->sstart[1] - (int64_t)c->hcnt->sstart[0];
+        if (hipMalloc(&g->perm, 4 * nn) != hipSuccess) {
+            (void)hipGetLastError();
+            g->perm = nullptr;
+            msf_graph_destroy(g);
+            set_error("device allocation failed");
+            return MSF_ENOMEM;
+        }
+        if ((rc = ws_get(c, WS_DEG, 8 * nn, &vdeg)) ||
+            (rc = ws_get(c, WS_T2, 4 * relabel_table_words(n), &vtab)) ||
+            (rc = ws_get(c, WS_Q2, 4 * nn, &vinv)) ||
+            (rc = ws_get(c, WS_RUNROW, 4 * (2 * nn + 1), &vseg)) ||
+            (rc = ws_get(c, WS_RUNS, 4 * relabel_segments_cap(n, nnz), &vsr)) ||
+            (rc = relabel_csr_by_degree(c, n, (const uint32_t *)vrp0, (const uint32_t *)vcol0,
+                                        (const uint64_t *)vkey0, (uint32_t *)vdeg,
+                                        (uint32_t *)vtab, g->perm, (uint32_t *)vinv,
+                                        (uint32_t *)vseg, (uint32_t *)vsr, (uint32_t *)g->bufs[2],
+                                        (uint32_t *)g->bufs[3], (uint64_t *)g->bufs[4]))) {
+            msf_graph_destroy(g);
+            return rc;
+        }
+        launch_relabel_edges(c->stream, (int32_t *)g->bufs[0], m, (const uint32_t *)vinv);
+        g->a.row_ptr = (uint32_t *)g->bufs[2];
+        g->a.col = (uint32_t *)g->bufs[3];
+        g->a.key = (uint64_t *)g->bufs[4];
+        g->a.chunk_row = (uint32_t *)g->bufs[5];
+        g->a.edges = (const int32_t *)g->bufs[0];
+    }
+    if (g->a.sl.S == 1) {
+        launch_long_entries(c->stream, g->a.row_ptr, n, c->dcnt);
+        if ((rc = read_counters(c))) {
+            msf_graph_destroy(g);
+            return rc;
+        }
     }
     for (int q = 0; q <= g->a.sl.S; ++q) g->a.sl.sstart[q] = c->hcnt->sstart[q];
     set_chunks(&g->a);

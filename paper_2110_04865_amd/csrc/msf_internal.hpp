@@ -484,13 +484,19 @@ void launch_cc_apply(hipStream_t s, const uint32_t *h, int32_t n, uint32_t *p);
 
 void zero_counters(Ctx *c);
 msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc);
-// Vertex order of a kept graph by decreasing degree class (relabel.hip):
-// perm[new] = old, inv[old] = new, edges_out = the edges renumbered.  deg
-// holds n words, tab relabel_table_words(n).  MSF_EINVAL for an endpoint
-// outside [0, n) (nothing is renumbered then).
-msf_status relabel_by_degree(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, uint32_t *deg,
-                             uint32_t *tab, uint32_t *perm, uint32_t *inv, int32_t *edges_out);
+// Vertex order of a kept graph by decreasing degree class (relabel.hip),
+// from its one-slice adjacency built in the caller's order (rp0, col0,
+// key0): perm[new] = old, inv[old] = new, and the adjacency renumbered into
+// rp (n + 1 words), col, key.  deg holds 2n words, tab
+// relabel_table_words(n), seg 2n + 1, seg_row relabel_segments_cap(n, nnz).
+msf_status relabel_csr_by_degree(Ctx *c, int32_t n, const uint32_t *rp0, const uint32_t *col0,
+                                 const uint64_t *key0, uint32_t *deg, uint32_t *tab,
+                                 uint32_t *perm, uint32_t *inv, uint32_t *seg,
+                                 uint32_t *seg_row, uint32_t *rp, uint32_t *col, uint64_t *key);
 size_t relabel_table_words(int32_t n);
+size_t relabel_segments_cap(int32_t n, int64_t nnz);
+// edges[e] <- (inv[u], inv[v]) in place
+void launch_relabel_edges(hipStream_t s, int32_t *edges, int64_t m, const uint32_t *inv);
 // q[i] = p[perm[i]] (a caller's parent vector in the graph's order)
 void launch_relabel_gather(hipStream_t s, const uint32_t *p, const uint32_t *perm, int32_t n,
                            uint32_t *q);

@@ -12,6 +12,12 @@
 // class (a stable counting sort, so the order is deterministic).  In R-MAT
 // graphs a few percent of the vertices hold most edge ends; with this order
 // their parents fit in each XCD's L2.
+//
+// The graph is first built in the caller's order (the degrees are its row
+// lengths, with no atomics); its rows are then copied to their new places,
+// a wave per segment of at most RL_SEG entries, columns renumbered.  Built
+// directly in the new order, the hub rows would crowd a few placement
+// buckets and serialise the build.
 #include <algorithm>
 
 #include "msf_internal.hpp"
@@ -28,26 +34,6 @@ __device__ __forceinline__ uint32_t rl_slot(uint32_t deg)
 {
     // slot 0 holds the largest degrees
     return (uint32_t)(RL_CLASSES - 1) - (deg ? 32u - (uint32_t)__builtin_clz(deg) : 0u);
-}
-
-// deg[v] += 1 for each end of every edge that is not a loop; endpoints
-// outside [0, n) raise ERR_ENDPOINT and are skipped.
-__global__ void k_rl_degree(const int32_t *__restrict__ edges, int64_t m, int32_t n,
-                            uint32_t *__restrict__ deg, Counters *cnt)
-{
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    bool bad = false;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
-        const int32_t u = edges[2 * e], v = edges[2 * e + 1];
-        if (u < 0 || v < 0 || u >= n || v >= n) {
-            bad = true;
-            continue;
-        }
-        if (u == v) continue;
-        atomicAdd(deg + u, 1u);
-        atomicAdd(deg + v, 1u);
-    }
-    if (__ballot(bad) && __lane_id() == 0) atomicOr(&cnt->err, ERR_ENDPOINT);
 }
 
 // Per tile (one wave): vertices of each class, into tab[slot * ntiles + tile].
@@ -100,9 +86,10 @@ __global__ __launch_bounds__(64) void k_rl_place(const uint32_t *__restrict__ de
     }
 }
 
-// edges_out = inv applied to both ends (endpoints already checked).
-__global__ void k_rl_edges(const int32_t *__restrict__ edges, int64_t m,
-                           const uint32_t *__restrict__ inv, int32_t *__restrict__ out)
+// out = inv applied to both ends of every edge (endpoints already checked;
+// out may be edges: each thread reads its edge before writing it).
+__global__ void k_rl_edges(const int32_t *edges, int64_t m, const uint32_t *__restrict__ inv,
+                           int32_t *out)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
@@ -133,29 +120,109 @@ __global__ void k_rl_labels(const uint32_t *__restrict__ q, const uint32_t *__re
 
 unsigned grid_of(int64_t n) { return (unsigned)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 16384); }
 
+// deg[v] = stored entries of row v of a one-slice adjacency.
+__global__ void k_rl_deg_rp(const uint32_t *__restrict__ rp, int32_t n, uint32_t *__restrict__ deg)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+        deg[v] = rp[v + 1] - rp[v];
+}
+
+// Entries a wave copies per segment of a renumbered row.
+constexpr uint32_t RL_SEG = 256;
+
+// nd[k] = entries of new row k (old row perm[k]), sc[k] = its segments.
+__global__ void k_rl_newdeg(const uint32_t *__restrict__ deg, const uint32_t *__restrict__ perm,
+                            int32_t n, uint32_t *__restrict__ nd, uint32_t *__restrict__ sc)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const uint32_t d = deg[perm[k]];
+        nd[k] = d;
+        sc[k] = (d + RL_SEG - 1u) / RL_SEG;
+    }
+}
+
+// seg_row[s] = the new row segment s belongs to.
+__global__ void k_rl_segrows(const uint32_t *__restrict__ so, int32_t n,
+                             uint32_t *__restrict__ seg_row)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+        for (uint32_t s = so[k]; s < so[k + 1]; ++s) seg_row[s] = (uint32_t)k;
+}
+
+// One wave per segment (grid-stride up to the segment count *ns): the
+// segment's entries of old row perm[k] go to new row k in the same order,
+// columns renumbered.
+__global__ __launch_bounds__(256) void k_rl_permute(
+    const uint32_t *__restrict__ rp0, const uint32_t *__restrict__ col0,
+    const uint64_t *__restrict__ key0, const uint32_t *__restrict__ perm,
+    const uint32_t *__restrict__ inv, const uint32_t *__restrict__ rp,
+    const uint32_t *__restrict__ so, const uint32_t *__restrict__ seg_row,
+    const uint32_t *__restrict__ ns, uint32_t *__restrict__ col, uint64_t *__restrict__ key)
+{
+    const uint32_t lane = __lane_id();
+    const uint32_t total = *ns;
+    const uint32_t nw = gridDim.x * (blockDim.x / 64u);
+    for (uint32_t s = blockIdx.x * (blockDim.x / 64u) + (threadIdx.x >> 6); s < total; s += nw) {
+        const uint32_t k = seg_row[s];
+        const uint32_t j0 = (s - so[k]) * RL_SEG;
+        const uint32_t ob = rp0[perm[k]], nb = rp[k], len = rp[k + 1] - nb;
+        const uint32_t je = j0 + RL_SEG < len ? j0 + RL_SEG : len;
+        for (uint32_t j = j0 + lane; j < je; j += 64u) {
+            col[nb + j] = inv[col0[ob + j]];
+            key[nb + j] = key0[ob + j];
+        }
+    }
+}
+
 }  // namespace
 
-msf_status relabel_by_degree(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, uint32_t *deg,
-                             uint32_t *tab, uint32_t *perm, uint32_t *inv, int32_t *edges_out)
+size_t relabel_segments_cap(int32_t n, int64_t nnz)
+{
+    return (size_t)(nnz > 0 ? nnz : 0) / RL_SEG + (size_t)(n > 0 ? n : 0) + 1;
+}
+
+// Stable counting sort of the vertices by degree class: perm, inv.
+static msf_status order_by_degree(Ctx *c, int32_t n, const uint32_t *deg, uint32_t *tab,
+                                  uint32_t *perm, uint32_t *inv)
 {
     hipStream_t s = c->stream;
     const uint32_t ntiles = (uint32_t)(((int64_t)n + RL_TILE - 1) / RL_TILE);
-    launch_fill_u32(s, deg, 0u, (size_t)n);
-    launch_fill_u32(s, &c->dcnt->err, 0u, 1);
-    if (m > 0) k_rl_degree<<<grid_of(m), 256, 0, s>>>(d_edges, m, n, deg, c->dcnt);
-    // the endpoints index inv below: stop here if any is out of range
-    MSF_TRY(read_counters(c));
-    MSF_TRY(decode_err(c->hcnt->err));
-    if (n > 0) {
-        k_rl_count<<<ntiles, 64, 0, s>>>(deg, n, ntiles, tab);
-        MSF_TRY(scan_u32(c, tab, tab + (size_t)RL_CLASSES * ntiles + 1,
-                         (int64_t)RL_CLASSES * ntiles, nullptr));
-        k_rl_place<<<ntiles, 64, 0, s>>>(deg, n, ntiles, tab + (size_t)RL_CLASSES * ntiles + 1,
-                                         perm, inv);
-    }
-    if (m > 0) k_rl_edges<<<grid_of(m), 256, 0, s>>>(d_edges, m, inv, edges_out);
+    if (n <= 0) return MSF_OK;
+    k_rl_count<<<ntiles, 64, 0, s>>>(deg, n, ntiles, tab);
+    MSF_TRY(scan_u32(c, tab, tab + (size_t)RL_CLASSES * ntiles + 1, (int64_t)RL_CLASSES * ntiles,
+                     nullptr));
+    k_rl_place<<<ntiles, 64, 0, s>>>(deg, n, ntiles, tab + (size_t)RL_CLASSES * ntiles + 1, perm,
+                                     inv);
     MSF_HIP(hipGetLastError());
     return MSF_OK;
+}
+
+msf_status relabel_csr_by_degree(Ctx *c, int32_t n, const uint32_t *rp0, const uint32_t *col0,
+                                 const uint64_t *key0, uint32_t *deg, uint32_t *tab,
+                                 uint32_t *perm, uint32_t *inv, uint32_t *seg,
+                                 uint32_t *seg_row, uint32_t *rp, uint32_t *col, uint64_t *key)
+{
+    hipStream_t s = c->stream;
+    if (n <= 0) return MSF_OK;
+    k_rl_deg_rp<<<grid_of(n), 256, 0, s>>>(rp0, n, deg);
+    MSF_TRY(order_by_degree(c, n, deg, tab, perm, inv));
+    uint32_t *nd = deg + n, *sc = seg, *so = seg + n;
+    k_rl_newdeg<<<grid_of(n), 256, 0, s>>>(deg, perm, n, nd, sc);
+    MSF_TRY(scan_u32(c, nd, rp, (int64_t)n, nullptr));  // rp[n]: the total
+    MSF_TRY(scan_u32(c, sc, so, (int64_t)n, nullptr));  // so[n]: the segment count
+    k_rl_segrows<<<grid_of(n), 256, 0, s>>>(so, n, seg_row);
+    k_rl_permute<<<8192, 256, 0, s>>>(rp0, col0, key0, perm, inv, rp, so, seg_row, so + n, col,
+                                      key);
+    MSF_HIP(hipGetLastError());
+    return MSF_OK;
+}
+
+void launch_relabel_edges(hipStream_t s, int32_t *edges, int64_t m, const uint32_t *inv)
+{
+    if (m > 0) k_rl_edges<<<grid_of(m), 256, 0, s>>>(edges, m, inv, edges);
 }
 
 size_t relabel_table_words(int32_t n)
