@@ -207,9 +207,10 @@ template <int WT, bool PK1>
 __global__ __launch_bounds__(TL_NT) void k_part_edges(
     const int32_t *__restrict__ edges, const void *__restrict__ w, int64_t m, int32_t n, int L1,
     int NC, int64_t epb, uint32_t nblk, const uint32_t *__restrict__ bo1, int L2, uint32_t cb,
-    RecT<PK1> *__restrict__ o1, uint8_t *__restrict__ sub1)
+    RecT<PK1> *__restrict__ o1, uint8_t *__restrict__ sub1, Counters *ctr)
 {
     const uint32_t smask = (1u << (L1 - L2)) - 1u;
+    bool nan = false;  // a NaN weight among the block's edges
     __shared__ uint4 s_ent[TL_TILE];
     __shared__ uint32_t s_run[TL_MAX_NC], s_pos[TL_MAX_NC * TP_C];  // s_pos: [bucket][copy]
     __shared__ uint32_t s_scr[TL_NT / 64 + 1];
@@ -246,6 +247,7 @@ __global__ __launch_bounds__(TL_NT) void k_part_edges(
             ew[k] = in ? pw[k] : 0u;
             ok[k] = in && (uint32_t)eu[k] < (uint32_t)n && (uint32_t)ev[k] < (uint32_t)n &&
                     eu[k] != ev[k];
+            if (WT == MSF_W_F32) nan |= in && (ew[k] & 0x7FFFFFFFu) > 0x7F800000u;
         }
 #pragma unroll
         for (int k = 0; k < TL_EP; ++k) {
@@ -295,6 +297,7 @@ __global__ __launch_bounds__(TL_NT) void k_part_edges(
         }
         __syncthreads();
     }
+    if (WT == MSF_W_F32 && __ballot(nan) && __lane_id() == 0) atomicOr(&ctr->err, ERR_NAN);
 }
 
 // P: coarse bucket starts cs[0..NC] (cs[NC] = total), level-2 workgroups
@@ -725,11 +728,11 @@ msf_status two_level_passes(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges
     // B1
     MSF_HIP(hipEventRecord(c->kev[6], s));
     if (wt == MSF_W_F32)
-        k_part_edges<MSF_W_F32, PK1><<<nblk, TL_NT, 0, s>>>(d_edges, d_w, m, n, tl.L1, NC, epb,
-                                                            nblk, B.bo, tl.L2, cb, e1, B.sub1);
+        k_part_edges<MSF_W_F32, PK1><<<nblk, TL_NT, 0, s>>>(
+            d_edges, d_w, m, n, tl.L1, NC, epb, nblk, B.bo, tl.L2, cb, e1, B.sub1, c->dcnt);
     else
-        k_part_edges<MSF_W_U32, PK1><<<nblk, TL_NT, 0, s>>>(d_edges, d_w, m, n, tl.L1, NC, epb,
-                                                            nblk, B.bo, tl.L2, cb, e1, B.sub1);
+        k_part_edges<MSF_W_U32, PK1><<<nblk, TL_NT, 0, s>>>(
+            d_edges, d_w, m, n, tl.L1, NC, epb, nblk, B.bo, tl.L2, cb, e1, B.sub1, c->dcnt);
     MSF_HIP(hipEventRecord(c->kev[7], s));
     // P, A2, scan, B2
     k_tl_plan<<<1, 1024, 0, s>>>(B.bo, nblk, NC, B.cs, B.nb2, B.P);
@@ -817,9 +820,10 @@ msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
     B.e2 = ve2;
     B.sub1 = (uint8_t *)vsub;
 
-    // A1 (coarse histogram; also validates endpoints and weights) + scan
+    // A1 (coarse histogram; also validates endpoints; the weights are
+    // validated by B1, which reads them anyway) + scan
     MSF_TRY(launch_bucket_hist(c, d_edges, d_w, m, n, tl.L1, NC, (uint32_t)n, (uint32_t)NC, epb,
-                               nblk, wt, bh));
+                               nblk, wt, bh, false));
     MSF_TRY(scan_u32(c, bh, (uint32_t *)vbo, (int64_t)nh, &c->dcnt->count));
     constexpr bool SOA = TL_L2_SOA != 0;
     if (pk1 && pk2)

@@ -49,20 +49,15 @@ static void prep_lookback(hipStream_t s, uint64_t *status, uint32_t tiles, Count
 
 // ----------------------------------------------------------- root list --
 // R = vertices with at least one stored entry (isolated vertices are
-// finished roots from the start).
+// finished roots from the start).  Counted per tile, scanned, then written
+// (a launch of this size has all its tiles resident at once, where a ticket
+// and a look-back per tile would chain them: 37 us for 1024 tiles).
 
-__global__ __launch_bounds__(CT_NT) void k_init_roots(const uint32_t *__restrict__ row_ptr,
-                                                      int32_t n, int S, uint32_t *__restrict__ R,
-                                                      uint64_t *status, Counters *cnt)
+// Active vertices of this thread's CT_IT items, as a mask.
+__device__ __forceinline__ uint32_t roots_mask(const uint32_t *__restrict__ row_ptr, int32_t n,
+                                               int S, int64_t base)
 {
-    __shared__ uint32_t s_tile;
-    __shared__ uint64_t s_lds[CT_NT / 64 + 1];
-    __shared__ uint64_t s_pre;
-    if (threadIdx.x == 0) s_tile = atomicAdd(&cnt->ticket, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const int64_t base = (int64_t)tile * CT_TILE + (int64_t)threadIdx.x * CT_IT;
-    uint32_t act = 0, c = 0;
+    uint32_t act = 0;
     for (int q = 0; q < S; ++q) {
         const uint32_t *rp = row_ptr + (size_t)q * ((size_t)n + 1);
         uint32_t prev = (base <= n) ? rp[base] : 0u;
@@ -73,23 +68,53 @@ __global__ __launch_bounds__(CT_NT) void k_init_roots(const uint32_t *__restrict
             prev = nx;
         }
     }
-    c = __popc(act);
-    uint32_t oa, ob;
-    uint64_t tot;
-    tile_offsets2<CT_NT>(tile, c, 0u, status, s_lds, &s_pre, &oa, &ob, &tot);
-#pragma unroll
-    for (int k = 0; k < CT_IT; ++k)
-        if (act & (1u << k)) R[oa++] = (uint32_t)(base + k);
-    if (tile == gridDim.x - 1 && threadIdx.x == 0) cnt->nR = (uint32_t)(tot >> 31);
+    return act;
 }
 
-void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S, uint32_t *R,
-                       uint64_t *status, Counters *dcnt)
+__global__ __launch_bounds__(CT_NT) void k_roots_count(const uint32_t *__restrict__ row_ptr,
+                                                       int32_t n, int S,
+                                                       uint32_t *__restrict__ tcnt)
+{
+    __shared__ uint32_t s_lds[CT_NT / 64 + 1];
+    const int64_t base = (int64_t)blockIdx.x * CT_TILE + (int64_t)threadIdx.x * CT_IT;
+    const uint32_t c = (uint32_t)__popc(roots_mask(row_ptr, n, S, base));
+    const uint32_t tot = block_sum<CT_NT>(c, s_lds);
+    if (threadIdx.x == 0) tcnt[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(CT_NT) void k_roots_write(const uint32_t *__restrict__ row_ptr,
+                                                       int32_t n, int S,
+                                                       const uint32_t *__restrict__ toff,
+                                                       uint32_t *__restrict__ R)
+{
+    __shared__ uint32_t s_lds[CT_NT / 64 + 1];
+    const int64_t base = (int64_t)blockIdx.x * CT_TILE + (int64_t)threadIdx.x * CT_IT;
+    const uint32_t act = roots_mask(row_ptr, n, S, base);
+    uint32_t tot;
+    uint32_t o = toff[blockIdx.x] + block_excl_sum<CT_NT>((uint32_t)__popc(act), s_lds, &tot);
+#pragma unroll
+    for (int k = 0; k < CT_IT; ++k)
+        if (act & (1u << k)) R[o++] = (uint32_t)(base + k);
+}
+
+msf_status launch_init_roots(Ctx *c, const uint32_t *row_ptr, int32_t n, int S, uint32_t *R,
+                             uint64_t *status)
 {
     const uint32_t tiles = ct_tiles((uint64_t)n);
-    if (!tiles) return;
-    prep_lookback(s, status, tiles, dcnt);
-    k_init_roots<<<tiles, CT_NT, 0, s>>>(row_ptr, n, S, R, status, dcnt);
+    hipStream_t s = c->stream;
+    if (!tiles) {
+        launch_fill_u32(s, &c->dcnt->nR, 0u, 1);
+        return MSF_OK;
+    }
+    // per-tile counts and their scan in the status buffer (8 bytes per
+    // tile and one more)
+    uint32_t *tcnt = reinterpret_cast<uint32_t *>(status);
+    uint32_t *toff = tcnt + tiles;
+    k_roots_count<<<tiles, CT_NT, 0, s>>>(row_ptr, n, S, tcnt);
+    MSF_TRY(scan_u32(c, tcnt, toff, (int64_t)tiles, &c->dcnt->nR));
+    k_roots_write<<<tiles, CT_NT, 0, s>>>(row_ptr, n, S, toff, R);
+    MSF_HIP(hipGetLastError());
+    return MSF_OK;
 }
 
 // ---------------------------------------------------------------- hook --

@@ -104,7 +104,7 @@ enum Slot {
     WS_BH, WS_BHOFF, WS_BRLO, WS_BCOL, WS_BKEY, WS_CHUNKINFO,
     WS_TL1, WS_TL2, WS_TLSUB, WS_TLORDER, WS_TLPLAN, WS_T2, WS_T2OFF, WS_FSTART,
     WS_RUNCHUNK, WS_RUNROW, WS_RUNS, WS_RUNPERM, WS_PAIR,
-    WS_PORDER, WS_PCTL, WS_PSCRATCH,
+    WS_PORDER, WS_PCTL, WS_PSCRATCH, WS_SCAN,
     WS_COUNT
 };
 
@@ -326,7 +326,8 @@ msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
 // bucket-major into bh[nb * nblk]; validates endpoints and weights.
 msf_status launch_bucket_hist(Ctx *c, const int32_t *d_edges, const void *d_w, int64_t m,
                               int32_t n, int lb, int nb, uint32_t slice_w, uint32_t nbr,
-                              int64_t epb, uint32_t nblk, msf_wtype wt, uint32_t *bh);
+                              int64_t epb, uint32_t nblk, msf_wtype wt, uint32_t *bh,
+                              bool check_w = true);
 
 // Adjacency build (section 2 adjacency matrix, both directions).
 // Fills row_ptr[n+1], col/key[nnz] (capacity 2m) and *a; the number of
@@ -384,12 +385,13 @@ void launch_sweep_compact(hipStream_t s, const Adj &a, const uint32_t *p, uint64
                           bool read_filter = true);
 size_t chunk_info_words(uint32_t nchunks);
 
-// Round kernels.  `status` is a look-back status array (>= tiles entries);
+// Round kernels.  `status` is a look-back status array (>= tiles entries;
+// the root list uses tiles + 1 entries as scratch for its per-tile counts);
 // `part` holds per-block partials (>= 4096 u32, chase_part_bytes() or
 // output_part_bytes(m)).
 uint32_t compaction_tiles(uint64_t n);
-void launch_init_roots(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S, uint32_t *R,
-                       uint64_t *status, Counters *dcnt);
+msf_status launch_init_roots(Ctx *c, const uint32_t *row_ptr, int32_t n, int S, uint32_t *R,
+                             uint64_t *status);
 // hwk[i]: the weight key (high word of the edge key) of root i's hook;
 // identity: p is the identity (round 1), so endpoints need no lookup; with
 // row_ptr, col and run_perm (a one-slice adjacency whose 64-entry chunks

@@ -189,7 +189,7 @@ static msf_status enqueue_round_state(Ctx *c)
     launch_iota_u32(s, S.b.h, (size_t)S.n);
     if (!S.first_done) launch_fill_u64(s, S.b.r, KEY_INF, (size_t)S.n);
     launch_fill_u32(s, reinterpret_cast<uint32_t *>(S.b.flags), 0u, ((size_t)S.m + 3) / 4);
-    launch_init_roots(s, S.a.row_ptr, S.n, S.a.sl.S, S.b.R[0], S.b.status, c->dcnt);
+    MSF_TRY(launch_init_roots(c, S.a.row_ptr, S.n, S.a.sl.S, S.b.R[0], S.b.status));
     return MSF_OK;
 }
 
