@@ -59,7 +59,10 @@ constexpr uint32_t RUN_LONG = 0x80000000u;
 
 
 // v from lane (lane ^ J): DPP quad permutations for 1 and 2, swizzles
-// within 32 lanes for 4..16, a permute for 32.
+// within 32 lanes for 4..16, a permute for 32.  The sort below is bound by
+// vector issue and the LDS crossbar together: swizzles for 1 and 2 (0.58 ->
+// 0.61 ms), a DPP row rotation for 8 (even), two DPP moves for 4 or the
+// permlane16/32 swaps for 16 and 32 (0.71-0.79 ms) all measured no better.
 template <int J>
 __device__ __forceinline__ uint32_t xor_move(uint32_t v)
 {
@@ -238,15 +241,16 @@ __global__ __launch_bounds__(256) void k_runs_write(const uint32_t *__restrict__
 // Order every 64-entry chunk by (run, key) with a bitonic network over the
 // lanes (one wave per chunk; keys are distinct within a row, and runs keep
 // their places) carrying each entry's chunk offset, write the order to
-// perm and store each run's head (its smallest key, and its column, read at
-// the head's own position) into its descriptor.  Reads the keys (8 bytes
-// per entry) and writes one byte per entry.  The chunk's runs are cfirst[c] .. cfirst[c + 1] - 1 (the
+// perm and store each run's head (its smallest key and its column) into its
+// descriptor.  Reads the keys and columns (12 bytes per entry) and writes one
+// byte per entry.  The chunk's runs are cfirst[c] .. cfirst[c + 1] - 1 (the
 // last chunk ends at *nruns); their starts are ORed across the lanes.  With
 // PACKED (edge ids of at most 26 bits) the sort key is one 64-bit word: run
 // index inside the chunk, weight key, edge id.
-// Chunks one wave orders: their loads (keys, first runs, then the runs'
-// starts) are all issued before the first network runs, so the chains of
-// dependent loads of different chunks overlap.
+// Chunks one wave orders: their loads (keys, columns, first runs, then the
+// runs' starts) are all issued before the first network runs, so the chains
+// of dependent loads of different chunks overlap; a run head's column then
+// comes from the lane that loaded it, not from a load after the network.
 #ifndef SORT_CHUNKS_PER_WAVE
 #define SORT_CHUNKS_PER_WAVE 8
 #endif
@@ -268,12 +272,13 @@ __global__ __launch_bounds__(256) void k_sort_chunks(const uint32_t *__restrict_
     if (c0 >= nch) return;  // whole waves
     const uint32_t total = *nruns;
     uint64_t kk[SORT_CH];
-    uint32_t r0[SORT_CH], r1[SORT_CH], rc[SORT_CH];
+    uint32_t cl[SORT_CH], r0[SORT_CH], r1[SORT_CH], rc[SORT_CH];
 #pragma unroll
     for (int t = 0; t < SORT_CH; ++t) {
         const uint32_t c = c0 + (uint32_t)t;
         const uint32_t pos = c * 64u + lane;
         kk[t] = c < nch && pos < nnz ? key[pos] : KEY_INF;
+        cl[t] = c < nch && pos < nnz ? col[pos] : 0u;
         r0[t] = c < nch ? cfirst[c] : 0u;
         r1[t] = c + 1u < nch ? cfirst[c + 1u] : total;
     }
@@ -309,11 +314,14 @@ __global__ __launch_bounds__(256) void k_sort_chunks(const uint32_t *__restrict_
             k = valid ? ((uint64_t)pi << 58) | ((k >> 32) << eb) | (k & emask) : ~0ull;
         bitonic_sort<PACKED, 2>(lb, pi, k, pl);
         if constexpr (PACKED) k = (((k >> eb) & 0xFFFFFFFFull) << 32) | (k & emask);
+        // the column of the entry now at this lane, from the lane that
+        // loaded it (every lane takes part; pl < 64)
+        const uint32_t hc = (uint32_t)__shfl((int)cl[t], (int)pl, 64);
         if (valid) {
             perm[pos] = (uint8_t)pl;
             if (is_start) {
                 const uint32_t ri = r0[t] + below;
-                hcol[ri] = col[c * 64u + pl];
+                hcol[ri] = hc;
                 hkey[ri] = k;
             }
         }
