@@ -160,6 +160,7 @@ msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc)
     if (const char *f = getenv("MSF_GRAPH_ORDER")) c->graph_order = atoi(f);
     if (const char *f = getenv("MSF_GRAPH_ROUNDS")) c->graph_rounds = atoi(f);
     if (const char *f = getenv("MSF_GRAPH_ROUNDS_MAX_N")) c->graph_rounds_max_n = atoll(f);
+    if (const char *f = getenv("MSF_TL_ROW_IN_COL")) c->tl_row_in_col = atoi(f);
     return MSF_OK;
 }
 

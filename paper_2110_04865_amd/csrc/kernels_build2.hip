@@ -380,7 +380,7 @@ __global__ __launch_bounds__(256) void k_tl_hist2(const uint8_t *__restrict__ su
 // TL_SP entries of a tile into registers once.
 constexpr int TL_SP = TL_TILE / TL_NT;  // entries per thread per tile
 
-template <bool PK1, bool PK2, bool SOA>
+template <bool PK1, bool PK2, bool SOA, bool SUBC>
 __global__ __launch_bounds__(TL_NT) void k_part_sub(
     const RecT<PK1> *__restrict__ e1, int L2, int nsub, int NC, const uint32_t *__restrict__ cs,
     const uint32_t *__restrict__ nb2, const uint32_t *__restrict__ P,
@@ -445,13 +445,14 @@ __global__ __launch_bounds__(TL_NT) void k_part_sub(
             const uint4 x = s_ent[i];
             const uint32_t s = (x.x >> L2) & mask;
             const uint32_t q = s_run[s] + (i - s_pos[s * TP_C]);
+            const uint32_t rf = x.x & ((1u << L2) - 1u);  // row inside the fine bucket
             if constexpr (SOA) {
-                c2[q] = x.y;
+                c2[q] = SUBC ? x.y | (rf << cb) : x.y;
                 k2[q] = ent_key(x);
             } else {
                 e2[q] = rec_pack<PK2>(x, (uint32_t)L2, cb);
             }
-            sub2[q] = (uint16_t)(x.x & ((1u << L2) - 1u));  // row inside the fine bucket
+            if constexpr (!SUBC) sub2[q] = (uint16_t)rf;
         }
         __syncthreads();
         for (int s = threadIdx.x; s < nsub; s += TL_NT) {
@@ -525,7 +526,7 @@ __global__ __launch_bounds__(TO_NT) void k_tl_order(const uint32_t *__restrict__
 // scan into row_ptr, place by row.  A bucket's output span is small (tens of
 // KB), so its scattered stores merge in L2 before they reach HBM.  MIN:
 // also store each row's smallest key into r (round 1 of the sweep).
-template <bool MIN, bool PK2, bool SOA>
+template <bool MIN, bool PK2, bool SOA, bool SUBC>
 __global__ __launch_bounds__(TC_NT) void k_tl_place(
     const RecT<PK2> *__restrict__ e2, int32_t n, int L2, uint32_t cb,
     const uint32_t *__restrict__ fstart,
@@ -537,6 +538,7 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
     extern __shared__ uint64_t tc_lds[];
     const uint32_t R = 1u << L2;
     const uint32_t C = tc_copies(L2), RC = R * C;  // counters are [row][copy]
+    const uint32_t cmask = SUBC ? (cb >= 32 ? ~0u : (1u << cb) - 1u) : ~0u;
     uint64_t *s_min = tc_lds;                                             // RC (MIN)
     uint32_t *s_cnt = reinterpret_cast<uint32_t *>(tc_lds + (MIN ? RC : 0));  // RC
     const uint32_t cp = threadIdx.x & (C - 1);  // this lane's copy
@@ -561,7 +563,12 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
 #pragma unroll
         for (int k = 0; k < TC_PT; ++k) {
             const uint64_t i = (uint64_t)fs + threadIdx.x + (uint32_t)k * TC_NT;
-            if constexpr (SOA) {
+            if constexpr (SOA && SUBC) {
+                const uint32_t w = i < fe ? c2[i] : 0u;
+                rl[k] = i < fe ? w >> cb : NONE32;
+                cc[k] = w & cmask;
+                kk[k] = i < fe ? k2[i] : KEY_INF;
+            } else if constexpr (SOA) {
                 rl[k] = i < fe ? (uint32_t)sub2[i] : NONE32;
                 cc[k] = i < fe ? c2[i] : 0u;
                 kk[k] = i < fe ? k2[i] : KEY_INF;
@@ -598,7 +605,8 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k) {
                 const uint64_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
-                rl[k] = i < fe ? (uint32_t)sub2[i] : NONE32;
+                if constexpr (SOA && SUBC) rl[k] = i < fe ? c2[i] >> cb : NONE32;
+                else rl[k] = i < fe ? (uint32_t)sub2[i] : NONE32;
             }
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k)
@@ -615,7 +623,12 @@ __global__ __launch_bounds__(TC_NT) void k_tl_place(
 #pragma unroll
             for (int k = 0; k < TC_PT; ++k) {
                 const uint64_t i = b + threadIdx.x + (uint32_t)k * TC_NT;
-                if constexpr (SOA) {
+                if constexpr (SOA && SUBC) {
+                    const uint32_t w = i < fe ? c2[i] : 0u;
+                    rl[k] = i < fe ? w >> cb : NONE32;
+                    cc[k] = w & cmask;
+                    kk[k] = i < fe ? k2[i] : KEY_INF;
+                } else if constexpr (SOA) {
                     rl[k] = i < fe ? (uint32_t)sub2[i] : NONE32;
                     cc[k] = i < fe ? c2[i] : 0u;
                     kk[k] = i < fe ? k2[i] : KEY_INF;
@@ -710,7 +723,7 @@ struct TLBufs {
     uint8_t *sub1;
 };
 
-template <bool PK1, bool PK2, bool SOA>
+template <bool PK1, bool PK2, bool SOA, bool SUBC>
 msf_status two_level_passes(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
                             const void *d_w, msf_wtype wt, const TwoLevel &tl, int64_t epb,
                             uint32_t nblk, size_t g2max, size_t nt2, uint32_t otiles,
@@ -743,7 +756,7 @@ msf_status two_level_passes(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges
     // their buffer takes each level-2 entry's row inside its fine bucket
     uint16_t *sub2 = reinterpret_cast<uint16_t *>(B.sub1);
     MSF_HIP(hipEventRecord(c->kev[4], s));
-    k_part_sub<PK1, PK2, SOA><<<(unsigned)g2max, TL_NT, 0, s>>>(
+    k_part_sub<PK1, PK2, SOA, SUBC><<<(unsigned)g2max, TL_NT, 0, s>>>(
         e1, tl.L2, tl.nsub, NC, B.cs, B.nb2, B.P, B.o2, cb, e2, c2, k2, sub2);
     MSF_HIP(hipEventRecord(c->kev[5], s));
     // C
@@ -755,15 +768,16 @@ msf_status two_level_passes(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges
     const size_t RC = ((size_t)1 << tl.L2) * tc_copies(tl.L2);
     MSF_HIP(hipEventRecord(c->kev[0], s));
     if (r_first)
-        k_tl_place<true, PK2, SOA><<<nf, TC_NT, 12 * RC, s>>>(
+        k_tl_place<true, PK2, SOA, SUBC><<<nf, TC_NT, 12 * RC, s>>>(
             e2, n, tl.L2, cb, B.fst, B.order, row_ptr, col, key, r_first, sub2, c2, k2);
     else
-        k_tl_place<false, PK2, SOA><<<nf, TC_NT, 4 * RC, s>>>(
+        k_tl_place<false, PK2, SOA, SUBC><<<nf, TC_NT, 4 * RC, s>>>(
             e2, n, tl.L2, cb, B.fst, B.order, row_ptr, col, key, nullptr, sub2, c2, k2);
     MSF_HIP(hipEventRecord(c->kev[1], s));
     c->pass_done |= 1u | 4u | 8u;
     c->rec1 = PK1 ? 12 : 16;
     c->rec2 = SOA ? 12 : PK2 ? 12 : 16;
+    c->sub2 = SUBC ? 0 : 2;
     MSF_HIP(hipGetLastError());
     return MSF_OK;
 }
@@ -826,17 +840,20 @@ msf_status build_two_level(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges,
                                nblk, wt, bh, false));
     MSF_TRY(scan_u32(c, bh, (uint32_t *)vbo, (int64_t)nh, &c->dcnt->count));
     constexpr bool SOA = TL_L2_SOA != 0;
-    if (pk1 && pk2)
-        return two_level_passes<true, true, SOA>(c, n, m, d_edges, d_w, wt, tl, epb, nblk, g2max,
-                                                 nt2, otiles, cb, B, row_ptr, col, key, r_first);
-    if (pk2)
-        return two_level_passes<false, true, SOA>(c, n, m, d_edges, d_w, wt, tl, epb, nblk, g2max,
-                                                  nt2, otiles, cb, B, row_ptr, col, key, r_first);
-    if (pk1)
-        return two_level_passes<true, false, SOA>(c, n, m, d_edges, d_w, wt, tl, epb, nblk, g2max,
-                                                  nt2, otiles, cb, B, row_ptr, col, key, r_first);
-    return two_level_passes<false, false, SOA>(c, n, m, d_edges, d_w, wt, tl, epb, nblk, g2max,
-                                               nt2, otiles, cb, B, row_ptr, col, key, r_first);
+    // the row inside the fine bucket rides in the level-2 column word
+    const bool subc = SOA && c->tl_row_in_col && (int)cb + tl.L2 <= 32;
+#define TL_PASSES(P1, P2, SC)                                                                  \
+    two_level_passes<P1, P2, SOA, SC>(c, n, m, d_edges, d_w, wt, tl, epb, nblk, g2max, nt2,    \
+                                      otiles, cb, B, row_ptr, col, key, r_first)
+    if (SOA) {  // level-2 records are not used: their packing does not apply
+        if (subc) return pk1 ? TL_PASSES(true, false, true) : TL_PASSES(false, false, true);
+        return pk1 ? TL_PASSES(true, false, false) : TL_PASSES(false, false, false);
+    }
+    if (pk1 && pk2) return TL_PASSES(true, true, false);
+    if (pk2) return TL_PASSES(false, true, false);
+    if (pk1) return TL_PASSES(true, false, false);
+    return TL_PASSES(false, false, false);
+#undef TL_PASSES
 }
 
 }  // namespace msf

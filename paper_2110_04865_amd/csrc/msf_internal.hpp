@@ -244,6 +244,7 @@ struct Ctx {
     hipEvent_t kev[8] = {};
     unsigned pass_done = 0;
     int rec1 = 0, rec2 = 0;
+    int sub2 = 2;  // bytes of the separate row-in-bucket array per level-2 entry
     msf_stats stats{};
     // msf_multilinear recorded sev[0..1] around its sweep; msf_get_stats
     // turns them into sweep_ms[0] once they have completed
@@ -281,6 +282,10 @@ struct Ctx {
     // host-stepped over compacted root lists, 2.28 ms on the device).
     int graph_rounds = 2;
     int64_t graph_rounds_max_n = (int64_t)1 << 20;
+    // two-level build: each level-2 entry's row inside its fine bucket in
+    // the high bits of its column word when column bits + L2 <= 32 (1), or
+    // in a separate 2-byte array (0)
+    int tl_row_in_col = 1;
     hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
     hipGraphExec_t gexec = nullptr;    // the captured rounds, for gkey
     uint64_t gkey[16] = {};

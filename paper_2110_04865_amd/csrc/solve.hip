@@ -519,9 +519,9 @@ msf_status solve_advance(Ctx *c)
         }
         const double nnz = (double)S.a.nnz;
         const double pass_bytes[4] = {
-            nnz * (c->rec2 + 2 + 12) + (double)S.n * (4.0 + (S.first_done ? 8.0 : 0.0)),
-            24.0 * nnz + 16.0 * S.nruns + 4.0 * std::ceil(nnz / 64.0),
-            nnz * (c->rec1 + c->rec2 + 2),
+            nnz * (c->rec2 + c->sub2 + 12) + (double)S.n * (4.0 + (S.first_done ? 8.0 : 0.0)),
+            13.0 * nnz + 16.0 * S.nruns + 4.0 * std::ceil(nnz / 64.0),
+            nnz * (c->rec1 + c->rec2 + c->sub2),
             12.0 * (double)S.m + nnz * (c->rec1 + 1),
         };
         for (int q = 0; q < 4; ++q) {

@@ -1241,7 +1241,9 @@ def test_build_modes_agree(pkg):
     sorted by degree (the first coarse bucket then holds over a million
     entries, more level-2 windows than a placement workgroup gathers at
     once), a grid, a multigraph with loops, and a graph with more vertices
-    than edges."""
+    than edges.  The two-level build runs twice: with each level-2 entry's
+    row inside its fine bucket in its column word (the default where the
+    bits fit) and in the separate 2-byte array."""
     rng = np.random.default_rng(31)
     nm = 3000
     multi_e = rng.integers(0, nm, size=(20000, 2)).astype(np.int32)
@@ -1258,19 +1260,22 @@ def test_build_modes_agree(pkg):
         ("multi", nm, multi_e, multi_w, U32),
         ("sparse", 50000, *gen.er(50000, 20000, seed=34), U32),
     ]
-    old = os.environ.get("MSF_BUCKETED_BUILD")
+    keys = ("MSF_BUCKETED_BUILD", "MSF_TL_ROW_IN_COL")
+    old = {k: os.environ.get(k) for k in keys}
     try:
-        for mode in ("0", "1", "2"):
+        for mode, ric in (("0", "1"), ("1", "1"), ("1", "0"), ("2", "1")):
             os.environ["MSF_BUCKETED_BUILD"] = mode
+            os.environ["MSF_TL_ROW_IN_COL"] = ric
             c = pkg.Context(0)
             for label, n, e, w, wt in graphs:
-                check_solve(c, pkg, n, e, w, wt, f"build={mode} {label}")
+                check_solve(c, pkg, n, e, w, wt, f"build={mode} row_in_col={ric} {label}")
             c.close()
     finally:
-        if old is None:
-            os.environ.pop("MSF_BUCKETED_BUILD", None)
-        else:
-            os.environ["MSF_BUCKETED_BUILD"] = old
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
 
 
 @pytest.mark.usefixtures("wide_path")
