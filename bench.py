@@ -849,8 +849,8 @@ def main():
     build_only_ms = r["build_ms"] - sort_ms
     units = {
         "build": (build_only_ms, build_bytes,
-                  "adjacency build (k_bucket_hist, k_scan_u32, k_part_edges, k_tl_plan, "
-                  "k_tl_hist2, k_part_sub, k_tl_fstart, k_tl_place, k_tl_order)"),
+                  "adjacency build (k_bucket_hist, the scans, k_part_edges, k_tl_plan, "
+                  "k_tl_hist2, k_part_sub, k_tl_fstart, k_tl_order, k_tl_place)"),
         "sort": (sort_ms, kt["sort"][1] / max(1, kt["sort"][2]),
                  "k_sort_chunks (run sort of the head sweep; 24 B per stored entry read + "
                  "written, 16 B per run, 4 B per chunk)"),
