@@ -354,6 +354,13 @@ void launch_chunk_rows_sliced(hipStream_t s, const Adj &a)
 }
 
 // Slice boundaries and the number of non-empty (row, slice) segments.
+// Each thread counts SI_ROWS consecutive rows of a slice (their pointers
+// loaded together); one atomic per workgroup, on a grid of at most
+// SI_BLOCKS workgroups (same-address atomics from thousands of workgroups
+// serialise: 30 us on 4.2M rows with 2048 workgroups of one row per thread).
+constexpr int SI_ROWS = 16;
+constexpr size_t SI_BLOCKS = 256;
+
 __global__ __launch_bounds__(256) void k_slice_info(const uint32_t *__restrict__ row_ptr,
                                                     int32_t n, int S, Counters *cnt)
 {
@@ -364,12 +371,20 @@ __global__ __launch_bounds__(256) void k_slice_info(const uint32_t *__restrict__
                                        ? row_ptr[(size_t)threadIdx.x * stride]
                                        : row_ptr[(size_t)(S - 1) * stride + n];
     uint32_t segs = 0;
-    const size_t total = (size_t)S * n;
+    const size_t groups = ((size_t)n + SI_ROWS - 1) / SI_ROWS;  // per slice
+    const size_t total = (size_t)S * groups;
     for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < total;
          j += (size_t)gridDim.x * blockDim.x) {
-        const size_t q = j / (size_t)n, i = j - q * (size_t)n;
+        const size_t q = j / groups, i0 = (j - q * groups) * SI_ROWS;
         const uint32_t *rp = row_ptr + q * stride;
-        segs += rp[i + 1] > rp[i] ? 1u : 0u;
+        uint32_t v[SI_ROWS + 1];
+#pragma unroll
+        for (int k = 0; k <= SI_ROWS; ++k) {
+            const size_t i = i0 + (size_t)k;
+            v[k] = rp[i < (size_t)n ? i : (size_t)n];  // clamped: past the end adds nothing
+        }
+#pragma unroll
+        for (int k = 0; k < SI_ROWS; ++k) segs += v[k + 1] > v[k] ? 1u : 0u;
     }
     segs = block_sum<256>(segs, s_lds);
     if (threadIdx.x == 0 && segs) atomicAdd(&cnt->segs, segs);
@@ -378,9 +393,10 @@ __global__ __launch_bounds__(256) void k_slice_info(const uint32_t *__restrict__
 void launch_slice_info(hipStream_t s, const Adj &a, Counters *dcnt)
 {
     launch_fill_u32(s, &dcnt->segs, 0u, 1);
-    size_t g = ((size_t)a.sl.S * (size_t)a.n + 255) / 256;
+    const size_t groups = (size_t)a.sl.S * (((size_t)a.n + SI_ROWS - 1) / SI_ROWS);
+    size_t g = (groups + 255) / 256;
     if (g < 1) g = 1;
-    if (g > 2048) g = 2048;
+    if (g > SI_BLOCKS) g = SI_BLOCKS;
     k_slice_info<<<(unsigned)g, 256, 0, s>>>(a.row_ptr, a.n, a.sl.S, dcnt);
 }
 

@@ -519,7 +519,10 @@ __global__ __launch_bounds__(256) void k_update_parents(const uint32_t *__restri
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        if (S > 1 || row_ptr[i + 1] > row_ptr[i]) p[i] = h[p[i]];
+        if (S > 1 || row_ptr[i + 1] > row_ptr[i]) {
+            const uint32_t x = p[i], y = h[x];
+            if (y != x) p[i] = y;  // most roots keep their place in a round
+        }
     }
 }
 

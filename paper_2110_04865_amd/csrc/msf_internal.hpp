@@ -420,6 +420,7 @@ void launch_chase(hipStream_t s, const uint32_t *F, uint32_t nF, uint32_t *h,
 // S > 1: every vertex is updated (stale parents of vertices without
 // entries are never read); S == 1: only rows that still have entries.
 // all: every vertex (as with S > 1), so p stays exact for every vertex.
+// A parent is written only where it changes.
 void launch_update_parents(hipStream_t s, const uint32_t *row_ptr, int32_t n, int S, uint32_t *p,
                            const uint32_t *h, uint32_t *part, Counters *dcnt, bool all = false);
 int64_t output_tiles(int64_t m);

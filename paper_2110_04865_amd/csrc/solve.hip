@@ -489,8 +489,11 @@ msf_status solve_advance(Ctx *c)
                 return MSF_EDEVICE;
             }
         }
+        // every vertex until the adjacency is filtered: a vertex without
+        // entries keeps p = h = itself, and skipping the row pointers costs
+        // less than reading them
         launch_update_parents(s, S.a.row_ptr, S.n, S.a.sl.S, S.b.p, S.b.h, (uint32_t *)S.b.part,
-                              c->dcnt, c->check_rounds);
+                              c->dcnt, c->check_rounds || S.st.filtered == 0);
         if (c->check_rounds) launch_check_stars(s, S.b.p, S.n, c->dcnt);
         S.ri ^= 1;
         S.nR = nRn;
