@@ -42,7 +42,7 @@ constexpr int TL_NT = 512;         // partition workgroup
 constexpr int TL_TILE = TL_TILE_ENTRIES;  // entries per LDS tile
 constexpr int TL_E2 = 8192;        // level-1 entries per level-2 workgroup
 #ifndef TL_PLACE_THREADS
-#define TL_PLACE_THREADS 256
+#define TL_PLACE_THREADS 512
 #endif
 constexpr int TC_NT = TL_PLACE_THREADS;  // placement workgroup
 #ifndef TL_PLACE_PER_THREAD
