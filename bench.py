@@ -852,8 +852,8 @@ def main():
                   "adjacency build (k_bucket_hist, the scans, k_part_edges, k_tl_plan, "
                   "k_tl_hist2, k_part_sub, k_tl_fstart, k_tl_order, k_tl_place)"),
         "sort": (sort_ms, kt["sort"][1] / max(1, kt["sort"][2]),
-                 "k_sort_chunks (run sort of the head sweep; 24 B per stored entry read + "
-                 "written, 16 B per run, 4 B per chunk)"),
+                 "k_sort_chunks (run sort of the head sweep; 13 B per stored entry: key and "
+                 "column read, order byte written; 16 B per run, 4 B per chunk)"),
         "heads": (kt["heads"][0] / steps, kt["heads"][1] / steps,
                   "k_heads + k_heads_rest (head sweeps of one solve; 24 B per run and sweep)"),
     }

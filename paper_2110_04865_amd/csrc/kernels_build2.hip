@@ -35,12 +35,18 @@ namespace msf {
 
 namespace {
 
-constexpr int TL_NT = 512;         // partition workgroup
+#ifndef TL_PART_THREADS
+#define TL_PART_THREADS 512
+#endif
+constexpr int TL_NT = TL_PART_THREADS;  // partition workgroup
 #ifndef TL_TILE_ENTRIES
 #define TL_TILE_ENTRIES 4096
 #endif
 constexpr int TL_TILE = TL_TILE_ENTRIES;  // entries per LDS tile
-constexpr int TL_E2 = 8192;        // level-1 entries per level-2 workgroup
+#ifndef TL_E2_ENTRIES
+#define TL_E2_ENTRIES 8192
+#endif
+constexpr int TL_E2 = TL_E2_ENTRIES;  // level-1 entries per level-2 workgroup
 #ifndef TL_PLACE_THREADS
 #define TL_PLACE_THREADS 512
 #endif
@@ -95,6 +101,7 @@ constexpr uint32_t TP_C = TL_PART_COPIES;
 #define TL_HIST2_COPIES 8
 #endif
 static_assert((TP_C & (TP_C - 1)) == 0, "copies: a power of two");
+static_assert(TL_TILE % (2 * TL_NT) == 0, "a tile: whole edges per partition thread");
 
 // In-place exclusive scan of a[0..N) in LDS by an NT-thread workgroup;
 // returns the total.  Every thread must call it.
