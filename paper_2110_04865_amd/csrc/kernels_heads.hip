@@ -252,7 +252,7 @@ __global__ __launch_bounds__(256) void k_runs_write(const uint32_t *__restrict__
 // of dependent loads of different chunks overlap; a run head's column then
 // comes from the lane that loaded it, not from a load after the network.
 #ifndef SORT_CHUNKS_PER_WAVE
-#define SORT_CHUNKS_PER_WAVE 8
+#define SORT_CHUNKS_PER_WAVE 7
 #endif
 constexpr int SORT_CH = SORT_CHUNKS_PER_WAVE;
 
