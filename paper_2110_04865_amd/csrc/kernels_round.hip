@@ -30,7 +30,10 @@ unsigned grid_for(size_t n, unsigned block = 256, unsigned cap = 8192)
 }
 
 constexpr int CT_NT = 256;                 // compaction tile: threads
-constexpr int CT_IT = 16;                  // items per thread
+#ifndef ROUND_ITEMS_PER_THREAD
+#define ROUND_ITEMS_PER_THREAD 8
+#endif
+constexpr int CT_IT = ROUND_ITEMS_PER_THREAD;  // items per thread
 constexpr int CT_TILE = CT_NT * CT_IT;     // items per tile
 static_assert(CT_IT <= 32, "a thread's items are kept in 32-bit masks");
 constexpr uint64_t M31 = (1ull << 31) - 1ull;
@@ -134,7 +137,10 @@ msf_status launch_init_roots(Ctx *c, const uint32_t *row_ptr, int32_t n, int S, 
 // phases so that the chains R -> r -> edge endpoints -> parents of
 // different items overlap).  Several items per thread only pay with many
 // roots; with fewer, one item per thread keeps every compute unit busy.
-constexpr uint32_t HK_MANY = 1u << 22;
+#ifndef HOOK_MANY_ROOTS
+#define HOOK_MANY_ROOTS (1u << 22)
+#endif
+constexpr uint32_t HK_MANY = HOOK_MANY_ROOTS;
 
 template <bool IDENTITY, int HK_IT>
 __global__ __launch_bounds__(256) void k_hook(const uint32_t *__restrict__ R, uint32_t nR,
