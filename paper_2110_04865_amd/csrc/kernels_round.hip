@@ -260,7 +260,10 @@ void launch_hook(hipStream_t s, const uint32_t *R, uint32_t nR, uint64_t *r, con
 // comes back from the key's high word: for float32 the key map is undone.
 
 // Most blocks a chase launch uses (each leaves one partial).
-constexpr unsigned CHASE_BLOCKS = 2048;
+#ifndef CHASE_WORKGROUPS
+#define CHASE_WORKGROUPS 2048
+#endif
+constexpr unsigned CHASE_BLOCKS = CHASE_WORKGROUPS;
 
 // ----------------------------------------------------------- tie break --
 // Tie-breaking step of Algorithm 2: a 2-cycle (i hooks on k and k on i) is the only
