@@ -36,7 +36,11 @@ static msf_status get_solve_bufs(Ctx *c, int32_t n, int64_t m, int S, SolveBufs 
     const size_t nnz_cap = 2 * mm;
     const size_t nch = chunk_cap(nnz_cap);
     size_t st = std::max<size_t>(nch, (size_t)output_tiles((int64_t)mm) + 1);
+    // a one-pass scan of n items takes its look-back status from this slot
+    // (it must not grow under the solve's pointer), and the root list's
+    // per-tile counts and their scan live here too
     st = std::max<size_t>(st, nn / 2048 + 2);
+    st = std::max<size_t>(st, (size_t)compaction_tiles((uint64_t)nn) + 1);
     const size_t part_bytes = std::max<size_t>(
         {output_part_bytes((int64_t)mm), chase_part_bytes(), 4 * 4096 + 256});
     struct Req {
