@@ -133,6 +133,11 @@ typedef struct {
        after the shortcut, and the roots drop by exactly the kept hooks
        (MSF_EDEVICE otherwise). */
     int64_t roots[64];
+    /* msf_solve with the two-level build: the adjacency build alone (device
+       events from the solve's start to the end of the placement; build_ms
+       also holds the head sweep's run set-up and the host step between
+       them); 0 with the other builds. */
+    double adjacency_ms;
 } msf_stats;
 
 typedef struct msf_ctx msf_ctx;

@@ -65,7 +65,7 @@ class Stats(ctypes.Structure):
                 ("pass_bytes", ctypes.c_double * 4), ("batch_config", ctypes.c_int32),
                 ("batch_grid", ctypes.c_int32), ("batch_graphs", ctypes.c_int64),
                 ("batch_large", ctypes.c_int64), ("batch_ms", ctypes.c_double),
-                ("roots", ctypes.c_int64 * 64)]
+                ("roots", ctypes.c_int64 * 64), ("adjacency_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -287,7 +287,8 @@ class Context:
                     runs=s.runs, pass_ms=list(s.pass_ms), pass_bytes=list(s.pass_bytes),
                     batch_config=s.batch_config, batch_grid=s.batch_grid,
                     batch_graphs=s.batch_graphs, batch_large=s.batch_large,
-                    batch_ms=s.batch_ms, roots=list(s.roots[:k]))
+                    batch_ms=s.batch_ms, roots=list(s.roots[:k]),
+                    adjacency_ms=s.adjacency_ms)
 
     # ------------------------------------------------------- primitives --
     def graph(self, n: int, edges, weights, wtype: int | None = None) -> "Graph":

@@ -517,6 +517,9 @@ msf_status solve_advance(Ctx *c)
         (void)hipEventElapsedTime(&ms_rounds, c->ev[1], c->ev[2]);
         S.st.build_ms = ms_build;
         S.st.rounds_ms = ms_rounds;
+        float ms_adj = 0.f;
+        if (c->pass_done & 1u) (void)hipEventElapsedTime(&ms_adj, c->ev[0], c->kev[1]);
+        S.st.adjacency_ms = ms_adj;
         // only the rounds that recorded their sweep events (none when the
         // rounds ran on the device)
         for (int k = 0; k < S.sweep_events; ++k) {
