@@ -11,6 +11,7 @@ raises :class:`MSFError` if ``libmsf.so`` has not been built.
 from __future__ import annotations
 
 import atexit
+from collections.abc import Sequence
 import ctypes
 import os
 import weakref
@@ -52,6 +53,24 @@ class MSFError(RuntimeError):
 
 class Total(ctypes.Structure):
     _fields_ = [("u64", ctypes.c_uint64), ("f64", ctypes.c_double)]
+
+
+class BatchTotals(Sequence):
+    """Per-graph totals of a batched solve as (u64, f64) pairs, read from the
+    library's output array on access (no per-graph conversion up front)."""
+
+    def __init__(self, arr, n: int):
+        self._a = np.frombuffer(arr, dtype=np.dtype([("u64", "<u8"), ("f64", "<f8")]),
+                                count=n)
+
+    def __len__(self) -> int:
+        return len(self._a)
+
+    def __getitem__(self, g):
+        if isinstance(g, slice):
+            return [self[i] for i in range(*g.indices(len(self)))]
+        x = self._a[g]
+        return (int(x["u64"]), float(x["f64"]))
 
 
 class Stats(ctypes.Structure):
@@ -387,7 +406,7 @@ class Context:
                                        ctypes.c_void_p(w.ctypes.data), wt, MEM_HOST,
                                        ctypes.c_void_p(ids.ctypes.data),
                                        ctypes.c_void_p(counts.ctypes.data), totals))
-        return ids, counts[:G], [(totals[g].u64, totals[g].f64) for g in range(G)]
+        return ids, counts[:G], BatchTotals(totals, G)
 
 
 def solve_batched_noalloc(ctx: "Context", vtx_off, edge_off, edges, weights, wtype: int,

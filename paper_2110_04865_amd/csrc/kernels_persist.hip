@@ -37,6 +37,9 @@
 // on that graph alone.  Outputs: the forest's local edge ids in ascending
 // order from out + vtx_off[g], count and exact totals.
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "exact_sum.hpp"
@@ -480,6 +483,20 @@ hipError_t launch_cfg(hipStream_t s, const PersistArgs &A, int wt, unsigned grid
 
 int persist_blocks_per_cu(const PersistCfg &cfg, int wt)
 {
+    // one occupancy query per (device, configuration, weight type)
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, uint32_t, int>, int> known;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const auto key = std::make_tuple(dev, cfg.nt, cfg.ept, (uint32_t)cfg.lds, wt);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = known.find(key);
+        if (it != known.end()) return it->second;
+    }
     const void *f = nullptr;
 #define MSF_PERSIST_FN(NT_, EPT_)                                                            \
     if (cfg.nt == NT_ && cfg.ept == EPT_)                                                   \
@@ -498,6 +515,8 @@ int persist_blocks_per_cu(const PersistCfg &cfg, int wt)
         (void)hipGetLastError();
         return 0;
     }
+    std::lock_guard<std::mutex> lk(mu);
+    known[key] = nb;
     return nb;
 }
 

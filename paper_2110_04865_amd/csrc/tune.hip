@@ -60,8 +60,15 @@ void store_cache(const Key &k, int idx)
     fclose(f);
 }
 
+// The device's architecture name, queried once per device (the full
+// property query costs far more than a batch's host-side set-up).
 std::string arch_of(int device)
 {
+    static std::mutex mu;
+    static std::map<int, std::string> known;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = known.find(device);
+    if (it != known.end()) return it->second;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
         (void)hipGetLastError();
@@ -69,7 +76,9 @@ std::string arch_of(int device)
     }
     std::string a = prop.gcnArchName;
     const size_t colon = a.find(':');
-    return colon == std::string::npos ? a : a.substr(0, colon);
+    a = colon == std::string::npos ? a : a.substr(0, colon);
+    known[device] = a;
+    return a;
 }
 
 int ilog2(double x) { return x >= 1.0 ? (int)std::floor(std::log2(x)) : 0; }
