@@ -1066,6 +1066,10 @@ def test_full_rmat_s22(ctx, pkg):
     n, e, w = gen.workload_rmat_s22()
     st = check_solve(ctx, pkg, n, e, w, F32, "rmat s22 full")
     say("rmat s22 stats", st)
+    # the two-level build's own interval lies inside the build interval,
+    # which also holds the run set-up and the run sort
+    assert 0.0 < st["adjacency_ms"] < st["build_ms"], st
+    assert st["adjacency_ms"] + st["pass_ms"][1] <= st["build_ms"], st
 
 
 def test_full_grid_256(ctx, pkg):
