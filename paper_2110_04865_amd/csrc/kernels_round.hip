@@ -50,6 +50,30 @@ static void prep_lookback(hipStream_t s, uint64_t *status, uint32_t tiles, Count
     launch_zero_lookback(s, status, tiles, &dcnt->ticket, 1, nullptr, 0);
 }
 
+// A solve's round state in one launch: p = h = identity over n vertices,
+// r = empty when given, and `words` words of forest flags cleared.
+__global__ void k_round_state(uint32_t *p, uint32_t *h, uint64_t *r, size_t n, uint32_t *flags,
+                              size_t words)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t top = n > words ? n : words;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < top; i += stride) {
+        if (i < n) {
+            p[i] = (uint32_t)i;
+            h[i] = (uint32_t)i;
+            if (r) r[i] = KEY_INF;
+        }
+        if (i < words) flags[i] = 0u;
+    }
+}
+
+void launch_round_state(hipStream_t s, uint32_t *p, uint32_t *h, uint64_t *r, size_t n,
+                        uint32_t *flags, size_t words)
+{
+    const size_t top = n > words ? n : words;
+    if (top) k_round_state<<<grid_for(top), 256, 0, s>>>(p, h, r, n, flags, words);
+}
+
 // ----------------------------------------------------------- root list --
 // R = vertices with at least one stored entry (isolated vertices are
 // finished roots from the start).  Counted per tile, scanned, then written

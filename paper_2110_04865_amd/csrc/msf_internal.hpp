@@ -363,6 +363,10 @@ void launch_chunk_rows(hipStream_t s, const uint32_t *row_ptr, int32_t n, uint32
 void launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t v, size_t n);
 void launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, size_t n);
 void launch_iota_u32(hipStream_t s, uint32_t *p, size_t n);
+// p = h = identity over n vertices, r = empty when non-null, `words`
+// words of flags cleared, in one launch.
+void launch_round_state(hipStream_t s, uint32_t *p, uint32_t *h, uint64_t *r, size_t n,
+                        uint32_t *flags, size_t words);
 // status[0..tiles) = 0, z1[0..n1) = 0, z2[0..n2) = 0 in one launch (n1, n2
 // at most a few hundred)
 void launch_zero_lookback(hipStream_t s, uint64_t *status, uint32_t tiles, uint32_t *z1,

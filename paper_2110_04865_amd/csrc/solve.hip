@@ -189,10 +189,8 @@ static msf_status enqueue_round_state(Ctx *c)
     SolveState &S = c->ss;
     hipStream_t s = c->stream;
     MSF_HIP(hipEventRecord(c->ev[1], s));
-    launch_iota_u32(s, S.b.p, (size_t)S.n);
-    launch_iota_u32(s, S.b.h, (size_t)S.n);
-    if (!S.first_done) launch_fill_u64(s, S.b.r, KEY_INF, (size_t)S.n);
-    launch_fill_u32(s, reinterpret_cast<uint32_t *>(S.b.flags), 0u, ((size_t)S.m + 3) / 4);
+    launch_round_state(s, S.b.p, S.b.h, S.first_done ? nullptr : S.b.r, (size_t)S.n,
+                       reinterpret_cast<uint32_t *>(S.b.flags), ((size_t)S.m + 3) / 4);
     MSF_TRY(launch_init_roots(c, S.a.row_ptr, S.n, S.a.sl.S, S.b.R[0], S.b.status));
     return MSF_OK;
 }
