@@ -1160,6 +1160,20 @@ def test_full_size_device_atomic_build(pkg, label):
     c.close()
 
 
+def test_one_pass_scan_of_many_vertices(pkg):
+    """Scans of more than 16K tiles of 2048 items take the one-pass
+    look-back scan instead of the three launches: the device-atomic build's
+    row-pointer scan over 36M vertices (2M edges, most vertices isolated)."""
+    n = 36 << 20
+    e, w = gen.er(n, 2_000_000, seed=41)
+    with env_set(MSF_BUCKETED_BUILD="0"):
+        c = pkg.Context(0)
+    try:
+        check_solve(c, pkg, n, e, w, U32, "36M vertices, device-atomic build")
+    finally:
+        c.close()
+
+
 @pytest.mark.usefixtures("wide_path")
 def test_column_slices_are_result_invariant(pkg):
     graphs = [
