@@ -25,7 +25,8 @@ Also reported on the same JSON line:
                 graph;
   served        continuous-batching server: p50/p99 latency and graphs/s of
                 a Poisson stream of mixed graphs at several rates, vs a plain
-                one-at-a-time FIFO;
+                one-at-a-time FIFO, and the CPU oracle's service rate on the
+                same pool (one thread and the host's cores);
   multilinear_ablation
                 the all-at-once multilinear kernel vs the pairwise
                 formulation (pairs (a_ij, p_j) stored first, then reduced) on
@@ -634,7 +635,7 @@ def serve_stream(srv, pkg, pool, arrivals, picks):
 
 def bench_served(ctx, pkg, torch, requests_per_rate=2000, warm_requests=100,
                  rates=(0.25, 0.5, 1.0, 2.0, 4.0), budget=32 << 30,
-                 budget_sweep=(8 << 30, 128 << 30), seed=5):
+                 budget_sweep=(8 << 30, 128 << 30), seed=5, cpu=False):
     """Poisson request stream over a pool of mixed graphs (half R-MAT with
     edge factor 16, half cubic grids with 5% of edges dropped, n log-uniform
     in [2^10, 2^22], float32 weights).  The rate is a multiple of the plain
@@ -642,7 +643,8 @@ def bench_served(ctx, pkg, torch, requests_per_rate=2000, warm_requests=100,
     out, timed here).  At every rate the same arrivals also go through a
     plain FIFO that is actually run (one msf_solve at a time); the first
     `warm_requests` of each stream are not counted.  At the plain rate the
-    server also runs under the budgets of `budget_sweep`."""
+    server also runs under the budgets of `budget_sweep`.  With `cpu`, the
+    oracle's service rate on the same pool is added (served_cpu)."""
     import numpy as np
     import gen
 
@@ -711,7 +713,41 @@ def bench_served(ctx, pkg, torch, requests_per_rate=2000, warm_requests=100,
                 servers.pop(b).close()
     for srv in servers.values():
         srv.close()
+    if cpu:
+        log("served: the oracle on the pool")
+        out.update(served_cpu(pool))
     return out
+
+
+def served_cpu(pool):
+    """The oracle's service rate on the served pool: every pool graph solved
+    once by the oracle on one thread and on the host's cores (a thread pool;
+    the oracle's sort and union-find run outside the interpreter lock), as
+    graphs/s over the pool's size mix."""
+    import concurrent.futures as cf
+    import oracle
+
+    def one(p):
+        n, e, w, kind = p
+        return oracle.msf(n, e, w, oracle.W_F32)
+
+    t = time.perf_counter()
+    for p in pool:
+        one(p)
+    t1 = time.perf_counter() - t
+    workers = min(16, len(os.sched_getaffinity(0)))
+    t = time.perf_counter()
+    with cf.ThreadPoolExecutor(workers) as ex:
+        for _ in ex.map(one, pool):
+            pass
+    tall = time.perf_counter() - t
+    return {"cpu_baseline": {"value": len(pool) / t1, "unit": "graphs/s", "cores": 1,
+                             "kind": "oracle",
+                             "sample": f"the {len(pool)} pool graphs once each, one thread"},
+            "cpu_parallel": {"value": len(pool) / tall, "unit": "graphs/s", "cores": workers,
+                             "kind": "oracle",
+                             "sample": f"the {len(pool)} pool graphs once each, {workers} "
+                                       "threads"}}
 
 
 def main():
@@ -921,7 +957,7 @@ def main():
         log("batched: 10^4 Erdos-Renyi graphs")
         line["batched"] = bench_batched(ctx, pkg, torch, cpu=not args.no_cpu)
         log("served: Poisson stream of mixed graphs")
-        sv = bench_served(ctx, pkg, torch, args.served_requests)
+        sv = bench_served(ctx, pkg, torch, args.served_requests, cpu=not args.no_cpu)
         line["served"] = sv
         at1 = [r for r in sv["rates"] if r["rate_x_plain"] == 1.0]
         if at1:
