@@ -134,7 +134,8 @@ msf_status launch_init_roots(Ctx *c, const uint32_t *row_ptr, int32_t n, int S, 
         return MSF_OK;
     }
     // per-tile counts and their scan in the status buffer (8 bytes per
-    // tile and one more)
+    // tile and one more); at most 2^20 tiles, so the scan takes its
+    // three-launch form, whose workspace is not the status buffer
     uint32_t *tcnt = reinterpret_cast<uint32_t *>(status);
     uint32_t *toff = tcnt + tiles;
     k_roots_count<<<tiles, CT_NT, 0, s>>>(row_ptr, n, S, tcnt);
