@@ -163,6 +163,32 @@ __device__ __forceinline__ void bitonic_sort(const bool (&lb)[7], uint32_t &pi, 
     if constexpr (KK < 64) bitonic_sort<PACKED, KK * 2>(lb, pi, k, pl);
 }
 
+// The same network over one distinct 32-bit word per lane: one lane move,
+// one compare and one select per step instead of three of each.
+template <int KK, int J>
+__device__ __forceinline__ void bitonic_merge32(uint32_t &w)
+{
+    const uint32_t ow = xor_move<J>(w);
+    constexpr uint64_t KEEP_MIN = keep_min_lanes(KK, J);
+    const uint64_t take = ~(__ballot(ow < w) ^ KEEP_MIN);
+    w = select_lanes(take, ow, w);
+    if constexpr (J > 1) bitonic_merge32<KK, J / 2>(w);
+}
+
+template <int KK>
+__device__ __forceinline__ void bitonic_sort32(uint32_t &w)
+{
+    bitonic_merge32<KK, KK / 2>(w);
+    if constexpr (KK < 64) bitonic_sort32<KK * 2>(w);
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, uint32_t src)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, (int)src, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), (int)src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Wave-wide minimum per run of consecutive lanes holding the same root; the
 // last lane of each run folds it into r (lanes without a root hold NONE32).
 __device__ __forceinline__ void flush_by_root(uint64_t *r, uint32_t root, uint64_t v)
@@ -244,15 +270,31 @@ __global__ __launch_bounds__(256) void k_runs_write(const uint32_t *__restrict__
 // perm and store each run's head (its smallest key and its column) into its
 // descriptor.  Reads the keys and columns (12 bytes per entry) and writes one
 // byte per entry.  The chunk's runs are cfirst[c] .. cfirst[c + 1] - 1 (the
-// last chunk ends at *nruns); their starts are ORed across the lanes.  With
-// PACKED (edge ids of at most 26 bits) the sort key is one 64-bit word: run
-// index inside the chunk, weight key, edge id.
+// last chunk ends at *nruns); their starts are flagged in the wave's LDS
+// bytes (before: ORed across the lanes, 0.509 -> 0.481 ms on R-MAT s22).
+// The network first orders one 32-bit word per entry (run index, the top
+// bits of the weight key below the bits all the chunk's keys share, lane):
+// a step then moves one register instead of three (0.563 -> 0.537 ms at
+// seven chunks per wave).  Entries of one run with equal words are put in
+// key order by a few transposition steps, or, past three such pairs, the
+// chunk is ordered again by the 64-bit network.  With PACKED (edge ids of
+// at most 26 bits) that network's key is one 64-bit word: run index inside
+// the chunk, weight key, edge id.
 // Chunks one wave orders: their loads (keys, columns, first runs, then the
 // runs' starts) are all issued before the first network runs, so the chains
 // of dependent loads of different chunks overlap; a run head's column then
 // comes from the lane that loaded it, not from a load after the network.
+// Five chunks (55-57 VGPRs, nine waves per SIMD) beat seven (67, seven
+// waves) once the network was lighter: 0.513 vs 0.537 ms; 2 / 3 / 4 / 10 /
+// 14 chunks gave 0.570 / 0.535 / 0.519 / 0.640 / 0.745 ms.
 #ifndef SORT_CHUNKS_PER_WAVE
-#define SORT_CHUNKS_PER_WAVE 7
+#define SORT_CHUNKS_PER_WAVE 5
+#endif
+#ifndef SORT_WORD32
+#define SORT_WORD32 1
+#endif
+#ifndef SORT_START_LDS
+#define SORT_START_LDS 1
 #endif
 constexpr int SORT_CH = SORT_CHUNKS_PER_WAVE;
 
@@ -289,6 +331,10 @@ __global__ __launch_bounds__(256) void k_sort_chunks(const uint32_t *__restrict_
     bool lb[7];
 #pragma unroll
     for (int b = 0; b < 7; ++b) lb[b] = (lane >> b) & 1u;
+#if SORT_START_LDS
+    __shared__ uint8_t flags[4][64];
+    const uint32_t wv = threadIdx.x >> 6;
+#endif
     const uint64_t emask = (1ull << eb) - 1ull;
 #pragma unroll
     for (int t = 0; t < SORT_CH; ++t) {
@@ -298,6 +344,15 @@ __global__ __launch_bounds__(256) void k_sort_chunks(const uint32_t *__restrict_
         const bool valid = pos < nnz;
         uint64_t k = kk[t];
         uint32_t pl = lane;  // carried through the network: the entry's chunk offset
+#if SORT_START_LDS
+        // one flag byte per chunk offset in the wave's own LDS bytes: the
+        // wave's LDS instructions run in order, so no barrier is needed
+        flags[wv][lane] = 0;
+        if (rc[t] != NONE32) flags[wv][rc[t] & 63u] = 1;
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t sm = __ballot(flags[wv][lane] != 0);
+        __builtin_amdgcn_wave_barrier();
+#else
         uint64_t sm = rc[t] != NONE32 ? 1ull << (rc[t] & 63u) : 0ull;
         sm |= xor_move64<1>(sm);
         sm |= xor_move64<2>(sm);
@@ -305,15 +360,81 @@ __global__ __launch_bounds__(256) void k_sort_chunks(const uint32_t *__restrict_
         sm |= xor_move64<8>(sm);
         sm |= xor_move64<16>(sm);
         sm |= xor_move64<32>(sm);
+#endif
         const uint64_t vmask = nnz - c * 64u >= 64u ? ~0ull : (1ull << (nnz - c * 64u)) - 1ull;
         const uint64_t starts = sm & vmask;
         const uint32_t below = (uint32_t)__popcll(starts & lanemask_lt());
         const bool is_start = (starts >> lane) & 1ull;
         uint32_t pi = valid ? below + (is_start ? 1u : 0u) - 1u : 63u;  // run inside the chunk
-        if constexpr (PACKED)
-            k = valid ? ((uint64_t)pi << 58) | ((k >> 32) << eb) | (k & emask) : ~0ull;
-        bitonic_sort<PACKED, 2>(lb, pi, k, pl);
-        if constexpr (PACKED) k = (((k >> eb) & 0xFFFFFFFFull) << 32) | (k & emask);
+        bool full = true;
+#if SORT_WORD32
+        {
+            // One 32-bit word per entry: run index (pb bits), the bits of the
+            // weight key below the highest bit in which the chunk's keys
+            // differ (shifted to fit 26 - pb bits: order-preserving, but it
+            // may merge keys), and the lane.  Words are distinct, so the
+            // network orders the entries by (run, word bits); where two
+            // neighbours of one run have equal bits their order is settled
+            // on the full keys below.
+            const uint32_t nv = nnz - c * 64u >= 64u ? 64u : nnz - c * 64u;
+            const uint32_t nr = (uint32_t)__popcll(starts);
+            const uint32_t wk = (uint32_t)(k >> 32);
+            const uint32_t ref = __builtin_amdgcn_readfirstlane(wk);  // lane 0 is valid
+            uint32_t x = valid ? wk ^ ref : 0u;
+            x |= xor_move<1>(x);
+            x |= xor_move<2>(x);
+            x |= xor_move<4>(x);
+            x |= xor_move<8>(x);
+            x |= xor_move<16>(x);
+            x |= xor_move<32>(x);
+            x = __builtin_amdgcn_readfirstlane(x);
+            const uint32_t hb = x ? 32u - (uint32_t)__clz((int)x) : 0u;
+            const uint32_t pb = nr > 1u ? 32u - (uint32_t)__clz((int)(nr - 1u)) : 0u;
+            const uint32_t vb = 26u - pb;
+            const uint32_t sh = hb > vb ? hb - vb : 0u;
+            const uint32_t lowm = hb >= 32u ? ~0u : (1u << hb) - 1u;
+            const uint32_t v = (wk & lowm) >> sh;
+            uint32_t w = valid ? (pb ? pi << (32u - pb) : 0u) | (v << 6) | lane
+                               : 0xFFFFFFC0u | lane;  // after every valid word
+            bitonic_sort32<2>(w);
+            const uint32_t wp = __shfl_up(w, 1);
+            const bool tie = lane > 0 && lane < nv && (wp >> 6) == (w >> 6);
+            const uint64_t tm = __ballot(tie);
+            const int nt = __popcll(tm);
+            // more than three tied pairs: the 64-bit network instead
+            if (nt <= 3) {
+                full = false;
+                pl = w & 63u;
+                k = shfl_u64(kk[t], pl);
+                if (nt) {
+                    // groups of at most four: four odd-even transposition
+                    // phases on the full keys, within tied neighbours only
+#pragma unroll
+                    for (int ph = 0; ph < 4; ++ph) {
+                        const uint32_t q = (ph & 1) ? ((lane & 1u) ? lane + 1u : lane - 1u)
+                                                    : lane ^ 1u;
+                        const uint32_t pq = q < 64u ? q : lane;
+                        const uint32_t ow = (uint32_t)__shfl((int)w, (int)pq, 64);
+                        const uint64_t ok = shfl_u64(k, pq);
+                        const bool pair = pq != lane && lane < nv && pq < nv &&
+                                          (ow >> 6) == (w >> 6);
+                        const bool swap = pair && (lane < pq ? ok < k : k < ok);
+                        if (swap) {
+                            w = ow;
+                            k = ok;
+                        }
+                    }
+                    pl = w & 63u;
+                }
+            }
+        }
+#endif
+        if (full) {
+            if constexpr (PACKED)
+                k = valid ? ((uint64_t)pi << 58) | ((k >> 32) << eb) | (k & emask) : ~0ull;
+            bitonic_sort<PACKED, 2>(lb, pi, k, pl);
+            if constexpr (PACKED) k = (((k >> eb) & 0xFFFFFFFFull) << 32) | (k & emask);
+        }
         // the column of the entry now at this lane, from the lane that
         // loaded it (every lane takes part; pl < 64)
         const uint32_t hc = (uint32_t)__shfl((int)cl[t], (int)pl, 64);

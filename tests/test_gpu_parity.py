@@ -332,7 +332,9 @@ def test_head_sweep_matches_oracle_and_full_sweep(pkg):
     (so every round's minima agree).  Cases: a grid (entries turn internal
     round by round, so long internal stretches reach the per-run second
     phase), skewed R-MAT (rows of thousands of entries split into many runs),
-    equal weights (order by edge id), a multigraph with loops and repeated
+    equal weights (order by edge id), few distinct weights and weights far
+    apart beside close ones (equal sort words inside runs, settled on the full
+    keys or by the 64-bit network), a multigraph with loops and repeated
     pairs, more vertices than edges, a path (one run per row, many rounds),
     and entry counts off the 64-entry chunk grid."""
     rng = np.random.default_rng(41)
@@ -344,7 +346,17 @@ def test_head_sweep_matches_oracle_and_full_sweep(pkg):
     path_w = rng.permutation(npath - 1).astype(np.uint32)
     eq_e, _ = gen.er(3000, 20000, seed=43)
     eq_w = np.full(len(eq_e), 7, dtype=np.uint32)
+    # few distinct weights (equal keys inside runs, ordered by edge id) and
+    # weights far apart next to weights close together (the chunk sort's
+    # 32-bit words drop the low bits, so distinct keys share words)
+    fw_n, fw_e, _ = gen.rmat(15, 16, seed=48)
+    fw_w = rng.integers(0, 4096, size=len(fw_e)).astype(np.uint32)
+    mg_n, mg_e, _ = gen.rmat(14, 16, seed=49)
+    mg_w = ((rng.integers(0, 4, size=len(mg_e)) << 30) |
+            rng.integers(0, 128, size=len(mg_e))).astype(np.uint32)
     graphs = [
+        ("rmat15 few weights", fw_n, fw_e, fw_w, U32),
+        ("rmat14 split weights", mg_n, mg_e, mg_w, U32),
         ("grid20", *gen.grid(20, 20, 20, 0.05, seed=42), U32),
         ("rmat15", *gen.rmat(15, 16, seed=44), F32),
         ("equal weights", 3000, eq_e, eq_w, U32),
