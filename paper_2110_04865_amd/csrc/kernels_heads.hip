@@ -301,7 +301,8 @@ constexpr int SORT_CH = SORT_CHUNKS_PER_WAVE;
 template <bool PACKED>
 __global__ __launch_bounds__(256) void k_sort_chunks(const uint32_t *__restrict__ col,
                                                      const uint64_t *__restrict__ key,
-                                                     uint8_t *__restrict__ perm, uint32_t nnz,
+                                                     uint8_t *__restrict__ perm,
+                                                     const uint32_t *__restrict__ d_nnz,
                                                      const uint32_t *__restrict__ cfirst,
                                                      const uint32_t *__restrict__ nruns,
                                                      const uint32_t *__restrict__ run_cur, int eb,
@@ -309,6 +310,7 @@ __global__ __launch_bounds__(256) void k_sort_chunks(const uint32_t *__restrict_
                                                      uint64_t *__restrict__ hkey)
 {
     const uint32_t lane = __lane_id();
+    const uint32_t nnz = *d_nnz;  // the grid covers an upper bound
     const uint32_t nch = (nnz + 63u) / 64u;
     const uint32_t c0 = (blockIdx.x * 4u + (threadIdx.x >> 6)) * (uint32_t)SORT_CH;
     if (c0 >= nch) return;  // whole waves
@@ -581,10 +583,10 @@ size_t heads_runs_cap(size_t nnz_cap, int32_t n)
 }
 
 msf_status build_runs(Ctx *c, const Runs &R, const uint32_t *row_ptr, int32_t n,
-                      const uint32_t *col, const uint64_t *key, uint32_t nnz, int eb)
+                      const uint32_t *col, const uint64_t *key, uint32_t nnz_max, int eb)
 {
     hipStream_t s = c->stream;
-    const uint32_t nch = (nnz + 63u) / 64u;
+    const uint32_t nch = (nnz_max + 63u) / 64u;
     if (nch == 0 || n <= 0) {
         launch_fill_u32(s, &c->dcnt->nruns, 0u, 1);
         return MSF_OK;
@@ -596,11 +598,12 @@ msf_status build_runs(Ctx *c, const Runs &R, const uint32_t *row_ptr, int32_t n,
     const unsigned gs = (nch + 4u * SORT_CH - 1u) / (4u * SORT_CH);
     const uint32_t *total = R.roff + n;  // the scan's total: the number of runs
     MSF_HIP(hipEventRecord(c->kev[2], s));
+    const uint32_t *d_nnz = row_ptr + n;  // one slice: the stored entry count
     if (eb <= 26)
-        k_sort_chunks<true><<<gs, 256, 0, s>>>(col, key, R.perm, nnz, R.cfirst, total, R.cur,
+        k_sort_chunks<true><<<gs, 256, 0, s>>>(col, key, R.perm, d_nnz, R.cfirst, total, R.cur,
                                                eb, R.hcol, R.hkey);
     else
-        k_sort_chunks<false><<<gs, 256, 0, s>>>(col, key, R.perm, nnz, R.cfirst, total, R.cur,
+        k_sort_chunks<false><<<gs, 256, 0, s>>>(col, key, R.perm, d_nnz, R.cfirst, total, R.cur,
                                                 eb, R.hcol, R.hkey);
     MSF_HIP(hipEventRecord(c->kev[3], s));
     c->pass_done |= 2u;

@@ -202,7 +202,8 @@ int choose_slices(int32_t n, int64_t m, int forced);
 void set_chunks(Adj *a);
 
 struct SolveState {
-    int phase = 0;  // 0 idle, 1 build, 2 roots, 3 round, 4 output, 5 done
+    int phase = 0;  // 0 idle, 1 build, 2 roots, 3 round, 4 output, 5 done,
+                    // 6 device-driven rounds, 7 build and runs (head sweep)
     int32_t n = 0;
     int64_t m = 0;
     const int32_t *edges = nullptr;
@@ -441,11 +442,12 @@ constexpr unsigned CHASE_MAX_BLOCKS = 2048;
 // one-slice adjacency from row_ptr, orders every 64-entry chunk of col/key
 // by (row, key) into R.perm (the entries stay where they are) and fills the
 // run arrays (keys' edge ids take eb bits); the run count lands in
-// dcnt->nruns.  launch_heads runs one sweep (queue counter
+// dcnt->nruns.  The entry count is read on the device (row_ptr[n]);
+// nnz_max, an upper bound of it, sizes the launches.  launch_heads runs one sweep (queue counter
 // dcnt->qn[parity], clearing the other one).
 size_t heads_runs_cap(size_t nnz_cap, int32_t n);
 msf_status build_runs(Ctx *c, const Runs &R, const uint32_t *row_ptr, int32_t n,
-                      const uint32_t *col, const uint64_t *key, uint32_t nnz, int eb);
+                      const uint32_t *col, const uint64_t *key, uint32_t nnz_max, int eb);
 void launch_heads(hipStream_t s, const Runs &R, uint32_t nruns, const uint32_t *col,
                   const uint64_t *key, const uint32_t *p, uint64_t *r, Counters *dcnt, int parity);
 msf_status launch_output(Ctx *c, const uint8_t *in_forest, int64_t m, const void *w,

@@ -149,6 +149,9 @@ static msf_status end_step(Ctx *c, int next_phase)
     return MSF_OK;
 }
 
+static msf_status enqueue_round_state(Ctx *c);
+static int edge_bits(int64_t m);
+
 msf_status solve_start(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, const void *d_w,
                        msf_wtype wt, int32_t *d_ids)
 {
@@ -179,6 +182,16 @@ msf_status solve_start(Ctx *c, int32_t n, int64_t m, const int32_t *d_edges, con
                             &S.first_done));
     // the build may have fallen back to another slice count
     if (S.a.sl.S != 1) S.heads = S.graph = false;
+    if (S.heads) {
+        // the run set-up and the round state need nothing the host would
+        // read back from the build (the run sort takes the entry count on
+        // the device), so they follow at once: one host step fewer, and
+        // the build's counters are read with the set-up's
+        MSF_TRY(build_runs(c, S.runs, S.a.row_ptr, S.n, S.a.col, S.a.key,
+                           (uint32_t)std::min<int64_t>(2 * m, UINT32_MAX), edge_bits(m)));
+        MSF_TRY(enqueue_round_state(c));
+        return end_step(c, 7);
+    }
     return end_step(c, 1);
 }
 
@@ -399,14 +412,16 @@ msf_status solve_advance(Ctx *c)
     hipStream_t s = c->stream;
     const Counters *h = c->hcnt;
     switch (S.phase) {
+    case 7:  // adjacency built and the head sweep's runs set up
     case 1: {  // adjacency built
         MSF_TRY(decode_err(h->err));
         for (int q = 0; q <= S.a.sl.S; ++q) S.a.sl.sstart[q] = h->sstart[q];
         set_chunks(&S.a);
         S.a.segs = h->segs;
-        if (S.heads)
-            MSF_TRY(build_runs(c, S.runs, S.a.row_ptr, S.n, S.a.col, S.a.key, S.a.nnz,
-                               edge_bits(S.m)));
+        if (S.phase == 7) {
+            S.phase = 2;
+            return solve_advance(c);  // the root list is ready too
+        }
         // the chunk-row table serves the full sweep only
         if (S.a.nnz && !S.heads) launch_chunk_rows_sliced(s, S.a);
         MSF_TRY(enqueue_round_state(c));
