@@ -259,7 +259,22 @@ bool solve_done(const Ctx *c) { return c->ss.phase == 5; }
 // Enqueue one round: sweep (+ filtering), hook, tie break.
 // Live roots below which the sweep reads r before each atomic (measured:
 // with 200 roots the read saves 2.6x; with millions it costs up to 1.6x).
-constexpr uint32_t READ_FILTER_ROOTS = 1u << 16;
+#ifndef SWEEP_READ_FILTER_ROOTS
+#define SWEEP_READ_FILTER_ROOTS (1u << 16)
+#endif
+constexpr uint32_t READ_FILTER_ROOTS = SWEEP_READ_FILTER_ROOTS;
+// A sweep with that read counts every entry it passed over as live, so
+// once the roots are that few its count stops showing how many entries
+// turned internal.  Then, when the trees average at least
+// FILTER_ROOTS_RATIO vertices, the adaptive policy filters once anyway
+// (0: never).  Measured on the 256^3 grid: the filtering sweep in round 5
+// (46K roots) costs 1.3 ms, as in later rounds, and keeps 32% of the
+// entries; the six later sweeps take 0.24-0.31 ms instead of 0.43-0.48
+// (solve 9.13-9.18 -> 8.91-8.94 ms; waiting for fewer roots, 2^12 or 2^14,
+// gave 9.31-9.33 ms).
+#ifndef FILTER_ROOTS_RATIO
+#define FILTER_ROOTS_RATIO 16
+#endif
 
 static msf_status enqueue_round(Ctx *c)
 {
@@ -271,7 +286,12 @@ static msf_status enqueue_round(Ctx *c)
     // the end (its final root is its label)
     else if (S.kept) S.compact = false;
     else if (c->filter_mode == 2) S.compact = true;
-    else if (c->filter_mode == 1) S.compact = S.live_frac < c->filter_threshold;
+    else if (c->filter_mode == 1) {
+        S.compact = S.live_frac < c->filter_threshold;
+        if (!S.compact && FILTER_ROOTS_RATIO > 0 && S.st.filtered == 0 && S.rounds > 0 &&
+            S.nR < READ_FILTER_ROOTS && (int64_t)S.nR * FILTER_ROOTS_RATIO <= (int64_t)S.n)
+            S.compact = true;
+    }
     const int ev_k = S.rounds < 64 ? S.rounds : -1;
     if (ev_k >= 0) {
         S.sweep_events = ev_k + 1;
