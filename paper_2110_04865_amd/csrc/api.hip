@@ -48,6 +48,13 @@ msf_status ws_get(Ctx *c, Slot s, size_t bytes, void **out)
         }
         const size_t gran = c->async_alloc ? ((size_t)1 << 16) : ((size_t)1 << 20);
         size_t cap = (bytes + gran - 1) & ~(gran - 1);
+        if (c->fail_alloc_after == 0) {
+            // the test hook: this allocation fails as a real one would
+            c->fail_alloc_after = -1;
+            set_error("device allocation of %zu bytes refused (MSF_TEST_FAIL_ALLOC_AFTER)", cap);
+            return MSF_ENOMEM;
+        }
+        if (c->fail_alloc_after > 0) --c->fail_alloc_after;
         hipError_t e = c->async_alloc ? hipMallocAsync(&b.ptr, cap, c->stream)
                                       : hipMalloc(&b.ptr, cap);
         if (e != hipSuccess) {
@@ -161,6 +168,7 @@ msf_status ctx_init(Ctx *c, int device, hipStream_t stream, bool async_alloc)
     if (const char *f = getenv("MSF_GRAPH_ROUNDS")) c->graph_rounds = atoi(f);
     if (const char *f = getenv("MSF_GRAPH_ROUNDS_MAX_N")) c->graph_rounds_max_n = atoll(f);
     if (const char *f = getenv("MSF_TL_ROW_IN_COL")) c->tl_row_in_col = atoi(f);
+    if (const char *f = getenv("MSF_TEST_FAIL_ALLOC_AFTER")) c->fail_alloc_after = atoll(f);
     return MSF_OK;
 }
 

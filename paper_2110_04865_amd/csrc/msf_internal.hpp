@@ -287,6 +287,10 @@ struct Ctx {
     // the high bits of its column word when column bits + L2 <= 32 (1), or
     // in a separate 2-byte array (0)
     int tl_row_in_col = 1;
+    // failure-path test hook (MSF_TEST_FAIL_ALLOC_AFTER): after this many
+    // workspace allocations the next one is refused once, without calling
+    // the allocator (-1: never)
+    int64_t fail_alloc_after = -1;
     hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
     hipGraphExec_t gexec = nullptr;    // the captured rounds, for gkey
     uint64_t gkey[16] = {};

@@ -191,6 +191,62 @@ def test_ties_and_parallel_edges(ctx, pkg):
     check_solve(ctx, pkg, 2000, e, w, U32, "all equal")
 
 
+def test_forced_allocation_failure_leaves_outputs_and_context(pkg, wide_path):
+    """A workspace allocation refused from the host (MSF_TEST_FAIL_ALLOC_AFTER
+    = k: the allocation after k others fails once, no allocator call is
+    made) at every point of a solve in turn: the call ends with MSF_ENOMEM,
+    the caller's output is untouched, and the same context then solves the
+    graph to the oracle's forest.  Paths: the head sweep (runs set up after
+    the build) and the full sweep filtered every round (buffers taken in
+    the middle of the rounds)."""
+    ENOMEM = 2
+    cases = [
+        ("heads rmat12", {"MSF_HEADS": "2"}, *gen.rmat(12, 16, seed=61), F32),
+        ("filtered grid12", {"MSF_HEADS": "0", "MSF_FILTER": "2"},
+         *gen.grid(12, 12, 12, 0.05, seed=62), U32),
+    ]
+    for label, env, n, e, w, wt in cases:
+        want_ids, want_cnt, want_tot = oracle.msf(n, e, w, wt)
+        de, dw = dev(e), dev(w)
+        refused = 0
+        for k in range(64):
+            keys = dict(env, MSF_TEST_FAIL_ALLOC_AFTER=str(k))
+            old = {q: os.environ.get(q) for q in keys}
+            os.environ.update(keys)
+            try:
+                c = pkg.Context(0)
+            finally:
+                for q, v in old.items():
+                    if v is None:
+                        os.environ.pop(q, None)
+                    else:
+                        os.environ[q] = v
+            say("forced allocation failure", label, f"after {k}")
+            out = torch.full((n,), -7, dtype=torch.int32, device="cuda:0")
+            failed = False
+            try:
+                c.solve(n, de, dw, wtype=wt, out=out)
+            except pkg.MSFError as ex:
+                assert ex.status == ENOMEM, (label, k, str(ex))
+                failed = True
+            torch.cuda.synchronize()
+            if failed:
+                refused += 1
+                assert bool((out == -7).all()), (label, k)
+            # the hook fires once: the context solves normally afterwards
+            ids, cnt, tot = c.solve(n, de, dw, wtype=wt)
+            torch.cuda.synchronize()
+            assert cnt == want_cnt, (label, k)
+            assert np.array_equal(ids.cpu().numpy().astype(np.int64), want_ids), (label, k)
+            assert tot[1] == want_tot[1], (label, k)
+            c.close()
+            if not failed:
+                break
+        else:
+            pytest.fail(f"{label}: a solve still allocated after 64 refusals")
+        assert refused >= 3, (label, refused)
+
+
 def test_invalid_inputs_leave_outputs_untouched(ctx, pkg):
     L = pkg.lib()
     import ctypes
