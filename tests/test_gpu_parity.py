@@ -247,6 +247,41 @@ def test_forced_allocation_failure_leaves_outputs_and_context(pkg, wide_path):
         assert refused >= 3, (label, refused)
 
 
+def test_invalid_inputs_on_the_head_sweep_path(pkg, wide_path):
+    """With the head sweep on, the run set-up is enqueued right after the
+    build, before the host reads the build's error flags: a bad endpoint or
+    a NaN weight among valid edges must still end the call with
+    MSF_EINVAL, leave the output untouched, and leave the context solving
+    the valid graph to the oracle's forest (the build skips invalid edges in
+    every pass, so the set-up runs over a consistent adjacency)."""
+    EINVAL = 1
+    n, e, w = gen.rmat(11, 16, seed=63)
+    old = os.environ.get("MSF_HEADS")
+    os.environ["MSF_HEADS"] = "2"
+    try:
+        c = pkg.Context(0)
+    finally:
+        if old is None:
+            os.environ.pop("MSF_HEADS", None)
+        else:
+            os.environ["MSF_HEADS"] = old
+    bad_end = e.copy()
+    bad_end[len(e) // 2, 1] = n
+    bad_w = w.copy()
+    bad_w[len(w) // 3] = np.float32(np.nan)
+    for label, ee, ww in (("endpoint", bad_end, w), ("nan", e, bad_w)):
+        say("invalid on the head-sweep path", label)
+        out = torch.full((n,), -7, dtype=torch.int32, device="cuda:0")
+        with pytest.raises(pkg.MSFError) as info:
+            c.solve(n, dev(ee), dev(ww), wtype=F32, out=out)
+        assert info.value.status == EINVAL, (label, str(info.value))
+        torch.cuda.synchronize()
+        assert bool((out == -7).all()), label
+        st = check_solve(c, pkg, n, e, w, F32, f"valid after {label}")
+        assert st["runs"] > 0, label
+    c.close()
+
+
 def test_invalid_inputs_leave_outputs_untouched(ctx, pkg):
     L = pkg.lib()
     import ctypes
